@@ -1,0 +1,237 @@
+"""Algorithm 1 of arXiv:2206.07044 ("Approximate contraction", section II.F),
+with gauge distance r = 0 and early compression — float64 numpy oracle.
+
+Test infrastructure only (see the package docstring).
+
+Readings of the paper used here (each is also listed in the design notes):
+* Several compressions after one contraction run in ascending neighbour id
+  (Algorithm 1 loops over NEIGHBORS(T, k); the order is not fixed by the text).
+* All edges between two tensors form one composite bond whose size is the
+  product of their dimensions (BONDSIZE, Fig. "tensor primitives" A).
+* The new bond dimension is min(chi, k_A, k_B) with k = min(rows, D_AB), the
+  rank bound of the reduced factors; sigma^(1/2) goes to both sides (Eq. (svd)).
+* When a matricised factor has no more rows than D_AB its QR is skipped and
+  the factor itself serves as R (the result only depends on R up to an
+  orthogonal factor, SI B).
+* A singular value that is exactly zero, or below ``cutoff * sigma_1``, gives a
+  zero column/row in the projectors instead of a division by zero.
+* Every tensor an op writes is divided by its largest absolute entry and the
+  natural log of that scale is added to a running exponent (the value of the
+  contraction is linear in every tensor, so this leaves ln|Z| unchanged).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclass
+class OpRecord:
+    """One step of the expanded schedule (used to check the GPU planner)."""
+    kind: str            # "contract" or "compress"
+    a: int               # contract: i; compress: the tensor being compressed (k)
+    b: int               # contract: j; compress: its neighbour l
+    out: int             # contract: new id k; compress: new edge id
+    m: int               # contract: free size of i;  compress: rows of A_mat
+    n: int               # contract: shared size;     compress: D_AB
+    k: int               # contract: free size of j;  compress: columns of B_mat
+    new_dim: int = 0     # compress: chi'
+    discarded: float = 0.0   # compress: sum of discarded sigma^2 / sum sigma^2
+    tie: bool = False        # compress: sigma_chi' and the next one coincide
+
+
+@dataclass
+class OracleResult:
+    sign: float
+    ln_abs_z: float
+    ops: List[OpRecord] = field(default_factory=list)
+    log_scales: List[float] = field(default_factory=list)
+
+    @property
+    def log10_exponent(self) -> float:
+        if self.sign == 0:
+            return -math.inf
+        return math.floor(self.ln_abs_z / math.log(10.0))
+
+    @property
+    def mantissa(self) -> float:
+        if self.sign == 0:
+            return 0.0
+        frac = self.ln_abs_z / math.log(10.0) - self.log10_exponent
+        return self.sign * 10.0 ** frac
+
+
+class ZeroContraction(Exception):
+    """The network evaluates to exactly zero (e.g. no perfect matching)."""
+
+
+class _Network:
+    """Live tensors, each an ndarray with a list of edge ids naming its axes."""
+
+    def __init__(self, n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray]):
+        self.dim: Dict[int, int] = {e: int(d) for e, (_, _, d) in enumerate(edges)}
+        self.ends: Dict[int, List[int]] = {e: [int(u), int(v)] for e, (u, v, _) in enumerate(edges)}
+        self.legs: Dict[int, List[int]] = {v: [] for v in range(n)}
+        for e, (u, v, _) in enumerate(edges):
+            self.legs[u].append(e)
+            self.legs[v].append(e)
+        self.t: Dict[int, np.ndarray] = {}
+        for v in range(n):
+            self.legs[v].sort()
+            arr = np.asarray(tensors[v], dtype=np.float64)
+            want = tuple(self.dim[e] for e in self.legs[v])
+            if arr.shape != want:
+                raise ValueError(f"tensor {v} has shape {arr.shape}, expected {want}")
+            self.t[v] = arr.copy()
+        self.next_edge = len(edges)
+
+    def other_end(self, e: int, x: int) -> int:
+        a, b = self.ends[e]
+        return b if a == x else a
+
+    def neighbors(self, x: int) -> Dict[int, List[int]]:
+        """Neighbour id -> edge ids shared with it, in x's axis order."""
+        out: Dict[int, List[int]] = {}
+        for e in self.legs[x]:
+            out.setdefault(self.other_end(e, x), []).append(e)
+        return out
+
+
+def _normalise(arr: np.ndarray, scales: List[float]) -> np.ndarray:
+    s = float(np.max(np.abs(arr))) if arr.size else 0.0
+    if s == 0.0 or not math.isfinite(s):
+        if s == 0.0:
+            raise ZeroContraction()
+        raise FloatingPointError("non-finite tensor entry")
+    scales.append(math.log(s))
+    return arr / s
+
+
+def _contract(net: _Network, i: int, j: int, k: int, scales: List[float], ops: List[OpRecord]) -> None:
+    """Pairwise contraction (Fig. "tensor primitives" B): sum over the shared
+    edges; the result's axes are i's free edges then j's free edges."""
+    li, lj = net.legs.pop(i), net.legs.pop(j)
+    ti, tj = net.t.pop(i), net.t.pop(j)
+    shared = [e for e in li if e in lj]
+    ai = [li.index(e) for e in shared]
+    aj = [lj.index(e) for e in shared]
+    out = np.tensordot(ti, tj, axes=(ai, aj))
+    free_i = [e for e in li if e not in shared]
+    free_j = [e for e in lj if e not in shared]
+    m = int(np.prod([net.dim[e] for e in free_i])) if free_i else 1
+    s = int(np.prod([net.dim[e] for e in shared])) if shared else 1
+    q = int(np.prod([net.dim[e] for e in free_j])) if free_j else 1
+    ops.append(OpRecord("contract", i, j, k, m, s, q))
+    for e in shared:
+        del net.ends[e]
+    for e in free_i + free_j:
+        ends = net.ends[e]
+        ends[ends.index(i if e in free_i else j)] = k
+    net.legs[k] = free_i + free_j
+    net.t[k] = _normalise(out, scales)
+
+
+def _reduced_factors(a_mat: np.ndarray, b_mat: np.ndarray):
+    """R_A with R_A^T R_A = A^T A and R_B with R_B R_B^T = B B^T (section II.C)."""
+    D = a_mat.shape[1]
+    r_a = np.linalg.qr(a_mat, mode="r") if a_mat.shape[0] > D else a_mat
+    r_b = np.linalg.qr(b_mat.T, mode="r").T if b_mat.shape[1] > D else b_mat
+    return r_a, r_b
+
+
+def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
+              scales: List[float], ops: List[OpRecord], explicit: bool) -> None:
+    """Compress every edge between a and b into one edge of dimension chi'.
+
+    QR-reduced form: R_AB = R_A R_B ~ U s V^T truncated to chi' values
+    (Eq. (svd)); projectors P_L = R_B V s^-1/2 and P_R = s^-1/2 U^T R_A
+    (SI B) give a' = A P_L and b' = P_R B.  With ``explicit`` the SVD is of
+    the full product A B instead (the definition the QR form is equal to).
+    """
+    la, lb = net.legs[a], net.legs[b]
+    shared = [e for e in la if e in lb]
+    free_a = [e for e in la if e not in shared]
+    free_b = [e for e in lb if e not in shared]
+    ta = np.transpose(net.t[a], [la.index(e) for e in free_a + shared])
+    tb = np.transpose(net.t[b], [lb.index(e) for e in shared + free_b])
+    D = int(np.prod([net.dim[e] for e in shared]))
+    ma, mb = ta.size // D, tb.size // D
+    a_mat = ta.reshape(ma, D)
+    b_mat = tb.reshape(D, mb)
+    if explicit:
+        U, sig, Vt = np.linalg.svd(a_mat @ b_mat, full_matrices=False)
+        ka, kb = min(ma, D), min(mb, D)
+    else:
+        r_a, r_b = _reduced_factors(a_mat, b_mat)
+        ka, kb = r_a.shape[0], r_b.shape[1]
+        U, sig, Vt = np.linalg.svd(r_a @ r_b, full_matrices=False)
+    new = min(chi, ka, kb)
+    total = float(np.sum(sig ** 2))
+    disc = float(np.sum(sig[new:] ** 2)) / total if total > 0 else 0.0
+    tie = bool(len(sig) > new and sig[new - 1] - sig[new] <= 1e-12 * sig[0])
+    keep = sig[:new].copy()
+    mask = (keep > 0) & (keep >= cutoff * sig[0])
+    inv_sqrt = np.where(mask, 1.0 / np.sqrt(np.where(mask, keep, 1.0)), 0.0)
+    if explicit:
+        sq = np.where(mask, np.sqrt(keep), 0.0)
+        new_a = U[:, :new] * sq
+        new_b = sq[:, None] * Vt[:new]
+    else:
+        p_l = (r_b @ Vt[:new].T) * inv_sqrt           # D x chi'
+        p_r = inv_sqrt[:, None] * (U[:, :new].T @ r_a)  # chi' x D
+        new_a = a_mat @ p_l
+        new_b = p_r @ b_mat
+    e_new = net.next_edge
+    net.next_edge += 1
+    ops.append(OpRecord("compress", a, b, e_new, ma, D, mb, new, disc, tie))
+    for e in shared:
+        del net.ends[e]
+        del net.dim[e]
+    net.dim[e_new] = new
+    net.ends[e_new] = [a, b]
+    net.legs[a] = free_a + [e_new]
+    net.legs[b] = [e_new] + free_b
+    da = [net.dim[e] for e in free_a] + [new]
+    db = [new] + [net.dim[e] for e in free_b]
+    net.t[a] = _normalise(new_a.reshape(da), scales)
+    net.t[b] = _normalise(new_b.reshape(db), scales)
+
+
+def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
+                        pairs: Sequence[Tuple[int, int]], chi: Optional[int], cutoff: float = 0.0,
+                        explicit: bool = False) -> OracleResult:
+    """Run Algorithm 1 (early compression, r = 0) and return sign and ln|Z|.
+
+    ``chi=None`` is exact contraction (no compression).  Step t of ``pairs``
+    contracts live tensors (i, j) into a new tensor with id n + t; after each
+    contraction every bond of the new tensor larger than chi is compressed,
+    neighbours in ascending id.
+    """
+    net = _Network(n, edges, tensors)
+    scales: List[float] = []
+    ops: List[OpRecord] = []
+    if len(pairs) != n - 1:
+        raise ValueError("a tree over n tensors has n - 1 steps")
+    try:
+        for v in range(n):
+            net.t[v] = _normalise(net.t[v], scales)
+        for t, (i, j) in enumerate(pairs):
+            k = n + t
+            if i == j or i not in net.t or j not in net.t:
+                raise ValueError(f"step {t}: ({i}, {j}) are not two live tensors")
+            _contract(net, i, j, k, scales, ops)
+            if chi is None:
+                continue
+            for l, shared in sorted(net.neighbors(k).items()):
+                size = int(np.prod([net.dim[e] for e in shared]))
+                if size > chi:
+                    _compress(net, k, l, chi, cutoff, scales, ops, explicit)
+    except ZeroContraction:
+        return OracleResult(0.0, -math.inf, ops, scales)
+    (last,) = net.t.values()
+    x = float(last.reshape(()))
+    ln_abs = math.fsum(scales) + math.log(abs(x))
+    return OracleResult(math.copysign(1.0, x), ln_abs, ops, scales)
