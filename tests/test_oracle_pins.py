@@ -1,0 +1,269 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test compares the oracle with something that is not the oracle:
+closed forms, brute-force sums over spin/matching configurations, layer
+transfer matrices, numpy's SVD of an explicitly formed product (Eckart-Young),
+or an invariance the method must have.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from oracle.approx import _Network, _compress
+from tninputs import (dimer_tensors, greedy_tree, ising_bond_factors, ising_tensors, lattice,
+                      normal_tensors, random_regular3, Graph)
+from tninputs.trees import sweep_tree
+
+
+def run(g, T, pairs, chi, **kw):
+    return oracle.contract_compressed(g.n, g.edges, T, pairs, chi, **kw)
+
+
+# ---------------------------------------------------------------- inputs (SI F.1)
+@pytest.mark.parametrize("J", [1.0, -1.0, 0.7, -2.3])
+def test_ising_split_is_boltzmann_matrix(J):
+    beta = 0.44
+    lo, hi = ising_bond_factors(beta, J)
+    spins = np.array([1.0, -1.0])
+    want = np.exp(beta * J * np.outer(spins, spins))
+    np.testing.assert_allclose(lo @ hi, want, rtol=1e-14)
+    np.testing.assert_allclose(lo, lo.T, atol=0)
+    np.testing.assert_allclose(hi, hi.T, atol=0)
+
+
+def test_ising_factor_equals_paper_matrix_for_ferromagnet():
+    beta = 0.3
+    c, s = math.cosh(beta), math.sinh(beta)
+    paper = np.array([[math.sqrt(c) + math.sqrt(s), math.sqrt(c) - math.sqrt(s)],
+                      [math.sqrt(c) - math.sqrt(s), math.sqrt(c) + math.sqrt(s)]]) / math.sqrt(2)
+    lo, hi = ising_bond_factors(beta, 1.0)
+    np.testing.assert_allclose(lo, paper, rtol=1e-15)
+    np.testing.assert_allclose(hi, paper, rtol=1e-15)
+    np.testing.assert_allclose(paper @ paper, np.exp(beta * np.array([[1, -1], [-1, 1]])), rtol=1e-14)
+
+
+# ---------------------------------------------------------------- exact references agree with each other
+def test_transfer_matrix_equals_brute_force():
+    g = lattice((3, 4))
+    J = np.random.default_rng(3).choice([-1.0, 1.0], g.n_edges)
+    a = exact.ising_transfer_matrix((3, 4), 0.5, J, g.edges)
+    b = exact.ising_brute_force(g.n, g.edges, 0.5, J)
+    assert abs(a - b) < 1e-12
+
+
+def test_transfer_matrix_equals_brute_force_3d():
+    g = lattice((2, 2, 4))
+    a = exact.ising_transfer_matrix((2, 2, 4), 0.3)
+    b = exact.ising_brute_force(g.n, g.edges, 0.3)
+    assert abs(a - b) < 1e-12
+
+
+# ---------------------------------------------------------------- oracle exact mode (chi = None), Eq. tncontract
+@pytest.mark.parametrize("shape,beta", [((3, 3), 0.44), ((4, 4), 0.2), ((2, 3, 3), 0.3)])
+def test_exact_mode_matches_brute_force_ising(shape, beta):
+    g = lattice(shape)
+    J = np.random.default_rng(1).choice([-1.0, 1.0], g.n_edges)
+    T = ising_tensors(g, beta, J)
+    pairs = greedy_tree(g, 4, seed=0)
+    r = run(g, T, pairs, None)
+    assert r.sign == 1.0
+    assert abs(r.ln_abs_z - exact.ising_brute_force(g.n, g.edges, beta, J)) < 1e-11
+
+
+def test_exact_mode_8x8_transfer_matrix():
+    g = lattice((8, 8))
+    T = ising_tensors(g, 0.44)
+    tm = exact.ising_transfer_matrix((8, 8), 0.44)
+    assert abs(tm - 56.879536639072) < 1e-9          # value recomputed, not trusted
+    for pairs in (sweep_tree((8, 8)), greedy_tree(g, 16, seed=0)):
+        r = run(g, T, pairs, None)
+        assert abs(r.ln_abs_z - tm) / tm < 1e-13
+
+
+def test_forest_and_ring_closed_forms():
+    rng = np.random.default_rng(0)
+    # random tree on 12 vertices plus an isolated vertex (a forest with 2 components)
+    edges = sorted((int(rng.integers(0, v)), v, 2) for v in range(1, 12))
+    g = Graph(13, edges)
+    J = rng.normal(size=len(edges))
+    T = ising_tensors(g, 0.7, J)
+    r = run(g, T, greedy_tree(g, 4, seed=1), 2)        # chi=2: bonds of a forest never exceed 2
+    assert abs(r.ln_abs_z - exact.ising_forest(g.n, g.edges, 0.7, J)) < 1e-12
+    ring = Graph(9, sorted([(i, i + 1, 2) for i in range(8)] + [(0, 8, 2)]))
+    J = rng.choice([-1.0, 1.0], ring.n_edges)
+    T = ising_tensors(ring, 0.9, J)
+    r = run(ring, T, greedy_tree(ring, 2, seed=0), None)
+    assert abs(r.ln_abs_z - exact.ising_ring(0.9, J)) < 1e-12
+
+
+# ---------------------------------------------------------------- dimers (SI F.3)
+def _complete(n):
+    return Graph(n, [(u, v, 2) for u in range(n) for v in range(u + 1, n)])
+
+
+def _petersen():
+    outer = [(i, (i + 1) % 5) for i in range(5)]
+    spokes = [(i, i + 5) for i in range(5)]
+    inner = [(5 + i, 5 + (i + 2) % 5) for i in range(5)]
+    return Graph(10, sorted((min(u, v), max(u, v), 2) for u, v in outer + spokes + inner))
+
+
+def _cube():
+    return Graph(8, sorted((u, u ^ (1 << b), 2) for u in range(8) for b in range(3) if u < u ^ (1 << b)))
+
+
+def _k33():
+    return Graph(6, [(u, v, 2) for u in range(3) for v in range(3, 6)])
+
+
+def _prism():
+    e = [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5), (0, 3), (1, 4), (2, 5)]
+    return Graph(6, sorted((u, v, 2) for u, v in e))
+
+
+@pytest.mark.parametrize("g,count", [(_complete(4), 3), (_k33(), 6), (_prism(), 4), (_cube(), 9), (_petersen(), 6)])
+def test_dimer_counts_textbook(g, count):
+    assert exact.perfect_matchings(g.n, g.edges) == count
+    r = run(g, dimer_tensors(g), greedy_tree(g, 64, seed=0), None)
+    assert r.sign == 1.0 and abs(math.exp(r.ln_abs_z) - count) < 1e-9
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dimer_random_regular_exact(seed):
+    g = random_regular3(20, seed)
+    want = exact.perfect_matchings(g.n, g.edges)
+    r = run(g, dimer_tensors(g), greedy_tree(g, 1 << 20, seed=seed), None)
+    assert abs(r.ln_abs_z - math.log(want)) < 1e-11
+
+
+def test_dimer_zero_when_no_matching():
+    g = Graph(3, [(0, 1, 2), (0, 2, 2), (1, 2, 2)])     # triangle: odd vertex count
+    r = run(g, dimer_tensors(g), [(0, 1), (3, 2)], 4)
+    assert r.sign == 0.0 and r.ln_abs_z == -math.inf
+
+
+# ---------------------------------------------------------------- compression primitive (II.C, SI B)
+def _two_block_network(rng, m1, dims, m2):
+    """P -e0- A =shared= B -e3- Q, returns net and (A, B) ids."""
+    edges = [(0, 1, m1)] + [(1, 2, d) for d in dims] + [(2, 3, m2)]
+    A = rng.normal(size=(m1,) + tuple(dims))
+    B = rng.normal(size=tuple(dims) + (m2,))
+    T = [rng.normal(size=(m1,)), A, B, rng.normal(size=(m2,))]
+    return _Network(4, edges, T), A, B
+
+
+@pytest.mark.parametrize("m1,dims,m2,chi", [(40, (3, 4), 30, 5), (6, (3, 4), 50, 4), (7, (2, 2, 2), 5, 3), (64, (8, 8), 64, 16)])
+def test_compression_is_truncated_svd_of_product(m1, dims, m2, chi):
+    rng = np.random.default_rng(m1 + m2)
+    net, A, B = _two_block_network(rng, m1, dims, m2)
+    D = int(np.prod(dims))
+    M = A.reshape(m1, D) @ B.reshape(D, m2)
+    scales, ops = [], []
+    _compress(net, 1, 2, chi, 0.0, scales, ops, explicit=False)
+    a2, b2 = net.t[1], net.t[2]
+    approx = (a2.reshape(m1, -1) @ b2.reshape(-1, m2)) * math.exp(scales[0] + scales[1]) \
+        / (np.max(np.abs(A)) * np.max(np.abs(B))) * np.max(np.abs(A)) * np.max(np.abs(B))
+    U, s, Vt = np.linalg.svd(M)
+    k = min(chi, min(m1, D), min(m2, D))
+    best = (U[:, :k] * s[:k]) @ Vt[:k]
+    np.testing.assert_allclose(approx, best, rtol=0, atol=1e-11 * np.abs(M).max())
+    err = np.linalg.norm(M - approx)
+    assert abs(err - math.sqrt(np.sum(s[k:] ** 2))) <= 1e-9 * np.linalg.norm(M)
+    assert ops[0].new_dim == k
+    assert abs(ops[0].discarded - np.sum(s[k:] ** 2) / np.sum(s ** 2)) < 1e-12
+
+
+def test_qr_form_equals_explicit_product_svd():
+    g = lattice((3, 4))
+    T = normal_tensors(g, 0.3, 5)
+    pairs = sweep_tree((3, 4))
+    for chi in (2, 3, 4):
+        a = run(g, T, pairs, chi)
+        b = run(g, T, pairs, chi, explicit=True)
+        assert a.sign == b.sign and abs(a.ln_abs_z - b.ln_abs_z) < 1e-12
+
+
+# ---------------------------------------------------------------- executor invariants
+def test_large_chi_is_exact_3d():
+    g = lattice((3, 3, 4))
+    T = ising_tensors(g, 0.22)
+    tm = exact.ising_transfer_matrix((3, 3, 4), 0.22)
+    pairs = sweep_tree((3, 3, 4))
+    r = run(g, T, pairs, 1 << 12)
+    assert not any(o.kind == "compress" for o in r.ops)
+    assert abs(r.ln_abs_z - tm) / tm < 1e-13
+    # compressions at or above the rank discard nothing and stay exact
+    # (Ising copy tensors make bonds rank deficient: chi below the bond size)
+    for shape, chi in (((3, 3, 2), 4), ((2, 2, 5), 32), ((2, 2, 2, 2), 16)):
+        g2 = lattice(shape)
+        T2 = ising_tensors(g2, 0.3)
+        r2 = run(g2, T2, sweep_tree(shape), chi)
+        comp = [o for o in r2.ops if o.kind == "compress"]
+        assert comp and max(o.discarded for o in comp) < 1e-24
+        assert abs(r2.ln_abs_z - exact.ising_brute_force(g2.n, g2.edges, 0.3)) < 1e-12
+
+
+def test_truncation_error_falls_with_chi():
+    g = lattice((8, 8))
+    T = ising_tensors(g, 0.44)
+    tm = exact.ising_transfer_matrix((8, 8), 0.44)
+    pairs = sweep_tree((8, 8))
+    errs = [abs(run(g, T, pairs, chi).ln_abs_z - tm) for chi in (2, 4, 8, 16, 32, 64)]
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-12   # chi = 64 covers every bond of this tree
+
+
+@pytest.mark.parametrize("chi", [2, 4, None])
+def test_homogeneity_in_each_tensor(chi):
+    g = lattice((3, 4))
+    T = normal_tensors(g, 0.2, 11)
+    pairs = sweep_tree((3, 4))
+    base = run(g, T, pairs, chi)
+    for v, alpha in ((0, -3.5), (5, 1e-7), (11, 2.0e5)):
+        T2 = [t.copy() for t in T]
+        T2[v] = T2[v] * alpha
+        r = run(g, T2, pairs, chi)
+        assert r.sign == base.sign * math.copysign(1.0, alpha)
+        assert abs(r.ln_abs_z - (base.ln_abs_z + math.log(abs(alpha)))) < 1e-11
+
+
+def _orthogonal(rng, d):
+    q, r = np.linalg.qr(rng.normal(size=(d, d)))
+    return q * np.sign(np.diag(r))
+
+
+@pytest.mark.parametrize("chi", [2, 3, 8])
+def test_orthogonal_gauge_invariance(chi):
+    """Inserting O O^T on any edge leaves the compressed value unchanged: the
+    QR-reduced truncated SVD only sees the bond space through orthogonally
+    invariant quantities."""
+    g = lattice((3, 4))
+    rng = np.random.default_rng(2)
+    T = normal_tensors(g, 0.25, 4)
+    pairs = sweep_tree((3, 4))
+    base = run(g, T, pairs, chi)
+    inc = g.incident()
+    T2 = [t.copy() for t in T]
+    for e, (u, v, d) in enumerate(g.edges):
+        O = _orthogonal(rng, d)
+        ax_u = inc[u].index(e)
+        ax_v = inc[v].index(e)
+        T2[u] = np.moveaxis(np.tensordot(T2[u], O, axes=([ax_u], [0])), -1, ax_u)
+        T2[v] = np.moveaxis(np.tensordot(T2[v], O, axes=([ax_v], [0])), -1, ax_v)
+    r = run(g, T2, pairs, chi)
+    assert r.sign == base.sign
+    assert abs(r.ln_abs_z - base.ln_abs_z) < 1e-11
+
+
+def test_running_exponent_avoids_overflow():
+    """ln Z ~ 4500 overflows float64 if contracted naively; the running
+    exponent keeps it exact (checked against a transfer matrix)."""
+    g = lattice((3, 3, 60))
+    T = ising_tensors(g, 2.0)
+    tm = exact.ising_transfer_matrix((3, 3, 60), 2.0)
+    assert tm > 709.8
+    r = run(g, T, sweep_tree((3, 3, 60), order=(2, 0, 1)), 1 << 12)
+    assert abs(r.ln_abs_z - tm) / tm < 1e-13

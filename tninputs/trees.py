@@ -17,7 +17,7 @@ import heapq
 import math
 from collections import deque
 from dataclasses import dataclass, field
-from typing import Dict, List, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -295,7 +295,7 @@ def span_tree(g: Graph, seed: int = 0, start: str = "max", temperature: float = 
     return pairs
 
 
-def sweep_tree(shape: Sequence[int]) -> List[Tuple[int, int]]:
+def sweep_tree(shape: Sequence[int], order: Optional[Sequence[int]] = None) -> List[Tuple[int, int]]:
     """Span-family tree on an open-boundary lattice with an axis-ordered spanning tree.
 
     The spanning tree is rooted at the origin; the parent of a site is its
@@ -304,19 +304,24 @@ def sweep_tree(shape: Sequence[int]) -> List[Tuple[int, int]]:
     axis, by distance from the root; contracting them in reverse (SI C.2)
     sweeps a boundary through the lattice along the last axis, then the
     next, like boundary-MPS/PEPS contraction (section III.A) but produced
-    by the generic Span machinery.
+    by the generic Span machinery.  ``order`` lists the axes in spanning-tree
+    order (default 0, 1, ...); the last one listed is contracted first.
     """
     shape = tuple(int(s) for s in shape)
     nd = len(shape)
     n = int(np.prod(shape))
     strides = [int(np.prod(shape[:a])) for a in range(nd)]
+    order = list(range(nd)) if order is None else [int(a) for a in order]
+    if sorted(order) != list(range(nd)):
+        raise ValueError("order must be a permutation of the axes")
+    rank = {a: i for i, a in enumerate(order)}
     tau: List[Tuple[int, int]] = []
-    for a in range(nd):
-        # sites whose last nonzero coordinate is on axis a, ordered by that coordinate
+    for a in order:
+        # sites whose nonzero coordinate latest in ``order`` is on axis a
         sites = []
         for v in range(n):
             c = [(v // strides[b]) % shape[b] for b in range(nd)]
-            nz = [b for b in range(nd) if c[b] > 0]
+            nz = sorted((b for b in range(nd) if c[b] > 0), key=rank.get)
             if nz and nz[-1] == a:
                 sites.append((c[a], tuple(reversed(c)), v))
         sites.sort()
