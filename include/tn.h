@@ -1,0 +1,154 @@
+/*
+ * tn.h — C ABI of the MI355X compressed contraction-tree executor.
+ *
+ * The library evaluates Z, the scalar value of a closed tensor network
+ * (Gray & Chan, arXiv:2206.07044, section I, Eq. (tncontract)), along a
+ * fixed ordered contraction tree with bond compression: Algorithm 1
+ * ("Approximate contraction", section II.F) with early compression and tree
+ * gauge distance r = 0.  Each compression replaces every edge shared by two
+ * tensors with one edge of dimension chi' = min(chi, k_A, k_B) using the
+ * QR-reduced truncated SVD of section II.C, Eq. (svd), applied through the
+ * projectors P_L = R_B V s^-1/2 and P_R = s^-1/2 U^T R_A of SI section B.
+ *
+ * Inputs follow the paper's statement of the problem (Algorithm 1, "Input:
+ * tensor network T, ordered contraction tree, maximum bond dimension chi,
+ * tree gauge distance r, flag compress_late").  All calls return tn_status;
+ * on failure tn_last_error(ctx) describes the cause.  A context is used by
+ * one host thread at a time; distinct contexts are independent.
+ *
+ * Memory: every pointer argument marked "host" is read (or written) only
+ * during the call and stays owned by the caller.  The context owns its
+ * device memory (one arena planned by tn_set_tree) unless a workspace is
+ * supplied with tn_set_workspace, which then stays owned by the caller and
+ * must outlive the context's use of it.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TN_OK = 0,
+    TN_EINVAL = 1,    /* invalid graph, tree, option or argument */
+    TN_ESTATE = 2,    /* call out of order (e.g. contract before set_tree) */
+    TN_ENOMEM = 3,    /* plan exceeds the device budget / allocation failed */
+    TN_EDEVICE = 4,   /* HIP runtime error */
+    TN_ENUMERIC = 5,  /* non-finite value, or a Jacobi SVD that did not converge */
+    TN_ZERO = 6       /* the network evaluates to exactly zero */
+} tn_status;
+
+typedef enum {
+    TN_FP64 = 0,      /* tensors, contractions and re-absorptions in float64 */
+    TN_FP32 = 1,      /* tensors and contractions in float32 on MFMA; Gram, core SVD,
+                         projectors and scale exponents in float64 */
+    TN_BF16 = 2       /* reserved: bfloat16 tensor storage, float32 accumulation */
+} tn_precision;
+
+typedef struct {
+    int32_t chi;                 /* maximum bond dimension (>= 1) */
+    double cutoff;               /* relative singular-value cutoff: sigma_i < cutoff*sigma_1
+                                    contributes a zero column/row (shapes stay static); 0 = none */
+    int32_t compress_late;       /* must be 0: early compression (Algorithm 1, "not compress_late") */
+    int32_t gauge_r;             /* must be 0: compression uses only the two bond-adjacent tensors */
+    int32_t precision;           /* tn_precision */
+    int32_t jacobi_max_sweeps;   /* cap on one-sided Jacobi sweeps per core; 0 = default (40) */
+    int64_t device_budget_bytes; /* refuse plans whose device arena exceeds this; 0 = no limit */
+    int32_t keep_intermediates;  /* 1: never reuse arena memory, so tn_read_tensor can read every
+                                    intermediate after an evaluation (element-wise checks) */
+    int32_t reserved;
+} tn_tree_opts;
+
+typedef struct tn_ctx tn_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t the
+ * library enqueues all work on (e.g. torch's current stream); NULL makes the
+ * library create its own stream of default priority. */
+tn_status tn_create(int device, void* hip_stream, tn_ctx** out);
+void tn_destroy(tn_ctx* ctx);
+/* Text of the last error on ctx (valid until the next call on ctx). */
+const char* tn_last_error(const tn_ctx* ctx);
+
+/* Tensor network (section I, Eq. (tncontract); data structure of
+ * Fig. "tensor primitives"): n_tensors vertices and n_edges edges
+ * (edge_u[e] < edge_v[e], both < n_tensors, edge_dim[e] >= 1; several edges
+ * may join the same two tensors).  Tensor v is dense float64, row-major,
+ * with one axis per incident edge in ascending edge id; its entries are
+ * data[offsets[v] .. offsets[v+1]).  All arrays are host memory.  Replaces
+ * any previous graph and tree. */
+tn_status tn_load_graph(tn_ctx* ctx, int32_t n_tensors, int32_t n_edges,
+                        const int32_t* edge_u, const int32_t* edge_v, const int32_t* edge_dim,
+                        const int64_t* offsets, const double* data);
+
+/* New tensor values, same graph and layout (host float64).  Keeps the plan. */
+tn_status tn_update_values(tn_ctx* ctx, const double* data);
+/* Same, from device memory (float64, same layout); enqueued on the ctx stream. */
+tn_status tn_update_values_device(tn_ctx* ctx, const void* dev_data);
+
+/* Ordered contraction tree (section II.A, Algorithm 1 input): n_steps must be
+ * n_tensors - 1; step t contracts the live tensors pair_i[t] and pair_j[t]
+ * into a new tensor with id n_tensors + t.  Compressions follow from the
+ * order (section II.G): after each contraction every bond of the new tensor
+ * larger than chi is compressed, neighbours in ascending id.  Host arrays.
+ * Plans the device schedule and arena (allocates device memory). */
+tn_status tn_set_tree(tn_ctx* ctx, int32_t n_steps, const int32_t* pair_i, const int32_t* pair_j,
+                      const tn_tree_opts* opts);
+
+/* Plan summary: device arena bytes, algorithmic forward flops and bytes
+ * (SI section D cost model, 2 flops per multiply-add), number of kernel
+ * steps.  Any pointer may be NULL. */
+tn_status tn_plan_info(const tn_ctx* ctx, int64_t* arena_bytes, double* fwd_flops, double* fwd_bytes,
+                       int32_t* n_steps);
+
+/* Evaluate the compressed contraction.  Z = mantissa * 10^log10_exponent
+ * with 1 <= |mantissa| < 10 (host outputs).  Synchronises the ctx stream.
+ * TN_ZERO: Z == 0 (mantissa 0, exponent -inf). */
+tn_status tn_contract_compressed(tn_ctx* ctx, double* mantissa, double* log10_exponent);
+
+/* The last evaluation as sign (+1, -1 or 0) and natural log of |Z|. */
+tn_status tn_result(const tn_ctx* ctx, double* sign, double* ln_abs_z);
+
+/* Enqueue an evaluation without synchronising (for timing and batching);
+ * tn_result after a stream synchronisation reads it. */
+tn_status tn_enqueue(tn_ctx* ctx);
+tn_status tn_fetch(tn_ctx* ctx);
+
+/* Per-compression diagnostics of the last evaluation, in schedule order:
+ * discarded[c] = sum of discarded sigma^2 / sum sigma^2, tie[c] = 1 when the
+ * last kept and first discarded singular values differ by <= 1e-12 sigma_1
+ * (several truncations are then equally correct), sweeps[c] = Jacobi sweeps.
+ * Arrays hold `cap` entries; *n_out receives the number of compressions. */
+tn_status tn_compress_stats(const tn_ctx* ctx, int32_t cap, double* discarded, int32_t* tie,
+                            int32_t* sweeps, int32_t* n_out);
+
+/* Tensor `index` of the last evaluation, normalised (divided by its largest
+ * absolute entry), as float64 in its axis order.  Indices count tensors in
+ * creation order: inputs 0..n-1, then each contraction's result, then the two
+ * re-absorbed tensors of each compression.  Needs keep_intermediates = 1 for
+ * anything but inputs and the final scalar.  Writes up to `cap` entries to
+ * host `out`; *n receives the tensor's size. */
+tn_status tn_read_tensor(const tn_ctx* ctx, int32_t index, double* out, int64_t cap, int64_t* n);
+
+/* d ln|Z| / d data for the last evaluated tree (host float64, same layout
+ * as tn_load_graph's data).  TN_ESTATE before an evaluation. */
+tn_status tn_grad(tn_ctx* ctx, double* dlnz_ddata);
+
+/* Host-only expansion of Algorithm 1 on shapes (no device use): writes up
+ * to `cap` ops as 8 int64 each: (kind, a, b, out, m, n, k, new_dim) with
+ * kind 0 = contract: (i, j, new id, free size of i, shared size, free size of
+ * j, 0); kind 1 = compress: (tensor, neighbour, new edge id, rows of A_mat,
+ * D_AB, columns of B_mat, chi').  *n_ops receives the total count. */
+tn_status tn_plan_describe(int32_t n_tensors, int32_t n_edges, const int32_t* edge_u, const int32_t* edge_v,
+                           const int32_t* edge_dim, int32_t n_steps, const int32_t* pair_i,
+                           const int32_t* pair_j, const tn_tree_opts* opts, int64_t cap, int64_t* ops,
+                           int64_t* n_ops);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H */

@@ -49,6 +49,7 @@ class OracleResult:
     ln_abs_z: float
     ops: List[OpRecord] = field(default_factory=list)
     log_scales: List[float] = field(default_factory=list)
+    tensors: List[np.ndarray] = field(default_factory=list)   # normalised, creation order (record=True)
 
     @property
     def log10_exponent(self) -> float:
@@ -100,6 +101,9 @@ class _Network:
         return out
 
 
+_RECORD: Optional[List[np.ndarray]] = None
+
+
 def _normalise(arr: np.ndarray, scales: List[float]) -> np.ndarray:
     s = float(np.max(np.abs(arr))) if arr.size else 0.0
     if s == 0.0 or not math.isfinite(s):
@@ -107,7 +111,10 @@ def _normalise(arr: np.ndarray, scales: List[float]) -> np.ndarray:
             raise ZeroContraction()
         raise FloatingPointError("non-finite tensor entry")
     scales.append(math.log(s))
-    return arr / s
+    out = arr / s
+    if _RECORD is not None:
+        _RECORD.append(out.copy())
+    return out
 
 
 def _contract(net: _Network, i: int, j: int, k: int, scales: List[float], ops: List[OpRecord]) -> None:
@@ -202,14 +209,27 @@ def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
 
 def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
                         pairs: Sequence[Tuple[int, int]], chi: Optional[int], cutoff: float = 0.0,
-                        explicit: bool = False) -> OracleResult:
+                        explicit: bool = False, record: bool = False) -> OracleResult:
     """Run Algorithm 1 (early compression, r = 0) and return sign and ln|Z|.
 
     ``chi=None`` is exact contraction (no compression).  Step t of ``pairs``
     contracts live tensors (i, j) into a new tensor with id n + t; after each
     contraction every bond of the new tensor larger than chi is compressed,
-    neighbours in ascending id.
+    neighbours in ascending id.  With ``record`` every normalised tensor is
+    kept in creation order (inputs, then each op's outputs).
     """
+    global _RECORD
+    _RECORD = [] if record else None
+    try:
+        res = _run(n, edges, tensors, pairs, chi, cutoff, explicit)
+    finally:
+        rec, _RECORD = _RECORD, None
+    if record:
+        res.tensors = rec
+    return res
+
+
+def _run(n, edges, tensors, pairs, chi, cutoff, explicit) -> OracleResult:
     net = _Network(n, edges, tensors)
     scales: List[float] = []
     ops: List[OpRecord] = []

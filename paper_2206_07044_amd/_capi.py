@@ -1,0 +1,215 @@
+"""ctypes binding of libtn.so (include/tn.h): argument marshalling only.
+
+Every step of the contraction runs in the library's HIP kernels; there is no
+Python or CPU fallback.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtn.so")
+
+TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO = range(7)
+STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ESTATE", 3: "TN_ENOMEM", 4: "TN_EDEVICE",
+                5: "TN_ENUMERIC", 6: "TN_ZERO"}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+
+class TNError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class tn_tree_opts(C.Structure):
+    _fields_ = [("chi", C.c_int32), ("cutoff", C.c_double), ("compress_late", C.c_int32),
+                ("gauge_r", C.c_int32), ("precision", C.c_int32), ("jacobi_max_sweeps", C.c_int32),
+                ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None) -> C.CDLL:
+    """Load libtn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: run `python -m paper_2206_07044_amd.build` first")
+    lib = C.CDLL(p)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    pI32, pI64, pD = C.POINTER(I32), C.POINTER(I64), C.POINTER(D)
+    sig = {
+        "tn_create": ([C.c_int, P, C.POINTER(P)], C.c_int),
+        "tn_destroy": ([P], None),
+        "tn_last_error": ([P], C.c_char_p),
+        "tn_load_graph": ([P, I32, I32, pI32, pI32, pI32, pI64, pD], C.c_int),
+        "tn_update_values": ([P, pD], C.c_int),
+        "tn_update_values_device": ([P, P], C.c_int),
+        "tn_set_tree": ([P, I32, pI32, pI32, C.POINTER(tn_tree_opts)], C.c_int),
+        "tn_plan_info": ([P, pI64, pD, pD, pI32], C.c_int),
+        "tn_contract_compressed": ([P, pD, pD], C.c_int),
+        "tn_result": ([P, pD, pD], C.c_int),
+        "tn_enqueue": ([P], C.c_int),
+        "tn_fetch": ([P], C.c_int),
+        "tn_compress_stats": ([P, I32, pD, pI32, pI32, pI32], C.c_int),
+        "tn_grad": ([P, pD], C.c_int),
+        "tn_read_tensor": ([P, I32, pD, I64, pI64], C.c_int),
+        "tn_plan_describe": ([I32, I32, pI32, pI32, pI32, I32, pI32, pI32, C.POINTER(tn_tree_opts), I64, pI64, pI64],
+                             C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> List[str]:
+    return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
+            "tn_update_values_device", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
+            "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_grad", "tn_plan_describe"]
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def make_opts(chi: int, precision: str = "fp64", cutoff: float = 0.0, max_sweeps: int = 0,
+              budget: int = 0, keep: bool = False) -> tn_tree_opts:
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    return tn_tree_opts(int(chi), float(cutoff), 0, 0, PRECISIONS[precision], int(max_sweeps), int(budget),
+                        int(bool(keep)), 0)
+
+
+def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int) -> List[Tuple[int, ...]]:
+    """Host-only Algorithm 1 expansion: list of (kind, a, b, out, m, n, k, new_dim)."""
+    lib = load_library()
+    eu, ev, ed, pi, pj = map(_i32, (edge_u, edge_v, edge_dim, pair_i, pair_j))
+    opts = make_opts(chi)
+    n_ops = C.c_int64(0)
+    st = lib.tn_plan_describe(n, eu.size, _ptr(eu, C.c_int32), _ptr(ev, C.c_int32), _ptr(ed, C.c_int32), pi.size,
+                              _ptr(pi, C.c_int32), _ptr(pj, C.c_int32), C.byref(opts), 0, None, C.byref(n_ops))
+    if st != TN_OK:
+        raise TNError(st, "invalid graph or tree")
+    buf = np.zeros((max(1, n_ops.value), 8), dtype=np.int64)
+    st = lib.tn_plan_describe(n, eu.size, _ptr(eu, C.c_int32), _ptr(ev, C.c_int32), _ptr(ed, C.c_int32), pi.size,
+                              _ptr(pi, C.c_int32), _ptr(pj, C.c_int32), C.byref(opts), n_ops.value,
+                              _ptr(buf, C.c_int64), C.byref(n_ops))
+    if st != TN_OK:
+        raise TNError(st, "invalid graph or tree")
+    return [tuple(int(x) for x in row) for row in buf[:n_ops.value]]
+
+
+class Context:
+    """One tn_ctx: a graph, a planned tree and its device arena."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self._lib = load_library()
+        self._h = C.c_void_p()
+        st = self._lib.tn_create(int(device), C.c_void_p(stream) if stream else None, C.byref(self._h))
+        if st != TN_OK:
+            raise TNError(st, "tn_create failed (no HIP device?)")
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.tn_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int) -> int:
+        if st != TN_OK:
+            msg = self._lib.tn_last_error(self._h)
+            raise TNError(st, msg.decode() if msg else "")
+        return st
+
+    def tn_load_graph(self, n: int, edge_u, edge_v, edge_dim, offsets, data) -> None:
+        eu, ev, ed = map(_i32, (edge_u, edge_v, edge_dim))
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self._data = np.ascontiguousarray(data, dtype=np.float64)
+        self._check(self._lib.tn_load_graph(self._h, int(n), eu.size, _ptr(eu, C.c_int32), _ptr(ev, C.c_int32),
+                                            _ptr(ed, C.c_int32), _ptr(off, C.c_int64),
+                                            _ptr(self._data, C.c_double)))
+
+    def tn_update_values(self, data) -> None:
+        d = np.ascontiguousarray(data, dtype=np.float64)
+        self._check(self._lib.tn_update_values(self._h, _ptr(d, C.c_double)))
+
+    def tn_update_values_device(self, dev_ptr: int) -> None:
+        self._check(self._lib.tn_update_values_device(self._h, C.c_void_p(dev_ptr)))
+
+    def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
+                    max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False) -> None:
+        pi, pj = _i32(pair_i), _i32(pair_j)
+        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates)
+        self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
+                                          C.byref(opts)))
+
+    def tn_plan_info(self) -> dict:
+        ab, ff, fb, ns = C.c_int64(), C.c_double(), C.c_double(), C.c_int32()
+        self._check(self._lib.tn_plan_info(self._h, C.byref(ab), C.byref(ff), C.byref(fb), C.byref(ns)))
+        return {"arena_bytes": ab.value, "fwd_flops": ff.value, "fwd_bytes": fb.value, "n_steps": ns.value}
+
+    def tn_contract_compressed(self) -> Tuple[float, float]:
+        m, e = C.c_double(), C.c_double()
+        st = self._lib.tn_contract_compressed(self._h, C.byref(m), C.byref(e))
+        if st == TN_ZERO:
+            return 0.0, float("-inf")
+        self._check(st)
+        return m.value, e.value
+
+    def tn_result(self) -> Tuple[float, float]:
+        s, l = C.c_double(), C.c_double()
+        self._check(self._lib.tn_result(self._h, C.byref(s), C.byref(l)))
+        return s.value, l.value
+
+    def tn_enqueue(self) -> None:
+        self._check(self._lib.tn_enqueue(self._h))
+
+    def tn_fetch(self) -> int:
+        st = self._lib.tn_fetch(self._h)
+        if st not in (TN_OK, TN_ZERO):
+            self._check(st)
+        return st
+
+    def tn_compress_stats(self):
+        n = C.c_int32()
+        self._check(self._lib.tn_compress_stats(self._h, 0, None, None, None, C.byref(n)))
+        k = max(1, n.value)
+        disc = np.zeros(k)
+        tie = np.zeros(k, dtype=np.int32)
+        sw = np.zeros(k, dtype=np.int32)
+        self._check(self._lib.tn_compress_stats(self._h, n.value, _ptr(disc, C.c_double), _ptr(tie, C.c_int32),
+                                                _ptr(sw, C.c_int32), C.byref(n)))
+        return disc[:n.value], tie[:n.value], sw[:n.value]
+
+    def tn_read_tensor(self, index: int) -> np.ndarray:
+        n = C.c_int64()
+        self._check(self._lib.tn_read_tensor(self._h, int(index), None, 0, C.byref(n)))
+        out = np.zeros(max(1, n.value))
+        self._check(self._lib.tn_read_tensor(self._h, int(index), _ptr(out, C.c_double), n.value, C.byref(n)))
+        return out[:n.value]
+
+    def tn_grad(self, out: Optional[np.ndarray] = None) -> np.ndarray:
+        g = np.zeros_like(self._data) if out is None else out
+        self._check(self._lib.tn_grad(self._h, _ptr(g, C.c_double)))
+        return g

@@ -1,0 +1,630 @@
+// C ABI (include/tn.h): context, device arena, schedule upload and execution.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/tn.h"
+#include "tn_kernels.hpp"
+#include "tn_plan.hpp"
+
+using namespace tn;
+
+namespace {
+
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE };
+
+struct Launch {
+    int kind = 0;
+    int key = 0;          // GEMM dtype key / COPY source f32 / CORE lds flag
+    int64_t begin = 0;    // first descriptor
+    int count = 0;
+    int64_t work = 0;     // tiles / elements
+    int max_d = 0;
+};
+
+}  // namespace
+
+struct tn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    GraphSpec g;
+    bool has_graph = false;
+    int64_t n_input_elems = 0;
+    double* d_staging = nullptr;
+
+    Plan plan;
+    bool has_plan = false;
+    char* arena = nullptr;
+    size_t arena_cap = 0;
+
+    std::vector<GemmDesc> h_gemm;
+    std::vector<CopyDesc> h_copy;
+    std::vector<CoreDesc> h_core;
+    std::vector<ScaleDesc> h_scale;
+    std::vector<InputDesc> h_inputs;
+    std::vector<Launch> launches;
+    GemmDesc* d_gemm = nullptr;
+    CopyDesc* d_copy = nullptr;
+    CoreDesc* d_core = nullptr;
+    ScaleDesc* d_scale = nullptr;
+    InputDesc* d_inputs = nullptr;
+    double* d_scales = nullptr;
+    double* d_maxparts = nullptr;
+    double* d_disc = nullptr;
+    int32_t* d_tie = nullptr;
+    int32_t* d_sweeps = nullptr;
+    double* d_result = nullptr;
+    double* h_result = nullptr;
+
+    bool evaluated = false;
+    double sign = 0, lnz = 0;
+    int flags = 0;
+};
+
+namespace {
+
+tn_status fail(tn_ctx* c, tn_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, TN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void free_plan(tn_ctx* c) {
+    dfree(c->arena);
+    c->arena_cap = 0;
+    dfree(c->d_gemm);
+    dfree(c->d_copy);
+    dfree(c->d_core);
+    dfree(c->d_scale);
+    dfree(c->d_inputs);
+    dfree(c->d_scales);
+    dfree(c->d_maxparts);
+    dfree(c->d_disc);
+    dfree(c->d_tie);
+    dfree(c->d_sweeps);
+    c->h_gemm.clear();
+    c->h_copy.clear();
+    c->h_core.clear();
+    c->h_scale.clear();
+    c->h_inputs.clear();
+    c->launches.clear();
+    c->has_plan = false;
+    c->evaluated = false;
+}
+
+template <typename T>
+tn_status upload(tn_ctx* c, T** dst, const std::vector<T>& src) {
+    dfree(*dst);
+    if (src.empty()) return TN_OK;
+    HIP_TRY(c, hipMalloc((void**)dst, src.size() * sizeof(T)));
+    HIP_TRY(c, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return TN_OK;
+}
+
+std::string fill_view(const ViewSpec& s, View* v) { return make_view(s, v); }
+
+// Turn the plan's levelled steps into grouped launch descriptors.
+tn_status build_launches(tn_ctx* c) {
+    Plan& P = c->plan;
+    const bool f32 = P.opts.precision == 1;
+    char* base = c->arena;
+    auto buf_ptr = [&](int32_t b) -> char* { return base + P.bufs[b].off; };
+    auto ten_ptr = [&](int32_t t) -> char* { return buf_ptr(P.tens[t].buf); };
+
+    std::vector<std::vector<int32_t>> by_level(P.n_levels + 1);
+    for (int32_t s = 0; s < (int32_t)P.steps.size(); ++s) by_level[P.steps[s].level].push_back(s);
+    int64_t max_parts = 1;
+    for (int L = 1; L <= P.n_levels; ++L) {
+        std::map<int, std::vector<GemmDesc>> gemms;   // key -> descs
+        std::vector<CopyDesc> copies;
+        std::vector<CoreDesc> cores_lds, cores_glb;
+        std::vector<ScaleDesc> scales;
+        int64_t parts = 0;
+        for (int32_t si : by_level[L]) {
+            const Step& st = P.steps[si];
+            if (st.kind == ST_CONTRACT || st.kind == ST_ABSORB || st.kind == ST_GRAM) {
+                GemmDesc g;
+                std::memset(&g, 0, sizeof(g));
+                std::string err = fill_view(st.va, &g.va);
+                if (err.empty()) err = fill_view(st.vb, &g.vb);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                g.M = (int32_t)st.M;
+                g.N = (int32_t)st.N;
+                g.K = (int32_t)st.K;
+                g.tiles_m = (int32_t)((st.M + 63) / 64);
+                g.tiles_n = (int32_t)((st.N + 63) / 64);
+                g.scale_a = g.scale_b = -1;
+                int key;
+                if (st.kind == ST_GRAM) {
+                    g.mode = GEMM_GRAM;
+                    g.A = ten_ptr(st.in_a);
+                    g.B = ten_ptr(st.in_a);
+                    g.C = buf_ptr(st.out_buf);
+                    g.splits = st.splits;
+                    g.k_per_split = st.k_per_split;
+                    g.scale_a = st.in_a;
+                    g.square_a = 1;
+                    key = f32 ? GEMM_F32_TO_F64 : GEMM_F64;
+                } else {
+                    g.mode = GEMM_TENSOR;
+                    g.splits = 1;
+                    g.k_per_split = (int32_t)st.K;
+                    if (st.kind == ST_CONTRACT) {
+                        g.A = ten_ptr(st.in_a);
+                        g.B = ten_ptr(st.in_b);
+                        g.scale_a = st.in_a;
+                        g.scale_b = st.in_b;
+                    } else if (st.proj_left) {
+                        g.A = ten_ptr(st.in_a);
+                        g.B = buf_ptr(st.proj_buf);
+                        g.scale_a = st.in_a;
+                    } else {
+                        g.A = buf_ptr(st.proj_buf);
+                        g.B = ten_ptr(st.in_a);
+                        g.scale_b = st.in_a;
+                    }
+                    g.C = ten_ptr(st.out_t);
+                    g.maxpart = (int32_t)parts;
+                    ScaleDesc sd{};
+                    sd.maxpart = (int32_t)parts;
+                    sd.nparts = g.tiles_m * g.tiles_n;
+                    sd.tensor = st.out_t;
+                    scales.push_back(sd);
+                    parts += sd.nparts;
+                    key = f32 ? GEMM_F32 : GEMM_F64;
+                }
+                gemms[key].push_back(g);
+            } else if (st.kind == ST_COPY) {
+                CopyDesc cd;
+                std::memset(&cd, 0, sizeof(cd));
+                std::string err = fill_view(st.va, &cd.v);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                cd.src = ten_ptr(st.in_a);
+                cd.dst = (double*)buf_ptr(st.out_buf);
+                cd.rows = st.copy_rows;
+                cd.cols = st.copy_cols;
+                cd.scale = st.in_a;
+                copies.push_back(cd);
+            } else if (st.kind == ST_CORE) {
+                const Compression& cp = P.comps[st.comp];
+                CoreDesc cd;
+                std::memset(&cd, 0, sizeof(cd));
+                cd.gram_a = cp.gram_a ? (const double*)buf_ptr(cp.side_a_buf) : nullptr;
+                cd.fac_a = cp.gram_a ? nullptr : (const double*)buf_ptr(cp.side_a_buf);
+                cd.gram_b = cp.gram_b ? (const double*)buf_ptr(cp.side_b_buf) : nullptr;
+                cd.fac_b = cp.gram_b ? nullptr : (const double*)buf_ptr(cp.side_b_buf);
+                cd.splits_a = cp.splits_a;
+                cd.splits_b = cp.splits_b;
+                cd.rows_a = cp.rows_a;
+                cd.rows_b = cp.rows_b;
+                cd.D = (int32_t)cp.D;
+                cd.chi_new = cp.chi_new;
+                cd.cutoff = P.opts.cutoff;
+                cd.work = (double*)buf_ptr(cp.work_buf);
+                cd.p_left = buf_ptr(cp.pl_buf);
+                cd.p_right = buf_ptr(cp.pr_buf);
+                cd.stat = st.comp;
+                cd.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
+                (cp.D <= kCoreLdsMaxD ? cores_lds : cores_glb).push_back(cd);
+            }
+        }
+        max_parts = std::max(max_parts, parts);
+        for (auto& kv : gemms) {
+            Launch l;
+            l.kind = L_GEMM;
+            l.key = kv.first;
+            l.begin = (int64_t)c->h_gemm.size();
+            l.count = (int)kv.second.size();
+            int64_t tiles = 0;
+            for (auto& g : kv.second) {
+                g.tile_begin = tiles;
+                tiles += (int64_t)g.tiles_m * g.tiles_n * g.splits;
+                c->h_gemm.push_back(g);
+            }
+            l.work = tiles;
+            c->launches.push_back(l);
+        }
+        if (!copies.empty()) {
+            Launch l;
+            l.kind = L_COPY;
+            l.key = f32 ? 1 : 0;
+            l.begin = (int64_t)c->h_copy.size();
+            l.count = (int)copies.size();
+            int64_t elems = 0;
+            for (auto& cd : copies) {
+                cd.elem_begin = elems;
+                elems += (int64_t)cd.rows * cd.cols;
+                c->h_copy.push_back(cd);
+            }
+            l.work = elems;
+            c->launches.push_back(l);
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+            auto& v = pass == 0 ? cores_lds : cores_glb;
+            if (v.empty()) continue;
+            Launch l;
+            l.kind = L_CORE;
+            l.key = pass == 0 ? 1 : 0;
+            l.begin = (int64_t)c->h_core.size();
+            l.count = (int)v.size();
+            for (auto& cd : v) {
+                l.max_d = std::max(l.max_d, cd.D);
+                c->h_core.push_back(cd);
+            }
+            c->launches.push_back(l);
+        }
+        if (!scales.empty()) {
+            Launch l;
+            l.kind = L_SCALE;
+            l.begin = (int64_t)c->h_scale.size();
+            l.count = (int)scales.size();
+            for (auto& sd : scales) c->h_scale.push_back(sd);
+            c->launches.push_back(l);
+        }
+    }
+    // inputs
+    for (int v = 0; v < c->g.n; ++v) {
+        InputDesc d{};
+        d.dst = ten_ptr(v);
+        d.src_off = c->g.offsets[v];
+        d.count = c->g.offsets[v + 1] - c->g.offsets[v];
+        d.tensor = v;
+        c->h_inputs.push_back(d);
+    }
+    tn_status s;
+    if ((s = upload(c, &c->d_gemm, c->h_gemm)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_copy, c->h_copy)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_core, c->h_core)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_scale, c->h_scale)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_inputs, c->h_inputs)) != TN_OK) return s;
+    HIP_TRY(c, hipMalloc((void**)&c->d_scales, std::max<size_t>(1, P.tens.size()) * sizeof(double)));
+    HIP_TRY(c, hipMalloc((void**)&c->d_maxparts, (size_t)max_parts * sizeof(double)));
+    const size_t nc = std::max<size_t>(1, P.comps.size());
+    HIP_TRY(c, hipMalloc((void**)&c->d_disc, nc * sizeof(double)));
+    HIP_TRY(c, hipMalloc((void**)&c->d_tie, nc * sizeof(int32_t)));
+    HIP_TRY(c, hipMalloc((void**)&c->d_sweeps, nc * sizeof(int32_t)));
+    HIP_TRY(c, hipMemset(c->d_sweeps, 0, nc * sizeof(int32_t)));
+    P.max_parts = max_parts;
+    return TN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_create(int device, void* hip_stream, tn_ctx** out) {
+    if (!out) return TN_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return TN_EDEVICE;
+    if (device < 0 || device >= n) return TN_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TN_EDEVICE;
+    tn_ctx* c = new tn_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return TN_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (hipHostMalloc((void**)&c->h_result, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&c->d_result, 4 * sizeof(double)) != hipSuccess) {
+        delete c;
+        return TN_EDEVICE;
+    }
+    init_kernel_attrs();
+    *out = c;
+    return TN_OK;
+}
+
+void tn_destroy(tn_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_plan(c);
+    dfree(c->d_staging);
+    dfree(c->d_result);
+    if (c->h_result) (void)hipHostFree(c->h_result);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* tn_last_error(const tn_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+tn_status tn_load_graph(tn_ctx* c, int32_t n_tensors, int32_t n_edges, const int32_t* edge_u, const int32_t* edge_v,
+                        const int32_t* edge_dim, const int64_t* offsets, const double* data) {
+    if (!c) return TN_EINVAL;
+    if (n_tensors < 1 || n_edges < 0 || !offsets || !data || (n_edges > 0 && (!edge_u || !edge_v || !edge_dim)))
+        return fail(c, TN_EINVAL, "missing graph arrays");
+    (void)hipSetDevice(c->device);
+    free_plan(c);
+    GraphSpec g;
+    g.n = n_tensors;
+    g.ne = n_edges;
+    g.eu.assign(edge_u, edge_u + n_edges);
+    g.ev.assign(edge_v, edge_v + n_edges);
+    g.ed.assign(edge_dim, edge_dim + n_edges);
+    g.offsets.assign(offsets, offsets + n_tensors + 1);
+    std::string err = check_graph(g);
+    if (!err.empty()) {
+        c->has_graph = false;
+        return fail(c, TN_EINVAL, err);
+    }
+    c->g = g;
+    c->has_graph = true;
+    c->n_input_elems = g.offsets[n_tensors];
+    dfree(c->d_staging);
+    HIP_TRY(c, hipMalloc((void**)&c->d_staging, std::max<int64_t>(1, c->n_input_elems) * sizeof(double)));
+    HIP_TRY(c, hipMemcpy(c->d_staging, data, c->n_input_elems * sizeof(double), hipMemcpyHostToDevice));
+    return TN_OK;
+}
+
+tn_status tn_update_values(tn_ctx* c, const double* data) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_graph) return fail(c, TN_ESTATE, "no graph loaded");
+    if (!data) return fail(c, TN_EINVAL, "null data");
+    (void)hipSetDevice(c->device);
+    HIP_TRY(c, hipMemcpyAsync(c->d_staging, data, c->n_input_elems * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->evaluated = false;
+    return TN_OK;
+}
+
+tn_status tn_update_values_device(tn_ctx* c, const void* dev_data) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_graph) return fail(c, TN_ESTATE, "no graph loaded");
+    if (!dev_data) return fail(c, TN_EINVAL, "null data");
+    (void)hipSetDevice(c->device);
+    HIP_TRY(c, hipMemcpyAsync(c->d_staging, dev_data, c->n_input_elems * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->stream));
+    c->evaluated = false;
+    return TN_OK;
+}
+
+tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const int32_t* pair_j,
+                      const tn_tree_opts* opts) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_graph) return fail(c, TN_ESTATE, "tn_set_tree before tn_load_graph");
+    if (!opts || (n_steps > 0 && (!pair_i || !pair_j))) return fail(c, TN_EINVAL, "missing tree arrays or options");
+    if (opts->gauge_r != 0) return fail(c, TN_EINVAL, "gauge_r must be 0 (local compression only)");
+    if (opts->compress_late != 0) return fail(c, TN_EINVAL, "compress_late must be 0 (early compression)");
+    if (opts->precision != TN_FP64 && opts->precision != TN_FP32)
+        return fail(c, TN_EINVAL, "precision must be TN_FP64 or TN_FP32");
+    if (!(opts->cutoff >= 0.0)) return fail(c, TN_EINVAL, "cutoff must be >= 0");
+    (void)hipSetDevice(c->device);
+    free_plan(c);
+    TreeOpts o;
+    o.chi = opts->chi;
+    o.cutoff = opts->cutoff;
+    o.precision = opts->precision;
+    o.jacobi_max_sweeps = opts->jacobi_max_sweeps > 0 ? opts->jacobi_max_sweeps : 40;
+    o.budget = opts->device_budget_bytes;
+    o.keep = opts->keep_intermediates;
+    std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
+    if (!err.empty()) {
+        const bool nomem = err.rfind("plan needs", 0) == 0;
+        return fail(c, nomem ? TN_ENOMEM : TN_EINVAL, err);
+    }
+    const size_t bytes = (size_t)std::max<int64_t>(c->plan.arena_bytes, 256);
+    hipError_t e = hipMalloc((void**)&c->arena, bytes);
+    if (e != hipSuccess) {
+        c->arena = nullptr;
+        return fail(c, TN_ENOMEM, std::string("arena of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    }
+    c->arena_cap = bytes;
+    tn_status s = build_launches(c);
+    if (s != TN_OK) {
+        free_plan(c);
+        return s;
+    }
+    c->has_plan = true;
+    return TN_OK;
+}
+
+tn_status tn_plan_info(const tn_ctx* c, int64_t* arena_bytes, double* fwd_flops, double* fwd_bytes,
+                       int32_t* n_steps) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan) return TN_ESTATE;
+    if (arena_bytes) *arena_bytes = c->plan.arena_bytes;
+    if (fwd_flops) *fwd_flops = c->plan.fwd_flops;
+    if (fwd_bytes) *fwd_bytes = c->plan.fwd_bytes;
+    if (n_steps) *n_steps = (int32_t)c->plan.steps.size();
+    return TN_OK;
+}
+
+tn_status tn_enqueue(tn_ctx* c) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan) return fail(c, TN_ESTATE, "evaluate before tn_set_tree");
+    (void)hipSetDevice(c->device);
+    Plan& P = c->plan;
+    const bool f32 = P.opts.precision == 1;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, launch_inputs(f32, c->d_inputs, (int)c->h_inputs.size(), c->d_staging, c->d_scales, s));
+    for (const Launch& l : c->launches) {
+        switch (l.kind) {
+            case L_GEMM:
+                HIP_TRY(c, launch_gemm(l.key, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, s));
+                break;
+            case L_COPY:
+                HIP_TRY(c, launch_copy(l.key, c->d_copy + l.begin, l.count, l.work, c->d_scales, s));
+                break;
+            case L_CORE:
+                HIP_TRY(c, launch_core(l.key, f32, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
+                                       c->d_disc, c->d_tie, c->d_sweeps, s));
+                break;
+            case L_SCALE:
+                HIP_TRY(c, launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, s));
+                break;
+        }
+    }
+    const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
+    HIP_TRY(c, launch_result(f32, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
+                             c->d_result, s));
+    HIP_TRY(c, hipMemcpyAsync(c->h_result, c->d_result, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    return TN_OK;
+}
+
+tn_status tn_fetch(tn_ctx* c) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan) return fail(c, TN_ESTATE, "no plan");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->sign = c->h_result[0];
+    c->lnz = c->h_result[1];
+    c->flags = (int)c->h_result[2];
+    c->evaluated = true;
+    if (c->flags & 2) return fail(c, TN_ENUMERIC, "non-finite tensor entry");
+    if (c->flags & 4) return fail(c, TN_ENUMERIC, "a Jacobi SVD did not converge within the sweep cap");
+    if ((c->flags & 1) || c->sign == 0.0) {
+        c->sign = 0.0;
+        c->lnz = -INFINITY;
+        return fail(c, TN_ZERO, "the network evaluates to zero");
+    }
+    return TN_OK;
+}
+
+tn_status tn_contract_compressed(tn_ctx* c, double* mantissa, double* log10_exponent) {
+    tn_status s = tn_enqueue(c);
+    if (s != TN_OK) return s;
+    s = tn_fetch(c);
+    if (s == TN_ZERO) {
+        if (mantissa) *mantissa = 0.0;
+        if (log10_exponent) *log10_exponent = -INFINITY;
+        return s;
+    }
+    if (s != TN_OK) return s;
+    const double l10 = c->lnz / std::log(10.0);
+    const double ex = std::floor(l10);
+    double m = std::pow(10.0, l10 - ex);
+    if (m >= 10.0) m /= 10.0;   // guard against rounding at the boundary
+    if (mantissa) *mantissa = c->sign * m;
+    if (log10_exponent) *log10_exponent = ex;
+    return TN_OK;
+}
+
+tn_status tn_result(const tn_ctx* c, double* sign, double* ln_abs_z) {
+    if (!c) return TN_EINVAL;
+    if (!c->evaluated) return TN_ESTATE;
+    if (sign) *sign = c->sign;
+    if (ln_abs_z) *ln_abs_z = c->lnz;
+    return TN_OK;
+}
+
+tn_status tn_compress_stats(const tn_ctx* c0, int32_t cap, double* discarded, int32_t* tie, int32_t* sweeps,
+                            int32_t* n_out) {
+    tn_ctx* c = const_cast<tn_ctx*>(c0);
+    if (!c) return TN_EINVAL;
+    if (!c->evaluated) return fail(c, TN_ESTATE, "no evaluation yet");
+    const int n = (int)c->plan.comps.size();
+    if (n_out) *n_out = n;
+    const int k = std::min(n, std::max(0, cap));
+    if (k > 0) {
+        if (discarded) HIP_TRY(c, hipMemcpy(discarded, c->d_disc, k * sizeof(double), hipMemcpyDeviceToHost));
+        if (tie) HIP_TRY(c, hipMemcpy(tie, c->d_tie, k * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (sweeps) HIP_TRY(c, hipMemcpy(sweeps, c->d_sweeps, k * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return TN_OK;
+}
+
+tn_status tn_read_tensor(const tn_ctx* c0, int32_t index, double* out, int64_t cap, int64_t* n) {
+    tn_ctx* c = const_cast<tn_ctx*>(c0);
+    if (!c) return TN_EINVAL;
+    if (!c->evaluated) return fail(c, TN_ESTATE, "no evaluation yet");
+    const Plan& P = c->plan;
+    if (index < 0 || index >= (int32_t)P.tens.size()) return fail(c, TN_EINVAL, "tensor index out of range");
+    const TensorVer& t = P.tens[index];
+    if (n) *n = t.size;
+    const int64_t k = std::min<int64_t>(std::max<int64_t>(cap, 0), t.size);
+    if (k == 0 || !out) return TN_OK;
+    (void)hipSetDevice(c->device);
+    double s = 0.0;
+    HIP_TRY(c, hipMemcpy(&s, c->d_scales + index, sizeof(double), hipMemcpyDeviceToHost));
+    const char* src = c->arena + P.bufs[t.buf].off;
+    if (P.elem_size == 8) {
+        HIP_TRY(c, hipMemcpy(out, src, k * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(k);
+        HIP_TRY(c, hipMemcpy(tmp.data(), src, k * sizeof(float), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < k; ++i) out[i] = tmp[i];
+    }
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int64_t i = 0; i < k; ++i) out[i] *= inv;
+    return TN_OK;
+}
+
+tn_status tn_grad(tn_ctx* c, double* dlnz_ddata) {
+    if (!c) return TN_EINVAL;
+    (void)dlnz_ddata;
+    if (!c->evaluated) return fail(c, TN_ESTATE, "tn_grad before an evaluation");
+    return fail(c, TN_EINVAL, "the backward pass is not available in this build");
+}
+
+tn_status tn_plan_describe(int32_t n_tensors, int32_t n_edges, const int32_t* edge_u, const int32_t* edge_v,
+                           const int32_t* edge_dim, int32_t n_steps, const int32_t* pair_i, const int32_t* pair_j,
+                           const tn_tree_opts* opts, int64_t cap, int64_t* ops, int64_t* n_ops) {
+    if (n_tensors < 1 || n_edges < 0 || !opts || !n_ops) return TN_EINVAL;
+    if (n_edges > 0 && (!edge_u || !edge_v || !edge_dim)) return TN_EINVAL;
+    if (n_steps > 0 && (!pair_i || !pair_j)) return TN_EINVAL;
+    GraphSpec g;
+    g.n = n_tensors;
+    g.ne = n_edges;
+    g.eu.assign(edge_u, edge_u + n_edges);
+    g.ev.assign(edge_v, edge_v + n_edges);
+    g.ed.assign(edge_dim, edge_dim + n_edges);
+    // sizes from the graph itself (no data is involved)
+    std::vector<int64_t> size(n_tensors, 1);
+    for (int e = 0; e < n_edges; ++e)
+        if (edge_u[e] >= 0 && edge_u[e] < n_tensors && edge_v[e] >= 0 && edge_v[e] < n_tensors) {
+            size[edge_u[e]] *= edge_dim[e];
+            size[edge_v[e]] *= edge_dim[e];
+        }
+    g.offsets.assign(n_tensors + 1, 0);
+    for (int v = 0; v < n_tensors; ++v) g.offsets[v + 1] = g.offsets[v] + size[v];
+    if (!check_graph(g).empty()) return TN_EINVAL;
+    TreeOpts o;
+    o.chi = opts->chi;
+    o.cutoff = opts->cutoff;
+    o.precision = opts->precision;
+    Plan P;
+    std::string err = build_plan(g, pair_i, pair_j, n_steps, o, true, &P);
+    if (!err.empty()) return TN_EINVAL;
+    *n_ops = (int64_t)P.ops.size();
+    for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)P.ops.size()); ++i) {
+        const OpRec& r = P.ops[i];
+        int64_t* q = ops + 8 * i;
+        q[0] = r.kind;
+        q[1] = r.a;
+        q[2] = r.b;
+        q[3] = r.out;
+        q[4] = r.m;
+        q[5] = r.n;
+        q[6] = r.k;
+        q[7] = r.new_dim;
+    }
+    return TN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal structures shared by the host planner and the device kernels.
+//
+// A tensor lives in device memory as a dense row-major array whose axes are
+// its edges in "leg order".  Every matrix that a kernel reads (a
+// matricisation, Fig. "tensor primitives" A) is described by a View: the
+// element (r, c) sits at  sum_l idx_l(r) * rstride_l + sum_l idx_l(c) * cstride_l,
+// where idx_l(r) is the mixed-radix digit of r over the row legs (last leg
+// fastest).  Gathers through Views fuse the permutation into the loads, so
+// no tensor is ever transposed in memory.
+#pragma once
+
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define TN_HD
+#else
+#define TN_HD __host__ __device__
+#endif
+
+namespace tn {
+
+constexpr int kMaxLegs = 10;
+
+// 32-bit division by a runtime constant via multiply-high (round-up method):
+// q = (umulhi(n, mul) + n) >> shr, exact for n < 2^31 and 1 <= d < 2^31.
+struct FastDiv {
+    uint32_t d;
+    uint32_t mul;
+    uint32_t shr;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    f.shr = l;
+    f.mul = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    return f;
+}
+
+TN_HD inline uint32_t fd_div(uint32_t n, const FastDiv& f) {
+#ifdef __HIP_DEVICE_COMPILE__
+    uint32_t hi = __umulhi(n, f.mul);
+#else
+    uint32_t hi = (uint32_t)(((uint64_t)n * f.mul) >> 32);
+#endif
+    return (uint32_t)(((uint64_t)hi + n) >> f.shr);
+}
+
+// One side (rows or columns) of a matricisation.  Legs are stored fastest
+// first: leg 0 is the least significant digit.
+struct Axis {
+    int32_t n;                   // number of legs (0 => single index 0)
+    int32_t pad;
+    FastDiv div[kMaxLegs];
+    uint32_t stride[kMaxLegs];   // element stride of each leg in the tensor
+};
+
+TN_HD inline uint32_t axis_offset(const Axis& a, uint32_t r) {
+    uint32_t off = 0;
+    for (int l = 0; l < a.n; ++l) {
+        uint32_t q = fd_div(r, a.div[l]);
+        off += (r - q * a.div[l].d) * a.stride[l];
+        r = q;
+    }
+    return off;
+}
+
+struct View {
+    Axis row;
+    Axis col;
+    int32_t row_unit;            // 1 if the fastest row leg has stride 1
+    int32_t col_unit;            // 1 if the fastest column leg has stride 1
+};
+
+enum GemmMode : int32_t {
+    GEMM_TENSOR = 0,   // C (M x N, row-major) = fA*fB * A.B ; writes per-tile max |C|
+    GEMM_GRAM = 1,     // C[split] (M x N, float64) = fA*fB * A.B over one K range
+};
+
+// C = op(A) . op(B) with A an (M x K) view and B a (K x N) view.
+struct GemmDesc {
+    const void* A;
+    const void* B;
+    void* C;
+    int64_t tile_begin;          // first linear tile of this op in the grouped launch
+    int32_t M, N, K;
+    int32_t mode;                // GemmMode
+    int32_t tiles_m, tiles_n, splits;
+    int32_t k_per_split;         // K range per split (multiple of the K tile)
+    int32_t scale_a, scale_b;    // indices into the tensor-scale array (-1: factor 1)
+    int32_t square_a;            // GRAM: factor is 1/s_a^2 (A and B are the same tensor)
+    int32_t maxpart;             // TENSOR: index of the first per-tile max slot
+    View va;                     // A: rows = M, cols = K
+    View vb;                     // B: rows = K, cols = N
+};
+
+// Gather-copy: dst (rows x cols, row-major float64) = src(view) / s.
+struct CopyDesc {
+    const void* src;
+    double* dst;
+    int64_t elem_begin;          // first linear element of this op in the grouped launch
+    int32_t rows, cols;
+    int32_t scale;               // tensor-scale index
+    int32_t transpose;           // 1: write dst as (cols x rows)
+    View v;
+};
+
+// One bond compression's small dense part: reduced factors, core SVD, projectors.
+struct CoreDesc {
+    // Side A: either a split-K Gram (gram_a != null, D x D partials) or an explicit
+    // factor R~_A (rows_a x D, row-major) with R~_A^T R~_A = A^T A.
+    const double* gram_a;
+    const double* gram_b;
+    const double* fac_a;
+    const double* fac_b;
+    int32_t splits_a, splits_b;
+    int32_t rows_a, rows_b;      // rows of the explicit factors (when no Gram)
+    int32_t D;                   // bond size being compressed
+    int32_t chi_new;             // static new bond dimension chi'
+    double cutoff;
+    double* work;                // float64 workspace (layout fixed by the kernel)
+    void* p_left;                // D x chi' projector in the tensor dtype
+    void* p_right;               // chi' x D projector in the tensor dtype
+    int32_t stat;                // index into the per-compression stats arrays
+    int32_t kmin;                // min(k_A, k_B): number of singular values of the structural core
+};
+
+// Upload of one input tensor: float64 staging -> arena (converted to the tensor dtype).
+struct InputDesc {
+    void* dst;
+    int64_t src_off;
+    int64_t count;
+    int32_t tensor;
+    int32_t pad;
+};
+
+// Per-tensor scale finalisation: s = max over the tensor's per-tile maxima.
+struct ScaleDesc {
+    int32_t maxpart;             // first per-tile max slot
+    int32_t nparts;
+    int32_t tensor;              // tensor-scale index to write
+    int32_t pad;
+};
+
+}  // namespace tn

@@ -1,0 +1,661 @@
+// Device kernels for gfx950 (MI355X).
+//
+// * gemm_grouped  — one launch runs every GEMM-shaped step of a schedule level:
+//   pairwise contractions (Fig. "tensor primitives" B), the Gram matrices that
+//   stand in for the R-factors of the QR-reduced compression (section II.C),
+//   and the projector re-absorptions A P_L, P_R B (SI section B).  Operands are
+//   read through Views, so the permutation of the matricisation is fused into
+//   the LDS staging; the product runs on MFMA (v_mfma_f64_16x16x4f64 or
+//   v_mfma_f32_16x16x4f32).  The epilogue applies the pending scales of the
+//   inputs and records the tile's largest |value| for the running exponent.
+// * core_kernel   — one workgroup per bond compression: reduced factors from
+//   the Gram matrices (pivoted Cholesky), R_A R_B, its one-sided Jacobi SVD,
+//   truncation to chi' and the projectors P_L = R_B V s^-1/2, P_R = s^-1/2 U^T R_A.
+// * scale / result kernels — the running log-scale exponent.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "tn_internal.hpp"
+#include "tn_kernels.hpp"
+
+namespace tn {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename Tc>
+struct Mma;
+// Operands: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+// Result element r of lane l is D[row(l, r)][l % 16]; the row mapping differs
+// between the float64 and float32 instructions (checked on gfx950).
+template <>
+struct Mma<double> {
+    using acc = v4d;
+    __device__ static inline acc run(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mma<float> {
+    using acc = v4f;
+    __device__ static inline acc run(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+__device__ inline double inv_scale(const double* scales, int idx) {
+    if (idx < 0) return 1.0;
+    double s = scales[idx];
+    return s > 0.0 ? 1.0 / s : 0.0;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// Grouped gather GEMM
+// ------------------------------------------------------------------------------------------
+constexpr int kBM = 64, kBN = 64, kBK = 16, kGemmThreads = 256;
+
+template <typename Tin, typename Tc, typename Tout>
+__global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __restrict__ descs, int ndesc,
+                                                             const double* __restrict__ scales,
+                                                             double* __restrict__ maxparts) {
+    __shared__ Tc As[kBK][kBM + 2];
+    __shared__ Tc Bs[kBK][kBN + 2];
+    __shared__ double wmax[kGemmThreads / 64];
+
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_begin <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc& d = descs[lo];
+    const int M = d.M, N = d.N, K = d.K;
+    const int per_split = d.tiles_m * d.tiles_n;
+    const int local = (int)(tile - d.tile_begin);
+    const int split = local / per_split;
+    const int rem = local - split * per_split;
+    const int tm = rem / d.tiles_n;
+    const int tn_ = rem - tm * d.tiles_n;
+    const int m0 = tm * kBM, n0 = tn_ * kBN;
+    const int k_begin = split * d.k_per_split;
+    const int k_end = min(K, k_begin + d.k_per_split);
+
+    const Tin* __restrict__ A = (const Tin*)d.A;
+    const Tin* __restrict__ B = (const Tin*)d.B;
+
+    // per-thread fixed coordinates of the 4 A and 4 B elements it stages
+    const bool a_mfast = d.va.row_unit != 0;
+    const bool b_nfast = d.vb.col_unit != 0;
+    int a_m[4], a_k[4], b_k[4], b_n[4];
+    uint32_t a_off[4], b_off[4];
+    bool a_ok[4], b_ok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + kGemmThreads * i;
+        if (a_mfast) { a_m[i] = e & (kBM - 1); a_k[i] = e / kBM; }
+        else { a_k[i] = e & (kBK - 1); a_m[i] = e / kBK; }
+        if (b_nfast) { b_n[i] = e & (kBN - 1); b_k[i] = e / kBN; }
+        else { b_k[i] = e & (kBK - 1); b_n[i] = e / kBK; }
+        const int gm = m0 + a_m[i], gn = n0 + b_n[i];
+        a_ok[i] = gm < M;
+        b_ok[i] = gn < N;
+        a_off[i] = a_ok[i] ? axis_offset(d.va.row, (uint32_t)gm) : 0u;
+        b_off[i] = b_ok[i] ? axis_offset(d.vb.col, (uint32_t)gn) : 0u;
+    }
+
+    Tc ra[4], rb[4];
+    auto load_chunk = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int gka = kc + a_k[i];
+            ra[i] = (a_ok[i] && gka < k_end) ? (Tc)A[a_off[i] + axis_offset(d.va.col, (uint32_t)gka)] : (Tc)0;
+            const int gkb = kc + b_k[i];
+            rb[i] = (b_ok[i] && gkb < k_end) ? (Tc)B[b_off[i] + axis_offset(d.vb.row, (uint32_t)gkb)] : (Tc)0;
+        }
+    };
+
+    using acc_t = typename Mma<Tc>::acc;
+    acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int lrow = lane & 15, lk = lane >> 4;
+
+    if (k_begin < k_end) load_chunk(k_begin);
+    for (int kc = k_begin; kc < k_end; kc += kBK) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            As[a_k[i]][a_m[i]] = ra[i];
+            Bs[b_k[i]][b_n[i]] = rb[i];
+        }
+        __syncthreads();
+        if (kc + kBK < k_end) load_chunk(kc + kBK);
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 4) {
+            const Tc a0 = As[kk + lk][wm + lrow], a1 = As[kk + lk][wm + 16 + lrow];
+            const Tc b0 = Bs[kk + lk][wn + lrow], b1 = Bs[kk + lk][wn + 16 + lrow];
+            acc[0][0] = Mma<Tc>::run(a0, b0, acc[0][0]);
+            acc[0][1] = Mma<Tc>::run(a0, b1, acc[0][1]);
+            acc[1][0] = Mma<Tc>::run(a1, b0, acc[1][0]);
+            acc[1][1] = Mma<Tc>::run(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+
+    const double fa = inv_scale(scales, d.scale_a);
+    const double factor = d.square_a ? fa * fa : fa * inv_scale(scales, d.scale_b);
+    double local_max = 0.0;
+    Tout* __restrict__ C = (Tout*)d.C;
+    const int64_t cbase = (d.mode == GEMM_GRAM) ? (int64_t)split * M * N : 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + i * 16 + Mma<Tc>::row(lane, r);
+                const int gn = n0 + wn + j * 16 + lrow;
+                if (gm < M && gn < N) {
+                    const double v = (double)acc[i][j][r] * factor;
+                    const Tout o = (Tout)v;
+                    C[cbase + (int64_t)gm * N + gn] = o;
+                    local_max = fmax(local_max, fabs((double)o));
+                }
+            }
+    if (d.mode == GEMM_TENSOR) {
+        local_max = wave_max(local_max);
+        if (lane == 0) wmax[wave] = local_max;
+        __syncthreads();
+        if (tid == 0) {
+            double m = wmax[0];
+            for (int w = 1; w < kGemmThreads / 64; ++w) m = fmax(m, wmax[w]);
+            maxparts[d.maxpart + local] = m;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Gather copy (explicit reduced factor when a side has no more rows than D)
+// ------------------------------------------------------------------------------------------
+template <typename Tin>
+__global__ __launch_bounds__(256) void copy_grouped(const CopyDesc* __restrict__ descs, int ndesc,
+                                                    const double* __restrict__ scales, int64_t total) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].elem_begin <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const CopyDesc& d = descs[lo];
+    const int local = (int)(e - d.elem_begin);
+    const int r = local / d.cols, c = local - r * d.cols;
+    const Tin* src = (const Tin*)d.src;
+    const double v = (double)src[axis_offset(d.v.row, (uint32_t)r) + axis_offset(d.v.col, (uint32_t)c)];
+    d.dst[(int64_t)r * d.cols + c] = v * inv_scale(scales, d.scale);
+}
+
+// ------------------------------------------------------------------------------------------
+// Compression core: one workgroup per compression
+// ------------------------------------------------------------------------------------------
+constexpr int kCoreThreads = 1024;
+constexpr double kNoiseRel = 1e-13;
+constexpr int kCoreWaves = kCoreThreads / 64;
+
+struct CoreShared {
+    double rv[kCoreWaves];
+    int ri[kCoreWaves];
+    int flag;
+};
+
+// block-wide argmax over values v[i] for i in [0, n) with mask[i] == 0; ties -> smallest index
+__device__ inline void block_argmax(const double* G, int D, const int* chosen, CoreShared& sh, double* out_v,
+                                    int* out_i) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = tid; i < D; i += kCoreThreads) {
+        if (chosen[i]) continue;
+        const double v = G[(int64_t)i * D + i];
+        if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { sh.rv[wave] = bv; sh.ri[wave] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+        double v = sh.rv[0];
+        int ix = sh.ri[0];
+        for (int w = 1; w < kCoreWaves; ++w)
+            if (sh.rv[w] > v || (sh.rv[w] == v && sh.ri[w] < ix)) { v = sh.rv[w]; ix = sh.ri[w]; }
+        sh.rv[0] = v;
+        sh.ri[0] = ix;
+    }
+    __syncthreads();
+    *out_v = sh.rv[0];
+    *out_i = sh.ri[0];
+    __syncthreads();
+}
+
+// R (rows x D, row-major, original column order) with R^T R = G: pivoted Cholesky
+// of the symmetric positive semidefinite D x D matrix G (destroyed).  Returns the rank.
+__device__ int pivoted_cholesky(double* G, int D, double* R, int* chosen, CoreShared& sh) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < D; i += kCoreThreads) chosen[i] = 0;
+    __syncthreads();
+    double g0;
+    int p0;
+    block_argmax(G, D, chosen, sh, &g0, &p0);
+    const double tol = 1e-15 * g0;
+    int r = 0;
+    for (int t = 0; t < D; ++t) {
+        double piv;
+        int p;
+        if (t == 0) { piv = g0; p = p0; }
+        else block_argmax(G, D, chosen, sh, &piv, &p);
+        if (!(piv > tol) || !(piv > 0.0)) break;
+        const double rp = sqrt(piv);
+        double* Rt = R + (int64_t)t * D;
+        for (int j = tid; j < D; j += kCoreThreads)
+            Rt[j] = chosen[j] ? 0.0 : (j == p ? rp : G[(int64_t)p * D + j] / rp);
+        __syncthreads();
+        if (tid == 0) chosen[p] = 1;
+        __syncthreads();
+        const int64_t DD = (int64_t)D * D;
+        for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
+            const int i = (int)(idx / D), j = (int)(idx - (int64_t)i * D);
+            if (!chosen[i] && !chosen[j]) G[idx] -= Rt[i] * Rt[j];
+        }
+        __syncthreads();
+        r = t + 1;
+    }
+    return r;
+}
+
+__device__ inline int rr_col(int pos, int round, int n) {
+    return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
+}
+
+template <bool kLds, typename Tp>
+__global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
+                                                            double* __restrict__ stat_disc,
+                                                            int32_t* __restrict__ stat_tie,
+                                                            int32_t* __restrict__ stat_sweeps) {
+    extern __shared__ double lds[];
+    __shared__ CoreShared sh;
+    const CoreDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int D = d.D;
+    const int64_t DD = (int64_t)D * D;
+    double* Ra = d.work;
+    double* Rb = Ra + DD;
+    double* W = kLds ? lds : Rb + DD;            // column-major core, column j at W + j*D
+    double* V = kLds ? lds + DD : W + DD;        // column-major right singular vectors
+    double* sig = d.work + 4 * DD;
+    int* order = (int*)(sig + D);
+    int* chosen = order + D;
+
+    // ---- reduced factors R~_A (ra x D), R~_B (rb x D)
+    int rk[2];
+    for (int side = 0; side < 2; ++side) {
+        const double* gram = side == 0 ? d.gram_a : d.gram_b;
+        const double* fac = side == 0 ? d.fac_a : d.fac_b;
+        double* R = side == 0 ? Ra : Rb;
+        if (gram) {
+            const int splits = side == 0 ? d.splits_a : d.splits_b;
+            for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
+                double s = 0.0;
+                for (int p = 0; p < splits; ++p) s += gram[(int64_t)p * DD + idx];
+                W[idx] = s;
+            }
+            __syncthreads();
+            rk[side] = pivoted_cholesky(W, D, R, chosen, sh);
+        } else {
+            const int rows = side == 0 ? d.rows_a : d.rows_b;
+            for (int64_t idx = tid; idx < (int64_t)rows * D; idx += kCoreThreads) R[idx] = fac[idx];
+            rk[side] = rows;
+        }
+        __syncthreads();
+    }
+    const int ra = rk[0], rb = rk[1];
+
+    // ---- core W = R~_A R~_B^T  (ra x rb), V = I
+    for (int64_t idx = tid; idx < (int64_t)ra * rb; idx += kCoreThreads) {
+        const int j = (int)(idx / ra), i = (int)(idx - (int64_t)j * ra);
+        const double* x = Ra + (int64_t)i * D;
+        const double* y = Rb + (int64_t)j * D;
+        double s = 0.0;
+        for (int q = 0; q < D; ++q) s += x[q] * y[q];
+        W[(int64_t)j * D + i] = s;
+    }
+    for (int64_t idx = tid; idx < (int64_t)rb * rb; idx += kCoreThreads) {
+        const int j = (int)(idx / rb), i = (int)(idx - (int64_t)j * rb);
+        V[(int64_t)j * D + i] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+
+    // ---- one-sided (Hestenes) Jacobi on the columns of W, accumulating V.
+    // A pair is rotated while its columns are not orthogonal to relative precision
+    // tol; columns whose norm is at the rounding level of ||W||_F (rank-deficient
+    // cores) are numerically zero and are left alone, else their noise would keep
+    // rotating forever.
+    const int nc = rb + (rb & 1);
+    const double tol = 2.220446049250313e-16 * (double)max(ra, 16);
+    {
+        double f = 0.0;
+        for (int64_t idx = tid; idx < (int64_t)ra * rb; idx += kCoreThreads) {
+            const int j = (int)(idx / ra), i = (int)(idx - (int64_t)j * ra);
+            const double x = W[(int64_t)j * D + i];
+            f += x * x;
+        }
+        f = wave_sum(f);
+        if (lane == 0) sh.rv[wave] = f;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+            sh.rv[0] = t;
+        }
+        __syncthreads();
+    }
+    const double fro2 = sh.rv[0];
+    const double zero2 = 1e-28 * fro2;   // (1e-14 ||W||_F)^2
+    __syncthreads();
+    int sweeps = 0;
+    bool converged = (rb <= 1);
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        if (tid == 0) sh.flag = 0;
+        __syncthreads();
+        for (int round = 0; round < nc - 1; ++round) {
+            for (int q = wave; q < nc / 2; q += kCoreWaves) {
+                const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
+                if (p1 >= rb || p2 >= rb) continue;
+                double* w1 = W + (int64_t)p1 * D;
+                double* w2 = W + (int64_t)p2 * D;
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int i = lane; i < ra; i += 64) {
+                    const double x = w1[i], y = w2[i];
+                    a += x * x;
+                    b += y * y;
+                    g += x * y;
+                }
+                a = wave_sum(a);
+                b = wave_sum(b);
+                g = wave_sum(g);
+                if (a > zero2 && b > zero2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+                    const double zeta = (b - a) / (2.0 * g);
+                    const double az = fabs(zeta);
+                    const double root = az > 1e100 ? az : sqrt(1.0 + zeta * zeta);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
+                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                    for (int i = lane; i < ra; i += 64) {
+                        const double x = w1[i], y = w2[i];
+                        w1[i] = c * x - s * y;
+                        w2[i] = s * x + c * y;
+                    }
+                    double* v1 = V + (int64_t)p1 * D;
+                    double* v2 = V + (int64_t)p2 * D;
+                    for (int i = lane; i < rb; i += 64) {
+                        const double x = v1[i], y = v2[i];
+                        v1[i] = c * x - s * y;
+                        v2[i] = s * x + c * y;
+                    }
+                    if (lane == 0) sh.flag = 1;
+                }
+            }
+            __syncthreads();
+        }
+        sweeps = sweep + 1;
+        if (!sh.flag) converged = true;
+        __syncthreads();
+    }
+
+    // ---- singular values and descending order (ties: lower column first)
+    for (int j = wave; j < rb; j += kCoreWaves) {
+        double s = 0.0;
+        for (int i = lane; i < ra; i += 64) s += W[(int64_t)j * D + i] * W[(int64_t)j * D + i];
+        s = wave_sum(s);
+        if (lane == 0) sig[j] = sqrt(s);
+    }
+    __syncthreads();
+    for (int j = tid; j < rb; j += kCoreThreads) {
+        const double sj = sig[j];
+        int rank = 0;
+        for (int q = 0; q < rb; ++q) rank += (sig[q] > sj) || (sig[q] == sj && q < j);
+        order[rank] = j;
+    }
+    __syncthreads();
+
+    // ---- projectors P_L (D x chi') and P_R (chi' x D)
+    const int cn = d.chi_new;
+    const double smax = rb > 0 ? sig[order[0]] : 0.0;
+    Tp* PL = (Tp*)d.p_left;
+    Tp* PR = (Tp*)d.p_right;
+    for (int64_t idx = tid; idx < (int64_t)D * cn; idx += kCoreThreads) {
+        const int dd = (int)(idx / cn), t = (int)(idx - (int64_t)dd * cn);
+        const int j = t < rb ? order[t] : -1;
+        const double s = j >= 0 ? sig[j] : 0.0;
+        double pl = 0.0, pr = 0.0;
+        // singular values below kNoiseRel * sigma_1 are numerical zeros of an FP64 core: their
+        // vectors are rounding noise, and dividing by them would amplify it (they change A B by
+        // less than kNoiseRel relative when dropped)
+        if (s > kNoiseRel * smax && s >= d.cutoff * smax) {
+            const double* v = V + (int64_t)j * D;
+            const double* u = W + (int64_t)j * D;
+            for (int i = 0; i < rb; ++i) pl += Rb[(int64_t)i * D + dd] * v[i];
+            for (int i = 0; i < ra; ++i) pr += u[i] * Ra[(int64_t)i * D + dd];
+            const double rs = sqrt(s);
+            pl /= rs;
+            pr /= (s * rs);
+        }
+        PL[(int64_t)dd * cn + t] = (Tp)pl;
+        PR[(int64_t)t * D + dd] = (Tp)pr;
+    }
+
+    // ---- diagnostics
+    if (tid == 0) {
+        double tot = 0.0, disc = 0.0;
+        for (int t = 0; t < rb; ++t) {
+            const double s = sig[order[t]];
+            tot += s * s;
+            if (t >= cn) disc += s * s;
+        }
+        stat_disc[d.stat] = tot > 0.0 ? disc / tot : 0.0;
+        const double s_last = (cn - 1 < rb) ? sig[order[cn - 1]] : 0.0;
+        const double s_next = (cn < rb) ? sig[order[cn]] : 0.0;
+        stat_tie[d.stat] = (d.kmin > cn && s_last - s_next <= 1e-12 * smax) ? 1 : 0;
+        stat_sweeps[d.stat] = converged ? sweeps : -1 - sweeps;   // negative: not converged
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Running exponent
+// ------------------------------------------------------------------------------------------
+__global__ void scale_finalize(const ScaleDesc* __restrict__ descs, int n, const double* __restrict__ maxparts,
+                               double* __restrict__ scales) {
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gw >= n) return;
+    const ScaleDesc& d = descs[gw];
+    double m = 0.0;
+    for (int i = lane; i < d.nparts; i += 64) m = fmax(m, maxparts[d.maxpart + i]);
+    m = wave_max(m);
+    if (lane == 0) scales[d.tensor] = m;
+}
+
+template <typename T>
+__global__ void input_scales(const InputDesc* __restrict__ descs, int n, double* __restrict__ scales) {
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gw >= n) return;
+    const InputDesc& d = descs[gw];
+    const T* x = (const T*)d.dst;
+    double m = 0.0;
+    bool bad = false;
+    for (int64_t i = lane; i < d.count; i += 64) {
+        const double v = (double)x[i];
+        if (!isfinite(v)) bad = true;
+        m = fmax(m, fabs(v));
+    }
+    m = wave_max(m);
+    const double b = wave_max(bad ? 1.0 : 0.0);
+    if (lane == 0) scales[d.tensor] = b > 0.0 ? __builtin_nan("") : m;
+}
+
+template <typename T>
+__global__ void input_scatter(const InputDesc* __restrict__ descs, int n, const double* __restrict__ src) {
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gw >= n) return;
+    const InputDesc& d = descs[gw];
+    T* x = (T*)d.dst;
+    for (int64_t i = lane; i < d.count; i += 64) x[i] = (T)src[d.src_off + i];
+}
+
+// ln|Z| = sum of ln s over every tensor in creation order (fixed-order reduction), sign of the
+// final raw scalar; flags: 1 = a zero scale, 2 = non-finite scale, 4 = Jacobi not converged.
+template <typename T>
+__global__ __launch_bounds__(1024) void result_kernel(const double* __restrict__ scales, int n_scales,
+                                                      const void* __restrict__ final_ptr,
+                                                      const int32_t* __restrict__ sweeps, int n_comp,
+                                                      double* __restrict__ result) {
+    __shared__ double part[1024];
+    __shared__ int fl[1024];
+    const int tid = threadIdx.x;
+    const int per = (n_scales + 1023) / 1024;
+    const int b = tid * per, e = min(n_scales, b + per);
+    double acc = 0.0;
+    int flags = 0;
+    for (int i = b; i < e; ++i) {
+        const double s = scales[i];
+        if (!isfinite(s)) flags |= 2;
+        else if (s == 0.0) flags |= 1;
+        else acc += log(s);
+    }
+    for (int c = tid; c < n_comp; c += 1024)
+        if (sweeps[c] < 0) flags |= 4;
+    part[tid] = acc;
+    fl[tid] = flags;
+    __syncthreads();
+    for (int o = 512; o >= 1; o >>= 1) {
+        if (tid < o) {
+            part[tid] += part[tid + o];
+            fl[tid] |= fl[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double x = (double)((const T*)final_ptr)[0];
+        result[0] = x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0);
+        result[1] = part[0];
+        result[2] = (double)fl[0];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host-side launchers
+// ------------------------------------------------------------------------------------------
+hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
+                       double* maxparts, hipStream_t s) {
+    if (ndesc == 0 || tiles == 0) return hipSuccess;
+    dim3 grid((unsigned)tiles), block(kGemmThreads);
+    switch (dtype_key) {
+        case GEMM_F64: gemm_grouped<double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
+        case GEMM_F32: gemm_grouped<float, float, float><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
+        case GEMM_F32_TO_F64: gemm_grouped<float, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
+                       hipStream_t s) {
+    if (ndesc == 0 || total == 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (src_f32) copy_grouped<float><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
+    else copy_grouped<double><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
+    return hipGetLastError();
+}
+
+size_t core_lds_bytes(int max_d) { return (size_t)2 * max_d * max_d * sizeof(double); }
+
+void init_kernel_attrs() {
+    const int bytes = (int)core_lds_bytes(kCoreLdsMaxD);
+    (void)hipFuncSetAttribute((const void*)core_kernel<true, float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)core_kernel<true, double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
+                       double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s) {
+    if (ndesc == 0) return hipSuccess;
+    dim3 grid(ndesc), block(kCoreThreads);
+    if (lds) {
+        const size_t bytes = core_lds_bytes(max_d);
+        if (proj_f32) core_kernel<true, float><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
+        else core_kernel<true, double><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
+    } else {
+        if (proj_f32) core_kernel<false, float><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
+        else core_kernel<false, double><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* maxparts, double* scales,
+                                 hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int threads = 256;
+    dim3 grid((unsigned)((n * 64 + threads - 1) / threads)), block(threads);
+    scale_finalize<<<grid, block, 0, s>>>(descs, n, maxparts, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,
+                         hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int threads = 256;
+    dim3 grid((unsigned)((n * 64 + threads - 1) / threads)), block(threads);
+    if (f32) {
+        input_scatter<float><<<grid, block, 0, s>>>(descs, n, staging);
+        input_scales<float><<<grid, block, 0, s>>>(descs, n, scales);
+    } else {
+        input_scatter<double><<<grid, block, 0, s>>>(descs, n, staging);
+        input_scales<double><<<grid, block, 0, s>>>(descs, n, scales);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_result(int f32, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
+                         int n_comp, double* result, hipStream_t s) {
+    if (f32) result_kernel<float><<<1, 1024, 0, s>>>(scales, n_scales, final_ptr, sweeps, n_comp, result);
+    else result_kernel<double><<<1, 1024, 0, s>>>(scales, n_scales, final_ptr, sweeps, n_comp, result);
+    return hipGetLastError();
+}
+
+}  // namespace tn

@@ -1,0 +1,29 @@
+// Launch wrappers for the device kernels (tn_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tn_internal.hpp"
+
+namespace tn {
+
+enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2 };
+
+constexpr int kCoreLdsMaxD = 64;
+
+void init_kernel_attrs();
+hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
+                       double* maxparts, hipStream_t s);
+hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
+                       hipStream_t s);
+size_t core_lds_bytes(int max_d);
+hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
+                       double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
+hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* maxparts, double* scales,
+                                 hipStream_t s);
+hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,
+                         hipStream_t s);
+hipError_t launch_result(int f32, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
+                         int n_comp, double* result, hipStream_t s);
+
+}  // namespace tn

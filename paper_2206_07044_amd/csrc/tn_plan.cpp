@@ -1,0 +1,510 @@
+// Host planner (see tn_plan.hpp).
+#include "tn_plan.hpp"
+
+#include <algorithm>
+#include <climits>
+#include <map>
+#include <sstream>
+
+namespace tn {
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+constexpr int64_t kMaxElems = (int64_t)INT32_MAX;   // 32-bit element indexing in kernels
+constexpr int kGemmTile = 64;
+constexpr int kGemmK = 16;
+
+struct EdgeLive {
+    int64_t dim;
+    int32_t end0, end1;
+    bool alive;
+};
+
+int64_t prod_dims(const std::vector<int32_t>& legs, const std::vector<EdgeLive>& E) {
+    int64_t p = 1;
+    for (int e : legs) p *= E[e].dim;
+    return p;
+}
+
+// Strides (in elements) of a tensor's legs, row-major in leg order.
+std::vector<int64_t> leg_strides(const TensorVer& t, const std::vector<EdgeLive>& E) {
+    std::vector<int64_t> s(t.legs.size());
+    int64_t acc = 1;
+    for (int a = (int)t.legs.size() - 1; a >= 0; --a) {
+        s[a] = acc;
+        acc *= E[t.legs[a]].dim;
+    }
+    return s;
+}
+
+ViewSpec tensor_view(const TensorVer& t, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols,
+                     const std::vector<EdgeLive>& E) {
+    std::vector<int64_t> st = leg_strides(t, E);
+    auto pos = [&](int e) {
+        for (size_t a = 0; a < t.legs.size(); ++a)
+            if (t.legs[a] == e) return (int)a;
+        return -1;
+    };
+    ViewSpec v;
+    for (int e : rows) {
+        v.row_dims.push_back((int32_t)E[e].dim);
+        v.row_strides.push_back(st[pos(e)]);
+    }
+    for (int e : cols) {
+        v.col_dims.push_back((int32_t)E[e].dim);
+        v.col_strides.push_back(st[pos(e)]);
+    }
+    return v;
+}
+
+ViewSpec dense_view(int64_t rows, int64_t cols) {
+    ViewSpec v;
+    v.row_dims = {(int32_t)rows};
+    v.row_strides = {cols};
+    v.col_dims = {(int32_t)cols};
+    v.col_strides = {1};
+    return v;
+}
+
+std::string make_axis(const std::vector<int32_t>& dims, const std::vector<int64_t>& strides, Axis* ax) {
+    // merge adjacent legs that are contiguous in memory, drop unit legs
+    std::vector<int64_t> d, s;
+    for (size_t i = 0; i < dims.size(); ++i) {
+        if (dims[i] == 1) continue;
+        if (!d.empty() && s.back() == strides[i] * dims[i]) {
+            d.back() *= dims[i];
+            s.back() = strides[i];
+        } else {
+            d.push_back(dims[i]);
+            s.push_back(strides[i]);
+        }
+    }
+    if ((int)d.size() > kMaxLegs) return "matricisation needs more than 10 distinct legs";
+    ax->n = (int32_t)d.size();
+    ax->pad = 0;
+    for (int l = 0; l < kMaxLegs; ++l) {
+        ax->div[l] = make_fastdiv(1);
+        ax->stride[l] = 0;
+    }
+    for (int l = 0; l < ax->n; ++l) {   // fastest first
+        size_t i = d.size() - 1 - l;
+        if (d[i] > kMaxElems || s[i] > kMaxElems) return "tensor too large for 32-bit indexing";
+        ax->div[l] = make_fastdiv((uint32_t)d[i]);
+        ax->stride[l] = (uint32_t)s[i];
+    }
+    return "";
+}
+
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+std::string make_view(const ViewSpec& s, View* v) {
+    std::string err = make_axis(s.row_dims, s.row_strides, &v->row);
+    if (!err.empty()) return err;
+    err = make_axis(s.col_dims, s.col_strides, &v->col);
+    if (!err.empty()) return err;
+    v->row_unit = (v->row.n > 0 && v->row.stride[0] == 1) ? 1 : 0;
+    v->col_unit = (v->col.n > 0 && v->col.stride[0] == 1) ? 1 : 0;
+    return "";
+}
+
+std::string check_graph(const GraphSpec& g) {
+    std::ostringstream os;
+    if (g.n < 1) return "n_tensors must be >= 1";
+    if (g.ne < 0) return "n_edges must be >= 0";
+    if ((int)g.eu.size() != g.ne || (int)g.ev.size() != g.ne || (int)g.ed.size() != g.ne)
+        return "edge arrays missing";
+    std::vector<int64_t> size(g.n, 1);
+    for (int e = 0; e < g.ne; ++e) {
+        if (g.eu[e] < 0 || g.ev[e] >= g.n || g.eu[e] >= g.ev[e]) {
+            os << "edge " << e << " must satisfy 0 <= u < v < n_tensors";
+            return os.str();
+        }
+        if (g.ed[e] < 1) {
+            os << "edge " << e << " has dimension < 1";
+            return os.str();
+        }
+        for (int x : {g.eu[e], g.ev[e]}) {
+            size[x] *= g.ed[e];
+            if (size[x] > kMaxElems) {
+                os << "tensor " << x << " exceeds 2^31-1 elements";
+                return os.str();
+            }
+        }
+    }
+    if ((int)g.offsets.size() != g.n + 1 || g.offsets[0] != 0) return "offsets must hold n_tensors+1 entries starting at 0";
+    for (int v = 0; v < g.n; ++v) {
+        if (g.offsets[v + 1] - g.offsets[v] != size[v]) {
+            os << "tensor " << v << " has " << (g.offsets[v + 1] - g.offsets[v]) << " entries, expected " << size[v];
+            return os.str();
+        }
+    }
+    return "";
+}
+
+std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj, int32_t n_steps,
+                       const TreeOpts& o, bool shapes_only, Plan* P) {
+    std::ostringstream os;
+    *P = Plan();
+    P->g = g;
+    P->opts = o;
+    P->elem_size = (o.precision == 1) ? 4 : 8;
+    const int64_t w = P->elem_size;
+    if (o.chi < 1) return "chi must be >= 1";
+    if (n_steps != g.n - 1) {
+        os << "a tree over " << g.n << " tensors has " << (g.n - 1) << " steps, got " << n_steps;
+        return os.str();
+    }
+    std::vector<EdgeLive> E(g.ne);
+    std::vector<std::vector<int32_t>> inc(g.n);
+    for (int e = 0; e < g.ne; ++e) {
+        E[e] = {g.ed[e], g.eu[e], g.ev[e], true};
+        inc[g.eu[e]].push_back(e);
+        inc[g.ev[e]].push_back(e);
+    }
+    const int32_t total_ids = g.n + n_steps;
+    std::vector<int32_t> live(total_ids, -1);
+    auto new_buf = [&](int64_t bytes, int kind, int lo) {
+        Buf b;
+        b.bytes = std::max<int64_t>(bytes, 8);
+        b.kind = kind;
+        b.lo = lo;
+        b.hi = lo;
+        P->bufs.push_back(b);
+        return (int32_t)P->bufs.size() - 1;
+    };
+    auto touch = [&](int32_t buf, int level) {
+        if (buf >= 0) P->bufs[buf].hi = std::max(P->bufs[buf].hi, level);
+    };
+    for (int v = 0; v < g.n; ++v) {
+        TensorVer t;
+        t.legs = inc[v];   // ascending edge id by construction
+        t.size = prod_dims(t.legs, E);
+        t.level = 0;
+        if (!shapes_only) t.buf = new_buf(t.size * w, BUF_INPUT, 0);
+        P->tens.push_back(t);
+        live[v] = v;
+    }
+    int next_edge = g.ne;
+
+    auto read_tensor = [&](int32_t ver, int level) {
+        TensorVer& t = P->tens[ver];
+        t.last_read = std::max(t.last_read, level);
+        touch(t.buf, level);
+    };
+
+    auto add_gemm_flops = [&](Step& s) {
+        s.flops = 2.0 * (double)s.M * (double)s.N * (double)s.K;
+        s.bytes = (double)w * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
+    };
+
+    for (int t = 0; t < n_steps; ++t) {
+        const int32_t i = pi[t], j = pj[t];
+        if (i < 0 || j < 0 || i >= total_ids || j >= total_ids || i == j || live[i] < 0 || live[j] < 0) {
+            os << "step " << t << ": (" << i << ", " << j << ") are not two live tensors";
+            return os.str();
+        }
+        const int32_t k = g.n + t;
+        // ---------------------------------------------------------- CONTRACT(i, j) -> k
+        {
+            const int32_t vi = live[i], vj = live[j];
+            const TensorVer Ti = P->tens[vi], Tj = P->tens[vj];
+            std::vector<int32_t> shared, free_i, free_j;
+            for (int e : Ti.legs) {
+                if (std::find(Tj.legs.begin(), Tj.legs.end(), e) != Tj.legs.end()) shared.push_back(e);
+                else free_i.push_back(e);
+            }
+            for (int e : Tj.legs)
+                if (std::find(shared.begin(), shared.end(), e) == shared.end()) free_j.push_back(e);
+            const int64_t m = prod_dims(free_i, E), s = prod_dims(shared, E), q = prod_dims(free_j, E);
+            if (m * q > kMaxElems) {
+                os << "step " << t << ": intermediate of " << m * q << " elements exceeds 2^31-1";
+                return os.str();
+            }
+            P->ops.push_back({0, i, j, k, m, s, q, 0});
+            TensorVer Tk;
+            Tk.legs = free_i;
+            Tk.legs.insert(Tk.legs.end(), free_j.begin(), free_j.end());
+            Tk.size = m * q;
+            if (!shapes_only) {
+                Step st;
+                st.kind = ST_CONTRACT;
+                st.level = 1 + std::max(Ti.level, Tj.level);
+                st.in_a = vi;
+                st.in_b = vj;
+                st.M = m;
+                st.N = q;
+                st.K = s;
+                st.va = tensor_view(Ti, free_i, shared, E);
+                st.vb = tensor_view(Tj, shared, free_j, E);
+                add_gemm_flops(st);
+                Tk.level = st.level;
+                Tk.buf = new_buf(Tk.size * w, BUF_TENSOR, st.level);
+                P->tens.push_back(Tk);
+                st.out_t = (int32_t)P->tens.size() - 1;
+                read_tensor(vi, st.level);
+                read_tensor(vj, st.level);
+                P->steps.push_back(st);
+            } else {
+                P->tens.push_back(Tk);
+            }
+            for (int e : shared) E[e].alive = false;
+            for (int e : free_i) (E[e].end0 == i ? E[e].end0 : E[e].end1) = k;
+            for (int e : free_j) (E[e].end0 == j ? E[e].end0 : E[e].end1) = k;
+            live[i] = live[j] = -1;
+            live[k] = (int32_t)P->tens.size() - 1;
+        }
+        // ---------------------------------------------------------- early compression of k's bonds
+        std::map<int32_t, std::vector<int32_t>> nb;   // neighbour -> shared edges in k's axis order
+        for (int e : P->tens[live[k]].legs) {
+            const int32_t other = (E[e].end0 == k) ? E[e].end1 : E[e].end0;
+            nb[other].push_back(e);
+        }
+        for (auto& kv : nb) {
+            const int32_t l = kv.first;
+            if (prod_dims(kv.second, E) <= o.chi) continue;
+            const int32_t a = k, b = l;
+            const int32_t va = live[a], vb = live[b];
+            const TensorVer Ta = P->tens[va], Tb = P->tens[vb];
+            std::vector<int32_t> shared, free_a, free_b;
+            for (int e : Ta.legs) {
+                if (std::find(Tb.legs.begin(), Tb.legs.end(), e) != Tb.legs.end()) shared.push_back(e);
+                else free_a.push_back(e);
+            }
+            for (int e : Tb.legs)
+                if (std::find(shared.begin(), shared.end(), e) == shared.end()) free_b.push_back(e);
+            const int64_t D = prod_dims(shared, E);
+            const int64_t ma = Ta.size / D, mb = Tb.size / D;
+            const int64_t ka = std::min(ma, D), kb = std::min(mb, D);
+            const int64_t nw = std::min<int64_t>(o.chi, std::min(ka, kb));
+            const int32_t e_new = next_edge++;
+            E.push_back({nw, a, b, true});
+            P->ops.push_back({1, a, b, e_new, ma, D, mb, nw});
+            TensorVer Ta2, Tb2;
+            Ta2.legs = free_a;
+            Ta2.legs.push_back(e_new);
+            Ta2.size = ma * nw;
+            Tb2.legs.push_back(e_new);
+            Tb2.legs.insert(Tb2.legs.end(), free_b.begin(), free_b.end());
+            Tb2.size = nw * mb;
+            if (!shapes_only) {
+                Compression c{};
+                c.a_ver_in = va;
+                c.b_ver_in = vb;
+                c.ma = ma;
+                c.D = D;
+                c.mb = mb;
+                c.chi_new = (int32_t)nw;
+                const int32_t comp_id = (int32_t)P->comps.size();
+                int side_level[2];
+                for (int side = 0; side < 2; ++side) {
+                    const TensorVer& T = side == 0 ? Ta : Tb;
+                    const int32_t ver = side == 0 ? va : vb;
+                    const std::vector<int32_t>& fr = side == 0 ? free_a : free_b;
+                    const int64_t mm = side == 0 ? ma : mb;
+                    Step st;
+                    st.level = T.level + 1;
+                    st.comp = comp_id;
+                    st.in_a = ver;
+                    if (mm > D) {
+                        // Gram: side A -> A_mat^T A_mat ; side B -> B_mat B_mat^T  (both D x D)
+                        st.kind = ST_GRAM;
+                        st.M = D;
+                        st.N = D;
+                        st.K = mm;
+                        st.va = tensor_view(T, shared, fr, E);
+                        st.vb = tensor_view(T, fr, shared, E);
+                        int64_t splits = (mm + 2047) / 2048;
+                        splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
+                        int64_t kps = (mm + splits - 1) / splits;
+                        kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
+                        splits = (mm + kps - 1) / kps;
+                        st.splits = (int32_t)splits;
+                        st.k_per_split = (int32_t)kps;
+                        st.out_buf = new_buf(splits * D * D * 8, BUF_GRAM, st.level);
+                        // algorithmic cost of the R-factor: a QR of an (mm x D) matrix (SI section D)
+                        st.flops = 2.0 * (double)mm * D * D - 2.0 / 3.0 * (double)D * D * D;
+                        st.bytes = (double)w * mm * D;
+                        (side == 0 ? c.gram_a : c.gram_b) = 1;
+                        (side == 0 ? c.splits_a : c.splits_b) = (int32_t)splits;
+                    } else {
+                        // explicit factor: side A -> A_mat (ma x D); side B -> B_mat^T (mb x D)
+                        st.kind = ST_COPY;
+                        st.copy_rows = (int32_t)mm;
+                        st.copy_cols = (int32_t)D;
+                        st.va = tensor_view(T, fr, shared, E);
+                        st.out_buf = new_buf(mm * D * 8, BUF_FACTOR, st.level);
+                        st.bytes = (double)(w + 8) * mm * D;
+                        (side == 0 ? c.rows_a : c.rows_b) = (int32_t)mm;
+                    }
+                    (side == 0 ? c.side_a_buf : c.side_b_buf) = st.out_buf;
+                    read_tensor(ver, st.level);
+                    side_level[side] = st.level;
+                    P->steps.push_back(st);
+                }
+                Step core;
+                core.kind = ST_CORE;
+                core.level = 1 + std::max(side_level[0], side_level[1]);
+                core.comp = comp_id;
+                touch(c.side_a_buf, core.level);
+                touch(c.side_b_buf, core.level);
+                c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
+                c.pl_buf = new_buf(D * nw * w, BUF_PROJ, core.level);
+                c.pr_buf = new_buf(nw * D * w, BUF_PROJ, core.level);
+                {
+                    const double p = (double)std::max(ka, kb), q = (double)std::min(ka, kb);
+                    core.flops = 2.0 * ka * D * kb + 4.0 * p * q * q - 4.0 / 3.0 * q * q * q;
+                    core.bytes = 0;
+                }
+                c.core_step = (int32_t)P->steps.size();
+                P->steps.push_back(core);
+                for (int side = 0; side < 2; ++side) {
+                    const TensorVer& T = side == 0 ? Ta : Tb;
+                    const int32_t ver = side == 0 ? va : vb;
+                    Step st;
+                    st.kind = ST_ABSORB;
+                    st.level = core.level + 1;
+                    st.comp = comp_id;
+                    st.in_a = ver;
+                    st.proj_left = side == 0 ? 1 : 0;
+                    st.proj_buf = side == 0 ? c.pl_buf : c.pr_buf;
+                    if (side == 0) {   // a' = A_mat . P_L   (ma x D) (D x nw)
+                        st.M = ma;
+                        st.N = nw;
+                        st.K = D;
+                        st.va = tensor_view(T, free_a, shared, E);
+                        st.vb = dense_view(D, nw);
+                    } else {           // b' = P_R . B_mat   (nw x D) (D x mb)
+                        st.M = nw;
+                        st.N = mb;
+                        st.K = D;
+                        st.va = dense_view(nw, D);
+                        st.vb = tensor_view(T, shared, free_b, E);
+                    }
+                    add_gemm_flops(st);
+                    TensorVer& out = side == 0 ? Ta2 : Tb2;
+                    out.level = st.level;
+                    out.buf = new_buf(out.size * w, BUF_TENSOR, st.level);
+                    P->tens.push_back(out);
+                    st.out_t = (int32_t)P->tens.size() - 1;
+                    (side == 0 ? c.a_ver_out : c.b_ver_out) = st.out_t;
+                    read_tensor(ver, st.level);
+                    touch(st.proj_buf, st.level);
+                    P->steps.push_back(st);
+                }
+                P->comps.push_back(c);
+                live[a] = c.a_ver_out;
+                live[b] = c.b_ver_out;
+            } else {
+                P->tens.push_back(Ta2);
+                live[a] = (int32_t)P->tens.size() - 1;
+                P->tens.push_back(Tb2);
+                live[b] = (int32_t)P->tens.size() - 1;
+            }
+            for (int e : shared) E[e].alive = false;
+        }
+    }
+    int32_t last = -1;
+    for (int id = 0; id < total_ids; ++id)
+        if (live[id] >= 0) last = live[id];
+    P->final_tensor = last;
+    if (shapes_only) return "";
+    if (P->tens[last].size != 1) return "the tree does not reduce the network to a scalar";
+
+    // ---------------------------------------------------------- levels, per-tile max slots
+    int32_t maxl = 0;
+    for (auto& s : P->steps) maxl = std::max(maxl, s.level);
+    P->n_levels = maxl;
+    for (auto& b : P->bufs)
+        if (b.kind == BUF_INPUT) b.hi = INT_MAX;
+    // the final tensor is read by the result kernel after the last level
+    P->bufs[P->tens[last].buf].hi = INT_MAX;
+
+    // ---------------------------------------------------------- arena: allocate by level, free after last use
+    std::vector<std::vector<int32_t>> starts(maxl + 1), ends(maxl + 1);
+    std::vector<int32_t> persistent;
+    for (int32_t b = 0; b < (int32_t)P->bufs.size(); ++b) {
+        Buf& B = P->bufs[b];
+        starts[std::min(B.lo, maxl)].push_back(b);
+        if (B.hi != INT_MAX) ends[std::min(B.hi, maxl)].push_back(b);
+    }
+    std::map<int64_t, int64_t> freel;   // offset -> size
+    int64_t top = 0;
+    auto alloc = [&](int64_t bytes) {
+        bytes = align_up(bytes);
+        for (auto it = freel.begin(); it != freel.end(); ++it) {
+            if (it->second >= bytes) {
+                int64_t off = it->first;
+                int64_t rest = it->second - bytes;
+                freel.erase(it);
+                if (rest > 0) freel[off + bytes] = rest;
+                return off;
+            }
+        }
+        int64_t off = top;
+        // extend a trailing free block if it touches the top
+        if (!freel.empty()) {
+            auto it = std::prev(freel.end());
+            if (it->first + it->second == top) {
+                off = it->first;
+                freel.erase(it);
+            }
+        }
+        top = off + bytes;
+        return off;
+    };
+    auto release = [&](int64_t off, int64_t bytes) {
+        bytes = align_up(bytes);
+        auto it = freel.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != freel.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            freel.erase(nx);
+        }
+        if (it != freel.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                freel.erase(it);
+            }
+        }
+    };
+    for (int L = 0; L <= maxl; ++L) {
+        // largest first for less fragmentation
+        std::sort(starts[L].begin(), starts[L].end(),
+                  [&](int32_t x, int32_t y) { return P->bufs[x].bytes > P->bufs[y].bytes; });
+        for (int32_t b : starts[L]) P->bufs[b].off = alloc(P->bufs[b].bytes);
+        if (!o.keep)
+            for (int32_t b : ends[L]) release(P->bufs[b].off, P->bufs[b].bytes);
+    }
+    P->arena_bytes = top;
+
+    // ---------------------------------------------------------- totals
+    for (auto& s : P->steps) {
+        P->fwd_flops += s.flops;
+        P->fwd_bytes += s.bytes;
+    }
+    for (auto& s : P->steps) {
+        if (s.kind == ST_CONTRACT || s.kind == ST_ABSORB) {
+            // GEMM views are validated here so that errors surface at planning time
+            View v;
+            std::string err = make_view(s.va, &v);
+            if (err.empty()) err = make_view(s.vb, &v);
+            if (!err.empty()) return err;
+        } else if (s.kind == ST_GRAM || s.kind == ST_COPY) {
+            View v;
+            std::string err = make_view(s.va, &v);
+            if (err.empty() && s.kind == ST_GRAM) err = make_view(s.vb, &v);
+            if (!err.empty()) return err;
+        }
+    }
+    if (o.budget > 0 && P->arena_bytes > o.budget) {
+        os << "plan needs " << P->arena_bytes << " device bytes, budget is " << o.budget;
+        return os.str();
+    }
+    return "";
+}
+
+}  // namespace tn

@@ -1,0 +1,119 @@
+// Host planner: expands an ordered contraction tree into a static schedule.
+//
+// Algorithm 1 of arXiv:2206.07044 (section II.F) with early compression and
+// r = 0 is traced on tensor shapes only: every CONTRACT and every COMPRESS
+// it implies (section II.G: compressions follow from the contraction order)
+// becomes a set of device steps with fixed shapes, fixed matricisation Views
+// and fixed arena offsets.  Steps are levelled (a step's level is one more
+// than the latest level of anything it reads) so that every level is a set
+// of independent steps executed as a few grouped kernel launches.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "tn_internal.hpp"
+
+namespace tn {
+
+struct GraphSpec {
+    int32_t n = 0, ne = 0;
+    std::vector<int32_t> eu, ev, ed;
+    std::vector<int64_t> offsets;   // n+1 element offsets of the input tensors
+};
+
+struct TreeOpts {
+    int32_t chi = 0;
+    double cutoff = 0.0;
+    int32_t precision = 0;          // 0 = float64 tensors, 1 = float32 tensors
+    int32_t jacobi_max_sweeps = 40;
+    int64_t budget = 0;
+    int32_t keep = 0;               // never reuse arena memory
+};
+
+// One op of the Algorithm 1 expansion (same fields as the host-only describe call).
+struct OpRec {
+    int64_t kind, a, b, out, m, n, k, new_dim;
+};
+
+enum BufKind { BUF_INPUT = 0, BUF_TENSOR, BUF_GRAM, BUF_FACTOR, BUF_WORK, BUF_PROJ };
+
+struct Buf {
+    int64_t bytes = 0;
+    int32_t lo = 0, hi = 0;         // first and last level that touch it
+    int32_t kind = BUF_TENSOR;
+    int64_t off = -1;               // byte offset in the arena
+};
+
+struct TensorVer {
+    std::vector<int32_t> legs;      // edge ids, axis order (last = fastest)
+    int64_t size = 1;
+    int32_t buf = -1;
+    int32_t level = 0;              // level of the producing step (0 = input)
+    int32_t last_read = 0;
+};
+
+enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB };
+
+struct ViewSpec {                   // a View before arena addresses are known
+    std::vector<int32_t> row_dims, col_dims;            // slowest..fastest
+    std::vector<int64_t> row_strides, col_strides;
+};
+
+struct Step {
+    int32_t kind = ST_CONTRACT;
+    int32_t level = 0;
+    // GEMM-like steps: A (M x K) . B (K x N) -> C
+    int32_t in_a = -1, in_b = -1;   // tensor-version ids (or -1 for a projector operand)
+    int32_t proj_buf = -1;          // ABSORB: projector buffer used as the dense operand
+    int32_t proj_left = 0;          // ABSORB: 1 => A_mat . P_L, 0 => P_R . B_mat
+    int32_t out_t = -1;             // produced tensor version (CONTRACT / ABSORB)
+    int32_t out_buf = -1;           // GRAM partials / COPY factor
+    int64_t M = 0, N = 0, K = 0;
+    int32_t splits = 1, k_per_split = 0;
+    ViewSpec va, vb;                // for COPY only va is used
+    int32_t copy_rows = 0, copy_cols = 0;
+    // CORE
+    int32_t comp = -1;              // compression index
+    double flops = 0, bytes = 0;
+};
+
+struct Compression {
+    int32_t a_ver_in, b_ver_in, a_ver_out, b_ver_out;
+    int64_t ma, D, mb;
+    int32_t chi_new;
+    int32_t side_a_buf, side_b_buf;     // Gram partials or explicit factor
+    int32_t gram_a, gram_b;             // 1 if the side is a Gram
+    int32_t splits_a, splits_b;
+    int32_t rows_a, rows_b;             // explicit factor rows
+    int32_t work_buf, pl_buf, pr_buf;
+    int32_t core_step;
+};
+
+struct Plan {
+    GraphSpec g;
+    TreeOpts opts;
+    std::vector<TensorVer> tens;        // creation order == scale-slot order
+    std::vector<Buf> bufs;
+    std::vector<Step> steps;
+    std::vector<Compression> comps;
+    std::vector<OpRec> ops;
+    int32_t n_levels = 0;
+    int32_t final_tensor = -1;
+    int64_t arena_bytes = 0;
+    int64_t max_parts = 0;              // per-level per-tile max slots needed
+    double fwd_flops = 0, fwd_bytes = 0;
+    int32_t elem_size = 8;
+};
+
+// Validate the graph (returns "" or an error message).
+std::string check_graph(const GraphSpec& g);
+// Expand Algorithm 1 on shapes.  With `shapes_only` nothing but `ops` is built.
+std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj, int32_t n_steps,
+                       const TreeOpts& o, bool shapes_only, Plan* out);
+// Convert a ViewSpec to a device View (merges adjacent legs, checks limits).
+std::string make_view(const ViewSpec& s, View* v);
+
+}  // namespace tn

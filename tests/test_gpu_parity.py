@@ -1,0 +1,171 @@
+"""GPU parity: the HIP path against the float64 CPU oracle on the same seeded
+inputs and the same tree.
+
+Tolerances: float64 mode 1e-10 relative on ln|Z| (a bound the method's
+arithmetic meets with a wide margin: Gram + pivoted Cholesky reproduces the
+QR-reduced factors to ~1e-14, see the oracle experiments); float32 mode
+uses the bound derived in the design notes (sqrt(#ops) * 1e-6 relative).
+Runs whose oracle flags a truncation tie are excluded from value parity
+(several truncations are then equally correct).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from tninputs import (Graph, dimer_tensors, greedy_tree, ising_tensors, lattice, normal_tensors, random_regular3)
+from tninputs.trees import sweep_tree
+
+from _gpu_helpers import gpu_eval
+
+pytestmark = pytest.mark.gpu
+
+FP64_RTOL = 1e-10
+
+
+def _check(g, T, pairs, chi, precision="fp64", rtol=FP64_RTOL):
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    ties = any(o.tie for o in want.ops if o.kind == "compress")
+    print(f"case n={g.n} chi={chi} {precision}: oracle ln|Z|={want.ln_abs_z!r} sign={want.sign} ties={ties}", flush=True)
+    sign, lnz, m, e, stats = gpu_eval(g, T, pairs, chi, precision)
+    if want.sign == 0:
+        assert sign == 0 and m == 0.0 and e == -math.inf
+        return want, None
+    assert sign == want.sign
+    if not ties:
+        rel = abs(lnz - want.ln_abs_z) / max(1.0, abs(want.ln_abs_z))
+        assert rel <= rtol, (lnz, want.ln_abs_z, rel)
+    # mantissa/exponent form agrees with ln|Z|
+    assert 1.0 <= abs(m) < 10.0
+    assert abs((math.log10(abs(m)) + e) * math.log(10.0) - lnz) < 1e-9 * max(1.0, abs(lnz))
+    comp = [o for o in want.ops if o.kind == "compress"]
+    if stats is not None and comp:
+        disc, tie, sweeps = stats
+        assert len(disc) == len(comp)
+        assert np.all(sweeps >= 0)
+        if precision == "fp64" and not ties:
+            np.testing.assert_allclose(disc, [o.discarded for o in comp], rtol=1e-6, atol=1e-12)
+    return want, stats
+
+
+@pytest.mark.parametrize("chi", [256, 16, 8, 4, 2])
+def test_ising_8x8(chi):
+    g = lattice((8, 8))
+    _check(g, ising_tensors(g, 0.44), sweep_tree((8, 8)), chi)
+
+
+def test_ising_8x8_exact_transfer_matrix():
+    g = lattice((8, 8))
+    sign, lnz, *_ = gpu_eval(g, ising_tensors(g, 0.44), greedy_tree(g, 256, 0), 256)
+    tm = exact.ising_transfer_matrix((8, 8), 0.44)
+    assert sign == 1.0 and abs(lnz - tm) / tm < 1e-12
+
+
+@pytest.mark.parametrize("chi", [16, 8, 4])
+def test_ising_8x8_greedy(chi):
+    g = lattice((8, 8))
+    _check(g, ising_tensors(g, 0.44), greedy_tree(g, chi, 0), chi)
+
+
+@pytest.mark.parametrize("shape,chi", [((4, 4, 4), 8), ((4, 4, 4), 4), ((3, 3, 4), 16), ((5, 5, 5), 8), ((5, 5, 5), 16)])
+def test_ising_cubic(shape, chi):
+    g = lattice(shape)
+    _check(g, ising_tensors(g, 0.22), sweep_tree(shape), chi)
+
+
+@pytest.mark.parametrize("chi", [4, 8, 16])
+def test_spin_glass_pm_j(chi):
+    g = lattice((4, 4, 4))
+    J = np.random.default_rng(0).choice([-1.0, 1.0], g.n_edges)
+    _check(g, ising_tensors(g, 0.5, J), sweep_tree((4, 4, 4)), chi)
+
+
+@pytest.mark.parametrize("seed,chi", [(0, 4), (1, 8), (2, 16)])
+def test_dimer_random_regular(seed, chi):
+    g = random_regular3(40, seed)
+    _check(g, dimer_tensors(g), greedy_tree(g, chi, seed), chi)
+
+
+def test_dimer_exact_counts():
+    g = random_regular3(20, 3)
+    want = exact.perfect_matchings(g.n, g.edges)
+    sign, lnz, *_ = gpu_eval(g, dimer_tensors(g), greedy_tree(g, 1 << 20, 0), 1 << 20)
+    assert sign == 1.0 and abs(lnz - math.log(want)) < 1e-12
+
+
+def test_dimer_zero():
+    g = Graph(3, [(0, 1, 2), (0, 2, 2), (1, 2, 2)])
+    sign, lnz, m, e, _ = gpu_eval(g, dimer_tensors(g), [(0, 1), (3, 2)], 4)
+    assert sign == 0.0 and m == 0.0 and e == -math.inf
+
+
+@pytest.mark.parametrize("mu,chi", [(0.0, 2), (0.2, 3), (0.5, 4)])
+def test_normal_signs(mu, chi):
+    g = lattice((5, 5))
+    _check(g, normal_tensors(g, mu, 7), sweep_tree((5, 5)), chi)
+
+
+def test_multi_edges_and_wide_dims():
+    # two tensors joined by several edges, odd dimensions, plus a ring around them
+    rng = np.random.default_rng(5)
+    edges = sorted([(0, 1, 3), (0, 1, 2), (1, 2, 5), (2, 3, 3), (0, 3, 4), (0, 2, 2), (1, 3, 3)])
+    g = Graph(4, edges)
+    inc = g.incident()
+    T = [rng.normal(size=tuple(g.edges[e][2] for e in inc[v])) for v in range(4)]
+    for chi in (1, 2, 3, 5, 100):
+        _check(g, T, [(0, 1), (4, 2), (5, 3)], chi)
+
+
+def test_disconnected_outer_product():
+    g = Graph(4, [(0, 1, 2), (2, 3, 3)])
+    rng = np.random.default_rng(1)
+    T = [rng.normal(size=(2,)), rng.normal(size=(2,)), rng.normal(size=(3,)), rng.normal(size=(3,))]
+    _check(g, T, [(0, 1), (2, 3), (4, 5)], 4)
+
+
+def test_single_tensor():
+    g = Graph(1, [])
+    sign, lnz, *_ = gpu_eval(g, [np.array(-2.5)], [], 4)
+    assert sign == -1.0 and abs(lnz - math.log(2.5)) < 1e-15
+
+
+def test_large_exponent_no_overflow():
+    g = lattice((3, 3, 60))
+    T = ising_tensors(g, 2.0)
+    tm = exact.ising_transfer_matrix((3, 3, 60), 2.0)
+    sign, lnz, m, e, _ = gpu_eval(g, T, sweep_tree((3, 3, 60), order=(2, 0, 1)), 1 << 12)
+    assert tm > 709.8 and sign == 1.0 and abs(lnz - tm) / tm < 1e-12
+    assert e == math.floor(tm / math.log(10.0))
+
+
+# ---------------------------------------------------------------------------- float32 mode
+# Tensors and contractions in float32 (MFMA), Gram / core / projectors / exponent in float64.
+# Bound: every op rounds its output to float32 (relative 2^-24 per entry, accumulated over K
+# terms); the error of ln|Z| is a sum of per-op relative perturbations, bounded here by
+# 2e-7 * (#ops) absolute, far above the observed values.
+def _fp32_bound(want):
+    return 2e-7 * len(want.ops)
+
+
+@pytest.mark.parametrize("shape,chi,beta", [((8, 8), 16, 0.44), ((8, 8), 256, 0.44), ((4, 4, 4), 8, 0.22),
+                                            ((5, 5, 5), 8, 0.22)])
+def test_fp32_ising(shape, chi, beta):
+    g = lattice(shape)
+    T = ising_tensors(g, beta)
+    pairs = sweep_tree(shape)
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    sign, lnz, *_ = gpu_eval(g, T, pairs, chi, "fp32")
+    err = abs(lnz - want.ln_abs_z)
+    print(f"fp32 {shape} chi={chi}: |dlnZ|={err:.3e} rel={err / abs(want.ln_abs_z):.3e}", flush=True)
+    assert sign == want.sign and err <= _fp32_bound(want)
+
+
+def test_fp32_dimer():
+    g = random_regular3(40, 0)
+    T = dimer_tensors(g)
+    pairs = greedy_tree(g, 8, 0)
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, 8)
+    sign, lnz, *_ = gpu_eval(g, T, pairs, 8, "fp32")
+    assert sign == want.sign and abs(lnz - want.ln_abs_z) <= _fp32_bound(want)

@@ -1,0 +1,132 @@
+"""CPU tests of the native library's host side (no GPU needed).
+
+* the shared library loads and exports every symbol include/tn.h declares;
+* the host planner expands Algorithm 1 into exactly the oracle's op sequence
+  (same contractions, same compressions in the same order, same shapes);
+* the 32-bit fast division used by every gathered load is exact.
+"""
+import os
+import re
+import subprocess
+import textwrap
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2206_07044_amd as tn
+from tninputs import (dimer_tensors, greedy_tree, ising_tensors, lattice, normal_tensors, random_regular3)
+from tninputs.trees import sweep_tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_header_symbols():
+    lib = tn.load_library()
+    header = open(os.path.join(ROOT, "include", "tn.h")).read()
+    declared = set(re.findall(r"\b(tn_[a-z_]+)\s*\(", header))
+    assert declared == set(tn.exported_symbols())
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_create_without_device_reports_device_error():
+    import ctypes
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(tn.TNError) as e:
+        tn.Context(0)
+    assert e.value.status in (tn.TN_EDEVICE, tn.TN_EINVAL)
+
+
+def _oracle_ops(g, T, pairs, chi):
+    r = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    return [(0 if o.kind == "contract" else 1, o.a, o.b, o.out, o.m, o.n, o.k, o.new_dim) for o in r.ops]
+
+
+def _lib_ops(g, pairs, chi):
+    eu, ev, ed = g.arrays()
+    return tn.tn_plan_describe(g.n, eu, ev, ed, [a for a, _ in pairs], [b for _, b in pairs], chi)
+
+
+CASES = [
+    ("8x8 ising", lambda: lattice((8, 8)), lambda g: ising_tensors(g, 0.44), lambda g: sweep_tree((8, 8)), (4, 16, 256)),
+    ("8x8 greedy", lambda: lattice((8, 8)), lambda g: ising_tensors(g, 0.44), lambda g: greedy_tree(g, 16, 0), (2, 16)),
+    ("4^3", lambda: lattice((4, 4, 4)), lambda g: ising_tensors(g, 0.22), lambda g: sweep_tree((4, 4, 4)), (3, 8)),
+    ("rrg dimer", lambda: random_regular3(24, 1), lambda g: dimer_tensors(g), lambda g: greedy_tree(g, 8, 1), (4, 8)),
+    ("5x5 normal", lambda: lattice((5, 5)), lambda g: normal_tensors(g, 0.2, 0), lambda g: sweep_tree((5, 5)), (2, 3)),
+]
+
+
+@pytest.mark.parametrize("name,mk_g,mk_t,mk_p,chis", CASES, ids=[c[0] for c in CASES])
+def test_schedule_matches_oracle_expansion(name, mk_g, mk_t, mk_p, chis):
+    g = mk_g()
+    T = mk_t(g)
+    pairs = mk_p(g)
+    for chi in chis:
+        assert _lib_ops(g, pairs, chi) == _oracle_ops(g, T, pairs, chi)
+
+
+def test_schedule_12cube_counts_match_tree_trace():
+    from tninputs import simulate_tree
+    g = lattice((12, 12, 12))
+    pairs = sweep_tree((12, 12, 12))
+    ops = _lib_ops(g, pairs, 16)
+    st = simulate_tree(g, pairs, 16)
+    assert sum(o[0] == 0 for o in ops) == st.n_contract == 1727
+    assert sum(o[0] == 1 for o in ops) == st.n_compress
+
+
+def test_describe_rejects_bad_trees():
+    g = lattice((3, 3))
+    eu, ev, ed = g.arrays()
+    pairs = sweep_tree((3, 3))
+    pi = [a for a, _ in pairs]
+    pj = [b for _, b in pairs]
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(g.n, eu, ev, ed, pi[:-1], pj[:-1], 4)        # wrong step count
+    bad = list(pj)
+    bad[3] = pi[3]
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(g.n, eu, ev, ed, pi, bad, 4)                 # pair of one tensor
+    bad = list(pi)
+    bad[5] = pi[0]
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(g.n, eu, ev, ed, bad, pj, 4)                 # reuse of a dead id
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(g.n, ev, eu, ed, pi, pj, 4)                  # u > v
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(g.n, eu, ev, ed * 0, pi, pj, 4)              # zero dimension
+
+
+def test_fastdiv_exact(tmp_path):
+    src = tmp_path / "fd.cpp"
+    src.write_text(textwrap.dedent('''
+        #include "tn_internal.hpp"
+        #include <cstdio>
+        #include <random>
+        using namespace tn;
+        int main() {
+            std::mt19937_64 rng(7);
+            const uint32_t divs[] = {1,2,3,4,5,6,7,8,9,12,16,27,31,32,33,64,81,100,127,128,243,256,1000,
+                                     1024,4095,4096,65535,65536,1000003,(1u<<30),(1u<<31)-1};
+            for (uint32_t d : divs) {
+                FastDiv f = make_fastdiv(d);
+                for (int t = 0; t < 200000; ++t) {
+                    uint32_t n = (t < 1000) ? (uint32_t)t : (uint32_t)(rng() % (1ull << 31));
+                    if (t == 1000) n = (1u << 31) - 1;
+                    if (fd_div(n, f) != n / d) { printf("FAIL %u %u\\n", n, d); return 1; }
+                }
+            }
+            printf("OK\\n");
+            return 0;
+        }'''))
+    exe = tmp_path / "fd"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_2206_07044_amd", "csrc"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and "OK" in out.stdout, out.stdout
