@@ -125,6 +125,29 @@ tn_status tn_fetch(tn_ctx* ctx);
 tn_status tn_compress_stats(const tn_ctx* ctx, int32_t cap, double* discarded, int32_t* tie,
                             int32_t* sweeps, int32_t* n_out);
 
+/* Kernel kinds for tn_profile: grouped contraction / re-absorption GEMMs, Gram
+ * GEMMs, explicit-factor copies, compression cores (LDS-resident, D <= 64, and
+ * global-memory), scale finalisation, large-bond Lanczos compressions. */
+typedef enum {
+    TN_KERNEL_GEMM = 0,
+    TN_KERNEL_GRAM = 1,
+    TN_KERNEL_COPY = 2,
+    TN_KERNEL_CORE_LDS = 3,
+    TN_KERNEL_CORE_GLOBAL = 4,
+    TN_KERNEL_SCALE = 5,
+    TN_KERNEL_LANCZOS = 6
+} tn_kernel_kind;
+
+/* Time every launch of the kinds in `kind_mask` (bit k = tn_kernel_kind k) with
+ * HIP events on the ctx stream during later evaluations, and reset the
+ * totals.  0 switches timing off. */
+tn_status tn_profile(tn_ctx* ctx, uint32_t kind_mask);
+/* Totals since tn_profile for one kind: summed launch durations (ms, measured
+ * at tn_fetch / tn_contract_compressed), number of launches, and the
+ * algorithmic flops and bytes of the steps those launches ran. */
+tn_status tn_profile_read(const tn_ctx* ctx, int32_t kind, double* ms, int64_t* launches, double* flops,
+                          double* bytes);
+
 /* Tensor `index` of the last evaluation, normalised (divided by its largest
  * absolute entry), as float64 in its axis order.  Indices count tensors in
  * creation order: inputs 0..n-1, then each contraction's result, then the two

@@ -229,16 +229,44 @@ def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: 
     return res
 
 
-def _run(n, edges, tensors, pairs, chi, cutoff, explicit) -> OracleResult:
+@dataclass
+class PartialRun:
+    steps_done: int
+    ops: List[OpRecord]
+
+
+def contract_compressed_budget(n, edges, tensors, pairs, chi, budget_s: float, cutoff: float = 0.0) -> PartialRun:
+    """Run the same Algorithm 1 loop for at most ``budget_s`` seconds of wall time
+    (the CPU-baseline timing sample); returns how many tree steps and ops ran."""
+    import time
+    deadline = time.time() + budget_s
+    box = {}
+    try:
+        _run(n, edges, tensors, pairs, chi, cutoff, False, deadline=deadline, progress=box)
+    except _OutOfTime:
+        pass
+    return PartialRun(box.get("steps", 0), box.get("ops", []))
+
+
+class _OutOfTime(Exception):
+    pass
+
+
+def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progress=None) -> OracleResult:
+    import time
     net = _Network(n, edges, tensors)
     scales: List[float] = []
     ops: List[OpRecord] = []
     if len(pairs) != n - 1:
         raise ValueError("a tree over n tensors has n - 1 steps")
+    if progress is not None:
+        progress["ops"] = ops
     try:
         for v in range(n):
             net.t[v] = _normalise(net.t[v], scales)
         for t, (i, j) in enumerate(pairs):
+            if deadline is not None and time.time() > deadline:
+                raise _OutOfTime()
             k = n + t
             if i == j or i not in net.t or j not in net.t:
                 raise ValueError(f"step {t}: ({i}, {j}) are not two live tensors")
@@ -249,6 +277,8 @@ def _run(n, edges, tensors, pairs, chi, cutoff, explicit) -> OracleResult:
                 size = int(np.prod([net.dim[e] for e in shared]))
                 if size > chi:
                     _compress(net, k, l, chi, cutoff, scales, ops, explicit)
+            if progress is not None:
+                progress["steps"] = t + 1
     except ZeroContraction:
         return OracleResult(0.0, -math.inf, ops, scales)
     (last,) = net.t.values()

@@ -18,6 +18,7 @@ TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO = range
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ESTATE", 3: "TN_ENOMEM", 4: "TN_EDEVICE",
                 5: "TN_ENUMERIC", 6: "TN_ZERO"}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+KERNEL_KINDS = {"gemm": 0, "gram": 1, "copy": 2, "core_lds": 3, "core_global": 4, "scale": 5, "lanczos": 6}
 
 
 class TNError(RuntimeError):
@@ -63,6 +64,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_compress_stats": ([P, I32, pD, pI32, pI32, pI32], C.c_int),
         "tn_grad": ([P, pD], C.c_int),
         "tn_read_tensor": ([P, I32, pD, I64, pI64], C.c_int),
+        "tn_profile": ([P, C.c_uint32], C.c_int),
+        "tn_profile_read": ([P, I32, pD, pI64, pD, pD], C.c_int),
         "tn_plan_describe": ([I32, I32, pI32, pI32, pI32, I32, pI32, pI32, C.POINTER(tn_tree_opts), I64, pI64, pI64],
                              C.c_int),
     }
@@ -77,7 +80,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
 def exported_symbols() -> List[str]:
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
             "tn_update_values_device", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
-            "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_grad", "tn_plan_describe"]
+            "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
+            "tn_plan_describe"]
 
 
 def _i32(a) -> np.ndarray:
@@ -201,6 +205,18 @@ class Context:
         self._check(self._lib.tn_compress_stats(self._h, n.value, _ptr(disc, C.c_double), _ptr(tie, C.c_int32),
                                                 _ptr(sw, C.c_int32), C.byref(n)))
         return disc[:n.value], tie[:n.value], sw[:n.value]
+
+    def tn_profile(self, kinds) -> None:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KERNEL_KINDS[k]
+        self._check(self._lib.tn_profile(self._h, mask))
+
+    def tn_profile_read(self, kind: str) -> dict:
+        ms, n, f, b = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        self._check(self._lib.tn_profile_read(self._h, KERNEL_KINDS[kind], C.byref(ms), C.byref(n), C.byref(f),
+                                              C.byref(b)))
+        return {"ms": ms.value, "launches": n.value, "flops": f.value, "bytes": b.value}
 
     def tn_read_tensor(self, index: int) -> np.ndarray:
         n = C.c_int64()

@@ -17,7 +17,7 @@ using namespace tn;
 
 namespace {
 
-enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE };
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS };
 
 struct Launch {
     int kind = 0;
@@ -26,7 +26,12 @@ struct Launch {
     int count = 0;
     int64_t work = 0;     // tiles / elements
     int max_d = 0;
+    int prof = 0;         // tn_kernel_kind for timing
+    double flops = 0;     // algorithmic flops of the steps in this launch
+    double bytes = 0;     // algorithmic bytes of the steps in this launch
 };
+
+constexpr int kKinds = 8;   // >= number of tn_kernel_kind values
 
 }  // namespace
 
@@ -51,6 +56,8 @@ struct tn_ctx {
     std::vector<CoreDesc> h_core;
     std::vector<ScaleDesc> h_scale;
     std::vector<InputDesc> h_inputs;
+    std::vector<LanczosDesc> h_lanczos;
+    LanczosDesc* d_lanczos = nullptr;
     std::vector<Launch> launches;
     GemmDesc* d_gemm = nullptr;
     CopyDesc* d_copy = nullptr;
@@ -68,6 +75,14 @@ struct tn_ctx {
     bool evaluated = false;
     double sign = 0, lnz = 0;
     int flags = 0;
+
+    // per-kind launch timing with HIP events (tn_profile)
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, size_t>> ev_used;   // (kind, index of the start event)
+    double prof_ms[kKinds] = {0};
+    int64_t prof_launches[kKinds] = {0};
+    double prof_flops[kKinds] = {0}, prof_bytes[kKinds] = {0};
 };
 
 namespace {
@@ -98,6 +113,7 @@ void free_plan(tn_ctx* c) {
     dfree(c->d_core);
     dfree(c->d_scale);
     dfree(c->d_inputs);
+    dfree(c->d_lanczos);
     dfree(c->d_scales);
     dfree(c->d_maxparts);
     dfree(c->d_disc);
@@ -108,6 +124,7 @@ void free_plan(tn_ctx* c) {
     c->h_core.clear();
     c->h_scale.clear();
     c->h_inputs.clear();
+    c->h_lanczos.clear();
     c->launches.clear();
     c->has_plan = false;
     c->evaluated = false;
@@ -136,9 +153,14 @@ tn_status build_launches(tn_ctx* c) {
     for (int32_t s = 0; s < (int32_t)P.steps.size(); ++s) by_level[P.steps[s].level].push_back(s);
     int64_t max_parts = 1;
     for (int L = 1; L <= P.n_levels; ++L) {
-        std::map<int, std::vector<GemmDesc>> gemms;   // key -> descs
+        std::map<int, std::vector<GemmDesc>> gemms;   // 2*dtype key + is_gram -> descs
+        std::map<int, std::pair<double, double>> gemm_work;
+        std::pair<double, double> copy_work{0, 0}, core_work[2] = {{0, 0}, {0, 0}};
         std::vector<CopyDesc> copies;
         std::vector<CoreDesc> cores_lds, cores_glb;
+        std::vector<LanczosDesc> lanczos;
+        std::pair<double, double> lanczos_work{0, 0};
+        int lanczos_smax = 1;
         std::vector<ScaleDesc> scales;
         int64_t parts = 0;
         for (int32_t si : by_level[L]) {
@@ -165,7 +187,7 @@ tn_status build_launches(tn_ctx* c) {
                     g.k_per_split = st.k_per_split;
                     g.scale_a = st.in_a;
                     g.square_a = 1;
-                    key = f32 ? GEMM_F32_TO_F64 : GEMM_F64;
+                    key = 2 * (f32 ? GEMM_F32_TO_F64 : GEMM_F64) + 1;
                 } else {
                     g.mode = GEMM_TENSOR;
                     g.splits = 1;
@@ -192,9 +214,11 @@ tn_status build_launches(tn_ctx* c) {
                     sd.tensor = st.out_t;
                     scales.push_back(sd);
                     parts += sd.nparts;
-                    key = f32 ? GEMM_F32 : GEMM_F64;
+                    key = 2 * (f32 ? GEMM_F32 : GEMM_F64);
                 }
                 gemms[key].push_back(g);
+                gemm_work[key].first += st.flops;
+                gemm_work[key].second += st.bytes;
             } else if (st.kind == ST_COPY) {
                 CopyDesc cd;
                 std::memset(&cd, 0, sizeof(cd));
@@ -206,6 +230,35 @@ tn_status build_launches(tn_ctx* c) {
                 cd.cols = st.copy_cols;
                 cd.scale = st.in_a;
                 copies.push_back(cd);
+                copy_work.first += st.flops;
+                copy_work.second += st.bytes;
+            } else if (st.kind == ST_LANCZOS) {
+                const Compression& cp = P.comps[st.comp];
+                LanczosDesc ld;
+                std::memset(&ld, 0, sizeof(ld));
+                std::string err = fill_view(st.va, &ld.va);
+                if (err.empty()) err = fill_view(st.vb, &ld.vb);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                ld.A = ten_ptr(st.in_a);
+                ld.B = ten_ptr(st.in_b);
+                ld.work = (double*)buf_ptr(cp.work_buf);
+                ld.p_left = buf_ptr(cp.pl_buf);
+                ld.p_right = buf_ptr(cp.pr_buf);
+                ld.cutoff = P.opts.cutoff;
+                ld.ma = (int32_t)cp.ma;
+                ld.mb = (int32_t)cp.mb;
+                ld.D = (int32_t)cp.D;
+                ld.chi_new = cp.chi_new;
+                ld.s_min = cp.s_min;
+                ld.s_max = cp.s_max;
+                ld.scale_a = st.in_a;
+                ld.scale_b = st.in_b;
+                ld.stat = st.comp;
+                ld.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
+                lanczos_smax = std::max(lanczos_smax, cp.s_max);
+                lanczos.push_back(ld);
+                lanczos_work.first += st.flops;
+                lanczos_work.second += st.bytes;
             } else if (st.kind == ST_CORE) {
                 const Compression& cp = P.comps[st.comp];
                 CoreDesc cd;
@@ -227,13 +280,19 @@ tn_status build_launches(tn_ctx* c) {
                 cd.stat = st.comp;
                 cd.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
                 (cp.D <= kCoreLdsMaxD ? cores_lds : cores_glb).push_back(cd);
+                auto& cw = core_work[cp.D <= kCoreLdsMaxD ? 0 : 1];
+                cw.first += st.flops;
+                cw.second += st.bytes;
             }
         }
         max_parts = std::max(max_parts, parts);
         for (auto& kv : gemms) {
             Launch l;
             l.kind = L_GEMM;
-            l.key = kv.first;
+            l.key = kv.first / 2;
+            l.prof = (kv.first & 1) ? TN_KERNEL_GRAM : TN_KERNEL_GEMM;
+            l.flops = gemm_work[kv.first].first;
+            l.bytes = gemm_work[kv.first].second;
             l.begin = (int64_t)c->h_gemm.size();
             l.count = (int)kv.second.size();
             int64_t tiles = 0;
@@ -249,6 +308,9 @@ tn_status build_launches(tn_ctx* c) {
             Launch l;
             l.kind = L_COPY;
             l.key = f32 ? 1 : 0;
+            l.prof = TN_KERNEL_COPY;
+            l.flops = copy_work.first;
+            l.bytes = copy_work.second;
             l.begin = (int64_t)c->h_copy.size();
             l.count = (int)copies.size();
             int64_t elems = 0;
@@ -266,6 +328,9 @@ tn_status build_launches(tn_ctx* c) {
             Launch l;
             l.kind = L_CORE;
             l.key = pass == 0 ? 1 : 0;
+            l.prof = pass == 0 ? TN_KERNEL_CORE_LDS : TN_KERNEL_CORE_GLOBAL;
+            l.flops = core_work[pass].first;
+            l.bytes = core_work[pass].second;
             l.begin = (int64_t)c->h_core.size();
             l.count = (int)v.size();
             for (auto& cd : v) {
@@ -274,9 +339,23 @@ tn_status build_launches(tn_ctx* c) {
             }
             c->launches.push_back(l);
         }
+        if (!lanczos.empty()) {
+            Launch l;
+            l.kind = L_LANCZOS;
+            l.key = f32 ? 1 : 0;
+            l.prof = TN_KERNEL_LANCZOS;
+            l.begin = (int64_t)c->h_lanczos.size();
+            l.count = (int)lanczos.size();
+            l.max_d = lanczos_smax;
+            l.flops = lanczos_work.first;
+            l.bytes = lanczos_work.second;
+            for (auto& ld : lanczos) c->h_lanczos.push_back(ld);
+            c->launches.push_back(l);
+        }
         if (!scales.empty()) {
             Launch l;
             l.kind = L_SCALE;
+            l.prof = TN_KERNEL_SCALE;
             l.begin = (int64_t)c->h_scale.size();
             l.count = (int)scales.size();
             for (auto& sd : scales) c->h_scale.push_back(sd);
@@ -298,6 +377,7 @@ tn_status build_launches(tn_ctx* c) {
     if ((s = upload(c, &c->d_core, c->h_core)) != TN_OK) return s;
     if ((s = upload(c, &c->d_scale, c->h_scale)) != TN_OK) return s;
     if ((s = upload(c, &c->d_inputs, c->h_inputs)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_lanczos, c->h_lanczos)) != TN_OK) return s;
     HIP_TRY(c, hipMalloc((void**)&c->d_scales, std::max<size_t>(1, P.tens.size()) * sizeof(double)));
     HIP_TRY(c, hipMalloc((void**)&c->d_maxparts, (size_t)max_parts * sizeof(double)));
     const size_t nc = std::max<size_t>(1, P.comps.size());
@@ -350,6 +430,7 @@ void tn_destroy(tn_ctx* c) {
     dfree(c->d_result);
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -465,6 +546,20 @@ tn_status tn_enqueue(tn_ctx* c) {
     hipStream_t s = c->stream;
     HIP_TRY(c, launch_inputs(f32, c->d_inputs, (int)c->h_inputs.size(), c->d_staging, c->d_scales, s));
     for (const Launch& l : c->launches) {
+        const bool timed = (c->prof_mask >> l.prof) & 1u;
+        if (timed) {
+            const size_t i0 = c->ev_used.empty() ? 0 : c->ev_used.back().second + 2;
+            while (c->ev_pool.size() < i0 + 2) {
+                hipEvent_t e;
+                HIP_TRY(c, hipEventCreate(&e));
+                c->ev_pool.push_back(e);
+            }
+            HIP_TRY(c, hipEventRecord(c->ev_pool[i0], s));
+            c->ev_used.push_back({l.prof, i0});
+            c->prof_launches[l.prof] += 1;
+            c->prof_flops[l.prof] += l.flops;
+            c->prof_bytes[l.prof] += l.bytes;
+        }
         switch (l.kind) {
             case L_GEMM:
                 HIP_TRY(c, launch_gemm(l.key, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, s));
@@ -476,10 +571,15 @@ tn_status tn_enqueue(tn_ctx* c) {
                 HIP_TRY(c, launch_core(l.key, f32, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
                                        c->d_disc, c->d_tie, c->d_sweeps, s));
                 break;
+            case L_LANCZOS:
+                HIP_TRY(c, launch_lanczos(l.key, c->d_lanczos + l.begin, l.count, l.max_d, c->d_scales,
+                                          P.opts.jacobi_max_sweeps, c->d_disc, c->d_tie, c->d_sweeps, s));
+                break;
             case L_SCALE:
                 HIP_TRY(c, launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, s));
                 break;
         }
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
     }
     const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
     HIP_TRY(c, launch_result(f32, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
@@ -492,6 +592,12 @@ tn_status tn_fetch(tn_ctx* c) {
     if (!c) return TN_EINVAL;
     if (!c->has_plan) return fail(c, TN_ESTATE, "no plan");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& u : c->ev_used) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
+        c->prof_ms[u.first] += ms;
+    }
+    c->ev_used.clear();
     c->sign = c->h_result[0];
     c->lnz = c->h_result[1];
     c->flags = (int)c->h_result[2];
@@ -546,6 +652,28 @@ tn_status tn_compress_stats(const tn_ctx* c0, int32_t cap, double* discarded, in
         if (tie) HIP_TRY(c, hipMemcpy(tie, c->d_tie, k * sizeof(int32_t), hipMemcpyDeviceToHost));
         if (sweeps) HIP_TRY(c, hipMemcpy(sweeps, c->d_sweeps, k * sizeof(int32_t), hipMemcpyDeviceToHost));
     }
+    return TN_OK;
+}
+
+tn_status tn_profile(tn_ctx* c, uint32_t kind_mask) {
+    if (!c) return TN_EINVAL;
+    c->prof_mask = kind_mask;
+    for (int k = 0; k < kKinds; ++k) {
+        c->prof_ms[k] = 0;
+        c->prof_launches[k] = 0;
+        c->prof_flops[k] = c->prof_bytes[k] = 0;
+    }
+    return TN_OK;
+}
+
+tn_status tn_profile_read(const tn_ctx* c, int32_t kind, double* ms, int64_t* launches, double* flops,
+                          double* bytes) {
+    if (!c) return TN_EINVAL;
+    if (kind < 0 || kind >= kKinds) return TN_EINVAL;
+    if (ms) *ms = c->prof_ms[kind];
+    if (launches) *launches = c->prof_launches[kind];
+    if (flops) *flops = c->prof_flops[kind];
+    if (bytes) *bytes = c->prof_bytes[kind];
     return TN_OK;
 }
 

@@ -127,6 +127,22 @@ struct CoreDesc {
     int32_t kmin;                // min(k_A, k_B): number of singular values of the structural core
 };
 
+// Large-core compression by Golub-Kahan-Lanczos on M = (A/s_a)(B/s_b) read through Views.
+struct LanczosDesc {
+    const void* A;               // tensor a
+    const void* B;               // tensor b
+    double* work;                // float64 workspace (layout fixed by the kernel)
+    void* p_left;                // D x chi' projector in the tensor dtype
+    void* p_right;               // chi' x D projector in the tensor dtype
+    double cutoff;
+    int32_t ma, mb, D, chi_new;
+    int32_t s_min, s_max;        // Krylov steps before the first convergence check / at most
+    int32_t scale_a, scale_b;
+    int32_t stat, kmin;
+    View va;                     // A_mat: rows = free legs of a, cols = shared legs
+    View vb;                     // B_mat: rows = shared legs, cols = free legs of b
+};
+
 // Upload of one input tensor: float64 staging -> arena (converted to the tensor dtype).
 struct InputDesc {
     void* dst;

@@ -222,7 +222,9 @@ __global__ __launch_bounds__(256) void copy_grouped(const CopyDesc* __restrict__
 // Compression core: one workgroup per compression
 // ------------------------------------------------------------------------------------------
 constexpr int kCoreThreads = 1024;
-constexpr double kNoiseRel = 1e-13;
+constexpr double kNoiseRel = 1e-13;   // singular values below this * sigma_1 are zeros
+constexpr double kZeroRel = 1e-14;    // Jacobi leaves columns below this * ||W||_F alone
+constexpr double kLanczosBreak = 1e-13;   // Krylov breakdown relative to the largest alpha/beta
 constexpr int kCoreWaves = kCoreThreads / 64;
 
 struct CoreShared {
@@ -303,6 +305,107 @@ __device__ inline int rr_col(int pos, int round, int n) {
     return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
 }
 
+// One-sided (Hestenes) Jacobi on the columns of W (rows x cols, column j at W + j*ld),
+// accumulating the rotations in V (cols x cols, column j at V + j*ld, identity on entry).
+// Pairs follow a round-robin tournament; one wave rotates one pair.  A pair is rotated
+// while its columns are not orthogonal to relative precision tol; columns whose norm is
+// at the rounding level of ||W||_F (rank-deficient matrices) are numerically zero and are
+// left alone, else their noise would keep rotating forever.  Returns convergence.
+__device__ bool jacobi_svd(double* W, double* V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
+                           int* sweeps_out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nc = cols + (cols & 1);
+    const double tol = 2.220446049250313e-16 * (double)max(rows, 16);
+    {
+        double f = 0.0;
+        for (int64_t idx = tid; idx < (int64_t)rows * cols; idx += kCoreThreads) {
+            const int j = (int)(idx / rows), i = (int)(idx - (int64_t)j * rows);
+            const double x = W[(int64_t)j * ld + i];
+            f += x * x;
+        }
+        f = wave_sum(f);
+        if (lane == 0) sh.rv[wave] = f;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+            sh.rv[0] = t;
+        }
+        __syncthreads();
+    }
+    const double zero2 = kZeroRel * kZeroRel * sh.rv[0];
+    __syncthreads();
+    int sweeps = 0;
+    bool converged = (cols <= 1);
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        if (tid == 0) sh.flag = 0;
+        __syncthreads();
+        for (int round = 0; round < nc - 1; ++round) {
+            for (int q = wave; q < nc / 2; q += kCoreWaves) {
+                const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
+                if (p1 >= cols || p2 >= cols) continue;
+                double* w1 = W + (int64_t)p1 * ld;
+                double* w2 = W + (int64_t)p2 * ld;
+                double a = 0.0, b = 0.0, g = 0.0;
+                for (int i = lane; i < rows; i += 64) {
+                    const double x = w1[i], y = w2[i];
+                    a += x * x;
+                    b += y * y;
+                    g += x * y;
+                }
+                a = wave_sum(a);
+                b = wave_sum(b);
+                g = wave_sum(g);
+                if (a > zero2 && b > zero2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+                    const double zeta = (b - a) / (2.0 * g);
+                    const double az = fabs(zeta);
+                    const double root = az > 1e100 ? az : sqrt(1.0 + zeta * zeta);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
+                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                    for (int i = lane; i < rows; i += 64) {
+                        const double x = w1[i], y = w2[i];
+                        w1[i] = c * x - s * y;
+                        w2[i] = s * x + c * y;
+                    }
+                    double* v1 = V + (int64_t)p1 * ld;
+                    double* v2 = V + (int64_t)p2 * ld;
+                    for (int i = lane; i < cols; i += 64) {
+                        const double x = v1[i], y = v2[i];
+                        v1[i] = c * x - s * y;
+                        v2[i] = s * x + c * y;
+                    }
+                    if (lane == 0) sh.flag = 1;
+                }
+            }
+            __syncthreads();
+        }
+        sweeps = sweep + 1;
+        if (!sh.flag) converged = true;
+        __syncthreads();
+    }
+    *sweeps_out = sweeps;
+    return converged;
+}
+
+// Column norms of W (sig[j], j < cols) and their descending order (ties: lower column first).
+__device__ void sorted_norms(const double* W, int rows, int cols, int ld, double* sig, int* order) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = wave; j < cols; j += kCoreWaves) {
+        double s = 0.0;
+        for (int i = lane; i < rows; i += 64) s += W[(int64_t)j * ld + i] * W[(int64_t)j * ld + i];
+        s = wave_sum(s);
+        if (lane == 0) sig[j] = sqrt(s);
+    }
+    __syncthreads();
+    for (int j = tid; j < cols; j += kCoreThreads) {
+        const double sj = sig[j];
+        int rank = 0;
+        for (int q = 0; q < cols; ++q) rank += (sig[q] > sj) || (sig[q] == sj && q < j);
+        order[rank] = j;
+    }
+    __syncthreads();
+}
+
 template <bool kLds, typename Tp>
 __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
                                                             double* __restrict__ stat_disc,
@@ -361,97 +464,15 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
     }
     __syncthreads();
 
-    // ---- one-sided (Hestenes) Jacobi on the columns of W, accumulating V.
-    // A pair is rotated while its columns are not orthogonal to relative precision
-    // tol; columns whose norm is at the rounding level of ||W||_F (rank-deficient
-    // cores) are numerically zero and are left alone, else their noise would keep
-    // rotating forever.
-    const int nc = rb + (rb & 1);
-    const double tol = 2.220446049250313e-16 * (double)max(ra, 16);
-    {
-        double f = 0.0;
-        for (int64_t idx = tid; idx < (int64_t)ra * rb; idx += kCoreThreads) {
-            const int j = (int)(idx / ra), i = (int)(idx - (int64_t)j * ra);
-            const double x = W[(int64_t)j * D + i];
-            f += x * x;
-        }
-        f = wave_sum(f);
-        if (lane == 0) sh.rv[wave] = f;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
-            sh.rv[0] = t;
-        }
-        __syncthreads();
-    }
-    const double fro2 = sh.rv[0];
-    const double zero2 = 1e-28 * fro2;   // (1e-14 ||W||_F)^2
-    __syncthreads();
+    // ---- one-sided (Hestenes) Jacobi on the columns of W, accumulating V
     int sweeps = 0;
-    bool converged = (rb <= 1);
-    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-        if (tid == 0) sh.flag = 0;
-        __syncthreads();
-        for (int round = 0; round < nc - 1; ++round) {
-            for (int q = wave; q < nc / 2; q += kCoreWaves) {
-                const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
-                if (p1 >= rb || p2 >= rb) continue;
-                double* w1 = W + (int64_t)p1 * D;
-                double* w2 = W + (int64_t)p2 * D;
-                double a = 0.0, b = 0.0, g = 0.0;
-                for (int i = lane; i < ra; i += 64) {
-                    const double x = w1[i], y = w2[i];
-                    a += x * x;
-                    b += y * y;
-                    g += x * y;
-                }
-                a = wave_sum(a);
-                b = wave_sum(b);
-                g = wave_sum(g);
-                if (a > zero2 && b > zero2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-                    const double zeta = (b - a) / (2.0 * g);
-                    const double az = fabs(zeta);
-                    const double root = az > 1e100 ? az : sqrt(1.0 + zeta * zeta);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                    for (int i = lane; i < ra; i += 64) {
-                        const double x = w1[i], y = w2[i];
-                        w1[i] = c * x - s * y;
-                        w2[i] = s * x + c * y;
-                    }
-                    double* v1 = V + (int64_t)p1 * D;
-                    double* v2 = V + (int64_t)p2 * D;
-                    for (int i = lane; i < rb; i += 64) {
-                        const double x = v1[i], y = v2[i];
-                        v1[i] = c * x - s * y;
-                        v2[i] = s * x + c * y;
-                    }
-                    if (lane == 0) sh.flag = 1;
-                }
-            }
-            __syncthreads();
-        }
-        sweeps = sweep + 1;
-        if (!sh.flag) converged = true;
-        __syncthreads();
-    }
+    const bool converged = jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
 
     // ---- singular values and descending order (ties: lower column first)
-    for (int j = wave; j < rb; j += kCoreWaves) {
-        double s = 0.0;
-        for (int i = lane; i < ra; i += 64) s += W[(int64_t)j * D + i] * W[(int64_t)j * D + i];
-        s = wave_sum(s);
-        if (lane == 0) sig[j] = sqrt(s);
-    }
-    __syncthreads();
-    for (int j = tid; j < rb; j += kCoreThreads) {
-        const double sj = sig[j];
-        int rank = 0;
-        for (int q = 0; q < rb; ++q) rank += (sig[q] > sj) || (sig[q] == sj && q < j);
-        order[rank] = j;
-    }
-    __syncthreads();
+    sorted_norms(W, ra, rb, D, sig, order);
+    double fro = 0.0;
+    for (int j = 0; j < rb; ++j) fro += sig[j] * sig[j];
+    fro = sqrt(fro);
 
     // ---- projectors P_L (D x chi') and P_R (chi' x D)
     const int cn = d.chi_new;
@@ -466,7 +487,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
         // singular values below kNoiseRel * sigma_1 are numerical zeros of an FP64 core: their
         // vectors are rounding noise, and dividing by them would amplify it (they change A B by
         // less than kNoiseRel relative when dropped)
-        if (s > kNoiseRel * smax && s >= d.cutoff * smax) {
+        if (s > kNoiseRel * smax && s > 4.0 * kZeroRel * fro && s >= d.cutoff * smax) {
             const double* v = V + (int64_t)j * D;
             const double* u = W + (int64_t)j * D;
             for (int i = 0; i < rb; ++i) pl += Rb[(int64_t)i * D + dd] * v[i];
@@ -492,6 +513,293 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
         const double s_next = (cn < rb) ? sig[order[cn]] : 0.0;
         stat_tie[d.stat] = (d.kmin > cn && s_last - s_next <= 1e-12 * smax) ? 1 : 0;
         stat_sweeps[d.stat] = converged ? sweeps : -1 - sweeps;   // negative: not converged
+    }
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Large cores: Golub-Kahan-Lanczos truncated SVD of M = (A/s_a)(B/s_b), one workgroup per
+// compression, reading the two tensors through their matricisation Views.
+// ------------------------------------------------------------------------------------------
+__device__ double block_sum(double v, CoreShared& sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh.rv[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+    __syncthreads();
+    return t;
+}
+
+// x (n) -= Q[:, :k] (Q[:, :k]^T x), twice (classical Gram-Schmidt with reorthogonalisation).
+__device__ void reorthogonalise(double* x, const double* Q, int n, int k, double* coef) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = wave; j < k; j += kCoreWaves) {
+            const double* q = Q + (int64_t)j * n;
+            double c = 0.0;
+            for (int i = lane; i < n; i += 64) c += q[i] * x[i];
+            c = wave_sum(c);
+            if (lane == 0) coef[j] = c;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += kCoreThreads) {
+            double acc = x[i];
+            for (int j = 0; j < k; ++j) acc -= Q[(int64_t)j * n + i] * coef[j];
+            x[i] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// deterministic, generic start / restart vector
+__device__ inline double probe_entry(int i, int r) {
+    const double x = (double)i;
+    return cos(0.7 * x + 0.3 + 1.1 * r) + 0.5 * sin(1.9 * x + 0.7 * r + 0.1);
+}
+
+template <typename Tin, typename Tp>
+__global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc* __restrict__ descs,
+                                                               const double* __restrict__ scales, int max_sweeps,
+                                                               double* __restrict__ stat_disc,
+                                                               int32_t* __restrict__ stat_tie,
+                                                               int32_t* __restrict__ stat_sweeps) {
+    extern __shared__ double lds[];
+    __shared__ CoreShared sh;
+    __shared__ double coef[kLanczosMaxSteps + 1];
+    const LanczosDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ma = d.ma, mb = d.mb, D = d.D, cn = d.chi_new, smax_steps = d.s_max, ls = d.s_max + 1;
+    const Tin* __restrict__ A = (const Tin*)d.A;
+    const Tin* __restrict__ B = (const Tin*)d.B;
+    const double ia = inv_scale(scales, d.scale_a), ib = inv_scale(scales, d.scale_b);
+
+    double* U = d.work;                                   // ma x s_max
+    double* V = U + (int64_t)ma * smax_steps;             // mb x (s_max + 1)
+    double* Ut = V + (int64_t)mb * (smax_steps + 1);      // ma x cn  Ritz vectors of M
+    double* Vt = Ut + (int64_t)ma * cn;                   // mb x cn
+    double* t1 = Vt + (int64_t)mb * cn;                   // D
+    double* t2 = t1 + D;                                  // D
+    double* alpha = t2 + D;                               // s_max
+    double* beta = alpha + smax_steps;                    // s_max
+    double* sig = beta + smax_steps;                      // s_max + 1
+    double* Wg = sig + ls;                                // (s_max + 1)^2 (global fallback)
+    double* Vg = Wg + (int64_t)ls * ls;                   // (s_max + 1)^2
+    int* order = (int*)(Vg + (int64_t)ls * ls);           // s_max + 1
+    uint32_t* roa = (uint32_t*)(order + ls);              // ma
+    uint32_t* coa = roa + ma;                             // D
+    uint32_t* rob = coa + D;                              // D
+    uint32_t* cob = rob + D;                              // mb
+    double* W = Wg;                                       // small bidiagonal -> its SVD (LDS when it fits)
+    double* Vs = Vg;
+    int lw = ls;                                          // their leading dimension
+
+    for (int i = tid; i < ma; i += kCoreThreads) roa[i] = axis_offset(d.va.row, (uint32_t)i);
+    for (int i = tid; i < D; i += kCoreThreads) {
+        coa[i] = axis_offset(d.va.col, (uint32_t)i);
+        rob[i] = axis_offset(d.vb.row, (uint32_t)i);
+    }
+    for (int i = tid; i < mb; i += kCoreThreads) cob[i] = axis_offset(d.vb.col, (uint32_t)i);
+    // start vector
+    for (int i = tid; i < mb; i += kCoreThreads) V[i] = probe_entry(i, 0);
+    __syncthreads();
+    {
+        double nrm = 0.0;
+        for (int i = tid; i < mb; i += kCoreThreads) nrm += V[i] * V[i];
+        nrm = sqrt(block_sum(nrm, sh));
+        for (int i = tid; i < mb; i += kCoreThreads) V[i] /= nrm;
+        __syncthreads();
+    }
+
+    int s = 0, restarts = 0, sweeps_total = 0, extra_col = 0;
+    bool exhausted = false, converged = false;
+    double amax = 0.0;
+    int target = d.s_min;
+    int nsv = 0;
+    for (;;) {
+        for (; s < target && !exhausted; ++s) {
+            const int j = s;
+            const double* vj = V + (int64_t)j * mb;
+            double* uj = U + (int64_t)j * ma;
+            // t1 = B v_j
+            for (int dd = wave; dd < D; dd += kCoreWaves) {
+                double acc = 0.0;
+                for (int f = lane; f < mb; f += 64) acc += (double)B[rob[dd] + cob[f]] * vj[f];
+                acc = wave_sum(acc);
+                if (lane == 0) t1[dd] = acc * ib;
+            }
+            __syncthreads();
+            // u_j = A t1 - beta_{j-1} u_{j-1}
+            for (int i = tid; i < ma; i += kCoreThreads) {
+                double acc = 0.0;
+                const uint32_t r = roa[i];
+                for (int q = 0; q < D; ++q) acc += (double)A[r + coa[q]] * t1[q];
+                acc *= ia;
+                if (j > 0) acc -= beta[j - 1] * U[(int64_t)(j - 1) * ma + i];
+                uj[i] = acc;
+            }
+            __syncthreads();
+            reorthogonalise(uj, U, ma, j, coef);
+            double an = 0.0;
+            for (int i = tid; i < ma; i += kCoreThreads) an += uj[i] * uj[i];
+            an = sqrt(block_sum(an, sh));
+            amax = fmax(amax, an);
+            if (!(an > kLanczosBreak * amax)) {
+                // M v_j lies in span(U): the range is exhausted.  v_j stays in the
+                // factorisation M V_{j+1} = U_j B with B of size j x (j+1).
+                exhausted = true;
+                extra_col = 1;
+                break;
+            }
+            alpha[j] = an;
+            for (int i = tid; i < ma; i += kCoreThreads) uj[i] /= an;
+            __syncthreads();
+            // t2 = A^T u_j
+            for (int dd = wave; dd < D; dd += kCoreWaves) {
+                double acc = 0.0;
+                const uint32_t c = coa[dd];
+                for (int i = lane; i < ma; i += 64) acc += (double)A[roa[i] + c] * uj[i];
+                acc = wave_sum(acc);
+                if (lane == 0) t2[dd] = acc * ia;
+            }
+            __syncthreads();
+            // v_{j+1} = B^T t2 - alpha_j v_j
+            double* w = V + (int64_t)(j + 1) * mb;
+            for (int f = tid; f < mb; f += kCoreThreads) {
+                double acc = 0.0;
+                const uint32_t c = cob[f];
+                for (int q = 0; q < D; ++q) acc += (double)B[rob[q] + c] * t2[q];
+                w[f] = acc * ib - an * vj[f];
+            }
+            __syncthreads();
+            reorthogonalise(w, V, mb, j + 1, coef);
+            double bn = 0.0;
+            for (int i = tid; i < mb; i += kCoreThreads) bn += w[i] * w[i];
+            bn = sqrt(block_sum(bn, sh));
+            amax = fmax(amax, bn);
+            if (bn > kLanczosBreak * amax) {
+                beta[j] = bn;
+                for (int i = tid; i < mb; i += kCoreThreads) w[i] /= bn;
+                __syncthreads();
+            } else {
+                // invariant Krylov space: restart with a fresh direction orthogonal to V
+                beta[j] = 0.0;
+                ++restarts;
+                for (int i = tid; i < mb; i += kCoreThreads) w[i] = probe_entry(i, restarts);
+                __syncthreads();
+                reorthogonalise(w, V, mb, j + 1, coef);
+                double rn = 0.0;
+                for (int i = tid; i < mb; i += kCoreThreads) rn += w[i] * w[i];
+                rn = sqrt(block_sum(rn, sh));
+                if (!(rn > 1e-8)) {
+                    exhausted = true;
+                    s = j + 1;
+                    break;
+                }
+                for (int i = tid; i < mb; i += kCoreThreads) w[i] /= rn;
+                __syncthreads();
+            }
+        }
+        // SVD of the s x nc upper bidiagonal (diag alpha, superdiag beta); nc = s + 1 after a
+        // breakdown of alpha, whose last column holds beta_{s-1} only
+        const int ncol = s + extra_col;
+        if ((size_t)2 * ncol * ncol * sizeof(double) <= (size_t)kLanczosLdsBytes) {
+            W = lds;
+            Vs = lds + (int64_t)ncol * ncol;
+            lw = ncol;
+        } else {
+            W = Wg;
+            Vs = Vg;
+            lw = ls;
+        }
+        for (int64_t idx = tid; idx < (int64_t)ncol * ncol; idx += kCoreThreads) {
+            const int c = (int)(idx / ncol), r = (int)(idx - (int64_t)c * ncol);
+            if (r < s) W[(int64_t)c * lw + r] = (r == c) ? alpha[c] : ((r + 1 == c) ? beta[r] : 0.0);
+            Vs[(int64_t)c * lw + r] = (r == c) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        int sw = 0;
+        const bool jc = jacobi_svd(W, Vs, s, ncol, lw, max_sweeps, sh, &sw);
+        sweeps_total += sw;
+        sorted_norms(W, s, ncol, lw, sig, order);
+        nsv = ncol;
+        // residual of Ritz triplet t: beta_{s-1} |Ub[s-1, t]| (zero when the space is exhausted)
+        const double smax_v = s > 0 ? sig[order[0]] : 0.0;
+        const double bl = (exhausted || s == 0) ? 0.0 : beta[s - 1];
+        bool ok = jc;
+        for (int t = 0; t < min(cn, ncol); ++t) {
+            const int c = order[t];
+            const double sv = sig[c];
+            if (!(sv > kNoiseRel * smax_v)) continue;
+            const double res = bl * fabs(W[(int64_t)c * lw + (s - 1)]) / sv;
+            if (res > 1e-13 * smax_v) ok = false;
+        }
+        if (ok || exhausted || s >= smax_steps) {
+            converged = ok || exhausted;
+            break;
+        }
+        target = min(smax_steps, s + 16);
+        __syncthreads();
+    }
+
+    // Ritz vectors of M: Ut = U Ub, Vt = V Vb for the kept columns
+    const double smax_v = nsv > 0 ? sig[order[0]] : 0.0;
+    const int nrow = nsv - extra_col;
+    for (int64_t idx = tid; idx < (int64_t)(ma + mb) * cn; idx += kCoreThreads) {
+        const int t = (int)(idx / (ma + mb)), i = (int)(idx - (int64_t)t * (ma + mb));
+        double acc = 0.0;
+        if (t < nsv) {
+            const int c = order[t];
+            const double sv = sig[c];
+            if (sv > 0.0) {
+                if (i < ma) {
+                    for (int j = 0; j < nrow; ++j) acc += U[(int64_t)j * ma + i] * W[(int64_t)c * lw + j];
+                    acc /= sv;
+                } else {
+                    const int f = i - ma;
+                    for (int j = 0; j < nsv; ++j) acc += V[(int64_t)j * mb + f] * Vs[(int64_t)c * lw + j];
+                }
+            }
+        }
+        if (i < ma) Ut[(int64_t)t * ma + i] = acc;
+        else Vt[(int64_t)t * mb + (i - ma)] = acc;
+    }
+    __syncthreads();
+    // projectors P_L = (B/s_b) Vt S^-1/2 (D x cn), P_R = S^-1/2 Ut^T (A/s_a) (cn x D)
+    Tp* PL = (Tp*)d.p_left;
+    Tp* PR = (Tp*)d.p_right;
+    for (int64_t idx = wave; idx < (int64_t)D * cn; idx += kCoreWaves) {
+        const int dd = (int)(idx / cn), t = (int)(idx - (int64_t)dd * cn);
+        const double sv = t < nsv ? sig[order[t]] : 0.0;
+        double pl = 0.0, pr = 0.0;
+        if (sv > kNoiseRel * smax_v && sv >= d.cutoff * smax_v) {
+            const double* vt = Vt + (int64_t)t * mb;
+            const double* ut = Ut + (int64_t)t * ma;
+            for (int f = lane; f < mb; f += 64) pl += (double)B[rob[dd] + cob[f]] * vt[f];
+            for (int i = lane; i < ma; i += 64) pr += ut[i] * (double)A[roa[i] + coa[dd]];
+            pl = wave_sum(pl) * ib / sqrt(sv);
+            pr = wave_sum(pr) * ia / sqrt(sv);
+        }
+        if (lane == 0) {
+            PL[(int64_t)dd * cn + t] = (Tp)pl;
+            PR[(int64_t)t * D + dd] = (Tp)pr;
+        }
+    }
+    if (tid == 0) {
+        // diagnostics within the Krylov space (the full spectrum of M is never formed)
+        double tot = 0.0, disc = 0.0;
+        for (int t = 0; t < nsv; ++t) {
+            const double sv = sig[order[t]];
+            tot += sv * sv;
+            if (t >= cn) disc += sv * sv;
+        }
+        stat_disc[d.stat] = tot > 0.0 ? disc / tot : 0.0;
+        const double s_last = (cn - 1 < nsv) ? sig[order[cn - 1]] : 0.0;
+        const double s_next = (cn < nsv) ? sig[order[cn]] : 0.0;
+        stat_tie[d.stat] = (d.kmin > cn && nsv > cn && s_last - s_next <= 1e-12 * smax_v) ? 1 : 0;
+        stat_sweeps[d.stat] = converged ? nsv : -1 - nsv;
     }
 }
 
@@ -607,6 +915,8 @@ hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t to
 size_t core_lds_bytes(int max_d) { return (size_t)2 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
+    (void)hipFuncSetAttribute((const void*)lanczos_kernel<float, float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
+    (void)hipFuncSetAttribute((const void*)lanczos_kernel<double, double>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
     const int bytes = (int)core_lds_bytes(kCoreLdsMaxD);
     (void)hipFuncSetAttribute((const void*)core_kernel<true, float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<true, double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -624,6 +934,19 @@ hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, 
         if (proj_f32) core_kernel<false, float><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
         else core_kernel<false, double><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
     }
+    return hipGetLastError();
+}
+
+size_t lanczos_lds_bytes(int s_max) { return (size_t)2 * (s_max + 1) * (s_max + 1) * sizeof(double); }
+
+hipError_t launch_lanczos(int tin_f32, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
+                          int max_sweeps, double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s) {
+    (void)s_max;
+    if (ndesc == 0) return hipSuccess;
+    dim3 grid(ndesc), block(kCoreThreads);
+    const size_t bytes = kLanczosLdsBytes;
+    if (tin_f32) lanczos_kernel<float, float><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
+    else lanczos_kernel<double, double><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
     return hipGetLastError();
 }
 

@@ -4,12 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include "tn_internal.hpp"
+#include "../../include/tn.h"
 
 namespace tn {
 
 enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2 };
 
 constexpr int kCoreLdsMaxD = 64;
+constexpr int kLanczosMaxSteps = 512;     // cap on Krylov steps per compression
+constexpr int kLanczosLdsBytes = 150 * 1024;   // dynamic LDS for the small SVD (static use is ~4.3 KB)
 
 void init_kernel_attrs();
 hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
@@ -19,6 +22,9 @@ hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t to
 size_t core_lds_bytes(int max_d);
 hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
                        double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
+size_t lanczos_lds_bytes(int s_max);
+hipError_t launch_lanczos(int tin_f32, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
+                          int max_sweeps, double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
 hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* maxparts, double* scales,
                                  hipStream_t s);
 hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,

@@ -298,65 +298,100 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 c.mb = mb;
                 c.chi_new = (int32_t)nw;
                 const int32_t comp_id = (int32_t)P->comps.size();
-                int side_level[2];
-                for (int side = 0; side < 2; ++side) {
-                    const TensorVer& T = side == 0 ? Ta : Tb;
-                    const int32_t ver = side == 0 ? va : vb;
-                    const std::vector<int32_t>& fr = side == 0 ? free_a : free_b;
-                    const int64_t mm = side == 0 ? ma : mb;
-                    Step st;
-                    st.level = T.level + 1;
-                    st.comp = comp_id;
-                    st.in_a = ver;
-                    if (mm > D) {
-                        // Gram: side A -> A_mat^T A_mat ; side B -> B_mat B_mat^T  (both D x D)
-                        st.kind = ST_GRAM;
-                        st.M = D;
-                        st.N = D;
-                        st.K = mm;
-                        st.va = tensor_view(T, shared, fr, E);
-                        st.vb = tensor_view(T, fr, shared, E);
-                        int64_t splits = (mm + 2047) / 2048;
-                        splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
-                        int64_t kps = (mm + splits - 1) / splits;
-                        kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
-                        splits = (mm + kps - 1) / kps;
-                        st.splits = (int32_t)splits;
-                        st.k_per_split = (int32_t)kps;
-                        st.out_buf = new_buf(splits * D * D * 8, BUF_GRAM, st.level);
-                        // algorithmic cost of the R-factor: a QR of an (mm x D) matrix (SI section D)
-                        st.flops = 2.0 * (double)mm * D * D - 2.0 / 3.0 * (double)D * D * D;
-                        st.bytes = (double)w * mm * D;
-                        (side == 0 ? c.gram_a : c.gram_b) = 1;
-                        (side == 0 ? c.splits_a : c.splits_b) = (int32_t)splits;
-                    } else {
-                        // explicit factor: side A -> A_mat (ma x D); side B -> B_mat^T (mb x D)
-                        st.kind = ST_COPY;
-                        st.copy_rows = (int32_t)mm;
-                        st.copy_cols = (int32_t)D;
-                        st.va = tensor_view(T, fr, shared, E);
-                        st.out_buf = new_buf(mm * D * 8, BUF_FACTOR, st.level);
-                        st.bytes = (double)(w + 8) * mm * D;
-                        (side == 0 ? c.rows_a : c.rows_b) = (int32_t)mm;
-                    }
-                    (side == 0 ? c.side_a_buf : c.side_b_buf) = st.out_buf;
-                    read_tensor(ver, st.level);
-                    side_level[side] = st.level;
-                    P->steps.push_back(st);
-                }
+                const bool lanczos = D >= kLanczosMinD && (ma + mb) <= kLanczosMaxRowsPerD * D;
+                c.lanczos = lanczos ? 1 : 0;
                 Step core;
-                core.kind = ST_CORE;
-                core.level = 1 + std::max(side_level[0], side_level[1]);
-                core.comp = comp_id;
-                touch(c.side_a_buf, core.level);
-                touch(c.side_b_buf, core.level);
-                c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
+                if (lanczos) {
+                    // one step: Golub-Kahan-Lanczos truncated SVD of A_mat B_mat read through Views
+                    const int64_t r = std::min(std::min(ma, mb), D);
+                    c.s_min = (int32_t)std::min<int64_t>(r, 2 * nw + 16);
+                    // r + 1: the start vector's component outside the row space of A B adds one
+                    // Krylov direction before the range is exhausted
+                    c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(r + 1, 8 * nw + 64), 512);
+                    c.s_min = std::min(c.s_min, c.s_max);
+                    core.kind = ST_LANCZOS;
+                    core.level = 1 + std::max(Ta.level, Tb.level);
+                    core.comp = comp_id;
+                    core.in_a = va;
+                    core.in_b = vb;
+                    core.va = tensor_view(Ta, free_a, shared, E);
+                    core.vb = tensor_view(Tb, shared, free_b, E);
+                    const int64_t sm = c.s_max;
+                    const int64_t ls = sm + 1;   // small bidiagonal leading dimension (see the kernel)
+                    const int64_t words = ma * sm + mb * (sm + 1) + (ma + mb) * nw + 2 * D + 2 * sm + ls + 2 * ls * ls +
+                                          (ls + ma + mb + 2 * D + 1) / 2 + 8;
+                    c.work_buf = new_buf(words * 8, BUF_WORK, core.level);
+                    read_tensor(va, core.level);
+                    read_tensor(vb, core.level);
+                } else {
+                    int side_level[2];
+                    for (int side = 0; side < 2; ++side) {
+                        const TensorVer& T = side == 0 ? Ta : Tb;
+                        const int32_t ver = side == 0 ? va : vb;
+                        const std::vector<int32_t>& fr = side == 0 ? free_a : free_b;
+                        const int64_t mm = side == 0 ? ma : mb;
+                        Step st;
+                        st.level = T.level + 1;
+                        st.comp = comp_id;
+                        st.in_a = ver;
+                        if (mm > D) {
+                            // Gram: side A -> A_mat^T A_mat ; side B -> B_mat B_mat^T  (both D x D)
+                            st.kind = ST_GRAM;
+                            st.M = D;
+                            st.N = D;
+                            st.K = mm;
+                            st.va = tensor_view(T, shared, fr, E);
+                            st.vb = tensor_view(T, fr, shared, E);
+                            int64_t splits = (mm + 2047) / 2048;
+                            splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
+                            int64_t kps = (mm + splits - 1) / splits;
+                            kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
+                            splits = (mm + kps - 1) / kps;
+                            st.splits = (int32_t)splits;
+                            st.k_per_split = (int32_t)kps;
+                            st.out_buf = new_buf(splits * D * D * 8, BUF_GRAM, st.level);
+                            // algorithmic cost of this R-factor: a QR of an (mm x D) matrix (SI section D)
+                            st.flops = 2.0 * (double)mm * D * D - 2.0 / 3.0 * (double)D * D * D;
+                            st.bytes = (double)w * mm * D;
+                            (side == 0 ? c.gram_a : c.gram_b) = 1;
+                            (side == 0 ? c.splits_a : c.splits_b) = (int32_t)splits;
+                        } else {
+                            // explicit factor: side A -> A_mat (ma x D); side B -> B_mat^T (mb x D)
+                            st.kind = ST_COPY;
+                            st.copy_rows = (int32_t)mm;
+                            st.copy_cols = (int32_t)D;
+                            st.va = tensor_view(T, fr, shared, E);
+                            st.out_buf = new_buf(mm * D * 8, BUF_FACTOR, st.level);
+                            st.bytes = (double)(w + 8) * mm * D;
+                            (side == 0 ? c.rows_a : c.rows_b) = (int32_t)mm;
+                        }
+                        (side == 0 ? c.side_a_buf : c.side_b_buf) = st.out_buf;
+                        read_tensor(ver, st.level);
+                        side_level[side] = st.level;
+                        P->steps.push_back(st);
+                    }
+                    core.kind = ST_CORE;
+                    core.level = 1 + std::max(side_level[0], side_level[1]);
+                    core.comp = comp_id;
+                    touch(c.side_a_buf, core.level);
+                    touch(c.side_b_buf, core.level);
+                    c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
+                }
                 c.pl_buf = new_buf(D * nw * w, BUF_PROJ, core.level);
                 c.pr_buf = new_buf(nw * D * w, BUF_PROJ, core.level);
                 {
+                    // algorithmic cost of the compression (SI section D): QR of each tall side,
+                    // the R_A R_B core and its SVD; the same whichever kernel computes it
+                    double f = 0.0, b = 0.0;
+                    for (int64_t mm : {ma, mb})
+                        if (lanczos && mm > D) {   // Gram steps carry these terms otherwise
+                            f += 2.0 * (double)mm * D * D - 2.0 / 3.0 * (double)D * D * D;
+                            b += (double)w * mm * D;
+                        }
                     const double p = (double)std::max(ka, kb), q = (double)std::min(ka, kb);
-                    core.flops = 2.0 * ka * D * kb + 4.0 * p * q * q - 4.0 / 3.0 * q * q * q;
-                    core.bytes = 0;
+                    f += 2.0 * ka * D * kb + 4.0 * p * q * q - 4.0 / 3.0 * q * q * q;
+                    core.flops = f;
+                    core.bytes = b;
                 }
                 c.core_step = (int32_t)P->steps.size();
                 P->steps.push_back(core);

@@ -55,7 +55,7 @@ struct TensorVer {
     int32_t last_read = 0;
 };
 
-enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB };
+enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS };
 
 struct ViewSpec {                   // a View before arena addresses are known
     std::vector<int32_t> row_dims, col_dims;            // slowest..fastest
@@ -90,7 +90,14 @@ struct Compression {
     int32_t rows_a, rows_b;             // explicit factor rows
     int32_t work_buf, pl_buf, pr_buf;
     int32_t core_step;
+    int32_t lanczos;                    // 1: Golub-Kahan-Lanczos on A B (large D), 0: Gram + core
+    int32_t s_min, s_max;               // Krylov steps (lanczos)
 };
+
+// Compressions with D above this use Golub-Kahan-Lanczos on A B instead of Gram matrices,
+// unless the matricised tensors are much taller than D.
+constexpr int64_t kLanczosMinD = 65;
+constexpr int64_t kLanczosMaxRowsPerD = 256;
 
 struct Plan {
     GraphSpec g;

@@ -1,0 +1,62 @@
+"""Write oracle reference values for the GPU parity tests (calls only oracle/ and tninputs/).
+
+    python tests/golden/make_golden.py [--big]
+
+ising_8x8.json   : 8x8 open-boundary Ising, beta=0.44 — transfer-matrix ln Z and the oracle's
+                   ln|Z| for chi in {4, 8, 16, 256} along the sweep tree (section II.F, SI F.1).
+cubic_12.json    : 12x12x12 Ising, beta=0.22, chi=16, sweep tree (--big, ~10 min of CPU):
+                   the oracle's ln|Z| and its spread when one input tensor is perturbed at the
+                   1e-15 level (the conditioning of this workload; see the design notes).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+from oracle import exact  # noqa: E402
+from tninputs import ising_tensors, lattice  # noqa: E402
+from tninputs.trees import sweep_tree  # noqa: E402
+
+
+def ising_8x8():
+    g = lattice((8, 8))
+    T = ising_tensors(g, 0.44)
+    p = sweep_tree((8, 8))
+    out = {"shape": [8, 8], "beta": 0.44, "tree": "sweep_tree((8, 8))",
+           "transfer_matrix_lnZ": exact.ising_transfer_matrix((8, 8), 0.44), "oracle_lnZ": {}}
+    for chi in (4, 8, 16, 256):
+        out["oracle_lnZ"][str(chi)] = oracle.contract_compressed(g.n, g.edges, T, p, chi).ln_abs_z
+    return out
+
+
+def cubic_12(n_perturb=3):
+    g = lattice((12, 12, 12))
+    T = ising_tensors(g, 0.22)
+    p = sweep_tree((12, 12, 12))
+    t0 = time.time()
+    base = oracle.contract_compressed(g.n, g.edges, T, p, 16).ln_abs_z
+    spread = []
+    for seed in range(n_perturb):
+        rng = np.random.default_rng(seed)
+        T2 = [t.copy() for t in T]
+        v = int(rng.integers(0, g.n))
+        T2[v] = T2[v] * (1.0 + 1e-15 * rng.normal(size=T2[v].shape))
+        spread.append(oracle.contract_compressed(g.n, g.edges, T2, p, 16).ln_abs_z - base)
+    return {"shape": [12, 12, 12], "beta": 0.22, "chi": 16, "tree": "sweep_tree((12, 12, 12))",
+            "oracle_lnZ": base, "perturbed_minus_base": spread,
+            "perturbation": "one input tensor scaled entrywise by 1 + 1e-15 * Normal(0, 1)",
+            "cpu_seconds": time.time() - t0}
+
+
+if __name__ == "__main__":
+    with open(os.path.join(HERE, "ising_8x8.json"), "w") as f:
+        json.dump(ising_8x8(), f, indent=1)
+    if "--big" in sys.argv:
+        with open(os.path.join(HERE, "cubic_12.json"), "w") as f:
+            json.dump(cubic_12(), f, indent=1)

@@ -46,7 +46,10 @@ def _check(g, T, pairs, chi, precision="fp64", rtol=FP64_RTOL):
         assert len(disc) == len(comp)
         assert np.all(sweeps >= 0)
         if precision == "fp64" and not ties:
-            np.testing.assert_allclose(disc, [o.discarded for o in comp], rtol=1e-6, atol=1e-12)
+            # the discarded-weight diagnostic is exact on the Gram path; bonds with D > 64 that
+            # run Golub-Kahan-Lanczos report it within the Krylov space only
+            gram = [i for i, o in enumerate(comp) if o.n <= 64 or o.m + o.k > 256 * o.n]
+            np.testing.assert_allclose(disc[gram], [comp[i].discarded for i in gram], rtol=1e-6, atol=1e-12)
     return want, stats
 
 
@@ -169,3 +172,18 @@ def test_fp32_dimer():
     want = oracle.contract_compressed(g.n, g.edges, T, pairs, 8)
     sign, lnz, *_ = gpu_eval(g, T, pairs, 8, "fp32")
     assert sign == want.sign and abs(lnz - want.ln_abs_z) <= _fp32_bound(want)
+
+
+# ---------------------------------------------------------------------------- large bonds (Lanczos path)
+@pytest.mark.parametrize("shape,chi", [((6, 6, 6), 16), ((4, 4, 6), 16), ((6, 6, 6), 8)])
+def test_ising_cubic_large_bonds(shape, chi):
+    """The last sweep stage merges two chi-bonds (D = chi^2 > 64): these compressions run
+    Golub-Kahan-Lanczos on A B instead of Gram matrices."""
+    g = lattice(shape)
+    _check(g, ising_tensors(g, 0.22), sweep_tree(shape), chi)
+
+
+def test_large_bonds_random_signs():
+    g = lattice((4, 4, 4))
+    T = normal_tensors(g, 0.1, 3)
+    _check(g, T, sweep_tree((4, 4, 4)), 16)
