@@ -17,7 +17,7 @@ using namespace tn;
 
 namespace {
 
-enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS };
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS };
 
 struct Launch {
     int kind = 0;
@@ -58,6 +58,8 @@ struct tn_ctx {
     std::vector<InputDesc> h_inputs;
     std::vector<LanczosDesc> h_lanczos;
     LanczosDesc* d_lanczos = nullptr;
+    std::vector<GLanczosDesc> h_glanczos;
+    GLanczosDesc* d_glanczos = nullptr;
     std::vector<Launch> launches;
     GemmDesc* d_gemm = nullptr;
     CopyDesc* d_copy = nullptr;
@@ -114,6 +116,7 @@ void free_plan(tn_ctx* c) {
     dfree(c->d_scale);
     dfree(c->d_inputs);
     dfree(c->d_lanczos);
+    dfree(c->d_glanczos);
     dfree(c->d_scales);
     dfree(c->d_maxparts);
     dfree(c->d_disc);
@@ -125,6 +128,7 @@ void free_plan(tn_ctx* c) {
     c->h_scale.clear();
     c->h_inputs.clear();
     c->h_lanczos.clear();
+    c->h_glanczos.clear();
     c->launches.clear();
     c->has_plan = false;
     c->evaluated = false;
@@ -159,6 +163,8 @@ tn_status build_launches(tn_ctx* c) {
         std::vector<CopyDesc> copies;
         std::vector<CoreDesc> cores_lds, cores_glb;
         std::vector<LanczosDesc> lanczos;
+        std::vector<GLanczosDesc> glanczos;
+        std::pair<double, double> glanczos_work{0, 0};
         std::pair<double, double> lanczos_work{0, 0};
         int lanczos_smax = 1;
         std::vector<ScaleDesc> scales;
@@ -259,6 +265,34 @@ tn_status build_launches(tn_ctx* c) {
                 lanczos.push_back(ld);
                 lanczos_work.first += st.flops;
                 lanczos_work.second += st.bytes;
+            } else if (st.kind == ST_CORE && P.comps[st.comp].glanczos) {
+                const Compression& cp = P.comps[st.comp];
+                GLanczosDesc gd;
+                std::memset(&gd, 0, sizeof(gd));
+                const int xb = cp.x_is_b;
+                const int32_t xbuf = xb ? cp.side_b_buf : cp.side_a_buf;
+                const int32_t ybuf = xb ? cp.side_a_buf : cp.side_b_buf;
+                const int ygram = xb ? cp.gram_a : cp.gram_b;
+                gd.fx = (const double*)buf_ptr(xbuf);
+                gd.gram_y = ygram ? (const double*)buf_ptr(ybuf) : nullptr;
+                gd.fy = ygram ? nullptr : (const double*)buf_ptr(ybuf);
+                gd.splits_y = xb ? cp.splits_a : cp.splits_b;
+                gd.work = (double*)buf_ptr(cp.work_buf);
+                gd.p_left = buf_ptr(cp.pl_buf);
+                gd.p_right = buf_ptr(cp.pr_buf);
+                gd.cutoff = P.opts.cutoff;
+                gd.n = (int32_t)(xb ? cp.mb : cp.ma);
+                gd.my = (int32_t)(xb ? cp.ma : cp.mb);
+                gd.D = (int32_t)cp.D;
+                gd.chi_new = cp.chi_new;
+                gd.x_is_b = xb;
+                gd.s_min = cp.s_min;
+                gd.s_max = cp.s_max;
+                gd.stat = st.comp;
+                gd.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
+                glanczos.push_back(gd);
+                glanczos_work.first += st.flops;
+                glanczos_work.second += st.bytes;
             } else if (st.kind == ST_CORE) {
                 const Compression& cp = P.comps[st.comp];
                 CoreDesc cd;
@@ -352,6 +386,18 @@ tn_status build_launches(tn_ctx* c) {
             for (auto& ld : lanczos) c->h_lanczos.push_back(ld);
             c->launches.push_back(l);
         }
+        if (!glanczos.empty()) {
+            Launch l;
+            l.kind = L_GLANCZOS;
+            l.key = f32 ? 1 : 0;
+            l.prof = TN_KERNEL_LANCZOS;
+            l.begin = (int64_t)c->h_glanczos.size();
+            l.count = (int)glanczos.size();
+            l.flops = glanczos_work.first;
+            l.bytes = glanczos_work.second;
+            for (auto& gd : glanczos) c->h_glanczos.push_back(gd);
+            c->launches.push_back(l);
+        }
         if (!scales.empty()) {
             Launch l;
             l.kind = L_SCALE;
@@ -378,6 +424,7 @@ tn_status build_launches(tn_ctx* c) {
     if ((s = upload(c, &c->d_scale, c->h_scale)) != TN_OK) return s;
     if ((s = upload(c, &c->d_inputs, c->h_inputs)) != TN_OK) return s;
     if ((s = upload(c, &c->d_lanczos, c->h_lanczos)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_glanczos, c->h_glanczos)) != TN_OK) return s;
     HIP_TRY(c, hipMalloc((void**)&c->d_scales, std::max<size_t>(1, P.tens.size()) * sizeof(double)));
     HIP_TRY(c, hipMalloc((void**)&c->d_maxparts, (size_t)max_parts * sizeof(double)));
     const size_t nc = std::max<size_t>(1, P.comps.size());
@@ -574,6 +621,10 @@ tn_status tn_enqueue(tn_ctx* c) {
             case L_LANCZOS:
                 HIP_TRY(c, launch_lanczos(l.key, c->d_lanczos + l.begin, l.count, l.max_d, c->d_scales,
                                           P.opts.jacobi_max_sweeps, c->d_disc, c->d_tie, c->d_sweeps, s));
+                break;
+            case L_GLANCZOS:
+                HIP_TRY(c, launch_gram_lanczos(l.key, c->d_glanczos + l.begin, l.count, P.opts.jacobi_max_sweeps,
+                                               c->d_disc, c->d_tie, c->d_sweeps, s));
                 break;
             case L_SCALE:
                 HIP_TRY(c, launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, s));

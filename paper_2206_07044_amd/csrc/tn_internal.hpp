@@ -143,6 +143,21 @@ struct LanczosDesc {
     View vb;                     // B_mat: rows = shared legs, cols = free legs of b
 };
 
+// Large-core compression with an explicit side X: symmetric Lanczos on F_X G_Y F_X^T.
+struct GLanczosDesc {
+    const double* fx;            // explicit factor of side X (n x D, row-major)
+    const double* gram_y;        // split-K Gram partials of side Y (D x D each), or null
+    const double* fy;            // explicit factor of side Y (my x D) when it has no Gram
+    double* work;
+    void* p_left;                // D x chi'
+    void* p_right;               // chi' x D
+    double cutoff;
+    int32_t n, my, D, chi_new;
+    int32_t splits_y, x_is_b;    // x_is_b: X is the B side (operator M^T M), else A (M M^T)
+    int32_t s_min, s_max;
+    int32_t stat, kmin;
+};
+
 // Upload of one input tensor: float64 staging -> arena (converted to the tensor dtype).
 struct InputDesc {
     void* dst;

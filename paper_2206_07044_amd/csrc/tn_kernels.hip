@@ -53,16 +53,36 @@ __device__ inline double inv_scale(const double* scales, int idx) {
     return s > 0.0 ? 1.0 / s : 0.0;
 }
 
+// Wave reductions with DPP: xor-1 and xor-2 quad permutes, then half-row and row mirrors
+// leave every lane holding its 16-lane row's total; the four row totals are read with
+// readlane and combined in a fixed order, so every lane gets the same, deterministic value.
+template <int kCtrl>
+__device__ inline double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double read_lane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
+    v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1)
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 __device__ inline double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_mov<0xB1>(v));
+    v = fmax(v, dpp_mov<0x4E>(v));
+    v = fmax(v, dpp_mov<0x141>(v));
+    v = fmax(v, dpp_mov<0x140>(v));
+    return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -121,14 +141,25 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
         b_off[i] = b_ok[i] ? axis_offset(d.vb.col, (uint32_t)gn) : 0u;
     }
 
+    // K offsets of the current and next chunk, decomposed once per chunk (not per element)
+    __shared__ uint32_t koff_a[2][kBK], koff_b[2][kBK];
+    auto fill_koff = [&](int buf, int kc) {
+        if (tid < kBK) {
+            const int gk = kc + tid;
+            koff_a[buf][tid] = gk < k_end ? axis_offset(d.va.col, (uint32_t)gk) : 0u;
+        } else if (tid < 2 * kBK) {
+            const int gk = kc + tid - kBK;
+            koff_b[buf][tid - kBK] = gk < k_end ? axis_offset(d.vb.row, (uint32_t)gk) : 0u;
+        }
+    };
     Tc ra[4], rb[4];
-    auto load_chunk = [&](int kc) {
+    auto load_chunk = [&](int buf, int kc) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int gka = kc + a_k[i];
-            ra[i] = (a_ok[i] && gka < k_end) ? (Tc)A[a_off[i] + axis_offset(d.va.col, (uint32_t)gka)] : (Tc)0;
+            ra[i] = (a_ok[i] && gka < k_end) ? (Tc)A[a_off[i] + koff_a[buf][a_k[i]]] : (Tc)0;
             const int gkb = kc + b_k[i];
-            rb[i] = (b_ok[i] && gkb < k_end) ? (Tc)B[b_off[i] + axis_offset(d.vb.row, (uint32_t)gkb)] : (Tc)0;
+            rb[i] = (b_ok[i] && gkb < k_end) ? (Tc)B[b_off[i] + koff_b[buf][b_k[i]]] : (Tc)0;
         }
     };
 
@@ -143,15 +174,19 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
     const int lrow = lane & 15, lk = lane >> 4;
 
-    if (k_begin < k_end) load_chunk(k_begin);
+    fill_koff(0, k_begin);
+    __syncthreads();
+    if (k_begin < k_end) load_chunk(0, k_begin);
+    int buf = 0;
     for (int kc = k_begin; kc < k_end; kc += kBK) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             As[a_k[i]][a_m[i]] = ra[i];
             Bs[b_k[i]][b_n[i]] = rb[i];
         }
+        if (kc + kBK < k_end) fill_koff(buf ^ 1, kc + kBK);
         __syncthreads();
-        if (kc + kBK < k_end) load_chunk(kc + kBK);
+        if (kc + kBK < k_end) load_chunk(buf ^ 1, kc + kBK);
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             const Tc a0 = As[kk + lk][wm + lrow], a1 = As[kk + lk][wm + 16 + lrow];
@@ -162,6 +197,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
             acc[1][1] = Mma<Tc>::run(a1, b1, acc[1][1]);
         }
         __syncthreads();
+        buf ^= 1;
     }
 
     const double fa = inv_scale(scales, d.scale_a);
@@ -225,76 +261,63 @@ constexpr int kCoreThreads = 1024;
 constexpr double kNoiseRel = 1e-13;   // singular values below this * sigma_1 are zeros
 constexpr double kZeroRel = 1e-14;    // Jacobi leaves columns below this * ||W||_F alone
 constexpr double kLanczosBreak = 1e-13;   // Krylov breakdown relative to the largest alpha/beta
+constexpr double kNoiseRelSq = 1e-13;     // eigenvalues sigma^2 of M^T M below this * sigma_1^2 are zeros
 constexpr int kCoreWaves = kCoreThreads / 64;
 
 struct CoreShared {
     double rv[kCoreWaves];
     int ri[kCoreWaves];
     int flag;
+    double row[kCoreLdsMaxD];
 };
-
-// block-wide argmax over values v[i] for i in [0, n) with mask[i] == 0; ties -> smallest index
-__device__ inline void block_argmax(const double* G, int D, const int* chosen, CoreShared& sh, double* out_v,
-                                    int* out_i) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double bv = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = tid; i < D; i += kCoreThreads) {
-        if (chosen[i]) continue;
-        const double v = G[(int64_t)i * D + i];
-        if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { sh.rv[wave] = bv; sh.ri[wave] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-        double v = sh.rv[0];
-        int ix = sh.ri[0];
-        for (int w = 1; w < kCoreWaves; ++w)
-            if (sh.rv[w] > v || (sh.rv[w] == v && sh.ri[w] < ix)) { v = sh.rv[w]; ix = sh.ri[w]; }
-        sh.rv[0] = v;
-        sh.ri[0] = ix;
-    }
-    __syncthreads();
-    *out_v = sh.rv[0];
-    *out_i = sh.ri[0];
-    __syncthreads();
-}
 
 // R (rows x D, row-major, original column order) with R^T R = G: pivoted Cholesky
 // of the symmetric positive semidefinite D x D matrix G (destroyed).  Returns the rank.
+// Wave 0 picks each pivot (largest remaining diagonal, lowest index on ties); two barriers
+// per step.
 __device__ int pivoted_cholesky(double* G, int D, double* R, int* chosen, CoreShared& sh) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < D; i += kCoreThreads) chosen[i] = 0;
     __syncthreads();
-    double g0;
-    int p0;
-    block_argmax(G, D, chosen, sh, &g0, &p0);
-    const double tol = 1e-15 * g0;
+    double tol = 0.0;
     int r = 0;
     for (int t = 0; t < D; ++t) {
-        double piv;
-        int p;
-        if (t == 0) { piv = g0; p = p0; }
-        else block_argmax(G, D, chosen, sh, &piv, &p);
+        if (tid < 64) {
+            double bv = -1.0;
+            int bi = 0x7fffffff;
+            for (int i = lane; i < D; i += 64) {
+                if (chosen[i]) continue;
+                const double v = G[(int64_t)i * D + i];
+                if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) { sh.rv[0] = bv; sh.ri[0] = bi; }
+        }
+        __syncthreads();
+        const double piv = sh.rv[0];
+        const int p = sh.ri[0];
+        if (t == 0) tol = 1e-15 * piv;
         if (!(piv > tol) || !(piv > 0.0)) break;
         const double rp = sqrt(piv);
         double* Rt = R + (int64_t)t * D;
-        for (int j = tid; j < D; j += kCoreThreads)
-            Rt[j] = chosen[j] ? 0.0 : (j == p ? rp : G[(int64_t)p * D + j] / rp);
-        __syncthreads();
-        if (tid == 0) chosen[p] = 1;
+        double* rrow = D <= kCoreLdsMaxD ? sh.row : Rt;   // the row the update reads, in LDS when small
+        for (int j = tid; j < D; j += kCoreThreads) {
+            const double v = chosen[j] ? 0.0 : (j == p ? rp : G[(int64_t)p * D + j] / rp);
+            Rt[j] = v;
+            if (D <= kCoreLdsMaxD) sh.row[j] = v;
+        }
         __syncthreads();
         const int64_t DD = (int64_t)D * D;
         for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
             const int i = (int)(idx / D), j = (int)(idx - (int64_t)i * D);
-            if (!chosen[i] && !chosen[j]) G[idx] -= Rt[i] * Rt[j];
+            if (i != p && j != p && !chosen[i] && !chosen[j]) G[idx] -= rrow[i] * rrow[j];
         }
+        if (tid == 0) chosen[p] = 1;
         __syncthreads();
         r = t + 1;
     }
@@ -387,6 +410,104 @@ __device__ bool jacobi_svd(double* W, double* V, int rows, int cols, int ld, int
     return converged;
 }
 
+// Sum over the lane's 16-lane DPP row (every lane of the row gets the row total).
+__device__ inline double row16_sum(double v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    return v;
+}
+
+// jacobi_svd for rows, cols <= 64: each pair is rotated by one 16-lane row of a wave (up
+// to four rows of W per lane), so reductions stay inside DPP rows and a wave rotates four
+// pairs at once.  Same pair order, thresholds and result contract as jacobi_svd.
+__device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
+                                 int* sweeps_out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int quarter = lane >> 4, ql = lane & 15;
+    const int nc = cols + (cols & 1);
+    const double tol = 2.220446049250313e-16 * (double)max(rows, 16);
+    double f = 0.0;
+    for (int64_t idx = tid; idx < (int64_t)rows * cols; idx += kCoreThreads) {
+        const int j = (int)(idx / rows), i = (int)(idx - (int64_t)j * rows);
+        const double x = W[(int64_t)j * ld + i];
+        f += x * x;
+    }
+    f = wave_sum(f);
+    if (lane == 0) sh.rv[wave] = f;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+        sh.rv[0] = t;
+    }
+    __syncthreads();
+    const double zero2 = kZeroRel * kZeroRel * sh.rv[0];
+    __syncthreads();
+    int sweeps = 0;
+    bool converged = (cols <= 1);
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        if (tid == 0) sh.flag = 0;
+        __syncthreads();
+        for (int round = 0; round < nc - 1; ++round) {
+            for (int q = wave * 4 + quarter; q < nc / 2; q += kCoreWaves * 4) {
+                const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
+                if (p1 >= cols || p2 >= cols) continue;
+                double* w1 = W + (int64_t)p1 * ld;
+                double* w2 = W + (int64_t)p2 * ld;
+                double x[4], y[4];
+                double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int i = ql + 16 * k;
+                    x[k] = i < rows ? w1[i] : 0.0;
+                    y[k] = i < rows ? w2[i] : 0.0;
+                    a += x[k] * x[k];
+                    b += y[k] * y[k];
+                    g += x[k] * y[k];
+                }
+                a = row16_sum(a);
+                b = row16_sum(b);
+                g = row16_sum(g);
+                if (a > zero2 && b > zero2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+                    const double zeta = (b - a) / (2.0 * g);
+                    const double az = fabs(zeta);
+                    const double root = az > 1e100 ? az : sqrt(1.0 + zeta * zeta);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
+                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int i = ql + 16 * k;
+                        if (i < rows) {
+                            w1[i] = c * x[k] - s * y[k];
+                            w2[i] = s * x[k] + c * y[k];
+                        }
+                    }
+                    double* v1 = V + (int64_t)p1 * ld;
+                    double* v2 = V + (int64_t)p2 * ld;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int i = ql + 16 * k;
+                        if (i < cols) {
+                            const double xv = v1[i], yv = v2[i];
+                            v1[i] = c * xv - s * yv;
+                            v2[i] = s * xv + c * yv;
+                        }
+                    }
+                    if (ql == 0) sh.flag = 1;
+                }
+            }
+            __syncthreads();
+        }
+        sweeps = sweep + 1;
+        if (!sh.flag) converged = true;
+        __syncthreads();
+    }
+    *sweeps_out = sweeps;
+    return converged;
+}
+
 // Column norms of W (sig[j], j < cols) and their descending order (ties: lower column first).
 __device__ void sorted_norms(const double* W, int rows, int cols, int ld, double* sig, int* order) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -466,7 +587,8 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
 
     // ---- one-sided (Hestenes) Jacobi on the columns of W, accumulating V
     int sweeps = 0;
-    const bool converged = jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
+    const bool converged = (ra <= 64 && rb <= 64) ? jacobi_svd_small(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                                                  : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
 
     // ---- singular values and descending order (ties: lower column first)
     sorted_norms(W, ra, rb, D, sig, order);
@@ -554,6 +676,53 @@ __device__ void reorthogonalise(double* x, const double* Q, int n, int k, double
     }
 }
 
+
+// y[r] = scale * sum_c X[ro[r] + co[c]] x[c]  (r < nrow): lanes run along the unit-stride side.
+template <typename Tin>
+__device__ void mv_rows(const Tin* __restrict__ X, const uint32_t* ro, const uint32_t* co, int nrow, int ncol,
+                        bool col_unit, const double* x, double* y, double scale) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (col_unit) {   // a wave per row, lanes along the (contiguous) columns
+        for (int r = wave; r < nrow; r += kCoreWaves) {
+            const uint32_t base = ro[r];
+            double acc = 0.0;
+            for (int c = lane; c < ncol; c += 64) acc += (double)X[base + co[c]] * x[c];
+            acc = wave_sum(acc);
+            if (lane == 0) y[r] = acc * scale;
+        }
+    } else {          // a thread per row: neighbouring lanes read neighbouring rows
+        for (int r = tid; r < nrow; r += kCoreThreads) {
+            const uint32_t base = ro[r];
+            double acc = 0.0;
+            for (int c = 0; c < ncol; ++c) acc += (double)X[base + co[c]] * x[c];
+            y[r] = acc * scale;
+        }
+    }
+}
+
+// y[c] = scale * sum_r X[ro[r] + co[c]] x[r]  (c < ncol)
+template <typename Tin>
+__device__ void mv_cols(const Tin* __restrict__ X, const uint32_t* ro, const uint32_t* co, int nrow, int ncol,
+                        bool row_unit, const double* x, double* y, double scale) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (row_unit) {   // a wave per column, lanes along the (contiguous) rows
+        for (int c = wave; c < ncol; c += kCoreWaves) {
+            const uint32_t off = co[c];
+            double acc = 0.0;
+            for (int r = lane; r < nrow; r += 64) acc += (double)X[ro[r] + off] * x[r];
+            acc = wave_sum(acc);
+            if (lane == 0) y[c] = acc * scale;
+        }
+    } else {          // a thread per column: neighbouring lanes read neighbouring columns
+        for (int c = tid; c < ncol; c += kCoreThreads) {
+            const uint32_t off = co[c];
+            double acc = 0.0;
+            for (int r = 0; r < nrow; ++r) acc += (double)X[ro[r] + off] * x[r];
+            y[c] = acc * scale;
+        }
+    }
+}
+
 // deterministic, generic start / restart vector
 __device__ inline double probe_entry(int i, int r) {
     const double x = (double)i;
@@ -575,6 +744,8 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
     const Tin* __restrict__ A = (const Tin*)d.A;
     const Tin* __restrict__ B = (const Tin*)d.B;
     const double ia = inv_scale(scales, d.scale_a), ib = inv_scale(scales, d.scale_b);
+    const bool a_col_unit = d.va.col_unit != 0, a_row_unit = d.va.row_unit != 0;
+    const bool b_col_unit = d.vb.col_unit != 0, b_row_unit = d.vb.row_unit != 0;
 
     double* U = d.work;                                   // ma x s_max
     double* V = U + (int64_t)ma * smax_steps;             // mb x (s_max + 1)
@@ -623,24 +794,17 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
             const int j = s;
             const double* vj = V + (int64_t)j * mb;
             double* uj = U + (int64_t)j * ma;
-            // t1 = B v_j
-            for (int dd = wave; dd < D; dd += kCoreWaves) {
-                double acc = 0.0;
-                for (int f = lane; f < mb; f += 64) acc += (double)B[rob[dd] + cob[f]] * vj[f];
-                acc = wave_sum(acc);
-                if (lane == 0) t1[dd] = acc * ib;
-            }
+            // t1 = B v_j ; u_j = A t1 - beta_{j-1} u_{j-1}
+            mv_rows(B, rob, cob, D, mb, b_col_unit, vj, t1, ib);
             __syncthreads();
-            // u_j = A t1 - beta_{j-1} u_{j-1}
-            for (int i = tid; i < ma; i += kCoreThreads) {
-                double acc = 0.0;
-                const uint32_t r = roa[i];
-                for (int q = 0; q < D; ++q) acc += (double)A[r + coa[q]] * t1[q];
-                acc *= ia;
-                if (j > 0) acc -= beta[j - 1] * U[(int64_t)(j - 1) * ma + i];
-                uj[i] = acc;
-            }
+            mv_rows(A, roa, coa, ma, D, a_col_unit, t1, uj, ia);
             __syncthreads();
+            if (j > 0) {
+                const double bprev = beta[j - 1];
+                const double* uprev = U + (int64_t)(j - 1) * ma;
+                for (int i = tid; i < ma; i += kCoreThreads) uj[i] -= bprev * uprev[i];
+                __syncthreads();
+            }
             reorthogonalise(uj, U, ma, j, coef);
             double an = 0.0;
             for (int i = tid; i < ma; i += kCoreThreads) an += uj[i] * uj[i];
@@ -656,23 +820,13 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
             alpha[j] = an;
             for (int i = tid; i < ma; i += kCoreThreads) uj[i] /= an;
             __syncthreads();
-            // t2 = A^T u_j
-            for (int dd = wave; dd < D; dd += kCoreWaves) {
-                double acc = 0.0;
-                const uint32_t c = coa[dd];
-                for (int i = lane; i < ma; i += 64) acc += (double)A[roa[i] + c] * uj[i];
-                acc = wave_sum(acc);
-                if (lane == 0) t2[dd] = acc * ia;
-            }
+            // t2 = A^T u_j ; v_{j+1} = B^T t2 - alpha_j v_j
+            mv_cols(A, roa, coa, ma, D, a_row_unit, uj, t2, ia);
             __syncthreads();
-            // v_{j+1} = B^T t2 - alpha_j v_j
             double* w = V + (int64_t)(j + 1) * mb;
-            for (int f = tid; f < mb; f += kCoreThreads) {
-                double acc = 0.0;
-                const uint32_t c = cob[f];
-                for (int q = 0; q < D; ++q) acc += (double)B[rob[q] + c] * t2[q];
-                w[f] = acc * ib - an * vj[f];
-            }
+            mv_cols(B, rob, cob, D, mb, b_row_unit, t2, w, ib);
+            __syncthreads();
+            for (int f = tid; f < mb; f += kCoreThreads) w[f] -= an * vj[f];
             __syncthreads();
             reorthogonalise(w, V, mb, j + 1, coef);
             double bn = 0.0;
@@ -740,7 +894,7 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
             converged = ok || exhausted;
             break;
         }
-        target = min(smax_steps, s + 16);
+        target = min(smax_steps, s + 8);
         __syncthreads();
     }
 
@@ -767,25 +921,23 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
         else Vt[(int64_t)t * mb + (i - ma)] = acc;
     }
     __syncthreads();
-    // projectors P_L = (B/s_b) Vt S^-1/2 (D x cn), P_R = S^-1/2 Ut^T (A/s_a) (cn x D)
+    // projectors P_L = (B/s_b) Vt S^-1/2 (D x cn), P_R = S^-1/2 Ut^T (A/s_a) (cn x D), one column
+    // (row) at a time through the same matvecs; t1 / t2 hold the float64 results
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
-    for (int64_t idx = wave; idx < (int64_t)D * cn; idx += kCoreWaves) {
-        const int dd = (int)(idx / cn), t = (int)(idx - (int64_t)dd * cn);
+    for (int t = 0; t < cn; ++t) {
         const double sv = t < nsv ? sig[order[t]] : 0.0;
-        double pl = 0.0, pr = 0.0;
-        if (sv > kNoiseRel * smax_v && sv >= d.cutoff * smax_v) {
-            const double* vt = Vt + (int64_t)t * mb;
-            const double* ut = Ut + (int64_t)t * ma;
-            for (int f = lane; f < mb; f += 64) pl += (double)B[rob[dd] + cob[f]] * vt[f];
-            for (int i = lane; i < ma; i += 64) pr += ut[i] * (double)A[roa[i] + coa[dd]];
-            pl = wave_sum(pl) * ib / sqrt(sv);
-            pr = wave_sum(pr) * ia / sqrt(sv);
+        const bool keep = sv > kNoiseRel * smax_v && sv >= d.cutoff * smax_v;
+        if (keep) {
+            mv_rows(B, rob, cob, D, mb, b_col_unit, Vt + (int64_t)t * mb, t1, ib / sqrt(sv));
+            mv_cols(A, roa, coa, ma, D, a_row_unit, Ut + (int64_t)t * ma, t2, ia / sqrt(sv));
+            __syncthreads();
         }
-        if (lane == 0) {
-            PL[(int64_t)dd * cn + t] = (Tp)pl;
-            PR[(int64_t)t * D + dd] = (Tp)pr;
+        for (int dd = tid; dd < D; dd += kCoreThreads) {
+            PL[(int64_t)dd * cn + t] = (Tp)(keep ? t1[dd] : 0.0);
+            PR[(int64_t)t * D + dd] = (Tp)(keep ? t2[dd] : 0.0);
         }
+        __syncthreads();
     }
     if (tid == 0) {
         // diagnostics within the Krylov space (the full spectrum of M is never formed)
@@ -800,6 +952,283 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
         const double s_next = (cn < nsv) ? sig[order[cn]] : 0.0;
         stat_tie[d.stat] = (d.kmin > cn && nsv > cn && s_last - s_next <= 1e-12 * smax_v) ? 1 : 0;
         stat_sweeps[d.stat] = converged ? nsv : -1 - nsv;
+    }
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Large cores with at least one explicit side: symmetric Lanczos on S = F_X G_Y F_X^T, where
+// F_X (n x D) is the explicit factor of side X (n <= D rows) and G_Y the D x D Gram matrix of
+// side Y (or F_Y^T F_Y when Y is explicit too).  S = M^T M (X = B) or M M^T (X = A), so its
+// eigenpairs are (sigma^2, right / left singular vectors of M).  Projectors:
+//   side-X projector column t: F_X^T w_t / sqrt(sigma_t)
+//   side-Y projector column t: G_Y F_X^T w_t / sigma_t^(3/2)
+// (P_L = the B-side one as D x chi', P_R = the A-side one transposed).
+// ------------------------------------------------------------------------------------------
+// y[i] = scale * sum_d F[i*D + d] x[d]   (dense row-major F, n rows): a wave per group of
+// four rows, lanes along the contiguous columns, four independent loads in flight per lane.
+__device__ void dense_mv(const double* __restrict__ F, int n, int D, const double* __restrict__ x,
+                         double* __restrict__ y, double scale) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i0 = wave * 4; i0 < n; i0 += kCoreWaves * 4) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        const int nr = min(4, n - i0);
+        const double* f = F + (int64_t)i0 * D;
+        for (int d = lane; d < D; d += 64) {
+            const double xv = x[d];
+            a0 += f[d] * xv;
+            if (nr > 1) a1 += f[D + d] * xv;
+            if (nr > 2) a2 += f[2 * D + d] * xv;
+            if (nr > 3) a3 += f[3 * D + d] * xv;
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        a2 = wave_sum(a2);
+        a3 = wave_sum(a3);
+        if (lane == 0) {
+            y[i0] = a0 * scale;
+            if (nr > 1) y[i0 + 1] = a1 * scale;
+            if (nr > 2) y[i0 + 2] = a2 * scale;
+            if (nr > 3) y[i0 + 3] = a3 * scale;
+        }
+    }
+}
+// y[d] = scale * sum_i F[i*D + d] x[i]: waves split the rows, lanes run along the columns
+// (four per lane per block of 256), then the per-wave partials are summed in fixed order.
+// part: kCoreWaves * D doubles of scratch.  Ends with a barrier.
+__device__ void dense_mvt(const double* __restrict__ F, int n, int D, const double* __restrict__ x,
+                          double* __restrict__ y, double scale, double* __restrict__ part) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int d0 = 0; d0 < D; d0 += 256) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = wave; i < n; i += kCoreWaves) {
+            const double xv = x[i];
+            const double* f = F + (int64_t)i * D + d0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int dd = lane + 64 * q;
+                if (d0 + dd < D) a[q] += f[dd] * xv;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int dd = d0 + lane + 64 * q;
+            if (dd < D) part[(int64_t)wave * D + dd] = a[q];
+        }
+    }
+    __syncthreads();
+    for (int dd = tid; dd < D; dd += kCoreThreads) {
+        double acc = 0.0;
+        for (int w = 0; w < kCoreWaves; ++w) acc += part[(int64_t)w * D + dd];
+        y[dd] = acc * scale;
+    }
+    __syncthreads();
+}
+
+template <typename Tp>
+__global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLanczosDesc* __restrict__ descs,
+                                                                    int max_sweeps, double* __restrict__ stat_disc,
+                                                                    int32_t* __restrict__ stat_tie,
+                                                                    int32_t* __restrict__ stat_sweeps) {
+    extern __shared__ double lds[];
+    __shared__ CoreShared sh;
+    __shared__ double coef[kLanczosMaxSteps + 1];
+    const GLanczosDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int n = d.n, D = d.D, cn = d.chi_new, sm = d.s_max, ls = d.s_max + 1;
+    const int64_t DD = (int64_t)D * D;
+    double* G = d.work;                          // D x D Gram of side Y (when it is a Gram)
+    double* Q = G + DD;                          // n x s_max Lanczos basis
+    double* Wt = Q + (int64_t)n * sm;            // n x cn Ritz vectors
+    double* t1 = Wt + (int64_t)n * cn;           // D
+    double* t2 = t1 + D;                         // D
+    double* py = t2 + D;                         // max(n, m_y) scratch
+    double* alpha = py + max(n, d.my);           // s_max
+    double* beta = alpha + sm;                   // s_max
+    double* sig = beta + sm;                     // ls
+    double* Wg = sig + ls;                       // ls^2
+    double* Vg = Wg + (int64_t)ls * ls;          // ls^2
+    double* part = Vg + (int64_t)ls * ls;        // kCoreWaves x D partial sums
+    int* order = (int*)(part + (int64_t)kCoreWaves * D);   // ls
+    const double* FX = d.fx;
+    if (d.gram_y) {
+        for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
+            double acc = 0.0;
+            for (int p = 0; p < d.splits_y; ++p) acc += d.gram_y[(int64_t)p * DD + idx];
+            G[idx] = acc;
+        }
+        __syncthreads();
+    }
+    // apply G_Y to t (D) -> out (D)
+    auto apply_gy = [&](const double* t, double* out) {
+        if (d.gram_y) {
+            dense_mv(G, D, D, t, out, 1.0);
+        } else {
+            dense_mv(d.fy, d.my, D, t, py, 1.0);
+            __syncthreads();
+            dense_mvt(d.fy, d.my, D, py, out, 1.0, part);
+        }
+        __syncthreads();
+    };
+    // S x = F_X (G_Y (F_X^T x))
+    auto apply_s = [&](const double* x, double* y) {
+        dense_mvt(FX, n, D, x, t1, 1.0, part);
+        apply_gy(t1, t2);
+        dense_mv(FX, n, D, t2, y, 1.0);
+        __syncthreads();
+    };
+
+    for (int i = tid; i < n; i += kCoreThreads) Q[i] = probe_entry(i, 0);
+    __syncthreads();
+    {
+        double nrm = 0.0;
+        for (int i = tid; i < n; i += kCoreThreads) nrm += Q[i] * Q[i];
+        nrm = sqrt(block_sum(nrm, sh));
+        for (int i = tid; i < n; i += kCoreThreads) Q[i] /= nrm;
+        __syncthreads();
+    }
+    int s = 0, restarts = 0, nev = 0;
+    bool exhausted = false, converged = false;
+    double bmax = 0.0;
+    int target = d.s_min;
+    double* W = Wg;
+    double* Vs = Vg;
+    int lw = ls;
+    double* qnext = py;   // reuse as the next Lanczos vector candidate (length n)
+    for (;;) {
+        for (; s < target && !exhausted; ++s) {
+            const int j = s;
+            double* qj = Q + (int64_t)j * n;
+            apply_s(qj, qnext);
+            double a = 0.0;
+            for (int i = tid; i < n; i += kCoreThreads) a += qnext[i] * qj[i];
+            a = block_sum(a, sh);
+            alpha[j] = a;
+            for (int i = tid; i < n; i += kCoreThreads) {
+                double v = qnext[i] - a * qj[i];
+                if (j > 0) v -= beta[j - 1] * Q[(int64_t)(j - 1) * n + i];
+                qnext[i] = v;
+            }
+            __syncthreads();
+            reorthogonalise(qnext, Q, n, j + 1, coef);
+            double b = 0.0;
+            for (int i = tid; i < n; i += kCoreThreads) b += qnext[i] * qnext[i];
+            b = sqrt(block_sum(b, sh));
+            bmax = fmax(bmax, fmax(b, fabs(a)));
+            if (j + 1 >= n) {   // the basis spans the whole space
+                beta[j] = 0.0;
+                exhausted = true;
+                s = j + 1;
+                break;
+            }
+            double* qn = Q + (int64_t)(j + 1) * n;
+            if (b > kLanczosBreak * bmax) {
+                beta[j] = b;
+                for (int i = tid; i < n; i += kCoreThreads) qn[i] = qnext[i] / b;
+                __syncthreads();
+            } else {
+                beta[j] = 0.0;   // invariant subspace: restart orthogonally to the basis
+                ++restarts;
+                for (int i = tid; i < n; i += kCoreThreads) qn[i] = probe_entry(i, restarts);
+                __syncthreads();
+                reorthogonalise(qn, Q, n, j + 1, coef);
+                double rn = 0.0;
+                for (int i = tid; i < n; i += kCoreThreads) rn += qn[i] * qn[i];
+                rn = sqrt(block_sum(rn, sh));
+                if (!(rn > 1e-8)) {
+                    exhausted = true;
+                    s = j + 1;
+                    break;
+                }
+                for (int i = tid; i < n; i += kCoreThreads) qn[i] /= rn;
+                __syncthreads();
+            }
+        }
+        // eigenpairs of the s x s tridiagonal T (symmetric positive semidefinite: its
+        // one-sided Jacobi SVD gives eigenvalues as column norms and eigenvectors in Vs)
+        if ((size_t)2 * s * s * sizeof(double) <= (size_t)kLanczosLdsBytes) {
+            W = lds;
+            Vs = lds + (int64_t)s * s;
+            lw = s;
+        } else {
+            W = Wg;
+            Vs = Vg;
+            lw = ls;
+        }
+        for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
+            const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
+            double v = 0.0;
+            if (r == c) v = alpha[c];
+            else if (r + 1 == c) v = beta[r];
+            else if (c + 1 == r) v = beta[c];
+            W[(int64_t)c * lw + r] = v;
+            Vs[(int64_t)c * lw + r] = (r == c) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        int sw = 0;
+        const bool jc = jacobi_svd(W, Vs, s, s, lw, max_sweeps, sh, &sw);
+        sorted_norms(W, s, s, lw, sig, order);
+        nev = s;
+        const double lmax = s > 0 ? sig[order[0]] : 0.0;
+        const double bl = (exhausted || s == 0) ? 0.0 : beta[s - 1];
+        bool ok = jc;
+        for (int t = 0; t < min(cn, s); ++t) {
+            const int c = order[t];
+            const double lv = sig[c];
+            if (!(lv > kNoiseRelSq * lmax)) continue;
+            // residual of the Ritz pair: beta_s |last entry of its eigenvector|
+            if (bl * fabs(Vs[(int64_t)c * lw + (s - 1)]) > 1e-13 * lmax) ok = false;
+        }
+        if (ok || exhausted || s >= sm) {
+            converged = ok || exhausted;
+            break;
+        }
+        target = min(sm, s + 8);
+        __syncthreads();
+    }
+    // Ritz vectors w_t = Q Vs[:, order[t]]
+    for (int64_t idx = tid; idx < (int64_t)n * cn; idx += kCoreThreads) {
+        const int t = (int)(idx / n), i = (int)(idx - (int64_t)t * n);
+        double acc = 0.0;
+        if (t < nev) {
+            const int c = order[t];
+            for (int j = 0; j < nev; ++j) acc += Q[(int64_t)j * n + i] * Vs[(int64_t)c * lw + j];
+        }
+        Wt[(int64_t)t * n + i] = acc;
+    }
+    __syncthreads();
+    const double lmax = nev > 0 ? sig[order[0]] : 0.0;
+    Tp* PL = (Tp*)d.p_left;
+    Tp* PR = (Tp*)d.p_right;
+    for (int t = 0; t < cn; ++t) {
+        const double lv = t < nev ? sig[order[t]] : 0.0;   // eigenvalue = sigma^2
+        const double sv = sqrt(fmax(lv, 0.0));
+        const bool keep = lv > kNoiseRelSq * lmax && sv >= d.cutoff * sqrt(lmax);
+        if (keep) {
+            dense_mvt(FX, n, D, Wt + (int64_t)t * n, t1, 1.0, part);   // F_X^T w
+            apply_gy(t1, t2);                                          // G_Y F_X^T w
+        }
+        const double fx = keep ? 1.0 / sqrt(sv) : 0.0, fy = keep ? 1.0 / (sv * sqrt(sv)) : 0.0;
+        for (int dd = tid; dd < D; dd += kCoreThreads) {
+            const double px = keep ? t1[dd] * fx : 0.0, pyv = keep ? t2[dd] * fy : 0.0;
+            // X = B: P_L column = side-X vector, P_R row = side-Y vector; X = A: the reverse
+            PL[(int64_t)dd * cn + t] = (Tp)(d.x_is_b ? px : pyv);
+            PR[(int64_t)t * D + dd] = (Tp)(d.x_is_b ? pyv : px);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double tot = 0.0, disc = 0.0;
+        for (int t = 0; t < nev; ++t) {
+            const double lv = fmax(sig[order[t]], 0.0);
+            tot += lv;
+            if (t >= cn) disc += lv;
+        }
+        stat_disc[d.stat] = tot > 0.0 ? disc / tot : 0.0;
+        const double l_last = (cn - 1 < nev) ? sig[order[cn - 1]] : 0.0;
+        const double l_next = (cn < nev) ? sig[order[cn]] : 0.0;
+        stat_tie[d.stat] = (d.kmin > cn && nev > cn && sqrt(fmax(l_last, 0.0)) - sqrt(fmax(l_next, 0.0)) <= 1e-12 * sqrt(lmax)) ? 1 : 0;
+        stat_sweeps[d.stat] = converged ? nev : -1 - nev;
     }
 }
 
@@ -915,6 +1344,8 @@ hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t to
 size_t core_lds_bytes(int max_d) { return (size_t)2 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
+    (void)hipFuncSetAttribute((const void*)gram_lanczos_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
+    (void)hipFuncSetAttribute((const void*)gram_lanczos_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
     (void)hipFuncSetAttribute((const void*)lanczos_kernel<float, float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
     (void)hipFuncSetAttribute((const void*)lanczos_kernel<double, double>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
     const int bytes = (int)core_lds_bytes(kCoreLdsMaxD);
@@ -947,6 +1378,16 @@ hipError_t launch_lanczos(int tin_f32, const LanczosDesc* descs, int ndesc, int 
     const size_t bytes = kLanczosLdsBytes;
     if (tin_f32) lanczos_kernel<float, float><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
     else lanczos_kernel<double, double><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_lanczos(int proj_f32, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
+                               int32_t* tie, int32_t* sweeps, hipStream_t s) {
+    if (ndesc == 0) return hipSuccess;
+    dim3 grid(ndesc), block(kCoreThreads);
+    const size_t bytes = kLanczosLdsBytes;
+    if (proj_f32) gram_lanczos_kernel<float><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
+    else gram_lanczos_kernel<double><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
     return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@ hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, 
 size_t lanczos_lds_bytes(int s_max);
 hipError_t launch_lanczos(int tin_f32, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
                           int max_sweeps, double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
+hipError_t launch_gram_lanczos(int proj_f32, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
+                               int32_t* tie, int32_t* sweeps, hipStream_t s);
 hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* maxparts, double* scales,
                                  hipStream_t s);
 hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,

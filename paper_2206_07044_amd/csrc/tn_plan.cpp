@@ -298,13 +298,16 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 c.mb = mb;
                 c.chi_new = (int32_t)nw;
                 const int32_t comp_id = (int32_t)P->comps.size();
-                const bool lanczos = D >= kLanczosMinD && (ma + mb) <= kLanczosMaxRowsPerD * D;
+                const bool big = D >= kLanczosMinD;
+                const bool glanczos = big && (ma <= D || mb <= D);
+                const bool lanczos = big && !glanczos && (ma + mb) <= kLanczosMaxRowsPerD * D;
                 c.lanczos = lanczos ? 1 : 0;
+                c.glanczos = glanczos ? 1 : 0;
                 Step core;
                 if (lanczos) {
                     // one step: Golub-Kahan-Lanczos truncated SVD of A_mat B_mat read through Views
                     const int64_t r = std::min(std::min(ma, mb), D);
-                    c.s_min = (int32_t)std::min<int64_t>(r, 2 * nw + 16);
+                    c.s_min = (int32_t)std::min<int64_t>(r, 2 * nw + 4);
                     // r + 1: the start vector's component outside the row space of A B adds one
                     // Krylov direction before the range is exhausted
                     c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(r + 1, 8 * nw + 64), 512);
@@ -375,7 +378,19 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                     core.comp = comp_id;
                     touch(c.side_a_buf, core.level);
                     touch(c.side_b_buf, core.level);
-                    c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
+                    if (glanczos) {
+                        // X = the explicit side (the shorter one when both are explicit)
+                        c.x_is_b = (mb <= D && (ma > D || mb <= ma)) ? 1 : 0;
+                        const int64_t n = c.x_is_b ? mb : ma, my = c.x_is_b ? ma : mb;
+                        c.s_min = (int32_t)std::min<int64_t>(n, 2 * nw + 4);
+                        c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(n, 8 * nw + 64), 512);
+                        const int64_t sm = c.s_max, ls = sm + 1;
+                        const int64_t words = D * D + n * sm + n * nw + 2 * D + std::max(n, my) + 2 * sm + ls +
+                                              2 * ls * ls + 16 * D + ls / 2 + 8;   // 16 = waves of the kernel
+                        c.work_buf = new_buf(words * 8, BUF_WORK, core.level);
+                    } else {
+                        c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
+                    }
                 }
                 c.pl_buf = new_buf(D * nw * w, BUF_PROJ, core.level);
                 c.pr_buf = new_buf(nw * D * w, BUF_PROJ, core.level);

@@ -91,7 +91,9 @@ struct Compression {
     int32_t work_buf, pl_buf, pr_buf;
     int32_t core_step;
     int32_t lanczos;                    // 1: Golub-Kahan-Lanczos on A B (large D), 0: Gram + core
-    int32_t s_min, s_max;               // Krylov steps (lanczos)
+    int32_t glanczos;                   // 1: large D with an explicit side: Lanczos on F_X G_Y F_X^T
+    int32_t x_is_b;                     // glanczos: the explicit side X is B
+    int32_t s_min, s_max;               // Krylov steps (lanczos / glanczos)
 };
 
 // Compressions with D above this use Golub-Kahan-Lanczos on A B instead of Gram matrices,
