@@ -5,13 +5,14 @@ written from the paper (Gray & Chan, arXiv:2206.07044) and sharing no code
 with the library: ``approx`` is Algorithm 1 (section II.F) with QR-reduced
 bond compression (section II.C, Eq. (svd)) and the projector form (SI B);
 ``exact`` holds independent exact references (brute force, transfer
-matrices, matching counts) used to pin it; ``grad`` is a torch-CPU float64
-transcription used as the reference gradient.
+matrices, matching counts) used to pin it; ``grad`` is the reverse-mode
+adjoint of the same forward pass (textbook truncated-SVD adjoint over the
+complete core spectrum), the reference gradient.
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  The library never calls it and has no fallback to it.
 """
 from .approx import contract_compressed, OracleResult, OpRecord
-from . import exact
+from . import exact, grad
 
-__all__ = ["contract_compressed", "OracleResult", "OpRecord", "exact"]
+__all__ = ["contract_compressed", "OracleResult", "OpRecord", "exact", "grad"]
