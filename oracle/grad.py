@@ -20,8 +20,13 @@ readings, also listed in the design notes:
 * Pairs of kept singular values use 1/(s_i^2 - s_j^2) with Lorentzian
   broadening x / (x^2 + eps^2), eps = 1e-12 s_1^2 (their numerators cancel
   for a gauge-invariant continuation, so this only guards exact degeneracy).
-* Kept singular values that are masked in the forward pass (exact zero, or
-  below ``cutoff * s_1``) give constant zero columns and no gradient.
+* Singular values at or below 1e-13 s_1 are rounding-level zeros of the core:
+  they are treated as exactly zero (a kept one gives a constant zero column,
+  as does one below ``cutoff * s_1``).  The gradient is then that of the
+  rank-preserving truncation; contracted with a perturbation that keeps every
+  core's rank (Ising couplings, a rescaling) it is the exact derivative, while
+  a generic perturbation of a rank-deficient core would create new singular
+  values of order sqrt(|dK|) and ln|Z| need not be differentiable there.
 """
 from __future__ import annotations
 
@@ -34,6 +39,7 @@ import numpy as np
 from .approx import ZeroContraction, _Network
 
 _EPS_REL = 1e-12
+_NOISE_REL = 1e-13
 
 
 @dataclass
@@ -152,7 +158,7 @@ def _compress_fwd(net: _Network, a: int, b: int, chi: int, cutoff: float, log_sc
     U, sig, Vt = np.linalg.svd(r_a @ r_b, full_matrices=True)
     new = min(chi, ka, kb)
     keep = sig[:new]
-    mask = (keep > 0) & (keep >= cutoff * sig[0])
+    mask = (keep > _NOISE_REL * sig[0]) & (keep >= cutoff * sig[0])
     sq = np.where(mask, np.sqrt(np.where(mask, keep, 1.0)), 0.0)
     inv_sqrt = np.where(mask, 1.0 / np.where(mask, sq, 1.0), 0.0)
     p_l = (r_b @ Vt[:new].T) * inv_sqrt
@@ -193,7 +199,7 @@ def _compress_bwd(rec, adj: Dict[int, np.ndarray]) -> None:
     vh = q_b @ V                                     # mb x kb
     K_idx = [i for i in range(new) if mask[i]]
     s_all = np.zeros(max(ka, kb))
-    s_all[:len(sig)] = sig
+    s_all[:len(sig)] = np.where(sig > _NOISE_REL * sig[0], sig, 0.0)
     eps = _EPS_REL * sig[0] ** 2 if len(sig) else 0.0
 
     u_bar = g_a * sq                                 # dL/dU_K  (columns i < new; masked columns are 0)

@@ -66,12 +66,17 @@ def test_euler_identity(name, g, T, pairs, chi):
         assert float(np.sum(t * gr)) == pytest.approx(1.0, abs=1e-11)
 
 
-@pytest.mark.parametrize("shape,beta,seed", [((3, 3), 0.44, None), ((2, 2, 2), 0.3, 1), ((3, 4), 0.6, 2)])
-def test_exact_regime_matches_spin_correlations(shape, beta, seed):
+# chi = 4096: no compression at all; the others compress rank-deficient cores
+# (Ising copy-tensor structure) without truncating them, so ln Z is still exact
+@pytest.mark.parametrize("shape,beta,seed,chi", [((3, 3), 0.44, None, 4096), ((2, 2, 2), 0.3, 1, 4096),
+                                                 ((3, 4), 0.6, 2, 4096), ((3, 3), 0.44, None, 2),
+                                                 ((3, 4), 0.6, 3, 2), ((4, 4), 0.44, 4, 4), ((2, 2, 3), 0.3, 5, 8)])
+def test_exact_regime_matches_spin_correlations(shape, beta, seed, chi):
     g = lattice(shape)
     J = None if seed is None else np.where(np.random.default_rng(seed).random(g.n_edges) < 0.5, -1.0, 1.0)
     T = ising_tensors(g, beta, J)
-    res = lnz_and_grad(g.n, g.edges, T, sweep_tree(shape), 4096)   # no truncation
+    res = lnz_and_grad(g.n, g.edges, T, sweep_tree(shape), chi)
+    assert res.ln_abs_z == pytest.approx(exact.ising_brute_force(g.n, g.edges, beta, J), rel=1e-13)
     dJ = ising_coupling_grad(g.n, g.edges, beta, np.ones(g.n_edges) if J is None else J, res.grads)
     want = beta * exact.ising_correlations_brute(g.n, g.edges, beta, J)
     np.testing.assert_allclose(dJ, want, rtol=1e-10, atol=1e-12)
