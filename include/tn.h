@@ -60,7 +60,10 @@ typedef struct {
     int64_t device_budget_bytes; /* refuse plans whose device arena exceeds this; 0 = no limit */
     int32_t keep_intermediates;  /* 1: never reuse arena memory, so tn_read_tensor can read every
                                     intermediate after an evaluation (element-wise checks) */
-    int32_t reserved;
+    int32_t grad;                /* 1: also plan the reverse pass (tn_grad).  Every forward tensor,
+                                    core workspace and projector stays resident for it, and every
+                                    compression takes the Gram + full-spectrum Jacobi core (the
+                                    adjoint needs all singular triplets of the core) */
 } tn_tree_opts;
 
 typedef struct tn_ctx tn_ctx;
@@ -135,7 +138,9 @@ typedef enum {
     TN_KERNEL_CORE_LDS = 3,
     TN_KERNEL_CORE_GLOBAL = 4,
     TN_KERNEL_SCALE = 5,
-    TN_KERNEL_LANCZOS = 6
+    TN_KERNEL_LANCZOS = 6,
+    TN_KERNEL_BWD_GEMM = 7,      /* reverse pass: adjoint GEMMs and split-K reductions */
+    TN_KERNEL_BWD_CORE = 8       /* reverse pass: per-compression core adjoint */
 } tn_kernel_kind;
 
 /* Time every launch of the kinds in `kind_mask` (bit k = tn_kernel_kind k) with
@@ -156,9 +161,29 @@ tn_status tn_profile_read(const tn_ctx* ctx, int32_t kind, double* ms, int64_t* 
  * host `out`; *n receives the tensor's size. */
 tn_status tn_read_tensor(const tn_ctx* ctx, int32_t index, double* out, int64_t cap, int64_t* n);
 
-/* d ln|Z| / d data for the last evaluated tree (host float64, same layout
- * as tn_load_graph's data).  TN_ESTATE before an evaluation. */
+/* Reverse pass (no counterpart in the paper, which computes no gradients):
+ * d ln|Z| / d data for the last evaluated tree, where data are the input
+ * tensor entries of tn_load_graph / tn_update_values.  Written to host
+ * float64 `dlnz_ddata` in the same layout as data (n_input entries, caller
+ * owned).  Method: reverse mode over the same op order with the scale factors
+ * held constant (exact: the result is homogeneous of degree 1 in every
+ * tensor); each contraction's adjoint is two GEMMs; each compression's is the
+ * adjoint of the rank-chi' truncated SVD of A_mat B_mat (section II.C, Eq.
+ * (svd)), computed in the core's singular coordinates from all its singular
+ * triplets.  Core singular values at or below 1e-13 sigma_1 count as zero, so
+ * this is the derivative of the rank-preserving truncation: exact along
+ * perturbations that keep every core's rank (Ising couplings, rescalings).
+ * Needs tn_set_tree with opts.grad = 1 and a successful evaluation
+ * (TN_ESTATE otherwise); TN_ZERO if Z = 0 (no gradient of ln|Z|). */
 tn_status tn_grad(tn_ctx* ctx, double* dlnz_ddata);
+
+/* As tn_grad, writing float64 device memory `dlnz_ddata_dev` (n_input
+ * entries, caller owned) on the context's stream without synchronising. */
+tn_status tn_grad_device(tn_ctx* ctx, void* dlnz_ddata_dev);
+
+/* Backward-plan totals for opts.grad = 1: algorithmic flops and bytes of the
+ * reverse pass, its number of levels. */
+tn_status tn_grad_info(const tn_ctx* ctx, double* bwd_flops, double* bwd_bytes, int32_t* n_levels);
 
 /* Host-only expansion of Algorithm 1 on shapes (no device use): writes up
  * to `cap` ops as 8 int64 each: (kind, a, b, out, m, n, k, new_dim) with

@@ -18,7 +18,8 @@ TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO = range
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ESTATE", 3: "TN_ENOMEM", 4: "TN_EDEVICE",
                 5: "TN_ENUMERIC", 6: "TN_ZERO"}
 PRECISIONS = {"fp64": 0, "fp32": 1}
-KERNEL_KINDS = {"gemm": 0, "gram": 1, "copy": 2, "core_lds": 3, "core_global": 4, "scale": 5, "lanczos": 6}
+KERNEL_KINDS = {"gemm": 0, "gram": 1, "copy": 2, "core_lds": 3, "core_global": 4, "scale": 5, "lanczos": 6,
+                "bwd_gemm": 7, "bwd_core": 8}
 
 
 class TNError(RuntimeError):
@@ -31,7 +32,7 @@ class TNError(RuntimeError):
 class tn_tree_opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("cutoff", C.c_double), ("compress_late", C.c_int32),
                 ("gauge_r", C.c_int32), ("precision", C.c_int32), ("jacobi_max_sweeps", C.c_int32),
-                ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("reserved", C.c_int32)]
+                ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("grad", C.c_int32)]
 
 
 _lib = None
@@ -63,6 +64,8 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_fetch": ([P], C.c_int),
         "tn_compress_stats": ([P, I32, pD, pI32, pI32, pI32], C.c_int),
         "tn_grad": ([P, pD], C.c_int),
+        "tn_grad_device": ([P, P], C.c_int),
+        "tn_grad_info": ([P, pD, pD, pI32], C.c_int),
         "tn_read_tensor": ([P, I32, pD, I64, pI64], C.c_int),
         "tn_profile": ([P, C.c_uint32], C.c_int),
         "tn_profile_read": ([P, I32, pD, pI64, pD, pD], C.c_int),
@@ -81,7 +84,7 @@ def exported_symbols() -> List[str]:
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
             "tn_update_values_device", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
-            "tn_plan_describe"]
+            "tn_grad_device", "tn_grad_info", "tn_plan_describe"]
 
 
 def _i32(a) -> np.ndarray:
@@ -93,11 +96,11 @@ def _ptr(a: np.ndarray, ct):
 
 
 def make_opts(chi: int, precision: str = "fp64", cutoff: float = 0.0, max_sweeps: int = 0,
-              budget: int = 0, keep: bool = False) -> tn_tree_opts:
+              budget: int = 0, keep: bool = False, grad: bool = False) -> tn_tree_opts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     return tn_tree_opts(int(chi), float(cutoff), 0, 0, PRECISIONS[precision], int(max_sweeps), int(budget),
-                        int(bool(keep)), 0)
+                        int(bool(keep)), int(bool(grad)))
 
 
 def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int) -> List[Tuple[int, ...]]:
@@ -150,6 +153,7 @@ class Context:
         eu, ev, ed = map(_i32, (edge_u, edge_v, edge_dim))
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         self._data = np.ascontiguousarray(data, dtype=np.float64)
+        self._n_data = int(off[-1]) if off.size else 0
         self._check(self._lib.tn_load_graph(self._h, int(n), eu.size, _ptr(eu, C.c_int32), _ptr(ev, C.c_int32),
                                             _ptr(ed, C.c_int32), _ptr(off, C.c_int64),
                                             _ptr(self._data, C.c_double)))
@@ -162,9 +166,10 @@ class Context:
         self._check(self._lib.tn_update_values_device(self._h, C.c_void_p(dev_ptr)))
 
     def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
-                    max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False) -> None:
+                    max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False,
+                    grad: bool = False) -> None:
         pi, pj = _i32(pair_i), _i32(pair_j)
-        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates)
+        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad)
         self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
                                           C.byref(opts)))
 
@@ -226,6 +231,15 @@ class Context:
         return out[:n.value]
 
     def tn_grad(self, out: Optional[np.ndarray] = None) -> np.ndarray:
-        g = np.zeros_like(self._data) if out is None else out
+        """d ln|Z| / d data (float64, the layout of the loaded data)."""
+        g = np.zeros(self._n_data) if out is None else out
         self._check(self._lib.tn_grad(self._h, _ptr(g, C.c_double)))
         return g
+
+    def tn_grad_device(self, dev_ptr: int) -> None:
+        self._check(self._lib.tn_grad_device(self._h, C.c_void_p(dev_ptr)))
+
+    def tn_grad_info(self) -> dict:
+        f, b, n = C.c_double(), C.c_double(), C.c_int32()
+        self._check(self._lib.tn_grad_info(self._h, C.byref(f), C.byref(b), C.byref(n)))
+        return {"bwd_flops": f.value, "bwd_bytes": b.value, "n_levels": n.value}

@@ -17,7 +17,7 @@ using namespace tn;
 
 namespace {
 
-enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS };
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD };
 
 struct Launch {
     int kind = 0;
@@ -31,7 +31,7 @@ struct Launch {
     double bytes = 0;     // algorithmic bytes of the steps in this launch
 };
 
-constexpr int kKinds = 8;   // >= number of tn_kernel_kind values
+constexpr int kKinds = 12;   // >= number of tn_kernel_kind values
 
 }  // namespace
 
@@ -73,6 +73,18 @@ struct tn_ctx {
     int32_t* d_sweeps = nullptr;
     double* d_result = nullptr;
     double* h_result = nullptr;
+
+    // reverse pass
+    std::vector<GemmDesc> h_bgemm;
+    std::vector<ReduceDesc> h_reduce;
+    std::vector<CoreBwdDesc> h_cbwd;
+    std::vector<InputDesc> h_gin;
+    std::vector<Launch> blaunches;
+    GemmDesc* d_bgemm = nullptr;
+    ReduceDesc* d_reduce = nullptr;
+    CoreBwdDesc* d_cbwd = nullptr;
+    InputDesc* d_gin = nullptr;
+    double* d_grad = nullptr;         // host-destined gradient staging (n_input float64)
 
     bool evaluated = false;
     double sign = 0, lnz = 0;
@@ -122,6 +134,16 @@ void free_plan(tn_ctx* c) {
     dfree(c->d_disc);
     dfree(c->d_tie);
     dfree(c->d_sweeps);
+    dfree(c->d_bgemm);
+    dfree(c->d_reduce);
+    dfree(c->d_cbwd);
+    dfree(c->d_gin);
+    dfree(c->d_grad);
+    c->h_bgemm.clear();
+    c->h_reduce.clear();
+    c->h_cbwd.clear();
+    c->h_gin.clear();
+    c->blaunches.clear();
     c->h_gemm.clear();
     c->h_copy.clear();
     c->h_core.clear();
@@ -313,6 +335,7 @@ tn_status build_launches(tn_ctx* c) {
                 cd.p_right = buf_ptr(cp.pr_buf);
                 cd.stat = st.comp;
                 cd.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
+                cd.keep_out = P.opts.grad ? 1 : 0;
                 (cp.D <= kCoreLdsMaxD ? cores_lds : cores_glb).push_back(cd);
                 auto& cw = core_work[cp.D <= kCoreLdsMaxD ? 0 : 1];
                 cw.first += st.flops;
@@ -436,6 +459,163 @@ tn_status build_launches(tn_ctx* c) {
     return TN_OK;
 }
 
+// Reverse-pass launches, grouped by level like the forward ones.
+tn_status build_bwd_launches(tn_ctx* c) {
+    Plan& P = c->plan;
+    const bool f32 = P.opts.precision == 1;
+    char* base = c->arena;
+    auto buf_ptr = [&](int32_t b) -> char* { return base + P.bufs[b].off; };
+    std::vector<std::vector<int32_t>> by_level(P.n_blevels + 1);
+    for (int32_t s = 0; s < (int32_t)P.bsteps.size(); ++s)
+        if (P.bsteps[s].kind != BS_SEED) by_level[P.bsteps[s].level].push_back(s);
+    for (int L = 1; L <= P.n_blevels; ++L) {
+        std::map<int, std::vector<GemmDesc>> gemms;   // GemmKey -> descs
+        std::map<int, std::pair<double, double>> gwork;
+        std::vector<ReduceDesc> reds;
+        std::vector<CoreBwdDesc> cores;
+        double red_bytes = 0, core_flops = 0;
+        for (int32_t si : by_level[L]) {
+            const BStep& st = P.bsteps[si];
+            if (st.kind == BS_GEMM) {
+                GemmDesc g;
+                std::memset(&g, 0, sizeof(g));
+                std::string err = make_view(st.va, &g.va);
+                if (err.empty()) err = make_view(st.vb, &g.vb);
+                if (err.empty() && !st.partial) err = make_view(st.vc, &g.vc);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                g.A = buf_ptr(st.a_buf);
+                g.B = buf_ptr(st.b_buf);
+                g.C = buf_ptr(st.c_buf) + st.c_off;
+                g.M = (int32_t)st.M;
+                g.N = (int32_t)st.N;
+                g.K = (int32_t)st.K;
+                g.tiles_m = (int32_t)((st.M + 63) / 64);
+                g.tiles_n = (int32_t)((st.N + 63) / 64);
+                g.splits = st.splits;
+                g.k_per_split = st.k_per_split;
+                g.scale_a = st.scale_a;
+                g.scale_b = st.scale_b;
+                g.accumulate = st.accumulate;
+                g.mode = st.partial ? GEMM_GRAM : GEMM_ADJ;
+                const int key = st.partial ? (f32 ? GEMM_F32_TO_F64 : GEMM_F64) : (f32 ? GEMM_F32 : GEMM_F64);
+                gemms[key].push_back(g);
+                gwork[key].first += st.flops;
+                gwork[key].second += st.bytes;
+            } else if (st.kind == BS_REDUCE) {
+                ReduceDesc r;
+                std::memset(&r, 0, sizeof(r));
+                std::string err = make_view(st.vc, &r.vc);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                r.part = (const double*)buf_ptr(st.a_buf);
+                r.out = buf_ptr(st.c_buf);
+                r.M = (int32_t)st.M;
+                r.N = (int32_t)st.N;
+                r.splits = st.splits;
+                r.scale_a = st.scale_a;
+                r.scale_b = st.scale_b;
+                reds.push_back(r);
+                red_bytes += st.bytes;
+            } else if (st.kind == BS_CORE_BWD) {
+                const Compression& cp = P.comps[st.comp];
+                const CompBwd& cb = P.cbwd[st.comp];
+                CoreBwdDesc d;
+                std::memset(&d, 0, sizeof(d));
+                d.work = (const double*)buf_ptr(cp.work_buf);
+                d.h = (const double*)buf_ptr(cb.h_buf);
+                d.ws = (double*)buf_ptr(cb.work_buf);
+                d.n_a = buf_ptr(cb.na_buf);
+                d.n_b = buf_ptr(cb.nb_buf);
+                d.cutoff = P.opts.cutoff;
+                d.splits_a = cb.splits_a;
+                d.splits_b = cb.splits_b;
+                d.D = (int32_t)cp.D;
+                d.chi_new = cp.chi_new;
+                cores.push_back(d);
+                core_flops += st.flops;
+            }
+        }
+        for (auto& kv : gemms) {
+            Launch l;
+            l.kind = L_GEMM;
+            l.key = kv.first;
+            l.prof = TN_KERNEL_BWD_GEMM;
+            l.flops = gwork[kv.first].first;
+            l.bytes = gwork[kv.first].second;
+            l.begin = (int64_t)c->h_bgemm.size();
+            l.count = (int)kv.second.size();
+            int64_t tiles = 0;
+            for (auto& g : kv.second) {
+                g.tile_begin = tiles;
+                tiles += (int64_t)g.tiles_m * g.tiles_n * g.splits;
+                c->h_bgemm.push_back(g);
+            }
+            l.work = tiles;
+            c->blaunches.push_back(l);
+        }
+        if (!reds.empty()) {
+            Launch l;
+            l.kind = L_REDUCE;
+            l.key = f32 ? 1 : 0;
+            l.prof = TN_KERNEL_BWD_GEMM;
+            l.bytes = red_bytes;
+            l.begin = (int64_t)c->h_reduce.size();
+            l.count = (int)reds.size();
+            int64_t elems = 0;
+            for (auto& r : reds) {
+                r.elem_begin = elems;
+                elems += (int64_t)r.M * r.N;
+                c->h_reduce.push_back(r);
+            }
+            l.work = elems;
+            c->blaunches.push_back(l);
+        }
+        if (!cores.empty()) {
+            Launch l;
+            l.kind = L_CORE_BWD;
+            l.key = f32 ? 1 : 0;
+            l.prof = TN_KERNEL_BWD_CORE;
+            l.flops = core_flops;
+            l.begin = (int64_t)c->h_cbwd.size();
+            l.count = (int)cores.size();
+            for (auto& d : cores) c->h_cbwd.push_back(d);
+            c->blaunches.push_back(l);
+        }
+    }
+    for (int v = 0; v < c->g.n; ++v) {
+        InputDesc d{};
+        d.dst = buf_ptr(P.adj_buf[v]);
+        d.src_off = c->g.offsets[v];
+        d.count = c->g.offsets[v + 1] - c->g.offsets[v];
+        d.tensor = v;
+        c->h_gin.push_back(d);
+    }
+    tn_status s;
+    if ((s = upload(c, &c->d_bgemm, c->h_bgemm)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_reduce, c->h_reduce)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_cbwd, c->h_cbwd)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_gin, c->h_gin)) != TN_OK) return s;
+    HIP_TRY(c, hipMalloc((void**)&c->d_grad, std::max<int64_t>(1, c->n_input_elems) * sizeof(double)));
+    return TN_OK;
+}
+
+// Record HIP events around a launch of a profiled kind; returns the start-event slot or -1.
+tn_status prof_begin(tn_ctx* c, const Launch& l, hipStream_t s, bool* timed) {
+    *timed = (c->prof_mask >> l.prof) & 1u;
+    if (!*timed) return TN_OK;
+    const size_t i0 = c->ev_used.empty() ? 0 : c->ev_used.back().second + 2;
+    while (c->ev_pool.size() < i0 + 2) {
+        hipEvent_t e;
+        HIP_TRY(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_pool[i0], s));
+    c->ev_used.push_back({l.prof, i0});
+    c->prof_launches[l.prof] += 1;
+    c->prof_flops[l.prof] += l.flops;
+    c->prof_bytes[l.prof] += l.bytes;
+    return TN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -552,6 +732,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.jacobi_max_sweeps = opts->jacobi_max_sweeps > 0 ? opts->jacobi_max_sweeps : 40;
     o.budget = opts->device_budget_bytes;
     o.keep = opts->keep_intermediates;
+    o.grad = opts->grad ? 1 : 0;
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
     if (!err.empty()) {
         const bool nomem = err.rfind("plan needs", 0) == 0;
@@ -565,6 +746,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     }
     c->arena_cap = bytes;
     tn_status s = build_launches(c);
+    if (s == TN_OK && o.grad) s = build_bwd_launches(c);
     if (s != TN_OK) {
         free_plan(c);
         return s;
@@ -754,11 +936,65 @@ tn_status tn_read_tensor(const tn_ctx* c0, int32_t index, double* out, int64_t c
     return TN_OK;
 }
 
+tn_status tn_grad_device(tn_ctx* c, void* out) {
+    if (!c) return TN_EINVAL;
+    if (!out) return fail(c, TN_EINVAL, "null gradient buffer");
+    if (!c->has_plan || !c->plan.opts.grad) return fail(c, TN_ESTATE, "the tree was planned without opts.grad");
+    if (!c->evaluated) return fail(c, TN_ESTATE, "tn_grad before an evaluation");
+    if (c->sign == 0.0) return fail(c, TN_ZERO, "Z = 0: ln|Z| has no gradient");
+    (void)hipSetDevice(c->device);
+    Plan& P = c->plan;
+    const bool f32 = P.opts.precision == 1;
+    hipStream_t s = c->stream;
+    const int fin = P.final_tensor;
+    HIP_TRY(c, launch_seed(f32, c->arena + P.bufs[P.tens[fin].buf].off, c->arena + P.bufs[P.adj_buf[fin]].off,
+                           c->d_scales, fin, s));
+    for (const Launch& l : c->blaunches) {
+        bool timed = false;
+        tn_status st = prof_begin(c, l, s, &timed);
+        if (st != TN_OK) return st;
+        switch (l.kind) {
+            case L_GEMM:
+                HIP_TRY(c, launch_gemm(l.key, c->d_bgemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, s));
+                break;
+            case L_REDUCE:
+                HIP_TRY(c, launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, s));
+                break;
+            case L_CORE_BWD:
+                HIP_TRY(c, launch_core_bwd(l.key, c->d_cbwd + l.begin, l.count, s));
+                break;
+        }
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
+    }
+    HIP_TRY(c, launch_grad_inputs(f32, c->d_gin, (int)c->h_gin.size(), c->d_scales, (double*)out, s));
+    return TN_OK;
+}
+
 tn_status tn_grad(tn_ctx* c, double* dlnz_ddata) {
     if (!c) return TN_EINVAL;
-    (void)dlnz_ddata;
-    if (!c->evaluated) return fail(c, TN_ESTATE, "tn_grad before an evaluation");
-    return fail(c, TN_EINVAL, "the backward pass is not available in this build");
+    if (!dlnz_ddata) return fail(c, TN_EINVAL, "null gradient buffer");
+    if (!c->has_plan || !c->plan.opts.grad) return fail(c, TN_ESTATE, "the tree was planned without opts.grad");
+    tn_status st = tn_grad_device(c, c->d_grad);
+    if (st != TN_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(dlnz_ddata, c->d_grad, c->n_input_elems * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& u : c->ev_used) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
+        c->prof_ms[u.first] += ms;
+    }
+    c->ev_used.clear();
+    return TN_OK;
+}
+
+tn_status tn_grad_info(const tn_ctx* c, double* bwd_flops, double* bwd_bytes, int32_t* n_levels) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan || !c->plan.opts.grad) return TN_ESTATE;
+    if (bwd_flops) *bwd_flops = c->plan.bwd_flops;
+    if (bwd_bytes) *bwd_bytes = c->plan.bwd_bytes;
+    if (n_levels) *n_levels = c->plan.n_blevels;
+    return TN_OK;
 }
 
 tn_status tn_plan_describe(int32_t n_tensors, int32_t n_edges, const int32_t* edge_u, const int32_t* edge_v,

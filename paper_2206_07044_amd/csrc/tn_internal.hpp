@@ -77,6 +77,7 @@ struct View {
 enum GemmMode : int32_t {
     GEMM_TENSOR = 0,   // C (M x N, row-major) = fA*fB * A.B ; writes per-tile max |C|
     GEMM_GRAM = 1,     // C[split] (M x N, float64) = fA*fB * A.B over one K range
+    GEMM_ADJ = 2,      // C(view vc) = [C +] fA*fB * A.B  (reverse pass; no tile max)
 };
 
 // C = op(A) . op(B) with A an (M x K) view and B a (K x N) view.
@@ -92,8 +93,34 @@ struct GemmDesc {
     int32_t scale_a, scale_b;    // indices into the tensor-scale array (-1: factor 1)
     int32_t square_a;            // GRAM: factor is 1/s_a^2 (A and B are the same tensor)
     int32_t maxpart;             // TENSOR: index of the first per-tile max slot
+    int32_t accumulate;          // ADJ: add to C instead of overwriting it
+    int32_t pad;
     View va;                     // A: rows = M, cols = K
     View vb;                     // B: rows = K, cols = N
+    View vc;                     // ADJ: C, rows = M, cols = N
+};
+
+// Reverse pass: C(view vc) = f * sum over splits of dense float64 partials (M x N each).
+struct ReduceDesc {
+    const double* part;
+    void* out;                   // compute precision
+    int64_t elem_begin;          // first linear element of this op in the grouped launch
+    int32_t M, N, splits;
+    int32_t scale_a, scale_b;    // f = 1/(s[scale_a] s[scale_b]) (-1: factor 1)
+    int32_t pad;
+    View vc;
+};
+
+// Reverse pass of one compression in the space of its core (see core_bwd_kernel).
+struct CoreBwdDesc {
+    const double* work;          // the forward core workspace (R~_A, R~_B, W, V, sigma, order, ranks)
+    const double* h;             // H_A partials (splits_a x D x chi'), then H_B partials (splits_b x D x chi')
+    double* ws;                  // float64 workspace
+    void* n_a;                   // N_A (D x D, compute precision)
+    void* n_b;                   // N_B
+    double cutoff;
+    int32_t splits_a, splits_b;
+    int32_t D, chi_new;
 };
 
 // Gather-copy: dst (rows x cols, row-major float64) = src(view) / s.
@@ -125,6 +152,8 @@ struct CoreDesc {
     void* p_right;               // chi' x D projector in the tensor dtype
     int32_t stat;                // index into the per-compression stats arrays
     int32_t kmin;                // min(k_A, k_B): number of singular values of the structural core
+    int32_t keep_out;            // LDS variant: leave R~_A, R~_B, W, V in the workspace (reverse pass)
+    int32_t pad;
 };
 
 // Large-core compression by Golub-Kahan-Lanczos on M = (A/s_a)(B/s_b) read through Views.

@@ -69,6 +69,14 @@ __device__ inline double read_lane(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// value of v in lane src (src uniform across the wave)
+__device__ inline double bcast(double v, int src) {
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, src);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), src);
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ inline double wave_sum(double v) {
     v += dpp_mov<0xB1>(v);    // quad_perm(1,0,3,2)
     v += dpp_mov<0x4E>(v);    // quad_perm(2,3,0,1)
@@ -204,6 +212,25 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     const double factor = d.square_a ? fa * fa : fa * inv_scale(scales, d.scale_b);
     double local_max = 0.0;
     Tout* __restrict__ C = (Tout*)d.C;
+    if (d.mode == GEMM_ADJ) {
+        // reverse pass: scatter into the adjoint's own layout, optionally accumulating
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gm = m0 + wm + i * 16 + Mma<Tc>::row(lane, r);
+                    const int gn = n0 + wn + j * 16 + lrow;
+                    if (gm < M && gn < N) {
+                        const uint32_t off = axis_offset(d.vc.row, (uint32_t)gm) + axis_offset(d.vc.col, (uint32_t)gn);
+                        double v = (double)acc[i][j][r] * factor;
+                        if (d.accumulate) v += (double)C[off];
+                        C[off] = (Tout)v;
+                    }
+                }
+        return;
+    }
     const int64_t cbase = (d.mode == GEMM_GRAM) ? (int64_t)split * M * N : 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -324,6 +351,52 @@ __device__ int pivoted_cholesky(double* G, int D, double* R, int* chosen, CoreSh
     return r;
 }
 
+// pivoted_cholesky by a single wave for D <= 64: lane l owns index l, the pivot search is a
+// wave butterfly, and the rank-1 update runs down each lane's own column of G (LDS, symmetric,
+// destroyed).  Same pivot rule, stopping tolerance and output layout as pivoted_cholesky.
+__device__ int pivoted_cholesky_wave(double* G, int D, double* R) {
+    const int l = threadIdx.x & 63;
+    const bool own = l < D;
+    bool chosen = !own;
+    double diag = own ? G[l * D + l] : 0.0;
+    double tol = 0.0;
+    int r = 0;
+    for (int t = 0; t < D; ++t) {
+        double bv = chosen ? -1.0 : diag;
+        int bi = chosen ? 0x7fffffff : l;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (t == 0) tol = 1e-15 * bv;
+        if (!(bv > tol) || !(bv > 0.0)) break;
+        const int p = bi;
+        const double rp = sqrt(bv);
+        double v = 0.0;
+        if (!chosen) v = (l == p) ? rp : G[p * D + l] / rp;
+        if (own) R[t * D + l] = v;
+        if (!chosen && l != p) {
+            double* col = G + l;
+            int i = 0;
+            for (; i + 4 <= D; i += 4) {
+                const double v0 = bcast(v, i), v1 = bcast(v, i + 1), v2 = bcast(v, i + 2), v3 = bcast(v, i + 3);
+                const double g0 = col[i * D], g1 = col[(i + 1) * D], g2 = col[(i + 2) * D], g3 = col[(i + 3) * D];
+                col[i * D] = g0 - v0 * v;
+                col[(i + 1) * D] = g1 - v1 * v;
+                col[(i + 2) * D] = g2 - v2 * v;
+                col[(i + 3) * D] = g3 - v3 * v;
+            }
+            for (; i < D; ++i) col[i * D] -= bcast(v, i) * v;
+        }
+        if (l == p) chosen = true;
+        if (!chosen) diag = G[l * D + l];
+        r = t + 1;
+    }
+    return r;
+}
+
 __device__ inline int rr_col(int pos, int round, int n) {
     return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
 }
@@ -429,8 +502,8 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
     const int nc = cols + (cols & 1);
     const double tol = 2.220446049250313e-16 * (double)max(rows, 16);
     double f = 0.0;
-    for (int64_t idx = tid; idx < (int64_t)rows * cols; idx += kCoreThreads) {
-        const int j = (int)(idx / rows), i = (int)(idx - (int64_t)j * rows);
+    for (int idx = tid; idx < rows * cols; idx += kCoreThreads) {
+        const int j = idx / rows, i = idx - j * rows;
         const double x = W[(int64_t)j * ld + i];
         f += x * x;
     }
@@ -538,49 +611,98 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int D = d.D;
     const int64_t DD = (int64_t)D * D;
-    double* Ra = d.work;
+    // LDS variant (D <= 64): W, V, R~_A, R~_B all in LDS; else all in the global workspace
+    double* W = kLds ? lds : d.work + 2 * DD;    // column-major core, column j at W + j*D
+    double* V = W + DD;                          // column-major right singular vectors
+    double* Ra = kLds ? lds + 2 * DD : d.work;   // row-major R~_A, row t at Ra + t*D
     double* Rb = Ra + DD;
-    double* W = kLds ? lds : Rb + DD;            // column-major core, column j at W + j*D
-    double* V = kLds ? lds + DD : W + DD;        // column-major right singular vectors
     double* sig = d.work + 4 * DD;
     int* order = (int*)(sig + D);
     int* chosen = order + D;
 
     // ---- reduced factors R~_A (ra x D), R~_B (rb x D)
-    int rk[2];
-    for (int side = 0; side < 2; ++side) {
-        const double* gram = side == 0 ? d.gram_a : d.gram_b;
-        const double* fac = side == 0 ? d.fac_a : d.fac_b;
-        double* R = side == 0 ? Ra : Rb;
-        if (gram) {
-            const int splits = side == 0 ? d.splits_a : d.splits_b;
-            for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
-                double s = 0.0;
-                for (int p = 0; p < splits; ++p) s += gram[(int64_t)p * DD + idx];
-                W[idx] = s;
+    int ra, rb;
+    if (kLds) {
+        // split-K Gram partials summed into LDS (side A into W, side B into V), explicit
+        // factors copied; then one wave per side runs its pivoted Cholesky
+        const int DDi = D * D;
+        for (int side = 0; side < 2; ++side) {
+            const double* gram = side == 0 ? d.gram_a : d.gram_b;
+            if (gram) {
+                const int splits = side == 0 ? d.splits_a : d.splits_b;
+                double* G = side == 0 ? W : V;
+                for (int idx = tid; idx < DDi; idx += kCoreThreads) {
+                    const double* g = gram + idx;
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                    int p = 0;
+                    for (; p + 4 <= splits; p += 4) {
+                        s0 += g[(int64_t)p * DD];
+                        s1 += g[(int64_t)(p + 1) * DD];
+                        s2 += g[(int64_t)(p + 2) * DD];
+                        s3 += g[(int64_t)(p + 3) * DD];
+                    }
+                    for (; p < splits; ++p) s0 += g[(int64_t)p * DD];
+                    G[idx] = (s0 + s1) + (s2 + s3);
+                }
+            } else {
+                const int rows = side == 0 ? d.rows_a : d.rows_b;
+                const double* fac = side == 0 ? d.fac_a : d.fac_b;
+                double* R = side == 0 ? Ra : Rb;
+                for (int idx = tid; idx < rows * D; idx += kCoreThreads) R[idx] = fac[idx];
             }
-            __syncthreads();
-            rk[side] = pivoted_cholesky(W, D, R, chosen, sh);
-        } else {
-            const int rows = side == 0 ? d.rows_a : d.rows_b;
-            for (int64_t idx = tid; idx < (int64_t)rows * D; idx += kCoreThreads) R[idx] = fac[idx];
-            rk[side] = rows;
         }
         __syncthreads();
+        if (wave < 2) {
+            const double* gram = wave == 0 ? d.gram_a : d.gram_b;
+            int r = wave == 0 ? d.rows_a : d.rows_b;
+            if (gram) r = pivoted_cholesky_wave(wave == 0 ? W : V, D, wave == 0 ? Ra : Rb);
+            if (lane == 0) sh.ri[wave] = r;
+        }
+        __syncthreads();
+        ra = sh.ri[0];
+        rb = sh.ri[1];
+    } else {
+        int rk[2];
+        for (int side = 0; side < 2; ++side) {
+            const double* gram = side == 0 ? d.gram_a : d.gram_b;
+            const double* fac = side == 0 ? d.fac_a : d.fac_b;
+            double* R = side == 0 ? Ra : Rb;
+            if (gram) {
+                const int splits = side == 0 ? d.splits_a : d.splits_b;
+                for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
+                    double s = 0.0;
+                    for (int p = 0; p < splits; ++p) s += gram[(int64_t)p * DD + idx];
+                    W[idx] = s;
+                }
+                __syncthreads();
+                rk[side] = pivoted_cholesky(W, D, R, chosen, sh);
+            } else {
+                const int rows = side == 0 ? d.rows_a : d.rows_b;
+                for (int64_t idx = tid; idx < (int64_t)rows * D; idx += kCoreThreads) R[idx] = fac[idx];
+                rk[side] = rows;
+            }
+            __syncthreads();
+        }
+        ra = rk[0];
+        rb = rk[1];
     }
-    const int ra = rk[0], rb = rk[1];
 
     // ---- core W = R~_A R~_B^T  (ra x rb), V = I
-    for (int64_t idx = tid; idx < (int64_t)ra * rb; idx += kCoreThreads) {
-        const int j = (int)(idx / ra), i = (int)(idx - (int64_t)j * ra);
+    for (int idx = tid; idx < ra * rb; idx += kCoreThreads) {
+        const int j = idx / ra, i = idx - j * ra;
         const double* x = Ra + (int64_t)i * D;
         const double* y = Rb + (int64_t)j * D;
+        // start each thread at its own offset so neighbouring rows hit different LDS banks
+        int q = i % D;
         double s = 0.0;
-        for (int q = 0; q < D; ++q) s += x[q] * y[q];
+        for (int c = 0; c < D; ++c) {
+            s += x[q] * y[q];
+            q = q + 1 == D ? 0 : q + 1;
+        }
         W[(int64_t)j * D + i] = s;
     }
-    for (int64_t idx = tid; idx < (int64_t)rb * rb; idx += kCoreThreads) {
-        const int j = (int)(idx / rb), i = (int)(idx - (int64_t)j * rb);
+    for (int idx = tid; idx < rb * rb; idx += kCoreThreads) {
+        const int j = idx / rb, i = idx - j * rb;
         V[(int64_t)j * D + i] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -601,8 +723,8 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
     const double smax = rb > 0 ? sig[order[0]] : 0.0;
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
-    for (int64_t idx = tid; idx < (int64_t)D * cn; idx += kCoreThreads) {
-        const int dd = (int)(idx / cn), t = (int)(idx - (int64_t)dd * cn);
+    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+        const int dd = idx / cn, t = idx - dd * cn;
         const int j = t < rb ? order[t] : -1;
         const double s = j >= 0 ? sig[j] : 0.0;
         double pl = 0.0, pr = 0.0;
@@ -620,6 +742,21 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
         }
         PL[(int64_t)dd * cn + t] = (Tp)pl;
         PR[(int64_t)t * D + dd] = (Tp)pr;
+    }
+
+    // ---- what the reverse pass reads back: factors, core, V (LDS variant) and the ranks
+    if (kLds && d.keep_out) {
+        double* gw = d.work;
+        for (int idx = tid; idx < 4 * D * D; idx += kCoreThreads) {
+            const int part = idx / (D * D), off = idx - part * D * D;
+            const double* src = part == 0 ? Ra : part == 1 ? Rb : part == 2 ? W : V;
+            gw[idx] = src[off];
+        }
+    }
+    if (tid == 0) {
+        int* ranks = (int*)(sig + 2 * D);
+        ranks[0] = ra;
+        ranks[1] = rb;
     }
 
     // ---- diagnostics
@@ -1341,7 +1478,219 @@ hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t to
     return hipGetLastError();
 }
 
-size_t core_lds_bytes(int max_d) { return (size_t)2 * max_d * max_d * sizeof(double); }
+// ------------------------------------------------------------------------------------------
+// Reverse pass
+// ------------------------------------------------------------------------------------------
+// C(view) = f * sum of split-K partials, converted to the compute precision.
+template <typename Tout>
+__global__ __launch_bounds__(256) void reduce_grouped(const ReduceDesc* __restrict__ descs, int ndesc,
+                                                      const double* __restrict__ scales, int64_t total) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].elem_begin <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const ReduceDesc& d = descs[lo];
+    const int64_t local = e - d.elem_begin;
+    const int64_t MN = (int64_t)d.M * d.N;
+    const int r = (int)(local / d.N), c = (int)(local - (int64_t)r * d.N);
+    double acc = 0.0;
+    for (int p = 0; p < d.splits; ++p) acc += d.part[p * MN + local];
+    const double f = inv_scale(scales, d.scale_a) * inv_scale(scales, d.scale_b);
+    Tout* out = (Tout*)d.out;
+    out[axis_offset(d.vc.row, (uint32_t)r) + axis_offset(d.vc.col, (uint32_t)c)] = (Tout)(acc * f);
+}
+
+// Adjoint of one compression in the space of its core.  With the core SVD
+// R~_A R~_B^T = U s V^T (all singular triplets above the rounding level, the "+" set, r of them,
+// the first nK kept), L = R~_B^T V s^-1 and M = R~_A^T U s^-1 (D x r), the inputs
+// H_A = A^T G_a, H_B = B G_b^T (D x nK) give a = L^T H_A, b = M^T H_B (r x nK) and
+//   Phi (r x r): the truncated-SVD adjoint in singular coordinates (full spectrum, Lorentzian
+//                broadening between kept pairs),
+//   N_A = L Psi_A L^T + sum_t L_t H_B,t^T / sqrt(s_t),   N_B = M Psi_B M^T + sum_t H_A,t M_t^T / sqrt(s_t),
+//   Psi_A = Phi s - a s^1/2 E^T - E s^-1/2 b^T s,   Psi_B = s Phi - s a s^-1/2 E^T - E s^1/2 b^T,
+// so that A_bar = G_a P_L^T + A N_A and B_bar = P_R^T G_b + N_B B need no inverse of R~.
+template <typename Tp>
+__global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDesc* __restrict__ descs) {
+    const CoreBwdDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int D = d.D, cn = d.chi_new, DD = D * D;
+    const double* Ra = d.work;
+    const double* Rb = Ra + DD;
+    const double* W = Rb + DD;
+    const double* V = W + DD;
+    const double* sig = V + DD;
+    const int* order = (const int*)(sig + D);
+    const int* ranks = (const int*)(sig + 2 * D);
+    const int ra = ranks[0], rb = ranks[1];
+    double* L = d.ws;             // D x D, L[dd*D + p]
+    double* Mm = L + DD;          // D x D
+    double* Phi = Mm + DD;        // r x r (ld D)
+    double* PsiA = Phi + DD;
+    double* PsiB = PsiA + DD;
+    double* T = PsiB + DD;        // D x D scratch
+    double* HA = T + DD;          // D x cn
+    double* HB = HA + D * cn;
+    double* a = HB + D * cn;      // r x cn (ld cn)
+    double* b = a + D * cn;
+    double* sg = b + D * cn;      // sigma of the + set, descending
+    double* sq = sg + D;          // sqrt(sigma)
+    __shared__ int sh_r, sh_nk;
+    __shared__ double sh_eps;
+
+    if (tid == 0) {
+        double smax = rb > 0 ? sig[order[0]] : 0.0, fro = 0.0;
+        for (int j = 0; j < rb; ++j) fro += sig[j] * sig[j];
+        fro = sqrt(fro);
+        int r = 0;
+        while (r < rb && sig[order[r]] > kNoiseRel * smax && sig[order[r]] > 4.0 * kZeroRel * fro) ++r;
+        int nk = 0;
+        while (nk < min(cn, r) && sig[order[nk]] >= d.cutoff * smax) ++nk;
+        sh_r = r;
+        sh_nk = nk;
+        sh_eps = 1e-12 * smax * smax;
+    }
+    __syncthreads();
+    const int r = sh_r, nk = sh_nk;
+    const double eps = sh_eps;
+    for (int p = tid; p < r; p += kCoreThreads) {
+        sg[p] = sig[order[p]];
+        sq[p] = sqrt(sg[p]);
+    }
+    const double* ha = d.h;
+    const double* hb = d.h + (int64_t)d.splits_a * D * cn;
+    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+        double x = 0.0, y = 0.0;
+        for (int p = 0; p < d.splits_a; ++p) x += ha[(int64_t)p * D * cn + idx];
+        for (int p = 0; p < d.splits_b; ++p) y += hb[(int64_t)p * D * cn + idx];
+        HA[idx] = x;
+        HB[idx] = y;
+    }
+    __syncthreads();
+    // L = R~_B^T V_+ s^-1, M = R~_A^T (W_+ s^-1) s^-1  (W's columns are U s)
+    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
+        const int dd = idx / r, p = idx - dd * r;
+        const int j = order[p];
+        const double* v = V + (int64_t)j * D;
+        const double* w = W + (int64_t)j * D;
+        double x = 0.0, y = 0.0;
+        for (int i = 0; i < rb; ++i) x += Rb[i * D + dd] * v[i];
+        for (int i = 0; i < ra; ++i) y += Ra[i * D + dd] * w[i];
+        L[dd * D + p] = x / sg[p];
+        Mm[dd * D + p] = y / (sg[p] * sg[p]);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < r * nk; idx += kCoreThreads) {
+        const int p = idx / nk, t = idx - p * nk;
+        double x = 0.0, y = 0.0;
+        for (int dd = 0; dd < D; ++dd) {
+            x += L[dd * D + p] * HA[dd * cn + t];
+            y += Mm[dd * D + p] * HB[dd * cn + t];
+        }
+        a[p * cn + t] = x;
+        b[p * cn + t] = y;
+    }
+    __syncthreads();
+    // Phi[x][y]: diagonal of the kept block, plus the contributions of kept index y (to row x)
+    // and of kept index x (to column y) for every other singular index
+    for (int idx = tid; idx < r * r; idx += kCoreThreads) {
+        const int x = idx / r, y = idx - x * r;
+        const double sx = sg[x], sy = sg[y];
+        double v = 0.0;
+        if (x == y) {
+            if (x < nk) v = (a[x * cn + x] + b[x * cn + x]) / (2.0 * sq[x]);
+        } else {
+            const double d2 = sy * sy - sx * sx;   // sigma_y^2 - sigma_x^2
+            if (y < nk) {   // i = y kept, j = x
+                const double f = x < nk ? d2 / (d2 * d2 + eps * eps) : 1.0 / d2;
+                v += (a[x * cn + y] * sq[y] * sy + b[x * cn + y] * sq[y] * sx) * f;
+            }
+            if (x < nk) {   // i = x kept, j = y
+                const double f = y < nk ? -d2 / (d2 * d2 + eps * eps) : -1.0 / d2;
+                v += (a[y * cn + x] * sq[x] * sy + b[y * cn + x] * sq[x] * sx) * f;
+            }
+        }
+        Phi[x * D + y] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < r * r; idx += kCoreThreads) {
+        const int x = idx / r, y = idx - x * r;
+        const double ph = Phi[x * D + y], sx = sg[x], sy = sg[y];
+        double pa = ph * sy, pb = sx * ph;
+        if (y < nk) {
+            pa -= a[x * cn + y] * sq[y];
+            pb -= sx * a[x * cn + y] / sq[y];
+        }
+        if (x < nk) {
+            pa -= b[y * cn + x] * sy / sq[x];
+            pb -= sq[x] * b[y * cn + x];
+        }
+        PsiA[x * D + y] = pa;
+        PsiB[x * D + y] = pb;
+    }
+    __syncthreads();
+    // T = L Psi_A ; N_A = T L^T + sum_t L_t H_B,t^T / sqrt(s_t)
+    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
+        const int dd = idx / r, y = idx - dd * r;
+        double x = 0.0;
+        for (int q = 0; q < r; ++q) x += L[dd * D + q] * PsiA[q * D + y];
+        T[dd * D + y] = x;
+    }
+    __syncthreads();
+    Tp* na = (Tp*)d.n_a;
+    for (int idx = tid; idx < DD; idx += kCoreThreads) {
+        const int d1 = idx / D, d2 = idx - d1 * D;
+        double x = 0.0;
+        for (int y = 0; y < r; ++y) x += T[d1 * D + y] * L[d2 * D + y];
+        for (int t = 0; t < nk; ++t) x += L[d1 * D + t] * HB[d2 * cn + t] / sq[t];
+        na[idx] = (Tp)x;
+    }
+    __syncthreads();
+    // T = M Psi_B ; N_B = T M^T + sum_t H_A,t M_t^T / sqrt(s_t)
+    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
+        const int dd = idx / r, y = idx - dd * r;
+        double x = 0.0;
+        for (int q = 0; q < r; ++q) x += Mm[dd * D + q] * PsiB[q * D + y];
+        T[dd * D + y] = x;
+    }
+    __syncthreads();
+    Tp* nb = (Tp*)d.n_b;
+    for (int idx = tid; idx < DD; idx += kCoreThreads) {
+        const int d1 = idx / D, d2 = idx - d1 * D;
+        double x = 0.0;
+        for (int y = 0; y < r; ++y) x += T[d1 * D + y] * Mm[d2 * D + y];
+        for (int t = 0; t < nk; ++t) x += HA[d1 * cn + t] * Mm[d2 * D + t] / sq[t];
+        nb[idx] = (Tp)x;
+    }
+}
+
+// Adjoint of the final scalar: d ln|x| / d x^ = 1 / x^ with x^ = x / s the normalised value.
+template <typename Tp>
+__global__ void seed_kernel(const void* __restrict__ final_ptr, void* __restrict__ adj, const double* scales,
+                            int final_index) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double x = (double)((const Tp*)final_ptr)[0];
+        ((Tp*)adj)[0] = (Tp)(x != 0.0 ? scales[final_index] / x : 0.0);
+    }
+}
+
+// d ln|Z| / d data_v = adj(T^_v) / s_v, in the input layout (float64).
+template <typename Tp>
+__global__ void grad_inputs_kernel(const InputDesc* __restrict__ descs, int n, const double* __restrict__ scales,
+                                   double* __restrict__ out) {
+    const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (gw >= n) return;
+    const InputDesc& d = descs[gw];
+    const Tp* x = (const Tp*)d.dst;
+    const double inv = 1.0 / scales[d.tensor];
+    for (int64_t i = lane; i < d.count; i += 64) out[d.src_off + i] = (double)x[i] * inv;
+}
+
+size_t core_lds_bytes(int max_d) { return (size_t)4 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
     (void)hipFuncSetAttribute((const void*)gram_lanczos_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
@@ -1412,6 +1761,38 @@ hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* s
         input_scatter<double><<<grid, block, 0, s>>>(descs, n, staging);
         input_scales<double><<<grid, block, 0, s>>>(descs, n, scales);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int f32, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
+                         hipStream_t s) {
+    if (ndesc == 0 || total == 0) return hipSuccess;
+    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (f32) reduce_grouped<float><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
+    else reduce_grouped<double><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_core_bwd(int f32, const CoreBwdDesc* descs, int ndesc, hipStream_t s) {
+    if (ndesc == 0) return hipSuccess;
+    if (f32) core_bwd_kernel<float><<<ndesc, kCoreThreads, 0, s>>>(descs);
+    else core_bwd_kernel<double><<<ndesc, kCoreThreads, 0, s>>>(descs);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(int f32, const void* final_ptr, void* adj_final, const double* scales, int final_index,
+                       hipStream_t s) {
+    if (f32) seed_kernel<float><<<1, 64, 0, s>>>(final_ptr, adj_final, scales, final_index);
+    else seed_kernel<double><<<1, 64, 0, s>>>(final_ptr, adj_final, scales, final_index);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_inputs(int f32, const InputDesc* descs, int n, const double* scales, double* out,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n * 64 + 255) / 256)), block(256);
+    if (f32) grad_inputs_kernel<float><<<grid, block, 0, s>>>(descs, n, scales, out);
+    else grad_inputs_kernel<double><<<grid, block, 0, s>>>(descs, n, scales, out);
     return hipGetLastError();
 }
 

@@ -31,6 +31,13 @@ hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* ma
                                  hipStream_t s);
 hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,
                          hipStream_t s);
+hipError_t launch_reduce(int f32, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
+                         hipStream_t s);
+hipError_t launch_core_bwd(int f32, const CoreBwdDesc* descs, int ndesc, hipStream_t s);
+hipError_t launch_seed(int f32, const void* final_ptr, void* adj_final, const double* scales, int final_index,
+                       hipStream_t s);
+hipError_t launch_grad_inputs(int f32, const InputDesc* descs, int n, const double* scales, double* out,
+                              hipStream_t s);
 hipError_t launch_result(int f32, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
                          int n_comp, double* result, hipStream_t s);
 

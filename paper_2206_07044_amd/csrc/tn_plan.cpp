@@ -98,6 +98,35 @@ std::string make_axis(const std::vector<int32_t>& dims, const std::vector<int64_
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Transposed view of a dense row-major (rows x cols) matrix: (cols x rows).
+ViewSpec dense_view_t(int64_t rows, int64_t cols) {
+    ViewSpec v;
+    v.row_dims = {(int32_t)cols};
+    v.row_strides = {1};
+    v.col_dims = {(int32_t)rows};
+    v.col_strides = {cols};
+    return v;
+}
+
+// Split-K factor for a reduction of length K into an M x N result.
+int32_t split_k(int64_t M, int64_t N, int64_t K, int64_t max_bytes) {
+    const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int64_t s = (K + 255) / 256;
+    s = std::min<int64_t>(s, std::max<int64_t>(1, 1024 / tiles));
+    s = std::min<int64_t>(s, std::max<int64_t>(1, max_bytes / std::max<int64_t>(1, M * N * 8)));
+    return (int32_t)std::max<int64_t>(1, s);
+}
+
+// Reverse-pass record of one forward op: its steps carry levels relative to the
+// moment the adjoints of all its outputs are complete.
+struct BwdOp {
+    int32_t outs[2] = {-1, -1};      // tensor versions whose adjoints it reads
+    int32_t ins[2] = {-1, -1};       // tensor versions whose adjoints it writes
+    int32_t done[2] = {0, 0};        // relative level at which each input adjoint is complete
+    std::vector<BStep> steps;
+    int32_t comp = -1;
+};
+
 }  // namespace
 
 std::string make_view(const ViewSpec& s, View* v) {
@@ -195,6 +224,65 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
         touch(t.buf, level);
     };
 
+    std::vector<BwdOp> bops;
+    auto adj_of = [&](int32_t ver) {
+        if ((int32_t)P->adj_buf.size() <= ver) P->adj_buf.resize(ver + 1, -1);
+        if (P->adj_buf[ver] < 0) P->adj_buf[ver] = new_buf(P->tens[ver].size * w, BUF_BWD, 0);
+        return P->adj_buf[ver];
+    };
+    // reverse-pass GEMM: C(vc) = [C +] f A(va) B(vb), or split-K float64 partials + a reduction
+    // (the reduction reads the partials into C(vc) one level later); returns the levels used
+    auto bwd_gemm = [&](BwdOp& op, int rel, int32_t a_buf, int32_t b_buf, int32_t c_buf, const ViewSpec& va,
+                        const ViewSpec& vb, const ViewSpec& vc, int64_t M, int64_t N, int64_t K, int32_t sa,
+                        int32_t sb, int32_t acc, bool allow_split) {
+        BStep g;
+        g.kind = BS_GEMM;
+        g.level = rel;
+        g.a_buf = a_buf;
+        g.b_buf = b_buf;
+        g.c_buf = c_buf;
+        g.va = va;
+        g.vb = vb;
+        g.vc = vc;
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.scale_a = sa;
+        g.scale_b = sb;
+        g.accumulate = acc;
+        g.flops = 2.0 * (double)M * N * K;
+        g.bytes = (double)w * ((double)M * K + (double)K * N + (double)M * N);
+        const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+        if (allow_split && !acc && K > 2048 && tiles < 64) {
+            g.partial = 1;
+            g.splits = split_k(M, N, K, 64 << 20);
+            int64_t kps = (K + g.splits - 1) / g.splits;
+            kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
+            g.splits = (int32_t)((K + kps - 1) / kps);
+            g.k_per_split = (int32_t)kps;
+            g.c_buf = new_buf((int64_t)g.splits * M * N * 8, BUF_BWD, 0);
+            BStep r;
+            r.kind = BS_REDUCE;
+            r.level = rel + 1;
+            r.a_buf = g.c_buf;
+            r.c_buf = c_buf;
+            r.vc = vc;
+            r.M = M;
+            r.N = N;
+            r.splits = g.splits;
+            r.scale_a = sa;
+            r.scale_b = sb;
+            r.bytes = 8.0 * g.splits * M * N + (double)w * M * N;
+            op.steps.push_back(g);
+            op.steps.push_back(r);
+            return 2;
+        }
+        g.splits = 1;
+        g.k_per_split = (int32_t)K;
+        op.steps.push_back(g);
+        return 1;
+    };
+
     auto add_gemm_flops = [&](Step& s) {
         s.flops = 2.0 * (double)s.M * (double)s.N * (double)s.K;
         s.bytes = (double)w * ((double)s.M * s.K + (double)s.K * s.N + (double)s.M * s.N);
@@ -247,6 +335,20 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 read_tensor(vi, st.level);
                 read_tensor(vj, st.level);
                 P->steps.push_back(st);
+                if (o.grad) {
+                    // C = A B:  A_bar = C_bar B^T / (s_C s_B),  B_bar = A^T C_bar / (s_A s_C)
+                    BwdOp op;
+                    op.outs[0] = st.out_t;
+                    op.ins[0] = vi;
+                    op.ins[1] = vj;
+                    const ViewSpec cbar = tensor_view(P->tens[st.out_t], free_i, free_j, E);
+                    op.done[0] = bwd_gemm(op, 1, adj_of(st.out_t), Tj.buf, adj_of(vi), cbar,
+                                          tensor_view(Tj, free_j, shared, E), st.va, m, s, q, st.out_t, vj, 0, true);
+                    op.done[1] = bwd_gemm(op, 1, Ti.buf, adj_of(st.out_t), adj_of(vj),
+                                          tensor_view(Ti, shared, free_i, E), cbar, st.vb, s, q, m, vi, st.out_t, 0,
+                                          true);
+                    bops.push_back(op);
+                }
             } else {
                 P->tens.push_back(Tk);
             }
@@ -298,7 +400,7 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 c.mb = mb;
                 c.chi_new = (int32_t)nw;
                 const int32_t comp_id = (int32_t)P->comps.size();
-                const bool big = D >= kLanczosMinD;
+                const bool big = D >= kLanczosMinD && !o.grad;   // the reverse pass needs the full core spectrum
                 const bool glanczos = big && (ma <= D || mb <= D);
                 const bool lanczos = big && !glanczos && (ma + mb) <= kLanczosMaxRowsPerD * D;
                 c.lanczos = lanczos ? 1 : 0;
@@ -345,8 +447,14 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                             st.K = mm;
                             st.va = tensor_view(T, shared, fr, E);
                             st.vb = tensor_view(T, fr, shared, E);
-                            int64_t splits = (mm + 2047) / 2048;
-                            splits = std::max<int64_t>(1, std::min<int64_t>(splits, 64));
+                            // split-K: short chunks keep each workgroup's serial loop short (the
+                            // compressions of one level are few, so latency, not throughput, rules);
+                            // about a thousand workgroups per Gram and 32 MiB of partials at most
+                            const int64_t tiles = ((D + 63) / 64) * ((D + 63) / 64);
+                            int64_t splits = (mm + 255) / 256;
+                            splits = std::min<int64_t>(splits, std::max<int64_t>(1, 1024 / tiles));
+                            splits = std::min<int64_t>(splits, std::max<int64_t>(1, (32 << 20) / (D * D * 8)));
+                            splits = std::max<int64_t>(1, splits);
                             int64_t kps = (mm + splits - 1) / splits;
                             kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
                             splits = (mm + kps - 1) / kps;
@@ -447,6 +555,87 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 P->comps.push_back(c);
                 live[a] = c.a_ver_out;
                 live[b] = c.b_ver_out;
+                if (o.grad) {
+                    // a' = A P_L, b' = P_R B depend on (A, B) through K = A B only:
+                    //   A_bar = G_a P_L^T + A N_A,   B_bar = P_R^T G_b + N_B B
+                    // with H_A = A^T G_a, H_B = B G_b^T and the D x D matrices N_A, N_B from the core
+                    BwdOp op;
+                    op.comp = comp_id;
+                    op.outs[0] = c.a_ver_out;
+                    op.outs[1] = c.b_ver_out;
+                    op.ins[0] = va;
+                    op.ins[1] = vb;
+                    const std::vector<int32_t> enew = {e_new};
+                    const ViewSpec ga = tensor_view(P->tens[c.a_ver_out], free_a, enew, E);    // ma x nw
+                    const ViewSpec gbt = tensor_view(P->tens[c.b_ver_out], free_b, enew, E);   // mb x nw
+                    const ViewSpec gb = tensor_view(P->tens[c.b_ver_out], enew, free_b, E);    // nw x mb
+                    const ViewSpec out_a = tensor_view(Ta, free_a, shared, E);                 // A's own layout
+                    const ViewSpec out_b = tensor_view(Tb, shared, free_b, E);
+                    CompBwd cb;
+                    auto hsplits = [&](int64_t mm) {
+                        int32_t sp = split_k(D, nw, mm, 16 << 20);
+                        int64_t kps = (mm + sp - 1) / sp;
+                        kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
+                        return std::make_pair((int32_t)((mm + kps - 1) / kps), (int32_t)kps);
+                    };
+                    const auto spa = hsplits(ma), spb = hsplits(mb);
+                    cb.splits_a = spa.first;
+                    cb.splits_b = spb.first;
+                    cb.h_buf = new_buf((int64_t)(spa.first + spb.first) * D * nw * 8, BUF_BWD, 0);
+                    cb.na_buf = new_buf(D * D * w, BUF_BWD, 0);
+                    cb.nb_buf = new_buf(D * D * w, BUF_BWD, 0);
+                    cb.work_buf = new_buf((9 * D * D + 6 * D * nw + 8 * D + 64) * 8, BUF_BWD, 0);
+                    P->cbwd.push_back(cb);
+                    auto hgemm = [&](int32_t tbuf, const ViewSpec& vt, int32_t gbuf, const ViewSpec& vg, int64_t mm,
+                                     std::pair<int32_t, int32_t> sp, int32_t s_t, int32_t s_g, int64_t off) {
+                        BStep g;
+                        g.kind = BS_GEMM;
+                        g.level = 1;
+                        g.partial = 1;
+                        g.a_buf = tbuf;
+                        g.b_buf = gbuf;
+                        g.c_buf = cb.h_buf;
+                        g.c_off = off;
+                        g.va = vt;
+                        g.vb = vg;
+                        g.M = D;
+                        g.N = nw;
+                        g.K = mm;
+                        g.splits = sp.first;
+                        g.k_per_split = sp.second;
+                        g.scale_a = s_t;
+                        g.scale_b = s_g;
+                        g.flops = 2.0 * (double)D * nw * mm;
+                        g.bytes = (double)w * (double)mm * (D + nw);
+                        op.steps.push_back(g);
+                    };
+                    // H_A = A^T G_a / (s_A s_a'),  H_B = B G_b^T / (s_B s_b')
+                    hgemm(Ta.buf, tensor_view(Ta, shared, free_a, E), adj_of(c.a_ver_out), ga, ma, spa, va,
+                          c.a_ver_out, 0);
+                    hgemm(Tb.buf, tensor_view(Tb, shared, free_b, E), adj_of(c.b_ver_out), gbt, mb, spb, vb,
+                          c.b_ver_out, (int64_t)spa.first * D * nw * 8);
+                    // first terms: A_bar = G_a P_L^T / s_a',  B_bar = P_R^T G_b / s_b'
+                    bwd_gemm(op, 1, adj_of(c.a_ver_out), c.pl_buf, adj_of(va), ga, dense_view_t(D, nw), out_a, ma, D,
+                             nw, c.a_ver_out, -1, 0, false);
+                    bwd_gemm(op, 1, c.pr_buf, adj_of(c.b_ver_out), adj_of(vb), dense_view_t(nw, D), gb, out_b, D, mb,
+                             nw, -1, c.b_ver_out, 0, false);
+                    BStep core_b;
+                    core_b.kind = BS_CORE_BWD;
+                    core_b.level = 2;
+                    core_b.comp = comp_id;
+                    {
+                        const double r = (double)std::min(ka, kb);
+                        core_b.flops = 2.0 * D * r * (double)(ka + kb) + 4.0 * D * r * r + 4.0 * D * D * r;
+                    }
+                    op.steps.push_back(core_b);
+                    // second terms, accumulated: A_bar += A N_A / s_A,  B_bar += N_B B / s_B
+                    bwd_gemm(op, 3, Ta.buf, cb.na_buf, adj_of(va), tensor_view(Ta, free_a, shared, E),
+                             dense_view(D, D), out_a, ma, D, D, va, -1, 1, false);
+                    bwd_gemm(op, 3, cb.nb_buf, Tb.buf, adj_of(vb), dense_view(D, D), tensor_view(Tb, shared, free_b, E),
+                             out_b, D, mb, D, -1, vb, 1, false);
+                    op.done[0] = op.done[1] = 3;
+                    bops.push_back(op);
+                }
             } else {
                 P->tens.push_back(Ta2);
                 live[a] = (int32_t)P->tens.size() - 1;
@@ -469,6 +658,11 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
     P->n_levels = maxl;
     for (auto& b : P->bufs)
         if (b.kind == BUF_INPUT) b.hi = INT_MAX;
+    if (o.grad) {
+        // the reverse pass reads every tensor version, core workspace and projector
+        for (auto& b : P->bufs)
+            if (b.kind == BUF_TENSOR || b.kind == BUF_WORK || b.kind == BUF_PROJ) b.hi = INT_MAX;
+    }
     // the final tensor is read by the result kernel after the last level
     P->bufs[P->tens[last].buf].hi = INT_MAX;
 
@@ -477,6 +671,7 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
     std::vector<int32_t> persistent;
     for (int32_t b = 0; b < (int32_t)P->bufs.size(); ++b) {
         Buf& B = P->bufs[b];
+        if (B.kind == BUF_BWD) continue;
         starts[std::min(B.lo, maxl)].push_back(b);
         if (B.hi != INT_MAX) ends[std::min(B.hi, maxl)].push_back(b);
     }
@@ -528,6 +723,40 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
         for (int32_t b : starts[L]) P->bufs[b].off = alloc(P->bufs[b].bytes);
         if (!o.keep)
             for (int32_t b : ends[L]) release(P->bufs[b].off, P->bufs[b].bytes);
+    }
+    // ---------------------------------------------------------- reverse pass: levels and buffers
+    if (o.grad) {
+        adj_of(last);
+        std::vector<int32_t> ready(P->tens.size(), 0);
+        BStep seed;
+        seed.kind = BS_SEED;
+        seed.level = 1;
+        P->bsteps.push_back(seed);
+        ready[last] = 1;
+        int32_t maxb = 1;
+        for (auto it = bops.rbegin(); it != bops.rend(); ++it) {
+            int32_t L0 = 0;
+            for (int32_t v : it->outs)
+                if (v >= 0) L0 = std::max(L0, ready[v]);
+            for (BStep st : it->steps) {
+                st.level += L0;
+                if (st.kind == BS_CORE_BWD) st.comp = it->comp;
+                maxb = std::max(maxb, st.level);
+                P->bsteps.push_back(st);
+            }
+            for (int t = 0; t < 2; ++t)
+                if (it->ins[t] >= 0) ready[it->ins[t]] = L0 + it->done[t];
+        }
+        P->n_blevels = maxb;
+        for (auto& b : P->bufs)
+            if (b.kind == BUF_BWD) {
+                b.off = top;
+                top += align_up(b.bytes);
+            }
+        for (auto& st : P->bsteps) {
+            P->bwd_flops += st.flops;
+            P->bwd_bytes += st.bytes;
+        }
     }
     P->arena_bytes = top;
 

@@ -31,6 +31,7 @@ struct TreeOpts {
     int32_t jacobi_max_sweeps = 40;
     int64_t budget = 0;
     int32_t keep = 0;               // never reuse arena memory
+    int32_t grad = 0;               // plan the reverse pass too
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).
@@ -38,7 +39,7 @@ struct OpRec {
     int64_t kind, a, b, out, m, n, k, new_dim;
 };
 
-enum BufKind { BUF_INPUT = 0, BUF_TENSOR, BUF_GRAM, BUF_FACTOR, BUF_WORK, BUF_PROJ };
+enum BufKind { BUF_INPUT = 0, BUF_TENSOR, BUF_GRAM, BUF_FACTOR, BUF_WORK, BUF_PROJ, BUF_BWD };
 
 struct Buf {
     int64_t bytes = 0;
@@ -101,6 +102,35 @@ struct Compression {
 constexpr int64_t kLanczosMinD = 65;
 constexpr int64_t kLanczosMaxRowsPerD = 256;
 
+// One step of the reverse pass (levels count from the seed of the final scalar).
+enum BStepKind { BS_GEMM = 0, BS_REDUCE, BS_CORE_BWD, BS_SEED };
+
+struct BStep {
+    int32_t kind = BS_GEMM;
+    int32_t level = 0;
+    // BS_GEMM: C(view vc) = [C +] f * A(view va) . B(view vb), f = 1/(s[scale_a] s[scale_b]);
+    //          partial: split-K float64 partials (dense M x N per split) into c_buf instead
+    // BS_REDUCE: C(view vc) = f * sum over splits of a_buf (float64 partials, dense M x N)
+    int32_t a_buf = -1, b_buf = -1, c_buf = -1;   // arena buffers (forward ones or reverse-pass ones)
+    int64_t c_off = 0;                             // byte offset of C inside c_buf
+    int32_t scale_a = -1, scale_b = -1;
+    int32_t accumulate = 0, partial = 0;
+    int32_t splits = 1, k_per_split = 0;
+    int64_t M = 0, N = 0, K = 0;
+    ViewSpec va, vb, vc;
+    // BS_CORE_BWD
+    int32_t comp = -1;
+    double flops = 0, bytes = 0;
+};
+
+// Reverse-pass buffers of one compression.
+struct CompBwd {
+    int32_t h_buf = -1;             // H_A partials then H_B partials (float64, D x chi' each)
+    int32_t splits_a = 1, splits_b = 1;
+    int32_t na_buf = -1, nb_buf = -1;   // N_A, N_B (D x D, compute precision)
+    int32_t work_buf = -1;          // core-space workspace (float64)
+};
+
 struct Plan {
     GraphSpec g;
     TreeOpts opts;
@@ -115,6 +145,12 @@ struct Plan {
     int64_t max_parts = 0;              // per-level per-tile max slots needed
     double fwd_flops = 0, fwd_bytes = 0;
     int32_t elem_size = 8;
+    // reverse pass (opts.grad)
+    std::vector<int32_t> adj_buf;       // per tensor version: its adjoint (compute precision)
+    std::vector<BStep> bsteps;
+    std::vector<CompBwd> cbwd;
+    int32_t n_blevels = 0;
+    double bwd_flops = 0, bwd_bytes = 0;
 };
 
 // Validate the graph (returns "" or an error message).
