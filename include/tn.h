@@ -181,6 +181,23 @@ tn_status tn_grad(tn_ctx* ctx, double* dlnz_ddata);
  * entries, caller owned) on the context's stream without synchronising. */
 tn_status tn_grad_device(tn_ctx* ctx, void* dlnz_ddata_dev);
 
+/* Block the host until all work enqueued on the context's stream has finished. */
+tn_status tn_sync(tn_ctx* ctx);
+
+/* Ising model of SI F.1 on the loaded graph (every edge of dimension 2):
+ * writes the input tensors for couplings J (device float64, one per edge,
+ * beta*J_e != 0) into the context, as tn_update_values would.  Each edge's
+ * Boltzmann matrix exp(beta J s s') is split as W_lo W_hi with
+ * W = H diag(sqrt(cosh beta J), +-sqrt|sinh beta J|) H / sqrt 2 (the sign of
+ * sinh on the higher vertex id), and T_v = sum_x prod over v's edges of W[x, :]
+ * (axes in ascending edge id).  Runs on the context's stream. */
+tn_status tn_ising_values_device(tn_ctx* ctx, double beta, const void* J_dev);
+
+/* Chain rule of the map above: d ln|Z| / d J (device float64, n_edges) from
+ * d ln|Z| / d data (device float64, e.g. tn_grad_device's output). */
+tn_status tn_ising_coupling_grad_device(tn_ctx* ctx, double beta, const void* J_dev, const void* dlnz_ddata_dev,
+                                        void* dlnz_dJ_dev);
+
 /* Backward-plan totals for opts.grad = 1: algorithmic flops and bytes of the
  * reverse pass, its number of levels. */
 tn_status tn_grad_info(const tn_ctx* ctx, double* bwd_flops, double* bwd_bytes, int32_t* n_levels);

@@ -66,6 +66,9 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_grad": ([P, pD], C.c_int),
         "tn_grad_device": ([P, P], C.c_int),
         "tn_grad_info": ([P, pD, pD, pI32], C.c_int),
+        "tn_ising_values_device": ([P, D, P], C.c_int),
+        "tn_sync": ([P], C.c_int),
+        "tn_ising_coupling_grad_device": ([P, D, P, P, P], C.c_int),
         "tn_read_tensor": ([P, I32, pD, I64, pI64], C.c_int),
         "tn_profile": ([P, C.c_uint32], C.c_int),
         "tn_profile_read": ([P, I32, pD, pI64, pD, pD], C.c_int),
@@ -84,7 +87,8 @@ def exported_symbols() -> List[str]:
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
             "tn_update_values_device", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
-            "tn_grad_device", "tn_grad_info", "tn_plan_describe"]
+            "tn_grad_device", "tn_grad_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
+            "tn_plan_describe"]
 
 
 def _i32(a) -> np.ndarray:
@@ -238,6 +242,16 @@ class Context:
 
     def tn_grad_device(self, dev_ptr: int) -> None:
         self._check(self._lib.tn_grad_device(self._h, C.c_void_p(dev_ptr)))
+
+    def tn_sync(self) -> None:
+        self._check(self._lib.tn_sync(self._h))
+
+    def tn_ising_values_device(self, beta: float, J_ptr: int) -> None:
+        self._check(self._lib.tn_ising_values_device(self._h, float(beta), C.c_void_p(J_ptr)))
+
+    def tn_ising_coupling_grad_device(self, beta: float, J_ptr: int, dT_ptr: int, dJ_ptr: int) -> None:
+        self._check(self._lib.tn_ising_coupling_grad_device(self._h, float(beta), C.c_void_p(J_ptr),
+                                                            C.c_void_p(dT_ptr), C.c_void_p(dJ_ptr)))
 
     def tn_grad_info(self) -> dict:
         f, b, n = C.c_double(), C.c_double(), C.c_int32()

@@ -43,6 +43,11 @@ struct tn_ctx {
 
     GraphSpec g;
     bool has_graph = false;
+    // Ising coupling map (graphs whose edges all have dimension 2)
+    bool ising_ok = false;
+    IsingGraph ising{};
+    int32_t* d_ising_i32 = nullptr;     // inc_off | inc_edge | edge_u | edge_v
+    int64_t* d_ising_off = nullptr;
     int64_t n_input_elems = 0;
     double* d_staging = nullptr;
 
@@ -654,6 +659,8 @@ void tn_destroy(tn_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_plan(c);
     dfree(c->d_staging);
+    dfree(c->d_ising_i32);
+    dfree(c->d_ising_off);
     dfree(c->d_result);
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -688,6 +695,40 @@ tn_status tn_load_graph(tn_ctx* c, int32_t n_tensors, int32_t n_edges, const int
     dfree(c->d_staging);
     HIP_TRY(c, hipMalloc((void**)&c->d_staging, std::max<int64_t>(1, c->n_input_elems) * sizeof(double)));
     HIP_TRY(c, hipMemcpy(c->d_staging, data, c->n_input_elems * sizeof(double), hipMemcpyHostToDevice));
+    // incidence lists for the Ising coupling map (only when every edge has dimension 2)
+    dfree(c->d_ising_i32);
+    dfree(c->d_ising_off);
+    c->ising_ok = std::all_of(g.ed.begin(), g.ed.end(), [](int32_t d) { return d == 2; });
+    if (c->ising_ok) {
+        std::vector<std::vector<int32_t>> inc(g.n);
+        for (int e = 0; e < g.ne; ++e) {
+            inc[g.eu[e]].push_back(e);
+            inc[g.ev[e]].push_back(e);
+        }
+        std::vector<int32_t> h;
+        h.reserve(g.n + 1 + 4 * (size_t)g.ne);
+        int32_t acc = 0;
+        for (int v = 0; v < g.n; ++v) {
+            h.push_back(acc);
+            acc += (int32_t)inc[v].size();
+        }
+        h.push_back(acc);
+        for (int v = 0; v < g.n; ++v) h.insert(h.end(), inc[v].begin(), inc[v].end());
+        h.insert(h.end(), g.eu.begin(), g.eu.end());
+        h.insert(h.end(), g.ev.begin(), g.ev.end());
+        HIP_TRY(c, hipMalloc((void**)&c->d_ising_i32, h.size() * sizeof(int32_t)));
+        HIP_TRY(c, hipMemcpy(c->d_ising_i32, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMalloc((void**)&c->d_ising_off, g.offsets.size() * sizeof(int64_t)));
+        HIP_TRY(c, hipMemcpy(c->d_ising_off, g.offsets.data(), g.offsets.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice));
+        c->ising.inc_off = c->d_ising_i32;
+        c->ising.inc_edge = c->d_ising_i32 + g.n + 1;
+        c->ising.edge_u = c->ising.inc_edge + 2 * g.ne;
+        c->ising.edge_v = c->ising.edge_u + g.ne;
+        c->ising.data_off = c->d_ising_off;
+        c->ising.n = g.n;
+        c->ising.ne = g.ne;
+    }
     return TN_OK;
 }
 
@@ -985,6 +1026,36 @@ tn_status tn_grad(tn_ctx* c, double* dlnz_ddata) {
         c->prof_ms[u.first] += ms;
     }
     c->ev_used.clear();
+    return TN_OK;
+}
+
+tn_status tn_sync(tn_ctx* c) {
+    if (!c) return TN_EINVAL;
+    (void)hipSetDevice(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return TN_OK;
+}
+
+tn_status tn_ising_values_device(tn_ctx* c, double beta, const void* J_dev) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_graph) return fail(c, TN_ESTATE, "no graph loaded");
+    if (!c->ising_ok) return fail(c, TN_EINVAL, "the Ising map needs every edge of dimension 2");
+    if (!J_dev) return fail(c, TN_EINVAL, "null couplings");
+    (void)hipSetDevice(c->device);
+    HIP_TRY(c, launch_ising_values(c->ising, beta, (const double*)J_dev, c->d_staging, c->n_input_elems, c->stream));
+    c->evaluated = false;
+    return TN_OK;
+}
+
+tn_status tn_ising_coupling_grad_device(tn_ctx* c, double beta, const void* J_dev, const void* dlnz_ddata_dev,
+                                        void* dlnz_dJ_dev) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_graph) return fail(c, TN_ESTATE, "no graph loaded");
+    if (!c->ising_ok) return fail(c, TN_EINVAL, "the Ising map needs every edge of dimension 2");
+    if (!J_dev || !dlnz_ddata_dev || !dlnz_dJ_dev) return fail(c, TN_EINVAL, "null device buffer");
+    (void)hipSetDevice(c->device);
+    HIP_TRY(c, launch_ising_grad(c->ising, beta, (const double*)J_dev, (const double*)dlnz_ddata_dev,
+                                 (double*)dlnz_dJ_dev, c->stream));
     return TN_OK;
 }
 

@@ -196,6 +196,16 @@ struct InputDesc {
     int32_t pad;
 };
 
+// Ising model on a graph whose edges all have dimension 2 (coupling map and its adjoint).
+struct IsingGraph {
+    const int32_t* inc_off;      // n+1 offsets into inc_edge
+    const int32_t* inc_edge;     // incident edges of each vertex, ascending (= its axis order)
+    const int32_t* edge_u;       // lower endpoint of each edge
+    const int32_t* edge_v;
+    const int64_t* data_off;     // n+1 element offsets of the tensors
+    int32_t n, ne;
+};
+
 // Per-tensor scale finalisation: s = max over the tensor's per-tile maxima.
 struct ScaleDesc {
     int32_t maxpart;             // first per-tile max slot

@@ -1481,7 +1481,8 @@ hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t to
 // ------------------------------------------------------------------------------------------
 // Reverse pass
 // ------------------------------------------------------------------------------------------
-// C(view) = f * sum of split-K partials, converted to the compute precision.
+// C(view) = f * sum of split-K partials, converted to the compute precision (the partial GEMM
+// normally carries the factor already, and f = 1).
 template <typename Tout>
 __global__ __launch_bounds__(256) void reduce_grouped(const ReduceDesc* __restrict__ descs, int ndesc,
                                                       const double* __restrict__ scales, int64_t total) {
@@ -1688,6 +1689,99 @@ __global__ void grad_inputs_kernel(const InputDesc* __restrict__ descs, int n, c
     const Tp* x = (const Tp*)d.dst;
     const double inv = 1.0 / scales[d.tensor];
     for (int64_t i = lane; i < d.count; i += 64) out[d.src_off + i] = (double)x[i] * inv;
+}
+
+// ------------------------------------------------------------------------------------------
+// Ising couplings (SI F.1): T_v[s_1..s_d] = sum_x prod_k W^(e_k)[x, s_k], with the bond matrix
+// exp(beta J s s') split as W_lo W_hi, W = H diag(sqrt c, +-sqrt|sh|) H / sqrt 2, c = cosh(beta J),
+// sh = sinh(beta J), the sign of sinh on the higher vertex id; so W[x][s] = (d0 + (x == s ? d1 : -d1)) / sqrt 2.
+// ------------------------------------------------------------------------------------------
+__device__ inline void ising_factor(double beta, double J, bool hi, bool deriv, double* w) {
+    const double x = beta * J, c = cosh(x), sh = sinh(x);
+    const double sg = sh < 0.0 ? -1.0 : 1.0;
+    double d0, d1;
+    if (!deriv) {
+        d0 = sqrt(c);
+        d1 = (hi ? sg : 1.0) * sqrt(fabs(sh));
+    } else {   // d/dJ of (sqrt c, +-sqrt|sh|)
+        d0 = beta * sh / (2.0 * sqrt(c));
+        d1 = (hi ? 1.0 : sg) * beta * c / (2.0 * sqrt(fabs(sh)));
+    }
+    const double r = 0.70710678118654752440;   // 1 / sqrt 2
+    w[0] = (d0 + d1) * r;   // [x][s] with x == s
+    w[1] = (d0 - d1) * r;   // x != s
+}
+
+// One thread per tensor entry.
+__global__ void ising_values_kernel(IsingGraph g, double beta, const double* __restrict__ J, double* __restrict__ data,
+                                    int64_t total) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = g.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.data_off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const int v = lo;
+    const int b = g.inc_off[v], d = g.inc_off[v + 1] - b;
+    const int64_t idx = e - g.data_off[v];
+    double acc = 0.0;
+    for (int x = 0; x < 2; ++x) {
+        double p = 1.0;
+        for (int k = 0; k < d; ++k) {
+            const int ed = g.inc_edge[b + k];
+            const int s = (int)((idx >> (d - 1 - k)) & 1);
+            double w[2];
+            ising_factor(beta, J[ed], g.edge_v[ed] == v, false, w);
+            p *= (x == s) ? w[0] : w[1];
+        }
+        acc += p;
+    }
+    data[e] = acc;
+}
+
+// d ln|Z| / d J_e = sum over both ends v of sum_s (d ln|Z| / d T_v[s]) (d T_v[s] / d J_e); one thread per edge.
+__global__ void ising_grad_kernel(IsingGraph g, double beta, const double* __restrict__ J,
+                                  const double* __restrict__ dT, double* __restrict__ dJ) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.ne) return;
+    double total = 0.0;
+    for (int end = 0; end < 2; ++end) {
+        const int v = end == 0 ? g.edge_u[e] : g.edge_v[e];
+        const int b = g.inc_off[v], d = g.inc_off[v + 1] - b;
+        const double* gv = dT + g.data_off[v];
+        for (int64_t idx = 0; idx < ((int64_t)1 << d); ++idx) {
+            double acc = 0.0;
+            for (int x = 0; x < 2; ++x) {
+                double p = 1.0;
+                for (int k = 0; k < d; ++k) {
+                    const int ed = g.inc_edge[b + k];
+                    const int s = (int)((idx >> (d - 1 - k)) & 1);
+                    double w[2];
+                    ising_factor(beta, J[ed], g.edge_v[ed] == v, ed == e, w);
+                    p *= (x == s) ? w[0] : w[1];
+                }
+                acc += p;
+            }
+            total += gv[idx] * acc;
+        }
+    }
+    dJ[e] = total;
+}
+
+hipError_t launch_ising_values(const IsingGraph& g, double beta, const double* J, double* data, int64_t total,
+                               hipStream_t s) {
+    if (total == 0) return hipSuccess;
+    ising_values_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(g, beta, J, data, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, const double* dlnz_ddata,
+                             double* dlnz_dJ, hipStream_t s) {
+    if (g.ne == 0) return hipSuccess;
+    ising_grad_kernel<<<(g.ne + 127) / 128, 128, 0, s>>>(g, beta, J, dlnz_ddata, dlnz_dJ);
+    return hipGetLastError();
 }
 
 size_t core_lds_bytes(int max_d) { return (size_t)4 * max_d * max_d * sizeof(double); }

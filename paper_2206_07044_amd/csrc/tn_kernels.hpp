@@ -38,6 +38,10 @@ hipError_t launch_seed(int f32, const void* final_ptr, void* adj_final, const do
                        hipStream_t s);
 hipError_t launch_grad_inputs(int f32, const InputDesc* descs, int n, const double* scales, double* out,
                               hipStream_t s);
+hipError_t launch_ising_values(const IsingGraph& g, double beta, const double* J, double* data, int64_t total,
+                               hipStream_t s);
+hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, const double* dlnz_ddata,
+                             double* dlnz_dJ, hipStream_t s);
 hipError_t launch_result(int f32, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
                          int n_comp, double* result, hipStream_t s);
 

@@ -270,8 +270,8 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
             r.M = M;
             r.N = N;
             r.splits = g.splits;
-            r.scale_a = sa;
-            r.scale_b = sb;
+            r.scale_a = -1;   // the partials already carry the factor
+            r.scale_b = -1;
             r.bytes = 8.0 * g.splits * M * N + (double)w * M * N;
             op.steps.push_back(g);
             op.steps.push_back(r);

@@ -68,6 +68,9 @@ def _cases():
     J4 = np.where(np.random.default_rng(9).random(g4.n_edges) < 0.5, -1.0, 1.0)
     yield "pmJ-4x4x4-chi4", g4, ising_tensors(g4, 0.5, J4), sweep_tree((4, 4, 4)), 4
     yield "normal-4x4x4-chi6", g4, normal_tensors(g4, 0.3, seed=3), sweep_tree((4, 4, 4)), 6
+    g6 = lattice((6, 6, 6))      # long reductions: split-K contraction adjoints
+    J6 = np.where(np.random.default_rng(0).random(g6.n_edges) < 0.5, -1.0, 1.0)
+    yield "pmJ-6x6x6-chi8", g6, ising_tensors(g6, 0.5, J6), sweep_tree((6, 6, 6)), 8
 
 
 CASES = list(_cases())
