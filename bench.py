@@ -70,6 +70,21 @@ def op_flops(op) -> float:
     return f
 
 
+def roofline_of(kind, prof, avg_ms, launches, precision):
+    """Bound, unit, peak and achieved rate of one kernel kind (algorithmic work / time)."""
+    per_s = 1.0 / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+    if kind == "gemm":
+        peak = PEAKS["fp32_TFLOPs"] if precision == "fp32" else PEAKS["fp64_TFLOPs"]
+        return "mfma", "TFLOP/s", peak, prof["flops"] / launches * per_s / 1e12
+    if kind == "gram":   # Gram matrices accumulate on float64 MFMA in both precisions
+        return "mfma", "TFLOP/s", PEAKS["fp64_TFLOPs"], prof["flops"] / launches * per_s / 1e12
+    if kind in ("core_lds", "core_global", "lanczos"):
+        # per-compression SVD kernels: float64 vector arithmetic, one workgroup per compression;
+        # peak = 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2 (dual issue) x 2.4 GHz = 78.6 TFLOP/s
+        return "alu", "TFLOP/s", PEAKS["fp64_TFLOPs"], prof["flops"] / launches * per_s / 1e12
+    return "hbm", "GB/s", PEAKS["hbm_GBps"], prof["bytes"] / launches * per_s / 1e9
+
+
 def cpu_baseline(g, T, pairs, chi, total_flops, budget_s):
     """The CPU oracle on a bounded prefix of the same tree, scaled to trees/s."""
     import oracle
@@ -107,6 +122,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--fwd-bwd-steps", type=int, default=1, help="timed forward+reverse passes (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -151,25 +167,10 @@ def main() -> int:
     trees_per_s = args.steps / dt
     ms_per_step = dt * 1e3 / args.steps
 
-    # roofline of the dominant kernel (algorithmic work / measured launch time)
+    # roofline of the dominant kernel (algorithmic work per launch / measured launch time)
     launches = max(1, prof["launches"])
     avg_ms = prof["ms"] / launches
-    if dominant in ("gemm",):
-        bound, unit = "mfma", "TFLOP/s"
-        peak = PEAKS["fp32_TFLOPs"] if args.precision == "fp32" else PEAKS["fp64_TFLOPs"]
-        achieved = (prof["flops"] / launches) / (avg_ms * 1e-3) / 1e12
-    elif dominant == "gram":
-        bound, unit = "mfma", "TFLOP/s"
-        peak = PEAKS["fp64_TFLOPs"]   # Gram matrices accumulate on float64 MFMA in both modes
-        achieved = (prof["flops"] / launches) / (avg_ms * 1e-3) / 1e12
-    elif dominant in ("core_lds", "core_global"):
-        bound, unit = "alu", "TFLOP/s"
-        peak = PEAKS["fp64_TFLOPs"]   # float64 vector ALU: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz x 2 (dual issue)
-        achieved = (prof["flops"] / launches) / (avg_ms * 1e-3) / 1e12
-    else:
-        bound, unit = "hbm", "GB/s"
-        peak = PEAKS["hbm_GBps"]
-        achieved = (prof["bytes"] / launches) / (avg_ms * 1e-3) / 1e9
+    bound, unit, peak, achieved = roofline_of(dominant, prof, avg_ms, launches, args.precision)
 
     out = {
         "metric": METRIC,
@@ -204,6 +205,13 @@ def main() -> int:
             "kernel_ms_per_step": {k: v["ms"] / max(1, args.warmup) for k, v in kinds.items()},
         },
     }
+    g_prof = kinds["gemm"]
+    if g_prof["launches"]:
+        gl = g_prof["launches"]
+        gb, gu, gp, ga = roofline_of("gemm", g_prof, g_prof["ms"] / gl, gl, args.precision)
+        out["contraction_roofline"] = {"kernel": "gemm", "bound": gb, "achieved": ga, "peak": gp, "unit": gu,
+                                       "frac": ga / gp, "avg_launch_ms": g_prof["ms"] / gl,
+                                       "launches_per_step": gl / max(1, args.warmup)}
 
     if not args.no_fp64_reference and args.precision != "fp64":
         ref = make_ctx("fp64")
@@ -222,6 +230,31 @@ def main() -> int:
         out["abs_dlnz_vs_fp64"] = abs(lnz - rl)
         out["rel_dlnz_vs_fp64"] = abs(lnz - rl) / abs(rl)
         ref.close()
+
+    if args.fwd_bwd_steps > 0:
+        # forward + reverse pass (d ln|Z| / d inputs) in the same precision, on a gradient plan
+        gctx = tn.Context(0, stream)
+        gctx.tn_load_graph(g.n, eu, ev, ed, off, data)
+        gctx.tn_set_tree(pi, pj, args.chi, precision=args.precision, grad=True)
+        ginfo = gctx.tn_plan_info()
+        gbi = gctx.tn_grad_info()
+        gctx.tn_contract_compressed()
+        gctx.tn_grad()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.fwd_bwd_steps):
+            gctx.tn_contract_compressed()
+            gg = gctx.tn_grad()
+        torch.cuda.synchronize()
+        gdt = (time.perf_counter() - t0) / args.fwd_bwd_steps
+        total_f = ginfo["fwd_flops"] + gbi["bwd_flops"]
+        euler = float(np.max(np.abs([float(np.dot(data[off[v]:off[v + 1]], gg[off[v]:off[v + 1]])) - 1.0
+                                     for v in range(g.n)])))
+        out["fwd_bwd"] = {"ms_per_step": gdt * 1e3, "trees_per_s": 1.0 / gdt, "tflops": total_f / gdt / 1e12,
+                          "fwd_flops": ginfo["fwd_flops"], "bwd_flops": gbi["bwd_flops"],
+                          "arena_bytes": ginfo["arena_bytes"], "max_euler_identity_error": euler,
+                          "steps": args.fwd_bwd_steps}
+        gctx.close()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, T, pairs, args.chi, info["fwd_flops"], args.cpu_seconds)
