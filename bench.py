@@ -33,6 +33,7 @@ PEAKS = {  # MI355X published dense peaks
     "hbm_GBps": 8000.0,
     "fp64_TFLOPs": 78.6,
     "fp32_TFLOPs": 157.3,
+    "bf16_TFLOPs": 2500.0,
 }
 
 
@@ -74,7 +75,7 @@ def roofline_of(kind, prof, avg_ms, launches, precision):
     """Bound, unit, peak and achieved rate of one kernel kind (algorithmic work / time)."""
     per_s = 1.0 / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
     if kind == "gemm":
-        peak = PEAKS["fp32_TFLOPs"] if precision == "fp32" else PEAKS["fp64_TFLOPs"]
+        peak = {"fp32": PEAKS["fp32_TFLOPs"], "bf16": PEAKS["bf16_TFLOPs"], "fp64": PEAKS["fp64_TFLOPs"]}[precision]
         return "mfma", "TFLOP/s", peak, prof["flops"] / launches * per_s / 1e12
     if kind == "gram":   # Gram matrices accumulate on float64 MFMA in both precisions
         return "mfma", "TFLOP/s", PEAKS["fp64_TFLOPs"], prof["flops"] / launches * per_s / 1e12
@@ -116,7 +117,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chi", type=int, default=16)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--shape", default="12,12,12")
     ap.add_argument("--beta", type=float, default=0.22)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -183,15 +184,17 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"ising-cubic-{'x'.join(map(str, shape))}-beta{args.beta}-chi{args.chi}-span-sweep",
             "lattice": list(shape), "beta": args.beta, "chi": args.chi, "batch": 1,
             "tree": "Span family, axis-ordered spanning tree swept leaves-inwards",
             "compression": "early, gauge distance r=0",
-            "precision": ("float32 tensors/contractions on MFMA; float64 Gram, core SVD, projectors, exponent"
-                          if args.precision == "fp32" else "float64 throughout"),
+            "precision": {"fp32": "float32 tensors/contractions on MFMA; float64 Gram, core SVD, exponent",
+                          "bf16": "bfloat16 tensors, bf16 MFMA with float32 accumulation; float64 Gram, core SVD, "
+                                  "exponent",
+                          "fp64": "float64 throughout"}[args.precision],
             "flops_per_tree": info["fwd_flops"],
             "tflops_fwd": info["fwd_flops"] * trees_per_s / 1e12,
             "arena_bytes": info["arena_bytes"],

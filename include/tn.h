@@ -46,7 +46,9 @@ typedef enum {
     TN_FP64 = 0,      /* tensors, contractions and re-absorptions in float64 */
     TN_FP32 = 1,      /* tensors and contractions in float32 on MFMA; Gram, core SVD,
                          projectors and scale exponents in float64 */
-    TN_BF16 = 2       /* reserved: bfloat16 tensor storage, float32 accumulation */
+    TN_BF16 = 2       /* tensors and projectors stored in bfloat16, contractions on bf16 MFMA with
+                         float32 accumulation (rounded to bfloat16 on store); Gram, core SVD and
+                         scale exponents in float64 */
 } tn_precision;
 
 typedef struct {

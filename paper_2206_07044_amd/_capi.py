@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtn.so")
 TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO = range(7)
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ESTATE", 3: "TN_ENOMEM", 4: "TN_EDEVICE",
                 5: "TN_ENUMERIC", 6: "TN_ZERO"}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 KERNEL_KINDS = {"gemm": 0, "gram": 1, "copy": 2, "core_lds": 3, "core_global": 4, "scale": 5, "lanczos": 6,
                 "bwd_gemm": 7, "bwd_core": 8}
 

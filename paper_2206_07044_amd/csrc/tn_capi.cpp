@@ -21,7 +21,7 @@ enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_
 
 struct Launch {
     int kind = 0;
-    int key = 0;          // GEMM dtype key / COPY source f32 / CORE lds flag
+    int key = 0;          // GEMM instantiation / tensor precision / CORE lds flag
     int64_t begin = 0;    // first descriptor
     int count = 0;
     int64_t work = 0;     // tiles / elements
@@ -106,6 +106,11 @@ struct tn_ctx {
 
 namespace {
 
+// GEMM instantiation for tensor operands (contractions, re-absorptions, adjoints) and for
+// Gram / float64-partial outputs, by tensor precision (0 float64, 1 float32, 2 bfloat16).
+int tensor_key(int prec) { return prec == 0 ? GEMM_F64 : prec == 1 ? GEMM_F32 : GEMM_BF16; }
+int wide_key(int prec) { return prec == 0 ? GEMM_F64 : prec == 1 ? GEMM_F32_TO_F64 : GEMM_BF16_TO_F64; }
+
 tn_status fail(tn_ctx* c, tn_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;
@@ -175,7 +180,7 @@ std::string fill_view(const ViewSpec& s, View* v) { return make_view(s, v); }
 // Turn the plan's levelled steps into grouped launch descriptors.
 tn_status build_launches(tn_ctx* c) {
     Plan& P = c->plan;
-    const bool f32 = P.opts.precision == 1;
+    const int prec = P.opts.precision;
     char* base = c->arena;
     auto buf_ptr = [&](int32_t b) -> char* { return base + P.bufs[b].off; };
     auto ten_ptr = [&](int32_t t) -> char* { return buf_ptr(P.tens[t].buf); };
@@ -220,7 +225,7 @@ tn_status build_launches(tn_ctx* c) {
                     g.k_per_split = st.k_per_split;
                     g.scale_a = st.in_a;
                     g.square_a = 1;
-                    key = 2 * (f32 ? GEMM_F32_TO_F64 : GEMM_F64) + 1;
+                    key = 2 * wide_key(prec) + 1;
                 } else {
                     g.mode = GEMM_TENSOR;
                     g.splits = 1;
@@ -247,7 +252,7 @@ tn_status build_launches(tn_ctx* c) {
                     sd.tensor = st.out_t;
                     scales.push_back(sd);
                     parts += sd.nparts;
-                    key = 2 * (f32 ? GEMM_F32 : GEMM_F64);
+                    key = 2 * tensor_key(prec);
                 }
                 gemms[key].push_back(g);
                 gemm_work[key].first += st.flops;
@@ -369,7 +374,7 @@ tn_status build_launches(tn_ctx* c) {
         if (!copies.empty()) {
             Launch l;
             l.kind = L_COPY;
-            l.key = f32 ? 1 : 0;
+            l.key = prec;
             l.prof = TN_KERNEL_COPY;
             l.flops = copy_work.first;
             l.bytes = copy_work.second;
@@ -404,7 +409,7 @@ tn_status build_launches(tn_ctx* c) {
         if (!lanczos.empty()) {
             Launch l;
             l.kind = L_LANCZOS;
-            l.key = f32 ? 1 : 0;
+            l.key = prec;
             l.prof = TN_KERNEL_LANCZOS;
             l.begin = (int64_t)c->h_lanczos.size();
             l.count = (int)lanczos.size();
@@ -417,7 +422,7 @@ tn_status build_launches(tn_ctx* c) {
         if (!glanczos.empty()) {
             Launch l;
             l.kind = L_GLANCZOS;
-            l.key = f32 ? 1 : 0;
+            l.key = prec;
             l.prof = TN_KERNEL_LANCZOS;
             l.begin = (int64_t)c->h_glanczos.size();
             l.count = (int)glanczos.size();
@@ -467,7 +472,7 @@ tn_status build_launches(tn_ctx* c) {
 // Reverse-pass launches, grouped by level like the forward ones.
 tn_status build_bwd_launches(tn_ctx* c) {
     Plan& P = c->plan;
-    const bool f32 = P.opts.precision == 1;
+    const int prec = P.opts.precision;
     char* base = c->arena;
     auto buf_ptr = [&](int32_t b) -> char* { return base + P.bufs[b].off; };
     std::vector<std::vector<int32_t>> by_level(P.n_blevels + 1);
@@ -502,7 +507,7 @@ tn_status build_bwd_launches(tn_ctx* c) {
                 g.scale_b = st.scale_b;
                 g.accumulate = st.accumulate;
                 g.mode = st.partial ? GEMM_GRAM : GEMM_ADJ;
-                const int key = st.partial ? (f32 ? GEMM_F32_TO_F64 : GEMM_F64) : (f32 ? GEMM_F32 : GEMM_F64);
+                const int key = st.partial ? wide_key(prec) : tensor_key(prec);
                 gemms[key].push_back(g);
                 gwork[key].first += st.flops;
                 gwork[key].second += st.bytes;
@@ -560,7 +565,7 @@ tn_status build_bwd_launches(tn_ctx* c) {
         if (!reds.empty()) {
             Launch l;
             l.kind = L_REDUCE;
-            l.key = f32 ? 1 : 0;
+            l.key = prec;
             l.prof = TN_KERNEL_BWD_GEMM;
             l.bytes = red_bytes;
             l.begin = (int64_t)c->h_reduce.size();
@@ -577,7 +582,7 @@ tn_status build_bwd_launches(tn_ctx* c) {
         if (!cores.empty()) {
             Launch l;
             l.kind = L_CORE_BWD;
-            l.key = f32 ? 1 : 0;
+            l.key = prec;
             l.prof = TN_KERNEL_BWD_CORE;
             l.flops = core_flops;
             l.begin = (int64_t)c->h_cbwd.size();
@@ -761,8 +766,8 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     if (!opts || (n_steps > 0 && (!pair_i || !pair_j))) return fail(c, TN_EINVAL, "missing tree arrays or options");
     if (opts->gauge_r != 0) return fail(c, TN_EINVAL, "gauge_r must be 0 (local compression only)");
     if (opts->compress_late != 0) return fail(c, TN_EINVAL, "compress_late must be 0 (early compression)");
-    if (opts->precision != TN_FP64 && opts->precision != TN_FP32)
-        return fail(c, TN_EINVAL, "precision must be TN_FP64 or TN_FP32");
+    if (opts->precision != TN_FP64 && opts->precision != TN_FP32 && opts->precision != TN_BF16)
+        return fail(c, TN_EINVAL, "precision must be TN_FP64, TN_FP32 or TN_BF16");
     if (!(opts->cutoff >= 0.0)) return fail(c, TN_EINVAL, "cutoff must be >= 0");
     (void)hipSetDevice(c->device);
     free_plan(c);
@@ -812,9 +817,9 @@ tn_status tn_enqueue(tn_ctx* c) {
     if (!c->has_plan) return fail(c, TN_ESTATE, "evaluate before tn_set_tree");
     (void)hipSetDevice(c->device);
     Plan& P = c->plan;
-    const bool f32 = P.opts.precision == 1;
+    const int prec = P.opts.precision;
     hipStream_t s = c->stream;
-    HIP_TRY(c, launch_inputs(f32, c->d_inputs, (int)c->h_inputs.size(), c->d_staging, c->d_scales, s));
+    HIP_TRY(c, launch_inputs(prec, c->d_inputs, (int)c->h_inputs.size(), c->d_staging, c->d_scales, s));
     for (const Launch& l : c->launches) {
         const bool timed = (c->prof_mask >> l.prof) & 1u;
         if (timed) {
@@ -838,7 +843,7 @@ tn_status tn_enqueue(tn_ctx* c) {
                 HIP_TRY(c, launch_copy(l.key, c->d_copy + l.begin, l.count, l.work, c->d_scales, s));
                 break;
             case L_CORE:
-                HIP_TRY(c, launch_core(l.key, f32, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
+                HIP_TRY(c, launch_core(l.key, prec, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
                                        c->d_disc, c->d_tie, c->d_sweeps, s));
                 break;
             case L_LANCZOS:
@@ -856,7 +861,7 @@ tn_status tn_enqueue(tn_ctx* c) {
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
     }
     const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
-    HIP_TRY(c, launch_result(f32, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
+    HIP_TRY(c, launch_result(prec, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
                              c->d_result, s));
     HIP_TRY(c, hipMemcpyAsync(c->h_result, c->d_result, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     return TN_OK;
@@ -967,10 +972,19 @@ tn_status tn_read_tensor(const tn_ctx* c0, int32_t index, double* out, int64_t c
     const char* src = c->arena + P.bufs[t.buf].off;
     if (P.elem_size == 8) {
         HIP_TRY(c, hipMemcpy(out, src, k * sizeof(double), hipMemcpyDeviceToHost));
-    } else {
+    } else if (P.elem_size == 4) {
         std::vector<float> tmp(k);
         HIP_TRY(c, hipMemcpy(tmp.data(), src, k * sizeof(float), hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < k; ++i) out[i] = tmp[i];
+    } else {   // bfloat16: the upper half of a binary32
+        std::vector<uint16_t> tmp(k);
+        HIP_TRY(c, hipMemcpy(tmp.data(), src, k * sizeof(uint16_t), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < k; ++i) {
+            const uint32_t u = (uint32_t)tmp[i] << 16;
+            float f;
+            std::memcpy(&f, &u, sizeof(f));
+            out[i] = f;
+        }
     }
     const double inv = s > 0.0 ? 1.0 / s : 0.0;
     for (int64_t i = 0; i < k; ++i) out[i] *= inv;
@@ -985,10 +999,10 @@ tn_status tn_grad_device(tn_ctx* c, void* out) {
     if (c->sign == 0.0) return fail(c, TN_ZERO, "Z = 0: ln|Z| has no gradient");
     (void)hipSetDevice(c->device);
     Plan& P = c->plan;
-    const bool f32 = P.opts.precision == 1;
+    const int prec = P.opts.precision;
     hipStream_t s = c->stream;
     const int fin = P.final_tensor;
-    HIP_TRY(c, launch_seed(f32, c->arena + P.bufs[P.tens[fin].buf].off, c->arena + P.bufs[P.adj_buf[fin]].off,
+    HIP_TRY(c, launch_seed(prec, c->arena + P.bufs[P.tens[fin].buf].off, c->arena + P.bufs[P.adj_buf[fin]].off,
                            c->d_scales, fin, s));
     for (const Launch& l : c->blaunches) {
         bool timed = false;
@@ -1007,7 +1021,7 @@ tn_status tn_grad_device(tn_ctx* c, void* out) {
         }
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
     }
-    HIP_TRY(c, launch_grad_inputs(f32, c->d_gin, (int)c->h_gin.size(), c->d_scales, (double*)out, s));
+    HIP_TRY(c, launch_grad_inputs(prec, c->d_gin, (int)c->h_gin.size(), c->d_scales, (double*)out, s));
     return TN_OK;
 }
 

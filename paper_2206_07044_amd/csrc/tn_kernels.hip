@@ -24,6 +24,24 @@ namespace tn {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// bfloat16 storage: the upper 16 bits of an IEEE binary32 (8 exponent, 7 fraction bits).
+// float -> bf16 rounds to nearest, ties to even; NaN stays NaN.
+struct bf16 {
+    uint16_t bits;
+    bf16() = default;
+    __device__ explicit bf16(float f) : bits(round(f)) {}
+    __device__ explicit bf16(double d) : bits(round((float)d)) {}
+    __device__ explicit bf16(int i) : bits(round((float)i)) {}
+    __device__ explicit operator float() const { return __uint_as_float((uint32_t)bits << 16); }
+    __device__ explicit operator double() const { return (double)__uint_as_float((uint32_t)bits << 16); }
+    __device__ static uint16_t round(float f) {
+        const uint32_t u = __float_as_uint(f);
+        if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    }
+};
 
 template <typename Tc>
 struct Mma;
@@ -33,6 +51,7 @@ struct Mma;
 template <>
 struct Mma<double> {
     using acc = v4d;
+    static constexpr int kK = 4;
     __device__ static inline acc run(double a, double b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -41,8 +60,21 @@ struct Mma<double> {
 template <>
 struct Mma<float> {
     using acc = v4f;
+    static constexpr int kK = 4;
     __device__ static inline acc run(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+// bfloat16 inputs, float32 accumulation, K = 16 per instruction: lane l supplies
+// A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j = 0..3; the result layout is the
+// float32 one (checked on gfx950).
+template <>
+struct Mma<bf16> {
+    using acc = v4f;
+    static constexpr int kK = 16;
+    __device__ static inline acc run(v4s a, v4s b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
     }
     __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
@@ -195,10 +227,25 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
         if (kc + kBK < k_end) fill_koff(buf ^ 1, kc + kBK);
         __syncthreads();
         if (kc + kBK < k_end) load_chunk(buf ^ 1, kc + kBK);
+        if constexpr (Mma<Tc>::kK == 4) {
 #pragma unroll
-        for (int kk = 0; kk < kBK; kk += 4) {
-            const Tc a0 = As[kk + lk][wm + lrow], a1 = As[kk + lk][wm + 16 + lrow];
-            const Tc b0 = Bs[kk + lk][wn + lrow], b1 = Bs[kk + lk][wn + 16 + lrow];
+            for (int kk = 0; kk < kBK; kk += 4) {
+                const Tc a0 = As[kk + lk][wm + lrow], a1 = As[kk + lk][wm + 16 + lrow];
+                const Tc b0 = Bs[kk + lk][wn + lrow], b1 = Bs[kk + lk][wn + 16 + lrow];
+                acc[0][0] = Mma<Tc>::run(a0, b0, acc[0][0]);
+                acc[0][1] = Mma<Tc>::run(a0, b1, acc[0][1]);
+                acc[1][0] = Mma<Tc>::run(a1, b0, acc[1][0]);
+                acc[1][1] = Mma<Tc>::run(a1, b1, acc[1][1]);
+            }
+        } else {   // one 16-deep instruction covers the whole K chunk
+            v4s a0, a1, b0, b1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a0[j] = (short)As[4 * lk + j][wm + lrow].bits;
+                a1[j] = (short)As[4 * lk + j][wm + 16 + lrow].bits;
+                b0[j] = (short)Bs[4 * lk + j][wn + lrow].bits;
+                b1[j] = (short)Bs[4 * lk + j][wn + 16 + lrow].bits;
+            }
             acc[0][0] = Mma<Tc>::run(a0, b0, acc[0][0]);
             acc[0][1] = Mma<Tc>::run(a0, b1, acc[0][1]);
             acc[1][0] = Mma<Tc>::run(a1, b0, acc[1][0]);
@@ -1456,6 +1503,18 @@ __global__ __launch_bounds__(1024) void result_kernel(const double* __restrict__
 // ------------------------------------------------------------------------------------------
 // Host-side launchers
 // ------------------------------------------------------------------------------------------
+// Runs f(T{}) with T the tensor storage type of precision 0 (float64), 1 (float32) or 2 (bfloat16).
+template <typename F>
+hipError_t by_prec(int prec, F&& f) {
+    switch (prec) {
+        case 0: f(double{}); break;
+        case 1: f(float{}); break;
+        case 2: f(bf16{}); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
                        double* maxparts, hipStream_t s) {
     if (ndesc == 0 || tiles == 0) return hipSuccess;
@@ -1464,18 +1523,18 @@ hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t 
         case GEMM_F64: gemm_grouped<double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
         case GEMM_F32: gemm_grouped<float, float, float><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
         case GEMM_F32_TO_F64: gemm_grouped<float, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
+        case GEMM_BF16: gemm_grouped<bf16, bf16, bf16><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
+        case GEMM_BF16_TO_F64: gemm_grouped<bf16, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
+hipError_t launch_copy(int prec, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
                        hipStream_t s) {
     if (ndesc == 0 || total == 0) return hipSuccess;
     dim3 grid((unsigned)((total + 255) / 256)), block(256);
-    if (src_f32) copy_grouped<float><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
-    else copy_grouped<double><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) { copy_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total); });
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1794,44 +1853,45 @@ void init_kernel_attrs() {
     const int bytes = (int)core_lds_bytes(kCoreLdsMaxD);
     (void)hipFuncSetAttribute((const void*)core_kernel<true, float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<true, double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)core_kernel<true, bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    (void)hipFuncSetAttribute((const void*)gram_lanczos_kernel<bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
+    (void)hipFuncSetAttribute((const void*)lanczos_kernel<bf16, bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
 }
 
-hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
+hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
                        double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s) {
     if (ndesc == 0) return hipSuccess;
     dim3 grid(ndesc), block(kCoreThreads);
-    if (lds) {
-        const size_t bytes = core_lds_bytes(max_d);
-        if (proj_f32) core_kernel<true, float><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
-        else core_kernel<true, double><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
-    } else {
-        if (proj_f32) core_kernel<false, float><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
-        else core_kernel<false, double><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
-    }
-    return hipGetLastError();
+    const size_t bytes = core_lds_bytes(max_d);
+    return by_prec(prec, [&](auto t) {
+        using Tp = decltype(t);
+        if (lds) core_kernel<true, Tp><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
+        else core_kernel<false, Tp><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
+    });
 }
 
 size_t lanczos_lds_bytes(int s_max) { return (size_t)2 * (s_max + 1) * (s_max + 1) * sizeof(double); }
 
-hipError_t launch_lanczos(int tin_f32, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
+hipError_t launch_lanczos(int prec, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
                           int max_sweeps, double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s) {
     (void)s_max;
     if (ndesc == 0) return hipSuccess;
     dim3 grid(ndesc), block(kCoreThreads);
     const size_t bytes = kLanczosLdsBytes;
-    if (tin_f32) lanczos_kernel<float, float><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
-    else lanczos_kernel<double, double><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) {
+        using T = decltype(t);
+        lanczos_kernel<T, T><<<grid, block, bytes, s>>>(descs, scales, max_sweeps, disc, tie, sweeps);
+    });
 }
 
-hipError_t launch_gram_lanczos(int proj_f32, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
+hipError_t launch_gram_lanczos(int prec, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
                                int32_t* tie, int32_t* sweeps, hipStream_t s) {
     if (ndesc == 0) return hipSuccess;
     dim3 grid(ndesc), block(kCoreThreads);
     const size_t bytes = kLanczosLdsBytes;
-    if (proj_f32) gram_lanczos_kernel<float><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
-    else gram_lanczos_kernel<double><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) {
+        gram_lanczos_kernel<decltype(t)><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
+    });
 }
 
 hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* maxparts, double* scales,
@@ -1843,58 +1903,47 @@ hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* ma
     return hipGetLastError();
 }
 
-hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,
+hipError_t launch_inputs(int prec, const InputDesc* descs, int n, const double* staging, double* scales,
                          hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int threads = 256;
     dim3 grid((unsigned)((n * 64 + threads - 1) / threads)), block(threads);
-    if (f32) {
-        input_scatter<float><<<grid, block, 0, s>>>(descs, n, staging);
-        input_scales<float><<<grid, block, 0, s>>>(descs, n, scales);
-    } else {
-        input_scatter<double><<<grid, block, 0, s>>>(descs, n, staging);
-        input_scales<double><<<grid, block, 0, s>>>(descs, n, scales);
-    }
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) {
+        using T = decltype(t);
+        input_scatter<T><<<grid, block, 0, s>>>(descs, n, staging);
+        input_scales<T><<<grid, block, 0, s>>>(descs, n, scales);
+    });
 }
 
-hipError_t launch_reduce(int f32, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
+hipError_t launch_reduce(int prec, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
                          hipStream_t s) {
     if (ndesc == 0 || total == 0) return hipSuccess;
     const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-    if (f32) reduce_grouped<float><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
-    else reduce_grouped<double><<<grid, block, 0, s>>>(descs, ndesc, scales, total);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) { reduce_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total); });
 }
 
-hipError_t launch_core_bwd(int f32, const CoreBwdDesc* descs, int ndesc, hipStream_t s) {
+hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, hipStream_t s) {
     if (ndesc == 0) return hipSuccess;
-    if (f32) core_bwd_kernel<float><<<ndesc, kCoreThreads, 0, s>>>(descs);
-    else core_bwd_kernel<double><<<ndesc, kCoreThreads, 0, s>>>(descs);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) { core_bwd_kernel<decltype(t)><<<ndesc, kCoreThreads, 0, s>>>(descs); });
 }
 
-hipError_t launch_seed(int f32, const void* final_ptr, void* adj_final, const double* scales, int final_index,
+hipError_t launch_seed(int prec, const void* final_ptr, void* adj_final, const double* scales, int final_index,
                        hipStream_t s) {
-    if (f32) seed_kernel<float><<<1, 64, 0, s>>>(final_ptr, adj_final, scales, final_index);
-    else seed_kernel<double><<<1, 64, 0, s>>>(final_ptr, adj_final, scales, final_index);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) { seed_kernel<decltype(t)><<<1, 64, 0, s>>>(final_ptr, adj_final, scales, final_index); });
 }
 
-hipError_t launch_grad_inputs(int f32, const InputDesc* descs, int n, const double* scales, double* out,
+hipError_t launch_grad_inputs(int prec, const InputDesc* descs, int n, const double* scales, double* out,
                               hipStream_t s) {
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n * 64 + 255) / 256)), block(256);
-    if (f32) grad_inputs_kernel<float><<<grid, block, 0, s>>>(descs, n, scales, out);
-    else grad_inputs_kernel<double><<<grid, block, 0, s>>>(descs, n, scales, out);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) { grad_inputs_kernel<decltype(t)><<<grid, block, 0, s>>>(descs, n, scales, out); });
 }
 
-hipError_t launch_result(int f32, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
+hipError_t launch_result(int prec, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
                          int n_comp, double* result, hipStream_t s) {
-    if (f32) result_kernel<float><<<1, 1024, 0, s>>>(scales, n_scales, final_ptr, sweeps, n_comp, result);
-    else result_kernel<double><<<1, 1024, 0, s>>>(scales, n_scales, final_ptr, sweeps, n_comp, result);
-    return hipGetLastError();
+    return by_prec(prec, [&](auto t) {
+        result_kernel<decltype(t)><<<1, 1024, 0, s>>>(scales, n_scales, final_ptr, sweeps, n_comp, result);
+    });
 }
 
 }  // namespace tn

@@ -8,7 +8,7 @@
 
 namespace tn {
 
-enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2 };
+enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2, GEMM_BF16 = 3, GEMM_BF16_TO_F64 = 4 };
 
 constexpr int kCoreLdsMaxD = 64;
 constexpr int kLanczosMaxSteps = 512;     // cap on Krylov steps per compression
@@ -17,32 +17,32 @@ constexpr int kLanczosLdsBytes = 150 * 1024;   // dynamic LDS for the small SVD 
 void init_kernel_attrs();
 hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
                        double* maxparts, hipStream_t s);
-hipError_t launch_copy(int src_f32, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
+hipError_t launch_copy(int prec, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
                        hipStream_t s);
 size_t core_lds_bytes(int max_d);
-hipError_t launch_core(int lds, int proj_f32, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
+hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
                        double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
 size_t lanczos_lds_bytes(int s_max);
-hipError_t launch_lanczos(int tin_f32, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
+hipError_t launch_lanczos(int prec, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
                           int max_sweeps, double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
-hipError_t launch_gram_lanczos(int proj_f32, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
+hipError_t launch_gram_lanczos(int prec, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
                                int32_t* tie, int32_t* sweeps, hipStream_t s);
 hipError_t launch_scale_finalize(const ScaleDesc* descs, int n, const double* maxparts, double* scales,
                                  hipStream_t s);
-hipError_t launch_inputs(int f32, const InputDesc* descs, int n, const double* staging, double* scales,
+hipError_t launch_inputs(int prec, const InputDesc* descs, int n, const double* staging, double* scales,
                          hipStream_t s);
-hipError_t launch_reduce(int f32, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
+hipError_t launch_reduce(int prec, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
                          hipStream_t s);
-hipError_t launch_core_bwd(int f32, const CoreBwdDesc* descs, int ndesc, hipStream_t s);
-hipError_t launch_seed(int f32, const void* final_ptr, void* adj_final, const double* scales, int final_index,
+hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, hipStream_t s);
+hipError_t launch_seed(int prec, const void* final_ptr, void* adj_final, const double* scales, int final_index,
                        hipStream_t s);
-hipError_t launch_grad_inputs(int f32, const InputDesc* descs, int n, const double* scales, double* out,
+hipError_t launch_grad_inputs(int prec, const InputDesc* descs, int n, const double* scales, double* out,
                               hipStream_t s);
 hipError_t launch_ising_values(const IsingGraph& g, double beta, const double* J, double* data, int64_t total,
                                hipStream_t s);
 hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, const double* dlnz_ddata,
                              double* dlnz_dJ, hipStream_t s);
-hipError_t launch_result(int f32, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
+hipError_t launch_result(int prec, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
                          int n_comp, double* result, hipStream_t s);
 
 }  // namespace tn

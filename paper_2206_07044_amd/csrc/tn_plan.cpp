@@ -179,7 +179,7 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
     *P = Plan();
     P->g = g;
     P->opts = o;
-    P->elem_size = (o.precision == 1) ? 4 : 8;
+    P->elem_size = o.precision == 1 ? 4 : o.precision == 2 ? 2 : 8;
     const int64_t w = P->elem_size;
     if (o.chi < 1) return "chi must be >= 1";
     if (n_steps != g.n - 1) {

@@ -27,7 +27,7 @@ struct GraphSpec {
 struct TreeOpts {
     int32_t chi = 0;
     double cutoff = 0.0;
-    int32_t precision = 0;          // 0 = float64 tensors, 1 = float32 tensors
+    int32_t precision = 0;          // 0 = float64 tensors, 1 = float32, 2 = bfloat16
     int32_t jacobi_max_sweeps = 40;
     int64_t budget = 0;
     int32_t keep = 0;               // never reuse arena memory

@@ -108,6 +108,19 @@ def test_grad_fp32_bound(name, g, T, pairs, chi):
     assert worst <= FP32_GRAD_RTOL * scale
 
 
+@pytest.mark.parametrize("name,g,T,pairs,chi", CASES[:7], ids=[c[0] for c in CASES[:7]])
+def test_grad_bf16_bound(name, g, T, pairs, chi):
+    # bfloat16 tensors: every stored entry is rounded to 8 significant bits
+    _, lnz, grads, tie = gpu_grad(g, T, pairs, chi, precision="bf16")
+    if tie.any():
+        pytest.skip("a truncation tie")
+    ref = lnz_and_grad(g.n, g.edges, T, pairs, chi)
+    scale = max(float(np.max(np.abs(r))) for r in ref.grads)
+    worst = max(float(np.max(np.abs(a - r))) for a, r in zip(grads, ref.grads))
+    print(f"bf16 grad {name}: max |dg| / max |g| = {worst / scale:.2e}", flush=True)
+    assert worst <= 0.1 * scale
+
+
 @pytest.mark.parametrize("shape,beta,seed,chi", [((3, 3), 0.44, None, 2), ((4, 4), 0.44, 4, 4),
                                                  ((2, 2, 3), 0.3, 5, 8), ((3, 4), 0.6, 3, 2)])
 def test_coupling_gradient_exact_regime(shape, beta, seed, chi):

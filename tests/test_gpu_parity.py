@@ -174,6 +174,37 @@ def test_fp32_dimer():
     assert sign == want.sign and abs(lnz - want.ln_abs_z) <= _fp32_bound(want)
 
 
+# ---------------------------------------------------------------------------- bfloat16 mode
+# Tensors, projectors and contraction operands in bfloat16 (8-bit significand, unit roundoff
+# 2^-9 ~ 2e-3), MFMA products accumulated in float32; Gram / core / exponent in float64.
+# Each stored entry carries a relative rounding error up to 2^-9, so the worst case for ln|Z|
+# is about 2e-3 per op; the observed error is printed for the record.
+def _bf16_bound(want):
+    return 2e-3 * len(want.ops)
+
+
+@pytest.mark.parametrize("shape,chi,beta", [((8, 8), 16, 0.44), ((4, 4, 4), 8, 0.22), ((5, 5, 5), 8, 0.22)])
+def test_bf16_ising(shape, chi, beta):
+    g = lattice(shape)
+    T = ising_tensors(g, beta)
+    pairs = sweep_tree(shape)
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    sign, lnz, *_ = gpu_eval(g, T, pairs, chi, "bf16")
+    err = abs(lnz - want.ln_abs_z)
+    print(f"bf16 {shape} chi={chi}: |dlnZ|={err:.3e} rel={err / abs(want.ln_abs_z):.3e}", flush=True)
+    assert sign == want.sign and err <= _bf16_bound(want)
+
+
+def test_bf16_normal_signs():
+    g = lattice((5, 5))
+    T = normal_tensors(g, 0.5, seed=2)
+    pairs = sweep_tree((5, 5))
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, 4)
+    sign, lnz, *_ = gpu_eval(g, T, pairs, 4, "bf16")
+    print(f"bf16 normal 5x5 chi=4: |dlnZ|={abs(lnz - want.ln_abs_z):.3e}", flush=True)
+    assert sign == want.sign and abs(lnz - want.ln_abs_z) <= _bf16_bound(want)
+
+
 # ---------------------------------------------------------------------------- large bonds (Lanczos path)
 @pytest.mark.parametrize("shape,chi", [((6, 6, 6), 16), ((4, 4, 6), 16), ((6, 6, 6), 8)])
 def test_ising_cubic_large_bonds(shape, chi):
