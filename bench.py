@@ -138,10 +138,9 @@ def main() -> int:
     eu, ev, ed, off, data = flat(g, T)
     pi = [a for a, _ in pairs]
     pj = [b for _, b in pairs]
-    stream = torch.cuda.current_stream().cuda_stream
 
     def make_ctx(precision):
-        c = tn.Context(0, stream)
+        c = tn.Context(0)
         c.tn_load_graph(g.n, eu, ev, ed, off, data)
         c.tn_set_tree(pi, pj, args.chi, precision=precision)
         return c
@@ -236,7 +235,7 @@ def main() -> int:
 
     if args.fwd_bwd_steps > 0:
         # forward + reverse pass (d ln|Z| / d inputs) in the same precision, on a gradient plan
-        gctx = tn.Context(0, stream)
+        gctx = tn.Context(0)
         gctx.tn_load_graph(g.n, eu, ev, ed, off, data)
         gctx.tn_set_tree(pi, pj, args.chi, precision=args.precision, grad=True)
         ginfo = gctx.tn_plan_info()

@@ -204,6 +204,37 @@ tn_status tn_ising_coupling_grad_device(tn_ctx* ctx, double beta, const void* J_
  * reverse pass, its number of levels. */
 tn_status tn_grad_info(const tn_ctx* ctx, double* bwd_flops, double* bwd_bytes, int32_t* n_levels);
 
+/* ---- Batches: independent instances evaluated together ------------------
+ * Steps of different instances never depend on each other, so the schedules
+ * of several planned contexts are merged level by level (level L of every
+ * instance in the same grouped launches) and the whole merged schedule is
+ * captured once in a hipGraph; each tn_batch_contract replays it.  Instances
+ * may differ in graph, tree, chi and size; they must share the device and the
+ * precision.  The contexts stay owned by the caller and must outlive the
+ * batch; new values are given with tn_update_values / tn_update_values_device
+ * / tn_ising_values_device on the contexts (no recapture).  A batch keeps
+ * its own stream, scale and statistics arrays (device memory it owns). */
+typedef struct tn_batch tn_batch;
+
+/* Merge and capture.  TN_ESTATE if a context has no plan; TN_EINVAL for
+ * mixed devices or precisions or a repeated context. */
+tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out);
+void tn_batch_destroy(tn_batch* batch);
+const char* tn_batch_last_error(const tn_batch* batch);
+
+/* Replay: evaluates every instance; writes n mantissas and log10 exponents
+ * (host arrays, may be NULL) and leaves each context as after its own
+ * tn_contract_compressed (tn_result, tn_compress_stats and tn_grad work on it).
+ * Instances with Z = 0 get mantissa 0 and exponent -inf; the first other
+ * failure is returned. */
+tn_status tn_batch_contract(tn_batch* batch, double* mantissas, double* log10_exponents);
+
+/* Reverse pass of every instance after tn_batch_contract, into device float64
+ * buffers dlnz_ddata_dev[i] (one per instance, layout of its data).  Needs
+ * every context planned with opts.grad.  The reverse schedule is captured on
+ * the first call and recaptured when the output buffers change. */
+tn_status tn_batch_grad(tn_batch* batch, void* const* dlnz_ddata_dev);
+
 /* Host-only expansion of Algorithm 1 on shapes (no device use): writes up
  * to `cap` ops as 8 int64 each: (kind, a, b, out, m, n, k, new_dim) with
  * kind 0 = contract: (i, j, new id, free size of i, shared size, free size of

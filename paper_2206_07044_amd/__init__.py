@@ -6,8 +6,8 @@ with early compression and local (r = 0) QR-reduced truncated-SVD bond
 compression, in hand-written HIP kernels for gfx950 behind the C ABI of
 include/tn.h.  This package is the thin Python binding of that library.
 """
-from ._capi import (Context, TNError, load_library, tn_plan_describe, exported_symbols, LIB_PATH, KERNEL_KINDS,
+from ._capi import (Batch, Context, TNError, load_library, tn_plan_describe, exported_symbols, LIB_PATH, KERNEL_KINDS,
                     TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO)
 
-__all__ = ["Context", "TNError", "load_library", "tn_plan_describe", "exported_symbols", "LIB_PATH", "KERNEL_KINDS",
+__all__ = ["Batch", "Context", "TNError", "load_library", "tn_plan_describe", "exported_symbols", "LIB_PATH", "KERNEL_KINDS",
            "TN_OK", "TN_EINVAL", "TN_ESTATE", "TN_ENOMEM", "TN_EDEVICE", "TN_ENUMERIC", "TN_ZERO"]

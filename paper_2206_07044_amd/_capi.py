@@ -38,6 +38,19 @@ class tn_tree_opts(C.Structure):
 _lib = None
 
 
+def _init_torch_first() -> None:
+    """PyTorch-ROCm carries its own HIP runtime; the library links the system one.  Both run
+    in one process as long as torch's initialises the device first, so when torch is
+    importable and sees a GPU it is initialised before the library is loaded.  Stream
+    handles are never passed between the two runtimes (contexts use their own streams)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
 def load_library(path: Optional[str] = None) -> C.CDLL:
     """Load libtn.so (raises if it has not been built)."""
     global _lib
@@ -46,6 +59,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(f"{p} is missing: run `python -m paper_2206_07044_amd.build` first")
+    _init_torch_first()
     lib = C.CDLL(p)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     pI32, pI64, pD = C.POINTER(I32), C.POINTER(I64), C.POINTER(D)
@@ -68,6 +82,11 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_grad_info": ([P, pD, pD, pI32], C.c_int),
         "tn_ising_values_device": ([P, D, P], C.c_int),
         "tn_sync": ([P], C.c_int),
+        "tn_batch_create": ([I32, C.POINTER(P), C.POINTER(P)], C.c_int),
+        "tn_batch_destroy": ([P], None),
+        "tn_batch_last_error": ([P], C.c_char_p),
+        "tn_batch_contract": ([P, pD, pD], C.c_int),
+        "tn_batch_grad": ([P, C.POINTER(P)], C.c_int),
         "tn_ising_coupling_grad_device": ([P, D, P, P, P], C.c_int),
         "tn_read_tensor": ([P, I32, pD, I64, pI64], C.c_int),
         "tn_profile": ([P, C.c_uint32], C.c_int),
@@ -88,6 +107,7 @@ def exported_symbols() -> List[str]:
             "tn_update_values_device", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
             "tn_grad_device", "tn_grad_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
+            "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
             "tn_plan_describe"]
 
 
@@ -135,6 +155,10 @@ class Context:
         st = self._lib.tn_create(int(device), C.c_void_p(stream) if stream else None, C.byref(self._h))
         if st != TN_OK:
             raise TNError(st, "tn_create failed (no HIP device?)")
+
+    def last_error(self) -> str:
+        msg = self._lib.tn_last_error(self._h) if self._h else None
+        return msg.decode() if msg else ""
 
     def close(self) -> None:
         if self._h:
@@ -257,3 +281,45 @@ class Context:
         f, b, n = C.c_double(), C.c_double(), C.c_int32()
         self._check(self._lib.tn_grad_info(self._h, C.byref(f), C.byref(b), C.byref(n)))
         return {"bwd_flops": f.value, "bwd_bytes": b.value, "n_levels": n.value}
+
+
+class Batch:
+    """tn_batch: several planned contexts merged level by level and replayed from one hipGraph."""
+
+    def __init__(self, contexts: Sequence["Context"]):
+        self._lib = load_library()
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        self._h = C.c_void_p()
+        st = self._lib.tn_batch_create(len(self.contexts), arr, C.byref(self._h))
+        if st != TN_OK:
+            msgs = [c.last_error() for c in self.contexts]
+            raise TNError(st, "tn_batch_create failed: " + "; ".join(m for m in msgs if m))
+
+    def _check(self, st: int) -> int:
+        if st != TN_OK:
+            msg = self._lib.tn_batch_last_error(self._h)
+            raise TNError(st, msg.decode() if msg else "")
+        return st
+
+    def tn_batch_contract(self):
+        n = len(self.contexts)
+        m = np.zeros(n)
+        e = np.zeros(n)
+        self._check(self._lib.tn_batch_contract(self._h, _ptr(m, C.c_double), _ptr(e, C.c_double)))
+        return m, e
+
+    def tn_batch_grad(self, dev_ptrs: Sequence[int]) -> None:
+        arr = (C.c_void_p * len(dev_ptrs))(*[int(p) for p in dev_ptrs])
+        self._check(self._lib.tn_batch_grad(self._h, arr))
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.tn_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

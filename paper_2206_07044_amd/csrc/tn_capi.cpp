@@ -29,6 +29,7 @@ struct Launch {
     int prof = 0;         // tn_kernel_kind for timing
     double flops = 0;     // algorithmic flops of the steps in this launch
     double bytes = 0;     // algorithmic bytes of the steps in this launch
+    int level = 0;        // schedule level (forward or reverse numbering)
 };
 
 constexpr int kKinds = 12;   // >= number of tn_kernel_kind values
@@ -355,6 +356,7 @@ tn_status build_launches(tn_ctx* c) {
         max_parts = std::max(max_parts, parts);
         for (auto& kv : gemms) {
             Launch l;
+            l.level = L;
             l.kind = L_GEMM;
             l.key = kv.first / 2;
             l.prof = (kv.first & 1) ? TN_KERNEL_GRAM : TN_KERNEL_GEMM;
@@ -373,6 +375,7 @@ tn_status build_launches(tn_ctx* c) {
         }
         if (!copies.empty()) {
             Launch l;
+            l.level = L;
             l.kind = L_COPY;
             l.key = prec;
             l.prof = TN_KERNEL_COPY;
@@ -393,6 +396,7 @@ tn_status build_launches(tn_ctx* c) {
             auto& v = pass == 0 ? cores_lds : cores_glb;
             if (v.empty()) continue;
             Launch l;
+            l.level = L;
             l.kind = L_CORE;
             l.key = pass == 0 ? 1 : 0;
             l.prof = pass == 0 ? TN_KERNEL_CORE_LDS : TN_KERNEL_CORE_GLOBAL;
@@ -408,6 +412,7 @@ tn_status build_launches(tn_ctx* c) {
         }
         if (!lanczos.empty()) {
             Launch l;
+            l.level = L;
             l.kind = L_LANCZOS;
             l.key = prec;
             l.prof = TN_KERNEL_LANCZOS;
@@ -421,6 +426,7 @@ tn_status build_launches(tn_ctx* c) {
         }
         if (!glanczos.empty()) {
             Launch l;
+            l.level = L;
             l.kind = L_GLANCZOS;
             l.key = prec;
             l.prof = TN_KERNEL_LANCZOS;
@@ -433,6 +439,7 @@ tn_status build_launches(tn_ctx* c) {
         }
         if (!scales.empty()) {
             Launch l;
+            l.level = L;
             l.kind = L_SCALE;
             l.prof = TN_KERNEL_SCALE;
             l.begin = (int64_t)c->h_scale.size();
@@ -546,6 +553,7 @@ tn_status build_bwd_launches(tn_ctx* c) {
         }
         for (auto& kv : gemms) {
             Launch l;
+            l.level = L;
             l.kind = L_GEMM;
             l.key = kv.first;
             l.prof = TN_KERNEL_BWD_GEMM;
@@ -564,6 +572,7 @@ tn_status build_bwd_launches(tn_ctx* c) {
         }
         if (!reds.empty()) {
             Launch l;
+            l.level = L;
             l.kind = L_REDUCE;
             l.key = prec;
             l.prof = TN_KERNEL_BWD_GEMM;
@@ -581,6 +590,7 @@ tn_status build_bwd_launches(tn_ctx* c) {
         }
         if (!cores.empty()) {
             Launch l;
+            l.level = L;
             l.kind = L_CORE_BWD;
             l.key = prec;
             l.prof = TN_KERNEL_BWD_CORE;
@@ -1124,6 +1134,513 @@ tn_status tn_plan_describe(int32_t n_tensors, int32_t n_edges, const int32_t* ed
         q[6] = r.k;
         q[7] = r.new_dim;
     }
+    return TN_OK;
+}
+
+}  // extern "C"
+
+// ==========================================================================================
+// Batches: several planned contexts merged level by level and captured in one hipGraph
+// ==========================================================================================
+struct tn_batch {
+    int device = 0;
+    int prec = 0;
+    hipStream_t stream = nullptr;
+    std::vector<tn_ctx*> ctxs;
+    std::vector<int64_t> scale_off, comp_off;
+    int64_t n_scales = 0, n_comps = 0;
+    std::string err;
+    // merged forward schedule
+    std::vector<GemmDesc> h_gemm;
+    std::vector<CopyDesc> h_copy;
+    std::vector<CoreDesc> h_core;
+    std::vector<ScaleDesc> h_scale;
+    std::vector<LanczosDesc> h_lanczos;
+    std::vector<GLanczosDesc> h_glanczos;
+    std::vector<Launch> launches;
+    GemmDesc* d_gemm = nullptr;
+    CopyDesc* d_copy = nullptr;
+    CoreDesc* d_core = nullptr;
+    ScaleDesc* d_scale = nullptr;
+    LanczosDesc* d_lanczos = nullptr;
+    GLanczosDesc* d_glanczos = nullptr;
+    int64_t max_parts = 1;
+    // merged reverse schedule (when every context was planned with opts.grad)
+    bool grad = false;
+    std::vector<GemmDesc> h_bgemm;
+    std::vector<ReduceDesc> h_reduce;
+    std::vector<CoreBwdDesc> h_cbwd;
+    std::vector<Launch> blaunches;
+    GemmDesc* d_bgemm = nullptr;
+    ReduceDesc* d_reduce = nullptr;
+    CoreBwdDesc* d_cbwd = nullptr;
+    // batch-wide state
+    double* d_scales = nullptr;
+    double* d_maxparts = nullptr;
+    double* d_disc = nullptr;
+    int32_t* d_tie = nullptr;
+    int32_t* d_sweeps = nullptr;
+    double* d_result = nullptr;      // 4 per context
+    double* h_result = nullptr;      // pinned
+    hipGraph_t graph = nullptr, bgraph = nullptr;
+    hipGraphExec_t exec = nullptr, bexec = nullptr;
+    std::vector<void*> bgrad_ptrs;   // the device outputs the reverse graph was captured with
+};
+
+namespace {
+
+tn_status bfail(tn_batch* b, tn_status s, const std::string& msg) {
+    if (b) b->err = msg;
+    return s;
+}
+
+#define BHIP_TRY(b, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return bfail(b, TN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+template <typename T>
+tn_status bupload(tn_batch* b, T** dst, const std::vector<T>& src) {
+    dfree(*dst);
+    if (src.empty()) return TN_OK;
+    BHIP_TRY(b, hipMalloc((void**)dst, src.size() * sizeof(T)));
+    BHIP_TRY(b, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return TN_OK;
+}
+
+inline void shift(int32_t& idx, int64_t off) {
+    if (idx >= 0) idx = (int32_t)(idx + off);
+}
+
+// Merge the contexts' launches of one level and kind/key into one grouped launch.
+void merge_forward(tn_batch* b) {
+    int max_level = 0;
+    for (tn_ctx* c : b->ctxs) max_level = std::max(max_level, c->plan.n_levels);
+    for (int L = 1; L <= max_level; ++L) {
+        // per (kind, key): the launches of every context at this level, in context order
+        std::map<std::pair<int, int>, std::vector<std::pair<int, const Launch*>>> groups;
+        for (int i = 0; i < (int)b->ctxs.size(); ++i)
+            for (const Launch& l : b->ctxs[i]->launches)
+                if (l.level == L) groups[{l.kind, l.kind == L_GEMM ? l.key * 4 + l.prof : l.key}].push_back({i, &l});
+        // per-tile max slots of this level: each context's block follows the previous ones
+        std::vector<int64_t> part_off(b->ctxs.size(), 0);
+        int64_t parts = 0;
+        for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+            part_off[i] = parts;
+            for (const Launch& l : b->ctxs[i]->launches)
+                if (l.level == L && l.kind == L_SCALE)
+                    for (int k = 0; k < l.count; ++k) parts += b->ctxs[i]->h_scale[l.begin + k].nparts;
+        }
+        b->max_parts = std::max(b->max_parts, parts);
+        // GEMM and lanczos-type launches first, SCALE last (it reads the GEMMs' tile maxima)
+        for (int pass = 0; pass < 2; ++pass)
+            for (auto& kv : groups) {
+                const int kind = kv.first.first;
+                if ((kind == L_SCALE) != (pass == 1)) continue;
+                Launch m = *kv.second.front().second;
+                m.count = 0;
+                m.work = 0;
+                m.flops = m.bytes = 0;
+                m.max_d = 0;
+                switch (kind) {
+                    case L_GEMM: m.begin = (int64_t)b->h_gemm.size(); break;
+                    case L_COPY: m.begin = (int64_t)b->h_copy.size(); break;
+                    case L_CORE: m.begin = (int64_t)b->h_core.size(); break;
+                    case L_LANCZOS: m.begin = (int64_t)b->h_lanczos.size(); break;
+                    case L_GLANCZOS: m.begin = (int64_t)b->h_glanczos.size(); break;
+                    case L_SCALE: m.begin = (int64_t)b->h_scale.size(); break;
+                }
+                for (auto& pr : kv.second) {
+                    const int i = pr.first;
+                    const Launch& l = *pr.second;
+                    tn_ctx* c = b->ctxs[i];
+                    const int64_t so = b->scale_off[i], co = b->comp_off[i], po = part_off[i];
+                    m.count += l.count;
+                    m.flops += l.flops;
+                    m.bytes += l.bytes;
+                    m.max_d = std::max(m.max_d, l.max_d);
+                    for (int k = 0; k < l.count; ++k) {
+                        switch (kind) {
+                            case L_GEMM: {
+                                GemmDesc g = c->h_gemm[l.begin + k];
+                                shift(g.scale_a, so);
+                                shift(g.scale_b, so);
+                                if (g.mode == GEMM_TENSOR) g.maxpart = (int32_t)(g.maxpart + po);
+                                g.tile_begin = m.work;
+                                m.work += (int64_t)g.tiles_m * g.tiles_n * g.splits;
+                                b->h_gemm.push_back(g);
+                                break;
+                            }
+                            case L_COPY: {
+                                CopyDesc d = c->h_copy[l.begin + k];
+                                shift(d.scale, so);
+                                d.elem_begin = m.work;
+                                m.work += (int64_t)d.rows * d.cols;
+                                b->h_copy.push_back(d);
+                                break;
+                            }
+                            case L_CORE: {
+                                CoreDesc d = c->h_core[l.begin + k];
+                                shift(d.stat, co);
+                                b->h_core.push_back(d);
+                                break;
+                            }
+                            case L_LANCZOS: {
+                                LanczosDesc d = c->h_lanczos[l.begin + k];
+                                shift(d.scale_a, so);
+                                shift(d.scale_b, so);
+                                shift(d.stat, co);
+                                b->h_lanczos.push_back(d);
+                                break;
+                            }
+                            case L_GLANCZOS: {
+                                GLanczosDesc d = c->h_glanczos[l.begin + k];
+                                shift(d.stat, co);
+                                b->h_glanczos.push_back(d);
+                                break;
+                            }
+                            case L_SCALE: {
+                                ScaleDesc d = c->h_scale[l.begin + k];
+                                d.maxpart = (int32_t)(d.maxpart + po);
+                                shift(d.tensor, so);
+                                b->h_scale.push_back(d);
+                                break;
+                            }
+                        }
+                    }
+                }
+                b->launches.push_back(m);
+            }
+    }
+}
+
+void merge_backward(tn_batch* b) {
+    int max_level = 0;
+    for (tn_ctx* c : b->ctxs) max_level = std::max(max_level, c->plan.n_blevels);
+    for (int L = 1; L <= max_level; ++L) {
+        std::map<std::pair<int, int>, std::vector<std::pair<int, const Launch*>>> groups;
+        for (int i = 0; i < (int)b->ctxs.size(); ++i)
+            for (const Launch& l : b->ctxs[i]->blaunches)
+                if (l.level == L) groups[{l.kind, l.key}].push_back({i, &l});
+        for (auto& kv : groups) {
+            const int kind = kv.first.first;
+            Launch m = *kv.second.front().second;
+            m.count = 0;
+            m.work = 0;
+            m.flops = m.bytes = 0;
+            m.begin = kind == L_GEMM ? (int64_t)b->h_bgemm.size()
+                                     : kind == L_REDUCE ? (int64_t)b->h_reduce.size() : (int64_t)b->h_cbwd.size();
+            for (auto& pr : kv.second) {
+                const Launch& l = *pr.second;
+                tn_ctx* c = b->ctxs[pr.first];
+                const int64_t so = b->scale_off[pr.first];
+                m.count += l.count;
+                m.flops += l.flops;
+                m.bytes += l.bytes;
+                for (int k = 0; k < l.count; ++k) {
+                    if (kind == L_GEMM) {
+                        GemmDesc g = c->h_bgemm[l.begin + k];
+                        shift(g.scale_a, so);
+                        shift(g.scale_b, so);
+                        g.tile_begin = m.work;
+                        m.work += (int64_t)g.tiles_m * g.tiles_n * g.splits;
+                        b->h_bgemm.push_back(g);
+                    } else if (kind == L_REDUCE) {
+                        ReduceDesc r = c->h_reduce[l.begin + k];
+                        shift(r.scale_a, so);
+                        shift(r.scale_b, so);
+                        r.elem_begin = m.work;
+                        m.work += (int64_t)r.M * r.N;
+                        b->h_reduce.push_back(r);
+                    } else {
+                        b->h_cbwd.push_back(c->h_cbwd[l.begin + k]);
+                    }
+                }
+            }
+            b->blaunches.push_back(m);
+        }
+    }
+}
+
+// Enqueue the merged forward schedule on the batch stream (captured into the graph).
+tn_status enqueue_batch_forward(tn_batch* b) {
+    hipStream_t s = b->stream;
+    for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+        tn_ctx* c = b->ctxs[i];
+        BHIP_TRY(b, launch_inputs(b->prec, c->d_inputs, (int)c->h_inputs.size(), c->d_staging,
+                                  b->d_scales + b->scale_off[i], s));
+    }
+    for (const Launch& l : b->launches) {
+        switch (l.kind) {
+            case L_GEMM:
+                BHIP_TRY(b, launch_gemm(l.key, b->d_gemm + l.begin, l.count, l.work, b->d_scales, b->d_maxparts, s));
+                break;
+            case L_COPY:
+                BHIP_TRY(b, launch_copy(l.key, b->d_copy + l.begin, l.count, l.work, b->d_scales, s));
+                break;
+            case L_CORE:
+                BHIP_TRY(b, launch_core(l.key, b->prec, b->d_core + l.begin, l.count, l.max_d,
+                                        b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps, s));
+                break;
+            case L_LANCZOS:
+                BHIP_TRY(b, launch_lanczos(l.key, b->d_lanczos + l.begin, l.count, l.max_d, b->d_scales,
+                                           b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps, s));
+                break;
+            case L_GLANCZOS:
+                BHIP_TRY(b, launch_gram_lanczos(l.key, b->d_glanczos + l.begin, l.count,
+                                                b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie,
+                                                b->d_sweeps, s));
+                break;
+            case L_SCALE:
+                BHIP_TRY(b, launch_scale_finalize(b->d_scale + l.begin, l.count, b->d_maxparts, b->d_scales, s));
+                break;
+        }
+    }
+    for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+        tn_ctx* c = b->ctxs[i];
+        const Plan& P = c->plan;
+        const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
+        BHIP_TRY(b, launch_result(b->prec, b->d_scales + b->scale_off[i], (int)P.tens.size(), fin,
+                                  b->d_sweeps + b->comp_off[i], (int)P.comps.size(), b->d_result + 4 * i, s));
+    }
+    return TN_OK;
+}
+
+tn_status enqueue_batch_backward(tn_batch* b, void* const* outs) {
+    hipStream_t s = b->stream;
+    for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+        tn_ctx* c = b->ctxs[i];
+        const Plan& P = c->plan;
+        const int fin = P.final_tensor;
+        BHIP_TRY(b, launch_seed(b->prec, c->arena + P.bufs[P.tens[fin].buf].off, c->arena + P.bufs[P.adj_buf[fin]].off,
+                                b->d_scales + b->scale_off[i], fin, s));
+    }
+    for (const Launch& l : b->blaunches) {
+        switch (l.kind) {
+            case L_GEMM:
+                BHIP_TRY(b, launch_gemm(l.key, b->d_bgemm + l.begin, l.count, l.work, b->d_scales, b->d_maxparts, s));
+                break;
+            case L_REDUCE:
+                BHIP_TRY(b, launch_reduce(l.key, b->d_reduce + l.begin, l.count, l.work, b->d_scales, s));
+                break;
+            case L_CORE_BWD:
+                BHIP_TRY(b, launch_core_bwd(l.key, b->d_cbwd + l.begin, l.count, s));
+                break;
+        }
+    }
+    for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+        tn_ctx* c = b->ctxs[i];
+        BHIP_TRY(b, launch_grad_inputs(b->prec, c->d_gin, (int)c->h_gin.size(), b->d_scales + b->scale_off[i],
+                                       (double*)outs[i], s));
+    }
+    return TN_OK;
+}
+
+void free_batch(tn_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->bexec) (void)hipGraphExecDestroy(b->bexec);
+    if (b->bgraph) (void)hipGraphDestroy(b->bgraph);
+    b->exec = b->bexec = nullptr;
+    b->graph = b->bgraph = nullptr;
+    dfree(b->d_gemm);
+    dfree(b->d_copy);
+    dfree(b->d_core);
+    dfree(b->d_scale);
+    dfree(b->d_lanczos);
+    dfree(b->d_glanczos);
+    dfree(b->d_bgemm);
+    dfree(b->d_reduce);
+    dfree(b->d_cbwd);
+    dfree(b->d_scales);
+    dfree(b->d_maxparts);
+    dfree(b->d_disc);
+    dfree(b->d_tie);
+    dfree(b->d_sweeps);
+    dfree(b->d_result);
+    if (b->h_result) (void)hipHostFree(b->h_result);
+    b->h_result = nullptr;
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    b->stream = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out) {
+    if (!out || n < 1 || !ctxs) return TN_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return TN_EINVAL;
+        if (!ctxs[i]->has_plan) return fail(ctxs[i], TN_ESTATE, "tn_batch_create: context without a plan");
+    }
+    const int dev = ctxs[0]->device, prec = ctxs[0]->plan.opts.precision;
+    bool grad = true;
+    for (int i = 0; i < n; ++i) {
+        if (ctxs[i]->device != dev) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: contexts on different devices");
+        if (ctxs[i]->plan.opts.precision != prec)
+            return fail(ctxs[i], TN_EINVAL, "tn_batch_create: contexts with different precisions");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context appears twice");
+        grad = grad && ctxs[i]->plan.opts.grad;
+    }
+    (void)hipSetDevice(dev);
+    tn_batch* b = new tn_batch();
+    b->device = dev;
+    b->prec = prec;
+    b->grad = grad;
+    b->ctxs.assign(ctxs, ctxs + n);
+    for (tn_ctx* c : b->ctxs) {
+        b->scale_off.push_back(b->n_scales);
+        b->comp_off.push_back(b->n_comps);
+        b->n_scales += (int64_t)c->plan.tens.size();
+        b->n_comps += (int64_t)c->plan.comps.size();
+        (void)hipStreamSynchronize(c->stream);
+    }
+    merge_forward(b);
+    if (grad) merge_backward(b);
+    auto bail = [&](tn_status s) {
+        free_batch(b);
+        delete b;
+        return s;
+    };
+    tn_status s;
+    if ((s = bupload(b, &b->d_gemm, b->h_gemm)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_copy, b->h_copy)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_core, b->h_core)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_scale, b->h_scale)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_lanczos, b->h_lanczos)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_glanczos, b->h_glanczos)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_bgemm, b->h_bgemm)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_reduce, b->h_reduce)) != TN_OK) return bail(s);
+    if ((s = bupload(b, &b->d_cbwd, b->h_cbwd)) != TN_OK) return bail(s);
+    const size_t nc = (size_t)std::max<int64_t>(1, b->n_comps);
+    if (hipMalloc((void**)&b->d_scales, (size_t)std::max<int64_t>(1, b->n_scales) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&b->d_maxparts, (size_t)b->max_parts * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&b->d_disc, nc * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&b->d_tie, nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&b->d_sweeps, nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void**)&b->d_result, 4 * (size_t)n * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_result, 4 * (size_t)n * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipMemset(b->d_sweeps, 0, nc * sizeof(int32_t)) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(TN_ENOMEM);
+    // capture the forward schedule once; replays evaluate every instance
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return bail(TN_EDEVICE);
+    const tn_status es = enqueue_batch_forward(b);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (es != TN_OK || ce != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return bail(es != TN_OK ? es : TN_EDEVICE);
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return bail(TN_EDEVICE);
+    *out = b;
+    return TN_OK;
+}
+
+void tn_batch_destroy(tn_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    free_batch(b);
+    delete b;
+}
+
+const char* tn_batch_last_error(const tn_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+tn_status tn_batch_contract(tn_batch* b, double* mantissas, double* log10_exponents) {
+    if (!b) return TN_EINVAL;
+    (void)hipSetDevice(b->device);
+    for (tn_ctx* c : b->ctxs) BHIP_TRY(b, hipStreamSynchronize(c->stream));
+    BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    BHIP_TRY(b, hipMemcpyAsync(b->h_result, b->d_result, 4 * b->ctxs.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream));
+    // hand each context its scales and compression statistics, so that tn_result, tn_grad and
+    // tn_compress_stats work on it as after its own evaluation
+    for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+        tn_ctx* c = b->ctxs[i];
+        const size_t ns = c->plan.tens.size(), nc = c->plan.comps.size();
+        BHIP_TRY(b, hipMemcpyAsync(c->d_scales, b->d_scales + b->scale_off[i], ns * sizeof(double),
+                                   hipMemcpyDeviceToDevice, b->stream));
+        if (nc) {
+            BHIP_TRY(b, hipMemcpyAsync(c->d_disc, b->d_disc + b->comp_off[i], nc * sizeof(double),
+                                       hipMemcpyDeviceToDevice, b->stream));
+            BHIP_TRY(b, hipMemcpyAsync(c->d_tie, b->d_tie + b->comp_off[i], nc * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, b->stream));
+            BHIP_TRY(b, hipMemcpyAsync(c->d_sweeps, b->d_sweeps + b->comp_off[i], nc * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, b->stream));
+        }
+    }
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    tn_status worst = TN_OK;
+    for (int i = 0; i < (int)b->ctxs.size(); ++i) {
+        tn_ctx* c = b->ctxs[i];
+        const double* r = b->h_result + 4 * i;
+        c->sign = r[0];
+        c->lnz = r[1];
+        c->flags = (int)r[2];
+        c->evaluated = true;
+        double m = 0.0, e = -INFINITY;
+        tn_status st = TN_OK;
+        if (c->flags & 2) st = fail(c, TN_ENUMERIC, "non-finite tensor entry");
+        else if (c->flags & 4) st = fail(c, TN_ENUMERIC, "a Jacobi SVD did not converge within the sweep cap");
+        else if ((c->flags & 1) || c->sign == 0.0) {
+            c->sign = 0.0;
+            c->lnz = -INFINITY;
+            st = TN_ZERO;
+        } else {
+            const double l10 = c->lnz / std::log(10.0);
+            e = std::floor(l10);
+            m = std::pow(10.0, l10 - e);
+            if (m >= 10.0) m /= 10.0;
+            m *= c->sign;
+        }
+        if (mantissas) mantissas[i] = m;
+        if (log10_exponents) log10_exponents[i] = e;
+        if (st != TN_OK && st != TN_ZERO && worst == TN_OK) {
+            worst = st;
+            b->err = "instance " + std::to_string(i) + ": " + c->err;
+        }
+    }
+    return worst;
+}
+
+tn_status tn_batch_grad(tn_batch* b, void* const* dlnz_ddata_dev) {
+    if (!b) return TN_EINVAL;
+    if (!b->grad) return bfail(b, TN_ESTATE, "the batch's contexts were not all planned with opts.grad");
+    if (!dlnz_ddata_dev) return bfail(b, TN_EINVAL, "null output array");
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+        if (!dlnz_ddata_dev[i]) return bfail(b, TN_EINVAL, "null gradient buffer");
+        if (!b->ctxs[i]->evaluated) return bfail(b, TN_ESTATE, "tn_batch_grad before tn_batch_contract");
+        if (b->ctxs[i]->sign == 0.0) return bfail(b, TN_ZERO, "instance " + std::to_string(i) + " has Z = 0");
+    }
+    (void)hipSetDevice(b->device);
+    std::vector<void*> want(dlnz_ddata_dev, dlnz_ddata_dev + b->ctxs.size());
+    if (!b->bexec || want != b->bgrad_ptrs) {
+        // (re)capture the reverse schedule for these output buffers
+        if (b->bexec) (void)hipGraphExecDestroy(b->bexec);
+        if (b->bgraph) (void)hipGraphDestroy(b->bgraph);
+        b->bexec = nullptr;
+        b->bgraph = nullptr;
+        BHIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        const tn_status es = enqueue_batch_backward(b, want.data());
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+        if (es != TN_OK || ce != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return es != TN_OK ? es : bfail(b, TN_EDEVICE, "graph capture of the reverse pass failed");
+        }
+        b->bgraph = g;
+        BHIP_TRY(b, hipGraphInstantiate(&b->bexec, b->bgraph, nullptr, nullptr, 0));
+        b->bgrad_ptrs = want;
+    }
+    BHIP_TRY(b, hipGraphLaunch(b->bexec, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
     return TN_OK;
 }
 
