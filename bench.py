@@ -124,6 +124,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--fwd-bwd-steps", type=int, default=1, help="timed forward+reverse passes (0: skip)")
+    ap.add_argument("--batch", type=int, default=8, help="instances in the batched leg (<= 1: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -232,6 +234,30 @@ def main() -> int:
         out["abs_dlnz_vs_fp64"] = abs(lnz - rl)
         out["rel_dlnz_vs_fp64"] = abs(lnz - rl) / abs(rl)
         ref.close()
+
+    if args.batch > 1:
+        # the same lattice and tree at a sweep of beta values (independent instances), merged level by
+        # level and replayed from one hipGraph
+        betas = np.linspace(args.beta - 0.02, args.beta + 0.02, args.batch)
+        bctx = []
+        for b_ in betas:
+            Tb = __import__("tninputs").ising_tensors(g, float(b_))
+            c = tn.Context(0)
+            c.tn_load_graph(g.n, eu, ev, ed, off, flat(g, Tb)[4])
+            c.tn_set_tree(pi, pj, args.chi, precision=args.precision)
+            bctx.append(c)
+        batch = tn.Batch(bctx)
+        batch.tn_batch_contract()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            batch.tn_batch_contract()
+        bdt = (time.perf_counter() - t0) / args.batch_steps
+        out["batched"] = {"instances": args.batch, "betas": [float(x) for x in betas], "ms_per_replay": bdt * 1e3,
+                          "trees_per_s": args.batch / bdt, "speedup_vs_single": args.batch / bdt / trees_per_s,
+                          "replays": args.batch_steps, "graph": "one hipGraph per batch"}
+        batch.close()
+        for c in bctx:
+            c.close()
 
     if args.fwd_bwd_steps > 0:
         # forward + reverse pass (d ln|Z| / d inputs) in the same precision, on a gradient plan
