@@ -1209,6 +1209,30 @@ __device__ void dense_mvt(const double* __restrict__ F, int n, int D, const doub
     __syncthreads();
 }
 
+// C[r * cols + t] = sum_k A[k * ak + r * ar] B[k * bk + t * bt] for r < rows, t < cols, by the
+// whole workgroup: each thread owns one row and four consecutive columns, so A is read cols/4
+// times in total.  Ends with a barrier.
+__device__ void small_mm(const double* __restrict__ A, int64_t ak, int64_t ar, const double* __restrict__ B,
+                         int64_t bk, int64_t bt, double* __restrict__ C, int rows, int cols, int K) {
+    const int tb = (cols + 3) / 4;
+    for (int idx = threadIdx.x; idx < rows * tb; idx += kCoreThreads) {
+        const int r = idx % rows, t0 = 4 * (idx / rows);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const double* a = A + r * ar;
+        for (int k = 0; k < K; ++k) {
+            const double av = a[k * ak];
+            const double* bb = B + k * bk + t0 * bt;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (t0 + q < cols) acc[q] += av * bb[q * bt];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (t0 + q < cols) C[(int64_t)r * cols + t0 + q] = acc[q];
+    }
+    __syncthreads();
+}
+
 template <typename Tp>
 __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLanczosDesc* __restrict__ descs,
                                                                     int max_sweeps, double* __restrict__ stat_disc,
@@ -1233,7 +1257,10 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     double* Wg = sig + ls;                       // ls^2
     double* Vg = Wg + (int64_t)ls * ls;          // ls^2
     double* part = Vg + (int64_t)ls * ls;        // kCoreWaves x D partial sums
-    int* order = (int*)(part + (int64_t)kCoreWaves * D);   // ls
+    double* P1 = part + (int64_t)kCoreWaves * D; // D x cn: F_X^T W
+    double* P2 = P1 + (int64_t)D * cn;           // D x cn: G_Y F_X^T W
+    double* PY = P2 + (int64_t)D * cn;           // m_y x cn (explicit Y)
+    int* order = (int*)(PY + (int64_t)max(n, d.my) * cn);   // ls
     const double* FX = d.fx;
     if (d.gram_y) {
         for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
@@ -1350,7 +1377,8 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         }
         __syncthreads();
         int sw = 0;
-        const bool jc = jacobi_svd(W, Vs, s, s, lw, max_sweeps, sh, &sw);
+        const bool jc = s <= 64 ? jacobi_svd_small(W, Vs, s, s, lw, max_sweeps, sh, &sw)
+                                : jacobi_svd(W, Vs, s, s, lw, max_sweeps, sh, &sw);
         sorted_norms(W, s, s, lw, sig, order);
         nev = s;
         const double lmax = s > 0 ? sig[order[0]] : 0.0;
@@ -1384,22 +1412,24 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     const double lmax = nev > 0 ? sig[order[0]] : 0.0;
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
-    for (int t = 0; t < cn; ++t) {
+    // all kept columns at once: P1 = F_X^T W, P2 = G_Y P1
+    small_mm(FX, D, 1, Wt, 1, n, P1, D, cn, n);
+    if (d.gram_y) {
+        small_mm(G, D, 1, P1, cn, 1, P2, D, cn, D);   // G_Y is symmetric: row dd = column dd
+    } else {
+        small_mm(d.fy, 1, D, P1, cn, 1, PY, d.my, cn, D);
+        small_mm(d.fy, D, 1, PY, cn, 1, P2, D, cn, d.my);
+    }
+    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+        const int dd = idx / cn, t = idx - dd * cn;
         const double lv = t < nev ? sig[order[t]] : 0.0;   // eigenvalue = sigma^2
         const double sv = sqrt(fmax(lv, 0.0));
         const bool keep = lv > kNoiseRelSq * lmax && sv >= d.cutoff * sqrt(lmax);
-        if (keep) {
-            dense_mvt(FX, n, D, Wt + (int64_t)t * n, t1, 1.0, part);   // F_X^T w
-            apply_gy(t1, t2);                                          // G_Y F_X^T w
-        }
         const double fx = keep ? 1.0 / sqrt(sv) : 0.0, fy = keep ? 1.0 / (sv * sqrt(sv)) : 0.0;
-        for (int dd = tid; dd < D; dd += kCoreThreads) {
-            const double px = keep ? t1[dd] * fx : 0.0, pyv = keep ? t2[dd] * fy : 0.0;
-            // X = B: P_L column = side-X vector, P_R row = side-Y vector; X = A: the reverse
-            PL[(int64_t)dd * cn + t] = (Tp)(d.x_is_b ? px : pyv);
-            PR[(int64_t)t * D + dd] = (Tp)(d.x_is_b ? pyv : px);
-        }
-        __syncthreads();
+        const double px = P1[idx] * fx, pyv = P2[idx] * fy;
+        // X = B: P_L column = side-X vector, P_R row = side-Y vector; X = A: the reverse
+        PL[(int64_t)dd * cn + t] = (Tp)(d.x_is_b ? px : pyv);
+        PR[(int64_t)t * D + dd] = (Tp)(d.x_is_b ? pyv : px);
     }
     if (tid == 0) {
         double tot = 0.0, disc = 0.0;
