@@ -33,6 +33,7 @@ struct Launch {
 };
 
 constexpr int kKinds = 12;   // >= number of tn_kernel_kind values
+constexpr int kLanes = 4;    // streams per level: tensor GEMMs + scales, cores, Lanczos, Gram GEMMs + copies
 
 }  // namespace
 
@@ -40,6 +41,9 @@ struct tn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // independent kernel kinds of one level run concurrently on these (fork/join per level)
+    hipStream_t aux[kLanes - 1] = {nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> sync_ev;   // fork/join events (timing disabled)
     std::string err;
 
     GraphSpec g;
@@ -636,6 +640,63 @@ tn_status prof_begin(tn_ctx* c, const Launch& l, hipStream_t s, bool* timed) {
     return TN_OK;
 }
 
+// Which stream of a level a launch runs on.  Launches of one level never depend on each other,
+// except SCALE on the tensor GEMMs of its level, which share lane 0.
+int lane_of(const Launch& l) {
+    switch (l.kind) {
+        case L_GEMM: return l.prof == TN_KERNEL_GRAM ? 3 : 0;
+        case L_SCALE: return 0;
+        case L_CORE: return 1;
+        case L_LANCZOS:
+        case L_GLANCZOS: return 2;
+        default: return 3;
+    }
+}
+
+// Enqueue launches [b, e) of one level: on `main` alone when they all share a lane, else forked
+// onto the lanes' streams after an event on `main` and joined back with one event per lane.
+// `run` enqueues one launch on a given stream.  `events` supplies timing-disabled events.
+template <typename Run>
+hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStream_t main, hipStream_t* aux,
+                     std::vector<hipEvent_t>& events, size_t& next_ev, Run&& run) {
+    int used = 0;
+    for (size_t i = b; i < e; ++i) used |= 1 << lane_of(ls[i]);
+    auto event = [&](hipEvent_t* out) -> hipError_t {
+        if (next_ev == events.size()) {
+            hipEvent_t ev;
+            hipError_t err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (err != hipSuccess) return err;
+            events.push_back(ev);
+        }
+        *out = events[next_ev++];
+        return hipSuccess;
+    };
+    if ((used & (used - 1)) == 0) {   // a single lane: no fork
+        for (size_t i = b; i < e; ++i) {
+            hipError_t err = run(ls[i], main);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+    hipEvent_t fork;
+    hipError_t err = event(&fork);
+    if (err == hipSuccess) err = hipEventRecord(fork, main);
+    for (int lane = 1; lane < kLanes && err == hipSuccess; ++lane)
+        if (used & (1 << lane)) err = hipStreamWaitEvent(aux[lane - 1], fork, 0);
+    for (size_t i = b; i < e && err == hipSuccess; ++i) {
+        const int lane = lane_of(ls[i]);
+        err = run(ls[i], lane == 0 ? main : aux[lane - 1]);
+    }
+    for (int lane = 1; lane < kLanes && err == hipSuccess; ++lane)
+        if (used & (1 << lane)) {
+            hipEvent_t join;
+            err = event(&join);
+            if (err == hipSuccess) err = hipEventRecord(join, aux[lane - 1]);
+            if (err == hipSuccess) err = hipStreamWaitEvent(main, join, 0);
+        }
+    return err;
+}
+
 }  // namespace
 
 extern "C" {
@@ -663,6 +724,11 @@ tn_status tn_create(int device, void* hip_stream, tn_ctx** out) {
         delete c;
         return TN_EDEVICE;
     }
+    for (int i = 0; i < kLanes - 1; ++i)
+        if (hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking) != hipSuccess) {
+            tn_destroy(c);
+            return TN_EDEVICE;
+        }
     init_kernel_attrs();
     *out = c;
     return TN_OK;
@@ -680,6 +746,9 @@ void tn_destroy(tn_ctx* c) {
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->sync_ev) (void)hipEventDestroy(e);
+    for (hipStream_t a : c->aux)
+        if (a) (void)hipStreamDestroy(a);
     delete c;
 }
 
@@ -830,45 +899,56 @@ tn_status tn_enqueue(tn_ctx* c) {
     const int prec = P.opts.precision;
     hipStream_t s = c->stream;
     HIP_TRY(c, launch_inputs(prec, c->d_inputs, (int)c->h_inputs.size(), c->d_staging, c->d_scales, s));
-    for (const Launch& l : c->launches) {
+    auto run = [&](const Launch& l, hipStream_t st) -> hipError_t {
         const bool timed = (c->prof_mask >> l.prof) & 1u;
         if (timed) {
             const size_t i0 = c->ev_used.empty() ? 0 : c->ev_used.back().second + 2;
             while (c->ev_pool.size() < i0 + 2) {
                 hipEvent_t e;
-                HIP_TRY(c, hipEventCreate(&e));
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
                 c->ev_pool.push_back(e);
             }
-            HIP_TRY(c, hipEventRecord(c->ev_pool[i0], s));
+            hipError_t err = hipEventRecord(c->ev_pool[i0], st);
+            if (err != hipSuccess) return err;
             c->ev_used.push_back({l.prof, i0});
             c->prof_launches[l.prof] += 1;
             c->prof_flops[l.prof] += l.flops;
             c->prof_bytes[l.prof] += l.bytes;
         }
+        hipError_t err = hipSuccess;
         switch (l.kind) {
             case L_GEMM:
-                HIP_TRY(c, launch_gemm(l.key, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, s));
+                err = launch_gemm(l.key, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
                 break;
             case L_COPY:
-                HIP_TRY(c, launch_copy(l.key, c->d_copy + l.begin, l.count, l.work, c->d_scales, s));
+                err = launch_copy(l.key, c->d_copy + l.begin, l.count, l.work, c->d_scales, st);
                 break;
             case L_CORE:
-                HIP_TRY(c, launch_core(l.key, prec, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
-                                       c->d_disc, c->d_tie, c->d_sweeps, s));
+                err = launch_core(l.key, prec, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
+                                  c->d_disc, c->d_tie, c->d_sweeps, st);
                 break;
             case L_LANCZOS:
-                HIP_TRY(c, launch_lanczos(l.key, c->d_lanczos + l.begin, l.count, l.max_d, c->d_scales,
-                                          P.opts.jacobi_max_sweeps, c->d_disc, c->d_tie, c->d_sweeps, s));
+                err = launch_lanczos(l.key, c->d_lanczos + l.begin, l.count, l.max_d, c->d_scales,
+                                     P.opts.jacobi_max_sweeps, c->d_disc, c->d_tie, c->d_sweeps, st);
                 break;
             case L_GLANCZOS:
-                HIP_TRY(c, launch_gram_lanczos(l.key, c->d_glanczos + l.begin, l.count, P.opts.jacobi_max_sweeps,
-                                               c->d_disc, c->d_tie, c->d_sweeps, s));
+                err = launch_gram_lanczos(l.key, c->d_glanczos + l.begin, l.count, P.opts.jacobi_max_sweeps,
+                                          c->d_disc, c->d_tie, c->d_sweeps, st);
                 break;
             case L_SCALE:
-                HIP_TRY(c, launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, s));
+                err = launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, st);
                 break;
         }
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
+        if (err == hipSuccess && timed) err = hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], st);
+        return err;
+    };
+    size_t next_ev = 0;
+    for (size_t b = 0; b < c->launches.size();) {
+        size_t e = b;
+        while (e < c->launches.size() && c->launches[e].level == c->launches[b].level) ++e;
+        HIP_TRY(c, run_level(c->launches, b, e, s, c->aux, c->sync_ev, next_ev, run));
+        b = e;
     }
     const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
     HIP_TRY(c, launch_result(prec, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
@@ -1184,6 +1264,8 @@ struct tn_batch {
     double* h_result = nullptr;      // pinned
     hipGraph_t graph = nullptr, bgraph = nullptr;
     hipGraphExec_t exec = nullptr, bexec = nullptr;
+    hipStream_t aux[kLanes - 1] = {nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> sync_ev;
     std::vector<void*> bgrad_ptrs;   // the device outputs the reverse graph was captured with
 };
 
@@ -1240,6 +1322,7 @@ void merge_forward(tn_batch* b) {
                 const int kind = kv.first.first;
                 if ((kind == L_SCALE) != (pass == 1)) continue;
                 Launch m = *kv.second.front().second;
+                m.level = L;
                 m.count = 0;
                 m.work = 0;
                 m.flops = m.bytes = 0;
@@ -1372,31 +1455,30 @@ tn_status enqueue_batch_forward(tn_batch* b) {
         BHIP_TRY(b, launch_inputs(b->prec, c->d_inputs, (int)c->h_inputs.size(), c->d_staging,
                                   b->d_scales + b->scale_off[i], s));
     }
-    for (const Launch& l : b->launches) {
+    auto run = [&](const Launch& l, hipStream_t st) -> hipError_t {
         switch (l.kind) {
-            case L_GEMM:
-                BHIP_TRY(b, launch_gemm(l.key, b->d_gemm + l.begin, l.count, l.work, b->d_scales, b->d_maxparts, s));
-                break;
-            case L_COPY:
-                BHIP_TRY(b, launch_copy(l.key, b->d_copy + l.begin, l.count, l.work, b->d_scales, s));
-                break;
+            case L_GEMM: return launch_gemm(l.key, b->d_gemm + l.begin, l.count, l.work, b->d_scales, b->d_maxparts, st);
+            case L_COPY: return launch_copy(l.key, b->d_copy + l.begin, l.count, l.work, b->d_scales, st);
             case L_CORE:
-                BHIP_TRY(b, launch_core(l.key, b->prec, b->d_core + l.begin, l.count, l.max_d,
-                                        b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps, s));
-                break;
+                return launch_core(l.key, b->prec, b->d_core + l.begin, l.count, l.max_d,
+                                   b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps, st);
             case L_LANCZOS:
-                BHIP_TRY(b, launch_lanczos(l.key, b->d_lanczos + l.begin, l.count, l.max_d, b->d_scales,
-                                           b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps, s));
-                break;
+                return launch_lanczos(l.key, b->d_lanczos + l.begin, l.count, l.max_d, b->d_scales,
+                                      b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps, st);
             case L_GLANCZOS:
-                BHIP_TRY(b, launch_gram_lanczos(l.key, b->d_glanczos + l.begin, l.count,
-                                                b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie,
-                                                b->d_sweeps, s));
-                break;
-            case L_SCALE:
-                BHIP_TRY(b, launch_scale_finalize(b->d_scale + l.begin, l.count, b->d_maxparts, b->d_scales, s));
-                break;
+                return launch_gram_lanczos(l.key, b->d_glanczos + l.begin, l.count,
+                                           b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps,
+                                           st);
+            case L_SCALE: return launch_scale_finalize(b->d_scale + l.begin, l.count, b->d_maxparts, b->d_scales, st);
         }
+        return hipSuccess;
+    };
+    size_t next_ev = 0;
+    for (size_t i = 0; i < b->launches.size();) {
+        size_t e = i;
+        while (e < b->launches.size() && b->launches[e].level == b->launches[i].level) ++e;
+        BHIP_TRY(b, run_level(b->launches, i, e, s, b->aux, b->sync_ev, next_ev, run));
+        i = e;
     }
     for (int i = 0; i < (int)b->ctxs.size(); ++i) {
         tn_ctx* c = b->ctxs[i];
@@ -1464,6 +1546,12 @@ void free_batch(tn_batch* b) {
     b->h_result = nullptr;
     if (b->stream) (void)hipStreamDestroy(b->stream);
     b->stream = nullptr;
+    for (hipStream_t& a : b->aux) {
+        if (a) (void)hipStreamDestroy(a);
+        a = nullptr;
+    }
+    for (hipEvent_t e : b->sync_ev) (void)hipEventDestroy(e);
+    b->sync_ev.clear();
 }
 
 }  // namespace
@@ -1528,6 +1616,8 @@ tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out) {
         hipMemset(b->d_sweeps, 0, nc * sizeof(int32_t)) != hipSuccess ||
         hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(TN_ENOMEM);
+    for (int i = 0; i < kLanes - 1; ++i)
+        if (hipStreamCreateWithFlags(&b->aux[i], hipStreamNonBlocking) != hipSuccess) return bail(TN_EDEVICE);
     // capture the forward schedule once; replays evaluate every instance
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return bail(TN_EDEVICE);
     const tn_status es = enqueue_batch_forward(b);
