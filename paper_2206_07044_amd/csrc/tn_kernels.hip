@@ -398,6 +398,41 @@ __device__ int pivoted_cholesky(double* G, int D, double* R, int* chosen, CoreSh
     return r;
 }
 
+// 1/x and 1/sqrt(x) (x > 0) from the hardware estimates refined by two Newton-Raphson steps
+// each (every step doubles the correct bits), to within a few ulp in float64.
+__device__ inline double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ inline double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+
+// Jacobi rotation annihilating the off-diagonal g of the 2 x 2 Gram [[a, g], [g, b]] of two
+// columns: zeta = (b - a) / 2g, t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) (the smaller angle),
+// c = 1 / sqrt(1 + t^2), s = c t.
+__device__ inline void jacobi_rotation(double a, double b, double g, double* c, double* s) {
+    const double zeta = (b - a) * rcp_nr(2.0 * g);
+    const double az = fabs(zeta);
+    double root;
+    if (az > 1e100) {
+        root = az;
+    } else {
+        const double r2 = fma(zeta, zeta, 1.0);
+        root = r2 * rsq_nr(r2);
+    }
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + root);
+    const double cc = rsq_nr(fma(t, t, 1.0));
+    *c = cc;
+    *s = cc * t;
+}
+
 // pivoted_cholesky by a single wave for D <= 64: lane l owns index l, the pivot search is a
 // wave butterfly, and the rank-1 update runs down each lane's own column of G (LDS, symmetric,
 // destroyed).  Same pivot rule, stopping tolerance and output layout as pivoted_cholesky.
@@ -499,12 +534,9 @@ __device__ bool jacobi_svd(double* W, double* V, int rows, int cols, int ld, int
                 a = wave_sum(a);
                 b = wave_sum(b);
                 g = wave_sum(g);
-                if (a > zero2 && b > zero2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-                    const double zeta = (b - a) / (2.0 * g);
-                    const double az = fabs(zeta);
-                    const double root = az > 1e100 ? az : sqrt(1.0 + zeta * zeta);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                if (a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
+                    double c, s;
+                    jacobi_rotation(a, b, g, &c, &s);
                     for (int i = lane; i < rows; i += 64) {
                         const double x = w1[i], y = w2[i];
                         w1[i] = c * x - s * y;
@@ -590,12 +622,9 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                 a = row16_sum(a);
                 b = row16_sum(b);
                 g = row16_sum(g);
-                if (a > zero2 && b > zero2 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-                    const double zeta = (b - a) / (2.0 * g);
-                    const double az = fabs(zeta);
-                    const double root = az > 1e100 ? az : sqrt(1.0 + zeta * zeta);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (az + root);
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                if (a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
+                    double c, s;
+                    jacobi_rotation(a, b, g, &c, &s);
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int i = ql + 16 * k;
@@ -1395,7 +1424,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
             converged = ok || exhausted;
             break;
         }
-        target = min(sm, s + 8);
+        target = min(sm, s + 4);
         __syncthreads();
     }
     // Ritz vectors w_t = Q Vs[:, order[t]]

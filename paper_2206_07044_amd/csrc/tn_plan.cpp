@@ -454,6 +454,8 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                             int64_t splits = (mm + 255) / 256;
                             splits = std::min<int64_t>(splits, std::max<int64_t>(1, 1024 / tiles));
                             splits = std::min<int64_t>(splits, std::max<int64_t>(1, (32 << 20) / (D * D * 8)));
+                            // large bonds: a single workgroup sums the partials, keep them few
+                            if (D >= kLanczosMinD) splits = std::min<int64_t>(splits, 4);
                             splits = std::max<int64_t>(1, splits);
                             int64_t kps = (mm + splits - 1) / splits;
                             kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
@@ -490,7 +492,7 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         // X = the explicit side (the shorter one when both are explicit)
                         c.x_is_b = (mb <= D && (ma > D || mb <= ma)) ? 1 : 0;
                         const int64_t n = c.x_is_b ? mb : ma, my = c.x_is_b ? ma : mb;
-                        c.s_min = (int32_t)std::min<int64_t>(n, 2 * nw + 4);
+                        c.s_min = (int32_t)std::min<int64_t>(n, nw + 8);
                         c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(n, 8 * nw + 64), 512);
                         const int64_t sm = c.s_max, ls = sm + 1;
                         const int64_t words = D * D + n * sm + n * nw + 2 * D + std::max(n, my) + 2 * sm + ls +
