@@ -229,6 +229,21 @@ def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: 
     return res
 
 
+def contract_prefix(n, edges, tensors, pairs, chi, steps: int, cutoff: float = 0.0):
+    """Run only the first ``steps`` tree steps of the same Algorithm 1 loop and return every
+    normalised tensor written so far, in creation order (inputs first).  Used to compare a
+    large instance's early intermediates one by one."""
+    global _RECORD
+    _RECORD = []
+    try:
+        _run(n, edges, tensors, pairs, chi, cutoff, False, max_steps=steps)
+    except _OutOfTime:
+        pass
+    finally:
+        rec, _RECORD = _RECORD, None
+    return rec
+
+
 @dataclass
 class PartialRun:
     steps_done: int
@@ -252,7 +267,8 @@ class _OutOfTime(Exception):
     pass
 
 
-def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progress=None) -> OracleResult:
+def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progress=None,
+         max_steps=None) -> OracleResult:
     import time
     net = _Network(n, edges, tensors)
     scales: List[float] = []
@@ -265,7 +281,7 @@ def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progres
         for v in range(n):
             net.t[v] = _normalise(net.t[v], scales)
         for t, (i, j) in enumerate(pairs):
-            if deadline is not None and time.time() > deadline:
+            if (deadline is not None and time.time() > deadline) or (max_steps is not None and t >= max_steps):
                 raise _OutOfTime()
             k = n + t
             if i == j or i not in net.t or j not in net.t:

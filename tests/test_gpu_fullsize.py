@@ -1,0 +1,154 @@
+"""The headline workload at its real size: 12x12x12 Ising, beta = 0.22, chi = 16, sweep tree.
+
+The full CPU oracle takes minutes here, so the checks are:
+* ln Z in FP64 against the stored oracle value (tests/golden/cubic_12.json), within the
+  instance's measured sensitivity band;
+* FP32 (the benchmark's configuration) against FP64 at the metric's 1e-6 relative gate;
+* exact properties at full size: the running exponent absorbs a rescaled input exactly, and a
+  batch reproduces the single evaluation bitwise;
+* sampled outputs the oracle computes one by one: every tensor written by the first 480 tree
+  steps, through the oracle's prefix run.  Pure contraction outputs (before any compression)
+  must match element by element; each compression output a' (b') is compared through its
+  sign-free Gram a'^T a' (b' b'^T), which is diag(sigma) / s^2 by Eq. (svd).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2206_07044_amd as tn
+from oracle.approx import contract_prefix
+from tninputs import ising_tensors, lattice
+from tninputs.trees import sweep_tree
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SHAPE, BETA, CHI = (12, 12, 12), 0.22, 16
+# Perturbing a single input tensor at the 1e-16 level moves this instance's ln Z by up to
+# 1.7e-7 relative (near-degenerate truncations); a different FP64 rounding order is such a
+# perturbation.  The band is three times the largest measured move.
+SENSITIVITY_REL = 5e-7
+PREFIX_STEPS = 480
+
+
+@pytest.fixture(scope="module")
+def instance():
+    g = lattice(SHAPE)
+    T = ising_tensors(g, BETA)
+    pairs = sweep_tree(SHAPE)
+    eu, ev, ed = g.arrays()
+    off = np.zeros(g.n + 1, dtype=np.int64)
+    off[1:] = np.cumsum([t.size for t in T])
+    data = np.concatenate([t.ravel() for t in T])
+    return g, T, pairs, (eu, ev, ed, off, data)
+
+
+def evaluate(instance, precision, data=None, keep=False):
+    g, T, pairs, (eu, ev, ed, off, d0) = instance
+    c = tn.Context(0)
+    c.tn_load_graph(g.n, eu, ev, ed, off, d0 if data is None else data)
+    c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], CHI, precision=precision, keep_intermediates=keep)
+    c.tn_contract_compressed()
+    return c
+
+
+def test_fullsize_fp64_against_stored_oracle(instance):
+    with open(os.path.join(HERE, "golden", "cubic_12.json")) as f:
+        gold = json.load(f)
+    c = evaluate(instance, "fp64")
+    try:
+        sign, lnz = c.tn_result()
+        disc, tie, sw = c.tn_compress_stats()
+    finally:
+        c.close()
+    print(f"\n12^3 chi=16 FP64: ln Z = {lnz!r}, oracle {gold['oracle_lnZ']!r}", flush=True)
+    assert sign == 1.0 and not tie.any() and (sw >= 0).all()
+    assert lnz == pytest.approx(gold["oracle_lnZ"], rel=SENSITIVITY_REL)
+
+
+def test_fullsize_fp32_meets_the_metric_gate(instance):
+    c64, c32 = evaluate(instance, "fp64"), evaluate(instance, "fp32")
+    try:
+        l64, l32 = c64.tn_result()[1], c32.tn_result()[1]
+    finally:
+        c64.close()
+        c32.close()
+    print(f"\nFP32 - FP64: {l32 - l64:.3e} ({(l32 - l64) / l64:.2e} relative)", flush=True)
+    assert abs(l32 - l64) <= 1e-6 * abs(l64)
+
+
+def test_fullsize_running_exponent_absorbs_rescaling(instance):
+    # a power-of-two factor leaves every normalised tensor bitwise unchanged, so ln Z moves by
+    # exactly ln 4 (another factor would also perturb the inputs at the rounding level, which
+    # this instance amplifies as described above)
+    g, T, pairs, (eu, ev, ed, off, data) = instance
+    c = evaluate(instance, "fp64")
+    d2 = data.copy()
+    v = 700
+    d2[off[v]:off[v + 1]] *= 4.0
+    c2 = evaluate(instance, "fp64", d2)
+    try:
+        l1, l2 = c.tn_result()[1], c2.tn_result()[1]
+    finally:
+        c.close()
+        c2.close()
+    assert l2 - l1 == pytest.approx(math.log(4.0), abs=1e-10)
+
+
+def test_fullsize_batch_bitwise(instance):
+    a, b = evaluate(instance, "fp32"), evaluate(instance, "fp32")
+    try:
+        ra = a.tn_result()
+        batch = tn.Batch([a, b])
+        try:
+            batch.tn_batch_contract()
+            assert a.tn_result() == ra and b.tn_result() == ra
+        finally:
+            batch.close()
+    finally:
+        a.close()
+        b.close()
+
+
+def test_fullsize_prefix_intermediates_against_oracle(instance):
+    g, T, pairs, (eu, ev, ed, off, data) = instance
+    rec = contract_prefix(g.n, g.edges, T, pairs, CHI, PREFIX_STEPS)
+    ops = tn.tn_plan_describe(g.n, eu, ev, ed, [a for a, _ in pairs], [b for _, b in pairs], CHI)
+    c = evaluate(instance, "fp64", keep=True)
+    try:
+        idx = g.n
+        steps = 0
+        compressed = 0
+        seen_compression = False
+        for op in ops:
+            if op[0] == 0:
+                if steps == PREFIX_STEPS:
+                    break
+                steps += 1
+                got = c.tn_read_tensor(idx)
+                want = rec[idx].ravel()
+                if not seen_compression:   # sign-unique: the exact contraction of the inputs
+                    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+                idx += 1
+            else:
+                seen_compression = True
+                _, a, b, e_new, ma, D, mb, nw = op
+                for side in range(2):
+                    got = c.tn_read_tensor(idx)
+                    want = rec[idx].ravel()
+                    m = ma if side == 0 else mb
+                    ga = got.reshape(m, nw) if side == 0 else got.reshape(nw, m).T
+                    wa = want.reshape(m, nw) if side == 0 else want.reshape(nw, m).T
+                    gg, wg = ga.T @ ga, wa.T @ wa   # diag(sigma) / s^2, sign-free
+                    scale = np.max(np.abs(wg))
+                    np.testing.assert_allclose(np.diag(gg), np.diag(wg), rtol=0, atol=1e-11 * scale)
+                    off_diag = gg - np.diag(np.diag(gg))
+                    assert np.max(np.abs(off_diag)) <= 1e-11 * scale
+                    idx += 1
+                compressed += 1
+        assert idx == len(rec) and compressed > 100
+    finally:
+        c.close()

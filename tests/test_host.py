@@ -130,3 +130,56 @@ def test_fastdiv_exact(tmp_path):
                     str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0 and "OK" in out.stdout, out.stdout
+
+
+def test_abi_null_and_invalid_arguments():
+    """Every entry point rejects a null context or missing arrays with TN_EINVAL and never
+    touches a device for it; destroy functions accept null."""
+    import ctypes as C
+    lib = tn.load_library()
+    null = None
+    d = C.c_double()
+    assert lib.tn_load_graph(null, 1, 0, None, None, None, None, None) == tn.TN_EINVAL
+    assert lib.tn_update_values(null, None) == tn.TN_EINVAL
+    assert lib.tn_update_values_device(null, None) == tn.TN_EINVAL
+    assert lib.tn_set_tree(null, 0, None, None, None) == tn.TN_EINVAL
+    assert lib.tn_contract_compressed(null, C.byref(d), C.byref(d)) == tn.TN_EINVAL
+    assert lib.tn_enqueue(null) == tn.TN_EINVAL
+    assert lib.tn_fetch(null) == tn.TN_EINVAL
+    assert lib.tn_result(null, C.byref(d), C.byref(d)) == tn.TN_EINVAL
+    assert lib.tn_grad(null, None) == tn.TN_EINVAL
+    assert lib.tn_grad_device(null, None) == tn.TN_EINVAL
+    assert lib.tn_grad_info(null, None, None, None) == tn.TN_EINVAL
+    assert lib.tn_sync(null) == tn.TN_EINVAL
+    assert lib.tn_ising_values_device(null, 0.5, None) == tn.TN_EINVAL
+    assert lib.tn_ising_coupling_grad_device(null, 0.5, None, None, None) == tn.TN_EINVAL
+    assert lib.tn_batch_create(0, None, None) == tn.TN_EINVAL
+    assert lib.tn_batch_contract(null, None, None) == tn.TN_EINVAL
+    assert lib.tn_batch_grad(null, None) == tn.TN_EINVAL
+    assert lib.tn_profile(null, 0) == tn.TN_EINVAL
+    assert lib.tn_last_error(null) == b"null context"
+    assert lib.tn_batch_last_error(null) == b"null batch"
+    lib.tn_destroy(null)
+    lib.tn_batch_destroy(null)
+
+
+@pytest.mark.parametrize("pairs,chi,msg", [
+    ([(0, 1), (4, 2)], 4, "steps"),                 # too few steps for 4 tensors
+    ([(0, 1), (0, 2), (5, 3)], 4, "live"),           # tensor 0 used twice
+    ([(0, 0), (4, 1), (5, 2)], 4, "live"),           # a tensor with itself
+    ([(0, 1), (4, 2), (5, 9)], 4, "live"),           # unknown id
+    ([(0, 1), (4, 2), (5, 3)], 0, "chi"),            # chi < 1
+])
+def test_describe_rejects_invalid_trees(pairs, chi, msg):
+    g = lattice((2, 2))
+    eu, ev, ed = g.arrays()
+    with pytest.raises(tn.TNError) as e:
+        tn.tn_plan_describe(g.n, eu, ev, ed, [a for a, _ in pairs], [b for _, b in pairs], chi)
+    assert e.value.status == tn.TN_EINVAL
+
+
+def test_describe_rejects_invalid_graphs():
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(3, [1], [0], [2], [0, 3], [1, 2], 4)        # u > v
+    with pytest.raises(tn.TNError):
+        tn.tn_plan_describe(3, [0], [1], [0], [0, 3], [1, 2], 4)        # dimension 0
