@@ -205,6 +205,7 @@ tn_status build_launches(tn_ctx* c) {
         std::pair<double, double> lanczos_work{0, 0};
         int lanczos_smax = 1;
         std::vector<ScaleDesc> scales;
+        std::vector<ReduceDesc> sums;
         int64_t parts = 0;
         for (int32_t si : by_level[L]) {
             const Step& st = P.steps[si];
@@ -231,6 +232,26 @@ tn_status build_launches(tn_ctx* c) {
                     g.scale_a = st.in_a;
                     g.square_a = 1;
                     key = 2 * wide_key(prec) + 1;
+                    if (st.splits > 1) {
+                        // the split partials are summed in place right after the level's Gram
+                        // GEMMs (same stream, many workgroups), so readers see one matrix
+                        ReduceDesc r;
+                        std::memset(&r, 0, sizeof(r));
+                        ViewSpec vs;
+                        vs.row_dims = {(int32_t)st.M};
+                        vs.row_strides = {st.N};
+                        vs.col_dims = {(int32_t)st.N};
+                        vs.col_strides = {1};
+                        std::string verr = make_view(vs, &r.vc);
+                        if (!verr.empty()) return fail(c, TN_EINVAL, verr);
+                        r.part = (const double*)g.C;
+                        r.out = g.C;
+                        r.M = (int32_t)st.M;
+                        r.N = (int32_t)st.N;
+                        r.splits = st.splits;
+                        r.scale_a = r.scale_b = -1;
+                        sums.push_back(r);
+                    }
                 } else {
                     g.mode = GEMM_TENSOR;
                     g.splits = 1;
@@ -313,7 +334,7 @@ tn_status build_launches(tn_ctx* c) {
                 gd.fx = (const double*)buf_ptr(xbuf);
                 gd.gram_y = ygram ? (const double*)buf_ptr(ybuf) : nullptr;
                 gd.fy = ygram ? nullptr : (const double*)buf_ptr(ybuf);
-                gd.splits_y = xb ? cp.splits_a : cp.splits_b;
+                gd.splits_y = 1;   // the Gram partials were summed in place
                 gd.work = (double*)buf_ptr(cp.work_buf);
                 gd.p_left = buf_ptr(cp.pl_buf);
                 gd.p_right = buf_ptr(cp.pr_buf);
@@ -338,8 +359,8 @@ tn_status build_launches(tn_ctx* c) {
                 cd.fac_a = cp.gram_a ? nullptr : (const double*)buf_ptr(cp.side_a_buf);
                 cd.gram_b = cp.gram_b ? (const double*)buf_ptr(cp.side_b_buf) : nullptr;
                 cd.fac_b = cp.gram_b ? nullptr : (const double*)buf_ptr(cp.side_b_buf);
-                cd.splits_a = cp.splits_a;
-                cd.splits_b = cp.splits_b;
+                cd.splits_a = 1;   // the Gram partials were summed in place
+                cd.splits_b = 1;
                 cd.rows_a = cp.rows_a;
                 cd.rows_b = cp.rows_b;
                 cd.D = (int32_t)cp.D;
@@ -375,6 +396,23 @@ tn_status build_launches(tn_ctx* c) {
                 c->h_gemm.push_back(g);
             }
             l.work = tiles;
+            c->launches.push_back(l);
+        }
+        if (!sums.empty()) {
+            Launch l;
+            l.level = L;
+            l.kind = L_REDUCE;
+            l.key = 0;   // float64
+            l.prof = TN_KERNEL_GRAM;
+            l.begin = (int64_t)c->h_reduce.size();
+            l.count = (int)sums.size();
+            int64_t elems = 0;
+            for (auto& r : sums) {
+                r.elem_begin = elems;
+                elems += (int64_t)r.M * r.N;
+                c->h_reduce.push_back(r);
+            }
+            l.work = elems;
             c->launches.push_back(l);
         }
         if (!copies.empty()) {
@@ -469,6 +507,7 @@ tn_status build_launches(tn_ctx* c) {
     if ((s = upload(c, &c->d_inputs, c->h_inputs)) != TN_OK) return s;
     if ((s = upload(c, &c->d_lanczos, c->h_lanczos)) != TN_OK) return s;
     if ((s = upload(c, &c->d_glanczos, c->h_glanczos)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_reduce, c->h_reduce)) != TN_OK) return s;
     HIP_TRY(c, hipMalloc((void**)&c->d_scales, std::max<size_t>(1, P.tens.size()) * sizeof(double)));
     HIP_TRY(c, hipMalloc((void**)&c->d_maxparts, (size_t)max_parts * sizeof(double)));
     const size_t nc = std::max<size_t>(1, P.comps.size());
@@ -939,6 +978,9 @@ tn_status tn_enqueue(tn_ctx* c) {
             case L_SCALE:
                 err = launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, st);
                 break;
+            case L_REDUCE:
+                err = launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, st);
+                break;
         }
         if (err == hipSuccess && timed) err = hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], st);
         return err;
@@ -1334,6 +1376,7 @@ void merge_forward(tn_batch* b) {
                     case L_LANCZOS: m.begin = (int64_t)b->h_lanczos.size(); break;
                     case L_GLANCZOS: m.begin = (int64_t)b->h_glanczos.size(); break;
                     case L_SCALE: m.begin = (int64_t)b->h_scale.size(); break;
+                    case L_REDUCE: m.begin = (int64_t)b->h_reduce.size(); break;
                 }
                 for (auto& pr : kv.second) {
                     const int i = pr.first;
@@ -1389,6 +1432,13 @@ void merge_forward(tn_batch* b) {
                                 d.maxpart = (int32_t)(d.maxpart + po);
                                 shift(d.tensor, so);
                                 b->h_scale.push_back(d);
+                                break;
+                            }
+                            case L_REDUCE: {
+                                ReduceDesc r = c->h_reduce[l.begin + k];
+                                r.elem_begin = m.work;
+                                m.work += (int64_t)r.M * r.N;
+                                b->h_reduce.push_back(r);
                                 break;
                             }
                         }
@@ -1470,6 +1520,7 @@ tn_status enqueue_batch_forward(tn_batch* b) {
                                            b->ctxs[0]->plan.opts.jacobi_max_sweeps, b->d_disc, b->d_tie, b->d_sweeps,
                                            st);
             case L_SCALE: return launch_scale_finalize(b->d_scale + l.begin, l.count, b->d_maxparts, b->d_scales, st);
+            case L_REDUCE: return launch_reduce(l.key, b->d_reduce + l.begin, l.count, l.work, b->d_scales, st);
         }
         return hipSuccess;
     };

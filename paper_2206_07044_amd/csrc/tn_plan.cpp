@@ -454,8 +454,6 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                             int64_t splits = (mm + 255) / 256;
                             splits = std::min<int64_t>(splits, std::max<int64_t>(1, 1024 / tiles));
                             splits = std::min<int64_t>(splits, std::max<int64_t>(1, (32 << 20) / (D * D * 8)));
-                            // large bonds: a single workgroup sums the partials, keep them few
-                            if (D >= kLanczosMinD) splits = std::min<int64_t>(splits, 4);
                             splits = std::max<int64_t>(1, splits);
                             int64_t kps = (mm + splits - 1) / splits;
                             kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
