@@ -1238,6 +1238,63 @@ __device__ void dense_mvt(const double* __restrict__ F, int n, int D, const doub
     __syncthreads();
 }
 
+// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA, by the
+// whole workgroup: 128 x 128 tiles of C, each wave a 32 x 32 block (2 x 2 instructions of
+// 16 x 16 x 4), K staged through LDS in chunks of 32.  A(i, k) = A[i * ar + k * ac],
+// B(k, j) = B[k * br + j * bc]; stage holds 2 * 32 * 128 doubles.  Ends with a barrier.
+__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
+                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
+                            double* __restrict__ stage) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
+    const int lrow = lane & 15, lk = lane >> 4;
+    double* As = stage;              // As[k * 128 + i]
+    double* Bs = stage + 32 * 128;   // Bs[k * 128 + j]
+    const bool a_kfast = ac == 1, b_jfast = bc == 1;
+    for (int i0 = 0; i0 < M; i0 += 128)
+        for (int j0 = 0; j0 < N; j0 += 128) {
+            v4d acc[2][2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                for (int e = tid; e < 32 * 128; e += kCoreThreads) {
+                    // coalesced along whichever index has unit stride
+                    const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
+                    const int gi = i0 + ii, gk = k0 + kk;
+                    As[kk * 128 + ii] = (gi < M && gk < K) ? A[gi * ar + gk * ac] : 0.0;
+                    const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
+                    const int gj = j0 + jj, gkb = k0 + kb;
+                    Bs[kb * 128 + jj] = (gj < N && gkb < K) ? B[gkb * br + gj * bc] : 0.0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < 32; kk += 4) {
+                    const int k = kk + lk;
+                    const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
+                    const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
+                    acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
+                    acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
+                    acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
+                    acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
+                        const int gj = j0 + wc + 16 * y + lrow;
+                        if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[x][y][r];
+                    }
+        }
+    __syncthreads();
+}
+
 // C[r * cols + t] = sum_k A[k * ak + r * ar] B[k * bk + t * bt] for r < rows, t < cols, by the
 // whole workgroup: each thread owns one row and four consecutive columns, so A is read cols/4
 // times in total.  Ends with a barrier.
@@ -1274,8 +1331,9 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     const int tid = threadIdx.x;
     const int n = d.n, D = d.D, cn = d.chi_new, sm = d.s_max, ls = d.s_max + 1;
     const int64_t DD = (int64_t)D * D;
-    double* G = d.work;                          // D x D Gram of side Y (when it is a Gram)
-    double* Q = G + DD;                          // n x s_max Lanczos basis
+    double* S = d.work;                          // n x n operator F_X G_Y F_X^T
+    double* T1 = S + (int64_t)n * n;             // D x n (G_Y F_X^T) or n x my (F_X F_Y^T)
+    double* Q = T1 + (int64_t)max(D, d.my) * n;  // n x s_max Lanczos basis
     double* Wt = Q + (int64_t)n * sm;            // n x cn Ritz vectors
     double* t1 = Wt + (int64_t)n * cn;           // D
     double* t2 = t1 + D;                         // D
@@ -1291,30 +1349,18 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     double* PY = P2 + (int64_t)D * cn;           // m_y x cn (explicit Y)
     int* order = (int*)(PY + (int64_t)max(n, d.my) * cn);   // ls
     const double* FX = d.fx;
+    // the operator S = F_X G_Y F_X^T (n x n) is formed once on MFMA, so that a Lanczos step is one
+    // matvec: Y a Gram (its split partials already summed): T1 = G_Y F_X^T (D x n), S = F_X T1;
+    // Y explicit: C1 = F_X F_Y^T (n x my), S = C1 C1^T
     if (d.gram_y) {
-        for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
-            double acc = 0.0;
-            for (int p = 0; p < d.splits_y; ++p) acc += d.gram_y[(int64_t)p * DD + idx];
-            G[idx] = acc;
-        }
-        __syncthreads();
+        wg_gemm_f64(d.gram_y, D, 1, FX, 1, D, T1, n, D, n, D, lds);
+        wg_gemm_f64(FX, D, 1, T1, n, 1, S, n, n, n, D, lds);
+    } else {
+        wg_gemm_f64(FX, D, 1, d.fy, 1, D, T1, d.my, n, d.my, D, lds);
+        wg_gemm_f64(T1, d.my, 1, T1, 1, d.my, S, n, n, n, d.my, lds);
     }
-    // apply G_Y to t (D) -> out (D)
-    auto apply_gy = [&](const double* t, double* out) {
-        if (d.gram_y) {
-            dense_mv(G, D, D, t, out, 1.0);
-        } else {
-            dense_mv(d.fy, d.my, D, t, py, 1.0);
-            __syncthreads();
-            dense_mvt(d.fy, d.my, D, py, out, 1.0, part);
-        }
-        __syncthreads();
-    };
-    // S x = F_X (G_Y (F_X^T x))
     auto apply_s = [&](const double* x, double* y) {
-        dense_mvt(FX, n, D, x, t1, 1.0, part);
-        apply_gy(t1, t2);
-        dense_mv(FX, n, D, t2, y, 1.0);
+        dense_mv(S, n, n, x, y, 1.0);
         __syncthreads();
     };
 
@@ -1444,10 +1490,10 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     // all kept columns at once: P1 = F_X^T W, P2 = G_Y P1
     small_mm(FX, D, 1, Wt, 1, n, P1, D, cn, n);
     if (d.gram_y) {
-        small_mm(G, D, 1, P1, cn, 1, P2, D, cn, D);   // G_Y is symmetric: row dd = column dd
+        small_mm(T1, 1, n, Wt, 1, n, P2, D, cn, n);          // T1 W = G_Y F_X^T W
     } else {
-        small_mm(d.fy, 1, D, P1, cn, 1, PY, d.my, cn, D);
-        small_mm(d.fy, D, 1, PY, cn, 1, P2, D, cn, d.my);
+        small_mm(T1, d.my, 1, Wt, 1, n, PY, d.my, cn, n);    // C1^T W = F_Y F_X^T W
+        small_mm(d.fy, D, 1, PY, cn, 1, P2, D, cn, d.my);    // F_Y^T F_Y F_X^T W
     }
     for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
         const int dd = idx / cn, t = idx - dd * cn;

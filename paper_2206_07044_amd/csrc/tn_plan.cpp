@@ -493,7 +493,8 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         c.s_min = (int32_t)std::min<int64_t>(n, nw + 8);
                         c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(n, 8 * nw + 64), 512);
                         const int64_t sm = c.s_max, ls = sm + 1;
-                        const int64_t words = D * D + n * sm + n * nw + 2 * D + std::max(n, my) + 2 * sm + ls +
+                        const int64_t words = n * n + std::max(D, my) * n + n * sm + n * nw + 2 * D + std::max(n, my) +
+                                              2 * sm + ls +
                                               2 * ls * ls + 16 * D + 2 * D * nw + std::max(n, my) * nw + ls / 2 +
                                               8;   // 16 = waves of the kernel
                         c.work_buf = new_buf(words * 8, BUF_WORK, core.level);
