@@ -1295,26 +1295,39 @@ __device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac
     __syncthreads();
 }
 
-// C[r * cols + t] = sum_k A[k * ak + r * ar] B[k * bk + t * bt] for r < rows, t < cols, by the
-// whole workgroup: each thread owns one row and four consecutive columns, so A is read cols/4
-// times in total.  Ends with a barrier.
-__device__ void small_mm(const double* __restrict__ A, int64_t ak, int64_t ar, const double* __restrict__ B,
-                         int64_t bk, int64_t bt, double* __restrict__ C, int rows, int cols, int K) {
-    const int tb = (cols + 3) / 4;
-    for (int idx = threadIdx.x; idx < rows * tb; idx += kCoreThreads) {
-        const int r = idx % rows, t0 = 4 * (idx / rows);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        const double* a = A + r * ar;
-        for (int k = 0; k < K; ++k) {
-            const double av = a[k * ak];
-            const double* bb = B + k * bk + t0 * bt;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (t0 + q < cols) acc[q] += av * bb[q * bt];
+// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA for
+// narrow N, operands read straight from memory: each wave owns 16 x 32 blocks of C (two
+// 16 x 16 x 4 instructions per step of 4 along K).  A(i, k) = A[i * ar + k * ac],
+// B(k, j) = B[k * br + j * bc].  Ends with a barrier.
+__device__ void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int64_t ac,
+                                   const double* __restrict__ B, int64_t br, int64_t bc, double* __restrict__ C,
+                                   int64_t ldc, int M, int N, int K) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int mb = (M + 15) / 16, nb = (N + 31) / 32;
+    for (int blk = wave; blk < mb * nb; blk += kCoreWaves) {
+        const int i0 = (blk % mb) * 16, j0 = (blk / mb) * 32;
+        const int gi = i0 + lr, gj0 = j0 + lr, gj1 = j0 + 16 + lr;
+        const bool ri = gi < M, c0 = gj0 < N, c1 = gj1 < N;
+        v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            const bool kk = k < K;
+            const double a = (ri && kk) ? A[(int64_t)gi * ar + (int64_t)k * ac] : 0.0;
+            const double b0 = (kk && c0) ? B[(int64_t)k * br + (int64_t)gj0 * bc] : 0.0;
+            const double b1 = (kk && c1) ? B[(int64_t)k * br + (int64_t)gj1 * bc] : 0.0;
+            acc0 = Mma<double>::run(a, b0, acc0);
+            acc1 = Mma<double>::run(a, b1, acc1);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (t0 + q < cols) C[(int64_t)r * cols + t0 + q] = acc[q];
+        for (int r = 0; r < 4; ++r) {
+            const int row = i0 + Mma<double>::row(lane, r);
+            if (row < M) {
+                if (c0) C[(int64_t)row * ldc + gj0] = acc0[r];
+                if (c1) C[(int64_t)row * ldc + gj1] = acc1[r];
+            }
+        }
     }
     __syncthreads();
 }
@@ -1488,12 +1501,12 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
     // all kept columns at once: P1 = F_X^T W, P2 = G_Y P1
-    small_mm(FX, D, 1, Wt, 1, n, P1, D, cn, n);
+    wg_gemm_f64_narrow(FX, 1, D, Wt, 1, n, P1, cn, D, cn, n);
     if (d.gram_y) {
-        small_mm(T1, 1, n, Wt, 1, n, P2, D, cn, n);          // T1 W = G_Y F_X^T W
+        wg_gemm_f64_narrow(T1, n, 1, Wt, 1, n, P2, cn, D, cn, n);            // T1 W = G_Y F_X^T W
     } else {
-        small_mm(T1, d.my, 1, Wt, 1, n, PY, d.my, cn, n);    // C1^T W = F_Y F_X^T W
-        small_mm(d.fy, D, 1, PY, cn, 1, P2, D, cn, d.my);    // F_Y^T F_Y F_X^T W
+        wg_gemm_f64_narrow(T1, 1, d.my, Wt, 1, n, PY, cn, d.my, cn, n);      // C1^T W = F_Y F_X^T W
+        wg_gemm_f64_narrow(d.fy, 1, D, PY, cn, 1, P2, cn, D, cn, d.my);      // F_Y^T F_Y F_X^T W
     }
     for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
         const int dd = idx / cn, t = idx - dd * cn;
