@@ -17,7 +17,8 @@ using namespace tn;
 
 namespace {
 
-enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD };
+// L_SPRE: the float64 products that form a Gram-Lanczos operator (key 0: T1, key 1: S = F_X T1)
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD, L_SPRE };
 
 struct Launch {
     int kind = 0;
@@ -206,7 +207,63 @@ tn_status build_launches(tn_ctx* c) {
         int lanczos_smax = 1;
         std::vector<ScaleDesc> scales;
         std::vector<ReduceDesc> sums;
+        std::vector<GemmDesc> spre[2];
         int64_t parts = 0;
+        if (L < P.n_levels) {
+            // Gram-Lanczos cores of the next level: their operator S = F_X G_Y F_X^T (or C1 C1^T,
+            // C1 = F_X F_Y^T) is formed here, on the stream that wrote the side factors, after them
+            for (int32_t si : by_level[L + 1]) {
+                const Step& st = P.steps[si];
+                if (st.kind != ST_CORE || !P.comps[st.comp].glanczos) continue;
+                const Compression& cp = P.comps[st.comp];
+                const int xb = cp.x_is_b;
+                const int ygram = xb ? cp.gram_a : cp.gram_b;
+                const double* fx = (const double*)buf_ptr(xb ? cp.side_b_buf : cp.side_a_buf);
+                const double* y = (const double*)buf_ptr(xb ? cp.side_a_buf : cp.side_b_buf);
+                const int64_t n = xb ? cp.mb : cp.ma, my = xb ? cp.ma : cp.mb, D = cp.D;
+                double* S = (double*)buf_ptr(cp.work_buf);
+                double* T1 = S + n * n;
+                auto dense = [&](int64_t rows, int64_t rs, int64_t cols, int64_t cs, View* v) {
+                    ViewSpec vs;
+                    vs.row_dims = {(int32_t)rows};
+                    vs.row_strides = {rs};
+                    vs.col_dims = {(int32_t)cols};
+                    vs.col_strides = {cs};
+                    return make_view(vs, v);
+                };
+                auto product = [&](const double* A, int64_t M, int64_t K, int64_t ar, int64_t ac, const double* B,
+                                   int64_t N, int64_t br, int64_t bc, double* C, GemmDesc* g) {
+                    std::memset(g, 0, sizeof(*g));
+                    std::string e = dense(M, ar, K, ac, &g->va);
+                    if (e.empty()) e = dense(K, br, N, bc, &g->vb);
+                    g->A = A;
+                    g->B = B;
+                    g->C = C;
+                    g->M = (int32_t)M;
+                    g->N = (int32_t)N;
+                    g->K = (int32_t)K;
+                    g->mode = GEMM_GRAM;
+                    g->tiles_m = (int32_t)((M + 63) / 64);
+                    g->tiles_n = (int32_t)((N + 63) / 64);
+                    g->splits = 1;
+                    g->k_per_split = (int32_t)K;
+                    g->scale_a = g->scale_b = -1;
+                    return e;
+                };
+                GemmDesc g1, g2;
+                std::string err;
+                if (ygram) {   // T1 = G_Y F_X^T (D x n), S = F_X T1
+                    err = product(y, D, D, D, 1, fx, n, 1, D, T1, &g1);
+                    if (err.empty()) err = product(fx, n, D, D, 1, T1, n, n, 1, S, &g2);
+                } else {       // T1 = F_X F_Y^T (n x my), S = T1 T1^T
+                    err = product(fx, n, D, D, 1, y, my, 1, D, T1, &g1);
+                    if (err.empty()) err = product(T1, n, my, my, 1, T1, n, 1, my, S, &g2);
+                }
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                spre[0].push_back(g1);
+                spre[1].push_back(g2);
+            }
+        }
         for (int32_t si : by_level[L]) {
             const Step& st = P.steps[si];
             if (st.kind == ST_CONTRACT || st.kind == ST_ABSORB || st.kind == ST_GRAM) {
@@ -432,6 +489,24 @@ tn_status build_launches(tn_ctx* c) {
                 c->h_copy.push_back(cd);
             }
             l.work = elems;
+            c->launches.push_back(l);
+        }
+        for (int stage = 0; stage < 2; ++stage) {
+            if (spre[stage].empty()) continue;
+            Launch l;
+            l.level = L;
+            l.kind = L_SPRE;
+            l.key = stage;
+            l.prof = TN_KERNEL_LANCZOS;   // part of the Lanczos compressions' cost
+            l.begin = (int64_t)c->h_gemm.size();
+            l.count = (int)spre[stage].size();
+            int64_t tiles = 0;
+            for (auto& g : spre[stage]) {
+                g.tile_begin = tiles;
+                tiles += (int64_t)g.tiles_m * g.tiles_n;
+                c->h_gemm.push_back(g);
+            }
+            l.work = tiles;
             c->launches.push_back(l);
         }
         for (int pass = 0; pass < 2; ++pass) {
@@ -981,6 +1056,9 @@ tn_status tn_enqueue(tn_ctx* c) {
             case L_REDUCE:
                 err = launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, st);
                 break;
+            case L_SPRE:
+                err = launch_gemm(GEMM_F64, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
+                break;
         }
         if (err == hipSuccess && timed) err = hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], st);
         return err;
@@ -1370,7 +1448,8 @@ void merge_forward(tn_batch* b) {
                 m.flops = m.bytes = 0;
                 m.max_d = 0;
                 switch (kind) {
-                    case L_GEMM: m.begin = (int64_t)b->h_gemm.size(); break;
+                    case L_GEMM:
+                    case L_SPRE: m.begin = (int64_t)b->h_gemm.size(); break;
                     case L_COPY: m.begin = (int64_t)b->h_copy.size(); break;
                     case L_CORE: m.begin = (int64_t)b->h_core.size(); break;
                     case L_LANCZOS: m.begin = (int64_t)b->h_lanczos.size(); break;
@@ -1389,7 +1468,8 @@ void merge_forward(tn_batch* b) {
                     m.max_d = std::max(m.max_d, l.max_d);
                     for (int k = 0; k < l.count; ++k) {
                         switch (kind) {
-                            case L_GEMM: {
+                            case L_GEMM:
+                            case L_SPRE: {
                                 GemmDesc g = c->h_gemm[l.begin + k];
                                 shift(g.scale_a, so);
                                 shift(g.scale_b, so);
@@ -1521,6 +1601,8 @@ tn_status enqueue_batch_forward(tn_batch* b) {
                                            st);
             case L_SCALE: return launch_scale_finalize(b->d_scale + l.begin, l.count, b->d_maxparts, b->d_scales, st);
             case L_REDUCE: return launch_reduce(l.key, b->d_reduce + l.begin, l.count, l.work, b->d_scales, st);
+            case L_SPRE:
+                return launch_gemm(GEMM_F64, b->d_gemm + l.begin, l.count, l.work, b->d_scales, b->d_maxparts, st);
         }
         return hipSuccess;
     };

@@ -175,9 +175,9 @@ struct LanczosDesc {
 // Large-core compression with an explicit side X: symmetric Lanczos on F_X G_Y F_X^T.
 struct GLanczosDesc {
     const double* fx;            // explicit factor of side X (n x D, row-major)
-    const double* gram_y;        // split-K Gram partials of side Y (D x D each), or null
+    const double* gram_y;        // summed Gram of side Y (D x D), or null
     const double* fy;            // explicit factor of side Y (my x D) when it has no Gram
-    double* work;
+    double* work;                // on entry: S (n x n) then T1 (D x n, or n x my), then scratch
     void* p_left;                // D x chi'
     void* p_right;               // chi' x D
     double cutoff;

@@ -1238,63 +1238,6 @@ __device__ void dense_mvt(const double* __restrict__ F, int n, int D, const doub
     __syncthreads();
 }
 
-// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA, by the
-// whole workgroup: 128 x 128 tiles of C, each wave a 32 x 32 block (2 x 2 instructions of
-// 16 x 16 x 4), K staged through LDS in chunks of 32.  A(i, k) = A[i * ar + k * ac],
-// B(k, j) = B[k * br + j * bc]; stage holds 2 * 32 * 128 doubles.  Ends with a barrier.
-__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
-                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
-                            double* __restrict__ stage) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
-    const int lrow = lane & 15, lk = lane >> 4;
-    double* As = stage;              // As[k * 128 + i]
-    double* Bs = stage + 32 * 128;   // Bs[k * 128 + j]
-    const bool a_kfast = ac == 1, b_jfast = bc == 1;
-    for (int i0 = 0; i0 < M; i0 += 128)
-        for (int j0 = 0; j0 < N; j0 += 128) {
-            v4d acc[2][2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                for (int e = tid; e < 32 * 128; e += kCoreThreads) {
-                    // coalesced along whichever index has unit stride
-                    const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
-                    const int gi = i0 + ii, gk = k0 + kk;
-                    As[kk * 128 + ii] = (gi < M && gk < K) ? A[gi * ar + gk * ac] : 0.0;
-                    const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
-                    const int gj = j0 + jj, gkb = k0 + kb;
-                    Bs[kb * 128 + jj] = (gj < N && gkb < K) ? B[gkb * br + gj * bc] : 0.0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int kk = 0; kk < 32; kk += 4) {
-                    const int k = kk + lk;
-                    const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
-                    const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
-                    acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
-                    acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
-                    acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
-                    acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
-                        const int gj = j0 + wc + 16 * y + lrow;
-                        if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[x][y][r];
-                    }
-        }
-    __syncthreads();
-}
-
 // C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA for
 // narrow N, operands read straight from memory: each wave owns 16 x 32 blocks of C (two
 // 16 x 16 x 4 instructions per step of 4 along K).  A(i, k) = A[i * ar + k * ac],
@@ -1362,16 +1305,9 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     double* PY = P2 + (int64_t)D * cn;           // m_y x cn (explicit Y)
     int* order = (int*)(PY + (int64_t)max(n, d.my) * cn);   // ls
     const double* FX = d.fx;
-    // the operator S = F_X G_Y F_X^T (n x n) is formed once on MFMA, so that a Lanczos step is one
-    // matvec: Y a Gram (its split partials already summed): T1 = G_Y F_X^T (D x n), S = F_X T1;
-    // Y explicit: C1 = F_X F_Y^T (n x my), S = C1 C1^T
-    if (d.gram_y) {
-        wg_gemm_f64(d.gram_y, D, 1, FX, 1, D, T1, n, D, n, D, lds);
-        wg_gemm_f64(FX, D, 1, T1, n, 1, S, n, n, n, D, lds);
-    } else {
-        wg_gemm_f64(FX, D, 1, d.fy, 1, D, T1, d.my, n, d.my, D, lds);
-        wg_gemm_f64(T1, d.my, 1, T1, 1, d.my, S, n, n, n, d.my, lds);
-    }
+    // S and T1 were formed before this launch by grouped float64 GEMMs, so that a Lanczos step is
+    // one matvec: Y a Gram: T1 = G_Y F_X^T (D x n), S = F_X T1; Y explicit: T1 = C1 = F_X F_Y^T
+    // (n x my), S = C1 C1^T
     auto apply_s = [&](const double* x, double* y) {
         dense_mv(S, n, n, x, y, 1.0);
         __syncthreads();

@@ -497,7 +497,10 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                                               2 * sm + ls +
                                               2 * ls * ls + 16 * D + 2 * D * nw + std::max(n, my) * nw + ls / 2 +
                                               8;   // 16 = waves of the kernel
-                        c.work_buf = new_buf(words * 8, BUF_WORK, core.level);
+                        // the operator S and its half product T1 are formed at the sides' level,
+                        // after the side factors (same stream), so the workspace lives from there
+                        c.work_buf = new_buf(words * 8, BUF_WORK, core.level - 1);
+                        touch(c.work_buf, core.level);
                     } else {
                         c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
                     }
