@@ -490,7 +490,9 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         // X = the explicit side (the shorter one when both are explicit)
                         c.x_is_b = (mb <= D && (ma > D || mb <= ma)) ? 1 : 0;
                         const int64_t n = c.x_is_b ? mb : ma, my = c.x_is_b ? ma : mb;
-                        c.s_min = (int32_t)std::min<int64_t>(n, nw + 8);
+                        // first convergence check after chi' + 16 steps: a step is one matvec with the
+                        // precomputed operator, far cheaper than the tridiagonal eigensolve of a check
+                        c.s_min = (int32_t)std::min<int64_t>(n, nw + 16);
                         c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(n, 8 * nw + 64), 512);
                         const int64_t sm = c.s_max, ls = sm + 1;
                         const int64_t words = n * n + std::max(D, my) * n + n * sm + n * nw + 2 * D + std::max(n, my) +
