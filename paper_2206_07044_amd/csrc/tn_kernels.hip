@@ -415,10 +415,23 @@ __device__ inline double rsq_nr(double x) {
 }
 
 // Jacobi rotation annihilating the off-diagonal g of the 2 x 2 Gram [[a, g], [g, b]] of two
-// columns: zeta = (b - a) / 2g, t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) (the smaller angle),
-// c = 1 / sqrt(1 + t^2), s = c t.
+// columns, through the smaller angle theta with tan(2 theta) = 2g / (b - a): with d = b - a and
+// r = sqrt(d^2 + 4 g^2), cos(2 theta) = |d| / r, so c = sqrt((1 + |d| / r) / 2) and
+// s = sgn(d) g / (r c).  Two refined reciprocal square roots form the whole dependent chain
+// (float64 latency rules here); squares out of range take the tangent form
+// t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g, c = 1 / sqrt(1 + t^2), s = c t.
 __device__ inline void jacobi_rotation(double a, double b, double g, double* c, double* s) {
-    const double zeta = (b - a) * rcp_nr(2.0 * g);
+    const double d = b - a;
+    const double q = fma(d, d, 4.0 * g * g);
+    if (q > 1e-290 && q < 1e290) {
+        const double y = rsq_nr(q);                       // 1 / r
+        const double h = fma(0.5 * fabs(d), y, 0.5);      // c^2, in [1/2, 1]
+        const double yc = rsq_nr(h);                      // 1 / c
+        *c = h * yc;
+        *s = (d >= 0.0 ? g : -g) * y * yc;
+        return;
+    }
+    const double zeta = d * rcp_nr(2.0 * g);
     const double az = fabs(zeta);
     double root;
     if (az > 1e100) {
@@ -480,7 +493,9 @@ __device__ int pivoted_cholesky_wave(double* G, int D, double* R) {
 }
 
 __device__ inline int rr_col(int pos, int round, int n) {
-    return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
+    int v = pos - 1 + round;   // pos - 1 and round are below n - 1: one wrap at most
+    if (v >= n - 1) v -= n - 1;
+    return pos == 0 ? 0 : 1 + v;
 }
 
 // One-sided (Hestenes) Jacobi on the columns of W (rows x cols, column j at W + j*ld),
@@ -608,16 +623,26 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                 if (p1 >= cols || p2 >= cols) continue;
                 double* w1 = W + (int64_t)p1 * ld;
                 double* w2 = W + (int64_t)p2 * ld;
-                double x[4], y[4];
+                double* v1 = V + (int64_t)p1 * ld;
+                double* v2 = V + (int64_t)p2 * ld;
+                // every load up front (clamped index, then zeroed), so their latencies overlap
+                double x[4], y[4], xv[4], yv[4];
                 double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int i = ql + 16 * k;
-                    x[k] = i < rows ? w1[i] : 0.0;
-                    y[k] = i < rows ? w2[i] : 0.0;
-                    a += x[k] * x[k];
-                    b += y[k] * y[k];
-                    g += x[k] * y[k];
+                    const int iw = min(i, max(rows, 1) - 1), iv = min(i, cols - 1);
+                    x[k] = w1[iw];
+                    y[k] = w2[iw];
+                    xv[k] = v1[iv];
+                    yv[k] = v2[iv];
+                    if (i >= rows) x[k] = y[k] = 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    a = fma(x[k], x[k], a);
+                    b = fma(y[k], y[k], b);
+                    g = fma(x[k], y[k], g);
                 }
                 a = row16_sum(a);
                 b = row16_sum(b);
@@ -632,16 +657,9 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                             w1[i] = c * x[k] - s * y[k];
                             w2[i] = s * x[k] + c * y[k];
                         }
-                    }
-                    double* v1 = V + (int64_t)p1 * ld;
-                    double* v2 = V + (int64_t)p2 * ld;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int i = ql + 16 * k;
                         if (i < cols) {
-                            const double xv = v1[i], yv = v2[i];
-                            v1[i] = c * xv - s * yv;
-                            v2[i] = s * xv + c * yv;
+                            v1[i] = c * xv[k] - s * yv[k];
+                            v2[i] = s * xv[k] + c * yv[k];
                         }
                     }
                     if (ql == 0) sh.flag = 1;
