@@ -184,6 +184,17 @@ tn_status upload(tn_ctx* c, T** dst, const std::vector<T>& src) {
 std::string fill_view(const ViewSpec& s, View* v) { return make_view(s, v); }
 
 // Turn the plan's levelled steps into grouped launch descriptors.
+// Within a level, the one-workgroup compression kernels are issued before the many-workgroup
+// GEMMs: they need a whole compute unit each, which a GEMM launch issued first would occupy
+// until its workgroups drain.  Stable: the order inside each stream is kept.
+void order_for_issue(std::vector<Launch>& ls) {
+    auto first = [](const Launch& l) { return l.kind == L_CORE || l.kind == L_LANCZOS || l.kind == L_GLANCZOS; };
+    std::stable_sort(ls.begin(), ls.end(), [&](const Launch& a, const Launch& b) {
+        if (a.level != b.level) return a.level < b.level;
+        return first(a) && !first(b);
+    });
+}
+
 tn_status build_launches(tn_ctx* c) {
     Plan& P = c->plan;
     const int prec = P.opts.precision;
@@ -591,6 +602,7 @@ tn_status build_launches(tn_ctx* c) {
     HIP_TRY(c, hipMalloc((void**)&c->d_sweeps, nc * sizeof(int32_t)));
     HIP_TRY(c, hipMemset(c->d_sweeps, 0, nc * sizeof(int32_t)));
     P.max_parts = max_parts;
+    order_for_issue(c->launches);
     return TN_OK;
 }
 
@@ -1527,6 +1539,7 @@ void merge_forward(tn_batch* b) {
                 b->launches.push_back(m);
             }
     }
+    order_for_issue(b->launches);
 }
 
 void merge_backward(tn_batch* b) {

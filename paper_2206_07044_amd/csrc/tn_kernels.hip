@@ -337,6 +337,9 @@ constexpr double kZeroRel = 1e-14;    // Jacobi leaves columns below this * ||W|
 constexpr double kLanczosBreak = 1e-13;   // Krylov breakdown relative to the largest alpha/beta
 constexpr double kNoiseRelSq = 1e-13;     // eigenvalues sigma^2 of M^T M below this * sigma_1^2 are zeros
 constexpr int kCoreWaves = kCoreThreads / 64;
+// LDS-resident cores (D <= 64): four waves rotate the at most 32 column pairs of a round, and a
+// small workgroup finds room on a compute unit while the GEMMs of the same level occupy it
+constexpr int kCoreLdsThreads = 256;
 
 struct CoreShared {
     double rv[kCoreWaves];
@@ -589,6 +592,7 @@ __device__ inline double row16_sum(double v) {
 // jacobi_svd for rows, cols <= 64: each pair is rotated by one 16-lane row of a wave (up
 // to four rows of W per lane), so reductions stay inside DPP rows and a wave rotates four
 // pairs at once.  Same pair order, thresholds and result contract as jacobi_svd.
+template <int NT = kCoreThreads>
 __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
                                  int* sweeps_out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -596,7 +600,7 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
     const int nc = cols + (cols & 1);
     const double tol = 2.220446049250313e-16 * (double)max(rows, 16);
     double f = 0.0;
-    for (int idx = tid; idx < rows * cols; idx += kCoreThreads) {
+    for (int idx = tid; idx < rows * cols; idx += NT) {
         const int j = idx / rows, i = idx - j * rows;
         const double x = W[(int64_t)j * ld + i];
         f += x * x;
@@ -606,7 +610,7 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
-        for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+        for (int w = 0; w < (NT / 64); ++w) t += sh.rv[w];
         sh.rv[0] = t;
     }
     __syncthreads();
@@ -618,7 +622,7 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
         if (tid == 0) sh.flag = 0;
         __syncthreads();
         for (int round = 0; round < nc - 1; ++round) {
-            for (int q = wave * 4 + quarter; q < nc / 2; q += kCoreWaves * 4) {
+            for (int q = wave * 4 + quarter; q < nc / 2; q += (NT / 64) * 4) {
                 const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
                 if (p1 >= cols || p2 >= cols) continue;
                 double* w1 = W + (int64_t)p1 * ld;
@@ -676,16 +680,17 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
 }
 
 // Column norms of W (sig[j], j < cols) and their descending order (ties: lower column first).
+template <int NT = kCoreThreads>
 __device__ void sorted_norms(const double* W, int rows, int cols, int ld, double* sig, int* order) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int j = wave; j < cols; j += kCoreWaves) {
+    for (int j = wave; j < cols; j += (NT / 64)) {
         double s = 0.0;
         for (int i = lane; i < rows; i += 64) s += W[(int64_t)j * ld + i] * W[(int64_t)j * ld + i];
         s = wave_sum(s);
         if (lane == 0) sig[j] = sqrt(s);
     }
     __syncthreads();
-    for (int j = tid; j < cols; j += kCoreThreads) {
+    for (int j = tid; j < cols; j += NT) {
         const double sj = sig[j];
         int rank = 0;
         for (int q = 0; q < cols; ++q) rank += (sig[q] > sj) || (sig[q] == sj && q < j);
@@ -695,12 +700,13 @@ __device__ void sorted_norms(const double* W, int rows, int cols, int ld, double
 }
 
 template <bool kLds, typename Tp>
-__global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
+__global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
                                                             double* __restrict__ stat_disc,
                                                             int32_t* __restrict__ stat_tie,
                                                             int32_t* __restrict__ stat_sweeps) {
     extern __shared__ double lds[];
     __shared__ CoreShared sh;
+    constexpr int NT = kLds ? kCoreLdsThreads : kCoreThreads;
     const CoreDesc& d = descs[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int D = d.D;
@@ -725,7 +731,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
             if (gram) {
                 const int splits = side == 0 ? d.splits_a : d.splits_b;
                 double* G = side == 0 ? W : V;
-                for (int idx = tid; idx < DDi; idx += kCoreThreads) {
+                for (int idx = tid; idx < DDi; idx += NT) {
                     const double* g = gram + idx;
                     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
                     int p = 0;
@@ -742,7 +748,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
                 const int rows = side == 0 ? d.rows_a : d.rows_b;
                 const double* fac = side == 0 ? d.fac_a : d.fac_b;
                 double* R = side == 0 ? Ra : Rb;
-                for (int idx = tid; idx < rows * D; idx += kCoreThreads) R[idx] = fac[idx];
+                for (int idx = tid; idx < rows * D; idx += NT) R[idx] = fac[idx];
             }
         }
         __syncthreads();
@@ -763,7 +769,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
             double* R = side == 0 ? Ra : Rb;
             if (gram) {
                 const int splits = side == 0 ? d.splits_a : d.splits_b;
-                for (int64_t idx = tid; idx < DD; idx += kCoreThreads) {
+                for (int64_t idx = tid; idx < DD; idx += NT) {
                     double s = 0.0;
                     for (int p = 0; p < splits; ++p) s += gram[(int64_t)p * DD + idx];
                     W[idx] = s;
@@ -772,7 +778,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
                 rk[side] = pivoted_cholesky(W, D, R, chosen, sh);
             } else {
                 const int rows = side == 0 ? d.rows_a : d.rows_b;
-                for (int64_t idx = tid; idx < (int64_t)rows * D; idx += kCoreThreads) R[idx] = fac[idx];
+                for (int64_t idx = tid; idx < (int64_t)rows * D; idx += NT) R[idx] = fac[idx];
                 rk[side] = rows;
             }
             __syncthreads();
@@ -782,7 +788,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
     }
 
     // ---- core W = R~_A R~_B^T  (ra x rb), V = I
-    for (int idx = tid; idx < ra * rb; idx += kCoreThreads) {
+    for (int idx = tid; idx < ra * rb; idx += NT) {
         const int j = idx / ra, i = idx - j * ra;
         const double* x = Ra + (int64_t)i * D;
         const double* y = Rb + (int64_t)j * D;
@@ -795,7 +801,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
         }
         W[(int64_t)j * D + i] = s;
     }
-    for (int idx = tid; idx < rb * rb; idx += kCoreThreads) {
+    for (int idx = tid; idx < rb * rb; idx += NT) {
         const int j = idx / rb, i = idx - j * rb;
         V[(int64_t)j * D + i] = (i == j) ? 1.0 : 0.0;
     }
@@ -803,11 +809,15 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
 
     // ---- one-sided (Hestenes) Jacobi on the columns of W, accumulating V
     int sweeps = 0;
-    const bool converged = (ra <= 64 && rb <= 64) ? jacobi_svd_small(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
-                                                  : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
+    bool converged;
+    if constexpr (kLds)   // ra, rb <= D <= 64
+        converged = jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
+    else
+        converged = (ra <= 64 && rb <= 64) ? jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                                           : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
 
     // ---- singular values and descending order (ties: lower column first)
-    sorted_norms(W, ra, rb, D, sig, order);
+    sorted_norms<NT>(W, ra, rb, D, sig, order);
     double fro = 0.0;
     for (int j = 0; j < rb; ++j) fro += sig[j] * sig[j];
     fro = sqrt(fro);
@@ -817,7 +827,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
     const double smax = rb > 0 ? sig[order[0]] : 0.0;
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
-    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+    for (int idx = tid; idx < D * cn; idx += NT) {
         const int dd = idx / cn, t = idx - dd * cn;
         const int j = t < rb ? order[t] : -1;
         const double s = j >= 0 ? sig[j] : 0.0;
@@ -841,7 +851,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(const CoreDesc* __re
     // ---- what the reverse pass reads back: factors, core, V (LDS variant) and the ranks
     if (kLds && d.keep_out) {
         double* gw = d.work;
-        for (int idx = tid; idx < 4 * D * D; idx += kCoreThreads) {
+        for (int idx = tid; idx < 4 * D * D; idx += NT) {
             const int part = idx / (D * D), off = idx - part * D * D;
             const double* src = part == 0 ? Ra : part == 1 ? Rb : part == 2 ? W : V;
             gw[idx] = src[off];
@@ -1933,7 +1943,7 @@ void init_kernel_attrs() {
 hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
                        double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s) {
     if (ndesc == 0) return hipSuccess;
-    dim3 grid(ndesc), block(kCoreThreads);
+    dim3 grid(ndesc), block(lds ? kCoreLdsThreads : kCoreThreads);
     const size_t bytes = core_lds_bytes(max_d);
     return by_prec(prec, [&](auto t) {
         using Tp = decltype(t);
