@@ -116,6 +116,9 @@ namespace {
 // Gram / float64-partial outputs, by tensor precision (0 float64, 1 float32, 2 bfloat16).
 int tensor_key(int prec) { return prec == 0 ? GEMM_F64 : prec == 1 ? GEMM_F32 : GEMM_BF16; }
 int wide_key(int prec) { return prec == 0 ? GEMM_F64 : prec == 1 ? GEMM_F32_TO_F64 : GEMM_BF16_TO_F64; }
+int narrow_gram_key(int prec) {
+    return prec == 0 ? GEMM_GRAM_NARROW_F64 : prec == 1 ? GEMM_GRAM_NARROW_F32 : GEMM_GRAM_NARROW_BF16;
+}
 
 tn_status fail(tn_ctx* c, tn_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -299,7 +302,7 @@ tn_status build_launches(tn_ctx* c) {
                     g.k_per_split = st.k_per_split;
                     g.scale_a = st.in_a;
                     g.square_a = 1;
-                    key = 2 * wide_key(prec) + 1;
+                    key = 2 * (st.M <= kGramNarrowMaxD ? narrow_gram_key(prec) : wide_key(prec)) + 1;
                     if (st.splits > 1) {
                         // the split partials are summed in place right after the level's Gram
                         // GEMMs (same stream, many workgroups), so readers see one matrix

@@ -307,6 +307,141 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
 }
 
 // ------------------------------------------------------------------------------------------
+// Grouped Gram of a narrow side: C[split] (D x D, float64) = f * X^T X over one row range, X the
+// (K x D) matricisation of a tensor (view va: rows = D, cols = K), D <= 64.  A workgroup takes
+// one split: chunks of kGramKC rows are staged through LDS as float64 (double buffered, one
+// barrier per chunk), and each wave accumulates 16 x 16 blocks of the upper triangle on the
+// float64 MFMA; the lower triangle is written by symmetry.
+// ------------------------------------------------------------------------------------------
+constexpr int kGramThreads = 256, kGramKC = 32;
+
+template <typename Tin>
+__global__ __launch_bounds__(kGramThreads) void gram_narrow_grouped(const GemmDesc* __restrict__ descs, int ndesc,
+                                                                   const double* __restrict__ scales) {
+    __shared__ double Xs[2][kGramKC][65];
+    __shared__ uint32_t koff[2][kGramKC];
+    __shared__ uint32_t doff[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_begin <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc& d = descs[lo];
+    const int D = d.M, K = d.K;
+    const int split = (int)(tile - d.tile_begin);
+    const int k_begin = split * d.k_per_split;
+    const int k_end = min(K, k_begin + d.k_per_split);
+    const Tin* __restrict__ X = (const Tin*)d.A;
+    if (tid < D) doff[tid] = axis_offset(d.va.row, (uint32_t)tid);
+    // staging map: 8 elements per thread, lanes along whichever index has unit stride
+    const bool kfast = d.va.col_unit != 0;
+    int st_k[8], st_d[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (kfast) {
+            st_k[j] = tid & 31;
+            st_d[j] = (tid >> 5) + 8 * j;
+        } else {
+            st_d[j] = tid & 63;
+            st_k[j] = (tid >> 6) + 4 * j;
+        }
+    }
+    auto fill_koff = [&](int buf, int kc) {
+        if (tid < kGramKC) {
+            const int gk = kc + tid;
+            koff[buf][tid] = gk < k_end ? axis_offset(d.va.col, (uint32_t)gk) : 0u;
+        }
+    };
+    double r[8];
+    auto load_chunk = [&](int buf, int kc) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int kk = st_k[j], dd = st_d[j];
+            r[j] = (dd < D && kc + kk < k_end) ? (double)X[doff[dd] + koff[buf][kk]] : 0.0;
+        }
+    };
+    // upper-triangle 16 x 16 blocks (bi <= bj) dealt round-robin to the waves; a single block is
+    // shared by all four waves, each taking every fourth step along K
+    const int nbd = (D + 15) / 16, nblk = nbd * (nbd + 1) / 2;
+    const bool shared_blk = nblk == 1;
+    int bi[3] = {0, 0, 0}, bj[3] = {0, 0, 0}, nmine = 0;
+    for (int b = shared_blk ? 0 : wave; b < nblk && nmine < 3; b += 4) {
+        int row = 0, rem = b;
+        while (rem >= nbd - row) {
+            rem -= nbd - row;
+            ++row;
+        }
+        bi[nmine] = row;
+        bj[nmine] = row + rem;
+        ++nmine;
+    }
+    v4d acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int lr = lane & 15, lk = lane >> 4;
+
+    __syncthreads();   // doff
+    fill_koff(0, k_begin);
+    __syncthreads();
+    if (k_begin < k_end) load_chunk(0, k_begin);
+    int buf = 0;
+    for (int kc = k_begin; kc < k_end; kc += kGramKC) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Xs[buf][st_k[j]][st_d[j]] = r[j];
+        if (kc + kGramKC < k_end) fill_koff(buf ^ 1, kc + kGramKC);
+        __syncthreads();
+        if (kc + kGramKC < k_end) load_chunk(buf ^ 1, kc + kGramKC);
+#pragma unroll
+        for (int ks = 0; ks < kGramKC / 4; ++ks) {
+            if (shared_blk && (ks & 3) != wave) continue;
+            const int k = 4 * ks + lk;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (q < nmine) {
+                    const double a = Xs[buf][k][16 * bi[q] + lr];
+                    const double b = Xs[buf][k][16 * bj[q] + lr];
+                    acc[q] = Mma<double>::run(a, b, acc[q]);
+                }
+        }
+        buf ^= 1;
+    }
+    const double fa = inv_scale(scales, d.scale_a);
+    const double factor = fa * fa;
+    double* C = (double*)d.C + (int64_t)split * D * D;
+    if (shared_blk) {
+        // the four waves' partial sums of the one block meet in LDS (staging is over)
+        __syncthreads();
+        double* red = &Xs[0][0][0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[(wave * 64 + lane) * 4 + q] = acc[0][q];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc[0][q] = ((red[lane * 4 + q] + red[(64 + lane) * 4 + q]) + red[(128 + lane) * 4 + q]) +
+                            red[(192 + lane) * 4 + q];
+        } else {
+            nmine = 0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (q < nmine)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int gi = 16 * bi[q] + Mma<double>::row(lane, rr), gj = 16 * bj[q] + lr;
+                if (gi < D && gj < D) {
+                    const double v = acc[q][rr] * factor;
+                    C[(int64_t)gi * D + gj] = v;
+                    C[(int64_t)gj * D + gi] = v;
+                }
+            }
+}
+
+// ------------------------------------------------------------------------------------------
 // Gather copy (explicit reduced factor when a side has no more rows than D)
 // ------------------------------------------------------------------------------------------
 template <typename Tin>
@@ -1607,6 +1742,15 @@ hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t 
         case GEMM_F32_TO_F64: gemm_grouped<float, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
         case GEMM_BF16: gemm_grouped<bf16, bf16, bf16><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
         case GEMM_BF16_TO_F64: gemm_grouped<bf16, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
+        case GEMM_GRAM_NARROW_F64:
+            gram_narrow_grouped<double><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales);
+            break;
+        case GEMM_GRAM_NARROW_F32:
+            gram_narrow_grouped<float><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales);
+            break;
+        case GEMM_GRAM_NARROW_BF16:
+            gram_narrow_grouped<bf16><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -8,7 +8,9 @@
 
 namespace tn {
 
-enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2, GEMM_BF16 = 3, GEMM_BF16_TO_F64 = 4 };
+// GEMM_GRAM_NARROW_*: forward Gram X^T X of a side with D <= 64 (by input type), float64 result
+enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2, GEMM_BF16 = 3, GEMM_BF16_TO_F64 = 4,
+               GEMM_GRAM_NARROW_F64 = 5, GEMM_GRAM_NARROW_F32 = 6, GEMM_GRAM_NARROW_BF16 = 7 };
 
 constexpr int kCoreLdsMaxD = 64;
 constexpr int kLanczosMaxSteps = 512;     // cap on Krylov steps per compression

@@ -451,13 +451,20 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                             // compressions of one level are few, so latency, not throughput, rules);
                             // about a thousand workgroups per Gram and 32 MiB of partials at most
                             const int64_t tiles = ((D + 63) / 64) * ((D + 63) / 64);
-                            int64_t splits = (mm + 255) / 256;
-                            splits = std::min<int64_t>(splits, std::max<int64_t>(1, 1024 / tiles));
-                            splits = std::min<int64_t>(splits, std::max<int64_t>(1, (32 << 20) / (D * D * 8)));
-                            splits = std::max<int64_t>(1, splits);
-                            int64_t kps = (mm + splits - 1) / splits;
-                            kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
-                            splits = (mm + kps - 1) / kps;
+                            int64_t splits, kps;
+                            if (D <= kGramNarrowMaxD) {
+                                // narrow side (its own kernel, one 512-row range per workgroup)
+                                kps = 512;
+                                splits = (mm + kps - 1) / kps;
+                            } else {
+                                splits = (mm + 255) / 256;
+                                splits = std::min<int64_t>(splits, std::max<int64_t>(1, 1024 / tiles));
+                                splits = std::min<int64_t>(splits, std::max<int64_t>(1, (32 << 20) / (D * D * 8)));
+                                splits = std::max<int64_t>(1, splits);
+                                kps = (mm + splits - 1) / splits;
+                                kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
+                                splits = (mm + kps - 1) / kps;
+                            }
                             st.splits = (int32_t)splits;
                             st.k_per_split = (int32_t)kps;
                             st.out_buf = new_buf(splits * D * D * 8, BUF_GRAM, st.level);

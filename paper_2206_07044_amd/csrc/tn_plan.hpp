@@ -58,6 +58,9 @@ struct TensorVer {
 
 enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS };
 
+// Gram steps of sides with D <= kGramNarrowMaxD run on the narrow-Gram kernel (512 rows per split)
+constexpr int kGramNarrowMaxD = 64;
+
 struct ViewSpec {                   // a View before arena addresses are known
     std::vector<int32_t> row_dims, col_dims;            // slowest..fastest
     std::vector<int64_t> row_strides, col_strides;
