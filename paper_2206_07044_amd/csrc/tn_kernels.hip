@@ -595,17 +595,12 @@ __device__ int pivoted_cholesky_wave(double* G, int D, double* R) {
     double tol = 0.0;
     int r = 0;
     for (int t = 0; t < D; ++t) {
-        double bv = chosen ? -1.0 : diag;
-        int bi = chosen ? 0x7fffffff : l;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            const double ov = __shfl_xor(bv, o, 64);
-            const int oi = __shfl_xor(bi, o, 64);
-            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-        }
+        // pivot: the largest remaining diagonal (DPP maximum), lowest lane on ties (ballot)
+        const double cand = chosen ? -1.0 : diag;
+        const double bv = wave_max(cand);
         if (t == 0) tol = 1e-15 * bv;
         if (!(bv > tol) || !(bv > 0.0)) break;
-        const int p = bi;
+        const int p = __ffsll((unsigned long long)__ballot(!chosen && cand == bv)) - 1;
         const double rp = sqrt(bv);
         double v = 0.0;
         if (!chosen) v = (l == p) ? rp : G[p * D + l] / rp;
@@ -851,9 +846,13 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     double* V = W + DD;                          // column-major right singular vectors
     double* Ra = kLds ? lds + 2 * DD : d.work;   // row-major R~_A, row t at Ra + t*D
     double* Rb = Ra + DD;
-    double* sig = d.work + 4 * DD;
-    int* order = (int*)(sig + D);
-    int* chosen = order + D;
+    double* gsig = d.work + 4 * DD;              // global copies read by the reverse pass
+    int* gorder = (int*)(gsig + D);
+    int* chosen = gorder + D;
+    __shared__ double lsig[kLds ? kCoreLdsMaxD : 1];
+    __shared__ int lorder[kLds ? kCoreLdsMaxD : 1];
+    double* sig = kLds ? lsig : gsig;
+    int* order = kLds ? lorder : gorder;
 
     // ---- reduced factors R~_A (ra x D), R~_B (rb x D)
     int ra, rb;
@@ -983,7 +982,8 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         PR[(int64_t)t * D + dd] = (Tp)pr;
     }
 
-    // ---- what the reverse pass reads back: factors, core, V (LDS variant) and the ranks
+    // ---- what the reverse pass reads back: factors, core, V, singular values, order (LDS
+    // variant) and the ranks
     if (kLds && d.keep_out) {
         double* gw = d.work;
         for (int idx = tid; idx < 4 * D * D; idx += NT) {
@@ -991,9 +991,13 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
             const double* src = part == 0 ? Ra : part == 1 ? Rb : part == 2 ? W : V;
             gw[idx] = src[off];
         }
+        for (int j = tid; j < rb; j += NT) {
+            gsig[j] = sig[j];
+            gorder[j] = order[j];
+        }
     }
     if (tid == 0) {
-        int* ranks = (int*)(sig + 2 * D);
+        int* ranks = (int*)(gsig + 2 * D);
         ranks[0] = ra;
         ranks[1] = rb;
     }
