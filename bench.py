@@ -37,6 +37,26 @@ PEAKS = {  # MI355X published dense peaks
 }
 
 
+# HBM traffic per launch of a kernel kind on the default workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by a plain copy of known size; valid only for the kernel source it
+# was measured on (SHA-256 prefix of tn_kernels.hip), else the bench line reports null.
+MEASURED_TRAFFIC = {
+    ("core_lds", "fp32", "ising-cubic-12x12x12-beta0.22-chi16-span-sweep"): {
+        "bytes_per_launch": 392.6 * 1024, "kernel_source_sha256": "6e6df7e1fa7bab35",
+        "source": "profiles/core_lds_traffic_ising12_chi16_fp32.md"},
+}
+
+
+def measured_traffic(kind, precision, workload):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((kind, precision, workload))
+    if rec is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2206_07044_amd", "csrc", "tn_kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return rec["bytes_per_launch"] if sha.startswith(rec["kernel_source_sha256"]) else None
+
+
 def build_instance(shape, beta):
     from tninputs import ising_tensors, lattice
     from tninputs.trees import sweep_tree
@@ -174,6 +194,7 @@ def main() -> int:
     avg_ms = prof["ms"] / launches
     bound, unit, peak, achieved = roofline_of(dominant, prof, avg_ms, launches, args.precision)
 
+    workload = f"ising-cubic-{'x'.join(map(str, shape))}-beta{args.beta}-chi{args.chi}-span-sweep"
     out = {
         "metric": METRIC,
         "value": trees_per_s,
@@ -188,7 +209,7 @@ def main() -> int:
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": f"ising-cubic-{'x'.join(map(str, shape))}-beta{args.beta}-chi{args.chi}-span-sweep",
+            "workload": workload,
             "lattice": list(shape), "beta": args.beta, "chi": args.chi, "batch": 1,
             "tree": "Span family, axis-ordered spanning tree swept leaves-inwards",
             "compression": "early, gauge distance r=0",
@@ -204,7 +225,9 @@ def main() -> int:
         },
         "roofline": {
             "kernel": dominant, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak if peak else None, "traffic": None,
+            "frac": achieved / peak if peak else None,
+            "traffic": measured_traffic(dominant, args.precision, workload),
+            "traffic_unit": "bytes per launch",
             "launches_per_step": prof["launches"] / args.steps, "avg_launch_ms": avg_ms,
             "kernel_ms_per_step": {k: v["ms"] / max(1, args.warmup) for k, v in kinds.items()},
         },
