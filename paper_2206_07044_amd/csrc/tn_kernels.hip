@@ -1480,13 +1480,49 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         __syncthreads();
     };
 
-    for (int i = tid; i < n; i += kCoreThreads) Q[i] = probe_entry(i, 0);
-    __syncthreads();
+    // Lanczos basis: its first jl columns live in LDS, after the room kept for the tridiagonal
+    // solve (s <= kTriLdsS), the rest in the workspace
+    constexpr int kTriLdsS = 48;
+    double* lq = lds + 2 * kTriLdsS * kTriLdsS;
+    const int jl = min(sm, (int)(((int64_t)kLanczosLdsBytes / 8 - 2 * kTriLdsS * kTriLdsS) / max(n, 1)));
+    auto qcol = [&](int j) -> double* { return j < jl ? lq + (int64_t)j * n : Q + (int64_t)j * n; };
+    // x -= Q[:, :k] (Q[:, :k]^T x), twice (classical Gram-Schmidt with reorthogonalisation).
+    // Returns the sum of the two passes' coefficients of column k - 1 and ||x||^2 after them.
+    const int wave = tid >> 6, lane = tid & 63;
+    auto cgs2 = [&](double* x, int k, double* last_coef) -> double {
+        double lc = 0.0, nrm2 = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c = wave; c < k; c += kCoreWaves) {
+                const double* q = qcol(c);
+                double v = 0.0;
+                for (int i = lane; i < n; i += 64) v += q[i] * x[i];
+                v = wave_sum(v);
+                if (lane == 0) coef[c] = v;
+            }
+            __syncthreads();
+            if (k > 0) lc += coef[k - 1];
+            double part = 0.0;
+            for (int i = tid; i < n; i += kCoreThreads) {
+                double acc = x[i];
+                for (int c = 0; c < k; ++c) acc -= qcol(c)[i] * coef[c];
+                x[i] = acc;
+                part += acc * acc;
+            }
+            if (pass == 1) nrm2 = block_sum(part, sh);
+            else __syncthreads();
+        }
+        if (last_coef) *last_coef = lc;
+        return nrm2;
+    };
+
     {
+        double* q0 = qcol(0);
+        for (int i = tid; i < n; i += kCoreThreads) q0[i] = probe_entry(i, 0);
+        __syncthreads();
         double nrm = 0.0;
-        for (int i = tid; i < n; i += kCoreThreads) nrm += Q[i] * Q[i];
+        for (int i = tid; i < n; i += kCoreThreads) nrm += q0[i] * q0[i];
         nrm = sqrt(block_sum(nrm, sh));
-        for (int i = tid; i < n; i += kCoreThreads) Q[i] /= nrm;
+        for (int i = tid; i < n; i += kCoreThreads) q0[i] /= nrm;
         __syncthreads();
     }
     int s = 0, restarts = 0, nev = 0;
@@ -1496,26 +1532,16 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     double* W = Wg;
     double* Vs = Vg;
     int lw = ls;
-    double* qnext = py;   // reuse as the next Lanczos vector candidate (length n)
+    double* qnext = py;   // the next Lanczos vector candidate (length n)
     for (;;) {
         for (; s < target && !exhausted; ++s) {
             const int j = s;
-            double* qj = Q + (int64_t)j * n;
-            apply_s(qj, qnext);
+            apply_s(qcol(j), qnext);
+            // full orthogonalisation against q_0..q_j: q_j's coefficient is alpha_j, the remaining
+            // norm beta_j (the three-term recurrence in exact arithmetic)
             double a = 0.0;
-            for (int i = tid; i < n; i += kCoreThreads) a += qnext[i] * qj[i];
-            a = block_sum(a, sh);
+            const double b = sqrt(cgs2(qnext, j + 1, &a));
             alpha[j] = a;
-            for (int i = tid; i < n; i += kCoreThreads) {
-                double v = qnext[i] - a * qj[i];
-                if (j > 0) v -= beta[j - 1] * Q[(int64_t)(j - 1) * n + i];
-                qnext[i] = v;
-            }
-            __syncthreads();
-            reorthogonalise(qnext, Q, n, j + 1, coef);
-            double b = 0.0;
-            for (int i = tid; i < n; i += kCoreThreads) b += qnext[i] * qnext[i];
-            b = sqrt(block_sum(b, sh));
             bmax = fmax(bmax, fmax(b, fabs(a)));
             if (j + 1 >= n) {   // the basis spans the whole space
                 beta[j] = 0.0;
@@ -1523,7 +1549,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
                 s = j + 1;
                 break;
             }
-            double* qn = Q + (int64_t)(j + 1) * n;
+            double* qn = qcol(j + 1);
             if (b > kLanczosBreak * bmax) {
                 beta[j] = b;
                 for (int i = tid; i < n; i += kCoreThreads) qn[i] = qnext[i] / b;
@@ -1533,10 +1559,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
                 ++restarts;
                 for (int i = tid; i < n; i += kCoreThreads) qn[i] = probe_entry(i, restarts);
                 __syncthreads();
-                reorthogonalise(qn, Q, n, j + 1, coef);
-                double rn = 0.0;
-                for (int i = tid; i < n; i += kCoreThreads) rn += qn[i] * qn[i];
-                rn = sqrt(block_sum(rn, sh));
+                const double rn = sqrt(cgs2(qn, j + 1, nullptr));
                 if (!(rn > 1e-8)) {
                     exhausted = true;
                     s = j + 1;
@@ -1548,7 +1571,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         }
         // eigenpairs of the s x s tridiagonal T (symmetric positive semidefinite: its
         // one-sided Jacobi SVD gives eigenvalues as column norms and eigenvectors in Vs)
-        if ((size_t)2 * s * s * sizeof(double) <= (size_t)kLanczosLdsBytes) {
+        if (s <= kTriLdsS) {
             W = lds;
             Vs = lds + (int64_t)s * s;
             lw = s;
@@ -1595,7 +1618,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         double acc = 0.0;
         if (t < nev) {
             const int c = order[t];
-            for (int j = 0; j < nev; ++j) acc += Q[(int64_t)j * n + i] * Vs[(int64_t)c * lw + j];
+            for (int j = 0; j < nev; ++j) acc += qcol(j)[i] * Vs[(int64_t)c * lw + j];
         }
         Wt[(int64_t)t * n + i] = acc;
     }
