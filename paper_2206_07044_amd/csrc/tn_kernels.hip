@@ -480,6 +480,7 @@ struct CoreShared {
     double rv[kCoreWaves];
     int ri[kCoreWaves];
     int flag;
+    int flag_big;                // a rotation of the sweep had |g| > 1e-8 sqrt(a b)
     double row[kCoreLdsMaxD];
 };
 
@@ -631,6 +632,11 @@ __device__ inline int rr_col(int pos, int round, int n) {
     return pos == 0 ? 0 : 1 + v;
 }
 
+// A sweep whose rotations all had |g| <= 1e-8 sqrt(a b) ends the iteration: convergence is
+// quadratic, so the off-diagonal it leaves is of order 1e-16 relative, and a confirming sweep
+// would rotate nothing above the tolerance.
+constexpr double kQuadRel2 = 1e-16;
+
 // One-sided (Hestenes) Jacobi on the columns of W (rows x cols, column j at W + j*ld),
 // accumulating the rotations in V (cols x cols, column j at V + j*ld, identity on entry).
 // Pairs follow a round-robin tournament; one wave rotates one pair.  A pair is rotated
@@ -664,7 +670,7 @@ __device__ bool jacobi_svd(double* W, double* V, int rows, int cols, int ld, int
     int sweeps = 0;
     bool converged = (cols <= 1);
     for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-        if (tid == 0) sh.flag = 0;
+        if (tid == 0) sh.flag = sh.flag_big = 0;
         __syncthreads();
         for (int round = 0; round < nc - 1; ++round) {
             for (int q = wave; q < nc / 2; q += kCoreWaves) {
@@ -697,13 +703,16 @@ __device__ bool jacobi_svd(double* W, double* V, int rows, int cols, int ld, int
                         v1[i] = c * x - s * y;
                         v2[i] = s * x + c * y;
                     }
-                    if (lane == 0) sh.flag = 1;
+                    if (lane == 0) {
+                        sh.flag = 1;
+                        if (g * g > kQuadRel2 * a * b) sh.flag_big = 1;
+                    }
                 }
             }
             __syncthreads();
         }
         sweeps = sweep + 1;
-        if (!sh.flag) converged = true;
+        if (!sh.flag || !sh.flag_big) converged = true;
         __syncthreads();
     }
     *sweeps_out = sweeps;
@@ -749,7 +758,7 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
     int sweeps = 0;
     bool converged = (cols <= 1);
     for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
-        if (tid == 0) sh.flag = 0;
+        if (tid == 0) sh.flag = sh.flag_big = 0;
         __syncthreads();
         for (int round = 0; round < nc - 1; ++round) {
             for (int q = wave * 4 + quarter; q < nc / 2; q += (NT / 64) * 4) {
@@ -796,13 +805,16 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                             v2[i] = s * xv[k] + c * yv[k];
                         }
                     }
-                    if (ql == 0) sh.flag = 1;
+                    if (ql == 0) {
+                        sh.flag = 1;
+                        if (g * g > kQuadRel2 * a * b) sh.flag_big = 1;
+                    }
                 }
             }
             __syncthreads();
         }
         sweeps = sweep + 1;
-        if (!sh.flag) converged = true;
+        if (!sh.flag || !sh.flag_big) converged = true;
         __syncthreads();
     }
     *sweeps_out = sweeps;
