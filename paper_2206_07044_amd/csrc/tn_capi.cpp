@@ -108,6 +108,19 @@ struct tn_ctx {
     double prof_ms[kKinds] = {0};
     int64_t prof_launches[kKinds] = {0};
     double prof_flops[kKinds] = {0}, prof_bytes[kKinds] = {0};
+
+    // forward-pass timing: device stamps around each profiled launch (valid inside graphs)
+    unsigned long long* d_stamps = nullptr;
+    size_t stamps_cap = 0;                          // stamp pairs
+    std::vector<std::pair<int, int>> st_used;       // (kind, stamp pair)
+    // the forward schedule captured once per plan (and profiling mask) and replayed; the stamps and
+    // counts that one evaluation adds to the profile, replayed with it
+    hipGraph_t fgraph = nullptr;
+    hipGraphExec_t fexec = nullptr;
+    uint32_t fgraph_mask = 0;
+    std::vector<std::pair<int, int>> fgraph_st;
+    int64_t fgraph_launches[kKinds] = {0};
+    double fgraph_flops[kKinds] = {0}, fgraph_bytes[kKinds] = {0};
 };
 
 namespace {
@@ -138,7 +151,16 @@ void dfree(T*& p) {
     p = nullptr;
 }
 
+void free_forward_graph(tn_ctx* c) {
+    if (c->fexec) (void)hipGraphExecDestroy(c->fexec);
+    if (c->fgraph) (void)hipGraphDestroy(c->fgraph);
+    c->fexec = nullptr;
+    c->fgraph = nullptr;
+    c->fgraph_st.clear();
+}
+
 void free_plan(tn_ctx* c) {
+    free_forward_graph(c);
     dfree(c->arena);
     c->arena_cap = 0;
     dfree(c->d_gemm);
@@ -872,6 +894,7 @@ void tn_destroy(tn_ctx* c) {
     dfree(c->d_ising_i32);
     dfree(c->d_ising_off);
     dfree(c->d_result);
+    dfree(c->d_stamps);
     if (c->h_result) (void)hipHostFree(c->h_result);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1020,27 +1043,33 @@ tn_status tn_plan_info(const tn_ctx* c, int64_t* arena_bytes, double* fwd_flops,
     return TN_OK;
 }
 
-tn_status tn_enqueue(tn_ctx* c) {
-    if (!c) return TN_EINVAL;
-    if (!c->has_plan) return fail(c, TN_ESTATE, "evaluate before tn_set_tree");
-    (void)hipSetDevice(c->device);
+// Add the stamped durations of the finished evaluation to the profile (stream synchronised).
+tn_status collect_stamps(tn_ctx* c) {
+    if (c->st_used.empty()) return TN_OK;
+    int npairs = 0;
+    for (auto& u : c->st_used) npairs = std::max(npairs, u.second + 1);
+    std::vector<unsigned long long> h(2 * (size_t)npairs);
+    HIP_TRY(c, hipMemcpy(h.data(), c->d_stamps, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (auto& u : c->st_used) c->prof_ms[u.first] += (double)(h[2 * u.second + 1] - h[2 * u.second]) * 1e-5;
+    c->st_used.clear();
+    return TN_OK;
+}
+
+// Enqueue one forward evaluation on the context's streams (eager, or inside a capture).
+tn_status enqueue_forward(tn_ctx* c) {
     Plan& P = c->plan;
     const int prec = P.opts.precision;
     hipStream_t s = c->stream;
     HIP_TRY(c, launch_inputs(prec, c->d_inputs, (int)c->h_inputs.size(), c->d_staging, c->d_scales, s));
     auto run = [&](const Launch& l, hipStream_t st) -> hipError_t {
         const bool timed = (c->prof_mask >> l.prof) & 1u;
+        int pair = -1;
         if (timed) {
-            const size_t i0 = c->ev_used.empty() ? 0 : c->ev_used.back().second + 2;
-            while (c->ev_pool.size() < i0 + 2) {
-                hipEvent_t e;
-                hipError_t err = hipEventCreate(&e);
-                if (err != hipSuccess) return err;
-                c->ev_pool.push_back(e);
-            }
-            hipError_t err = hipEventRecord(c->ev_pool[i0], st);
+            pair = (int)c->st_used.size();
+            if ((size_t)pair >= c->stamps_cap) return hipErrorInvalidValue;   // sized before enqueueing
+            hipError_t err = launch_stamp(c->d_stamps + 2 * pair, st);
             if (err != hipSuccess) return err;
-            c->ev_used.push_back({l.prof, i0});
+            c->st_used.push_back({l.prof, pair});
             c->prof_launches[l.prof] += 1;
             c->prof_flops[l.prof] += l.flops;
             c->prof_bytes[l.prof] += l.bytes;
@@ -1075,7 +1104,7 @@ tn_status tn_enqueue(tn_ctx* c) {
                 err = launch_gemm(GEMM_F64, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
                 break;
         }
-        if (err == hipSuccess && timed) err = hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], st);
+        if (err == hipSuccess && timed) err = launch_stamp(c->d_stamps + 2 * pair + 1, st);
         return err;
     };
     size_t next_ev = 0;
@@ -1092,16 +1121,73 @@ tn_status tn_enqueue(tn_ctx* c) {
     return TN_OK;
 }
 
+tn_status tn_enqueue(tn_ctx* c) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan) return fail(c, TN_ESTATE, "evaluate before tn_set_tree");
+    (void)hipSetDevice(c->device);
+    if (!c->fexec || c->fgraph_mask != c->prof_mask) {
+        // capture the schedule once (per profiling mask): replays skip the per-launch host work
+        free_forward_graph(c);
+        if (!c->st_used.empty()) {   // stamps of an unfetched evaluation: fold them in first
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (tn_status st = collect_stamps(c); st != TN_OK) return st;
+        }
+        size_t timed = 0;
+        for (const Launch& l : c->launches) timed += (c->prof_mask >> l.prof) & 1u;
+        if (timed > c->stamps_cap) {
+            dfree(c->d_stamps);
+            c->stamps_cap = 0;
+            HIP_TRY(c, hipMalloc((void**)&c->d_stamps, 2 * timed * sizeof(unsigned long long)));
+            c->stamps_cap = timed;
+        }
+        const auto st0 = c->st_used;
+        int64_t l0[kKinds];
+        double f0[kKinds], b0[kKinds];
+        for (int k = 0; k < kKinds; ++k) {
+            l0[k] = c->prof_launches[k];
+            f0[k] = c->prof_flops[k];
+            b0[k] = c->prof_bytes[k];
+        }
+        c->st_used.clear();
+        HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        const tn_status es = enqueue_forward(c);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(c->stream, &g);
+        c->fgraph_st = c->st_used;
+        c->st_used = st0;
+        for (int k = 0; k < kKinds; ++k) {
+            c->fgraph_launches[k] = c->prof_launches[k] - l0[k];
+            c->fgraph_flops[k] = c->prof_flops[k] - f0[k];
+            c->fgraph_bytes[k] = c->prof_bytes[k] - b0[k];
+            c->prof_launches[k] = l0[k];
+            c->prof_flops[k] = f0[k];
+            c->prof_bytes[k] = b0[k];
+        }
+        if (es != TN_OK || ce != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            c->fgraph_st.clear();
+            return es != TN_OK ? es : fail(c, TN_EDEVICE, std::string("forward capture: ") + hipGetErrorString(ce));
+        }
+        c->fgraph = g;
+        HIP_TRY(c, hipGraphInstantiate(&c->fexec, c->fgraph, nullptr, nullptr, 0));
+        c->fgraph_mask = c->prof_mask;
+    }
+    HIP_TRY(c, hipGraphLaunch(c->fexec, c->stream));
+    // a replay re-writes the same stamp pairs: the totals read at tn_fetch are the last replay's
+    c->st_used.insert(c->st_used.end(), c->fgraph_st.begin(), c->fgraph_st.end());
+    for (int k = 0; k < kKinds; ++k) {
+        c->prof_launches[k] += c->fgraph_launches[k];
+        c->prof_flops[k] += c->fgraph_flops[k];
+        c->prof_bytes[k] += c->fgraph_bytes[k];
+    }
+    return TN_OK;
+}
+
 tn_status tn_fetch(tn_ctx* c) {
     if (!c) return TN_EINVAL;
     if (!c->has_plan) return fail(c, TN_ESTATE, "no plan");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (auto& u : c->ev_used) {
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[u.second], c->ev_pool[u.second + 1]));
-        c->prof_ms[u.first] += ms;
-    }
-    c->ev_used.clear();
+    if (tn_status st = collect_stamps(c); st != TN_OK) return st;
     c->sign = c->h_result[0];
     c->lnz = c->h_result[1];
     c->flags = (int)c->h_result[2];

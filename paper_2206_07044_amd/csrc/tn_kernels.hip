@@ -2204,6 +2204,15 @@ hipError_t launch_grad_inputs(int prec, const InputDesc* descs, int n, const dou
     return by_prec(prec, [&](auto t) { grad_inputs_kernel<decltype(t)><<<grid, block, 0, s>>>(descs, n, scales, out); });
 }
 
+// Device wall-clock stamp (100 MHz counter) on a stream, for timing the launches between two stamps
+// also inside captured graphs.  One lane writes through a lane-indexed address (a vector store).
+__global__ void stamp_kernel(unsigned long long* __restrict__ dst) { dst[threadIdx.x] = wall_clock64(); }
+
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s) {
+    stamp_kernel<<<1, 1, 0, s>>>(dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_result(int prec, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
                          int n_comp, double* result, hipStream_t s) {
     return by_prec(prec, [&](auto t) {

@@ -44,6 +44,8 @@ hipError_t launch_ising_values(const IsingGraph& g, double beta, const double* J
                                hipStream_t s);
 hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, const double* dlnz_ddata,
                              double* dlnz_dJ, hipStream_t s);
+// One 8-byte wall-clock stamp (100 MHz) written by the device when the stream reaches it.
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 hipError_t launch_result(int prec, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,
                          int n_comp, double* result, hipStream_t s);
 
