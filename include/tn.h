@@ -118,7 +118,11 @@ tn_status tn_contract_compressed(tn_ctx* ctx, double* mantissa, double* log10_ex
 tn_status tn_result(const tn_ctx* ctx, double* sign, double* ln_abs_z);
 
 /* Enqueue an evaluation without synchronising (for timing and batching);
- * tn_result after a stream synchronisation reads it. */
+ * tn_fetch synchronises the ctx stream and makes it the last evaluation.
+ * The first evaluation after tn_set_tree (or after a change of the
+ * tn_profile mask) captures the schedule into a hipGraph on the ctx stream;
+ * later ones replay it, so the input values may change between evaluations
+ * (tn_update_values*) but not the addresses the plan holds. */
 tn_status tn_enqueue(tn_ctx* ctx);
 tn_status tn_fetch(tn_ctx* ctx);
 
@@ -145,9 +149,13 @@ typedef enum {
     TN_KERNEL_BWD_CORE = 8       /* reverse pass: per-compression core adjoint */
 } tn_kernel_kind;
 
-/* Time every launch of the kinds in `kind_mask` (bit k = tn_kernel_kind k) with
- * HIP events on the ctx stream during later evaluations, and reset the
- * totals.  0 switches timing off. */
+/* Time every launch of the kinds in `kind_mask` (bit k = tn_kernel_kind k)
+ * during later evaluations, and reset the totals.  Forward launches are timed
+ * by device wall-clock stamps (100 MHz) written on the launch's own stream just
+ * before and after it (so the duration includes one dispatch gap); reverse-pass
+ * launches by HIP events.  Totals are read at tn_fetch: replays enqueued
+ * without a fetch in between re-write the same stamps, so fetch after each
+ * evaluation for a per-evaluation total.  0 switches timing off. */
 tn_status tn_profile(tn_ctx* ctx, uint32_t kind_mask);
 /* Totals since tn_profile for one kind: summed launch durations (ms, measured
  * at tn_fetch / tn_contract_compressed), number of launches, and the
