@@ -1417,6 +1417,63 @@ __device__ void dense_mvt(const double* __restrict__ F, int n, int D, const doub
     __syncthreads();
 }
 
+// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA, by the
+// whole 1024-thread workgroup: 128 x 128 tiles of C, each wave a 32 x 32 block (2 x 2
+// instructions of 16 x 16 x 4), K staged through LDS in chunks of 32 with the loads coalesced
+// along whichever index has unit stride.  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc];
+// stage holds 2 * 32 * 128 doubles.  Ends with a barrier.
+__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
+                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
+                            double* __restrict__ stage) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
+    const int lrow = lane & 15, lk = lane >> 4;
+    double* As = stage;              // As[k * 128 + i]
+    double* Bs = stage + 32 * 128;   // Bs[k * 128 + j]
+    const bool a_kfast = ac == 1, b_jfast = bc == 1;
+    for (int i0 = 0; i0 < M; i0 += 128)
+        for (int j0 = 0; j0 < N; j0 += 128) {
+            v4d acc[2][2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                for (int e = tid; e < 32 * 128; e += kCoreThreads) {
+                    const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
+                    const int gi = i0 + ii, gk = k0 + kk;
+                    As[kk * 128 + ii] = (gi < M && gk < K) ? A[gi * ar + gk * ac] : 0.0;
+                    const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
+                    const int gj = j0 + jj, gkb = k0 + kb;
+                    Bs[kb * 128 + jj] = (gj < N && gkb < K) ? B[gkb * br + gj * bc] : 0.0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < 32; kk += 4) {
+                    const int k = kk + lk;
+                    const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
+                    const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
+                    acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
+                    acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
+                    acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
+                    acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
+                        const int gj = j0 + wc + 16 * y + lrow;
+                        if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[x][y][r];
+                    }
+        }
+    __syncthreads();
+}
+
 // C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA for
 // narrow N, operands read straight from memory: each wave owns 16 x 32 blocks of C (two
 // 16 x 16 x 4 instructions per step of 4 along K).  A(i, k) = A[i * ar + k * ac],
@@ -1838,8 +1895,11 @@ __global__ __launch_bounds__(256) void reduce_grouped(const ReduceDesc* __restri
 //   N_A = L Psi_A L^T + sum_t L_t H_B,t^T / sqrt(s_t),   N_B = M Psi_B M^T + sum_t H_A,t M_t^T / sqrt(s_t),
 //   Psi_A = Phi s - a s^1/2 E^T - E s^-1/2 b^T s,   Psi_B = s Phi - s a s^-1/2 E^T - E s^1/2 b^T,
 // so that A_bar = G_a P_L^T + A N_A and B_bar = P_R^T G_b + N_B B need no inverse of R~.
+constexpr size_t kCoreBwdLdsBytes = 2 * 32 * 128 * sizeof(double);
+
 template <typename Tp>
 __global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDesc* __restrict__ descs) {
+    extern __shared__ double lds[];   // GEMM staging, 2 x 32 x 128 doubles
     const CoreBwdDesc& d = descs[blockIdx.x];
     const int tid = threadIdx.x;
     const int D = d.D, cn = d.chi_new, DD = D * D;
@@ -1895,29 +1955,29 @@ __global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDes
         HB[idx] = y;
     }
     __syncthreads();
-    // L = R~_B^T V_+ s^-1, M = R~_A^T (W_+ s^-1) s^-1  (W's columns are U s)
-    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
-        const int dd = idx / r, p = idx - dd * r;
+    // singular vectors of the + set in descending order (columns), into the Psi slots (free
+    // until Psi is formed): Vs = V_+, Ws = W_+ = U_+ s
+    double* Vs = PsiA;
+    double* Ws = PsiB;
+    for (int idx = tid; idx < r * D; idx += kCoreThreads) {
+        const int p = idx / D, i = idx - p * D;
         const int j = order[p];
-        const double* v = V + (int64_t)j * D;
-        const double* w = W + (int64_t)j * D;
-        double x = 0.0, y = 0.0;
-        for (int i = 0; i < rb; ++i) x += Rb[i * D + dd] * v[i];
-        for (int i = 0; i < ra; ++i) y += Ra[i * D + dd] * w[i];
-        L[dd * D + p] = x / sg[p];
-        Mm[dd * D + p] = y / (sg[p] * sg[p]);
+        Vs[(int64_t)p * D + i] = i < rb ? V[(int64_t)j * D + i] : 0.0;
+        Ws[(int64_t)p * D + i] = i < ra ? W[(int64_t)j * D + i] : 0.0;
     }
     __syncthreads();
-    for (int idx = tid; idx < r * nk; idx += kCoreThreads) {
-        const int p = idx / nk, t = idx - p * nk;
-        double x = 0.0, y = 0.0;
-        for (int dd = 0; dd < D; ++dd) {
-            x += L[dd * D + p] * HA[dd * cn + t];
-            y += Mm[dd * D + p] * HB[dd * cn + t];
-        }
-        a[p * cn + t] = x;
-        b[p * cn + t] = y;
+    // L = R~_B^T V_+ s^-1, M = R~_A^T (W_+ s^-1) s^-1, on the MFMA
+    wg_gemm_f64(Rb, 1, D, Vs, 1, D, L, D, D, r, rb, lds);
+    wg_gemm_f64(Ra, 1, D, Ws, 1, D, Mm, D, D, r, ra, lds);
+    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
+        const int dd = idx / r, p = idx - dd * r;
+        L[dd * D + p] /= sg[p];
+        Mm[dd * D + p] /= sg[p] * sg[p];
     }
+    __syncthreads();
+    // a = L^T H_A, b = M^T H_B  (r x nk, leading dimension cn)
+    wg_gemm_f64_narrow(L, 1, D, HA, cn, 1, a, cn, r, nk, D);
+    wg_gemm_f64_narrow(Mm, 1, D, HB, cn, 1, b, cn, r, nk, D);
     __syncthreads();
     // Phi[x][y]: diagonal of the kept block, plus the contributions of kept index y (to row x)
     // and of kept index x (to column y) for every other singular index
@@ -1957,36 +2017,26 @@ __global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDes
         PsiB[x * D + y] = pb;
     }
     __syncthreads();
-    // T = L Psi_A ; N_A = T L^T + sum_t L_t H_B,t^T / sqrt(s_t)
-    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
-        const int dd = idx / r, y = idx - dd * r;
-        double x = 0.0;
-        for (int q = 0; q < r; ++q) x += L[dd * D + q] * PsiA[q * D + y];
-        T[dd * D + y] = x;
-    }
-    __syncthreads();
+    // T = L Psi_A ; N_A = T L^T + sum_t L_t H_B,t^T / sqrt(s_t)   (the products on the MFMA, into
+    // the Phi slot, which Psi no longer needs)
+    double* N2 = Phi;
+    wg_gemm_f64(L, D, 1, PsiA, D, 1, T, D, D, r, r, lds);
+    wg_gemm_f64(T, D, 1, L, 1, D, N2, D, D, D, r, lds);
     Tp* na = (Tp*)d.n_a;
     for (int idx = tid; idx < DD; idx += kCoreThreads) {
         const int d1 = idx / D, d2 = idx - d1 * D;
-        double x = 0.0;
-        for (int y = 0; y < r; ++y) x += T[d1 * D + y] * L[d2 * D + y];
+        double x = N2[idx];
         for (int t = 0; t < nk; ++t) x += L[d1 * D + t] * HB[d2 * cn + t] / sq[t];
         na[idx] = (Tp)x;
     }
     __syncthreads();
     // T = M Psi_B ; N_B = T M^T + sum_t H_A,t M_t^T / sqrt(s_t)
-    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
-        const int dd = idx / r, y = idx - dd * r;
-        double x = 0.0;
-        for (int q = 0; q < r; ++q) x += Mm[dd * D + q] * PsiB[q * D + y];
-        T[dd * D + y] = x;
-    }
-    __syncthreads();
+    wg_gemm_f64(Mm, D, 1, PsiB, D, 1, T, D, D, r, r, lds);
+    wg_gemm_f64(T, D, 1, Mm, 1, D, N2, D, D, D, r, lds);
     Tp* nb = (Tp*)d.n_b;
     for (int idx = tid; idx < DD; idx += kCoreThreads) {
         const int d1 = idx / D, d2 = idx - d1 * D;
-        double x = 0.0;
-        for (int y = 0; y < r; ++y) x += T[d1 * D + y] * Mm[d2 * D + y];
+        double x = N2[idx];
         for (int t = 0; t < nk; ++t) x += HA[d1 * cn + t] * Mm[d2 * D + t] / sq[t];
         nb[idx] = (Tp)x;
     }
@@ -2111,6 +2161,9 @@ hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, 
 size_t core_lds_bytes(int max_d) { return (size_t)4 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
+    (void)hipFuncSetAttribute((const void*)core_bwd_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
+    (void)hipFuncSetAttribute((const void*)core_bwd_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
+    (void)hipFuncSetAttribute((const void*)core_bwd_kernel<bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)gram_lanczos_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
     (void)hipFuncSetAttribute((const void*)gram_lanczos_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
     (void)hipFuncSetAttribute((const void*)lanczos_kernel<float, float>, hipFuncAttributeMaxDynamicSharedMemorySize, kLanczosLdsBytes);
@@ -2189,7 +2242,7 @@ hipError_t launch_reduce(int prec, const ReduceDesc* descs, int ndesc, int64_t t
 
 hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, hipStream_t s) {
     if (ndesc == 0) return hipSuccess;
-    return by_prec(prec, [&](auto t) { core_bwd_kernel<decltype(t)><<<ndesc, kCoreThreads, 0, s>>>(descs); });
+    return by_prec(prec, [&](auto t) { core_bwd_kernel<decltype(t)><<<ndesc, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs); });
 }
 
 hipError_t launch_seed(int prec, const void* final_ptr, void* adj_final, const double* scales, int final_index,
