@@ -719,6 +719,116 @@ __device__ bool jacobi_svd(double* W, double* V, int rows, int cols, int ld, int
     return converged;
 }
 
+// jacobi_svd for rows, cols <= 256 (W, V in global memory): a wave rotates two pairs at a time,
+// one row of each per lane for four rows, every operand held in registers between the dot
+// products and the update, the two pairs' reductions and rotations interleaved.  Same pair order,
+// thresholds and result contract as jacobi_svd.
+__device__ bool jacobi_svd_256(double* W, double* V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
+                               int* sweeps_out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nc = cols + (cols & 1);
+    const double tol = 2.220446049250313e-16 * (double)max(rows, 16);
+    {
+        double f = 0.0;
+        for (int64_t idx = tid; idx < (int64_t)rows * cols; idx += kCoreThreads) {
+            const int j = (int)(idx / rows), i = (int)(idx - (int64_t)j * rows);
+            const double x = W[(int64_t)j * ld + i];
+            f += x * x;
+        }
+        f = wave_sum(f);
+        if (lane == 0) sh.rv[wave] = f;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+            sh.rv[0] = t;
+        }
+        __syncthreads();
+    }
+    const double zero2 = kZeroRel * kZeroRel * sh.rv[0];
+    __syncthreads();
+    int sweeps = 0;
+    bool converged = (cols <= 1);
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        if (tid == 0) sh.flag = sh.flag_big = 0;
+        __syncthreads();
+        for (int round = 0; round < nc - 1; ++round) {
+            for (int q0 = 2 * wave; q0 < nc / 2; q0 += 2 * kCoreWaves) {
+                double* w1[2];
+                double* w2[2];
+                double* v1[2];
+                double* v2[2];
+                double x[2][4], y[2][4], xv[2][4], yv[2][4], a[2], b[2], g[2];
+                bool ok[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int q = q0 + u;
+                    const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
+                    ok[u] = q < nc / 2 && p1 < cols && p2 < cols;
+                    const int c1 = ok[u] ? p1 : 0, c2 = ok[u] ? p2 : 1;
+                    w1[u] = W + (int64_t)c1 * ld;
+                    w2[u] = W + (int64_t)c2 * ld;
+                    v1[u] = V + (int64_t)c1 * ld;
+                    v2[u] = V + (int64_t)c2 * ld;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int i = lane + 64 * k;
+                        x[u][k] = i < rows ? w1[u][i] : 0.0;
+                        y[u][k] = i < rows ? w2[u][i] : 0.0;
+                        xv[u][k] = i < cols ? v1[u][i] : 0.0;
+                        yv[u][k] = i < cols ? v2[u][i] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    a[u] = b[u] = g[u] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        a[u] = fma(x[u][k], x[u][k], a[u]);
+                        b[u] = fma(y[u][k], y[u][k], b[u]);
+                        g[u] = fma(x[u][k], y[u][k], g[u]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    a[u] = wave_sum(a[u]);
+                    b[u] = wave_sum(b[u]);
+                    g[u] = wave_sum(g[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (ok[u] && a[u] > zero2 && b[u] > zero2 && g[u] * g[u] > tol * tol * a[u] * b[u]) {
+                        double c, s;
+                        jacobi_rotation(a[u], b[u], g[u], &c, &s);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int i = lane + 64 * k;
+                            if (i < rows) {
+                                w1[u][i] = c * x[u][k] - s * y[u][k];
+                                w2[u][i] = s * x[u][k] + c * y[u][k];
+                            }
+                            if (i < cols) {
+                                v1[u][i] = c * xv[u][k] - s * yv[u][k];
+                                v2[u][i] = s * xv[u][k] + c * yv[u][k];
+                            }
+                        }
+                        if (lane == 0) {
+                            sh.flag = 1;
+                            if (g[u] * g[u] > kQuadRel2 * a[u] * b[u]) sh.flag_big = 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        sweeps = sweep + 1;
+        if (!sh.flag || !sh.flag_big) converged = true;
+        __syncthreads();
+    }
+    *sweeps_out = sweeps;
+    return converged;
+}
+
 // Sum over the lane's 16-lane DPP row (every lane of the row gets the row total).
 __device__ inline double row16_sum(double v) {
     v += dpp_mov<0xB1>(v);
@@ -959,8 +1069,9 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     if constexpr (kLds)   // ra, rb <= D <= 64
         converged = jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
     else
-        converged = (ra <= 64 && rb <= 64) ? jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
-                                           : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
+        converged = (ra <= 64 && rb <= 64)     ? jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                    : (ra <= 256 && rb <= 256) ? jacobi_svd_256(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                                               : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
 
     // ---- singular values and descending order (ties: lower column first)
     sorted_norms<NT>(W, ra, rb, D, sig, order);
