@@ -951,6 +951,100 @@ __device__ void sorted_norms(const double* W, int rows, int cols, int ld, double
     __syncthreads();
 }
 
+// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA, by the
+// whole 1024-thread workgroup: 128 x 128 tiles of C, each wave a 32 x 32 block (2 x 2
+// instructions of 16 x 16 x 4), K staged through LDS in chunks of 32 with the loads coalesced
+// along whichever index has unit stride.  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc];
+// stage holds 2 * 32 * 128 doubles.  Ends with a barrier.
+__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
+                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
+                            double* __restrict__ stage) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
+    const int lrow = lane & 15, lk = lane >> 4;
+    double* As = stage;              // As[k * 128 + i]
+    double* Bs = stage + 32 * 128;   // Bs[k * 128 + j]
+    const bool a_kfast = ac == 1, b_jfast = bc == 1;
+    for (int i0 = 0; i0 < M; i0 += 128)
+        for (int j0 = 0; j0 < N; j0 += 128) {
+            v4d acc[2][2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                for (int e = tid; e < 32 * 128; e += kCoreThreads) {
+                    const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
+                    const int gi = i0 + ii, gk = k0 + kk;
+                    As[kk * 128 + ii] = (gi < M && gk < K) ? A[gi * ar + gk * ac] : 0.0;
+                    const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
+                    const int gj = j0 + jj, gkb = k0 + kb;
+                    Bs[kb * 128 + jj] = (gj < N && gkb < K) ? B[gkb * br + gj * bc] : 0.0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < 32; kk += 4) {
+                    const int k = kk + lk;
+                    const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
+                    const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
+                    acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
+                    acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
+                    acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
+                    acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
+                        const int gj = j0 + wc + 16 * y + lrow;
+                        if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[x][y][r];
+                    }
+        }
+    __syncthreads();
+}
+
+// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA for
+// narrow N, operands read straight from memory: each wave owns 16 x 32 blocks of C (two
+// 16 x 16 x 4 instructions per step of 4 along K).  A(i, k) = A[i * ar + k * ac],
+// B(k, j) = B[k * br + j * bc].  Ends with a barrier.
+__device__ void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int64_t ac,
+                                   const double* __restrict__ B, int64_t br, int64_t bc, double* __restrict__ C,
+                                   int64_t ldc, int M, int N, int K) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int mb = (M + 15) / 16, nb = (N + 31) / 32;
+    for (int blk = wave; blk < mb * nb; blk += kCoreWaves) {
+        const int i0 = (blk % mb) * 16, j0 = (blk / mb) * 32;
+        const int gi = i0 + lr, gj0 = j0 + lr, gj1 = j0 + 16 + lr;
+        const bool ri = gi < M, c0 = gj0 < N, c1 = gj1 < N;
+        v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            const bool kk = k < K;
+            const double a = (ri && kk) ? A[(int64_t)gi * ar + (int64_t)k * ac] : 0.0;
+            const double b0 = (kk && c0) ? B[(int64_t)k * br + (int64_t)gj0 * bc] : 0.0;
+            const double b1 = (kk && c1) ? B[(int64_t)k * br + (int64_t)gj1 * bc] : 0.0;
+            acc0 = Mma<double>::run(a, b0, acc0);
+            acc1 = Mma<double>::run(a, b1, acc1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = i0 + Mma<double>::row(lane, r);
+            if (row < M) {
+                if (c0) C[(int64_t)row * ldc + gj0] = acc0[r];
+                if (c1) C[(int64_t)row * ldc + gj1] = acc1[r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <bool kLds, typename Tp>
 __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
                                                             double* __restrict__ stat_disc,
@@ -1044,6 +1138,10 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     }
 
     // ---- core W = R~_A R~_B^T  (ra x rb), V = I
+    if constexpr (!kLds) {
+        // column j of W is row j of R~_B R~_A^T: one workgroup GEMM on the MFMA (LDS staging)
+        wg_gemm_f64(Rb, D, 1, Ra, 1, D, W, D, rb, ra, D, lds);
+    } else
     for (int idx = tid; idx < ra * rb; idx += NT) {
         const int j = idx / ra, i = idx - j * ra;
         const double* x = Ra + (int64_t)i * D;
@@ -1242,7 +1340,7 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
     __shared__ CoreShared sh;
     __shared__ double coef[kLanczosMaxSteps + 1];
     const LanczosDesc& d = descs[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int ma = d.ma, mb = d.mb, D = d.D, cn = d.chi_new, smax_steps = d.s_max, ls = d.s_max + 1;
     const Tin* __restrict__ A = (const Tin*)d.A;
     const Tin* __restrict__ B = (const Tin*)d.B;
@@ -1287,7 +1385,7 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
         __syncthreads();
     }
 
-    int s = 0, restarts = 0, sweeps_total = 0, extra_col = 0;
+    int s = 0, restarts = 0, extra_col = 0;
     bool exhausted = false, converged = false;
     double amax = 0.0;
     int target = d.s_min;
@@ -1379,7 +1477,6 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
         __syncthreads();
         int sw = 0;
         const bool jc = jacobi_svd(W, Vs, s, ncol, lw, max_sweeps, sh, &sw);
-        sweeps_total += sw;
         sorted_norms(W, s, ncol, lw, sig, order);
         nsv = ncol;
         // residual of Ritz triplet t: beta_{s-1} |Ub[s-1, t]| (zero when the space is exhausted)
@@ -1528,99 +1625,6 @@ __device__ void dense_mvt(const double* __restrict__ F, int n, int D, const doub
     __syncthreads();
 }
 
-// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA, by the
-// whole 1024-thread workgroup: 128 x 128 tiles of C, each wave a 32 x 32 block (2 x 2
-// instructions of 16 x 16 x 4), K staged through LDS in chunks of 32 with the loads coalesced
-// along whichever index has unit stride.  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc];
-// stage holds 2 * 32 * 128 doubles.  Ends with a barrier.
-__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
-                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
-                            double* __restrict__ stage) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
-    const int lrow = lane & 15, lk = lane >> 4;
-    double* As = stage;              // As[k * 128 + i]
-    double* Bs = stage + 32 * 128;   // Bs[k * 128 + j]
-    const bool a_kfast = ac == 1, b_jfast = bc == 1;
-    for (int i0 = 0; i0 < M; i0 += 128)
-        for (int j0 = 0; j0 < N; j0 += 128) {
-            v4d acc[2][2];
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                for (int e = tid; e < 32 * 128; e += kCoreThreads) {
-                    const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
-                    const int gi = i0 + ii, gk = k0 + kk;
-                    As[kk * 128 + ii] = (gi < M && gk < K) ? A[gi * ar + gk * ac] : 0.0;
-                    const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
-                    const int gj = j0 + jj, gkb = k0 + kb;
-                    Bs[kb * 128 + jj] = (gj < N && gkb < K) ? B[gkb * br + gj * bc] : 0.0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int kk = 0; kk < 32; kk += 4) {
-                    const int k = kk + lk;
-                    const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
-                    const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
-                    acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
-                    acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
-                    acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
-                    acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
-                }
-                __syncthreads();
-            }
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
-                        const int gj = j0 + wc + 16 * y + lrow;
-                        if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[x][y][r];
-                    }
-        }
-    __syncthreads();
-}
-
-// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA for
-// narrow N, operands read straight from memory: each wave owns 16 x 32 blocks of C (two
-// 16 x 16 x 4 instructions per step of 4 along K).  A(i, k) = A[i * ar + k * ac],
-// B(k, j) = B[k * br + j * bc].  Ends with a barrier.
-__device__ void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int64_t ac,
-                                   const double* __restrict__ B, int64_t br, int64_t bc, double* __restrict__ C,
-                                   int64_t ldc, int M, int N, int K) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int mb = (M + 15) / 16, nb = (N + 31) / 32;
-    for (int blk = wave; blk < mb * nb; blk += kCoreWaves) {
-        const int i0 = (blk % mb) * 16, j0 = (blk / mb) * 32;
-        const int gi = i0 + lr, gj0 = j0 + lr, gj1 = j0 + 16 + lr;
-        const bool ri = gi < M, c0 = gj0 < N, c1 = gj1 < N;
-        v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            const int k = k0 + lk;
-            const bool kk = k < K;
-            const double a = (ri && kk) ? A[(int64_t)gi * ar + (int64_t)k * ac] : 0.0;
-            const double b0 = (kk && c0) ? B[(int64_t)k * br + (int64_t)gj0 * bc] : 0.0;
-            const double b1 = (kk && c1) ? B[(int64_t)k * br + (int64_t)gj1 * bc] : 0.0;
-            acc0 = Mma<double>::run(a, b0, acc0);
-            acc1 = Mma<double>::run(a, b1, acc1);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = i0 + Mma<double>::row(lane, r);
-            if (row < M) {
-                if (c0) C[(int64_t)row * ldc + gj0] = acc0[r];
-                if (c1) C[(int64_t)row * ldc + gj1] = acc1[r];
-            }
-        }
-    }
-    __syncthreads();
-}
 
 template <typename Tp>
 __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLanczosDesc* __restrict__ descs,
@@ -1633,7 +1637,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     const GLanczosDesc& d = descs[blockIdx.x];
     const int tid = threadIdx.x;
     const int n = d.n, D = d.D, cn = d.chi_new, sm = d.s_max, ls = d.s_max + 1;
-    const int64_t DD = (int64_t)D * D;
+
     double* S = d.work;                          // n x n operator F_X G_Y F_X^T
     double* T1 = S + (int64_t)n * n;             // D x n (G_Y F_X^T) or n x my (F_X F_Y^T)
     double* Q = T1 + (int64_t)max(D, d.my) * n;  // n x s_max Lanczos basis
@@ -2272,6 +2276,9 @@ hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, 
 size_t core_lds_bytes(int max_d) { return (size_t)4 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
+    (void)hipFuncSetAttribute((const void*)core_kernel<false, double>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
+    (void)hipFuncSetAttribute((const void*)core_kernel<false, float>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
+    (void)hipFuncSetAttribute((const void*)core_kernel<false, bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_bwd_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_bwd_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_bwd_kernel<bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
@@ -2295,7 +2302,7 @@ hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int 
     return by_prec(prec, [&](auto t) {
         using Tp = decltype(t);
         if (lds) core_kernel<true, Tp><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
-        else core_kernel<false, Tp><<<grid, block, 0, s>>>(descs, max_sweeps, disc, tie, sweeps);
+        else core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
     });
 }
 
