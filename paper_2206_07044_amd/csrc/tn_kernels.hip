@@ -838,10 +838,10 @@ __device__ inline double row16_sum(double v) {
     return v;
 }
 
-// jacobi_svd for rows, cols <= 64: each pair is rotated by one 16-lane row of a wave (up
-// to four rows of W per lane), so reductions stay inside DPP rows and a wave rotates four
+// jacobi_svd for rows, cols <= 16 KR (KR <= 4): each pair is rotated by one 16-lane row of a
+// wave (KR rows of W per lane), so reductions stay inside DPP rows and a wave rotates four
 // pairs at once.  Same pair order, thresholds and result contract as jacobi_svd.
-template <int NT = kCoreThreads>
+template <int NT = kCoreThreads, int KR = 4>
 __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
                                  int* sweeps_out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -879,10 +879,10 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                 double* v1 = V + (int64_t)p1 * ld;
                 double* v2 = V + (int64_t)p2 * ld;
                 // every load up front (clamped index, then zeroed), so their latencies overlap
-                double x[4], y[4], xv[4], yv[4];
+                double x[KR], y[KR], xv[KR], yv[KR];
                 double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < KR; ++k) {
                     const int i = ql + 16 * k;
                     const int iw = min(i, max(rows, 1) - 1), iv = min(i, cols - 1);
                     x[k] = w1[iw];
@@ -892,7 +892,7 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                     if (i >= rows) x[k] = y[k] = 0.0;
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < KR; ++k) {
                     a = fma(x[k], x[k], a);
                     b = fma(y[k], y[k], b);
                     g = fma(x[k], y[k], g);
@@ -904,7 +904,7 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
                     double c, s;
                     jacobi_rotation(a, b, g, &c, &s);
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
+                    for (int k = 0; k < KR; ++k) {
                         const int i = ql + 16 * k;
                         if (i < rows) {
                             w1[i] = c * x[k] - s * y[k];
@@ -1165,9 +1165,11 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     int sweeps = 0;
     bool converged;
     if constexpr (kLds)   // ra, rb <= D <= 64
-        converged = jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
+        converged = (ra <= 32 && rb <= 32) ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                                           : jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
     else
-        converged = (ra <= 64 && rb <= 64)     ? jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+        converged = (ra <= 32 && rb <= 32)     ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                    : (ra <= 64 && rb <= 64)   ? jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
                     : (ra <= 256 && rb <= 256) ? jacobi_svd_256(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
                                                : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
 
@@ -1775,7 +1777,8 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         }
         __syncthreads();
         int sw = 0;
-        const bool jc = s <= 64 ? jacobi_svd_small(W, Vs, s, s, lw, max_sweeps, sh, &sw)
+        const bool jc = s <= 32 ? jacobi_svd_small<kCoreThreads, 2>(W, Vs, s, s, lw, max_sweeps, sh, &sw)
+                      : s <= 64 ? jacobi_svd_small(W, Vs, s, s, lw, max_sweeps, sh, &sw)
                                 : jacobi_svd(W, Vs, s, s, lw, max_sweeps, sh, &sw);
         sorted_norms(W, s, s, lw, sig, order);
         nev = s;
