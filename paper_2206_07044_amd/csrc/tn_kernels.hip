@@ -1689,8 +1689,17 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
             if (k > 0) lc += coef[k - 1];
             double part = 0.0;
             for (int i = tid; i < n; i += kCoreThreads) {
-                double acc = x[i];
-                for (int c = 0; c < k; ++c) acc -= qcol(c)[i] * coef[c];
+                // four interleaved partial sums keep the dependent chain a quarter as long
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int c = 0;
+                for (; c + 4 <= k; c += 4) {
+                    s0 = fma(qcol(c)[i], coef[c], s0);
+                    s1 = fma(qcol(c + 1)[i], coef[c + 1], s1);
+                    s2 = fma(qcol(c + 2)[i], coef[c + 2], s2);
+                    s3 = fma(qcol(c + 3)[i], coef[c + 3], s3);
+                }
+                for (; c < k; ++c) s0 = fma(qcol(c)[i], coef[c], s0);
+                const double acc = x[i] - ((s0 + s1) + (s2 + s3));
                 x[i] = acc;
                 part += acc * acc;
             }
