@@ -1661,8 +1661,39 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     // S and T1 were formed before this launch by grouped float64 GEMMs, so that a Lanczos step is
     // one matvec: Y a Gram: T1 = G_Y F_X^T (D x n), S = F_X T1; Y explicit: T1 = C1 = F_X F_Y^T
     // (n x my), S = C1 C1^T
+    // y = S x: a wave per group of four rows, lanes along the contiguous columns, all sixteen
+    // loads of a group (n <= 256) issued before any is used; y lives in LDS, so no store can alias
+    // the loads of S
     auto apply_s = [&](const double* x, double* y) {
-        dense_mv(S, n, n, x, y, 1.0);
+        if (n > 256) {
+            dense_mv(S, n, n, x, y, 1.0);
+            __syncthreads();
+            return;
+        }
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int i0 = wave * 4; i0 < n; i0 += kCoreWaves * 4) {
+            double f[4][4], xv[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int dcol = lane + 64 * c;
+                xv[c] = dcol < n ? x[dcol] : 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    f[r][c] = (dcol < n && i0 + r < n) ? S[(int64_t)(i0 + r) * n + dcol] : 0.0;
+            }
+            double acc[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                acc[r] = 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r] = fma(f[r][c], xv[c], acc[r]);
+                acc[r] = wave_sum(acc[r]);
+            }
+            if (lane == 0)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (i0 + r < n) y[i0 + r] = acc[r];
+        }
         __syncthreads();
     };
 
@@ -1727,7 +1758,9 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     double* W = Wg;
     double* Vs = Vg;
     int lw = ls;
-    double* qnext = py;   // the next Lanczos vector candidate (length n)
+    // the next Lanczos vector candidate (length n): in LDS (the tridiagonal solve's room, free
+    // between checks) when it fits
+    double* qnext = n <= 2 * kTriLdsS * kTriLdsS ? lds : py;
     for (;;) {
         for (; s < target && !exhausted; ++s) {
             const int j = s;
