@@ -807,19 +807,20 @@ int lane_of(const Launch& l) {
 // Enqueue launches [b, e) of one level: on `main` alone when they all share a lane, else forked
 // onto the lanes' streams after an event on `main` and joined back with one event per lane.
 // `run` enqueues one launch on a given stream.  `events` supplies timing-disabled events.
-// A level whose Lanczos lane holds only Gram-Lanczos launches may leave that lane unjoined
-// (`allow_defer`): its event goes to `*pending`, and the next level makes `main` wait for it before
-// its first tensor-GEMM launch (the re-absorptions that read the projectors) or, failing that, at
-// its own join, so that the lane runs beside the next level's cores, Grams and copies.
+// The compression lanes (cores; Gram-Lanczos, unless a level holds other Lanczos launches) may be
+// left unjoined (`allow_defer`): their events go to `pending`, and the next level makes `main`
+// wait for them before its first tensor-GEMM launch (the re-absorptions that read the
+// projectors) or, failing that, at its own join.  So a compression runs beside the next level's
+// other compressions, Grams and copies; the planner keeps its inputs one level longer.
 template <typename Run>
 hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStream_t main, hipStream_t* aux,
                      std::vector<hipEvent_t>& events, size_t& next_ev, Run&& run, hipEvent_t* pending,
                      bool allow_defer) {
     int used = 0;
-    bool only_glanczos = true;
+    bool lane2_glanczos = true;
     for (size_t i = b; i < e; ++i) {
         used |= 1 << lane_of(ls[i]);
-        if (lane_of(ls[i]) == 2 && ls[i].kind != L_GLANCZOS) only_glanczos = false;
+        if (lane_of(ls[i]) == 2 && ls[i].kind != L_GLANCZOS) lane2_glanczos = false;
     }
     auto event = [&](hipEvent_t* out) -> hipError_t {
         if (next_ev == events.size()) {
@@ -831,16 +832,21 @@ hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStrea
         *out = events[next_ev++];
         return hipSuccess;
     };
+    auto wait_pending = [&]() -> hipError_t {
+        for (int k = 0; k < 2; ++k)
+            if (pending[k]) {
+                hipError_t err = hipStreamWaitEvent(main, pending[k], 0);
+                pending[k] = nullptr;
+                if (err != hipSuccess) return err;
+            }
+        return hipSuccess;
+    };
     hipError_t err = hipSuccess;
     if ((used & (used - 1)) == 0) {   // a single lane: no fork
-        if (*pending) {
-            err = hipStreamWaitEvent(main, *pending, 0);
-            *pending = nullptr;
-        }
+        err = wait_pending();
         for (size_t i = b; i < e && err == hipSuccess; ++i) err = run(ls[i], main);
         return err;
     }
-    const bool defer = allow_defer && only_glanczos && (used & (1 << 2));
     hipEvent_t fork;
     err = event(&fork);
     if (err == hipSuccess) err = hipEventRecord(fork, main);
@@ -848,25 +854,23 @@ hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStrea
         if (used & (1 << lane)) err = hipStreamWaitEvent(aux[lane - 1], fork, 0);
     for (size_t i = b; i < e && err == hipSuccess; ++i) {
         const int lane = lane_of(ls[i]);
-        if (lane == 0 && *pending) {   // the previous level's Gram-Lanczos projectors
-            err = hipStreamWaitEvent(main, *pending, 0);
-            *pending = nullptr;
-            if (err != hipSuccess) break;
-        }
-        err = run(ls[i], lane == 0 ? main : aux[lane - 1]);
+        if (lane == 0) err = wait_pending();   // the previous level's projectors
+        if (err == hipSuccess) err = run(ls[i], lane == 0 ? main : aux[lane - 1]);
     }
-    hipEvent_t deferred = nullptr;
+    hipEvent_t deferred[2] = {nullptr, nullptr};
     for (int lane = 1; lane < kLanes && err == hipSuccess; ++lane)
         if (used & (1 << lane)) {
             hipEvent_t join;
             err = event(&join);
             if (err == hipSuccess) err = hipEventRecord(join, aux[lane - 1]);
             if (err != hipSuccess) break;
-            if (lane == 2 && defer) deferred = join;
+            const bool defer = allow_defer && (lane == 1 || (lane == 2 && lane2_glanczos));
+            if (defer) deferred[lane - 1] = join;
             else err = hipStreamWaitEvent(main, join, 0);
         }
-    if (err == hipSuccess && *pending) err = hipStreamWaitEvent(main, *pending, 0);   // never past one level
-    *pending = deferred;
+    if (err == hipSuccess) err = wait_pending();   // never past one level
+    pending[0] = deferred[0];
+    pending[1] = deferred[1];
     return err;
 }
 
@@ -1130,14 +1134,15 @@ tn_status enqueue_forward(tn_ctx* c) {
         return err;
     };
     size_t next_ev = 0;
-    hipEvent_t pending = nullptr;
+    hipEvent_t pending[2] = {nullptr, nullptr};
     for (size_t b = 0; b < c->launches.size();) {
         size_t e = b;
         while (e < c->launches.size() && c->launches[e].level == c->launches[b].level) ++e;
-        HIP_TRY(c, run_level(c->launches, b, e, s, c->aux, c->sync_ev, next_ev, run, &pending, e < c->launches.size()));
+        HIP_TRY(c, run_level(c->launches, b, e, s, c->aux, c->sync_ev, next_ev, run, pending, e < c->launches.size()));
         b = e;
     }
-    if (pending) HIP_TRY(c, hipStreamWaitEvent(s, pending, 0));
+    for (hipEvent_t ev : pending)
+        if (ev) HIP_TRY(c, hipStreamWaitEvent(s, ev, 0));
     const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
     HIP_TRY(c, launch_result(prec, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
                              c->d_result, s));
@@ -1733,14 +1738,15 @@ tn_status enqueue_batch_forward(tn_batch* b) {
         return hipSuccess;
     };
     size_t next_ev = 0;
-    hipEvent_t pending = nullptr;
+    hipEvent_t pending[2] = {nullptr, nullptr};
     for (size_t i = 0; i < b->launches.size();) {
         size_t e = i;
         while (e < b->launches.size() && b->launches[e].level == b->launches[i].level) ++e;
-        BHIP_TRY(b, run_level(b->launches, i, e, s, b->aux, b->sync_ev, next_ev, run, &pending, e < b->launches.size()));
+        BHIP_TRY(b, run_level(b->launches, i, e, s, b->aux, b->sync_ev, next_ev, run, pending, e < b->launches.size()));
         i = e;
     }
-    if (pending) BHIP_TRY(b, hipStreamWaitEvent(s, pending, 0));
+    for (hipEvent_t ev : pending)
+        if (ev) BHIP_TRY(b, hipStreamWaitEvent(s, ev, 0));
     for (int i = 0; i < (int)b->ctxs.size(); ++i) {
         tn_ctx* c = b->ctxs[i];
         const Plan& P = c->plan;

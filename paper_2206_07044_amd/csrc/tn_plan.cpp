@@ -509,13 +509,17 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         // the operator S and its half product T1 are formed at the sides' level,
                         // after the side factors (same stream), so the workspace lives from there
                         c.work_buf = new_buf(words * 8, BUF_WORK, core.level - 1);
-                        // the executor lets a Gram-Lanczos launch run on into the next level (only
-                        // the re-absorbing GEMMs wait for it), so what it reads lives one level longer
+                        // the executor lets a compression launch run on into the next level (only the
+                        // re-absorbing GEMMs wait for it), so what it reads lives one level longer
                         touch(c.work_buf, core.level + 1);
                         touch(c.side_a_buf, core.level + 1);
                         touch(c.side_b_buf, core.level + 1);
                     } else {
                         c.work_buf = new_buf((4 * D * D + 4 * D) * 8, BUF_WORK, core.level);
+                        // like a Gram-Lanczos launch, a core launch may run on into the next level
+                        touch(c.work_buf, core.level + 1);
+                        touch(c.side_a_buf, core.level + 1);
+                        touch(c.side_b_buf, core.level + 1);
                     }
                 }
                 c.pl_buf = new_buf(D * nw * w, BUF_PROJ, core.level);
