@@ -537,6 +537,171 @@ __device__ int pivoted_cholesky(double* G, int D, double* R, int* chosen, CoreSh
     return r;
 }
 
+// The same factorisation for 64 < D <= kCholBlkMaxD, blocked: pivots are taken kCholPanel at a
+// time, the panel's rows of R kept in LDS (row t: R[t, j] = (G'[p, j] - sum over the panel's
+// earlier rows of R[s, p] R[s, j]) / R[t, p], with G' the Gram updated by the previous panels),
+// then one rank-kCholPanel update of the remaining rows and columns of G (destroyed).  The
+// remaining diagonal is kept in LDS; the pivot is its largest entry (DPP maximum, lowest index
+// among equals by ballot).  Same pivots, ties and stopping rule as pivoted_cholesky.
+constexpr int kCholPanel = 16;
+constexpr int kCholBlkMaxD = 384;
+__device__ int pivoted_cholesky_blocked(double* __restrict__ G, int D, double* __restrict__ R, double* lds,
+                                        CoreShared& sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* diag = lds;
+    double* pan = lds + D;                              // kCholPanel rows of length D
+    int* chosen = (int*)(pan + kCholPanel * D);
+    for (int j = tid; j < D; j += kCoreThreads) {
+        diag[j] = G[(int64_t)j * D + j];
+        chosen[j] = 0;
+    }
+    __syncthreads();
+    double tol = 0.0;
+    int r = 0;
+    bool done = false;
+    for (int t0 = 0; t0 < D && !done; t0 += kCholPanel) {
+        int np = 0;
+        for (int t = t0; t < D && t < t0 + kCholPanel; ++t) {
+            if (wave == 0) {
+                double bl = -1.0;
+                for (int i = lane; i < D; i += 64)
+                    if (!chosen[i]) bl = fmax(bl, diag[i]);
+                const double bv = wave_max(bl);
+                int bi = -1;
+                for (int i0 = 0; i0 < D && bi < 0; i0 += 64) {
+                    const int i = i0 + lane;
+                    const unsigned long long m = __ballot(i < D && !chosen[i] && diag[i] == bv);
+                    if (m) bi = i0 + __ffsll(m) - 1;
+                }
+                if (lane == 0) { sh.rv[0] = bv; sh.ri[0] = bi; }
+            }
+            __syncthreads();
+            const double piv = sh.rv[0];
+            const int p = sh.ri[0];
+            if (t == 0) tol = 1e-15 * piv;
+            if (!(piv > tol) || !(piv > 0.0)) { done = true; break; }
+            const double rp = sqrt(piv);
+            const int u = t - t0;
+            for (int j = tid; j < D; j += kCoreThreads) {
+                const bool ch = chosen[j] != 0;
+                double v = 0.0;
+                if (!ch) {
+                    if (j == p) {
+                        v = rp;
+                    } else {
+                        double a = G[(int64_t)p * D + j];
+                        for (int q = 0; q < u; ++q) a = fma(-pan[q * D + p], pan[q * D + j], a);
+                        v = a / rp;
+                    }
+                }
+                R[(int64_t)t * D + j] = v;
+                pan[u * D + j] = v;
+                if (j == p) chosen[j] = 1;
+                else if (!ch) diag[j] -= v * v;
+            }
+            __syncthreads();
+            np = u + 1;
+            r = t + 1;
+        }
+        if (done || t0 + kCholPanel >= D) break;
+        // G -= Pᵀ P over the rows and columns not yet chosen (the panel P in LDS): a wave per
+        // row, the lane's columns of P held in registers
+        for (int j0 = 0; j0 < D; j0 += 64) {
+            const int j = j0 + lane;
+            const bool cj = j < D && !chosen[j];
+            double pj[kCholPanel];
+#pragma unroll
+            for (int q = 0; q < kCholPanel; ++q) pj[q] = (cj && q < np) ? pan[q * D + j] : 0.0;
+            for (int i = wave; i < D; i += kCoreWaves) {
+                if (chosen[i]) continue;
+                double a = 0.0;
+#pragma unroll
+                for (int q = 0; q < kCholPanel; ++q) a = fma(pan[q * D + i], pj[q], a);
+                if (cj) G[(int64_t)i * D + j] -= a;
+            }
+        }
+        __syncthreads();
+    }
+    return r;
+}
+
+// The same factorisation, left-looking, for large D: step t computes only the pivot's row,
+// R[t, j] = (G[p, j] - sum_{s<t} R[s, p] R[s, j]) / R[t, p], from the rows already found, and keeps
+// the remaining diagonal d_j = G[j, j] - sum_s R[s, j]^2 in LDS (same pivots, ties and stopping
+// rule; G is read, not destroyed).  Four lanes share a column's sum.  LDS: 20 D bytes.
+constexpr int kCholLLMaxD = 3072;
+__device__ int pivoted_cholesky_ll(const double* __restrict__ G, int D, double* __restrict__ R, double* lds,
+                                   CoreShared& sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* diag = lds;
+    double* rcol = lds + D;                 // R[s, p] of the current pivot, s < t
+    int* chosen = (int*)(lds + 2 * D);
+    for (int j = tid; j < D; j += kCoreThreads) {
+        diag[j] = G[(int64_t)j * D + j];
+        chosen[j] = 0;
+    }
+    __syncthreads();
+    double tol = 0.0;
+    int r = 0;
+    for (int t = 0; t < D; ++t) {
+        if (wave == 0) {
+            double bv = -1.0;
+            int bi = 0x7fffffff;
+            for (int i = lane; i < D; i += 64) {
+                if (chosen[i]) continue;
+                const double v = diag[i];
+                if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (lane == 0) { sh.rv[0] = bv; sh.ri[0] = bi; }
+        }
+        __syncthreads();
+        const double piv = sh.rv[0];
+        const int p = sh.ri[0];
+        if (t == 0) tol = 1e-15 * piv;
+        if (!(piv > tol) || !(piv > 0.0)) break;
+        for (int q = tid; q < t; q += kCoreThreads) rcol[q] = R[(int64_t)q * D + p];
+        __syncthreads();
+        const double rp = sqrt(piv);
+        double* Rt = R + (int64_t)t * D;
+        const int k = tid & 3;
+        for (int j0 = 0; j0 < D; j0 += kCoreThreads / 4) {
+            const int j = j0 + (tid >> 2);
+            // eight independent loads in flight per lane (the rows come from L2)
+            double acc8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (j < D) {
+                int q = k;
+                for (; q + 28 < t; q += 32) {
+                    double x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = R[(int64_t)(q + 4 * u) * D + j];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc8[u] = fma(rcol[q + 4 * u], x[u], acc8[u]);
+                }
+                for (; q < t; q += 4) acc8[0] = fma(rcol[q], R[(int64_t)q * D + j], acc8[0]);
+            }
+            double acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            if (j < D && k == 0) {
+                const bool ch = chosen[j] != 0;
+                const double v = ch ? 0.0 : (j == p ? rp : (G[(int64_t)p * D + j] - acc) / rp);
+                Rt[j] = v;
+                if (j == p) chosen[j] = 1;
+                else if (!ch) diag[j] -= v * v;
+            }
+        }
+        __syncthreads();
+        r = t + 1;
+    }
+    return r;
+}
+
 // 1/x and 1/sqrt(x) (x > 0) from the hardware estimates refined by two Newton-Raphson steps
 // each (every step doubles the correct bits), to within a few ulp in float64.
 __device__ inline double rcp_nr(double x) {
@@ -932,20 +1097,26 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
 }
 
 // Column norms of W (sig[j], j < cols) and their descending order (ties: lower column first).
+// With stage (LDS, cols doubles) the ranking reads its copy of the norms instead of sig.
 template <int NT = kCoreThreads>
-__device__ void sorted_norms(const double* W, int rows, int cols, int ld, double* sig, int* order) {
+__device__ void sorted_norms(const double* W, int rows, int cols, int ld, double* sig, int* order,
+                             double* stage = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j = wave; j < cols; j += (NT / 64)) {
         double s = 0.0;
         for (int i = lane; i < rows; i += 64) s += W[(int64_t)j * ld + i] * W[(int64_t)j * ld + i];
         s = wave_sum(s);
-        if (lane == 0) sig[j] = sqrt(s);
+        if (lane == 0) {
+            sig[j] = sqrt(s);
+            if (stage) stage[j] = sqrt(s);
+        }
     }
     __syncthreads();
+    const double* sv = stage ? stage : sig;
     for (int j = tid; j < cols; j += NT) {
-        const double sj = sig[j];
+        const double sj = sv[j];
         int rank = 0;
-        for (int q = 0; q < cols; ++q) rank += (sig[q] > sj) || (sig[q] == sj && q < j);
+        for (int q = 0; q < cols; ++q) rank += (sv[q] > sj) || (sv[q] == sj && q < j);
         order[rank] = j;
     }
     __syncthreads();
@@ -1008,13 +1179,14 @@ __device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac
     __syncthreads();
 }
 
-// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA for
-// narrow N, operands read straight from memory: each wave owns 16 x 32 blocks of C (two
-// 16 x 16 x 4 instructions per step of 4 along K).  A(i, k) = A[i * ar + k * ac],
-// B(k, j) = B[k * br + j * bc].  Ends with a barrier.
-__device__ void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int64_t ac,
-                                   const double* __restrict__ B, int64_t br, int64_t bc, double* __restrict__ C,
-                                   int64_t ldc, int M, int N, int K) {
+// C (M x N) = A (M x K) . B (K x N) in float64 on MFMA for narrow N, operands read straight from
+// memory: each wave owns 16 x 32 blocks of C (two 16 x 16 x 4 instructions per step of 4 along
+// K).  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc], C(i, j) = C[i * cr + j * cc],
+// stored as TC.  Ends with a barrier.
+template <typename TC>
+__device__ void wg_gemm_narrow_to(const double* __restrict__ A, int64_t ar, int64_t ac,
+                                  const double* __restrict__ B, int64_t br, int64_t bc, TC* __restrict__ C,
+                                  int64_t cr, int64_t cc, int M, int N, int K) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int mb = (M + 15) / 16, nb = (N + 31) / 32;
@@ -1037,19 +1209,151 @@ __device__ void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int
         for (int r = 0; r < 4; ++r) {
             const int row = i0 + Mma<double>::row(lane, r);
             if (row < M) {
-                if (c0) C[(int64_t)row * ldc + gj0] = acc0[r];
-                if (c1) C[(int64_t)row * ldc + gj1] = acc1[r];
+                if (c0) C[(int64_t)row * cr + (int64_t)gj0 * cc] = (TC)acc0[r];
+                if (c1) C[(int64_t)row * cr + (int64_t)gj1 * cc] = (TC)acc1[r];
             }
         }
     }
     __syncthreads();
 }
 
+// wg_gemm_narrow_to into a row-major float64 C with leading dimension ldc.
+__device__ inline void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int64_t ac,
+                                          const double* __restrict__ B, int64_t br, int64_t bc,
+                                          double* __restrict__ C, int64_t ldc, int M, int N, int K) {
+    wg_gemm_narrow_to<double>(A, ar, ac, B, br, bc, C, ldc, 1, M, N, K);
+}
+
+// Block one-sided Jacobi for the global cores (64 < D <= 256): the columns of W are cut into
+// blocks of kBJCols, and the blocks follow a round-robin tournament, one launch per round and one
+// workgroup per block pair.  A workgroup stages its two blocks of W and V in LDS and rotates
+// every cross pair once (16 steps of 16 disjoint pairs); in the first round of a sweep each block
+// is met for the first time, so the workgroup also rotates the pairs inside its two blocks (a
+// 32-column tournament, 31 steps).  Every column pair is thus rotated once per sweep, as in the
+// one-workgroup Jacobi, with the same rotation, thresholds and stopping rule.
+constexpr int kBJCols = 16;
+constexpr int kBJRows = 256;
+constexpr int kBJSweeps = 32;   // sweeps issued as block launches; a core still rotating after
+                                // them finishes in the one-workgroup Jacobi
+constexpr size_t kBJLdsBytes = (size_t)2 * 2 * kBJCols * kBJRows * sizeof(double);
+
+// Per-core block-Jacobi state after the singular values: ranks (two ints), ||W||_F^2, and one
+// flag per issued sweep (set when the sweep made a rotation above the quadratic-convergence level).
+__device__ inline int* core_ranks(double* gsig, int D) { return (int*)(gsig + 2 * D); }
+__device__ inline double* core_fro2(double* gsig, int D) { return gsig + 2 * D + 1; }
+__device__ inline int* core_bigflags(double* gsig, int D) { return (int*)(gsig + 2 * D + 2); }
+
+__global__ __launch_bounds__(kCoreThreads) void block_jacobi_kernel(const CoreDesc* __restrict__ descs, int per_core,
+                                                                    int sweep, int round) {
+    extern __shared__ double lds[];
+    __shared__ int s_big;
+    const int ci = blockIdx.x / per_core, q = blockIdx.x - ci * per_core;
+    const CoreDesc& d = descs[ci];
+    const int D = d.D;
+    const int64_t DD = (int64_t)D * D;
+    double* W = d.work + 2 * DD;
+    double* V = W + DD;
+    double* gsig = d.work + 4 * DD;
+    int* big = core_bigflags(gsig, D);
+    if (sweep > 0 && big[sweep - 1] == 0) return;   // the previous sweep converged
+    const int* ranks = core_ranks(gsig, D);
+    const int ra = ranks[0], rb = ranks[1];
+    int nb = (rb + kBJCols - 1) / kBJCols;
+    nb += nb & 1;
+    if (q >= nb / 2 || round >= nb - 1) return;
+    const int b1 = rr_col(q, round, nb), b2 = rr_col(nb - 1 - q, round, nb);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* lw = lds;                              // local column c at lw + c * kBJRows
+    double* lv = lds + 2 * kBJCols * kBJRows;
+    {
+        // every load of the two blocks issued before the first LDS write (the columns were last
+        // written by other workgroups, possibly on other dies: far memory latency)
+        constexpr int kPer = 2 * kBJCols * kBJRows / kCoreThreads;
+        double xw[kPer], xv[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int idx = tid + u * kCoreThreads;
+            const int c = idx / kBJRows, i = idx - c * kBJRows;
+            const int g = c < kBJCols ? b1 * kBJCols + c : b2 * kBJCols + c - kBJCols;
+            xw[u] = (g < rb && i < ra) ? W[(int64_t)g * D + i] : 0.0;
+            xv[u] = (g < rb && i < rb) ? V[(int64_t)g * D + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            lw[tid + u * kCoreThreads] = xw[u];
+            lv[tid + u * kCoreThreads] = xv[u];
+        }
+    }
+    if (tid == 0) s_big = 0;
+    __syncthreads();
+    const double zero2 = kZeroRel * kZeroRel * *core_fro2(gsig, D);
+    const double tol = 2.220446049250313e-16 * (double)max(ra, 16);
+    const int steps = round == 0 ? 2 * kBJCols - 1 : kBJCols;
+    for (int t = 0; t < steps; ++t) {
+        // one pair per wave: the 32-column tournament in the first round, cross pairs after it
+        int p1, p2;
+        if (round == 0) {
+            p1 = rr_col(wave, t, 2 * kBJCols);
+            p2 = rr_col(2 * kBJCols - 1 - wave, t, 2 * kBJCols);
+        } else {
+            p1 = wave;
+            p2 = kBJCols + ((wave + t) & (kBJCols - 1));
+        }
+        const int g1 = p1 < kBJCols ? b1 * kBJCols + p1 : b2 * kBJCols + p1 - kBJCols;
+        const int g2 = p2 < kBJCols ? b1 * kBJCols + p2 : b2 * kBJCols + p2 - kBJCols;
+        double* w1 = lw + p1 * kBJRows;
+        double* w2 = lw + p2 * kBJRows;
+        double* v1 = lv + p1 * kBJRows;
+        double* v2 = lv + p2 * kBJRows;
+        double x[4], y[4], xv[4], yv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = w1[lane + 64 * k];
+            y[k] = w2[lane + 64 * k];
+            xv[k] = v1[lane + 64 * k];
+            yv[k] = v2[lane + 64 * k];
+        }
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a = fma(x[k], x[k], a);
+            b = fma(y[k], y[k], b);
+            g = fma(x[k], y[k], g);
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        g = wave_sum(g);
+        if (g1 < rb && g2 < rb && a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
+            double c, sn;
+            jacobi_rotation(a, b, g, &c, &sn);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w1[lane + 64 * k] = c * x[k] - sn * y[k];
+                w2[lane + 64 * k] = sn * x[k] + c * y[k];
+                v1[lane + 64 * k] = c * xv[k] - sn * yv[k];
+                v2[lane + 64 * k] = sn * xv[k] + c * yv[k];
+            }
+            if (lane == 0 && g * g > kQuadRel2 * a * b) s_big = 1;
+        }
+        __syncthreads();
+    }
+    for (int idx = tid; idx < 2 * kBJCols * kBJRows; idx += kCoreThreads) {
+        const int c = idx / kBJRows, i = idx - c * kBJRows;
+        const int g = c < kBJCols ? b1 * kBJCols + c : b2 * kBJCols + c - kBJCols;
+        if (g < rb && i < ra) W[(int64_t)g * D + i] = lw[idx];
+        if (g < rb && i < rb) V[(int64_t)g * D + i] = lv[idx];
+    }
+    if (tid == 0 && s_big) big[sweep] = 1;
+}
+
+// phase 0: the whole compression.  Global variant only: phase 1 stops after the core W and V = I
+// (with ranks, ||W||_F^2 and cleared sweep flags in the workspace) for block_jacobi_kernel;
+// phase 2 starts from the rotated W, V and does the rest.
 template <bool kLds, typename Tp>
 __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
                                                             double* __restrict__ stat_disc,
                                                             int32_t* __restrict__ stat_tie,
-                                                            int32_t* __restrict__ stat_sweeps) {
+                                                            int32_t* __restrict__ stat_sweeps, int phase) {
     extern __shared__ double lds[];
     __shared__ CoreShared sh;
     constexpr int NT = kLds ? kCoreLdsThreads : kCoreThreads;
@@ -1072,7 +1376,10 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
 
     // ---- reduced factors R~_A (ra x D), R~_B (rb x D)
     int ra, rb;
-    if (kLds) {
+    if (!kLds && phase == 2) {
+        ra = core_ranks(gsig, D)[0];
+        rb = core_ranks(gsig, D)[1];
+    } else if (kLds) {
         // split-K Gram partials summed into LDS (side A into W, side B into V), explicit
         // factors copied; then one wave per side runs its pivoted Cholesky
         const int DDi = D * D;
@@ -1125,7 +1432,9 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
                     W[idx] = s;
                 }
                 __syncthreads();
-                rk[side] = pivoted_cholesky(W, D, R, chosen, sh);
+                rk[side] = D <= kCholBlkMaxD ? pivoted_cholesky_blocked(W, D, R, lds, sh)
+                           : D <= kCholLLMaxD  ? pivoted_cholesky_ll(W, D, R, lds, sh)
+                                               : pivoted_cholesky(W, D, R, chosen, sh);
             } else {
                 const int rows = side == 0 ? d.rows_a : d.rows_b;
                 for (int64_t idx = tid; idx < (int64_t)rows * D; idx += NT) R[idx] = fac[idx];
@@ -1140,7 +1449,7 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     // ---- core W = R~_A R~_B^T  (ra x rb), V = I
     if constexpr (!kLds) {
         // column j of W is row j of R~_B R~_A^T: one workgroup GEMM on the MFMA (LDS staging)
-        wg_gemm_f64(Rb, D, 1, Ra, 1, D, W, D, rb, ra, D, lds);
+        if (phase != 2) wg_gemm_f64(Rb, D, 1, Ra, 1, D, W, D, rb, ra, D, lds);
     } else
     for (int idx = tid; idx < ra * rb; idx += NT) {
         const int j = idx / ra, i = idx - j * ra;
@@ -1155,16 +1464,53 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         }
         W[(int64_t)j * D + i] = s;
     }
-    for (int idx = tid; idx < rb * rb; idx += NT) {
-        const int j = idx / rb, i = idx - j * rb;
-        V[(int64_t)j * D + i] = (i == j) ? 1.0 : 0.0;
-    }
+    if (phase != 2)
+        for (int idx = tid; idx < rb * rb; idx += NT) {
+            const int j = idx / rb, i = idx - j * rb;
+            V[(int64_t)j * D + i] = (i == j) ? 1.0 : 0.0;
+        }
     __syncthreads();
+    if (!kLds && phase == 1) {
+        double f = 0.0;
+        for (int idx = tid; idx < ra * rb; idx += NT) {
+            const int j = idx / ra, i = idx - j * ra;
+            const double x = W[(int64_t)j * D + i];
+            f = fma(x, x, f);
+        }
+        f = wave_sum(f);
+        if (lane == 0) sh.rv[wave] = f;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < kCoreWaves; ++w) t += sh.rv[w];
+            *core_fro2(gsig, D) = t;
+            core_ranks(gsig, D)[0] = ra;
+            core_ranks(gsig, D)[1] = rb;
+        }
+        for (int t = tid; t < kBJSweeps; t += NT) core_bigflags(gsig, D)[t] = 0;
+        return;
+    }
 
     // ---- one-sided (Hestenes) Jacobi on the columns of W, accumulating V
     int sweeps = 0;
     bool converged;
-    if constexpr (kLds)   // ra, rb <= D <= 64
+    if (!kLds && phase == 2) {
+        // sweeps made by the block launches: the first one without a large rotation ended them
+        const int* big = core_bigflags(gsig, D);
+        const int issued = min(kBJSweeps, max_sweeps);
+        sweeps = issued;
+        converged = rb <= 1;
+        for (int t = 0; t < issued && !converged; ++t)
+            if (big[t] == 0) {
+                sweeps = t + 1;
+                converged = true;
+            }
+        if (!converged && max_sweeps > issued) {
+            int more = 0;
+            converged = jacobi_svd_256(W, V, ra, rb, D, max_sweeps - issued, sh, &more);
+            sweeps += more;
+        }
+    } else if constexpr (kLds)   // ra, rb <= D <= 64
         converged = (ra <= 32 && rb <= 32) ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
                                            : jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
     else
@@ -1174,7 +1520,7 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
                                                : jacobi_svd(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
 
     // ---- singular values and descending order (ties: lower column first)
-    sorted_norms<NT>(W, ra, rb, D, sig, order);
+    sorted_norms<NT>(W, ra, rb, D, sig, order, kLds ? nullptr : lds);
     double fro = 0.0;
     for (int j = 0; j < rb; ++j) fro += sig[j] * sig[j];
     fro = sqrt(fro);
@@ -1184,6 +1530,24 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     const double smax = rb > 0 ? sig[order[0]] : 0.0;
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
+    if constexpr (!kLds) {
+        // the kept columns of V and W, sorted and scaled by sigma^-1/2 and sigma^-3/2 (zero where
+        // the projector column is zero), then P_L = R~_B^T Vs and P_R^T = R~_A^T Ws on the MFMA
+        double* Vs = d.work + 4 * DD + 4 * D;
+        double* Ws = Vs + (int64_t)D * cn;
+        for (int idx = tid; idx < D * cn; idx += NT) {
+            const int t = idx / D, i = idx - t * D;
+            const int j = t < rb ? order[t] : -1;
+            const double s = j >= 0 ? sig[j] : 0.0;
+            const bool keep = s > kNoiseRel * smax && s > 4.0 * kZeroRel * fro && s >= d.cutoff * smax;
+            const double rs = keep ? sqrt(s) : 1.0;
+            Vs[idx] = (keep && i < rb) ? V[(int64_t)j * D + i] / rs : 0.0;
+            Ws[idx] = (keep && i < ra) ? W[(int64_t)j * D + i] / (s * rs) : 0.0;
+        }
+        __syncthreads();
+        wg_gemm_narrow_to<Tp>(Rb, 1, D, Vs, 1, D, PL, cn, 1, D, cn, rb);
+        wg_gemm_narrow_to<Tp>(Ra, 1, D, Ws, 1, D, PR, 1, D, D, cn, ra);
+    } else
     for (int idx = tid; idx < D * cn; idx += NT) {
         const int dd = idx / cn, t = idx - dd * cn;
         const int j = t < rb ? order[t] : -1;
@@ -2321,6 +2685,7 @@ hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, 
 size_t core_lds_bytes(int max_d) { return (size_t)4 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
+    (void)hipFuncSetAttribute((const void*)block_jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBJLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<false, double>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<false, float>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<false, bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
@@ -2346,8 +2711,22 @@ hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int 
     const size_t bytes = core_lds_bytes(max_d);
     return by_prec(prec, [&](auto t) {
         using Tp = decltype(t);
-        if (lds) core_kernel<true, Tp><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
-        else core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps);
+        if (lds) {
+            core_kernel<true, Tp><<<grid, block, bytes, s>>>(descs, max_sweeps, disc, tie, sweeps, 0);
+        } else if (max_d > 64 && max_d <= kBJRows) {
+            // factors and core; block-Jacobi sweeps, one launch per tournament round; the rest
+            core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps, 1);
+            int nb = (max_d + kBJCols - 1) / kBJCols;
+            nb += nb & 1;
+            const dim3 bgrid(ndesc * (nb / 2));
+            const int issued = kBJSweeps < max_sweeps ? kBJSweeps : max_sweeps;
+            for (int sw = 0; sw < issued; ++sw)
+                for (int r = 0; r < nb - 1; ++r)
+                    block_jacobi_kernel<<<bgrid, block, kBJLdsBytes, s>>>(descs, nb / 2, sw, r);
+            core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps, 2);
+        } else {
+            core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps, 0);
+        }
     });
 }
 
