@@ -1183,14 +1183,14 @@ __device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac
 // memory: each wave owns 16 x 32 blocks of C (two 16 x 16 x 4 instructions per step of 4 along
 // K).  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc], C(i, j) = C[i * cr + j * cc],
 // stored as TC.  Ends with a barrier.
-template <typename TC>
+template <typename TC, int NW = kCoreWaves>
 __device__ void wg_gemm_narrow_to(const double* __restrict__ A, int64_t ar, int64_t ac,
                                   const double* __restrict__ B, int64_t br, int64_t bc, TC* __restrict__ C,
                                   int64_t cr, int64_t cc, int M, int N, int K) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int mb = (M + 15) / 16, nb = (N + 31) / 32;
-    for (int blk = wave; blk < mb * nb; blk += kCoreWaves) {
+    for (int blk = wave; blk < mb * nb; blk += NW) {
         const int i0 = (blk % mb) * 16, j0 = (blk / mb) * 32;
         const int gi = i0 + lr, gj0 = j0 + lr, gj1 = j0 + 16 + lr;
         const bool ri = gi < M, c0 = gj0 < N, c1 = gj1 < N;
@@ -1226,16 +1226,21 @@ __device__ inline void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t 
 
 // Block one-sided Jacobi for the global cores (64 < D <= 256): the columns of W are cut into
 // blocks of kBJCols, and the blocks follow a round-robin tournament, one launch per round and one
-// workgroup per block pair.  A workgroup stages its two blocks of W and V in LDS and rotates
-// every cross pair once (16 steps of 16 disjoint pairs); in the first round of a sweep each block
-// is met for the first time, so the workgroup also rotates the pairs inside its two blocks (a
-// 32-column tournament, 31 steps).  Every column pair is thus rotated once per sweep, as in the
-// one-workgroup Jacobi, with the same rotation, thresholds and stopping rule.
+// workgroup per block pair.  A workgroup stages its two blocks of W in LDS and rotates every cross
+// pair once (16 steps of 16 disjoint pairs); in the first round of a sweep each block is met for
+// the first time, so the workgroup also rotates the pairs inside its two blocks (a 32-column
+// tournament, 31 steps).  Every column pair is thus rotated once per sweep, as in the
+// one-workgroup Jacobi, with the same rotation, thresholds and stopping rule.  A pair is rotated
+// by one 16-lane DPP row (16 rows of W per lane), four pairs per wave; the rotations of the
+// launch are accumulated in a 32 x 32 matrix Q and applied to the two blocks of V (staged in LDS
+// with W) once at the end, V <- V Q on the MFMA.
 constexpr int kBJCols = 16;
 constexpr int kBJRows = 256;
+constexpr int kBJThreads = 256;
+constexpr int kBJKR = kBJRows / 16;   // rows of W per lane
 constexpr int kBJSweeps = 32;   // sweeps issued as block launches; a core still rotating after
                                 // them finishes in the one-workgroup Jacobi
-constexpr size_t kBJLdsBytes = (size_t)2 * 2 * kBJCols * kBJRows * sizeof(double);
+constexpr size_t kBJLdsBytes = (size_t)(4 * kBJCols * kBJRows + 4 * kBJCols * kBJCols) * sizeof(double);
 
 // Per-core block-Jacobi state after the singular values: ranks (two ints), ||W||_F^2, and one
 // flag per issued sweep (set when the sweep made a rotation above the quadratic-convergence level).
@@ -1243,10 +1248,11 @@ __device__ inline int* core_ranks(double* gsig, int D) { return (int*)(gsig + 2 
 __device__ inline double* core_fro2(double* gsig, int D) { return gsig + 2 * D + 1; }
 __device__ inline int* core_bigflags(double* gsig, int D) { return (int*)(gsig + 2 * D + 2); }
 
-__global__ __launch_bounds__(kCoreThreads) void block_jacobi_kernel(const CoreDesc* __restrict__ descs, int per_core,
-                                                                    int sweep, int round) {
+__global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc* __restrict__ descs, int per_core,
+                                                                  int sweep, int round) {
     extern __shared__ double lds[];
     __shared__ int s_big;
+    constexpr int NC = 2 * kBJCols;
     const int ci = blockIdx.x / per_core, q = blockIdx.x - ci * per_core;
     const CoreDesc& d = descs[ci];
     const int D = d.D;
@@ -1263,85 +1269,121 @@ __global__ __launch_bounds__(kCoreThreads) void block_jacobi_kernel(const CoreDe
     if (q >= nb / 2 || round >= nb - 1) return;
     const int b1 = rr_col(q, round, nb), b2 = rr_col(nb - 1 - q, round, nb);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double* lw = lds;                              // local column c at lw + c * kBJRows
-    double* lv = lds + 2 * kBJCols * kBJRows;
+    const int quarter = lane >> 4, ql = lane & 15;
+    auto gcol = [&](int c) { return c < kBJCols ? b1 * kBJCols + c : b2 * kBJCols + c - kBJCols; };
+    double* lw = lds;                    // local column c of W at lw + c * kBJRows
+    double* lv = lw + NC * kBJRows;      // the same for V
+    double* lq = lv + NC * kBJRows;      // Q, column c at lq + c * NC
     {
         // every load of the two blocks issued before the first LDS write (the columns were last
         // written by other workgroups, possibly on other dies: far memory latency)
-        constexpr int kPer = 2 * kBJCols * kBJRows / kCoreThreads;
+        constexpr int kPer = NC * kBJRows / kBJThreads;
         double xw[kPer], xv[kPer];
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            const int idx = tid + u * kCoreThreads;
+            const int idx = tid + u * kBJThreads;
             const int c = idx / kBJRows, i = idx - c * kBJRows;
-            const int g = c < kBJCols ? b1 * kBJCols + c : b2 * kBJCols + c - kBJCols;
+            const int g = gcol(c);
             xw[u] = (g < rb && i < ra) ? W[(int64_t)g * D + i] : 0.0;
             xv[u] = (g < rb && i < rb) ? V[(int64_t)g * D + i] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
-            lw[tid + u * kCoreThreads] = xw[u];
-            lv[tid + u * kCoreThreads] = xv[u];
+            lw[tid + u * kBJThreads] = xw[u];
+            lv[tid + u * kBJThreads] = xv[u];
         }
+        for (int idx = tid; idx < NC * NC; idx += kBJThreads) lq[idx] = (idx / NC == idx % NC) ? 1.0 : 0.0;
     }
     if (tid == 0) s_big = 0;
     __syncthreads();
     const double zero2 = kZeroRel * kZeroRel * *core_fro2(gsig, D);
     const double tol = 2.220446049250313e-16 * (double)max(ra, 16);
-    const int steps = round == 0 ? 2 * kBJCols - 1 : kBJCols;
+    const int steps = round == 0 ? NC - 1 : kBJCols;
+    const int pi = wave * 4 + quarter;   // this 16-lane row's pair
     for (int t = 0; t < steps; ++t) {
-        // one pair per wave: the 32-column tournament in the first round, cross pairs after it
         int p1, p2;
         if (round == 0) {
-            p1 = rr_col(wave, t, 2 * kBJCols);
-            p2 = rr_col(2 * kBJCols - 1 - wave, t, 2 * kBJCols);
+            p1 = rr_col(pi, t, NC);
+            p2 = rr_col(NC - 1 - pi, t, NC);
         } else {
-            p1 = wave;
-            p2 = kBJCols + ((wave + t) & (kBJCols - 1));
+            p1 = pi;
+            p2 = kBJCols + ((pi + t) & (kBJCols - 1));
         }
-        const int g1 = p1 < kBJCols ? b1 * kBJCols + p1 : b2 * kBJCols + p1 - kBJCols;
-        const int g2 = p2 < kBJCols ? b1 * kBJCols + p2 : b2 * kBJCols + p2 - kBJCols;
         double* w1 = lw + p1 * kBJRows;
         double* w2 = lw + p2 * kBJRows;
-        double* v1 = lv + p1 * kBJRows;
-        double* v2 = lv + p2 * kBJRows;
-        double x[4], y[4], xv[4], yv[4];
+        double x[kBJKR], y[kBJKR];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            x[k] = w1[lane + 64 * k];
-            y[k] = w2[lane + 64 * k];
-            xv[k] = v1[lane + 64 * k];
-            yv[k] = v2[lane + 64 * k];
+        for (int k = 0; k < kBJKR; ++k) {
+            x[k] = w1[ql + 16 * k];
+            y[k] = w2[ql + 16 * k];
         }
-        double a = 0.0, b = 0.0, g = 0.0;
+        double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, g0 = 0.0, g1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            a = fma(x[k], x[k], a);
-            b = fma(y[k], y[k], b);
-            g = fma(x[k], y[k], g);
+        for (int k = 0; k < kBJKR; k += 2) {
+            a0 = fma(x[k], x[k], a0);
+            b0 = fma(y[k], y[k], b0);
+            g0 = fma(x[k], y[k], g0);
+            a1 = fma(x[k + 1], x[k + 1], a1);
+            b1 = fma(y[k + 1], y[k + 1], b1);
+            g1 = fma(x[k + 1], y[k + 1], g1);
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        g = wave_sum(g);
-        if (g1 < rb && g2 < rb && a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
+        const double a = row16_sum(a0 + a1), b = row16_sum(b0 + b1), g = row16_sum(g0 + g1);
+        if (gcol(p1) < rb && gcol(p2) < rb && a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
             double c, sn;
             jacobi_rotation(a, b, g, &c, &sn);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                w1[lane + 64 * k] = c * x[k] - sn * y[k];
-                w2[lane + 64 * k] = sn * x[k] + c * y[k];
-                v1[lane + 64 * k] = c * xv[k] - sn * yv[k];
-                v2[lane + 64 * k] = sn * xv[k] + c * yv[k];
+            for (int k = 0; k < kBJKR; ++k) {
+                w1[ql + 16 * k] = c * x[k] - sn * y[k];
+                w2[ql + 16 * k] = sn * x[k] + c * y[k];
             }
-            if (lane == 0 && g * g > kQuadRel2 * a * b) s_big = 1;
+            double* q1 = lq + p1 * NC;
+            double* q2 = lq + p2 * NC;
+#pragma unroll
+            for (int k = 0; k < NC / 16; ++k) {
+                const double u1 = q1[ql + 16 * k], u2 = q2[ql + 16 * k];
+                q1[ql + 16 * k] = c * u1 - sn * u2;
+                q2[ql + 16 * k] = sn * u1 + c * u2;
+            }
+            if (ql == 0 && g * g > kQuadRel2 * a * b) s_big = 1;
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < 2 * kBJCols * kBJRows; idx += kCoreThreads) {
+    for (int idx = tid; idx < NC * kBJRows; idx += kBJThreads) {
         const int c = idx / kBJRows, i = idx - c * kBJRows;
-        const int g = c < kBJCols ? b1 * kBJCols + c : b2 * kBJCols + c - kBJCols;
+        const int g = gcol(c);
         if (g < rb && i < ra) W[(int64_t)g * D + i] = lw[idx];
-        if (g < rb && i < rb) V[(int64_t)g * D + i] = lv[idx];
+    }
+    // V <- V Q on the MFMA (16 x 16 x 4): a wave per 64 rows of V, Q's fragments held in registers,
+    // a row block's fragments of V read from LDS before its products; the two 16-column halves
+    // of the result are the two blocks of V
+    {
+        const int lr = lane & 15, lk = lane >> 4;
+        double qb0[NC / 4], qb1[NC / 4];
+#pragma unroll
+        for (int u = 0; u < NC / 4; ++u) {
+            qb0[u] = lq[lr * NC + 4 * u + lk];
+            qb1[u] = lq[(kBJCols + lr) * NC + 4 * u + lk];
+        }
+        const int gA = b1 * kBJCols + lr, gB = b2 * kBJCols + lr;
+        for (int i1 = wave * 64; i1 < wave * 64 + 64 && i1 < rb; i1 += 16) {
+            double av[NC / 4];
+#pragma unroll
+            for (int u = 0; u < NC / 4; ++u) av[u] = lv[(4 * u + lk) * kBJRows + i1 + lr];
+            v4d acc0 = v4d{0.0, 0.0, 0.0, 0.0}, acc1 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < NC / 4; ++u) {
+                acc0 = Mma<double>::run(av[u], qb0[u], acc0);
+                acc1 = Mma<double>::run(av[u], qb1[u], acc1);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i1 + Mma<double>::row(lane, r);
+                if (row < rb) {
+                    if (gA < rb) V[(int64_t)gA * D + row] = acc0[r];
+                    if (gB < rb) V[(int64_t)gB * D + row] = acc1[r];
+                }
+            }
+        }
     }
     if (tid == 0 && s_big) big[sweep] = 1;
 }
@@ -2722,7 +2764,7 @@ hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int 
             const int issued = kBJSweeps < max_sweeps ? kBJSweeps : max_sweeps;
             for (int sw = 0; sw < issued; ++sw)
                 for (int r = 0; r < nb - 1; ++r)
-                    block_jacobi_kernel<<<bgrid, block, kBJLdsBytes, s>>>(descs, nb / 2, sw, r);
+                    block_jacobi_kernel<<<bgrid, dim3(kBJThreads), kBJLdsBytes, s>>>(descs, nb / 2, sw, r);
             core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps, 2);
         } else {
             core_kernel<false, Tp><<<grid, block, kCoreBwdLdsBytes, s>>>(descs, max_sweeps, disc, tie, sweeps, 0);
