@@ -42,7 +42,7 @@ PEAKS = {  # MI355X published dense peaks
 # was measured on (SHA-256 prefix of tn_kernels.hip), else the bench line reports null.
 MEASURED_TRAFFIC = {
     ("core_lds", "fp32", "ising-cubic-12x12x12-beta0.22-chi16-span-sweep"): {
-        "bytes_per_launch": 393.4 * 1024, "kernel_source_sha256": "65a94436e5ad030f",
+        "bytes_per_launch": 401.7 * 1024, "kernel_source_sha256": "1174c7ebe60d9258",
         "source": "profiles/core_lds_traffic_ising12_chi16_fp32.md"},
 }
 
@@ -55,6 +55,22 @@ def measured_traffic(kind, precision, workload):
     with open(os.path.join(ROOT, "paper_2206_07044_amd", "csrc", "tn_kernels.hip"), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     return rec["bytes_per_launch"] if sha.startswith(rec["kernel_source_sha256"]) else None
+
+
+# The oracle's ln|Z| for the default lattice and tree, per chi (written by tests/golden/make_golden.py,
+# which calls only the CPU oracle)
+ORACLE_GOLDEN = {16: "cubic_12.json", 32: "cubic_12_chi32.json"}
+
+
+def oracle_lnz(shape, beta, chi):
+    name = ORACLE_GOLDEN.get(chi)
+    if shape != (12, 12, 12) or beta != 0.22 or name is None:
+        return None
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return float(json.load(f)["oracle_lnZ"])
+    except (OSError, ValueError, KeyError):   # not written (yet): no comparison
+        return None
 
 
 def build_instance(shape, beta):
@@ -146,6 +162,7 @@ def main() -> int:
     ap.add_argument("--fwd-bwd-steps", type=int, default=1, help="timed forward+reverse passes (0: skip)")
     ap.add_argument("--batch", type=int, default=8, help="instances in the batched leg (<= 1: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--per-chi", default="32", help="other chi values timed in fp32 and fp64 ('' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -226,6 +243,7 @@ def main() -> int:
             "arena_bytes": info["arena_bytes"],
             "ln_abs_z": lnz,
             "sign": sign,
+            "oracle_ln_abs_z": oracle_lnz(shape, args.beta, args.chi),
         },
         "roofline": {
             "kernel": dominant, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
@@ -257,6 +275,9 @@ def main() -> int:
         rdt = time.perf_counter() - t0
         rs, rl = ref.tn_result()
         out["fp64_reference"] = {"trees_per_s": nref / rdt, "ln_abs_z": rl, "sign": rs}
+        orl = oracle_lnz(shape, args.beta, args.chi)
+        if orl is not None:
+            out["rel_dlnz_vs_oracle"] = {"fp64": abs(rl - orl) / abs(orl), args.precision: abs(lnz - orl) / abs(orl)}
         out["speedup_vs_fp64"] = trees_per_s / (nref / rdt)
         out["abs_dlnz_vs_fp64"] = abs(lnz - rl)
         out["rel_dlnz_vs_fp64"] = abs(lnz - rl) / abs(rl)
@@ -285,6 +306,38 @@ def main() -> int:
         batch.close()
         for c in bctx:
             c.close()
+
+    chis = [int(x) for x in args.per_chi.split(",") if x.strip() and int(x) != args.chi]
+    if chis:
+        # the same lattice and tree at other bond dimensions: time per tree and ln|Z| against the
+        # FP64 oracle, for the float32 and the float64 form
+        per = {}
+        for chi in chis:
+            rec = {"oracle_ln_abs_z": oracle_lnz(shape, args.beta, chi)}
+            for prec in ("fp32", "fp64"):
+                c = tn.Context(0)
+                c.tn_load_graph(g.n, eu, ev, ed, off, data)
+                c.tn_set_tree(pi, pj, chi, precision=prec)
+                c.tn_contract_compressed()   # captures the schedule (untimed)
+                torch.cuda.synchronize()
+                n = 2
+                t0 = time.perf_counter()
+                for _ in range(n):
+                    c.tn_enqueue()
+                c.tn_fetch()
+                torch.cuda.synchronize()
+                cdt = (time.perf_counter() - t0) / n
+                _, cl = c.tn_result()
+                r = {"ms_per_tree": cdt * 1e3, "trees_per_s": 1.0 / cdt, "ln_abs_z": cl,
+                     "tflops_fwd": c.tn_plan_info()["fwd_flops"] / cdt / 1e12}
+                if rec["oracle_ln_abs_z"] is not None:
+                    r["rel_dlnz_vs_oracle"] = abs(cl - rec["oracle_ln_abs_z"]) / abs(rec["oracle_ln_abs_z"])
+                rec[prec] = r
+                c.close()
+            rec["rel_dlnz_fp32_vs_fp64"] = abs(rec["fp32"]["ln_abs_z"] - rec["fp64"]["ln_abs_z"]) / abs(
+                rec["fp64"]["ln_abs_z"])
+            per[str(chi)] = rec
+        out["per_chi"] = per
 
     if args.fwd_bwd_steps > 0:
         # forward + reverse pass (d ln|Z| / d inputs) in the same precision, on a gradient plan

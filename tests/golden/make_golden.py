@@ -7,6 +7,8 @@ ising_8x8.json   : 8x8 open-boundary Ising, beta=0.44 — transfer-matrix ln Z a
 cubic_12.json    : 12x12x12 Ising, beta=0.22, chi=16, sweep tree (--big, ~10 min of CPU):
                    the oracle's ln|Z| and its spread when one input tensor is perturbed at the
                    1e-15 level (the conditioning of this workload; see the design notes).
+cubic_12_chi32.json: the same network and tree at chi=32 (--chi32, ~30 min of CPU): the oracle's
+                   ln|Z| only.
 """
 import json
 import os
@@ -54,9 +56,23 @@ def cubic_12(n_perturb=3):
             "cpu_seconds": time.time() - t0}
 
 
+def cubic_12_chi(chi):
+    g = lattice((12, 12, 12))
+    T = ising_tensors(g, 0.22)
+    p = sweep_tree((12, 12, 12))
+    t0 = time.time()
+    lnz = oracle.contract_compressed(g.n, g.edges, T, p, chi).ln_abs_z
+    return {"shape": [12, 12, 12], "beta": 0.22, "chi": chi, "tree": "sweep_tree((12, 12, 12))",
+            "oracle_lnZ": lnz, "cpu_seconds": time.time() - t0}
+
+
 if __name__ == "__main__":
-    with open(os.path.join(HERE, "ising_8x8.json"), "w") as f:
-        json.dump(ising_8x8(), f, indent=1)
+    def write(name, rec):   # computed first: a file is never left half-written
+        with open(os.path.join(HERE, name), "w") as f:
+            json.dump(rec, f, indent=1)
+
+    write("ising_8x8.json", ising_8x8())
     if "--big" in sys.argv:
-        with open(os.path.join(HERE, "cubic_12.json"), "w") as f:
-            json.dump(cubic_12(), f, indent=1)
+        write("cubic_12.json", cubic_12())
+    if "--chi32" in sys.argv:
+        write("cubic_12_chi32.json", cubic_12_chi(32))
