@@ -2586,26 +2586,26 @@ __global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDes
     // T = L Psi_A ; N_A = T L^T + sum_t L_t H_B,t^T / sqrt(s_t)   (the products on the MFMA, into
     // the Phi slot, which Psi no longer needs)
     double* N2 = Phi;
+    // H_B and H_A scaled by s_t^-1/2 (kept columns), into the a and b slots (free once Psi exists)
+    double* HBs = a;
+    double* HAs = b;
+    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+        const int t = idx % cn;
+        HBs[idx] = t < nk ? HB[idx] / sq[t] : 0.0;
+        HAs[idx] = t < nk ? HA[idx] / sq[t] : 0.0;
+    }
     wg_gemm_f64(L, D, 1, PsiA, D, 1, T, D, D, r, r, lds);
     wg_gemm_f64(T, D, 1, L, 1, D, N2, D, D, D, r, lds);
+    wg_gemm_f64(L, D, 1, HBs, 1, cn, T, D, D, D, nk, lds);     // sum_t L_t H_B,t^T / sqrt(s_t)
     Tp* na = (Tp*)d.n_a;
-    for (int idx = tid; idx < DD; idx += kCoreThreads) {
-        const int d1 = idx / D, d2 = idx - d1 * D;
-        double x = N2[idx];
-        for (int t = 0; t < nk; ++t) x += L[d1 * D + t] * HB[d2 * cn + t] / sq[t];
-        na[idx] = (Tp)x;
-    }
+    for (int idx = tid; idx < DD; idx += kCoreThreads) na[idx] = (Tp)(N2[idx] + T[idx]);
     __syncthreads();
     // T = M Psi_B ; N_B = T M^T + sum_t H_A,t M_t^T / sqrt(s_t)
     wg_gemm_f64(Mm, D, 1, PsiB, D, 1, T, D, D, r, r, lds);
     wg_gemm_f64(T, D, 1, Mm, 1, D, N2, D, D, D, r, lds);
+    wg_gemm_f64(HAs, cn, 1, Mm, 1, D, T, D, D, D, nk, lds);    // sum_t H_A,t M_t^T / sqrt(s_t)
     Tp* nb = (Tp*)d.n_b;
-    for (int idx = tid; idx < DD; idx += kCoreThreads) {
-        const int d1 = idx / D, d2 = idx - d1 * D;
-        double x = N2[idx];
-        for (int t = 0; t < nk; ++t) x += HA[d1 * cn + t] * Mm[d2 * D + t] / sq[t];
-        nb[idx] = (Tp)x;
-    }
+    for (int idx = tid; idx < DD; idx += kCoreThreads) nb[idx] = (Tp)(N2[idx] + T[idx]);
 }
 
 // Adjoint of the final scalar: d ln|x| / d x^ = 1 / x^ with x^ = x / s the normalised value.
