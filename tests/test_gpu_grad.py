@@ -71,6 +71,11 @@ def _cases():
     g6 = lattice((6, 6, 6))      # long reductions: split-K contraction adjoints
     J6 = np.where(np.random.default_rng(0).random(g6.n_edges) < 0.5, -1.0, 1.0)
     yield "pmJ-6x6x6-chi8", g6, ising_tensors(g6, 0.5, J6), sweep_tree((6, 6, 6)), 8
+    # bonds of D = chi^2 > 64: the global core path (blocked pivoted Cholesky, block Jacobi over
+    # 16-column blocks, MFMA projectors); D = 100 and 144 leave partial blocks, 256 fills 16
+    yield "normal-4x4x4-chi10-D100", g4, normal_tensors(g4, 0.3, seed=11), sweep_tree((4, 4, 4)), 10
+    yield "pmJ-4x4x4-chi12-D144", g4, ising_tensors(g4, 0.5, J4), sweep_tree((4, 4, 4)), 12
+    yield "normal-4x4x4-chi16-D256", g4, normal_tensors(g4, 0.1, seed=12), sweep_tree((4, 4, 4)), 16
 
 
 CASES = list(_cases())
