@@ -752,7 +752,10 @@ tn_status build_bwd_launches(tn_ctx* c) {
             l.flops = core_flops;
             l.begin = (int64_t)c->h_cbwd.size();
             l.count = (int)cores.size();
-            for (auto& d : cores) c->h_cbwd.push_back(d);
+            for (auto& d : cores) {
+                c->h_cbwd.push_back(d);
+                l.max_d = std::max(l.max_d, (int)d.D);
+            }
             c->blaunches.push_back(l);
         }
     }
@@ -1356,7 +1359,7 @@ tn_status tn_grad_device(tn_ctx* c, void* out) {
                 HIP_TRY(c, launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, s));
                 break;
             case L_CORE_BWD:
-                HIP_TRY(c, launch_core_bwd(l.key, c->d_cbwd + l.begin, l.count, s));
+                HIP_TRY(c, launch_core_bwd(l.key, c->d_cbwd + l.begin, l.count, l.max_d, s));
                 break;
         }
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
@@ -1674,6 +1677,7 @@ void merge_backward(tn_batch* b) {
             m.count = 0;
             m.work = 0;
             m.flops = m.bytes = 0;
+            m.max_d = 0;
             m.begin = kind == L_GEMM ? (int64_t)b->h_bgemm.size()
                                      : kind == L_REDUCE ? (int64_t)b->h_reduce.size() : (int64_t)b->h_cbwd.size();
             for (auto& pr : kv.second) {
@@ -1683,6 +1687,7 @@ void merge_backward(tn_batch* b) {
                 m.count += l.count;
                 m.flops += l.flops;
                 m.bytes += l.bytes;
+                m.max_d = std::max(m.max_d, l.max_d);
                 for (int k = 0; k < l.count; ++k) {
                     if (kind == L_GEMM) {
                         GemmDesc g = c->h_bgemm[l.begin + k];
@@ -1775,7 +1780,7 @@ tn_status enqueue_batch_backward(tn_batch* b, void* const* outs) {
                 BHIP_TRY(b, launch_reduce(l.key, b->d_reduce + l.begin, l.count, l.work, b->d_scales, s));
                 break;
             case L_CORE_BWD:
-                BHIP_TRY(b, launch_core_bwd(l.key, b->d_cbwd + l.begin, l.count, s));
+                BHIP_TRY(b, launch_core_bwd(l.key, b->d_cbwd + l.begin, l.count, l.max_d, s));
                 break;
         }
     }

@@ -1122,60 +1122,78 @@ __device__ void sorted_norms(const double* W, int rows, int cols, int ld, double
     __syncthreads();
 }
 
-// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N) in float64 on MFMA, by the
-// whole 1024-thread workgroup: 128 x 128 tiles of C, each wave a 32 x 32 block (2 x 2
-// instructions of 16 x 16 x 4), K staged through LDS in chunks of 32 with the loads coalesced
-// along whichever index has unit stride.  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc];
-// stage holds 2 * 32 * 128 doubles.  Ends with a barrier.
-__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
-                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
-                            double* __restrict__ stage) {
+// One 128 x 128 tile (rows i0.., columns j0..) of C (M x N, row-major, leading dimension ldc) =
+// A (M x K) . B (K x N) + A2 (M x K2) . B2 (K2 x N), in float64 on MFMA, stored as TC, by the whole
+// 1024-thread workgroup: each wave a 32 x 32 block (2 x 2 instructions of 16 x 16 x 4), K staged
+// through LDS in chunks of 32 with the loads coalesced along whichever index has unit stride.
+// A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc] (likewise A2, B2); stage holds
+// 2 * 32 * 128 doubles.
+template <typename TC>
+__device__ void wg_gemm_tile(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
+                             int64_t br, int64_t bc, int K, const double* __restrict__ A2, int64_t ar2,
+                             int64_t ac2, const double* __restrict__ B2, int64_t br2, int64_t bc2, int K2,
+                             TC* __restrict__ C, int64_t ldc, int M, int N, int i0, int j0,
+                             double* __restrict__ stage) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 2) * 32, wc = (wave & 3) * 32;
     const int lrow = lane & 15, lk = lane >> 4;
     double* As = stage;              // As[k * 128 + i]
     double* Bs = stage + 32 * 128;   // Bs[k * 128 + j]
-    const bool a_kfast = ac == 1, b_jfast = bc == 1;
-    for (int i0 = 0; i0 < M; i0 += 128)
-        for (int j0 = 0; j0 < N; j0 += 128) {
-            v4d acc[2][2];
+    v4d acc[2][2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                for (int e = tid; e < 32 * 128; e += kCoreThreads) {
-                    const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
-                    const int gi = i0 + ii, gk = k0 + kk;
-                    As[kk * 128 + ii] = (gi < M && gk < K) ? A[gi * ar + gk * ac] : 0.0;
-                    const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
-                    const int gj = j0 + jj, gkb = k0 + kb;
-                    Bs[kb * 128 + jj] = (gj < N && gkb < K) ? B[gkb * br + gj * bc] : 0.0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int kk = 0; kk < 32; kk += 4) {
-                    const int k = kk + lk;
-                    const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
-                    const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
-                    acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
-                    acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
-                    acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
-                    acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
-                }
-                __syncthreads();
+        for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int part = 0; part < 2; ++part) {
+        const double* PA = part == 0 ? A : A2;
+        const double* PB = part == 0 ? B : B2;
+        const int64_t pr = part == 0 ? ar : ar2, pc = part == 0 ? ac : ac2;
+        const int64_t qr = part == 0 ? br : br2, qc = part == 0 ? bc : bc2;
+        const int KK = part == 0 ? K : K2;
+        const bool a_kfast = pc == 1, b_jfast = qc == 1;
+        for (int k0 = 0; k0 < KK; k0 += 32) {
+            for (int e = tid; e < 32 * 128; e += kCoreThreads) {
+                const int kk = a_kfast ? (e & 31) : (e >> 7), ii = a_kfast ? (e >> 5) : (e & 127);
+                const int gi = i0 + ii, gk = k0 + kk;
+                As[kk * 128 + ii] = (gi < M && gk < KK) ? PA[gi * pr + gk * pc] : 0.0;
+                const int kb = b_jfast ? (e >> 7) : (e & 31), jj = b_jfast ? (e & 127) : (e >> 5);
+                const int gj = j0 + jj, gkb = k0 + kb;
+                Bs[kb * 128 + jj] = (gj < N && gkb < KK) ? PB[gkb * qr + gj * qc] : 0.0;
             }
+            __syncthreads();
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-                for (int y = 0; y < 2; ++y)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
-                        const int gj = j0 + wc + 16 * y + lrow;
-                        if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = acc[x][y][r];
-                    }
+            for (int kk = 0; kk < 32; kk += 4) {
+                const int k = kk + lk;
+                const double a0 = As[k * 128 + wr + lrow], a1 = As[k * 128 + wr + 16 + lrow];
+                const double b0 = Bs[k * 128 + wc + lrow], b1 = Bs[k * 128 + wc + 16 + lrow];
+                acc[0][0] = Mma<double>::run(a0, b0, acc[0][0]);
+                acc[0][1] = Mma<double>::run(a0, b1, acc[0][1]);
+                acc[1][0] = Mma<double>::run(a1, b0, acc[1][0]);
+                acc[1][1] = Mma<double>::run(a1, b1, acc[1][1]);
+            }
+            __syncthreads();
         }
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = i0 + wr + 16 * x + Mma<double>::row(lane, r);
+                const int gj = j0 + wc + 16 * y + lrow;
+                if (gi < M && gj < N) C[(int64_t)gi * ldc + gj] = (TC)acc[x][y][r];
+            }
+}
+
+// C (M x N, row-major, leading dimension ldc) = A (M x K) . B (K x N): every 128 x 128 tile by
+// the whole workgroup (wg_gemm_tile).  Ends with a barrier.
+__device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac, const double* __restrict__ B,
+                            int64_t br, int64_t bc, double* __restrict__ C, int64_t ldc, int M, int N, int K,
+                            double* __restrict__ stage) {
+    for (int i0 = 0; i0 < M; i0 += 128)
+        for (int j0 = 0; j0 < N; j0 += 128)
+            wg_gemm_tile<double>(A, ar, ac, B, br, bc, K, nullptr, 0, 0, nullptr, 0, 0, 0, C, ldc, M, N, i0, j0, stage);
     __syncthreads();
 }
 
@@ -2463,10 +2481,18 @@ __global__ __launch_bounds__(256) void reduce_grouped(const ReduceDesc* __restri
 // so that A_bar = G_a P_L^T + A N_A and B_bar = P_R^T G_b + N_B B need no inverse of R~.
 constexpr size_t kCoreBwdLdsBytes = 2 * 32 * 128 * sizeof(double);
 
+// Phases of core_bwd_kernel: 0 = the whole adjoint in one workgroup per compression; for large
+// cores the same steps split over launches, the D x D products one 128 x 128 tile per workgroup:
+// 1 = + set, H sums, sorted vectors; 2 = tiles of R~_B^T V_+ and R~_A^T W_+; 3 = scaling, a, b,
+// Phi, Psi, scaled H; 4 = tiles of L Psi_A and M Psi_B; 5 = tiles of N_A and N_B.
+constexpr int kBwdTile = 128;
+
 template <typename Tp>
-__global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDesc* __restrict__ descs) {
+__global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDesc* __restrict__ descs, int phase,
+                                                                int per_core) {
     extern __shared__ double lds[];   // GEMM staging, 2 x 32 x 128 doubles
-    const CoreBwdDesc& d = descs[blockIdx.x];
+    const int ci = blockIdx.x / per_core, q = blockIdx.x - ci * per_core;
+    const CoreBwdDesc& d = descs[ci];
     const int tid = threadIdx.x;
     const int D = d.D, cn = d.chi_new, DD = D * D;
     const double* Ra = d.work;
@@ -2489,123 +2515,197 @@ __global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDes
     double* b = a + D * cn;
     double* sg = b + D * cn;      // sigma of the + set, descending
     double* sq = sg + D;          // sqrt(sigma)
-    __shared__ int sh_r, sh_nk;
-    __shared__ double sh_eps;
-
-    if (tid == 0) {
-        double smax = rb > 0 ? sig[order[0]] : 0.0, fro = 0.0;
-        for (int j = 0; j < rb; ++j) fro += sig[j] * sig[j];
-        fro = sqrt(fro);
-        int r = 0;
-        while (r < rb && sig[order[r]] > kNoiseRel * smax && sig[order[r]] > 4.0 * kZeroRel * fro) ++r;
-        int nk = 0;
-        while (nk < min(cn, r) && sig[order[nk]] >= d.cutoff * smax) ++nk;
-        sh_r = r;
-        sh_nk = nk;
-        sh_eps = 1e-12 * smax * smax;
-    }
-    __syncthreads();
-    const int r = sh_r, nk = sh_nk;
-    const double eps = sh_eps;
-    for (int p = tid; p < r; p += kCoreThreads) {
-        sg[p] = sig[order[p]];
-        sq[p] = sqrt(sg[p]);
-    }
-    const double* ha = d.h;
-    const double* hb = d.h + (int64_t)d.splits_a * D * cn;
-    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
-        double x = 0.0, y = 0.0;
-        for (int p = 0; p < d.splits_a; ++p) x += ha[(int64_t)p * D * cn + idx];
-        for (int p = 0; p < d.splits_b; ++p) y += hb[(int64_t)p * D * cn + idx];
-        HA[idx] = x;
-        HB[idx] = y;
-    }
-    __syncthreads();
+    int* meta = (int*)(sq + D);   // r, nk (phase 1 -> later phases)
     // singular vectors of the + set in descending order (columns), into the Psi slots (free
-    // until Psi is formed): Vs = V_+, Ws = W_+ = U_+ s
+    // until Psi is formed): Vs = V_+, Ws = W_+ = U_+ s; H_B, H_A scaled by s^-1/2 into the a, b
+    // slots once Psi exists
     double* Vs = PsiA;
     double* Ws = PsiB;
-    for (int idx = tid; idx < r * D; idx += kCoreThreads) {
-        const int p = idx / D, i = idx - p * D;
-        const int j = order[p];
-        Vs[(int64_t)p * D + i] = i < rb ? V[(int64_t)j * D + i] : 0.0;
-        Ws[(int64_t)p * D + i] = i < ra ? W[(int64_t)j * D + i] : 0.0;
-    }
-    __syncthreads();
-    // L = R~_B^T V_+ s^-1, M = R~_A^T (W_+ s^-1) s^-1, on the MFMA
-    wg_gemm_f64(Rb, 1, D, Vs, 1, D, L, D, D, r, rb, lds);
-    wg_gemm_f64(Ra, 1, D, Ws, 1, D, Mm, D, D, r, ra, lds);
-    for (int idx = tid; idx < D * r; idx += kCoreThreads) {
-        const int dd = idx / r, p = idx - dd * r;
-        L[dd * D + p] /= sg[p];
-        Mm[dd * D + p] /= sg[p] * sg[p];
-    }
-    __syncthreads();
-    // a = L^T H_A, b = M^T H_B  (r x nk, leading dimension cn)
-    wg_gemm_f64_narrow(L, 1, D, HA, cn, 1, a, cn, r, nk, D);
-    wg_gemm_f64_narrow(Mm, 1, D, HB, cn, 1, b, cn, r, nk, D);
-    __syncthreads();
-    // Phi[x][y]: diagonal of the kept block, plus the contributions of kept index y (to row x)
-    // and of kept index x (to column y) for every other singular index
-    for (int idx = tid; idx < r * r; idx += kCoreThreads) {
-        const int x = idx / r, y = idx - x * r;
-        const double sx = sg[x], sy = sg[y];
-        double v = 0.0;
-        if (x == y) {
-            if (x < nk) v = (a[x * cn + x] + b[x * cn + x]) / (2.0 * sq[x]);
-        } else {
-            const double d2 = sy * sy - sx * sx;   // sigma_y^2 - sigma_x^2
-            if (y < nk) {   // i = y kept, j = x
-                const double f = x < nk ? d2 / (d2 * d2 + eps * eps) : 1.0 / d2;
-                v += (a[x * cn + y] * sq[y] * sy + b[x * cn + y] * sq[y] * sx) * f;
-            }
-            if (x < nk) {   // i = x kept, j = y
-                const double f = y < nk ? -d2 / (d2 * d2 + eps * eps) : -1.0 / d2;
-                v += (a[y * cn + x] * sq[x] * sy + b[y * cn + x] * sq[x] * sx) * f;
-            }
-        }
-        Phi[x * D + y] = v;
-    }
-    __syncthreads();
-    for (int idx = tid; idx < r * r; idx += kCoreThreads) {
-        const int x = idx / r, y = idx - x * r;
-        const double ph = Phi[x * D + y], sx = sg[x], sy = sg[y];
-        double pa = ph * sy, pb = sx * ph;
-        if (y < nk) {
-            pa -= a[x * cn + y] * sq[y];
-            pb -= sx * a[x * cn + y] / sq[y];
-        }
-        if (x < nk) {
-            pa -= b[y * cn + x] * sy / sq[x];
-            pb -= sq[x] * b[y * cn + x];
-        }
-        PsiA[x * D + y] = pa;
-        PsiB[x * D + y] = pb;
-    }
-    __syncthreads();
-    // T = L Psi_A ; N_A = T L^T + sum_t L_t H_B,t^T / sqrt(s_t)   (the products on the MFMA, into
-    // the Phi slot, which Psi no longer needs)
-    double* N2 = Phi;
-    // H_B and H_A scaled by s_t^-1/2 (kept columns), into the a and b slots (free once Psi exists)
     double* HBs = a;
     double* HAs = b;
-    for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
-        const int t = idx % cn;
-        HBs[idx] = t < nk ? HB[idx] / sq[t] : 0.0;
-        HAs[idx] = t < nk ? HA[idx] / sq[t] : 0.0;
+    const bool all = phase == 0;
+    const double smax = rb > 0 ? sig[order[0]] : 0.0;
+    int r, nk;
+    if (all || phase == 1) {
+        __shared__ double sh_part[kCoreWaves];
+        __shared__ int sh_cnt[2][kCoreWaves];
+        const int lane = tid & 63, wave = tid >> 6;
+        // ||sigma|| and, since order sorts sigma descending, the size r of the + set (sigma above
+        // both zero thresholds) and the kept count nk as plain counts (block reductions)
+        {
+            double f = 0.0;
+            for (int j = tid; j < rb; j += kCoreThreads) f = fma(sig[j], sig[j], f);
+            f = wave_sum(f);
+            if (lane == 0) sh_part[wave] = f;
+            __syncthreads();
+        }
+        double fro = 0.0;
+        for (int w = 0; w < kCoreWaves; ++w) fro += sh_part[w];
+        fro = sqrt(fro);
+        {
+            int c1 = 0, c2 = 0;
+            for (int j = tid; j < rb; j += kCoreThreads) {
+                c1 += (sig[j] > kNoiseRel * smax && sig[j] > 4.0 * kZeroRel * fro) ? 1 : 0;
+                c2 += sig[j] >= d.cutoff * smax ? 1 : 0;
+            }
+            c1 = (int)wave_sum((double)c1);
+            c2 = (int)wave_sum((double)c2);
+            if (lane == 0) {
+                sh_cnt[0][wave] = c1;
+                sh_cnt[1][wave] = c2;
+            }
+            __syncthreads();
+        }
+        int nc = 0;
+        r = 0;
+        for (int w = 0; w < kCoreWaves; ++w) {
+            r += sh_cnt[0][w];
+            nc += sh_cnt[1][w];
+        }
+        nk = min(min(cn, r), nc);
+        if (tid == 0) {
+            meta[0] = r;
+            meta[1] = nk;
+        }
+        for (int p = tid; p < r; p += kCoreThreads) {
+            sg[p] = sig[order[p]];
+            sq[p] = sqrt(sg[p]);
+        }
+        const double* ha = d.h;
+        const double* hb = d.h + (int64_t)d.splits_a * D * cn;
+        for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+            double x = 0.0, y = 0.0;
+            for (int p = 0; p < d.splits_a; ++p) x += ha[(int64_t)p * D * cn + idx];
+            for (int p = 0; p < d.splits_b; ++p) y += hb[(int64_t)p * D * cn + idx];
+            HA[idx] = x;
+            HB[idx] = y;
+        }
+        for (int idx = tid; idx < r * D; idx += kCoreThreads) {
+            const int p = idx / D, i = idx - p * D;
+            const int j = order[p];
+            Vs[(int64_t)p * D + i] = i < rb ? V[(int64_t)j * D + i] : 0.0;
+            Ws[(int64_t)p * D + i] = i < ra ? W[(int64_t)j * D + i] : 0.0;
+        }
+        __syncthreads();
+        if (!all) return;
+    } else {
+        r = meta[0];
+        nk = meta[1];
     }
-    wg_gemm_f64(L, D, 1, PsiA, D, 1, T, D, D, r, r, lds);
-    wg_gemm_f64(T, D, 1, L, 1, D, N2, D, D, D, r, lds);
-    wg_gemm_f64(L, D, 1, HBs, 1, cn, T, D, D, D, nk, lds);     // sum_t L_t H_B,t^T / sqrt(s_t)
+    // tile q of the phase's two products (the first product's tiles, then the second's)
+    const int tr = (r + kBwdTile - 1) / kBwdTile, td = (D + kBwdTile - 1) / kBwdTile;
+    auto tile_of = [&](int ntile_cols, int* which, int* i0, int* j0) {
+        const int per = td * ntile_cols;
+        if (per == 0) return false;   // empty + set
+        *which = q / per;
+        const int t = q - *which * per;
+        *i0 = (t / ntile_cols) * kBwdTile;
+        *j0 = (t % ntile_cols) * kBwdTile;
+        return *which < 2;
+    };
+    // L = R~_B^T V_+ s^-1, M = R~_A^T (W_+ s^-1) s^-1, on the MFMA (unscaled products first)
+    if (all) {
+        wg_gemm_f64(Rb, 1, D, Vs, 1, D, L, D, D, r, rb, lds);
+        wg_gemm_f64(Ra, 1, D, Ws, 1, D, Mm, D, D, r, ra, lds);
+    } else if (phase == 2) {
+        int which, i0, j0;
+        if (!tile_of(tr, &which, &i0, &j0)) return;
+        if (which == 0)
+            wg_gemm_tile<double>(Rb, 1, D, Vs, 1, D, rb, nullptr, 0, 0, nullptr, 0, 0, 0, L, D, D, r, i0, j0, lds);
+        else
+            wg_gemm_tile<double>(Ra, 1, D, Ws, 1, D, ra, nullptr, 0, 0, nullptr, 0, 0, 0, Mm, D, D, r, i0, j0, lds);
+        return;
+    }
+    if (all || phase == 3) {
+        for (int idx = tid; idx < D * r; idx += kCoreThreads) {
+            const int dd = idx / r, p = idx - dd * r;
+            L[dd * D + p] /= sg[p];
+            Mm[dd * D + p] /= sg[p] * sg[p];
+        }
+        __syncthreads();
+        // a = L^T H_A, b = M^T H_B  (r x nk, leading dimension cn)
+        wg_gemm_f64_narrow(L, 1, D, HA, cn, 1, a, cn, r, nk, D);
+        wg_gemm_f64_narrow(Mm, 1, D, HB, cn, 1, b, cn, r, nk, D);
+        __syncthreads();
+        const double eps = 1e-12 * smax * smax;
+        // Phi[x][y]: diagonal of the kept block, plus the contributions of kept index y (to row x)
+        // and of kept index x (to column y) for every other singular index
+        for (int idx = tid; idx < r * r; idx += kCoreThreads) {
+            const int x = idx / r, y = idx - x * r;
+            const double sx = sg[x], sy = sg[y];
+            double v = 0.0;
+            if (x == y) {
+                if (x < nk) v = (a[x * cn + x] + b[x * cn + x]) / (2.0 * sq[x]);
+            } else {
+                const double d2 = sy * sy - sx * sx;   // sigma_y^2 - sigma_x^2
+                if (y < nk) {   // i = y kept, j = x
+                    const double f = x < nk ? d2 / (d2 * d2 + eps * eps) : 1.0 / d2;
+                    v += (a[x * cn + y] * sq[y] * sy + b[x * cn + y] * sq[y] * sx) * f;
+                }
+                if (x < nk) {   // i = x kept, j = y
+                    const double f = y < nk ? -d2 / (d2 * d2 + eps * eps) : -1.0 / d2;
+                    v += (a[y * cn + x] * sq[x] * sy + b[y * cn + x] * sq[x] * sx) * f;
+                }
+            }
+            Phi[x * D + y] = v;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < r * r; idx += kCoreThreads) {
+            const int x = idx / r, y = idx - x * r;
+            const double ph = Phi[x * D + y], sx = sg[x], sy = sg[y];
+            double pa = ph * sy, pb = sx * ph;
+            if (y < nk) {
+                pa -= a[x * cn + y] * sq[y];
+                pb -= sx * a[x * cn + y] / sq[y];
+            }
+            if (x < nk) {
+                pa -= b[y * cn + x] * sy / sq[x];
+                pb -= sq[x] * b[y * cn + x];
+            }
+            PsiA[x * D + y] = pa;
+            PsiB[x * D + y] = pb;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
+            const int t = idx % cn;
+            HBs[idx] = t < nk ? HB[idx] / sq[t] : 0.0;
+            HAs[idx] = t < nk ? HA[idx] / sq[t] : 0.0;
+        }
+        __syncthreads();
+        if (!all) return;
+    }
+    // T_A = L Psi_A (T slot), T_B = M Psi_B (Phi slot: Phi is no longer needed)
+    double* TA = T;
+    double* TB = Phi;
+    if (all) {
+        wg_gemm_f64(L, D, 1, PsiA, D, 1, TA, D, D, r, r, lds);
+        wg_gemm_f64(Mm, D, 1, PsiB, D, 1, TB, D, D, r, r, lds);
+    } else if (phase == 4) {
+        int which, i0, j0;
+        if (!tile_of(tr, &which, &i0, &j0)) return;
+        if (which == 0)
+            wg_gemm_tile<double>(L, D, 1, PsiA, D, 1, r, nullptr, 0, 0, nullptr, 0, 0, 0, TA, D, D, r, i0, j0, lds);
+        else
+            wg_gemm_tile<double>(Mm, D, 1, PsiB, D, 1, r, nullptr, 0, 0, nullptr, 0, 0, 0, TB, D, D, r, i0, j0, lds);
+        return;
+    }
+    // N_A = T_A L^T + sum_t L_t H_B,t^T / sqrt(s_t);  N_B = T_B M^T + sum_t H_A,t M_t^T / sqrt(s_t)
     Tp* na = (Tp*)d.n_a;
-    for (int idx = tid; idx < DD; idx += kCoreThreads) na[idx] = (Tp)(N2[idx] + T[idx]);
-    __syncthreads();
-    // T = M Psi_B ; N_B = T M^T + sum_t H_A,t M_t^T / sqrt(s_t)
-    wg_gemm_f64(Mm, D, 1, PsiB, D, 1, T, D, D, r, r, lds);
-    wg_gemm_f64(T, D, 1, Mm, 1, D, N2, D, D, D, r, lds);
-    wg_gemm_f64(HAs, cn, 1, Mm, 1, D, T, D, D, D, nk, lds);    // sum_t H_A,t M_t^T / sqrt(s_t)
     Tp* nb = (Tp*)d.n_b;
-    for (int idx = tid; idx < DD; idx += kCoreThreads) nb[idx] = (Tp)(N2[idx] + T[idx]);
+    if (all) {
+        for (int i0 = 0; i0 < D; i0 += kBwdTile)
+            for (int j0 = 0; j0 < D; j0 += kBwdTile) {
+                wg_gemm_tile<Tp>(TA, D, 1, L, 1, D, r, L, D, 1, HBs, 1, cn, nk, na, D, D, D, i0, j0, lds);
+                wg_gemm_tile<Tp>(TB, D, 1, Mm, 1, D, r, HAs, cn, 1, Mm, 1, D, nk, nb, D, D, D, i0, j0, lds);
+            }
+    } else if (phase == 5) {
+        int which, i0, j0;
+        if (!tile_of(td, &which, &i0, &j0)) return;
+        if (which == 0)
+            wg_gemm_tile<Tp>(TA, D, 1, L, 1, D, r, L, D, 1, HBs, 1, cn, nk, na, D, D, D, i0, j0, lds);
+        else
+            wg_gemm_tile<Tp>(TB, D, 1, Mm, 1, D, r, HAs, cn, 1, Mm, 1, D, nk, nb, D, D, D, i0, j0, lds);
+    }
 }
 
 // Adjoint of the final scalar: d ln|x| / d x^ = 1 / x^ with x^ = x / s the normalised value.
@@ -2824,9 +2924,23 @@ hipError_t launch_reduce(int prec, const ReduceDesc* descs, int ndesc, int64_t t
     return by_prec(prec, [&](auto t) { reduce_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total); });
 }
 
-hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, hipStream_t s) {
+hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, int max_d, hipStream_t s) {
     if (ndesc == 0) return hipSuccess;
-    return by_prec(prec, [&](auto t) { core_bwd_kernel<decltype(t)><<<ndesc, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs); });
+    return by_prec(prec, [&](auto t) {
+        using Tp = decltype(t);
+        if (max_d <= kCoreLdsMaxD) {
+            core_bwd_kernel<Tp><<<ndesc, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs, 0, 1);
+        } else {
+            // the D x D products of large cores over many workgroups: two products per phase,
+            // one 128 x 128 tile per workgroup
+            const int td = (max_d + kBwdTile - 1) / kBwdTile, per = 2 * td * td;
+            core_bwd_kernel<Tp><<<ndesc, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs, 1, 1);
+            core_bwd_kernel<Tp><<<ndesc * per, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs, 2, per);
+            core_bwd_kernel<Tp><<<ndesc, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs, 3, 1);
+            core_bwd_kernel<Tp><<<ndesc * per, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs, 4, per);
+            core_bwd_kernel<Tp><<<ndesc * per, kCoreThreads, kCoreBwdLdsBytes, s>>>(descs, 5, per);
+        }
+    });
 }
 
 hipError_t launch_seed(int prec, const void* final_ptr, void* adj_final, const double* scales, int final_index,

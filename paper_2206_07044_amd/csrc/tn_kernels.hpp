@@ -35,7 +35,7 @@ hipError_t launch_inputs(int prec, const InputDesc* descs, int n, const double* 
                          hipStream_t s);
 hipError_t launch_reduce(int prec, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
                          hipStream_t s);
-hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, hipStream_t s);
+hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, int max_d, hipStream_t s);
 hipError_t launch_seed(int prec, const void* final_ptr, void* adj_final, const double* scales, int final_index,
                        hipStream_t s);
 hipError_t launch_grad_inputs(int prec, const InputDesc* descs, int n, const double* scales, double* out,
