@@ -1316,17 +1316,73 @@ __global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc
     __syncthreads();
     const double zero2 = kZeroRel * kZeroRel * *core_fro2(gsig, D);
     const double tol = 2.220446049250313e-16 * (double)max(ra, 16);
-    const int steps = round == 0 ? NC - 1 : kBJCols;
     const int pi = wave * 4 + quarter;   // this 16-lane row's pair
-    for (int t = 0; t < steps; ++t) {
-        int p1, p2;
-        if (round == 0) {
-            p1 = rr_col(pi, t, NC);
-            p2 = rr_col(NC - 1 - pi, t, NC);
-        } else {
-            p1 = pi;
-            p2 = kBJCols + ((pi + t) & (kBJCols - 1));
+    if (round > 0) {
+        // cross pairs only: this row keeps its first-block column (and its column of Q) in
+        // registers for the 16 steps, and meets the second block's columns in turn
+        const int p1 = pi;
+        const bool in1 = gcol(p1) < rb;
+        double x[kBJKR], qx[NC / 16];
+#pragma unroll
+        for (int k = 0; k < kBJKR; ++k) x[k] = lw[p1 * kBJRows + ql + 16 * k];
+#pragma unroll
+        for (int k = 0; k < NC / 16; ++k) qx[k] = lq[p1 * NC + ql + 16 * k];
+        double a = row16_sum([&] {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBJKR; k += 2) {
+                s0 = fma(x[k], x[k], s0);
+                s1 = fma(x[k + 1], x[k + 1], s1);
+            }
+            return s0 + s1;
+        }());
+        for (int t = 0; t < kBJCols; ++t) {
+            const int p2 = kBJCols + ((pi + t) & (kBJCols - 1));
+            double* w2 = lw + p2 * kBJRows;
+            double y[kBJKR];
+#pragma unroll
+            for (int k = 0; k < kBJKR; ++k) y[k] = w2[ql + 16 * k];
+            double b0 = 0.0, b1 = 0.0, g0 = 0.0, g1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBJKR; k += 2) {
+                b0 = fma(y[k], y[k], b0);
+                g0 = fma(x[k], y[k], g0);
+                b1 = fma(y[k + 1], y[k + 1], b1);
+                g1 = fma(x[k + 1], y[k + 1], g1);
+            }
+            const double b = row16_sum(b0 + b1), g = row16_sum(g0 + g1);
+            if (in1 && gcol(p2) < rb && a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
+                double c, sn;
+                jacobi_rotation(a, b, g, &c, &sn);
+                if (ql == 0 && g * g > kQuadRel2 * a * b) s_big = 1;
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < kBJKR; ++k) {
+                    const double xn = c * x[k] - sn * y[k];
+                    w2[ql + 16 * k] = sn * x[k] + c * y[k];
+                    x[k] = xn;
+                    if (k & 1) a1 = fma(xn, xn, a1);
+                    else a0 = fma(xn, xn, a0);
+                }
+                a = row16_sum(a0 + a1);
+                double* q2 = lq + p2 * NC;
+#pragma unroll
+                for (int k = 0; k < NC / 16; ++k) {
+                    const double u1 = qx[k], u2 = q2[ql + 16 * k];
+                    qx[k] = c * u1 - sn * u2;
+                    q2[ql + 16 * k] = sn * u1 + c * u2;
+                }
+            }
+            __syncthreads();
         }
+#pragma unroll
+        for (int k = 0; k < kBJKR; ++k) lw[p1 * kBJRows + ql + 16 * k] = x[k];
+#pragma unroll
+        for (int k = 0; k < NC / 16; ++k) lq[p1 * NC + ql + 16 * k] = qx[k];
+        __syncthreads();
+    }
+    for (int t = 0; t < (round == 0 ? NC - 1 : 0); ++t) {
+        const int p1 = rr_col(pi, t, NC), p2 = rr_col(NC - 1 - pi, t, NC);
         double* w1 = lw + p1 * kBJRows;
         double* w2 = lw + p2 * kBJRows;
         double x[kBJKR], y[kBJKR];
