@@ -111,7 +111,12 @@ def roofline_of(kind, prof, avg_ms, launches, precision):
     """Bound, unit, peak and achieved rate of one kernel kind (algorithmic work / time)."""
     per_s = 1.0 / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
     if kind == "gemm":
+        # contractions and re-absorptions: MFMA-bound when their arithmetic intensity (algorithmic
+        # flops / algorithmic bytes) reaches the ridge point, else HBM-bound
         peak = {"fp32": PEAKS["fp32_TFLOPs"], "bf16": PEAKS["bf16_TFLOPs"], "fp64": PEAKS["fp64_TFLOPs"]}[precision]
+        ridge = peak * 1e12 / (PEAKS["hbm_GBps"] * 1e9)
+        if prof["bytes"] > 0 and prof["flops"] / prof["bytes"] < ridge:
+            return "hbm", "GB/s", PEAKS["hbm_GBps"], prof["bytes"] / launches * per_s / 1e9
         return "mfma", "TFLOP/s", peak, prof["flops"] / launches * per_s / 1e12
     if kind == "gram":   # Gram matrices accumulate on float64 MFMA in both precisions
         return "mfma", "TFLOP/s", PEAKS["fp64_TFLOPs"], prof["flops"] / launches * per_s / 1e12
@@ -260,7 +265,9 @@ def main() -> int:
         gb, gu, gp, ga = roofline_of("gemm", g_prof, g_prof["ms"] / gl, gl, args.precision)
         out["contraction_roofline"] = {"kernel": "gemm", "bound": gb, "achieved": ga, "peak": gp, "unit": gu,
                                        "frac": ga / gp, "avg_launch_ms": g_prof["ms"] / gl,
-                                       "launches_per_step": gl / max(1, args.warmup)}
+                                       "launches_per_step": gl / max(1, args.warmup),
+                                       "arithmetic_intensity": g_prof["flops"] / g_prof["bytes"] if g_prof["bytes"] else None,
+                                       "tflops": g_prof["flops"] / g_prof["ms"] * 1e3 / 1e12 if g_prof["ms"] else None}
 
     if not args.no_fp64_reference and args.precision != "fp64":
         ref = make_ctx("fp64")

@@ -1614,8 +1614,8 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         // sweeps made by the block launches: the first one without a large rotation ended them
         const int* big = core_bigflags(gsig, D);
         const int issued = min(kBJSweeps, max_sweeps);
-        sweeps = issued;
         converged = rb <= 1;
+        sweeps = converged ? 0 : issued;
         for (int t = 0; t < issued && !converged; ++t)
             if (big[t] == 0) {
                 sweeps = t + 1;

@@ -4,6 +4,8 @@ The full CPU oracle takes minutes here, so the checks are:
 * ln Z in FP64 against the stored oracle value (tests/golden/cubic_12.json), within the
   instance's measured sensitivity band;
 * FP32 (the benchmark's configuration) against FP64 at the metric's 1e-6 relative gate;
+* the same at chi = 32 (bonds of D = 1024, Gram-Lanczos on 1024 x 1024 operators), FP64 against
+  the stored oracle value (tests/golden/cubic_12_chi32.json) within the metric's gate;
 * exact properties at full size: the running exponent absorbs a rescaled input exactly, and a
   batch reproduces the single evaluation bitwise;
 * sampled outputs the oracle computes one by one: every tensor written by the first 480 tree
@@ -46,11 +48,11 @@ def instance():
     return g, T, pairs, (eu, ev, ed, off, data)
 
 
-def evaluate(instance, precision, data=None, keep=False):
+def evaluate(instance, precision, data=None, keep=False, chi=CHI):
     g, T, pairs, (eu, ev, ed, off, d0) = instance
     c = tn.Context(0)
     c.tn_load_graph(g.n, eu, ev, ed, off, d0 if data is None else data)
-    c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], CHI, precision=precision, keep_intermediates=keep)
+    c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, precision=precision, keep_intermediates=keep)
     c.tn_contract_compressed()
     return c
 
@@ -152,3 +154,39 @@ def test_fullsize_prefix_intermediates_against_oracle(instance):
         assert idx == len(rec) and compressed >= 80
     finally:
         c.close()
+
+
+def _chi32_gold():
+    try:
+        with open(os.path.join(HERE, "golden", "cubic_12_chi32.json")) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def test_fullsize_chi32_fp64_against_stored_oracle(instance):
+    gold = _chi32_gold()
+    if gold is None:
+        pytest.skip("tests/golden/cubic_12_chi32.json not written (make_golden.py --chi32)")
+    c = evaluate(instance, "fp64", chi=32)
+    try:
+        sign, lnz = c.tn_result()
+        disc, tie, sw = c.tn_compress_stats()
+    finally:
+        c.close()
+    print(f"\n12^3 chi=32 FP64: ln Z = {lnz!r}, oracle {gold['oracle_lnZ']!r}", flush=True)
+    assert sign == 1.0 and not tie.any()
+    # the chi = 16 instance moves by up to 1.7e-7 relative under rounding-level perturbations;
+    # at chi = 32 its FP32 and FP64 evaluations differ by 3e-7: the metric's gate is the band
+    assert lnz == pytest.approx(gold["oracle_lnZ"], rel=1e-6)
+
+
+def test_fullsize_chi32_fp32_meets_the_metric_gate(instance):
+    c64, c32 = evaluate(instance, "fp64", chi=32), evaluate(instance, "fp32", chi=32)
+    try:
+        l64, l32 = c64.tn_result()[1], c32.tn_result()[1]
+    finally:
+        c64.close()
+        c32.close()
+    print(f"\nchi=32 FP32 - FP64: {l32 - l64:.3e} ({(l32 - l64) / l64:.2e} relative)", flush=True)
+    assert abs(l32 - l64) <= 1e-6 * abs(l64)
