@@ -791,6 +791,45 @@ __device__ int pivoted_cholesky_wave(double* G, int D, double* R) {
     return r;
 }
 
+// pivoted_cholesky_wave for D <= KMAX with lane l's column of G held in registers (G is read,
+// not destroyed): the pivot's entry G'[p][l] is picked by a select chain (p is the same on every
+// lane), and the rank-1 update is one unrolled row of readlane + FMA (a zero multiplier on the
+// lanes that keep their column).  Same pivot rule, stopping tolerance and output as
+// pivoted_cholesky_wave.
+template <int KMAX>
+__device__ int pivoted_cholesky_wave_reg(const double* G, int D, double* R) {
+    const int l = threadIdx.x & 63;
+    const bool own = l < D;
+    double g[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) g[i] = (own && i < D) ? G[i * D + l] : 0.0;
+    bool chosen = !own;
+    double diag = own ? G[l * D + l] : 0.0;
+    double tol = 0.0;
+    int r = 0;
+    for (int t = 0; t < D; ++t) {
+        const double cand = chosen ? -1.0 : diag;
+        const double bv = wave_max(cand);
+        if (t == 0) tol = 1e-15 * bv;
+        if (!(bv > tol) || !(bv > 0.0)) break;
+        const int p = __ffsll((unsigned long long)__ballot(!chosen && cand == bv)) - 1;
+        const double rp = sqrt(bv);
+        double gp = 0.0;
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) gp = i == p ? g[i] : gp;
+        double v = 0.0;
+        if (!chosen) v = (l == p) ? rp : gp / rp;
+        if (own) R[t * D + l] = v;
+        const double w = (!chosen && l != p) ? v : 0.0;
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) g[i] = fma(-bcast(v, i), w, g[i]);
+        diag = fma(-w, v, diag);
+        if (l == p) chosen = true;
+        r = t + 1;
+    }
+    return r;
+}
+
 __device__ inline int rr_col(int pos, int round, int n) {
     int v = pos - 1 + round;   // pos - 1 and round are below n - 1: one wrap at most
     if (v >= n - 1) v -= n - 1;
@@ -1528,7 +1567,9 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         if (wave < 2) {
             const double* gram = wave == 0 ? d.gram_a : d.gram_b;
             int r = wave == 0 ? d.rows_a : d.rows_b;
-            if (gram) r = pivoted_cholesky_wave(wave == 0 ? W : V, D, wave == 0 ? Ra : Rb);
+            if (gram)
+                r = D <= 32 ? pivoted_cholesky_wave_reg<32>(wave == 0 ? W : V, D, wave == 0 ? Ra : Rb)
+                            : pivoted_cholesky_wave(wave == 0 ? W : V, D, wave == 0 ? Ra : Rb);
             if (lane == 0) sh.ri[wave] = r;
         }
         __syncthreads();
