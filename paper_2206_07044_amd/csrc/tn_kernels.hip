@@ -807,6 +807,8 @@ __device__ int pivoted_cholesky_wave_reg(const double* G, int D, double* R) {
     double diag = own ? G[l * D + l] : 0.0;
     double tol = 0.0;
     int r = 0;
+    // not unrolled: two copies of the column would double the live registers
+#pragma nounroll
     for (int t = 0; t < D; ++t) {
         const double cand = chosen ? -1.0 : diag;
         const double bv = wave_max(cand);
