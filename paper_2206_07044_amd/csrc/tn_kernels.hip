@@ -1681,7 +1681,15 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     // ---- singular values and descending order (ties: lower column first)
     sorted_norms<NT>(W, ra, rb, D, sig, order, kLds ? nullptr : lds);
     double fro = 0.0;
-    for (int j = 0; j < rb; ++j) fro += sig[j] * sig[j];
+    {
+        double f4[4] = {0.0, 0.0, 0.0, 0.0};
+        int j = 0;
+        for (; j + 4 <= rb; j += 4)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f4[e] = fma(sig[j + e], sig[j + e], f4[e]);
+        for (; j < rb; ++j) f4[0] = fma(sig[j], sig[j], f4[0]);
+        fro = (f4[0] + f4[1]) + (f4[2] + f4[3]);
+    }
     fro = sqrt(fro);
 
     // ---- projectors P_L (D x chi') and P_R (chi' x D)
@@ -1718,8 +1726,20 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         if (s > kNoiseRel * smax && s > 4.0 * kZeroRel * fro && s >= d.cutoff * smax) {
             const double* v = V + (int64_t)j * D;
             const double* u = W + (int64_t)j * D;
-            for (int i = 0; i < rb; ++i) pl += Rb[(int64_t)i * D + dd] * v[i];
-            for (int i = 0; i < ra; ++i) pr += u[i] * Ra[(int64_t)i * D + dd];
+            // four partial sums per dot product, so that the LDS loads overlap
+            double l4[4] = {0.0, 0.0, 0.0, 0.0}, r4[4] = {0.0, 0.0, 0.0, 0.0};
+            int i = 0;
+            for (; i + 4 <= rb; i += 4)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) l4[e] = fma(Rb[(int64_t)(i + e) * D + dd], v[i + e], l4[e]);
+            for (; i < rb; ++i) l4[0] = fma(Rb[(int64_t)i * D + dd], v[i], l4[0]);
+            i = 0;
+            for (; i + 4 <= ra; i += 4)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) r4[e] = fma(u[i + e], Ra[(int64_t)(i + e) * D + dd], r4[e]);
+            for (; i < ra; ++i) r4[0] = fma(u[i], Ra[(int64_t)i * D + dd], r4[0]);
+            pl = (l4[0] + l4[1]) + (l4[2] + l4[3]);
+            pr = (r4[0] + r4[1]) + (r4[2] + r4[3]);
             const double rs = sqrt(s);
             pl /= rs;
             pr /= (s * rs);
