@@ -1306,6 +1306,11 @@ constexpr size_t kBJLdsBytes = (size_t)(4 * kBJCols * kBJRows + 4 * kBJCols * kB
 __device__ inline int* core_ranks(double* gsig, int D) { return (int*)(gsig + 2 * D); }
 __device__ inline double* core_fro2(double* gsig, int D) { return gsig + 2 * D + 1; }
 __device__ inline int* core_bigflags(double* gsig, int D) { return (int*)(gsig + 2 * D + 2); }
+// rows and columns of the matrix the block launches rotate (after the sweep flags)
+__device__ inline int* core_jdims(double* gsig, int D) { return core_bigflags(gsig, D) + kBJSweeps; }
+// The block launches rotate the columns of W^T = R~_B R~_A^T (rb x ra) and accumulate U: on these
+// graded cores that takes about 40% fewer sweeps than W's columns (same stopping rule).
+constexpr bool kBJTransposed = true;
 
 __global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc* __restrict__ descs, int per_core,
                                                                   int sweep, int round) {
@@ -1321,8 +1326,8 @@ __global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc
     double* gsig = d.work + 4 * DD;
     int* big = core_bigflags(gsig, D);
     if (sweep > 0 && big[sweep - 1] == 0) return;   // the previous sweep converged
-    const int* ranks = core_ranks(gsig, D);
-    const int ra = ranks[0], rb = ranks[1];
+    const int* jd = core_jdims(gsig, D);
+    const int ra = jd[0], rb = jd[1];   // rows, columns of the rotated matrix
     int nb = (rb + kBJCols - 1) / kBJCols;
     nb += nb & 1;
     if (q >= nb / 2 || round >= nb - 1) return;
@@ -1607,8 +1612,10 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
 
     // ---- core W = R~_A R~_B^T  (ra x rb), V = I
     if constexpr (!kLds) {
-        // column j of W is row j of R~_B R~_A^T: one workgroup GEMM on the MFMA (LDS staging)
-        if (phase != 2) wg_gemm_f64(Rb, D, 1, Ra, 1, D, W, D, rb, ra, D, lds);
+        // column j of W is row j of R~_B R~_A^T: one workgroup GEMM on the MFMA (LDS staging);
+        // for the block launches the transpose W^T (column i = row i of R~_A R~_B^T)
+        if (phase == 1 && kBJTransposed) wg_gemm_f64(Ra, D, 1, Rb, 1, D, W, D, ra, rb, D, lds);
+        else if (phase != 2) wg_gemm_f64(Rb, D, 1, Ra, 1, D, W, D, rb, ra, D, lds);
     } else
     for (int idx = tid; idx < ra * rb; idx += NT) {
         const int j = idx / ra, i = idx - j * ra;
@@ -1623,16 +1630,20 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         }
         W[(int64_t)j * D + i] = s;
     }
+    // V = I, the size of the rotated matrix's column count
+    const int nv = (!kLds && phase == 1 && kBJTransposed) ? ra : rb;
     if (phase != 2)
-        for (int idx = tid; idx < rb * rb; idx += NT) {
-            const int j = idx / rb, i = idx - j * rb;
+        for (int idx = tid; idx < nv * nv; idx += NT) {
+            const int j = idx / nv, i = idx - j * nv;
             V[(int64_t)j * D + i] = (i == j) ? 1.0 : 0.0;
         }
     __syncthreads();
     if (!kLds && phase == 1) {
+        // ||W||_F^2 over the rotated matrix (rows fr, columns fc, column j at W + j * D)
+        const int fr = kBJTransposed ? rb : ra, fc = kBJTransposed ? ra : rb;
         double f = 0.0;
-        for (int idx = tid; idx < ra * rb; idx += NT) {
-            const int j = idx / ra, i = idx - j * ra;
+        for (int idx = tid; idx < fr * fc; idx += NT) {
+            const int j = idx / fr, i = idx - j * fr;
             const double x = W[(int64_t)j * D + i];
             f = fma(x, x, f);
         }
@@ -1645,6 +1656,8 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
             *core_fro2(gsig, D) = t;
             core_ranks(gsig, D)[0] = ra;
             core_ranks(gsig, D)[1] = rb;
+            core_jdims(gsig, D)[0] = kBJTransposed ? rb : ra;
+            core_jdims(gsig, D)[1] = kBJTransposed ? ra : rb;
         }
         for (int t = tid; t < kBJSweeps; t += NT) core_bigflags(gsig, D)[t] = 0;
         return;
@@ -1656,8 +1669,9 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
     if (!kLds && phase == 2) {
         // sweeps made by the block launches: the first one without a large rotation ended them
         const int* big = core_bigflags(gsig, D);
+        const int jr = core_jdims(gsig, D)[0], jc = core_jdims(gsig, D)[1];
         const int issued = min(kBJSweeps, max_sweeps);
-        converged = rb <= 1;
+        converged = jc <= 1;
         sweeps = converged ? 0 : issued;
         for (int t = 0; t < issued && !converged; ++t)
             if (big[t] == 0) {
@@ -1666,8 +1680,31 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
             }
         if (!converged && max_sweeps > issued) {
             int more = 0;
-            converged = jacobi_svd_256(W, V, ra, rb, D, max_sweeps - issued, sh, &more);
+            converged = jacobi_svd_256(W, V, jr, jc, D, max_sweeps - issued, sh, &more);
             sweeps += more;
+        }
+        if (kBJTransposed) {
+            // W^T V = (V_W s) with V holding U: column j of the rotated W^T is v_j s_j, column j of
+            // V is u_j.  Rebuild W (columns u_t s_t) and V (columns v_t) in descending order
+            // through the scratch after the workspace's sorted projector columns.
+            sorted_norms<NT>(W, jr, jc, D, sig, order, lds);
+            double* Wn = d.work + 4 * DD + 4 * D + 2 * (int64_t)D * d.chi_new;
+            double* Vn = Wn + DD;
+            const int m = min(ra, rb);
+            for (int idx = tid; idx < rb * D; idx += NT) {
+                const int t = idx / D, i = idx - t * D;
+                const int j = t < m ? order[t] : -1;
+                const double sj = j >= 0 ? sig[j] : 0.0;
+                const bool ok = sj > 0.0;
+                Wn[idx] = (ok && i < ra) ? V[(int64_t)j * D + i] * sj : 0.0;
+                Vn[idx] = (ok && i < rb) ? W[(int64_t)j * D + i] / sj : 0.0;
+            }
+            __syncthreads();
+            for (int idx = tid; idx < rb * D; idx += NT) {
+                W[idx] = Wn[idx];
+                V[idx] = Vn[idx];
+            }
+            __syncthreads();
         }
     } else if constexpr (kLds)   // ra, rb <= D <= 64
         converged = (ra <= 32 && rb <= 32) ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)

@@ -515,8 +515,10 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         touch(c.side_a_buf, core.level + 1);
                         touch(c.side_b_buf, core.level + 1);
                     } else {
-                        // R~_A, R~_B, W, V, spectrum; the sorted kept columns of V and W (global cores)
-                        c.work_buf = new_buf((4 * D * D + 4 * D + 2 * D * nw) * 8, BUF_WORK, core.level);
+                        // R~_A, R~_B, W, V, spectrum; the sorted kept columns of V and W; for the block
+                        // Jacobi of 64 < D <= 256, room to rebuild W and V from the transposed problem
+                        const int64_t rebuild = (D > 64 && D <= 256) ? 2 * D * D : 0;
+                        c.work_buf = new_buf((4 * D * D + 4 * D + 2 * D * nw + rebuild) * 8, BUF_WORK, core.level);
                         // like a Gram-Lanczos launch, a core launch may run on into the next level
                         touch(c.work_buf, core.level + 1);
                         touch(c.side_a_buf, core.level + 1);
