@@ -1283,8 +1283,8 @@ __device__ inline void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t 
     wg_gemm_narrow_to<double>(A, ar, ac, B, br, bc, C, ldc, 1, M, N, K);
 }
 
-// Block one-sided Jacobi for the global cores (64 < D <= 256): the columns of W are cut into
-// blocks of kBJCols, and the blocks follow a round-robin tournament, one launch per round and one
+// Block one-sided Jacobi for the global cores (64 < D <= 256): the columns of the matrix it
+// rotates (here called W; the core's transpose when kBJTransposed) are cut into blocks of kBJCols, and the blocks follow a round-robin tournament, one launch per round and one
 // workgroup per block pair.  A workgroup stages its two blocks of W in LDS and rotates every cross
 // pair once (16 steps of 16 disjoint pairs); in the first round of a sweep each block is met for
 // the first time, so the workgroup also rotates the pairs inside its two blocks (a 32-column
@@ -1508,9 +1508,11 @@ __global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc
     if (tid == 0 && s_big) big[sweep] = 1;
 }
 
-// phase 0: the whole compression.  Global variant only: phase 1 stops after the core W and V = I
-// (with ranks, ||W||_F^2 and cleared sweep flags in the workspace) for block_jacobi_kernel;
-// phase 2 starts from the rotated W, V and does the rest.
+// phase 0: the whole compression.  Global variant only: phase 1 stops after the matrix for
+// block_jacobi_kernel (the core W, or W^T when kBJTransposed) and V = I, with ranks, the rotated
+// matrix's size, ||W||_F^2 and cleared sweep flags in the workspace; phase 2 starts from the
+// rotated matrix and V, rebuilds W (columns u s) and V (columns v) from the transposed problem,
+// and does the rest.
 template <bool kLds, typename Tp>
 __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_kernel(const CoreDesc* __restrict__ descs, int max_sweeps,
                                                             double* __restrict__ stat_disc,
