@@ -1297,7 +1297,7 @@ constexpr int kBJCols = 16;
 constexpr int kBJRows = 256;
 constexpr int kBJThreads = 256;
 constexpr int kBJKR = kBJRows / 16;   // rows of W per lane
-constexpr int kBJSweeps = 24;   // sweeps issued as block launches; a core still rotating after
+constexpr int kBJSweeps = 18;   // sweeps issued as block launches; a core still rotating after
                                 // them finishes in the one-workgroup Jacobi
 constexpr size_t kBJLdsBytes = (size_t)(4 * kBJCols * kBJRows + 4 * kBJCols * kBJCols) * sizeof(double);
 
