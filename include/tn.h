@@ -7,8 +7,22 @@
  * ("Approximate contraction", section II.F) with early compression and tree
  * gauge distance r = 0.  Each compression replaces every edge shared by two
  * tensors with one edge of dimension chi' = min(chi, k_A, k_B) using the
- * QR-reduced truncated SVD of section II.C, Eq. (svd), applied through the
+ * reduced truncated SVD of section II.C, Eq. (svd), applied through the
  * projectors P_L = R_B V s^-1/2 and P_R = s^-1/2 U^T R_A of SI section B.
+ *
+ * How the reduced factors are formed (the paper uses Householder QR; the
+ * projectors depend on R only through R^T R = A^T A, SI B):
+ *   - bonds of size D <= 64 and gradient plans: R from a float64 Gram matrix
+ *     A^T A by pivoted Cholesky.  Pivots below 1e-15 of the first one end the
+ *     factorisation, so directions of A whose singular value is below about
+ *     3e-8 of A's largest are dropped (the Gram squares the spectrum); the
+ *     core SVD is a one-sided Jacobi in float64.
+ *   - forward plans with D > 64: the leading chi' singular triplets of the
+ *     core come from a Krylov method on the same Gram operators (or on A B
+ *     directly); eigenvalues of the squared core below 1e-13 of the largest
+ *     count as zero, i.e. kept singular values below about 3.2e-7 sigma_1
+ *     give zero projector columns.
+ * Core singular values at or below 1e-13 sigma_1 always count as zero.
  *
  * Inputs follow the paper's statement of the problem (Algorithm 1, "Input:
  * tensor network T, ordered contraction tree, maximum bond dimension chi,
@@ -20,7 +34,7 @@
  * during the call and stays owned by the caller.  The context owns its
  * device memory (one arena planned by tn_set_tree) unless a workspace is
  * supplied with tn_set_workspace, which then stays owned by the caller and
- * must outlive the context's use of it.
+ * must outlive every plan made while it was set.
  */
 #ifndef TN_H
 #define TN_H
@@ -78,6 +92,15 @@ void tn_destroy(tn_ctx* ctx);
 /* Text of the last error on ctx (valid until the next call on ctx). */
 const char* tn_last_error(const tn_ctx* ctx);
 
+/* Device workspace for the arena of later tn_set_tree calls (e.g. memory
+ * owned by torch: size it with tn_plan_info's arena_bytes of a first plan).
+ * dev_ptr: device memory of `bytes` bytes, 256-byte aligned, caller owned; it
+ * must stay valid while a plan made with it is in use.  NULL switches back
+ * to library allocation.  A plan whose arena exceeds `bytes` fails with
+ * TN_ENOMEM before any launch.  The current plan, if any, is unaffected.
+ * Errors: TN_EINVAL for a misaligned pointer or zero bytes. */
+tn_status tn_set_workspace(tn_ctx* ctx, void* dev_ptr, size_t bytes);
+
 /* Tensor network (section I, Eq. (tncontract); data structure of
  * Fig. "tensor primitives"): n_tensors vertices and n_edges edges
  * (edge_u[e] < edge_v[e], both < n_tensors, edge_dim[e] >= 1; several edges
@@ -118,7 +141,9 @@ tn_status tn_contract_compressed(tn_ctx* ctx, double* mantissa, double* log10_ex
 tn_status tn_result(const tn_ctx* ctx, double* sign, double* ln_abs_z);
 
 /* Enqueue an evaluation without synchronising (for timing and batching);
- * tn_fetch synchronises the ctx stream and makes it the last evaluation.
+ * tn_fetch synchronises the ctx stream and, when it returns TN_OK or
+ * TN_ZERO, makes it the last evaluation (a TN_ENUMERIC evaluation leaves
+ * none: tn_result and tn_grad then return TN_ESTATE).
  * The first evaluation after tn_set_tree (or after a change of the
  * tn_profile mask) captures the schedule into a hipGraph on the ctx stream;
  * later ones replay it, so the input values may change between evaluations

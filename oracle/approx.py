@@ -178,7 +178,10 @@ def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
     new = min(chi, ka, kb)
     total = float(np.sum(sig ** 2))
     disc = float(np.sum(sig[new:] ** 2)) / total if total > 0 else 0.0
-    tie = bool(len(sig) > new and sig[new - 1] - sig[new] <= 1e-12 * sig[0])
+    # a tie: the last kept and first discarded values coincide to 1e-12 sigma_1 while the kept one
+    # is above the rounding level (1e-13 sigma_1); among rounding-level values the choice changes
+    # A B by less than 1e-13 relative, so it is not a tie in any sense that matters
+    tie = bool(len(sig) > new and sig[new - 1] > 1e-13 * sig[0] and sig[new - 1] - sig[new] <= 1e-12 * sig[0])
     keep = sig[:new].copy()
     mask = (keep > 0) & (keep >= cutoff * sig[0])
     inv_sqrt = np.where(mask, 1.0 / np.sqrt(np.where(mask, keep, 1.0)), 0.0)

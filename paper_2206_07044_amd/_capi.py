@@ -72,6 +72,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_update_values_device": ([P, P], C.c_int),
         "tn_set_tree": ([P, I32, pI32, pI32, C.POINTER(tn_tree_opts)], C.c_int),
         "tn_plan_info": ([P, pI64, pD, pD, pI32], C.c_int),
+        "tn_set_workspace": ([P, P, C.c_size_t], C.c_int),
         "tn_contract_compressed": ([P, pD, pD], C.c_int),
         "tn_result": ([P, pD, pD], C.c_int),
         "tn_enqueue": ([P], C.c_int),
@@ -104,7 +105,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
 
 def exported_symbols() -> List[str]:
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
-            "tn_update_values_device", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
+            "tn_update_values_device", "tn_set_workspace", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
             "tn_grad_device", "tn_grad_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
             "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
@@ -152,6 +153,10 @@ class Context:
     def __init__(self, device: int = 0, stream: Optional[int] = None):
         self._lib = load_library()
         self._h = C.c_void_p()
+        # bumped by every call that changes the inputs or the last evaluation (values, trees,
+        # evaluations): the autograd functions compare it to know whether the context still
+        # holds the forward pass they are asked to differentiate
+        self.state_id = 0
         st = self._lib.tn_create(int(device), C.c_void_p(stream) if stream else None, C.byref(self._h))
         if st != TN_OK:
             raise TNError(st, "tn_create failed (no HIP device?)")
@@ -182,15 +187,18 @@ class Context:
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         self._data = np.ascontiguousarray(data, dtype=np.float64)
         self._n_data = int(off[-1]) if off.size else 0
+        self.state_id += 1
         self._check(self._lib.tn_load_graph(self._h, int(n), eu.size, _ptr(eu, C.c_int32), _ptr(ev, C.c_int32),
                                             _ptr(ed, C.c_int32), _ptr(off, C.c_int64),
                                             _ptr(self._data, C.c_double)))
 
     def tn_update_values(self, data) -> None:
         d = np.ascontiguousarray(data, dtype=np.float64)
+        self.state_id += 1
         self._check(self._lib.tn_update_values(self._h, _ptr(d, C.c_double)))
 
     def tn_update_values_device(self, dev_ptr: int) -> None:
+        self.state_id += 1
         self._check(self._lib.tn_update_values_device(self._h, C.c_void_p(dev_ptr)))
 
     def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
@@ -198,8 +206,13 @@ class Context:
                     grad: bool = False) -> None:
         pi, pj = _i32(pair_i), _i32(pair_j)
         opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad)
+        self.state_id += 1
         self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
                                           C.byref(opts)))
+
+    def tn_set_workspace(self, dev_ptr: Optional[int], nbytes: int) -> None:
+        """Arena memory for later plans (device pointer, caller owned); None: library allocation."""
+        self._check(self._lib.tn_set_workspace(self._h, C.c_void_p(dev_ptr) if dev_ptr else None, int(nbytes)))
 
     def tn_plan_info(self) -> dict:
         ab, ff, fb, ns = C.c_int64(), C.c_double(), C.c_double(), C.c_int32()
@@ -208,6 +221,7 @@ class Context:
 
     def tn_contract_compressed(self) -> Tuple[float, float]:
         m, e = C.c_double(), C.c_double()
+        self.state_id += 1
         st = self._lib.tn_contract_compressed(self._h, C.byref(m), C.byref(e))
         if st == TN_ZERO:
             return 0.0, float("-inf")
@@ -220,6 +234,7 @@ class Context:
         return s.value, l.value
 
     def tn_enqueue(self) -> None:
+        self.state_id += 1
         self._check(self._lib.tn_enqueue(self._h))
 
     def tn_fetch(self) -> int:
@@ -271,6 +286,7 @@ class Context:
         self._check(self._lib.tn_sync(self._h))
 
     def tn_ising_values_device(self, beta: float, J_ptr: int) -> None:
+        self.state_id += 1
         self._check(self._lib.tn_ising_values_device(self._h, float(beta), C.c_void_p(J_ptr)))
 
     def tn_ising_coupling_grad_device(self, beta: float, J_ptr: int, dT_ptr: int, dJ_ptr: int) -> None:
@@ -306,6 +322,8 @@ class Batch:
         n = len(self.contexts)
         m = np.zeros(n)
         e = np.zeros(n)
+        for c in self.contexts:
+            c.state_id += 1
         self._check(self._lib.tn_batch_contract(self._h, _ptr(m, C.c_double), _ptr(e, C.c_double)))
         return m, e
 

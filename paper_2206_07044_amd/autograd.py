@@ -26,19 +26,29 @@ class _LogZFromData(torch.autograd.Function):
     """ln|Z| as a function of the flattened input tensors (float64, device)."""
 
     @staticmethod
-    def forward(ctx, data: torch.Tensor, tnctx: Context):
-        data = data.detach().contiguous()
+    def _evaluate(tnctx: Context, data: torch.Tensor) -> float:
         torch.cuda.current_stream().synchronize()
         tnctx.tn_update_values_device(data.data_ptr())
         tnctx.tn_contract_compressed()
-        _, lnz = tnctx.tn_result()
+        return tnctx.tn_result()[1]
+
+    @staticmethod
+    def forward(ctx, data: torch.Tensor, tnctx: Context):
+        data = data.detach().contiguous()
+        lnz = _LogZFromData._evaluate(tnctx, data)
+        ctx.save_for_backward(data)
         ctx.tnctx = tnctx
-        ctx.n = data.numel()
+        ctx.state_id = tnctx.state_id
         return torch.tensor(lnz, dtype=torch.float64, device=data.device)
 
     @staticmethod
     def backward(ctx, g):
-        out = torch.empty(ctx.n, dtype=torch.float64, device=g.device)
+        (data,) = ctx.saved_tensors
+        if ctx.tnctx.state_id != ctx.state_id:
+            # the context has evaluated something else since this forward pass: recompute it
+            # (the reverse pass reads the forward intermediates the context holds)
+            _LogZFromData._evaluate(ctx.tnctx, data)
+        out = torch.empty(data.numel(), dtype=torch.float64, device=g.device)
         torch.cuda.current_stream().synchronize()
         ctx.tnctx.tn_grad_device(out.data_ptr())
         ctx.tnctx.tn_sync()
@@ -49,19 +59,27 @@ class _LogZFromCouplings(torch.autograd.Function):
     """ln|Z| of the Ising model (SI F.1) as a function of the couplings J."""
 
     @staticmethod
+    def _evaluate(tnctx: Context, J: torch.Tensor, beta: float) -> float:
+        torch.cuda.current_stream().synchronize()
+        tnctx.tn_ising_values_device(beta, J.data_ptr())
+        tnctx.tn_contract_compressed()
+        return tnctx.tn_result()[1]
+
+    @staticmethod
     def forward(ctx, J: torch.Tensor, tnctx: Context, beta: float, n_data: int):
         Jc = J.detach().contiguous()
-        torch.cuda.current_stream().synchronize()
-        tnctx.tn_ising_values_device(beta, Jc.data_ptr())
-        tnctx.tn_contract_compressed()
-        _, lnz = tnctx.tn_result()
-        ctx.J = Jc
+        lnz = _LogZFromCouplings._evaluate(tnctx, Jc, beta)
+        ctx.save_for_backward(Jc)
         ctx.tnctx, ctx.beta, ctx.n_data = tnctx, beta, n_data
+        ctx.state_id = tnctx.state_id
         return torch.tensor(lnz, dtype=torch.float64, device=J.device)
 
     @staticmethod
     def backward(ctx, g):
-        J = ctx.J
+        (J,) = ctx.saved_tensors
+        if ctx.tnctx.state_id != ctx.state_id:
+            # another evaluation ran on this context after this forward pass: recompute it
+            _LogZFromCouplings._evaluate(ctx.tnctx, J, ctx.beta)
         dT = torch.empty(ctx.n_data, dtype=torch.float64, device=J.device)
         dJ = torch.empty_like(J)
         torch.cuda.current_stream().synchronize()

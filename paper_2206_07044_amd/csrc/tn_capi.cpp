@@ -61,6 +61,9 @@ struct tn_ctx {
     bool has_plan = false;
     char* arena = nullptr;
     size_t arena_cap = 0;
+    bool arena_owned = true;           // false: the arena is the caller's workspace (tn_set_workspace)
+    char* workspace = nullptr;         // caller-owned device memory for the next plans, or null
+    size_t workspace_bytes = 0;
 
     std::vector<GemmDesc> h_gemm;
     std::vector<CopyDesc> h_copy;
@@ -161,7 +164,9 @@ void free_forward_graph(tn_ctx* c) {
 
 void free_plan(tn_ctx* c) {
     free_forward_graph(c);
-    dfree(c->arena);
+    if (c->arena_owned) dfree(c->arena);
+    c->arena = nullptr;
+    c->arena_owned = true;
     c->arena_cap = 0;
     dfree(c->d_gemm);
     dfree(c->d_copy);
@@ -815,10 +820,15 @@ int lane_of(const Launch& l) {
 // wait for them before its first tensor-GEMM launch (the re-absorptions that read the
 // projectors) or, failing that, at its own join.  So a compression runs beside the next level's
 // other compressions, Grams and copies; the planner keeps its inputs one level longer.
+//
+// `open` is a ledger of the lanes whose work `main` has not yet waited for (bit = lane): forks
+// set bits, joins clear them, deferred joins keep them until the next level waits.  On a failed
+// launch every forked lane is joined back before returning, so a capture can always be ended
+// with no stream left forked; the caller checks the ledger is empty before ending a capture.
 template <typename Run>
 hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStream_t main, hipStream_t* aux,
                      std::vector<hipEvent_t>& events, size_t& next_ev, Run&& run, hipEvent_t* pending,
-                     bool allow_defer) {
+                     bool allow_defer, int& open) {
     int used = 0;
     bool lane2_glanczos = true;
     for (size_t i = b; i < e; ++i) {
@@ -841,20 +851,41 @@ hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStrea
                 hipError_t err = hipStreamWaitEvent(main, pending[k], 0);
                 pending[k] = nullptr;
                 if (err != hipSuccess) return err;
+                open &= ~(1 << (k + 1));
             }
         return hipSuccess;
+    };
+    // failure inside a level: bring every lane with outstanding work back to `main` (best
+    // effort: the first error is the one reported)
+    auto join_all = [&](hipError_t first) -> hipError_t {
+        for (int k = 0; k < 2; ++k)
+            if (pending[k]) {
+                (void)hipStreamWaitEvent(main, pending[k], 0);
+                pending[k] = nullptr;
+            }
+        for (int lane = 1; lane < kLanes; ++lane)
+            if (open & (1 << lane)) {
+                hipEvent_t j = nullptr;
+                if (event(&j) == hipSuccess && hipEventRecord(j, aux[lane - 1]) == hipSuccess &&
+                    hipStreamWaitEvent(main, j, 0) == hipSuccess)
+                    open &= ~(1 << lane);
+            }
+        return first;
     };
     hipError_t err = hipSuccess;
     if ((used & (used - 1)) == 0) {   // a single lane: no fork
         err = wait_pending();
         for (size_t i = b; i < e && err == hipSuccess; ++i) err = run(ls[i], main);
-        return err;
+        return err == hipSuccess ? err : join_all(err);
     }
     hipEvent_t fork;
     err = event(&fork);
     if (err == hipSuccess) err = hipEventRecord(fork, main);
     for (int lane = 1; lane < kLanes && err == hipSuccess; ++lane)
-        if (used & (1 << lane)) err = hipStreamWaitEvent(aux[lane - 1], fork, 0);
+        if (used & (1 << lane)) {
+            err = hipStreamWaitEvent(aux[lane - 1], fork, 0);
+            if (err == hipSuccess) open |= 1 << lane;
+        }
     for (size_t i = b; i < e && err == hipSuccess; ++i) {
         const int lane = lane_of(ls[i]);
         if (lane == 0) err = wait_pending();   // the previous level's projectors
@@ -868,13 +899,37 @@ hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStrea
             if (err == hipSuccess) err = hipEventRecord(join, aux[lane - 1]);
             if (err != hipSuccess) break;
             const bool defer = allow_defer && (lane == 1 || (lane == 2 && lane2_glanczos));
-            if (defer) deferred[lane - 1] = join;
-            else err = hipStreamWaitEvent(main, join, 0);
+            if (defer) {
+                deferred[lane - 1] = join;
+            } else {
+                err = hipStreamWaitEvent(main, join, 0);
+                if (err == hipSuccess) open &= ~(1 << lane);
+            }
         }
     if (err == hipSuccess) err = wait_pending();   // never past one level
+    if (err != hipSuccess) {
+        for (int k = 0; k < 2; ++k)
+            if (deferred[k] && !pending[k]) pending[k] = deferred[k];
+        return join_all(err);
+    }
     pending[0] = deferred[0];
     pending[1] = deferred[1];
     return err;
+}
+
+// Wait on `main` for the deferred joins of the last level and check the fork/join ledger.
+template <typename Ctx, typename Fail>
+tn_status join_tail(Ctx* x, hipStream_t main, hipEvent_t* pending, int& open, Fail&& failf) {
+    for (int k = 0; k < 2; ++k)
+        if (pending[k]) {
+            hipError_t e = hipStreamWaitEvent(main, pending[k], 0);
+            if (e != hipSuccess) return failf(x, TN_EDEVICE, std::string("join: ") + hipGetErrorString(e));
+            pending[k] = nullptr;
+            open &= ~(1 << (k + 1));
+        }
+    if (open != 0)
+        return failf(x, TN_EDEVICE, "internal: a stream forked for a schedule level was never joined");
+    return TN_OK;
 }
 
 }  // namespace
@@ -1045,10 +1100,22 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
         return fail(c, nomem ? TN_ENOMEM : TN_EINVAL, err);
     }
     const size_t bytes = (size_t)std::max<int64_t>(c->plan.arena_bytes, 256);
-    hipError_t e = hipMalloc((void**)&c->arena, bytes);
-    if (e != hipSuccess) {
-        c->arena = nullptr;
-        return fail(c, TN_ENOMEM, std::string("arena of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    if (c->workspace) {
+        if (bytes > c->workspace_bytes) {
+            const std::string msg = "plan needs an arena of " + std::to_string(bytes) + " bytes, the workspace holds " +
+                                    std::to_string(c->workspace_bytes);
+            free_plan(c);
+            return fail(c, TN_ENOMEM, msg);
+        }
+        c->arena = c->workspace;
+        c->arena_owned = false;
+    } else {
+        hipError_t e = hipMalloc((void**)&c->arena, bytes);
+        if (e != hipSuccess) {
+            c->arena = nullptr;
+            return fail(c, TN_ENOMEM, std::string("arena of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+        }
+        c->arena_owned = true;
     }
     c->arena_cap = bytes;
     tn_status s = build_launches(c);
@@ -1058,6 +1125,15 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
         return s;
     }
     c->has_plan = true;
+    return TN_OK;
+}
+
+tn_status tn_set_workspace(tn_ctx* c, void* dev_ptr, size_t bytes) {
+    if (!c) return TN_EINVAL;
+    if (dev_ptr && ((uintptr_t)dev_ptr % 256) != 0) return fail(c, TN_EINVAL, "workspace must be 256-byte aligned");
+    if (dev_ptr && bytes == 0) return fail(c, TN_EINVAL, "empty workspace");
+    c->workspace = (char*)dev_ptr;
+    c->workspace_bytes = dev_ptr ? bytes : 0;
     return TN_OK;
 }
 
@@ -1138,14 +1214,15 @@ tn_status enqueue_forward(tn_ctx* c) {
     };
     size_t next_ev = 0;
     hipEvent_t pending[2] = {nullptr, nullptr};
+    int open = 0;
     for (size_t b = 0; b < c->launches.size();) {
         size_t e = b;
         while (e < c->launches.size() && c->launches[e].level == c->launches[b].level) ++e;
-        HIP_TRY(c, run_level(c->launches, b, e, s, c->aux, c->sync_ev, next_ev, run, pending, e < c->launches.size()));
+        HIP_TRY(c, run_level(c->launches, b, e, s, c->aux, c->sync_ev, next_ev, run, pending, e < c->launches.size(),
+                             open));
         b = e;
     }
-    for (hipEvent_t ev : pending)
-        if (ev) HIP_TRY(c, hipStreamWaitEvent(s, ev, 0));
+    if (tn_status st = join_tail(c, s, pending, open, fail); st != TN_OK) return st;
     const void* fin = c->arena + P.bufs[P.tens[P.final_tensor].buf].off;
     HIP_TRY(c, launch_result(prec, c->d_scales, (int)P.tens.size(), fin, c->d_sweeps, (int)P.comps.size(),
                              c->d_result, s));
@@ -1223,9 +1300,11 @@ tn_status tn_fetch(tn_ctx* c) {
     c->sign = c->h_result[0];
     c->lnz = c->h_result[1];
     c->flags = (int)c->h_result[2];
-    c->evaluated = true;
+    // only a finished evaluation counts: tn_result and tn_grad refuse a failed one
+    c->evaluated = false;
     if (c->flags & 2) return fail(c, TN_ENUMERIC, "non-finite tensor entry");
     if (c->flags & 4) return fail(c, TN_ENUMERIC, "a Jacobi SVD did not converge within the sweep cap");
+    c->evaluated = true;
     if ((c->flags & 1) || c->sign == 0.0) {
         c->sign = 0.0;
         c->lnz = -INFINITY;
@@ -1744,14 +1823,15 @@ tn_status enqueue_batch_forward(tn_batch* b) {
     };
     size_t next_ev = 0;
     hipEvent_t pending[2] = {nullptr, nullptr};
+    int open = 0;
     for (size_t i = 0; i < b->launches.size();) {
         size_t e = i;
         while (e < b->launches.size() && b->launches[e].level == b->launches[i].level) ++e;
-        BHIP_TRY(b, run_level(b->launches, i, e, s, b->aux, b->sync_ev, next_ev, run, pending, e < b->launches.size()));
+        BHIP_TRY(b, run_level(b->launches, i, e, s, b->aux, b->sync_ev, next_ev, run, pending, e < b->launches.size(),
+                              open));
         i = e;
     }
-    for (hipEvent_t ev : pending)
-        if (ev) BHIP_TRY(b, hipStreamWaitEvent(s, ev, 0));
+    if (tn_status st = join_tail(b, s, pending, open, bfail); st != TN_OK) return st;
     for (int i = 0; i < (int)b->ctxs.size(); ++i) {
         tn_ctx* c = b->ctxs[i];
         const Plan& P = c->plan;

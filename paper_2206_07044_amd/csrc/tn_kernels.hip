@@ -1818,7 +1818,7 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
         stat_disc[d.stat] = tot > 0.0 ? disc / tot : 0.0;
         const double s_last = (cn - 1 < rb) ? sig[order[cn - 1]] : 0.0;
         const double s_next = (cn < rb) ? sig[order[cn]] : 0.0;
-        stat_tie[d.stat] = (d.kmin > cn && s_last - s_next <= 1e-12 * smax) ? 1 : 0;
+        stat_tie[d.stat] = (d.kmin > cn && s_last > 1e-13 * smax && s_last - s_next <= 1e-12 * smax) ? 1 : 0;
         stat_sweeps[d.stat] = converged ? sweeps : -1 - sweeps;   // negative: not converged
     }
 }
@@ -2134,7 +2134,7 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
         stat_disc[d.stat] = tot > 0.0 ? disc / tot : 0.0;
         const double s_last = (cn - 1 < nsv) ? sig[order[cn - 1]] : 0.0;
         const double s_next = (cn < nsv) ? sig[order[cn]] : 0.0;
-        stat_tie[d.stat] = (d.kmin > cn && nsv > cn && s_last - s_next <= 1e-12 * smax_v) ? 1 : 0;
+        stat_tie[d.stat] = (d.kmin > cn && nsv > cn && s_last > 1e-13 * smax_v && s_last - s_next <= 1e-12 * smax_v) ? 1 : 0;
         stat_sweeps[d.stat] = converged ? nsv : -1 - nsv;
     }
 }
@@ -2466,7 +2466,8 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         stat_disc[d.stat] = tot > 0.0 ? disc / tot : 0.0;
         const double l_last = (cn - 1 < nev) ? sig[order[cn - 1]] : 0.0;
         const double l_next = (cn < nev) ? sig[order[cn]] : 0.0;
-        stat_tie[d.stat] = (d.kmin > cn && nev > cn && sqrt(fmax(l_last, 0.0)) - sqrt(fmax(l_next, 0.0)) <= 1e-12 * sqrt(lmax)) ? 1 : 0;
+        const double sl = sqrt(fmax(l_last, 0.0)), sn = sqrt(fmax(l_next, 0.0));
+        stat_tie[d.stat] = (d.kmin > cn && nev > cn && sl > 1e-13 * sqrt(lmax) && sl - sn <= 1e-12 * sqrt(lmax)) ? 1 : 0;
         stat_sweeps[d.stat] = converged ? nev : -1 - nev;
     }
 }

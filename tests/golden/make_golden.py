@@ -7,6 +7,10 @@ ising_8x8.json   : 8x8 open-boundary Ising, beta=0.44 — transfer-matrix ln Z a
 cubic_12.json    : 12x12x12 Ising, beta=0.22, chi=16, sweep tree (--big, ~10 min of CPU):
                    the oracle's ln|Z| and its spread when one input tensor is perturbed at the
                    1e-15 level (the conditioning of this workload; see the design notes).
+                   With --threads (~25 min of CPU) it also records the oracle's ln|Z| with the
+                   BLAS library limited to 1, 2, 4 and all threads: the summation order inside
+                   LAPACK's QR and SVD changes with the thread count, and the spread of these
+                   unmodified oracle runs is the rounding sensitivity of this instance.
 cubic_12_chi32.json: the same network and tree at chi=32 (--chi32, ~30 min of CPU): the oracle's
                    ln|Z| only.
 """
@@ -56,6 +60,25 @@ def cubic_12(n_perturb=3):
             "cpu_seconds": time.time() - t0}
 
 
+def cubic_12_threads(rec):
+    """Add the oracle's ln|Z| under BLAS thread limits of 1, 2, 4 and all cores to ``rec``."""
+    from threadpoolctl import threadpool_limits
+    g = lattice((12, 12, 12))
+    T = ising_tensors(g, 0.22)
+    p = sweep_tree((12, 12, 12))
+    runs = {}
+    for nt in (1, 2, 4, os.cpu_count()):
+        with threadpool_limits(limits=nt, user_api="blas"):
+            t0 = time.time()
+            runs[str(nt)] = {"oracle_lnZ": oracle.contract_compressed(g.n, g.edges, T, p, 16).ln_abs_z,
+                             "cpu_seconds": time.time() - t0}
+        print(f"threads={nt}: {runs[str(nt)]}", flush=True)
+    vals = [r["oracle_lnZ"] for r in runs.values()]
+    rec["blas_threads"] = runs
+    rec["blas_thread_spread_rel"] = (max(vals) - min(vals)) / abs(rec["oracle_lnZ"])
+    return rec
+
+
 def cubic_12_chi(chi):
     g = lattice((12, 12, 12))
     T = ising_tensors(g, 0.22)
@@ -74,5 +97,9 @@ if __name__ == "__main__":
     write("ising_8x8.json", ising_8x8())
     if "--big" in sys.argv:
         write("cubic_12.json", cubic_12())
+    if "--threads" in sys.argv:
+        with open(os.path.join(HERE, "cubic_12.json")) as f:
+            rec = json.load(f)
+        write("cubic_12.json", cubic_12_threads(rec))
     if "--chi32" in sys.argv:
         write("cubic_12_chi32.json", cubic_12_chi(32))

@@ -1,8 +1,8 @@
 """The headline workload at its real size: 12x12x12 Ising, beta = 0.22, chi = 16, sweep tree.
 
 The full CPU oracle takes minutes here, so the checks are:
-* ln Z in FP64 against the stored oracle value (tests/golden/cubic_12.json), within the
-  instance's measured sensitivity band;
+* ln Z in FP64 against the stored oracle values (tests/golden/cubic_12.json), within the
+  spread of the unmodified oracle itself over BLAS thread counts;
 * FP32 (the benchmark's configuration) against FP64 at the metric's 1e-6 relative gate;
 * the same at chi = 32 (bonds of D = 1024, Gram-Lanczos on 1024 x 1024 operators), and FP64
   against the stored oracle value (tests/golden/cubic_12_chi32.json) at 1e-10 relative;
@@ -29,10 +29,16 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SHAPE, BETA, CHI = (12, 12, 12), 0.22, 16
-# Perturbing a single input tensor at the 1e-16 level moves this instance's ln Z by up to
-# 1.7e-7 relative (near-degenerate truncations); a different FP64 rounding order is such a
-# perturbation.  The band is three times the largest measured move.
-SENSITIVITY_REL = 5e-7
+# This instance is rounding-sensitive: the unmodified float64 oracle, run with its BLAS library
+# limited to 1, 2, 4 and 8 threads (only LAPACK's summation order changes), returns ln Z values
+# that spread over 4.0e-7 relative (make_golden.py --threads records them in cubic_12.json).
+# The GPU's float64 result is accepted inside that interval widened by half its width on each
+# side: it is one more float64 rounding order of the same computation.
+def sensitivity_band(gold):
+    vals = [r["oracle_lnZ"] for r in gold["blas_threads"].values()]
+    lo, hi = min(vals), max(vals)
+    return lo - 0.5 * (hi - lo), hi + 0.5 * (hi - lo)
+
 PREFIX_STEPS = 480
 
 
@@ -68,7 +74,9 @@ def test_fullsize_fp64_against_stored_oracle(instance):
         c.close()
     print(f"\n12^3 chi=16 FP64: ln Z = {lnz!r}, oracle {gold['oracle_lnZ']!r}", flush=True)
     assert sign == 1.0 and not tie.any() and (sw >= 0).all()
-    assert lnz == pytest.approx(gold["oracle_lnZ"], rel=SENSITIVITY_REL)
+    lo, hi = sensitivity_band(gold)
+    print(f"    oracle thread-count band [{lo!r}, {hi!r}]", flush=True)
+    assert lo <= lnz <= hi
 
 
 def test_fullsize_fp32_meets_the_metric_gate(instance):

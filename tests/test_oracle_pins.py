@@ -267,3 +267,118 @@ def test_running_exponent_avoids_overflow():
     assert tm > 709.8
     r = run(g, T, sweep_tree((3, 3, 60), order=(2, 0, 1)), 1 << 12)
     assert abs(r.ln_abs_z - tm) / tm < 1e-13
+
+
+# ---------------------------------------------------------------- cutoff mask and tie flag (section II.C, Eq. (svd))
+def _probe_value(a_mat, b_mat, caps, chi, cutoff):
+    """kron(P1,P2)^T trunc(A_mat B_mat) kron(Q1,Q2) from numpy's SVD of the explicit product:
+    the chi' = min(chi, k_A, k_B) largest triplets, those with sigma_i < cutoff * sigma_1 zeroed."""
+    M = a_mat @ b_mat
+    U, s, Vt = np.linalg.svd(M, full_matrices=False)
+    D = a_mat.shape[1]
+    k = min(chi, min(a_mat.shape[0], D), min(b_mat.shape[1], D))
+    keep = s[:k] * ((s[:k] > 0) & (s[:k] >= cutoff * s[0]))
+    u = np.kron(caps[0], caps[1])
+    w = np.kron(caps[2], caps[3])
+    return float(u @ (U[:, :k] * keep) @ Vt[:k] @ w), k
+
+
+def _probe_run(a_mat, b_mat, shared, p, q, caps, chi, cutoff):
+    from tninputs.probes import bond_probe
+    g, T, pairs = bond_probe(a_mat, b_mat, shared, p, q, caps)
+    r = run(g, T, pairs, chi, cutoff=cutoff)
+    comp = [o for o in r.ops if o.kind == "compress"]
+    assert len(comp) == 1, "the probe network must compress exactly one bond"
+    return r, comp[0]
+
+
+@pytest.mark.parametrize("cut_between", [None, 1, 2, 4])
+@pytest.mark.parametrize("chi", [3, 5])
+def test_cutoff_mask_is_relative_truncated_svd(cut_between, chi):
+    """cutoff > 0 zeroes the kept triplets with sigma_i < cutoff * sigma_1 (relative to the
+    largest), on top of the truncation to chi'; checked against numpy's SVD of A_mat B_mat."""
+    rng = np.random.default_rng(40 + chi)
+    p, q, shared = (2, 3), (3, 2), (2, 4)
+    a_mat = rng.normal(size=(6, 8)) * (0.3 ** np.arange(8))      # graded spectrum
+    b_mat = rng.normal(size=(8, 6))
+    caps = [rng.normal(size=d) + 1.0 for d in (*p, *q)]
+    s = np.linalg.svd(a_mat @ b_mat, compute_uv=False)
+    cutoff = 0.0 if cut_between is None else math.sqrt(s[cut_between - 1] * s[cut_between]) / s[0]
+    r, op = _probe_run(a_mat, b_mat, shared, p, q, caps, chi, cutoff)
+    want, k = _probe_value(a_mat, b_mat, caps, chi, cutoff)
+    assert op.new_dim == k
+    assert r.sign == math.copysign(1.0, want)
+    assert abs(r.ln_abs_z - math.log(abs(want))) < 1e-12
+
+
+def test_cutoff_scale_invariance():
+    """The cutoff is relative: scaling A by 1e-30 changes ln|Z| by ln(1e-30) only.  An
+    absolute cutoff would drop every triplet of the scaled network."""
+    rng = np.random.default_rng(9)
+    p, q, shared = (2, 2), (2, 2), (2, 3)
+    a_mat = rng.normal(size=(4, 6)) * (0.1 ** np.arange(6))
+    b_mat = rng.normal(size=(6, 4))
+    caps = [rng.normal(size=2) + 1.0 for _ in range(4)]
+    s = np.linalg.svd(a_mat @ b_mat, compute_uv=False)
+    cutoff = math.sqrt(s[1] * s[2]) / s[0]
+    r1, o1 = _probe_run(a_mat, b_mat, shared, p, q, caps, 3, cutoff)
+    r2, o2 = _probe_run(a_mat * 1e-30, b_mat, shared, p, q, caps, 3, cutoff)
+    assert abs(r2.ln_abs_z - (r1.ln_abs_z + math.log(1e-30))) < 1e-11
+    want, _ = _probe_value(a_mat, b_mat, caps, 3, cutoff)
+    assert abs(r1.ln_abs_z - math.log(abs(want))) < 1e-12
+
+
+def test_cutoff_boundary_value_is_kept():
+    """A singular value exactly equal to cutoff * sigma_1 is kept (only sigma_i < cutoff *
+    sigma_1 is zeroed); one ulp above the boundary drops it.  The core is an exactly
+    representable diagonal, so both sides of the comparison are exact."""
+    a = np.array([1.0, 0.5, 2.0 ** -5, 2.0 ** -9])
+    b = np.array([1.0, 0.5, 2.0 ** -5, 2.0 ** -11])        # sigma = 1, 2^-2, 2^-10, 2^-20
+    caps = [np.array([1.0, 0.75]), np.array([0.5, 1.0]), np.array([1.0, 0.25]), np.array([0.75, 1.0])]
+    args = (np.diag(a), np.diag(b), (2, 2), (2, 2), (2, 2), caps, 3)
+    at, _ = _probe_run(*args, 2.0 ** -10)
+    above, _ = _probe_run(*args, 2.0 ** -10 * (1.0 + 2.0 ** -52))
+    none, _ = _probe_run(*args, 0.0)
+    u = np.kron(caps[0], caps[1])
+    w = np.kron(caps[2], caps[3])
+    sig = a * b
+    assert at.ln_abs_z == pytest.approx(math.log(sum(u[i] * sig[i] * w[i] for i in range(3))), abs=1e-14)
+    assert above.ln_abs_z == pytest.approx(math.log(sum(u[i] * sig[i] * w[i] for i in range(2))), abs=1e-14)
+    assert none.ln_abs_z == at.ln_abs_z
+    assert abs(at.ln_abs_z - above.ln_abs_z) > 1e-4
+
+
+@pytest.mark.parametrize("last,gap,flag", [(0.5, 0.0, True), (0.5, 2.0 ** -41, True), (0.5, 2.0 ** -38, False),
+                                           (0.5, 1e-9, False), (2.0 ** -40, 0.0, True), (2.0 ** -60, 0.0, False)])
+def test_tie_flag_at_truncation_boundary(last, gap, flag):
+    """The tie flag marks sigma_chi' - sigma_chi'+1 <= 1e-12 sigma_1 (several truncations are
+    then equally correct): gaps 0 and 2^-41 ~ 4.5e-13 flag, 2^-38 ~ 3.6e-12 and 1e-9 do not.
+    Equal values at the rounding level (sigma_chi' <= 1e-13 sigma_1, here 2^-60) are no tie;
+    equal values just above it (2^-40 ~ 9.1e-13) are."""
+    sig = np.array([1.0, 0.75, last, last - gap])
+    caps = [np.array([1.0, 0.5]), np.array([0.5, 1.0]), np.array([1.0, 0.25]), np.array([0.75, 1.0])]
+    _, op = _probe_run(np.eye(4), np.diag(sig), (2, 2), (2, 2), (2, 2), caps, 3, 0.0)
+    assert op.tie is flag
+    assert op.discarded == pytest.approx(sig[3] ** 2 / np.sum(sig ** 2), rel=1e-14)
+
+
+def test_cutoff_is_relative_not_absolute():
+    """Factors close to all-ones give a core whose sigma_1 is far above 1 even after every
+    tensor is normalised to max |entry| = 1, so a relative and an absolute reading of the
+    cutoff keep different triplets here; the oracle must follow the relative one."""
+    rng = np.random.default_rng(17)
+    p, q, shared = (2, 2), (2, 2), (2, 3)
+    a_mat = np.ones((4, 6)) + 0.2 * rng.normal(size=(4, 6)) * (0.5 ** np.arange(6))
+    b_mat = np.ones((6, 4)) + 0.2 * rng.normal(size=(6, 4))
+    a_mat /= np.abs(a_mat).max()
+    b_mat /= np.abs(b_mat).max()
+    caps = [rng.uniform(0.5, 1.0, size=2) for _ in range(4)]
+    s = np.linalg.svd(a_mat @ b_mat, compute_uv=False)
+    assert s[0] > 10.0
+    cutoff = math.sqrt(s[1] * s[2]) / s[0]          # relative: keeps 2 of them
+    assert s[2] >= cutoff                             # absolute would keep the third too
+    r, op = _probe_run(a_mat, b_mat, shared, p, q, caps, 3, cutoff)
+    rel, _ = _probe_value(a_mat, b_mat, caps, 3, cutoff)
+    absolute, _ = _probe_value(a_mat, b_mat, caps, 3, cutoff / s[0])
+    assert abs(math.log(abs(rel)) - math.log(abs(absolute))) > 1e-6
+    assert abs(r.ln_abs_z - math.log(abs(rel))) < 1e-12

@@ -171,9 +171,6 @@ def greedy_tree(g: Graph, chi: int, seed: int = 0, temperature: float = 0.25) ->
         a, b = (i, j) if i < j else (j, i)
         heapq.heappush(heap, (score(a, b), a, b, version[a], version[b]))
 
-    for u, v, _ in g.edges:
-        if v not in bonds[u] or u < v:
-            pass
     seen = set()
     for u, v, _ in g.edges:
         if (u, v) not in seen:
