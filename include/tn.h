@@ -268,6 +268,28 @@ tn_status tn_batch_contract(tn_batch* batch, double* mantissas, double* log10_ex
  * the first call and recaptured when the output buffers change. */
 tn_status tn_batch_grad(tn_batch* batch, void* const* dlnz_ddata_dev);
 
+/* ---- One bond compression on its own ------------------------------------
+ * The compression primitive of section II.C, Eq. (svd) (Fig. "tensor
+ * primitives"): two tensors sharing a bond, given as their matricisations
+ * A (m_a x D, row-major) and B (D x m_b, row-major), device float64.  Writes
+ * a' = A P_L (m_a x chi', row-major) and b' = P_R B (chi' x m_b, row-major)
+ * into device float64 buffers a_out (>= m_a * chi' entries) and b_out
+ * (>= chi' * m_b), with P_L = R_B V s^-1/2 and P_R = s^-1/2 U^T R_A (SI B), so
+ * that a' b' is the rank-chi' truncated SVD of A B; chi' = min(chi, k_A, k_B),
+ * k = min(rows, D), goes to *chi_out (host, may be NULL).  `cutoff` zeroes kept
+ * triplets with sigma_i < cutoff * sigma_1, as in tn_tree_opts.  The reduced
+ * factors come from float64 Grams (or the matrix itself when it has <= D
+ * rows) by pivoted Cholesky; the core SVD is a float64 Jacobi.
+ * Limits: 1 <= D <= 64, m_a, m_b >= 1, m_a * D and m_b * D below 2^31.
+ * Work memory is allocated on the device for the call and freed before it
+ * returns; the call runs on ctx's stream and synchronises it.  All buffers
+ * stay owned by the caller.  Errors: TN_EINVAL (shapes, null pointers),
+ * TN_ENOMEM (work memory), TN_ENUMERIC (Jacobi not converged in 40 sweeps),
+ * TN_EDEVICE. */
+tn_status tn_compress_pair(tn_ctx* ctx, const double* a_dev, const double* b_dev, int64_t m_a, int32_t D,
+                           int64_t m_b, int32_t chi, double cutoff, double* a_out, double* b_out,
+                           int32_t* chi_out);
+
 /* Host-only expansion of Algorithm 1 on shapes (no device use): writes up
  * to `cap` ops as 8 int64 each: (kind, a, b, out, m, n, k, new_dim) with
  * kind 0 = contract: (i, j, new id, free size of i, shared size, free size of

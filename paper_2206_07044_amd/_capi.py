@@ -73,6 +73,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_set_tree": ([P, I32, pI32, pI32, C.POINTER(tn_tree_opts)], C.c_int),
         "tn_plan_info": ([P, pI64, pD, pD, pI32], C.c_int),
         "tn_set_workspace": ([P, P, C.c_size_t], C.c_int),
+        "tn_compress_pair": ([P, P, P, I64, I32, I64, I32, D, P, P, pI32], C.c_int),
         "tn_contract_compressed": ([P, pD, pD], C.c_int),
         "tn_result": ([P, pD, pD], C.c_int),
         "tn_enqueue": ([P], C.c_int),
@@ -109,7 +110,7 @@ def exported_symbols() -> List[str]:
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
             "tn_grad_device", "tn_grad_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
             "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
-            "tn_plan_describe"]
+            "tn_plan_describe", "tn_compress_pair"]
 
 
 def _i32(a) -> np.ndarray:
@@ -292,6 +293,15 @@ class Context:
     def tn_ising_coupling_grad_device(self, beta: float, J_ptr: int, dT_ptr: int, dJ_ptr: int) -> None:
         self._check(self._lib.tn_ising_coupling_grad_device(self._h, float(beta), C.c_void_p(J_ptr),
                                                             C.c_void_p(dT_ptr), C.c_void_p(dJ_ptr)))
+
+    def tn_compress_pair(self, a_ptr: int, b_ptr: int, m_a: int, D: int, m_b: int, chi: int, cutoff: float,
+                         a_out_ptr: int, b_out_ptr: int) -> int:
+        """One bond compression of device float64 matrices A (m_a x D) and B (D x m_b); returns chi'."""
+        nw = C.c_int32()
+        self._check(self._lib.tn_compress_pair(self._h, C.c_void_p(a_ptr), C.c_void_p(b_ptr), int(m_a), int(D),
+                                               int(m_b), int(chi), float(cutoff), C.c_void_p(a_out_ptr),
+                                               C.c_void_p(b_out_ptr), C.byref(nw)))
+        return nw.value
 
     def tn_grad_info(self) -> dict:
         f, b, n = C.c_double(), C.c_double(), C.c_int32()

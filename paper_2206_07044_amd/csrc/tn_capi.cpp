@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/tn.h"
+#include "tn_compress.hpp"
 #include "tn_kernels.hpp"
 #include "tn_plan.hpp"
 
@@ -1134,6 +1135,34 @@ tn_status tn_set_workspace(tn_ctx* c, void* dev_ptr, size_t bytes) {
     if (dev_ptr && bytes == 0) return fail(c, TN_EINVAL, "empty workspace");
     c->workspace = (char*)dev_ptr;
     c->workspace_bytes = dev_ptr ? bytes : 0;
+    return TN_OK;
+}
+
+tn_status tn_compress_pair(tn_ctx* c, const double* a_dev, const double* b_dev, int64_t m_a, int32_t D, int64_t m_b,
+                           int32_t chi, double cutoff, double* a_out, double* b_out, int32_t* chi_out) {
+    if (!c) return TN_EINVAL;
+    if (!a_dev || !b_dev || !a_out || !b_out) return fail(c, TN_EINVAL, "null matrix pointer");
+    if (!(cutoff >= 0.0)) return fail(c, TN_EINVAL, "cutoff must be >= 0");
+    PairLayout L;
+    std::string err = pair_layout(m_a, D, m_b, chi, &L);
+    if (!err.empty()) return fail(c, TN_EINVAL, err);
+    (void)hipSetDevice(c->device);
+    char* ws = nullptr;
+    hipError_t e = hipMalloc((void**)&ws, (size_t)L.bytes);
+    if (e != hipSuccess) return fail(c, TN_ENOMEM, std::string("compression workspace: ") + hipGetErrorString(e));
+    PairDescs h;
+    err = pair_enqueue(L, a_dev, b_dev, cutoff, 40, a_out, b_out, ws, &h, c->stream);
+    int32_t sweeps = 0;
+    if (err.empty()) {
+        e = hipMemcpyAsync(&sweeps, ws + L.off_stats + 12, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) err = std::string("stats: ") + hipGetErrorString(e);
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (err.empty() && e != hipSuccess) err = std::string("compression: ") + hipGetErrorString(e);
+    (void)hipFree(ws);
+    if (!err.empty()) return fail(c, TN_EDEVICE, err);
+    if (chi_out) *chi_out = (int32_t)L.nw;
+    if (sweeps < 0) return fail(c, TN_ENUMERIC, "the Jacobi SVD did not converge within the sweep cap");
     return TN_OK;
 }
 

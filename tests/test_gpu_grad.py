@@ -110,6 +110,7 @@ def test_grad_fp32_bound(name, g, T, pairs, chi):
     ref = lnz_and_grad(g.n, g.edges, T, pairs, chi)
     scale = max(float(np.max(np.abs(r))) for r in ref.grads)
     worst = max(float(np.max(np.abs(a - r))) for a, r in zip(grads, ref.grads))
+    print(f"fp32 grad {name}: max |dg| / max |g| = {worst / scale:.2e}", flush=True)
     assert worst <= FP32_GRAD_RTOL * scale
 
 
