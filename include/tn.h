@@ -290,6 +290,22 @@ tn_status tn_compress_pair(tn_ctx* ctx, const double* a_dev, const double* b_dev
                            int64_t m_b, int32_t chi, double cutoff, double* a_out, double* b_out,
                            int32_t* chi_out);
 
+/* Allocation-free variant of tn_compress_pair, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results (bitwise: the
+ * same kernels with the same launch shapes) and errors, but the work memory is
+ * a fixed 32 MiB device array per GPU, held by the library until the process
+ * ends; the call allocates and frees nothing.  32 MiB holds, at D = 64,
+ * about 260000 rows per side (float64 Gram partials of 512-row splits; more
+ * for smaller D); larger inputs fail with TN_EINVAL before any launch.  All calls on
+ * one GPU share that array, and nothing in it needs to start at zero (every
+ * word a call reads it has written first), but calls that overlap in time on
+ * one GPU (from several threads or contexts) race on it: serialise them.  Runs
+ * on ctx's stream and synchronises it before returning. */
+tn_status tn_compress_pair_static(tn_ctx* ctx, const double* a_dev, const double* b_dev, int64_t m_a, int32_t D,
+                                  int64_t m_b, int32_t chi, double cutoff, double* a_out, double* b_out,
+                                  int32_t* chi_out);
+
 /* Host-only expansion of Algorithm 1 on shapes (no device use): writes up
  * to `cap` ops as 8 int64 each: (kind, a, b, out, m, n, k, new_dim) with
  * kind 0 = contract: (i, j, new id, free size of i, shared size, free size of

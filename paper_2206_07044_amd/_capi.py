@@ -74,6 +74,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_plan_info": ([P, pI64, pD, pD, pI32], C.c_int),
         "tn_set_workspace": ([P, P, C.c_size_t], C.c_int),
         "tn_compress_pair": ([P, P, P, I64, I32, I64, I32, D, P, P, pI32], C.c_int),
+        "tn_compress_pair_static": ([P, P, P, I64, I32, I64, I32, D, P, P, pI32], C.c_int),
         "tn_contract_compressed": ([P, pD, pD], C.c_int),
         "tn_result": ([P, pD, pD], C.c_int),
         "tn_enqueue": ([P], C.c_int),
@@ -110,7 +111,7 @@ def exported_symbols() -> List[str]:
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
             "tn_grad_device", "tn_grad_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
             "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
-            "tn_plan_describe", "tn_compress_pair"]
+            "tn_plan_describe", "tn_compress_pair", "tn_compress_pair_static"]
 
 
 def _i32(a) -> np.ndarray:
@@ -301,6 +302,15 @@ class Context:
         self._check(self._lib.tn_compress_pair(self._h, C.c_void_p(a_ptr), C.c_void_p(b_ptr), int(m_a), int(D),
                                                int(m_b), int(chi), float(cutoff), C.c_void_p(a_out_ptr),
                                                C.c_void_p(b_out_ptr), C.byref(nw)))
+        return nw.value
+
+    def tn_compress_pair_static(self, a_ptr: int, b_ptr: int, m_a: int, D: int, m_b: int, chi: int,
+                                cutoff: float, a_out_ptr: int, b_out_ptr: int) -> int:
+        """tn_compress_pair on the library's fixed device scratch (allocates nothing); returns chi'."""
+        nw = C.c_int32()
+        self._check(self._lib.tn_compress_pair_static(self._h, C.c_void_p(a_ptr), C.c_void_p(b_ptr), int(m_a),
+                                                      int(D), int(m_b), int(chi), float(cutoff),
+                                                      C.c_void_p(a_out_ptr), C.c_void_p(b_out_ptr), C.byref(nw)))
         return nw.value
 
     def tn_grad_info(self) -> dict:

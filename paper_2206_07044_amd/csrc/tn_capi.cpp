@@ -13,6 +13,7 @@
 #include "tn_compress.hpp"
 #include "tn_kernels.hpp"
 #include "tn_plan.hpp"
+#include "tn_static.hpp"
 
 using namespace tn;
 
@@ -965,6 +966,11 @@ tn_status tn_create(int device, void* hip_stream, tn_ctx** out) {
             tn_destroy(c);
             return TN_EDEVICE;
         }
+    // the allocation-free entry point's scratch: its address on this device, looked up once
+    if (!static_scratch_init(device).empty()) {
+        tn_destroy(c);
+        return TN_EDEVICE;
+    }
     init_kernel_attrs();
     *out = c;
     return TN_OK;
@@ -1160,6 +1166,38 @@ tn_status tn_compress_pair(tn_ctx* c, const double* a_dev, const double* b_dev, 
     e = hipStreamSynchronize(c->stream);
     if (err.empty() && e != hipSuccess) err = std::string("compression: ") + hipGetErrorString(e);
     (void)hipFree(ws);
+    if (!err.empty()) return fail(c, TN_EDEVICE, err);
+    if (chi_out) *chi_out = (int32_t)L.nw;
+    if (sweeps < 0) return fail(c, TN_ENUMERIC, "the Jacobi SVD did not converge within the sweep cap");
+    return TN_OK;
+}
+
+tn_status tn_compress_pair_static(tn_ctx* c, const double* a_dev, const double* b_dev, int64_t m_a, int32_t D,
+                                  int64_t m_b, int32_t chi, double cutoff, double* a_out, double* b_out,
+                                  int32_t* chi_out) {
+    if (!c) return TN_EINVAL;
+    if (!a_dev || !b_dev || !a_out || !b_out) return fail(c, TN_EINVAL, "null matrix pointer");
+    if (!(cutoff >= 0.0)) return fail(c, TN_EINVAL, "cutoff must be >= 0");
+    PairLayout L;
+    std::string err = pair_layout(m_a, D, m_b, chi, &L);
+    if (!err.empty()) return fail(c, TN_EINVAL, err);
+    if ((size_t)L.bytes > kStaticScratchBytes)
+        return fail(c, TN_EINVAL, "the compression needs " + std::to_string(L.bytes) +
+                                      " bytes of work memory, more than the static scratch of " +
+                                      std::to_string(kStaticScratchBytes));
+    char* ws = (char*)static_scratch(c->device);
+    if (!ws) return fail(c, TN_ESTATE, "no static scratch address for this device");
+    (void)hipSetDevice(c->device);
+    PairDescs h;   // host copy of the descriptors: lives until the synchronisation below
+    err = pair_enqueue(L, a_dev, b_dev, cutoff, 40, a_out, b_out, ws, &h, c->stream);
+    int32_t sweeps = 0;
+    hipError_t e = hipSuccess;
+    if (err.empty()) {
+        e = hipMemcpyAsync(&sweeps, ws + L.off_stats + 12, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) err = std::string("stats: ") + hipGetErrorString(e);
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (err.empty() && e != hipSuccess) err = std::string("compression: ") + hipGetErrorString(e);
     if (!err.empty()) return fail(c, TN_EDEVICE, err);
     if (chi_out) *chi_out = (int32_t)L.nw;
     if (sweeps < 0) return fail(c, TN_ENUMERIC, "the Jacobi SVD did not converge within the sweep cap");
