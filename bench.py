@@ -127,29 +127,106 @@ def roofline_of(kind, prof, avg_ms, launches, precision):
     return "hbm", "GB/s", PEAKS["hbm_GBps"], prof["bytes"] / launches * per_s / 1e9
 
 
-def cpu_baseline(g, T, pairs, chi, total_flops, budget_s):
-    """The CPU oracle on a bounded prefix of the same tree, scaled to trees/s."""
-    import oracle
-    from oracle import approx
+def cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    t0 = time.time()
-    res = approx.contract_compressed_budget(g.n, g.edges, T, pairs, chi, budget_s)
-    dt = time.time() - t0
-    done = sum(op_flops(o) for o in res.ops)
-    rate = done / dt if dt > 0 else 0.0
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, T, pairs, chi, total_flops, budget_s):
+    """The CPU oracle, unmodified, on a bounded sample of the same workload: a fixed prefix of the
+    tree (the steps an all-thread run covers in about budget_s / 8), timed best of 3 with the BLAS
+    library on all host threads and on one thread (the paper's single-core convention), and scaled
+    to trees/s by the algorithmic flops of the prefix against those of the whole tree."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import approx
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    probe = approx.contract_compressed_budget(g.n, g.edges, T, pairs, chi, budget_s / 8)
+    steps = max(1, probe.steps_done)
+    runs = {}
+    for nt in (threads, 1):
+        best, ops = math.inf, []
+        with threadpool_limits(limits=nt, user_api="blas"):
+            for _ in range(3):
+                t0 = time.time()
+                ops = approx.contract_steps(g.n, g.edges, T, pairs, chi, steps)
+                best = min(best, time.time() - t0)
+        done = sum(op_flops(o) for o in ops)
+        runs[nt] = (best, done)
+    dt, done = runs[threads]
+    dt1, _ = runs[1]
+    rate = done / total_flops / dt if dt > 0 and total_flops > 0 else 0.0
     return {
-        "value": rate / total_flops if total_flops > 0 else 0.0,
+        "value": rate,
         "unit": "trees/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"float64 numpy oracle, first {res.steps_done} of {len(pairs)} tree steps "
-                   f"({len(res.ops)} ops, {done:.3e} of {total_flops:.3e} algorithmic flops) in {dt:.1f} s; "
-                   f"trees/s = (flops done / s) / flops per tree"),
+        "single_thread_value": done / total_flops / dt1 if dt1 > 0 and total_flops > 0 else 0.0,
+        "cpu_model": cpu_model(),
+        "sample": (f"float64 numpy oracle, first {steps} of {len(pairs)} tree steps ({done:.3e} of {total_flops:.3e} "
+                   f"algorithmic flops), best of 3: {dt:.2f} s with {threads} BLAS threads, {dt1:.2f} s with 1; "
+                   f"trees/s = (prefix flops / total flops) / seconds"),
     }
+
+
+def timed(c, n, torch, eager=False):
+    """Seconds per evaluation of context c over n back-to-back evaluations (after one untimed)."""
+    c.tn_contract_compressed()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if eager:
+        for _ in range(n):
+            c.tn_contract_compressed()
+    else:
+        for _ in range(n):
+            c.tn_enqueue()
+        c.tn_fetch()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / n
+
+
+def ising_8x8_leg(tn, torch, reps):
+    """The small configuration: 8x8 open-boundary Ising, beta = 0.44, seed-0 Greedy tree, chi 16 and
+    256, float64 in the plain form; latency of one synchronous evaluation and throughput of
+    back-to-back ones, ln|Z| against the stored oracle and transfer-matrix values."""
+    from tninputs import greedy_tree, ising_tensors, lattice
+    g = lattice((8, 8))
+    T = ising_tensors(g, 0.44)
+    pairs = greedy_tree(g, 2, 0)
+    eu, ev, ed, off, data = flat(g, T)
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "ising_8x8.json")) as f:
+            gold = json.load(f)
+    except (OSError, ValueError):
+        gold = None
+    out = {"workload": "ising-square-8x8-beta0.44-greedy-seed0", "precision": "fp64", "form": "plain"}
+    for chi in (16, 256):
+        c = tn.Context(0)
+        c.tn_load_graph(g.n, eu, ev, ed, off, data)
+        c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, precision="fp64", plain=True)
+        c.tn_contract_compressed()
+        lat = math.inf
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            c.tn_contract_compressed()
+            lat = min(lat, time.perf_counter() - t0)
+        per = timed(c, reps, torch)
+        _, lnz = c.tn_result()
+        rec = {"latency_ms": lat * 1e3, "trees_per_s": 1.0 / per, "ln_abs_z": lnz,
+               "compressions": len(c.tn_compress_stats()[0])}
+        if gold:
+            ref = gold["greedy"]["oracle_lnZ"][str(chi)]
+            rec["oracle_ln_abs_z"] = ref
+            rec["rel_dlnz_vs_oracle"] = abs(lnz - ref) / abs(ref)
+            rec["rel_dlnz_vs_transfer_matrix"] = abs(lnz - gold["transfer_matrix_lnZ"]) / gold["transfer_matrix_lnZ"]
+        out[f"chi{chi}"] = rec
+        c.close()
+    return out
 
 
 def main() -> int:
@@ -168,6 +245,7 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=8, help="instances in the batched leg (<= 1: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--per-chi", default="32", help="other chi values timed in fp32 and fp64 ('' to skip)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 8x8 Ising leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -269,26 +347,39 @@ def main() -> int:
                                        "arithmetic_intensity": g_prof["flops"] / g_prof["bytes"] if g_prof["bytes"] else None,
                                        "tflops": g_prof["flops"] / g_prof["ms"] * 1e3 / 1e12 if g_prof["ms"] else None}
 
-    if not args.no_fp64_reference and args.precision != "fp64":
+    if not args.no_fp64_reference:
+        # the same tree in float64: grouped and captured (the library's form), and the plain form
+        # (one launch per step, one stream, no graph), the denominator of the metric
         ref = make_ctx("fp64")
-        ref.tn_contract_compressed()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         nref = max(1, min(args.steps, 3))
-        for _ in range(nref):
-            ref.tn_enqueue()
-        ref.tn_fetch()
-        torch.cuda.synchronize()
-        rdt = time.perf_counter() - t0
+        rdt = timed(ref, nref, torch)
         rs, rl = ref.tn_result()
-        out["fp64_reference"] = {"trees_per_s": nref / rdt, "ln_abs_z": rl, "sign": rs}
+        ref.close()
+        plain = tn.Context(0)
+        plain.tn_load_graph(g.n, eu, ev, ed, off, data)
+        plain.tn_set_tree(pi, pj, args.chi, precision="fp64", plain=True)
+        pdt = timed(plain, 2, torch, eager=True)
+        ps, pl = plain.tn_result()
+        plain.close()
+        out["fp64_reference"] = {"trees_per_s": 1.0 / rdt, "ln_abs_z": rl, "sign": rs, "form": "grouped, captured"}
+        out["fp64_plain"] = {"trees_per_s": 1.0 / pdt, "ms_per_tree": pdt * 1e3, "ln_abs_z": pl,
+                             "bitwise_equal_to_grouped": pl == rl,
+                             "form": "one launch per step on one stream, no graph"}
         orl = oracle_lnz(shape, args.beta, args.chi)
         if orl is not None:
             out["rel_dlnz_vs_oracle"] = {"fp64": abs(rl - orl) / abs(orl), args.precision: abs(lnz - orl) / abs(orl)}
-        out["speedup_vs_fp64"] = trees_per_s / (nref / rdt)
+        out["speedup_vs_fp64"] = trees_per_s * rdt
+        out["speedup_vs_plain_fp64"] = trees_per_s * pdt
         out["abs_dlnz_vs_fp64"] = abs(lnz - rl)
         out["rel_dlnz_vs_fp64"] = abs(lnz - rl) / abs(rl)
-        ref.close()
+        if args.precision != "bf16":
+            bc = make_ctx("bf16")
+            bdt = timed(bc, nref, torch)
+            _, bl = bc.tn_result()
+            bc.close()
+            out["bf16"] = {"trees_per_s": 1.0 / bdt, "ln_abs_z": bl, "abs_dlnz_vs_fp64": abs(bl - rl),
+                           "rel_dlnz_vs_fp64": abs(bl - rl) / abs(rl),
+                           "speedup_vs_plain_fp64": pdt / bdt}
 
     if args.batch > 1:
         # the same lattice and tree at a sweep of beta values (independent instances), merged level by
@@ -370,6 +461,9 @@ def main() -> int:
                           "arena_bytes": ginfo["arena_bytes"], "max_euler_identity_error": euler,
                           "steps": args.fwd_bwd_steps}
         gctx.close()
+
+    if not args.no_small:
+        out["ising_8x8"] = ising_8x8_leg(tn, torch, 5)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, T, pairs, args.chi, info["fwd_flops"], args.cpu_seconds)

@@ -80,6 +80,12 @@ typedef struct {
                                     core workspace and projector stays resident for it, and every
                                     compression takes the Gram + full-spectrum Jacobi core (the
                                     adjoint needs all singular triplets of the core) */
+    int32_t plain;               /* 1: the plain form: every step (contraction, Gram, core,
+                                    re-absorption, scale) is its own kernel launch, issued in order
+                                    on the context's stream on every evaluation, with no grouping,
+                                    no concurrent streams and no graph replay; same kernels and same
+                                    results.  The baseline the grouped, captured form is measured
+                                    against.  Needs grad = 0; not accepted by tn_batch_create */
 } tn_tree_opts;
 
 typedef struct tn_ctx tn_ctx;

@@ -247,6 +247,18 @@ def contract_prefix(n, edges, tensors, pairs, chi, steps: int, cutoff: float = 0
     return rec
 
 
+def contract_steps(n, edges, tensors, pairs, chi, steps: int, cutoff: float = 0.0) -> List[OpRecord]:
+    """Run the first ``steps`` tree steps of the Algorithm 1 loop (nothing recorded) and return
+    the ops they expanded to; a fixed prefix for timing the oracle on a bounded sample."""
+    ops: List[OpRecord] = []
+    box = {"ops": ops}
+    try:
+        _run(n, edges, tensors, pairs, chi, cutoff, False, progress=box, max_steps=steps)
+    except _OutOfTime:
+        pass
+    return box["ops"]
+
+
 @dataclass
 class PartialRun:
     steps_done: int

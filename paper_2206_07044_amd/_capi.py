@@ -32,7 +32,8 @@ class TNError(RuntimeError):
 class tn_tree_opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("cutoff", C.c_double), ("compress_late", C.c_int32),
                 ("gauge_r", C.c_int32), ("precision", C.c_int32), ("jacobi_max_sweeps", C.c_int32),
-                ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("grad", C.c_int32)]
+                ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("grad", C.c_int32),
+                ("plain", C.c_int32)]
 
 
 _lib = None
@@ -123,11 +124,11 @@ def _ptr(a: np.ndarray, ct):
 
 
 def make_opts(chi: int, precision: str = "fp64", cutoff: float = 0.0, max_sweeps: int = 0,
-              budget: int = 0, keep: bool = False, grad: bool = False) -> tn_tree_opts:
+              budget: int = 0, keep: bool = False, grad: bool = False, plain: bool = False) -> tn_tree_opts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     return tn_tree_opts(int(chi), float(cutoff), 0, 0, PRECISIONS[precision], int(max_sweeps), int(budget),
-                        int(bool(keep)), int(bool(grad)))
+                        int(bool(keep)), int(bool(grad)), int(bool(plain)))
 
 
 def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int) -> List[Tuple[int, ...]]:
@@ -205,9 +206,9 @@ class Context:
 
     def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
                     max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False,
-                    grad: bool = False) -> None:
+                    grad: bool = False, plain: bool = False) -> None:
         pi, pj = _i32(pair_i), _i32(pair_j)
-        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad)
+        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad, plain)
         self.state_id += 1
         self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
                                           C.byref(opts)))

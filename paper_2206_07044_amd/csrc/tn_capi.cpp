@@ -608,6 +608,46 @@ tn_status build_launches(tn_ctx* c) {
             c->launches.push_back(l);
         }
     }
+    if (P.opts.plain) {
+        // the plain form: every step of a level is its own launch (one descriptor each), issued in
+        // order on one stream without graph capture, the way a host loop would run the ops
+        std::vector<Launch> split;
+        for (const Launch& l : c->launches) {
+            for (int i = 0; i < l.count; ++i) {
+                Launch x = l;
+                x.begin = l.begin + i;
+                x.count = 1;
+                x.flops = l.flops / l.count;
+                x.bytes = l.bytes / l.count;
+                switch (l.kind) {
+                    case L_GEMM:
+                    case L_SPRE: {
+                        GemmDesc& g = c->h_gemm[x.begin];
+                        g.tile_begin = 0;
+                        x.work = (int64_t)g.tiles_m * g.tiles_n * g.splits;
+                        break;
+                    }
+                    case L_REDUCE: {
+                        ReduceDesc& r = c->h_reduce[x.begin];
+                        r.elem_begin = 0;
+                        x.work = (int64_t)r.M * r.N;
+                        break;
+                    }
+                    case L_COPY: {
+                        CopyDesc& cd = c->h_copy[x.begin];
+                        cd.elem_begin = 0;
+                        x.work = (int64_t)cd.rows * cd.cols;
+                        break;
+                    }
+                    case L_CORE: x.max_d = c->h_core[x.begin].D; break;
+                    case L_LANCZOS: x.max_d = c->h_lanczos[x.begin].s_max; break;
+                    default: break;
+                }
+                split.push_back(x);
+            }
+        }
+        c->launches.swap(split);
+    }
     // inputs
     for (int v = 0; v < c->g.n; ++v) {
         InputDesc d{};
@@ -1101,6 +1141,8 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.budget = opts->device_budget_bytes;
     o.keep = opts->keep_intermediates;
     o.grad = opts->grad ? 1 : 0;
+    o.plain = opts->plain ? 1 : 0;
+    if (o.plain && o.grad) return fail(c, TN_EINVAL, "the plain form has no reverse pass (grad must be 0)");
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
     if (!err.empty()) {
         const bool nomem = err.rfind("plan needs", 0) == 0;
@@ -1282,7 +1324,10 @@ tn_status enqueue_forward(tn_ctx* c) {
     size_t next_ev = 0;
     hipEvent_t pending[2] = {nullptr, nullptr};
     int open = 0;
-    for (size_t b = 0; b < c->launches.size();) {
+    if (P.opts.plain) {   // one launch per step, in schedule order, on the context's stream
+        for (const Launch& l : c->launches) HIP_TRY(c, run(l, s));
+    }
+    for (size_t b = 0; !P.opts.plain && b < c->launches.size();) {
         size_t e = b;
         while (e < c->launches.size() && c->launches[e].level == c->launches[b].level) ++e;
         HIP_TRY(c, run_level(c->launches, b, e, s, c->aux, c->sync_ev, next_ev, run, pending, e < c->launches.size(),
@@ -1301,6 +1346,22 @@ tn_status tn_enqueue(tn_ctx* c) {
     if (!c) return TN_EINVAL;
     if (!c->has_plan) return fail(c, TN_ESTATE, "evaluate before tn_set_tree");
     (void)hipSetDevice(c->device);
+    if (c->plan.opts.plain) {
+        // the plain form is enqueued launch by launch on every evaluation (no graph)
+        if (!c->st_used.empty()) {
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (tn_status st = collect_stamps(c); st != TN_OK) return st;
+        }
+        size_t timed = 0;
+        for (const Launch& l : c->launches) timed += (c->prof_mask >> l.prof) & 1u;
+        if (timed > c->stamps_cap) {
+            dfree(c->d_stamps);
+            c->stamps_cap = 0;
+            HIP_TRY(c, hipMalloc((void**)&c->d_stamps, 2 * timed * sizeof(unsigned long long)));
+            c->stamps_cap = timed;
+        }
+        return enqueue_forward(c);
+    }
     if (!c->fexec || c->fgraph_mask != c->prof_mask) {
         // capture the schedule once (per profiling mask): replays skip the per-launch host work
         free_forward_graph(c);
@@ -1990,6 +2051,8 @@ tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out) {
         if (ctxs[i]->device != dev) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: contexts on different devices");
         if (ctxs[i]->plan.opts.precision != prec)
             return fail(ctxs[i], TN_EINVAL, "tn_batch_create: contexts with different precisions");
+        if (ctxs[i]->plan.opts.plain)
+            return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context planned in the plain form");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context appears twice");
         grad = grad && ctxs[i]->plan.opts.grad;

@@ -32,6 +32,7 @@ struct TreeOpts {
     int64_t budget = 0;
     int32_t keep = 0;               // never reuse arena memory
     int32_t grad = 0;               // plan the reverse pass too
+    int32_t plain = 0;              // one launch per step, no streams, no graph (the plain form)
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).

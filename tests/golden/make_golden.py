@@ -3,7 +3,8 @@
     python tests/golden/make_golden.py [--big]
 
 ising_8x8.json   : 8x8 open-boundary Ising, beta=0.44 — transfer-matrix ln Z and the oracle's
-                   ln|Z| for chi in {4, 8, 16, 256} along the sweep tree (section II.F, SI F.1).
+                   ln|Z| for chi in {4, 8, 16, 256} along the sweep tree (section II.F, SI F.1),
+                   and for chi in {16, 256} along the seed-0 Greedy tree.
 cubic_12.json    : 12x12x12 Ising, beta=0.22, chi=16, sweep tree (--big, ~10 min of CPU):
                    the oracle's ln|Z| and its spread when one input tensor is perturbed at the
                    1e-15 level (the conditioning of this workload; see the design notes).
@@ -26,7 +27,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
 from oracle import exact  # noqa: E402
-from tninputs import ising_tensors, lattice  # noqa: E402
+from tninputs import greedy_tree, ising_tensors, lattice  # noqa: E402
 from tninputs.trees import sweep_tree  # noqa: E402
 
 
@@ -38,6 +39,14 @@ def ising_8x8():
            "transfer_matrix_lnZ": exact.ising_transfer_matrix((8, 8), 0.44), "oracle_lnZ": {}}
     for chi in (4, 8, 16, 256):
         out["oracle_lnZ"][str(chi)] = oracle.contract_compressed(g.n, g.edges, T, p, chi).ln_abs_z
+    # the Greedy tree of the 8x8 workload: seed 0, scored with a simulated bond dimension of 2
+    # (SI C.1's chi_greedy), so that bonds above 16 appear and chi = 16 compresses
+    pg = greedy_tree(g, 2, 0)
+    out["greedy"] = {"tree": "greedy_tree(g, 2, 0)", "oracle_lnZ": {}, "compressions": {}}
+    for chi in (16, 256):
+        r = oracle.contract_compressed(g.n, g.edges, T, pg, chi)
+        out["greedy"]["oracle_lnZ"][str(chi)] = r.ln_abs_z
+        out["greedy"]["compressions"][str(chi)] = sum(o.kind == "compress" for o in r.ops)
     return out
 
 

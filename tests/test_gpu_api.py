@@ -136,3 +136,30 @@ def test_autograd_backward_after_a_second_forward():
     assert not np.allclose(ga, gb)
     want = oracle.contract_compressed(g.n, g.edges, ising_tensors(g, beta, J1), pairs, chi)
     assert abs(la.item() - want.ln_abs_z) < 1e-10 * abs(want.ln_abs_z)
+
+
+@pytest.mark.parametrize("shape,chi,precision", [((5, 5, 5), 8, "fp64"), ((8, 8), 16, "fp64"), ((6, 6, 6), 16, "fp64"),
+                                                 ((4, 4, 4), 8, "fp32")])
+def test_plain_form_equals_grouped_form(shape, chi, precision):
+    """The plain form (one launch per step, one stream, no graph) runs the same kernels on the
+    same descriptors as the grouped, captured form, so its result is bitwise the same."""
+    g = lattice(shape)
+    T = ising_tensors(g, 0.22 if len(shape) == 3 else 0.44)
+    pi, pj = _pairs(shape)
+    c = tn.Context(0)
+    try:
+        _load(c, g, T)
+        c.tn_set_tree(pi, pj, chi, precision=precision)
+        ref = c.tn_contract_compressed()
+        c.tn_set_tree(pi, pj, chi, precision=precision, plain=True)
+        got = [c.tn_contract_compressed() for _ in range(2)]
+        assert got[0] == ref and got[1] == ref
+        with pytest.raises(TNError) as ei:
+            c.tn_set_tree(pi, pj, chi, plain=True, grad=True)
+        assert ei.value.status == TN_EINVAL
+        c.tn_set_tree(pi, pj, chi, precision=precision, plain=True)
+        with pytest.raises(TNError) as ei:
+            tn.Batch([c])
+        assert ei.value.status == TN_EINVAL
+    finally:
+        c.close()
