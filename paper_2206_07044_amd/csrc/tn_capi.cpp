@@ -12,6 +12,7 @@
 #include "../../include/tn.h"
 #include "tn_compress.hpp"
 #include "tn_kernels.hpp"
+#include "tn_krylov.hpp"
 #include "tn_plan.hpp"
 #include "tn_static.hpp"
 
@@ -20,7 +21,8 @@ using namespace tn;
 namespace {
 
 // L_SPRE: the float64 products that form a Gram-Lanczos operator (key 0: T1, key 1: S = F_X T1)
-enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD, L_SPRE };
+// L_KRYLOV: the block-Krylov chains of a level (begin/count index the chain steps, KOp)
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD, L_SPRE, L_KRYLOV };
 
 struct Launch {
     int kind = 0;
@@ -39,6 +41,15 @@ constexpr int kKinds = 12;   // >= number of tn_kernel_kind values
 constexpr int kLanes = 4;    // streams per level: tensor GEMMs + scales, cores, Lanczos, Gram GEMMs + copies
 
 }  // namespace
+
+// Arena above which a plan is levelled in tree order (a third of an MI355X's 288 GB).
+constexpr int64_t kArenaSoftCap = (int64_t)96 << 30;
+// Forward schedules of more kernel launches than this are enqueued launch by launch on every
+// evaluation instead of being captured into a hipGraph: a capture of some 230,000 launches (the
+// 12^3 chi = 64 tree, ~1,700 block-Jacobi cores of up to 272 launches each) ended the process
+// inside the runtime, while captures of up to ~11,000 launches run; such schedules are bound by
+// their kernels, not by launch overhead, so replay gains nothing there.
+constexpr int64_t kMaxCaptureKernels = 20000;
 
 struct tn_ctx {
     int device = 0;
@@ -76,7 +87,16 @@ struct tn_ctx {
     LanczosDesc* d_lanczos = nullptr;
     std::vector<GLanczosDesc> h_glanczos;
     GLanczosDesc* d_glanczos = nullptr;
+    // block-Krylov chains: their steps, and the small-operation and block-factor descriptors
+    std::vector<KOp> h_kops;
+    std::vector<SmallDesc> h_small;
+    SmallDesc* d_small = nullptr;
+    std::vector<CholInvDesc> h_chol;
+    CholInvDesc* d_chol = nullptr;
+    std::vector<KrylovCheckDesc> h_kcheck;
+    KrylovCheckDesc* d_kcheck = nullptr;
     std::vector<Launch> launches;
+    int64_t n_kernels = 0;            // kernel launches of one forward evaluation
     GemmDesc* d_gemm = nullptr;
     CopyDesc* d_copy = nullptr;
     CoreDesc* d_core = nullptr;
@@ -177,6 +197,13 @@ void free_plan(tn_ctx* c) {
     dfree(c->d_inputs);
     dfree(c->d_lanczos);
     dfree(c->d_glanczos);
+    dfree(c->d_small);
+    dfree(c->d_chol);
+    dfree(c->d_kcheck);
+    c->h_kcheck.clear();
+    c->h_kops.clear();
+    c->h_small.clear();
+    c->h_chol.clear();
     dfree(c->d_scales);
     dfree(c->d_maxparts);
     dfree(c->d_disc);
@@ -220,7 +247,9 @@ std::string fill_view(const ViewSpec& s, View* v) { return make_view(s, v); }
 // GEMMs: they need a whole compute unit each, which a GEMM launch issued first would occupy
 // until its workgroups drain.  Stable: the order inside each stream is kept.
 void order_for_issue(std::vector<Launch>& ls) {
-    auto first = [](const Launch& l) { return l.kind == L_CORE || l.kind == L_LANCZOS || l.kind == L_GLANCZOS; };
+    auto first = [](const Launch& l) {
+        return l.kind == L_CORE || l.kind == L_LANCZOS || l.kind == L_GLANCZOS || l.kind == L_KRYLOV;
+    };
     std::stable_sort(ls.begin(), ls.end(), [&](const Launch& a, const Launch& b) {
         if (a.level != b.level) return a.level < b.level;
         return first(a) && !first(b);
@@ -246,6 +275,8 @@ tn_status build_launches(tn_ctx* c) {
         std::vector<LanczosDesc> lanczos;
         std::vector<GLanczosDesc> glanczos;
         std::pair<double, double> glanczos_work{0, 0};
+        std::vector<int32_t> krylov_steps;
+        std::pair<double, double> krylov_work{0, 0};
         std::pair<double, double> lanczos_work{0, 0};
         int lanczos_smax = 1;
         std::vector<ScaleDesc> scales;
@@ -423,6 +454,10 @@ tn_status build_launches(tn_ctx* c) {
                 lanczos.push_back(ld);
                 lanczos_work.first += st.flops;
                 lanczos_work.second += st.bytes;
+            } else if (st.kind == ST_KRYLOV) {
+                krylov_steps.push_back(si);
+                krylov_work.first += st.flops;
+                krylov_work.second += st.bytes;
             } else if (st.kind == ST_CORE && P.comps[st.comp].glanczos) {
                 const Compression& cp = P.comps[st.comp];
                 GLanczosDesc gd;
@@ -597,6 +632,58 @@ tn_status build_launches(tn_ctx* c) {
             for (auto& gd : glanczos) c->h_glanczos.push_back(gd);
             c->launches.push_back(l);
         }
+        if (!krylov_steps.empty()) {
+            // one chain per group of same-shape compressions (per compression in the plain form)
+            std::map<std::vector<int64_t>, std::vector<KrylovJob>> groups;
+            std::map<std::vector<int64_t>, KrylovShape> shapes;
+            for (int32_t si : krylov_steps) {
+                const Step& st = P.steps[si];
+                const Compression& cp = P.comps[st.comp];
+                KrylovShape sh;
+                sh.n = cp.kr_n;
+                sh.D = cp.D;
+                sh.my = cp.kr_my;
+                sh.nw = cp.chi_new;
+                sh.b = cp.kr_b;
+                sh.s = cp.kr_s;
+                sh.k = cp.kr_k;
+                sh.full = cp.kr_full;
+                sh.splits = cp.kr_splits;
+                sh.splits2 = cp.kr_splits2;
+                KrylovJob job;
+                std::string err = fill_view(st.va, &job.vy);
+                if (err.empty()) err = fill_view(st.vb, &job.vyt);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                job.fx = (const double*)buf_ptr(cp.x_is_b ? cp.side_b_buf : cp.side_a_buf);
+                job.y = ten_ptr(st.in_a);
+                job.y_scale = st.in_a;
+                job.ws = buf_ptr(cp.work_buf);
+                job.p_left = buf_ptr(cp.pl_buf);
+                job.p_right = buf_ptr(cp.pr_buf);
+                job.x_is_b = cp.x_is_b;
+                job.stat = st.comp;
+                job.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
+                job.cutoff = P.opts.cutoff;
+                std::vector<int64_t> key = {sh.n, sh.D, sh.my, sh.nw, sh.b, sh.s, sh.k, sh.full, sh.splits, sh.splits2};
+                if (P.opts.plain) key.push_back(si);
+                groups[key].push_back(job);
+                shapes[key] = sh;
+            }
+            Launch l;
+            l.level = L;
+            l.kind = L_KRYLOV;
+            l.prof = TN_KERNEL_LANCZOS;
+            l.flops = krylov_work.first;
+            l.bytes = krylov_work.second;
+            l.begin = (int64_t)c->h_kops.size();
+            KrylovSink sink{&c->h_gemm, &c->h_reduce, &c->h_small, &c->h_chol, &c->h_core, &c->h_kcheck, &c->h_kops};
+            for (auto& kv : groups) {
+                std::string err = krylov_chain(shapes[kv.first], prec, kv.second, sink);
+                if (!err.empty()) return fail(c, TN_EINVAL, "block-Krylov chain: " + err);
+            }
+            l.count = (int)((int64_t)c->h_kops.size() - l.begin);
+            c->launches.push_back(l);
+        }
         if (!scales.empty()) {
             Launch l;
             l.level = L;
@@ -666,6 +753,9 @@ tn_status build_launches(tn_ctx* c) {
     if ((s = upload(c, &c->d_lanczos, c->h_lanczos)) != TN_OK) return s;
     if ((s = upload(c, &c->d_glanczos, c->h_glanczos)) != TN_OK) return s;
     if ((s = upload(c, &c->d_reduce, c->h_reduce)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_small, c->h_small)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_chol, c->h_chol)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_kcheck, c->h_kcheck)) != TN_OK) return s;
     HIP_TRY(c, hipMalloc((void**)&c->d_scales, std::max<size_t>(1, P.tens.size()) * sizeof(double)));
     HIP_TRY(c, hipMalloc((void**)&c->d_maxparts, (size_t)max_parts * sizeof(double)));
     const size_t nc = std::max<size_t>(1, P.comps.size());
@@ -675,6 +765,16 @@ tn_status build_launches(tn_ctx* c) {
     HIP_TRY(c, hipMemset(c->d_sweeps, 0, nc * sizeof(int32_t)));
     P.max_parts = max_parts;
     order_for_issue(c->launches);
+    // kernel launches per evaluation (the capture budget)
+    c->n_kernels = 2 + (int64_t)c->launches.size();
+    for (const Launch& l : c->launches) {
+        if (l.kind == L_CORE) c->n_kernels += core_launch_count(l.key, l.max_d, P.opts.jacobi_max_sweeps) - 1;
+        if (l.kind == L_KRYLOV)
+            for (int64_t i = l.begin; i < l.begin + l.count; ++i)
+                c->n_kernels += c->h_kops[i].kind == KO_CORE
+                                    ? core_launch_count(c->h_kops[i].key, c->h_kops[i].max_d, P.opts.jacobi_max_sweeps)
+                                    : 1;
+    }
     return TN_OK;
 }
 
@@ -849,7 +949,8 @@ int lane_of(const Launch& l) {
         case L_SCALE: return 0;
         case L_CORE: return 1;
         case L_LANCZOS:
-        case L_GLANCZOS: return 2;
+        case L_GLANCZOS:
+        case L_KRYLOV: return 2;
         default: return 3;
     }
 }
@@ -875,7 +976,7 @@ hipError_t run_level(const std::vector<Launch>& ls, size_t b, size_t e, hipStrea
     bool lane2_glanczos = true;
     for (size_t i = b; i < e; ++i) {
         used |= 1 << lane_of(ls[i]);
-        if (lane_of(ls[i]) == 2 && ls[i].kind != L_GLANCZOS) lane2_glanczos = false;
+        if (lane_of(ls[i]) == 2 && ls[i].kind != L_GLANCZOS && ls[i].kind != L_KRYLOV) lane2_glanczos = false;
     }
     auto event = [&](hipEvent_t* out) -> hipError_t {
         if (next_ev == events.size()) {
@@ -1144,6 +1245,14 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.plain = opts->plain ? 1 : 0;
     if (o.plain && o.grad) return fail(c, TN_EINVAL, "the plain form has no reverse pass (grad must be 0)");
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
+    // level by level every independent branch advances at once; when that holds more than the
+    // budget (or, without one, more than a third of the device), plan again with the levels in
+    // tree order, which needs only the memory of a sequential run
+    const int64_t soft_cap = o.budget > 0 ? o.budget : kArenaSoftCap;
+    if (err.empty() && c->plan.arena_bytes > soft_cap) {
+        o.ordered = 1;
+        err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
+    }
     if (!err.empty()) {
         const bool nomem = err.rfind("plan needs", 0) == 0;
         return fail(c, nomem ? TN_ENOMEM : TN_EINVAL, err);
@@ -1317,6 +1426,25 @@ tn_status enqueue_forward(tn_ctx* c) {
             case L_SPRE:
                 err = launch_gemm(GEMM_F64, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
                 break;
+            case L_KRYLOV:
+                for (int64_t i = l.begin; i < l.begin + l.count && err == hipSuccess; ++i) {
+                    const KOp& o = c->h_kops[i];
+                    switch (o.kind) {
+                        case KO_GEMM:
+                            err = launch_gemm(o.key, c->d_gemm + o.begin, o.count, o.work, c->d_scales, c->d_maxparts,
+                                              st);
+                            break;
+                        case KO_REDUCE: err = launch_reduce(0, c->d_reduce + o.begin, o.count, o.work, c->d_scales, st); break;
+                        case KO_SMALL: err = launch_small(o.key, c->d_small + o.begin, o.count, o.work, st); break;
+                        case KO_CHOL: err = launch_cholinv(c->d_chol + o.begin, o.count, st); break;
+                        case KO_CORE:
+                            err = launch_core(o.key, 0, c->d_core + o.begin, o.count, o.max_d, P.opts.jacobi_max_sweeps,
+                                              c->d_disc, c->d_tie, c->d_sweeps, st);
+                            break;
+                        case KO_CHECK: err = launch_krylov_check(c->d_kcheck + o.begin, o.count, c->d_sweeps, st); break;
+                    }
+                }
+                break;
         }
         if (err == hipSuccess && timed) err = launch_stamp(c->d_stamps + 2 * pair + 1, st);
         return err;
@@ -1346,8 +1474,9 @@ tn_status tn_enqueue(tn_ctx* c) {
     if (!c) return TN_EINVAL;
     if (!c->has_plan) return fail(c, TN_ESTATE, "evaluate before tn_set_tree");
     (void)hipSetDevice(c->device);
-    if (c->plan.opts.plain) {
-        // the plain form is enqueued launch by launch on every evaluation (no graph)
+    if (c->plan.opts.plain || c->n_kernels > kMaxCaptureKernels) {
+        // the plain form, and schedules too long to capture, are enqueued launch by launch on every
+        // evaluation (no graph)
         if (!c->st_used.empty()) {
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             if (tn_status st = collect_stamps(c); st != TN_OK) return st;
@@ -1431,7 +1560,10 @@ tn_status tn_fetch(tn_ctx* c) {
     // only a finished evaluation counts: tn_result and tn_grad refuse a failed one
     c->evaluated = false;
     if (c->flags & 2) return fail(c, TN_ENUMERIC, "non-finite tensor entry");
-    if (c->flags & 4) return fail(c, TN_ENUMERIC, "a Jacobi SVD did not converge within the sweep cap");
+    if (c->flags & 4)
+        return fail(c, TN_ENUMERIC,
+                    "a compression did not converge (Jacobi sweep cap, or a block-Krylov basis too small for a flat "
+                    "core spectrum)");
     c->evaluated = true;
     if ((c->flags & 1) || c->sign == 0.0) {
         c->sign = 0.0;
@@ -2053,6 +2185,8 @@ tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out) {
             return fail(ctxs[i], TN_EINVAL, "tn_batch_create: contexts with different precisions");
         if (ctxs[i]->plan.opts.plain)
             return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context planned in the plain form");
+        if (!ctxs[i]->h_kops.empty())
+            return fail(ctxs[i], TN_EINVAL, "tn_batch_create: block-Krylov compressions are not merged into batches");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context appears twice");
         grad = grad && ctxs[i]->plan.opts.grad;

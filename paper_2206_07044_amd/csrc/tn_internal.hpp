@@ -19,7 +19,7 @@
 
 namespace tn {
 
-constexpr int kMaxLegs = 10;
+constexpr int kMaxLegs = 16;
 
 // 32-bit division by a runtime constant via multiply-high (round-up method):
 // q = (umulhi(n, mul) + n) >> shr, exact for n < 2^31 and 1 <= d < 2^31.
@@ -185,6 +185,55 @@ struct GLanczosDesc {
     int32_t splits_y, x_is_b;    // x_is_b: X is the B side (operator M^T M), else A (M M^T)
     int32_t s_min, s_max;
     int32_t stat, kmin;
+};
+
+// Small dense float64 operations of the block-Krylov compressions (one thread per element of
+// the destination).
+enum SmallOp : int32_t {
+    SM_RANDOM = 0,     // dst = uniform in [-1, 1) from a counter-based hash of (seed, element)
+    SM_COPY = 1,       // dst = src (transposed if `transpose`)
+    SM_NEG = 2,        // dst = -src (in place allowed)
+    SM_SYM = 3,        // dst (square) = (dst + dst^T) / 2, in place
+    SM_COLNORM2 = 4,   // dst[0, c] = sum over src_rows rows of src[r, c]^2
+    SM_COLSCALE = 5,   // dst[r, c] *= src[c]
+    SM_IDENTITY = 6,   // dst = I
+    SM_CAST = 7,       // dst (tensor dtype of the launch) = src (transposed if `transpose`)
+};
+
+struct SmallDesc {
+    const double* src;
+    void* dst;
+    int64_t elem_begin;          // first linear element of this op in the grouped launch
+    int32_t rows, cols;          // the destination's shape
+    int32_t src_ld, dst_ld;      // row strides in elements
+    int32_t op;                  // SmallOp
+    int32_t transpose;
+    uint32_t seed;
+    int32_t src_rows;            // COLNORM2
+};
+
+// Convergence check of a block-Krylov compression's kept Ritz pairs: with QP = Z s^-1/2 (Z the
+// Ritz vectors), nrm[i] = 1 / s_i (0 for a masked pair) and E = F_X P_Y = S Z s^-3/2, the
+// residual of pair i is ||S z_i - s_i^2 z_i|| = ||E_i - s_i QP_i|| s_i^(3/2); a pair whose
+// residual exceeds tol * s_1^2 marks the compression as not converged.
+struct KrylovCheckDesc {
+    const double* e;             // n x nw
+    const double* qp;            // n x nw
+    const double* nrm;           // nw
+    int32_t n, nw;
+    int32_t stat;
+    int32_t pad;
+    double tol;
+};
+
+// Orthonormalising factor of a block of b <= 64 columns from its Gram G = W^T W: pivoted
+// Cholesky P^T G P = R^T R stopped at pivots <= 1e-14 of the largest diagonal entry, and
+// M = P R^-1 (zero columns beyond the rank), so that W M has orthonormal columns.
+struct CholInvDesc {
+    const double* g;             // b x b, row-major
+    double* m;                   // b x b, row-major
+    int32_t b;
+    int32_t pad;
 };
 
 // Upload of one input tensor: float64 staging -> arena (converted to the tensor dtype).

@@ -17,6 +17,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "tn_internal.hpp"
 #include "tn_kernels.hpp"
 
@@ -130,16 +132,18 @@ __device__ inline double wave_max(double v) {
 // ------------------------------------------------------------------------------------------
 constexpr int kBM = 64, kBN = 64, kBK = 16, kGemmThreads = 256;
 
-template <typename Tin, typename Tc, typename Tout>
+// TinB: element type of B (the same as A's except for the block-Krylov passes, where a float32 or
+// bfloat16 tensor meets float64 vectors and the product is formed in float64)
+template <typename Tin, typename Tc, typename Tout, typename TinB = Tin>
 __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __restrict__ descs, int ndesc,
                                                              const double* __restrict__ scales,
-                                                             double* __restrict__ maxparts) {
+                                                             double* __restrict__ maxparts, int64_t tile0) {
     __shared__ Tc As[kBK][kBM + 2];
     __shared__ Tc Bs[kBK][kBN + 2];
     __shared__ double wmax[kGemmThreads / 64];
 
     const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = tile0 + blockIdx.x;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     const int k_end = min(K, k_begin + d.k_per_split);
 
     const Tin* __restrict__ A = (const Tin*)d.A;
-    const Tin* __restrict__ B = (const Tin*)d.B;
+    const TinB* __restrict__ B = (const TinB*)d.B;
 
     // per-thread fixed coordinates of the 4 A and 4 B elements it stages
     const bool a_mfast = d.va.row_unit != 0;
@@ -317,12 +321,12 @@ constexpr int kGramThreads = 256, kGramKC = 32;
 
 template <typename Tin>
 __global__ __launch_bounds__(kGramThreads) void gram_narrow_grouped(const GemmDesc* __restrict__ descs, int ndesc,
-                                                                   const double* __restrict__ scales) {
+                                                                   const double* __restrict__ scales, int64_t tile0) {
     __shared__ double Xs[2][kGramKC][65];
     __shared__ uint32_t koff[2][kGramKC];
     __shared__ uint32_t doff[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = tile0 + blockIdx.x;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -446,8 +450,8 @@ __global__ __launch_bounds__(kGramThreads) void gram_narrow_grouped(const GemmDe
 // ------------------------------------------------------------------------------------------
 template <typename Tin>
 __global__ __launch_bounds__(256) void copy_grouped(const CopyDesc* __restrict__ descs, int ndesc,
-                                                    const double* __restrict__ scales, int64_t total) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const double* __restrict__ scales, int64_t total, int64_t e0) {
+    const int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
@@ -2224,7 +2228,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
 
     double* S = d.work;                          // n x n operator F_X G_Y F_X^T
     double* T1 = S + (int64_t)n * n;             // D x n (G_Y F_X^T) or n x my (F_X F_Y^T)
-    double* Q = T1 + (int64_t)max(D, d.my) * n;  // n x s_max Lanczos basis
+    double* Q = T1 + (int64_t)min(D, d.my) * n;  // n x s_max Lanczos basis (T1 holds min(D, m_y) x n)
     double* Wt = Q + (int64_t)n * sm;            // n x cn Ritz vectors
     double* t1 = Wt + (int64_t)n * cn;           // D
     double* t2 = t1 + D;                         // D
@@ -2571,35 +2575,68 @@ hipError_t by_prec(int prec, F&& f) {
     return hipGetLastError();
 }
 
+// A dispatch holds at most 2^32 - 1 work-items per dimension: grids beyond kMaxGridBlocks
+// workgroups (of up to 256 work-items) are issued as several launches over consecutive ranges.
+constexpr int64_t kMaxGridBlocks = (int64_t)1 << 23;
+
 hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
                        double* maxparts, hipStream_t s) {
     if (ndesc == 0 || tiles == 0) return hipSuccess;
-    dim3 grid((unsigned)tiles), block(kGemmThreads);
-    switch (dtype_key) {
-        case GEMM_F64: gemm_grouped<double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
-        case GEMM_F32: gemm_grouped<float, float, float><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
-        case GEMM_F32_TO_F64: gemm_grouped<float, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
-        case GEMM_BF16: gemm_grouped<bf16, bf16, bf16><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
-        case GEMM_BF16_TO_F64: gemm_grouped<bf16, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts); break;
-        case GEMM_GRAM_NARROW_F64:
-            gram_narrow_grouped<double><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales);
-            break;
-        case GEMM_GRAM_NARROW_F32:
-            gram_narrow_grouped<float><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales);
-            break;
-        case GEMM_GRAM_NARROW_BF16:
-            gram_narrow_grouped<bf16><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales);
-            break;
-        default: return hipErrorInvalidValue;
+    for (int64_t t0 = 0; t0 < tiles; t0 += kMaxGridBlocks) {
+        const dim3 grid((unsigned)std::min<int64_t>(kMaxGridBlocks, tiles - t0)), block(kGemmThreads);
+        switch (dtype_key) {
+            case GEMM_F64:
+                gemm_grouped<double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_F32:
+                gemm_grouped<float, float, float><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_F32_TO_F64:
+                gemm_grouped<float, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_BF16:
+                gemm_grouped<bf16, bf16, bf16><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_BF16_TO_F64:
+                gemm_grouped<bf16, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_F32_X_F64:
+                gemm_grouped<float, double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_BF16_X_F64:
+                gemm_grouped<bf16, double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_GRAM_NARROW_F64:
+                gram_narrow_grouped<double><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales, t0);
+                break;
+            case GEMM_GRAM_NARROW_F32:
+                gram_narrow_grouped<float><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales, t0);
+                break;
+            case GEMM_GRAM_NARROW_BF16:
+                gram_narrow_grouped<bf16><<<grid, dim3(kGramThreads), 0, s>>>(descs, ndesc, scales, t0);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
+
+// Elementwise grouped kernels take an element offset e0 for the same reason (256 work-items each).
+constexpr int64_t kMaxGridElems = kMaxGridBlocks * 256;
 
 hipError_t launch_copy(int prec, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
                        hipStream_t s) {
     if (ndesc == 0 || total == 0) return hipSuccess;
-    dim3 grid((unsigned)((total + 255) / 256)), block(256);
-    return by_prec(prec, [&](auto t) { copy_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total); });
+    for (int64_t e0 = 0; e0 < total; e0 += kMaxGridElems) {
+        const dim3 grid((unsigned)((std::min(kMaxGridElems, total - e0) + 255) / 256)), block(256);
+        const hipError_t e = by_prec(prec, [&](auto t) {
+            copy_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total, e0);
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2609,8 +2646,8 @@ hipError_t launch_copy(int prec, const CopyDesc* descs, int ndesc, int64_t total
 // normally carries the factor already, and f = 1).
 template <typename Tout>
 __global__ __launch_bounds__(256) void reduce_grouped(const ReduceDesc* __restrict__ descs, int ndesc,
-                                                      const double* __restrict__ scales, int64_t total) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                      const double* __restrict__ scales, int64_t total, int64_t e0) {
+    const int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
@@ -3031,6 +3068,13 @@ hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int 
     });
 }
 
+int core_launch_count(int lds, int max_d, int max_sweeps) {
+    if (lds || max_d <= 64 || max_d > kBJRows) return 1;
+    int nb = (max_d + kBJCols - 1) / kBJCols;
+    nb += nb & 1;
+    return 2 + std::min(kBJSweeps, max_sweeps) * (nb - 1);
+}
+
 size_t lanczos_lds_bytes(int s_max) { return (size_t)2 * (s_max + 1) * (s_max + 1) * sizeof(double); }
 
 hipError_t launch_lanczos(int prec, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
@@ -3079,8 +3123,14 @@ hipError_t launch_inputs(int prec, const InputDesc* descs, int n, const double* 
 hipError_t launch_reduce(int prec, const ReduceDesc* descs, int ndesc, int64_t total, const double* scales,
                          hipStream_t s) {
     if (ndesc == 0 || total == 0) return hipSuccess;
-    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
-    return by_prec(prec, [&](auto t) { reduce_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total); });
+    for (int64_t e0 = 0; e0 < total; e0 += kMaxGridElems) {
+        const dim3 grid((unsigned)((std::min(kMaxGridElems, total - e0) + 255) / 256)), block(256);
+        const hipError_t e = by_prec(prec, [&](auto t) {
+            reduce_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, scales, total, e0);
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_core_bwd(int prec, const CoreBwdDesc* descs, int ndesc, int max_d, hipStream_t s) {
@@ -3112,6 +3162,205 @@ hipError_t launch_grad_inputs(int prec, const InputDesc* descs, int n, const dou
     if (n == 0) return hipSuccess;
     const dim3 grid((unsigned)((n * 64 + 255) / 256)), block(256);
     return by_prec(prec, [&](auto t) { grad_inputs_kernel<decltype(t)><<<grid, block, 0, s>>>(descs, n, scales, out); });
+}
+
+// ------------------------------------------------------------------------------------------
+// Block-Krylov compressions: small dense float64 operations and the orthonormalising factor of
+// a block (the products themselves run on gemm_grouped)
+// ------------------------------------------------------------------------------------------
+
+// SplitMix64 finaliser (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+// OOPSLA 2014): a counter-based generator for the Krylov start blocks.
+__device__ inline double hash_uniform(uint32_t seed, uint64_t i) {
+    uint64_t z = ((uint64_t)seed << 32) ^ i;
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;   // 53 bits -> [-1, 1)
+}
+
+template <typename Tp>
+__global__ __launch_bounds__(256) void small_grouped(const SmallDesc* __restrict__ descs, int ndesc,
+                                                     int64_t total, int64_t e0) {
+    const int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].elem_begin <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const SmallDesc& d = descs[lo];
+    const int64_t local = e - d.elem_begin;
+    const int r = (int)(local / d.cols), c = (int)(local - (int64_t)r * d.cols);
+    double* dst = (double*)d.dst;
+    const int64_t o = (int64_t)r * d.dst_ld + c;
+    switch (d.op) {
+        case SM_RANDOM: dst[o] = hash_uniform(d.seed, (uint64_t)local); break;
+        case SM_COPY:
+            dst[o] = d.transpose ? d.src[(int64_t)c * d.src_ld + r] : d.src[(int64_t)r * d.src_ld + c];
+            break;
+        case SM_NEG: dst[o] = -d.src[(int64_t)r * d.src_ld + c]; break;
+        case SM_SYM:
+            if (r < c) {
+                const int64_t t = (int64_t)c * d.dst_ld + r;
+                const double v = 0.5 * (dst[o] + dst[t]);
+                dst[o] = v;
+                dst[t] = v;
+            }
+            break;
+        case SM_COLNORM2: {
+            double acc = 0.0;
+            for (int t = 0; t < d.src_rows; ++t) {
+                const double v = d.src[(int64_t)t * d.src_ld + c];
+                acc = fma(v, v, acc);
+            }
+            dst[o] = acc;
+            break;
+        }
+        case SM_COLSCALE: dst[o] *= d.src[c]; break;
+        case SM_IDENTITY: dst[o] = r == c ? 1.0 : 0.0; break;
+        case SM_CAST: {
+            const double v = d.transpose ? d.src[(int64_t)c * d.src_ld + r] : d.src[(int64_t)r * d.src_ld + c];
+            ((Tp*)d.dst)[o] = (Tp)v;
+            break;
+        }
+    }
+}
+
+hipError_t launch_small(int prec, const SmallDesc* descs, int ndesc, int64_t total, hipStream_t s) {
+    if (ndesc == 0 || total == 0) return hipSuccess;
+    for (int64_t e0 = 0; e0 < total; e0 += kMaxGridElems) {
+        const dim3 grid((unsigned)((std::min(kMaxGridElems, total - e0) + 255) / 256)), block(256);
+        const hipError_t e = by_prec(prec, [&](auto t) {
+            small_grouped<decltype(t)><<<grid, block, 0, s>>>(descs, ndesc, total, e0);
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+__global__ __launch_bounds__(256) void krylov_check_kernel(const KrylovCheckDesc* __restrict__ descs,
+                                                           int32_t* __restrict__ stat_sweeps) {
+    __shared__ double part[4];
+    const KrylovCheckDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double s1 = d.nrm[0] > 0.0 ? 1.0 / d.nrm[0] : 0.0;
+    bool bad = false;
+    for (int i = 0; i < d.nw; ++i) {
+        const double inv = d.nrm[i];
+        if (!(inv > 0.0)) continue;   // masked pair
+        const double si = 1.0 / inv;
+        double acc = 0.0;
+        for (int r = tid; r < d.n; r += 256) {
+            const double v = d.e[(int64_t)r * d.nw + i] - si * d.qp[(int64_t)r * d.nw + i];
+            acc = fma(v, v, acc);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) part[wave] = acc;
+        __syncthreads();
+        const double tot = (part[0] + part[1]) + (part[2] + part[3]);
+        __syncthreads();
+        const double resid = sqrt(tot) * si * sqrt(si);
+        if (!(resid <= d.tol * s1 * s1)) bad = true;
+    }
+    if (tid == 0 && bad) {
+        const int32_t sw = stat_sweeps[d.stat];
+        stat_sweeps[d.stat] = sw < 0 ? sw : -1 - sw;
+    }
+}
+
+hipError_t launch_krylov_check(const KrylovCheckDesc* descs, int ndesc, int32_t* sweeps, hipStream_t s) {
+    if (ndesc == 0) return hipSuccess;
+    krylov_check_kernel<<<ndesc, 256, 0, s>>>(descs, sweeps);
+    return hipGetLastError();
+}
+
+constexpr int kCholMaxB = 64;
+
+// One wave per block; lane j owns column j.  Pivoted Cholesky on the full symmetric Gram in LDS
+// (pivot: the largest remaining diagonal entry, lowest index on ties), then the inverse of the
+// leading rank x rank triangle by back substitution, one column per lane.
+__global__ __launch_bounds__(64) void cholinv_kernel(const CholInvDesc* __restrict__ descs) {
+    __shared__ double A[kCholMaxB][kCholMaxB + 1];
+    __shared__ double R[kCholMaxB][kCholMaxB + 1];
+    __shared__ int perm[kCholMaxB];
+    const CholInvDesc& d = descs[blockIdx.x];
+    const int b = d.b, j = threadIdx.x;
+    for (int i = 0; i < b; ++i)
+        if (j < b) {
+            A[i][j] = d.g[i * b + j];
+            R[i][j] = 0.0;
+        }
+    if (j < b) perm[j] = j;
+    __syncthreads();
+    const double d0 = wave_max(j < b ? A[j][j] : 0.0);
+    int rank = 0;
+    for (int t = 0; t < b; ++t) {
+        const double dj = (j >= t && j < b) ? A[j][j] : -1.0;
+        const double dmax = wave_max(dj);
+        if (!(dmax > 1e-14 * d0) || !(d0 > 0.0)) break;
+        const unsigned long long hit = __ballot(dj == dmax);
+        const int p = __ffsll((long long)hit) - 1;
+        if (p != t) {   // symmetric swap of rows and columns t and p
+            if (j < b) {
+                const double x = A[t][j];
+                A[t][j] = A[p][j];
+                A[p][j] = x;
+            }
+            __syncthreads();
+            if (j < b) {
+                const double x = A[j][t];
+                A[j][t] = A[j][p];
+                A[j][p] = x;
+            }
+            if (j == 0) {
+                const int x = perm[t];
+                perm[t] = perm[p];
+                perm[p] = x;
+            }
+            for (int i = 0; i < t; ++i)   // earlier rows of R follow the column swap
+                if (j == 0) {
+                    const double x = R[i][t];
+                    R[i][t] = R[i][p];
+                    R[i][p] = x;
+                }
+            __syncthreads();
+        }
+        const double rtt = sqrt(A[t][t]);
+        if (j == t) R[t][t] = rtt;
+        if (j > t && j < b) R[t][j] = A[t][j] / rtt;
+        __syncthreads();
+        if (j > t && j < b) {
+            const double rj = R[t][j];
+            for (int i = t + 1; i < b; ++i) A[i][j] = fma(-R[t][i], rj, A[i][j]);
+        }
+        __syncthreads();
+        rank = t + 1;
+    }
+    // X = R[0:rank, 0:rank]^-1 (upper triangular), column j by back substitution into column j
+    // of A (no longer needed; each lane touches only its own column)
+    if (j < rank) {
+        A[j][j] = 1.0 / R[j][j];
+        for (int i = j - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (int l = i + 1; l <= j; ++l) acc = fma(R[i][l], A[l][j], acc);
+            A[i][j] = -acc / R[i][i];
+        }
+    }
+    // M[perm[i], j] = X[i, j] for i <= j < rank; zero elsewhere
+    if (j < b)
+        for (int i = 0; i < b; ++i) d.m[i * b + j] = 0.0;
+    __syncthreads();
+    if (j < rank)
+        for (int i = 0; i <= j; ++i) d.m[perm[i] * b + j] = A[i][j];
+}
+
+hipError_t launch_cholinv(const CholInvDesc* descs, int ndesc, hipStream_t s) {
+    if (ndesc == 0) return hipSuccess;
+    cholinv_kernel<<<ndesc, 64, 0, s>>>(descs);
+    return hipGetLastError();
 }
 
 // Device wall-clock stamp (100 MHz counter) on a stream, for timing the launches between two stamps

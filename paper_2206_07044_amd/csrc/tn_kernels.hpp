@@ -9,8 +9,10 @@
 namespace tn {
 
 // GEMM_GRAM_NARROW_*: forward Gram X^T X of a side with D <= 64 (by input type), float64 result
+// GEMM_*_X_F64: A in float32 / bfloat16, B in float64, product and result in float64
 enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2, GEMM_BF16 = 3, GEMM_BF16_TO_F64 = 4,
-               GEMM_GRAM_NARROW_F64 = 5, GEMM_GRAM_NARROW_F32 = 6, GEMM_GRAM_NARROW_BF16 = 7 };
+               GEMM_GRAM_NARROW_F64 = 5, GEMM_GRAM_NARROW_F32 = 6, GEMM_GRAM_NARROW_BF16 = 7, GEMM_F32_X_F64 = 8,
+               GEMM_BF16_X_F64 = 9 };
 
 constexpr int kCoreLdsMaxD = 64;
 constexpr int kLanczosMaxSteps = 512;     // cap on Krylov steps per compression
@@ -25,6 +27,8 @@ size_t core_lds_bytes(int max_d);
 hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
                        double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
 size_t lanczos_lds_bytes(int s_max);
+// Kernel launches one launch_core call issues (the block-Jacobi cores issue one per tournament round).
+int core_launch_count(int lds, int max_d, int max_sweeps);
 hipError_t launch_lanczos(int prec, const LanczosDesc* descs, int ndesc, int s_max, const double* scales,
                           int max_sweeps, double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);
 hipError_t launch_gram_lanczos(int prec, const GLanczosDesc* descs, int ndesc, int max_sweeps, double* disc,
@@ -44,6 +48,13 @@ hipError_t launch_ising_values(const IsingGraph& g, double beta, const double* J
                                hipStream_t s);
 hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, const double* dlnz_ddata,
                              double* dlnz_dJ, hipStream_t s);
+// Small dense float64 operations (SmallOp); `prec` is the dtype of SM_CAST destinations.
+hipError_t launch_small(int prec, const SmallDesc* descs, int ndesc, int64_t total, hipStream_t s);
+// One workgroup per compression: Ritz-pair residuals; non-converged compressions get a negative
+// sweep count (the evaluation then reports TN_ENUMERIC).
+hipError_t launch_krylov_check(const KrylovCheckDesc* descs, int ndesc, int32_t* sweeps, hipStream_t s);
+// One 64-lane wave per block: the orthonormalising factor M of W from G = W^T W.
+hipError_t launch_cholinv(const CholInvDesc* descs, int ndesc, hipStream_t s);
 // One 8-byte wall-clock stamp (100 MHz) written by the device when the stream reaches it.
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 hipError_t launch_result(int prec, const double* scales, int n_scales, const void* final_ptr, const int32_t* sweeps,

@@ -80,7 +80,7 @@ std::string make_axis(const std::vector<int32_t>& dims, const std::vector<int64_
             s.push_back(strides[i]);
         }
     }
-    if ((int)d.size() > kMaxLegs) return "matricisation needs more than 10 distinct legs";
+    if ((int)d.size() > kMaxLegs) return "matricisation needs more than 16 distinct legs";
     ax->n = (int32_t)d.size();
     ax->pad = 0;
     for (int l = 0; l < kMaxLegs; ++l) {
@@ -128,6 +128,42 @@ struct BwdOp {
 };
 
 }  // namespace
+
+KrylovLayout krylov_layout(int64_t n, int64_t D, int64_t my, int64_t nw, int64_t b, int64_t k, int full,
+                           int64_t splits, int64_t splits2, int64_t w) {
+    KrylovLayout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = off;
+        off = align_up(off + std::max<int64_t>(bytes, 8));
+        return at;
+    };
+    L.q = full ? -1 : take(8 * n * k);
+    L.ws = take(8 * n * k);
+    L.wo = full ? -1 : take(8 * n * b);
+    L.wx = full ? -1 : take(8 * n * b);
+    L.t1 = full ? -1 : take(8 * D * b);
+    L.t1t = -1;
+    L.u = take(8 * my * std::max(b, nw));   // float64 whatever the tensor dtype
+    L.t2p = take(8 * splits * D * b);
+    L.hc = full ? -1 : take(8 * k * b);
+    L.g = full ? -1 : take(8 * b * b);
+    L.m = full ? -1 : take(8 * b * b);
+    L.h = full ? -1 : take(8 * k * k);
+    L.ik = take(8 * k * k);
+    const int64_t rebuild = (k > 64 && k <= 256) ? 2 * k * k : 0;
+    L.core = take(8 * (4 * k * k + 4 * k + 2 * k * nw + rebuild));
+    L.plc = take(8 * k * nw);
+    L.prc = take(8 * nw * k);
+    L.qp = full ? -1 : take(8 * n * nw);
+    L.px = take(8 * D * nw);
+    L.pxt = -1;
+    L.pyp = take(8 * splits2 * D * nw);
+    L.nrm = take(8 * nw);
+    L.e = take(8 * n * nw);
+    L.bytes = off;
+    return L;
+}
 
 std::string make_view(const ViewSpec& s, View* v) {
     std::string err = make_axis(s.row_dims, s.row_strides, &v->row);
@@ -217,6 +253,8 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
         live[v] = v;
     }
     int next_edge = g.ne;
+    int32_t last_step_level = 0;
+    size_t step_mark = 0;
 
     auto read_tensor = [&](int32_t ver, int level) {
         TensorVer& t = P->tens[ver];
@@ -289,6 +327,9 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
     };
 
     for (int t = 0; t < n_steps; ++t) {
+        if (o.ordered)
+            for (size_t q = step_mark; q < P->steps.size(); ++q) last_step_level = std::max(last_step_level, P->steps[q].level);
+        step_mark = P->steps.size();
         const int32_t i = pi[t], j = pj[t];
         if (i < 0 || j < 0 || i >= total_ids || j >= total_ids || i == j || live[i] < 0 || live[j] < 0) {
             os << "step " << t << ": (" << i << ", " << j << ") are not two live tensors";
@@ -320,6 +361,10 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 Step st;
                 st.kind = ST_CONTRACT;
                 st.level = 1 + std::max(Ti.level, Tj.level);
+                // ordered levelling: a tree step starts no earlier than the last level of the one
+                // before it (its compressions included), so independent branches do not all hold
+                // their uncompressed intermediates at once: the memory of a sequential run
+                if (o.ordered) st.level = std::max(st.level, last_step_level);
                 st.in_a = vi;
                 st.in_b = vj;
                 st.M = m;
@@ -401,8 +446,16 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 c.chi_new = (int32_t)nw;
                 const int32_t comp_id = (int32_t)P->comps.size();
                 const bool big = D >= kLanczosMinD && !o.grad;   // the reverse pass needs the full core spectrum
-                const bool glanczos = big && (ma <= D || mb <= D);
-                const bool lanczos = big && !glanczos && (ma + mb) <= kLanczosMaxRowsPerD * D;
+                const bool xside = ma <= D || mb <= D;
+                // one explicit side and a large bond: block Krylov with the other side read in place
+                const bool krylov = big && xside && D >= kKrylovMinD;
+                const bool glanczos = big && xside && !krylov;
+                c.krylov = krylov ? 1 : 0;
+                // X = the explicit side (the shorter one when both are explicit)
+                const int x_is_b = (mb <= D && (ma > D || mb <= ma)) ? 1 : 0;
+                // both sides tall: Gram + block-Jacobi core up to D = 256 (one launch per tournament round over
+                // many workgroups); Golub-Kahan-Lanczos on A B (one workgroup) only beyond that
+                const bool lanczos = big && !xside && D > kBlockJacobiMaxD && (ma + mb) <= kLanczosMaxRowsPerD * D;
                 c.lanczos = lanczos ? 1 : 0;
                 c.glanczos = glanczos ? 1 : 0;
                 Step core;
@@ -435,6 +488,11 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         const int32_t ver = side == 0 ? va : vb;
                         const std::vector<int32_t>& fr = side == 0 ? free_a : free_b;
                         const int64_t mm = side == 0 ? ma : mb;
+                        if (krylov && side != x_is_b) {   // Y: read in place by the Krylov chain
+                            side_level[side] = T.level;
+                            (side == 0 ? c.side_a_buf : c.side_b_buf) = -1;
+                            continue;
+                        }
                         Step st;
                         st.level = T.level + 1;
                         st.comp = comp_id;
@@ -493,7 +551,50 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                     core.comp = comp_id;
                     touch(c.side_a_buf, core.level);
                     touch(c.side_b_buf, core.level);
-                    if (glanczos) {
+                    if (krylov) {
+                        core.kind = ST_KRYLOV;
+                        c.x_is_b = x_is_b;
+                        // Y (m_Y x D) and Y^T through the tensor's own layout
+                        const TensorVer& TY = x_is_b ? Ta : Tb;
+                        const std::vector<int32_t>& fy = x_is_b ? free_a : free_b;
+                        core.in_a = x_is_b ? va : vb;
+                        core.va = tensor_view(TY, fy, shared, E);
+                        core.vb = tensor_view(TY, shared, fy, E);
+                        const int64_t n = x_is_b ? mb : ma, my = x_is_b ? ma : mb;
+                        c.kr_n = n;
+                        c.kr_my = my;
+                        // basis: 4 chi' directions (at most 256, the core kernel's block-Jacobi range),
+                        // in blocks of about chi'/2; or all of R^n when n is that small
+                        const int64_t kcap = std::min<int64_t>(256, std::max<int64_t>(64, 4 * nw));
+                        if (n <= kcap) {
+                            c.kr_full = 1;
+                            c.kr_k = (int32_t)n;
+                            c.kr_b = (int32_t)std::min<int64_t>(64, n);
+                            c.kr_s = (int32_t)((n + c.kr_b - 1) / c.kr_b);
+                        } else {
+                            c.kr_full = 0;
+                            const int64_t bb = std::min<int64_t>(64, std::max<int64_t>(8, (nw / 2 + 7) / 8 * 8));
+                            c.kr_b = (int32_t)bb;
+                            c.kr_s = (int32_t)(kcap / bb);
+                            c.kr_k = c.kr_b * c.kr_s;
+                        }
+                        auto ysplits = [&](int64_t N) {
+                            const int64_t tiles = ((D + 63) / 64) * ((N + 63) / 64);
+                            int64_t sp = (my + 255) / 256;
+                            sp = std::min<int64_t>(sp, std::max<int64_t>(1, 1024 / tiles));
+                            sp = std::min<int64_t>(sp, std::max<int64_t>(1, (32 << 20) / (D * N * 8)));
+                            return (int32_t)std::max<int64_t>(1, sp);
+                        };
+                        c.kr_splits = ysplits(c.kr_b);
+                        c.kr_splits2 = ysplits(nw);
+                        const KrylovLayout L = krylov_layout(n, D, my, nw, c.kr_b, c.kr_k, c.kr_full, c.kr_splits,
+                                                             c.kr_splits2, w);
+                        c.work_buf = new_buf(L.bytes, BUF_WORK, core.level);
+                        // like a core launch, the chain may run on into the next level
+                        touch(c.work_buf, core.level + 1);
+                        touch(x_is_b ? c.side_b_buf : c.side_a_buf, core.level + 1);
+                        read_tensor(x_is_b ? va : vb, core.level + 1);
+                    } else if (glanczos) {
                         // X = the explicit side (the shorter one when both are explicit)
                         c.x_is_b = (mb <= D && (ma > D || mb <= ma)) ? 1 : 0;
                         const int64_t n = c.x_is_b ? mb : ma, my = c.x_is_b ? ma : mb;
@@ -502,7 +603,9 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         c.s_min = (int32_t)std::min<int64_t>(n, nw + 16);
                         c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(n, 8 * nw + 64), 512);
                         const int64_t sm = c.s_max, ls = sm + 1;
-                        const int64_t words = n * n + std::max(D, my) * n + n * sm + n * nw + 2 * D + std::max(n, my) +
+                        // T1 = G_Y F_X^T (D x n) when Y has a Gram, else F_X F_Y^T (n x my, my <= D)
+                        const int64_t t1 = (my > D ? D : my) * n;
+                        const int64_t words = n * n + t1 + n * sm + n * nw + 2 * D + std::max(n, my) +
                                               2 * sm + ls +
                                               2 * ls * ls + 16 * D + 2 * D * nw + std::max(n, my) * nw + ls / 2 +
                                               8;   // 16 = waves of the kernel
@@ -532,7 +635,7 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                     // the R_A R_B core and its SVD; the same whichever kernel computes it
                     double f = 0.0, b = 0.0;
                     for (int64_t mm : {ma, mb})
-                        if (lanczos && mm > D) {   // Gram steps carry these terms otherwise
+                        if ((lanczos || krylov) && mm > D) {   // Gram steps carry these terms otherwise
                             f += 2.0 * (double)mm * D * D - 2.0 / 3.0 * (double)D * D * D;
                             b += (double)w * mm * D;
                         }

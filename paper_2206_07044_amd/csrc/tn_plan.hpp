@@ -33,6 +33,7 @@ struct TreeOpts {
     int32_t keep = 0;               // never reuse arena memory
     int32_t grad = 0;               // plan the reverse pass too
     int32_t plain = 0;              // one launch per step, no streams, no graph (the plain form)
+    int32_t ordered = 0;            // contraction levels follow the tree order (memory of a sequential run)
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).
@@ -57,7 +58,7 @@ struct TensorVer {
     int32_t last_read = 0;
 };
 
-enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS };
+enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS, ST_KRYLOV };
 
 // Gram steps of sides with D <= kGramNarrowMaxD run on the narrow-Gram kernel (512 rows per split)
 constexpr int kGramNarrowMaxD = 64;
@@ -99,11 +100,29 @@ struct Compression {
     int32_t glanczos;                   // 1: large D with an explicit side: Lanczos on F_X G_Y F_X^T
     int32_t x_is_b;                     // glanczos: the explicit side X is B
     int32_t s_min, s_max;               // Krylov steps (lanczos / glanczos)
+    // block Krylov (large D with an explicit side X of n rows; the other side Y is read in place)
+    int32_t krylov;
+    int64_t kr_n, kr_my;                // rows of X and of Y
+    int32_t kr_b, kr_s, kr_k, kr_full;  // block size, blocks, basis dimension, 1: the basis is all of R^n
+    int32_t kr_splits, kr_splits2;      // split-K factors of Y^T U (b columns) and Y^T U2 (chi' columns)
 };
+
+// Large-D compressions with one explicit side use the block-Krylov path from this bond size on.
+constexpr int64_t kKrylovMinD = 512;
+
+// Byte offsets of a block-Krylov compression's workspace (see the chain in tn_krylov.cpp).
+struct KrylovLayout {
+    int64_t q, ws, wo, wx, t1, t1t, u, t2p, hc, g, m, h, ik, core, plc, prc, qp, px, pxt, pyp, nrm, e;
+    int64_t bytes;
+};
+KrylovLayout krylov_layout(int64_t n, int64_t D, int64_t my, int64_t nw, int64_t b, int64_t k, int full,
+                           int64_t splits, int64_t splits2, int64_t w);
 
 // Compressions with D above this use Golub-Kahan-Lanczos on A B instead of Gram matrices,
 // unless the matricised tensors are much taller than D.
 constexpr int64_t kLanczosMinD = 65;
+// Largest core the block Jacobi handles (the core kernel's kBJRows).
+constexpr int64_t kBlockJacobiMaxD = 256;
 constexpr int64_t kLanczosMaxRowsPerD = 256;
 
 // One step of the reverse pass (levels count from the seed of the final scalar).

@@ -20,6 +20,7 @@ from tninputs import (Graph, dimer_tensors, greedy_tree, ising_tensors, lattice,
 from tninputs.trees import sweep_tree
 
 from _gpu_helpers import gpu_eval
+import paper_2206_07044_amd as tn
 
 pytestmark = pytest.mark.gpu
 
@@ -286,3 +287,42 @@ def test_cutoff_probe_random(cut_between):
     caps = [rng.normal(size=d) + 1.0 for d in (2, 3, 3, 2)]
     g, T, pairs = bond_probe(a_mat, b_mat, (2, 4), (2, 3), (3, 2), caps)
     _check(g, T, pairs, 5, rtol=1e-13, min_comp=1, cutoff=cutoff)
+
+
+# ---------------------------------------------------------------------------- large bonds, block Krylov
+# Bonds of D >= 512 with one explicit side (the sweep trees' D = chi^2 merges) take the block-Krylov
+# path: a basis of 4 chi' directions in blocks of chi'/2 (Lanczos mode) when the explicit side has
+# more rows than that, else all of R^n (exact).  FP64 parity at 1e-10 relative.
+@pytest.mark.parametrize("shape,chi", [((5, 5, 5), 32), ((4, 4, 8), 32), ((4, 4, 4), 64), ((5, 5, 5), 64)])
+def test_ising_cubic_krylov_bonds(shape, chi):
+    g = lattice(shape)
+    _check(g, ising_tensors(g, 0.22), sweep_tree(shape), chi, min_comp=1)
+
+
+# At chi = 32 the kept singular values reach ~1e-3 sigma_1, and a float32 rounding of a tensor
+# (relative u on every entry) moves sigma_i by ~u sigma_1, i.e. by u sigma_1 / sigma_i relative:
+# the float32 error grows with chi beyond the per-op random walk of the small cases.  The float32
+# bound here is the metric's gate (1e-6 relative on ln Z); bfloat16 keeps the random-walk bound.
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_krylov_bonds_reduced_precision(precision):
+    shape, chi = (5, 5, 5), 32
+    g = lattice(shape)
+    T = ising_tensors(g, 0.22)
+    pairs = sweep_tree(shape)
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    sign, lnz, *_ = gpu_eval(g, T, pairs, chi, precision)
+    err = abs(lnz - want.ln_abs_z)
+    bound = 1e-6 * abs(want.ln_abs_z) if precision == "fp32" else _bf16_bound(want)
+    print(f"{precision} krylov {shape} chi={chi}: |dlnZ|={err:.3e} bound={bound:.3e}", flush=True)
+    assert sign == want.sign and err <= bound
+
+
+def test_krylov_flat_spectrum_is_reported():
+    """Normal(0.2, 1) entries on 5^3 at chi = 32: random cores have flat spectra, which a basis of
+    4 chi' directions does not resolve; the Ritz residual check must turn that into TN_ENUMERIC
+    instead of a silently wrong value."""
+    g = lattice((5, 5, 5))
+    T = normal_tensors(g, 0.2, 4)
+    with pytest.raises(tn.TNError) as ei:
+        gpu_eval(g, T, sweep_tree((5, 5, 5)), 32)
+    assert ei.value.status == tn.TN_ENUMERIC
