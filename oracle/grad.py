@@ -17,9 +17,21 @@ readings, also listed in the design notes:
   symmetrically (section II.C, Eq. (svd); SI B).  Its adjoint is the textbook
   adjoint of a truncated SVD, written out below with the COMPLETE singular
   spectrum of the reduced core (kept, discarded and zero singular values).
-* Pairs of kept singular values use 1/(s_i^2 - s_j^2) with Lorentzian
-  broadening x / (x^2 + eps^2), eps = 1e-12 s_1^2 (their numerators cancel
-  for a gauge-invariant continuation, so this only guards exact degeneracy).
+* Pairs of kept singular values take the gauge-invariant form.  The SVD of
+  Eq. (svd) fixes the kept singular vectors only up to rotations among equal
+  singular values, and every later step of Algorithm 1 (a contraction, or a
+  compression whose R factors and core see the new bond through a Gram matrix
+  or the product K) is equivariant under an orthogonal change of basis of the
+  bond a compression creates; so ln|Z| is invariant under it, and its
+  derivative along such a rotation vanishes.  Substituting that identity into
+  the textbook kept-kept entry f (alpha_ji s_i + beta_ji s_j - alpha_ij s_i
+  - beta_ij s_j), f = 1 / (s_i^2 - s_j^2), cancels the factor s_i - s_j and
+  leaves (alpha_ji + beta_ij) / (s_i + s_j): equal in exact arithmetic, but
+  with no division by a gap between kept values, which would amplify the
+  rounding of the incoming adjoint by s_1^2 / (s_i^2 - s_j^2), and with the
+  right limit at an exact degeneracy.  Pairs of a kept and a discarded (or
+  zero) value keep 1 / (s_i^2 - s_j^2): that gap is the conditioning of the
+  truncation itself.
 * Singular values at or below 1e-13 s_1 are rounding-level zeros of the core:
   they are treated as exactly zero (a kept one gives a constant zero column,
   as does one below ``cutoff * s_1``).  The gradient is then that of the
@@ -38,7 +50,6 @@ import numpy as np
 
 from .approx import ZeroContraction, _Network
 
-_EPS_REL = 1e-12
 _NOISE_REL = 1e-13
 
 
@@ -200,7 +211,6 @@ def _compress_bwd(rec, adj: Dict[int, np.ndarray]) -> None:
     K_idx = [i for i in range(new) if mask[i]]
     s_all = np.zeros(max(ka, kb))
     s_all[:len(sig)] = np.where(sig > _NOISE_REL * sig[0], sig, 0.0)
-    eps = _EPS_REL * sig[0] ** 2 if len(sig) else 0.0
 
     u_bar = g_a * sq                                 # dL/dU_K  (columns i < new; masked columns are 0)
     v_bar = g_b.T * sq                               # dL/dV_K
@@ -214,8 +224,10 @@ def _compress_bwd(rec, adj: Dict[int, np.ndarray]) -> None:
             if j == i:
                 continue
             sj = s_all[j]
-            x = si * si - sj * sj
-            f = x / (x * x + eps * eps) if (j in K_idx) else 1.0 / x
+            if j in K_idx:                           # kept pair: gauge-invariant form, row j column i
+                J[j, i] += (alpha[j, i] + beta[i, j]) / (si + sj)
+                continue
+            f = 1.0 / (si * si - sj * sj)
             if j < ka:                               # u_bar_i along u_j
                 J[j, i] += alpha[j, i] * si * f
                 if j < kb:

@@ -2670,8 +2670,8 @@ __global__ __launch_bounds__(256) void reduce_grouped(const ReduceDesc* __restri
 // R~_A R~_B^T = U s V^T (all singular triplets above the rounding level, the "+" set, r of them,
 // the first nK kept), L = R~_B^T V s^-1 and M = R~_A^T U s^-1 (D x r), the inputs
 // H_A = A^T G_a, H_B = B G_b^T (D x nK) give a = L^T H_A, b = M^T H_B (r x nK) and
-//   Phi (r x r): the truncated-SVD adjoint in singular coordinates (full spectrum, Lorentzian
-//                broadening between kept pairs),
+//   Phi (r x r): the truncated-SVD adjoint in singular coordinates (full spectrum; kept pairs in
+//                their gauge-invariant form),
 //   N_A = L Psi_A L^T + sum_t L_t H_B,t^T / sqrt(s_t),   N_B = M Psi_B M^T + sum_t H_A,t M_t^T / sqrt(s_t),
 //   Psi_A = Phi s - a s^1/2 E^T - E s^-1/2 b^T s,   Psi_B = s Phi - s a s^-1/2 E^T - E s^1/2 b^T,
 // so that A_bar = G_a P_L^T + A N_A and B_bar = P_R^T G_b + N_B B need no inverse of R~.
@@ -2823,25 +2823,21 @@ __global__ __launch_bounds__(kCoreThreads) void core_bwd_kernel(const CoreBwdDes
         wg_gemm_f64_narrow(L, 1, D, HA, cn, 1, a, cn, r, nk, D);
         wg_gemm_f64_narrow(Mm, 1, D, HB, cn, 1, b, cn, r, nk, D);
         __syncthreads();
-        const double eps = 1e-12 * smax * smax;
-        // Phi[x][y]: diagonal of the kept block, plus the contributions of kept index y (to row x)
-        // and of kept index x (to column y) for every other singular index
+        // Phi[x][y].  Kept block (x, y < nk, the diagonal included): the gauge-invariant form
+        // (s_y^1/2 a_xy + s_x^1/2 b_yx) / (s_x + s_y), equal to the textbook entry because ln|Z| is
+        // invariant under an orthogonal change of basis of the new bond, and free of any division
+        // by a gap between kept values.  A kept index against a discarded one: the textbook
+        // 1 / (s_y^2 - s_x^2) terms (the gap of the truncation itself).
         for (int idx = tid; idx < r * r; idx += kCoreThreads) {
             const int x = idx / r, y = idx - x * r;
             const double sx = sg[x], sy = sg[y];
             double v = 0.0;
-            if (x == y) {
-                if (x < nk) v = (a[x * cn + x] + b[x * cn + x]) / (2.0 * sq[x]);
-            } else {
-                const double d2 = sy * sy - sx * sx;   // sigma_y^2 - sigma_x^2
-                if (y < nk) {   // i = y kept, j = x
-                    const double f = x < nk ? d2 / (d2 * d2 + eps * eps) : 1.0 / d2;
-                    v += (a[x * cn + y] * sq[y] * sy + b[x * cn + y] * sq[y] * sx) * f;
-                }
-                if (x < nk) {   // i = x kept, j = y
-                    const double f = y < nk ? -d2 / (d2 * d2 + eps * eps) : -1.0 / d2;
-                    v += (a[y * cn + x] * sq[x] * sy + b[y * cn + x] * sq[x] * sx) * f;
-                }
+            if (x < nk && y < nk) {
+                v = (a[x * cn + y] * sq[y] + b[y * cn + x] * sq[x]) / (sx + sy);
+            } else if (y < nk) {   // i = y kept, j = x discarded
+                v = (a[x * cn + y] * sq[y] * sy + b[x * cn + y] * sq[y] * sx) / (sy * sy - sx * sx);
+            } else if (x < nk) {   // i = x kept, j = y discarded
+                v = -(a[y * cn + x] * sq[x] * sy + b[y * cn + x] * sq[x] * sx) / (sy * sy - sx * sx);
             }
             Phi[x * D + y] = v;
         }

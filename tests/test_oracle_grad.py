@@ -114,3 +114,33 @@ def test_ring_closed_form_derivative():
     pc, ps = np.prod(2 * c), np.prod(2 * s)
     want = beta * (pc * np.tanh(beta * Jg) + ps / np.tanh(beta * Jg)) / (pc + ps)
     np.testing.assert_allclose(dJ, want, rtol=1e-11)
+
+
+def _probe_with_spectrum(sig, chi, seed):
+    """One compression (tninputs.probes.bond_probe) of K = A_mat B_mat with singular values sig."""
+    from tninputs.probes import bond_probe
+    rng = np.random.default_rng(seed)
+    D = len(sig)
+    qa, _ = np.linalg.qr(rng.normal(size=(9, D)))
+    qb, _ = np.linalg.qr(rng.normal(size=(9, D)))
+    mix = np.linalg.qr(rng.normal(size=(D, D)))[0]          # A_mat and B_mat individually unstructured
+    a_mat = qa @ np.diag(sig) @ mix
+    b_mat = mix.T @ qb.T
+    caps = [rng.normal(size=3) for _ in range(4)]
+    return bond_probe(a_mat, b_mat, [D], (3, 3), (3, 3), caps), chi
+
+
+@pytest.mark.parametrize("sig", [[3.0, 2.0, 2.0, 1.0, 0.5],          # exactly equal kept pair
+                                 [3.0, 2.0, 2.0 - 1e-9, 1.0, 0.5],   # kept pair 1e-9 apart
+                                 [2.0, 2.0, 2.0, 1.0, 0.5]])         # three equal kept values
+def test_kept_degenerate_pairs_match_central_differences(sig):
+    # the compression is smooth in K while the kept/discarded gap is open, however close the
+    # kept values are: the gradient has a finite limit at an exact kept-kept degeneracy
+    (g, T, pairs), chi = _probe_with_spectrum(np.array(sig), 3, seed=2)
+    res = lnz_and_grad(g.n, g.edges, T, pairs, chi)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        dT = [rng.normal(size=t.shape) * np.max(np.abs(t)) for t in T]
+        want = _fd_directional(g, T, pairs, chi, dT, 1e-6)
+        got = sum(float(np.sum(gr * d)) for gr, d in zip(res.grads, dT))
+        assert got == pytest.approx(want, rel=1e-6, abs=1e-8)
