@@ -229,6 +229,196 @@ def ising_8x8_leg(tn, torch, reps):
     return out
 
 
+def spin_glass_leg(tn, torch, L, chi, beta, steps):
+    """The 3D +-J spin glass (SI F.1): L^3 open-boundary cubic lattice, couplings +-1 with equal
+    probability from default_rng(0), forward + reverse pass to d ln|Z| / d J for every bond, in
+    float64 and float32 on gradient plans.  The tensors are built on the device from J by the
+    library's Ising map; the Euler identity sum(T * dlnZ/dT) = 1 per tensor is checked on the host."""
+    from tninputs import ising_tensors, lattice
+    from tninputs.trees import sweep_tree
+    shape = (L, L, L)
+    g = lattice(shape)
+    J = np.where(np.random.default_rng(0).random(g.n_edges) < 0.5, -1.0, 1.0)
+    T = ising_tensors(g, beta, J)
+    eu, ev, ed, off, data = flat(g, T)
+    pairs = sweep_tree(shape)
+    pi = [a for a, _ in pairs]
+    pj = [b for _, b in pairs]
+    Jd = torch.tensor(J, dtype=torch.float64, device="cuda")
+    out = {"lattice": list(shape), "beta": beta, "chi": chi, "couplings": "+-1, default_rng(0)",
+           "tree": "Span family, axis-ordered spanning tree swept leaves-inwards", "n_bonds": g.n_edges}
+    grads = {}
+    for prec in ("fp64", "fp32"):
+        c = tn.Context(0)
+        c.tn_load_graph(g.n, eu, ev, ed, off, data)
+        c.tn_set_tree(pi, pj, chi, precision=prec, grad=True)
+        info, binfo = c.tn_plan_info(), c.tn_grad_info()
+        dT = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+        dJ = torch.empty(g.n_edges, dtype=torch.float64, device="cuda")
+
+        def step():
+            c.tn_ising_values_device(beta, Jd.data_ptr())
+            c.tn_contract_compressed()
+            c.tn_grad_device(dT.data_ptr())
+            c.tn_ising_coupling_grad_device(beta, Jd.data_ptr(), dT.data_ptr(), dJ.data_ptr())
+            c.tn_sync()
+
+        step()                                  # captures the forward and reverse schedules (untimed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        sign, lnz = c.tn_result()
+        gT = dT.cpu().numpy()
+        eul = np.abs([float(np.dot(data[off[v]:off[v + 1]], gT[off[v]:off[v + 1]])) - 1.0 for v in range(g.n)])
+        _, tie, _ = c.tn_compress_stats()
+        grads[prec] = dJ.cpu().numpy()
+        flops = info["fwd_flops"] + binfo["bwd_flops"]
+        out[prec] = {"ms_per_step": dt * 1e3, "fwd_bwd_per_s": 1.0 / dt, "tflops": flops / dt / 1e12,
+                     "fwd_flops": info["fwd_flops"], "bwd_flops": binfo["bwd_flops"],
+                     "arena_bytes": info["arena_bytes"], "ln_abs_z": lnz, "sign": sign,
+                     "euler_identity_error_max": float(eul.max()), "euler_identity_error_median": float(np.median(eul)),
+                     "tie_flags": int(np.sum(tie)), "steps": steps}
+        c.close()
+    d = np.abs(grads["fp32"] - grads["fp64"])
+    scale = float(np.max(np.abs(grads["fp64"])))
+    out["dJ_fp32_vs_fp64"] = {"max_abs": float(d.max()), "median_abs": float(np.median(d)),
+                              "max_abs_over_max_dJ": float(d.max()) / scale,
+                              "bonds_over_1e-3_max_dJ": int(np.sum(d > 1e-3 * scale))}
+    out["rel_dlnz_fp32_vs_fp64"] = abs(out["fp32"]["ln_abs_z"] - out["fp64"]["ln_abs_z"]) / abs(out["fp64"]["ln_abs_z"])
+    out["speedup_fp32_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    return out
+
+
+def _golden(name):
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def _load(tn, g, T, pairs, chi, precision):
+    eu, ev, ed, off, data = flat(g, T)
+    c = tn.Context(0)
+    c.tn_load_graph(g.n, eu, ev, ed, off, data)
+    c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, precision=precision)
+    return c
+
+
+def dimer_leg(tn, torch, reps):
+    """Dimer covers of random 3-regular graphs (section IV.B, SI F.3) on Agglom-family trees:
+    single graphs at N = 256 (chi = 4) and N = 512 (chi = 2) in float64 and float32 against the
+    stored oracle values, and 32 graphs of N = 2 U{48..96} (seeds 0..31, chi = 4) replayed as one
+    batch against the same graphs run one after another."""
+    from tninputs import configs, simulate_tree
+    gold = (_golden("random_graphs.json") or {}).get("dimer", {})
+    out = {"single": {}}
+    for n, chi, ts in ((256, 4, 2), (512, 2, 2)):
+        g, T, pairs = configs.dimer_rrg(n, chi, tree_seed=ts)
+        rec = {"chi": chi, "tree": f"agglom_tree(g, {chi}, k=4, seed={ts})",
+               "largest_tensor": simulate_tree(g, pairs, chi).largest_elems}
+        ref = gold.get(str(n))
+        for prec in ("fp64", "fp32"):
+            c = _load(tn, g, T, pairs, chi, prec)
+            dt = timed(c, reps, torch)
+            sign, lnz = c.tn_result()
+            r = {"trees_per_s": 1.0 / dt, "ms_per_tree": dt * 1e3, "ln_abs_z": lnz, "sign": sign,
+                 "arena_bytes": c.tn_plan_info()["arena_bytes"]}
+            if ref is not None:
+                r["rel_dlnz_vs_oracle"] = abs(lnz - ref["oracle_lnZ"]) / abs(ref["oracle_lnZ"])
+            rec[prec] = r
+            c.close()
+        out["single"][str(n)] = rec
+    # uneven batch: N_b = 2 U{48..96} from default_rng(b), graph seed b; per graph the tree seed
+    # (of 0..2) with the smallest largest intermediate, stopping at the first below 2^20 entries
+    sizes = [2 * int(np.random.default_rng(b).integers(48, 97)) for b in range(32)]
+    insts = []
+    for b, n in enumerate(sizes):
+        g = configs.random_regular3(n, b)
+        best = None
+        for ts in range(3):
+            pairs = configs.agglom_tree(g, 4, k=4, seed=ts)
+            w = simulate_tree(g, pairs, 4).largest_elems
+            if best is None or w < best[0]:
+                best = (w, pairs)
+            if w <= 1 << 20:
+                break
+        insts.append((g, configs.dimer_tensors(g), best[1]))
+    bres = {"graphs": 32, "sizes": sizes, "chi": 4, "largest_tensor_max": max(simulate_tree(g, p, 4).largest_elems for g, _, p in insts)}
+    for prec in ("fp64", "fp32"):
+        ctxs = [_load(tn, g, T, p, 4, prec) for g, T, p in insts]
+        seq = 0.0
+        for c in ctxs:
+            seq += timed(c, 1, torch)
+        lnz_seq = [c.tn_result()[1] for c in ctxs]
+        batch = tn.Batch(ctxs)
+        batch.tn_batch_contract()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batch.tn_batch_contract()
+        torch.cuda.synchronize()
+        bdt = (time.perf_counter() - t0) / reps
+        lnz_b = [c.tn_result()[1] for c in ctxs]
+        bres[prec] = {"batch_ms": bdt * 1e3, "trees_per_s": 32 / bdt, "sequential_ms": seq * 1e3,
+                      "speedup_vs_sequential": seq / bdt, "bitwise_equal_to_sequential": lnz_b == lnz_seq,
+                      "graph": "one hipGraph per batch"}
+        batch.close()
+        for c in ctxs:
+            c.close()
+    out["batch"] = bres
+    return out
+
+
+def normal_d3_leg(tn, torch, reps):
+    """Random tensor networks (section IV.C, SI F.2): one random 3-regular graph of N = 300 with
+    bond dimension 3 and Normal(mu, 1) entries, chi = 2 on an Agglom-family tree; 64 tensor seeds
+    per mu replayed as one batch in float32 and bfloat16, against float64 batches for the sign
+    and ln|Z|, and against the stored oracle values for seeds 0..3."""
+    from tninputs import configs, normal_tensors, random_regular3, simulate_tree
+    gold = (_golden("random_graphs.json") or {}).get("normal_d3_n300_chi2", {})
+    g = random_regular3(300, 0, dim=3)
+    pairs = configs.agglom_tree(g, 2, k=4, seed=0)
+    out = {"n": 300, "D": 3, "chi": 2, "seeds": 64, "tree": "agglom_tree(g, 2, k=4, seed=0)",
+           "largest_tensor": simulate_tree(g, pairs, 2).largest_elems, "mu": {}}
+    for mu in (0.0, 0.1, 0.2, 0.5):
+        Ts = [normal_tensors(g, mu, s) for s in range(64)]
+        res = {}
+        vals = {}
+        for prec in ("fp64", "fp32", "bf16"):
+            ctxs = [_load(tn, g, T, pairs, 2, prec) for T in Ts]
+            batch = tn.Batch(ctxs)
+            batch.tn_batch_contract()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                batch.tn_batch_contract()
+            torch.cuda.synchronize()
+            bdt = (time.perf_counter() - t0) / reps
+            vals[prec] = [c.tn_result() for c in ctxs]
+            res[prec] = {"batch_ms": bdt * 1e3, "trees_per_s": 64 / bdt}
+            batch.close()
+            for c in ctxs:
+                c.close()
+        for prec in ("fp32", "bf16"):
+            d = [abs(a[1] - b[1]) / abs(b[1]) for a, b in zip(vals[prec], vals["fp64"])]
+            res[prec]["sign_agreement_vs_fp64"] = sum(a[0] == b[0] for a, b in zip(vals[prec], vals["fp64"])) / 64
+            res[prec]["rel_dlnz_vs_fp64_median"] = float(np.median(d))
+            res[prec]["rel_dlnz_vs_fp64_max"] = float(np.max(d))
+        ref = [gold.get(f"{mu}/{s}") for s in range(4)]
+        if all(r is not None for r in ref):
+            res["fp64"]["max_rel_dlnz_vs_oracle_seeds_0_3"] = max(
+                abs(vals["fp64"][s][1] - ref[s]["oracle_lnZ"]) / abs(ref[s]["oracle_lnZ"]) for s in range(4))
+            res["fp64"]["sign_agreement_vs_oracle_seeds_0_3"] = all(
+                vals["fp64"][s][0] == ref[s]["sign"] for s in range(4))
+        res["fraction_negative_fp64"] = sum(v[0] < 0 for v in vals["fp64"]) / 64
+        out["mu"][str(mu)] = res
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,8 +434,10 @@ def main() -> int:
     ap.add_argument("--fwd-bwd-steps", type=int, default=1, help="timed forward+reverse passes (0: skip)")
     ap.add_argument("--batch", type=int, default=8, help="instances in the batched leg (<= 1: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--per-chi", default="32", help="other chi values timed in fp32 and fp64 ('' to skip)")
+    ap.add_argument("--per-chi", default="32,64", help="other chi values timed in fp32 and fp64 ('' to skip)")
     ap.add_argument("--no-small", action="store_true", help="skip the 8x8 Ising leg")
+    ap.add_argument("--spin-glass", default="16,16", help="L,chi of the +-J spin-glass forward+reverse leg ('' to skip)")
+    ap.add_argument("--no-random-graphs", action="store_true", help="skip the dimer and Normal(mu) random-graph legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -416,9 +608,13 @@ def main() -> int:
                 c = tn.Context(0)
                 c.tn_load_graph(g.n, eu, ev, ed, off, data)
                 c.tn_set_tree(pi, pj, chi, precision=prec)
-                c.tn_contract_compressed()   # captures the schedule (untimed)
+                pinfo = c.tn_plan_info()
+                if chi <= 32:
+                    c.tn_contract_compressed()   # captures the schedule (untimed)
+                    n = 2
+                else:
+                    n = 1                        # seconds per tree, enqueued launch by launch: no warm-up
                 torch.cuda.synchronize()
-                n = 2
                 t0 = time.perf_counter()
                 for _ in range(n):
                     c.tn_enqueue()
@@ -427,7 +623,7 @@ def main() -> int:
                 cdt = (time.perf_counter() - t0) / n
                 _, cl = c.tn_result()
                 r = {"ms_per_tree": cdt * 1e3, "trees_per_s": 1.0 / cdt, "ln_abs_z": cl,
-                     "tflops_fwd": c.tn_plan_info()["fwd_flops"] / cdt / 1e12}
+                     "tflops_fwd": pinfo["fwd_flops"] / cdt / 1e12, "arena_bytes": pinfo["arena_bytes"]}
                 if rec["oracle_ln_abs_z"] is not None:
                     r["rel_dlnz_vs_oracle"] = abs(cl - rec["oracle_ln_abs_z"]) / abs(rec["oracle_ln_abs_z"])
                 rec[prec] = r
@@ -438,32 +634,50 @@ def main() -> int:
         out["per_chi"] = per
 
     if args.fwd_bwd_steps > 0:
-        # forward + reverse pass (d ln|Z| / d inputs) in the same precision, on a gradient plan
-        gctx = tn.Context(0)
-        gctx.tn_load_graph(g.n, eu, ev, ed, off, data)
-        gctx.tn_set_tree(pi, pj, args.chi, precision=args.precision, grad=True)
-        ginfo = gctx.tn_plan_info()
-        gbi = gctx.tn_grad_info()
-        gctx.tn_contract_compressed()
-        gctx.tn_grad()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.fwd_bwd_steps):
+        # forward + reverse pass (d ln|Z| / d inputs) on gradient plans, in the bench precision and in
+        # float64; the gradient stays on the device (tn_grad_device) inside the timed region
+        fb = {}
+        for prec in dict.fromkeys((args.precision, "fp64")):
+            gctx = tn.Context(0)
+            gctx.tn_load_graph(g.n, eu, ev, ed, off, data)
+            gctx.tn_set_tree(pi, pj, args.chi, precision=prec, grad=True)
+            ginfo = gctx.tn_plan_info()
+            gbi = gctx.tn_grad_info()
+            gdev = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
             gctx.tn_contract_compressed()
-            gg = gctx.tn_grad()
-        torch.cuda.synchronize()
-        gdt = (time.perf_counter() - t0) / args.fwd_bwd_steps
-        total_f = ginfo["fwd_flops"] + gbi["bwd_flops"]
-        euler = float(np.max(np.abs([float(np.dot(data[off[v]:off[v + 1]], gg[off[v]:off[v + 1]])) - 1.0
-                                     for v in range(g.n)])))
-        out["fwd_bwd"] = {"ms_per_step": gdt * 1e3, "trees_per_s": 1.0 / gdt, "tflops": total_f / gdt / 1e12,
-                          "fwd_flops": ginfo["fwd_flops"], "bwd_flops": gbi["bwd_flops"],
-                          "arena_bytes": ginfo["arena_bytes"], "max_euler_identity_error": euler,
-                          "steps": args.fwd_bwd_steps}
-        gctx.close()
+            gctx.tn_grad_device(gdev.data_ptr())
+            gctx.tn_sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.fwd_bwd_steps):
+                gctx.tn_contract_compressed()
+                gctx.tn_grad_device(gdev.data_ptr())
+                gctx.tn_sync()
+            torch.cuda.synchronize()
+            gdt = (time.perf_counter() - t0) / args.fwd_bwd_steps
+            gg = gdev.cpu().numpy()
+            total_f = ginfo["fwd_flops"] + gbi["bwd_flops"]
+            eul = np.abs([float(np.dot(data[off[v]:off[v + 1]], gg[off[v]:off[v + 1]])) - 1.0 for v in range(g.n)])
+            fb[prec] = {"ms_per_step": gdt * 1e3, "trees_per_s": 1.0 / gdt, "tflops": total_f / gdt / 1e12,
+                        "fwd_flops": ginfo["fwd_flops"], "bwd_flops": gbi["bwd_flops"],
+                        "arena_bytes": ginfo["arena_bytes"], "max_euler_identity_error": float(eul.max()),
+                        "median_euler_identity_error": float(np.median(eul)), "steps": args.fwd_bwd_steps}
+            gctx.close()
+        out["fwd_bwd"] = fb
+        if "fp64" in fb and not args.no_fp64_reference:
+            out["fwd_bwd"]["tflops_vs_plain_fp64_forward"] = fb[args.precision]["tflops"] / (
+                info["fwd_flops"] * out["fp64_plain"]["trees_per_s"] / 1e12)
+
+    if args.spin_glass:
+        L_sg, chi_sg = (int(x) for x in args.spin_glass.split(","))
+        out["spin_glass"] = spin_glass_leg(tn, torch, L_sg, chi_sg, 0.5, 2)
 
     if not args.no_small:
         out["ising_8x8"] = ising_8x8_leg(tn, torch, 5)
+
+    if not args.no_random_graphs:
+        out["dimer_rrg"] = dimer_leg(tn, torch, 3)
+        out["normal_d3_rrg"] = normal_d3_leg(tn, torch, 3)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, T, pairs, args.chi, info["fwd_flops"], args.cpu_seconds)

@@ -14,6 +14,16 @@ cubic_12.json    : 12x12x12 Ising, beta=0.22, chi=16, sweep tree (--big, ~10 min
                    unmodified oracle runs is the rounding sensitivity of this instance.
 cubic_12_chi32.json: the same network and tree at chi=32 (--chi32, ~30 min of CPU): the oracle's
                    ln|Z| only.
+cubic_6_chi64.json: 6x6x6 Ising, beta=0.22, chi=64, sweep tree (--cubic6-chi64): bonds of D = 4096
+                   against 262144-row factors; the oracle's ln|Z|.
+spin_glass_grad.json: L^3 +-J spin glass (SI F.1), beta = 0.5, couplings from default_rng(0), chi = 16,
+                   sweep tree, L = 4 and 6 (--spin-glass, ~5 min of CPU; --spin-glass-8 adds L = 8):
+                   the oracle's ln|Z| and d ln|Z| / d J for every bond (oracle.grad).
+random_graphs.json: the random-graph workloads of sections IV.B and IV.C on their Agglom trees
+                   (--random-graphs, ~5 min of CPU): dimer covers of random 3-regular graphs at
+                   N = 256, chi = 4 and N = 512, chi = 2; Normal(mu, 1) tensors of bond dimension
+                   3 on the N = 300 graph at chi = 2 for mu in {0, 0.1, 0.2, 0.5} and tensor seeds
+                   0..3.  ln|Z|, sign, compressions and ties per instance.
 """
 import json
 import os
@@ -98,6 +108,63 @@ def cubic_12_chi(chi):
             "oracle_lnZ": lnz, "cpu_seconds": time.time() - t0}
 
 
+def cubic_6_chi64():
+    """6^3 Ising, beta = 0.22, chi = 64 along the sweep tree: its corner merges give bonds of
+    D = 4096 (two chi-bonds), compressed against 262144-row factors."""
+    g = lattice((6, 6, 6))
+    T = ising_tensors(g, 0.22)
+    p = sweep_tree((6, 6, 6))
+    t0 = time.time()
+    r = oracle.contract_compressed(g.n, g.edges, T, p, 64)
+    comp = [o for o in r.ops if o.kind == "compress"]
+    return {"shape": [6, 6, 6], "beta": 0.22, "chi": 64, "tree": "sweep_tree((6, 6, 6))",
+            "oracle_lnZ": r.ln_abs_z, "compressions": len(comp), "ties": sum(o.tie for o in comp),
+            "max_bond": max(o.n for o in comp), "cpu_seconds": time.time() - t0}
+
+
+def spin_glass_grads(sizes, chi=16, beta=0.5):
+    from oracle.grad import ising_coupling_grad, lnz_and_grad
+    from tninputs.configs import pm_couplings
+    out = {"beta": beta, "chi": chi, "couplings": "pm_couplings(n_edges, 0)", "tree": "sweep_tree((L, L, L))",
+           "sizes": {}}
+    for L in sizes:
+        g = lattice((L, L, L))
+        J = pm_couplings(g.n_edges, 0)
+        t0 = time.time()
+        res = lnz_and_grad(g.n, g.edges, ising_tensors(g, beta, J), sweep_tree((L, L, L)), chi)
+        dJ = ising_coupling_grad(g.n, g.edges, beta, J, res.grads)
+        ref = oracle.contract_compressed(g.n, g.edges, ising_tensors(g, beta, J), sweep_tree((L, L, L)), chi)
+        comp = [o for o in ref.ops if o.kind == "compress"]
+        out["sizes"][str(L)] = {"oracle_lnZ": res.ln_abs_z, "sign": res.sign, "dlnZ_dJ": [float(x) for x in dJ],
+                                "compressions": len(comp), "ties": sum(o.tie for o in comp),
+                                "cpu_seconds": time.time() - t0}
+        print(f"spin glass L={L}: lnZ={res.ln_abs_z!r} ({time.time() - t0:.0f} s)", flush=True)
+    return out
+
+
+def _record(g, T, pairs, chi):
+    t0 = time.time()
+    r = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    comp = [o for o in r.ops if o.kind == "compress"]
+    return {"oracle_lnZ": r.ln_abs_z, "sign": r.sign, "compressions": len(comp),
+            "ties": sum(o.tie for o in comp), "cpu_seconds": time.time() - t0}
+
+
+def random_graphs():
+    from tninputs import configs
+    out = {"dimer": {}, "normal_d3_n300_chi2": {}}
+    for n, chi, ts in ((256, 4, 2), (512, 2, 2)):
+        out["dimer"][f"{n}"] = dict(_record(*configs.dimer_rrg(n, chi, tree_seed=ts), chi), chi=chi,
+                                    tree=f"agglom_tree(g, {chi}, k=4, seed={ts})")
+        print(f"dimer N={n}: {out['dimer'][str(n)]}", flush=True)
+    for mu in (0.0, 0.1, 0.2, 0.5):
+        for ts in range(4):
+            rec = _record(*configs.normal_rrg(300, mu, 2, tensor_seed=ts), 2)
+            out["normal_d3_n300_chi2"][f"{mu}/{ts}"] = rec
+            print(f"normal mu={mu} seed={ts}: {rec}", flush=True)
+    return out
+
+
 if __name__ == "__main__":
     def write(name, rec):   # computed first: a file is never left half-written
         with open(os.path.join(HERE, name), "w") as f:
@@ -112,3 +179,9 @@ if __name__ == "__main__":
         write("cubic_12.json", cubic_12_threads(rec))
     if "--chi32" in sys.argv:
         write("cubic_12_chi32.json", cubic_12_chi(32))
+    if "--cubic6-chi64" in sys.argv:
+        write("cubic_6_chi64.json", cubic_6_chi64())
+    if "--random-graphs" in sys.argv:
+        write("random_graphs.json", random_graphs())
+    if "--spin-glass" in sys.argv or "--spin-glass-8" in sys.argv:
+        write("spin_glass_grad.json", spin_glass_grads((4, 6, 8) if "--spin-glass-8" in sys.argv else (4, 6)))

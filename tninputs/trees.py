@@ -330,3 +330,158 @@ def sweep_tree(shape: Sequence[int], order: Optional[Sequence[int]] = None) -> L
         pairs.append((cur[u], cur[v]))
         cur[u] = n + t
     return pairs
+
+
+class _BondSim:
+    """Live tensors of a partially contracted network, on bond sizes only, with
+    every bond of a new tensor capped at chi (early compression); contractions
+    are emitted as tree pairs with fresh ids n, n + 1, ..."""
+
+    def __init__(self, g: Graph, chi: int):
+        self.chi = chi
+        nb = _bond_sizes(g)
+        self.bonds: Dict[int, Dict[int, int]] = {v: dict(nb[v]) for v in range(g.n)}
+        self.nxt = g.n
+        self.pairs: List[Tuple[int, int]] = []
+
+    def lsize(self, v: int) -> float:
+        return sum(math.log2(d) for d in self.bonds[v].values())
+
+    def merged_lsize(self, i: int, j: int) -> float:
+        merged: Dict[int, int] = {}
+        for src, other in ((self.bonds[i], j), (self.bonds[j], i)):
+            for l, d in src.items():
+                if l != other:
+                    merged[l] = merged.get(l, 1) * d
+        return sum(math.log2(min(d, self.chi)) for d in merged.values())
+
+    def contract(self, a: int, b: int) -> int:
+        k = self.nxt
+        self.nxt += 1
+        self.pairs.append((a, b))
+        bi, bj = self.bonds.pop(a), self.bonds.pop(b)
+        bk: Dict[int, int] = {}
+        for src, other in ((bi, b), (bj, a)):
+            for l, d in src.items():
+                if l != other:
+                    bk[l] = bk.get(l, 1) * d
+        for l in bk:
+            self.bonds[l].pop(a, None)
+            self.bonds[l].pop(b, None)
+            bk[l] = min(bk[l], self.chi)
+            self.bonds[l][k] = bk[l]
+        self.bonds[k] = bk
+        return k
+
+
+def _spectral_bisect(nodes: List[int], w: Dict[int, Dict[int, float]], rng, noise: float) -> Tuple[List[int], List[int]]:
+    """Split ``nodes`` into two halves of equal size (+-1) along the Fiedler vector of the
+    weighted Laplacian of the subgraph they induce, then improve the cut by pair swaps."""
+    n = len(nodes)
+    idx = {v: i for i, v in enumerate(nodes)}
+    Lap = np.zeros((n, n))
+    for v in nodes:
+        for u, x in w[v].items():
+            if u in idx:
+                Lap[idx[v], idx[u]] -= x
+                Lap[idx[v], idx[v]] += x
+    vals, vecs = np.linalg.eigh(Lap)
+    f = vecs[:, 1] if n > 1 else np.zeros(1)
+    f = f + noise * np.std(f) * rng.normal(size=n)
+    order = np.argsort(f, kind="stable")
+    side = np.zeros(n, dtype=np.int8)
+    side[order[n // 2:]] = 1
+    # Kernighan-Lin style passes: swap the best pair while the cut weight falls
+    for _ in range(4):
+        gain = np.zeros(n)
+        for v in nodes:
+            iv = idx[v]
+            for u, x in w[v].items():
+                if u in idx:
+                    gain[iv] += x if side[idx[u]] != side[iv] else -x
+        improved = False
+        for _ in range(max(1, n // 4)):
+            a = [i for i in range(n) if side[i] == 0]
+            b = [i for i in range(n) if side[i] == 1]
+            ia = max(a, key=lambda i: gain[i])
+            ib = max(b, key=lambda i: gain[i])
+            wab = w[nodes[ia]].get(nodes[ib], 0.0)
+            if gain[ia] + gain[ib] - 2 * wab <= 1e-12:
+                break
+            for i in (ia, ib):
+                v = nodes[i]
+                side[i] ^= 1
+                gain[i] = -gain[i]
+                for u, x in w[v].items():
+                    if u in idx and u != nodes[ia + ib - i]:
+                        j = idx[u]
+                        gain[j] += 2 * x if side[j] != side[i] else -2 * x
+            improved = True
+        if not improved:
+            break
+    left = [nodes[i] for i in range(n) if side[i] == 0]
+    right = [nodes[i] for i in range(n) if side[i] == 1]
+    return left, right
+
+
+def agglom_tree(g: Graph, chi: int, k: int = 8, seed: int = 0, noise: float = 0.05,
+                temperature: float = 0.1) -> List[Tuple[int, int]]:
+    """Agglom family (main text II.G, SI C.3) with recursive spectral bisection in
+    place of a hypergraph partitioner.
+
+    The live network is split into parts of about ``k`` tensors (recursive
+    bisection of the graph weighted by log2 bond size); each part is
+    contracted by Greedy moves restricted to its members, with every bond of a
+    new tensor capped at chi (the compression that early compression will
+    perform); the parts then form the coarse network of the next round, which
+    is partitioned again, until one tensor is left.  ``seed`` drives the noise
+    added to the Fiedler vectors and the Gumbel term of the Greedy score, so
+    that different seeds give different trees.
+    """
+    rng = np.random.default_rng(seed)
+    sim = _BondSim(g, chi)
+    while len(sim.bonds) > 1:
+        live = sorted(sim.bonds)
+        w = {v: {u: math.log2(d) + 1e-3 for u, d in sim.bonds[v].items()} for v in live}
+        parts = [live]
+        while max(len(p) for p in parts) > k:
+            nxt_parts = []
+            for p in parts:
+                if len(p) > k:
+                    nxt_parts.extend(_spectral_bisect(p, w, rng, noise))
+                else:
+                    nxt_parts.append(p)
+            parts = nxt_parts
+        progressed = False
+        for p in parts:
+            members = set(p)
+            while True:
+                best = None
+                for i in sorted(members):
+                    for j in sorted(sim.bonds[i]):
+                        if j in members and i < j:
+                            s = sim.merged_lsize(i, j) - sim.lsize(i) - sim.lsize(j) + temperature * _gumbel(rng)
+                            if best is None or s < best[0]:
+                                best = (s, i, j)
+                if best is None:
+                    break
+                _, i, j = best
+                members.discard(i)
+                members.discard(j)
+                members.add(sim.contract(i, j))
+                progressed = True
+        if not progressed:
+            # parts with no internal bond left: join the two smallest connected live tensors
+            best = None
+            for i in sorted(sim.bonds):
+                for j in sorted(sim.bonds[i]):
+                    if i < j:
+                        s = sim.merged_lsize(i, j)
+                        if best is None or s < best[0]:
+                            best = (s, i, j)
+            if best is None:   # disconnected components: outer products
+                rest = sorted(sim.bonds)
+                sim.contract(rest[0], rest[1])
+            else:
+                sim.contract(best[1], best[2])
+    return sim.pairs
