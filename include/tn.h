@@ -69,7 +69,11 @@ typedef struct {
     int32_t chi;                 /* maximum bond dimension (>= 1) */
     double cutoff;               /* relative singular-value cutoff: sigma_i < cutoff*sigma_1
                                     contributes a zero column/row (shapes stay static); 0 = none */
-    int32_t compress_late;       /* must be 0: early compression (Algorithm 1, "not compress_late") */
+    int32_t compress_late;       /* 0: early compression, every bond of a new tensor larger than chi
+                                    right after its contraction; 1: late compression (section II.D,
+                                    Algorithm 1 with compress_late), before contracting i and j every
+                                    other bond of i, then of j, larger than chi; ascending neighbour
+                                    id in both */
     int32_t gauge_r;             /* must be 0: compression uses only the two bond-adjacent tensors */
     int32_t precision;           /* tn_precision */
     int32_t jacobi_max_sweeps;   /* cap on one-sided Jacobi sweeps per core; 0 = default (40) */

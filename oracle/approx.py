@@ -1,11 +1,16 @@
 """Algorithm 1 of arXiv:2206.07044 ("Approximate contraction", section II.F),
-with gauge distance r = 0 and early compression — float64 numpy oracle.
+with gauge distance r = 0 and early (default) or late compression — float64
+numpy oracle.
 
 Test infrastructure only (see the package docstring).
 
 Readings of the paper used here (each is also listed in the design notes):
 * Several compressions after one contraction run in ascending neighbour id
   (Algorithm 1 loops over NEIGHBORS(T, k); the order is not fixed by the text).
+  Late compression (section II.D, Algorithm 1 with compress_late) compresses,
+  before contracting i and j, every bond of i to a tensor other than j that is
+  larger than chi, then every such bond of j, each in ascending neighbour id;
+  nothing is compressed after a contraction.
 * All edges between two tensors form one composite bond whose size is the
   product of their dimensions (BONDSIZE, Fig. "tensor primitives" A).
 * The new bond dimension is min(chi, k_A, k_B) with k = min(rows, D_AB), the
@@ -212,19 +217,21 @@ def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
 
 def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
                         pairs: Sequence[Tuple[int, int]], chi: Optional[int], cutoff: float = 0.0,
-                        explicit: bool = False, record: bool = False) -> OracleResult:
-    """Run Algorithm 1 (early compression, r = 0) and return sign and ln|Z|.
+                        explicit: bool = False, record: bool = False, compress_late: bool = False) -> OracleResult:
+    """Run Algorithm 1 (r = 0) and return sign and ln|Z|.
 
     ``chi=None`` is exact contraction (no compression).  Step t of ``pairs``
     contracts live tensors (i, j) into a new tensor with id n + t; after each
     contraction every bond of the new tensor larger than chi is compressed,
-    neighbours in ascending id.  With ``record`` every normalised tensor is
-    kept in creation order (inputs, then each op's outputs).
+    neighbours in ascending id (early compression), or, with
+    ``compress_late``, the bonds of i and j are compressed just before they
+    are contracted.  With ``record`` every normalised tensor is kept in
+    creation order (inputs, then each op's outputs).
     """
     global _RECORD
     _RECORD = [] if record else None
     try:
-        res = _run(n, edges, tensors, pairs, chi, cutoff, explicit)
+        res = _run(n, edges, tensors, pairs, chi, cutoff, explicit, late=compress_late)
     finally:
         rec, _RECORD = _RECORD, None
     if record:
@@ -283,7 +290,7 @@ class _OutOfTime(Exception):
 
 
 def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progress=None,
-         max_steps=None) -> OracleResult:
+         max_steps=None, late=False) -> OracleResult:
     import time
     net = _Network(n, edges, tensors)
     scales: List[float] = []
@@ -301,8 +308,13 @@ def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progres
             k = n + t
             if i == j or i not in net.t or j not in net.t:
                 raise ValueError(f"step {t}: ({i}, {j}) are not two live tensors")
+            if late and chi is not None:
+                for x, partner in ((i, j), (j, i)):
+                    for l, shared in sorted(net.neighbors(x).items()):
+                        if l != partner and int(np.prod([net.dim[e] for e in shared])) > chi:
+                            _compress(net, x, l, chi, cutoff, scales, ops, explicit)
             _contract(net, i, j, k, scales, ops)
-            if chi is None:
+            if chi is None or late:
                 continue
             for l, shared in sorted(net.neighbors(k).items()):
                 size = int(np.prod([net.dim[e] for e in shared]))

@@ -70,8 +70,10 @@ def _scale(arr: np.ndarray) -> float:
 
 
 def lnz_and_grad(n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
-                 pairs: Sequence[Tuple[int, int]], chi: int, cutoff: float = 0.0) -> GradResult:
-    """Forward pass of Algorithm 1 recording a tape, then its adjoint."""
+                 pairs: Sequence[Tuple[int, int]], chi: int, cutoff: float = 0.0,
+                 compress_late: bool = False) -> GradResult:
+    """Forward pass of Algorithm 1 recording a tape, then its adjoint (early or late compression,
+    in the order of oracle.approx)."""
     net = _Network(n, edges, tensors)
     tape: List[tuple] = []
     log_scales: List[float] = []
@@ -83,7 +85,14 @@ def lnz_and_grad(n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequenc
         net.t[v] = net.t[v] / s
     for t, (i, j) in enumerate(pairs):
         k = n + t
+        if compress_late:
+            for x, partner in ((i, j), (j, i)):
+                for l, shared in sorted(net.neighbors(x).items()):
+                    if l != partner and int(np.prod([net.dim[e] for e in shared])) > chi:
+                        tape.append(_compress_fwd(net, x, l, chi, cutoff, log_scales))
         tape.append(_contract_fwd(net, i, j, k, log_scales))
+        if compress_late:
+            continue
         for l, shared in sorted(net.neighbors(k).items()):
             if int(np.prod([net.dim[e] for e in shared])) > chi:
                 tape.append(_compress_fwd(net, k, l, chi, cutoff, log_scales))

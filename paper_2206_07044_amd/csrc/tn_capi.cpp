@@ -1228,7 +1228,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     if (!c->has_graph) return fail(c, TN_ESTATE, "tn_set_tree before tn_load_graph");
     if (!opts || (n_steps > 0 && (!pair_i || !pair_j))) return fail(c, TN_EINVAL, "missing tree arrays or options");
     if (opts->gauge_r != 0) return fail(c, TN_EINVAL, "gauge_r must be 0 (local compression only)");
-    if (opts->compress_late != 0) return fail(c, TN_EINVAL, "compress_late must be 0 (early compression)");
+    if (opts->compress_late != 0 && opts->compress_late != 1) return fail(c, TN_EINVAL, "compress_late must be 0 or 1");
     if (opts->precision != TN_FP64 && opts->precision != TN_FP32 && opts->precision != TN_BF16)
         return fail(c, TN_EINVAL, "precision must be TN_FP64, TN_FP32 or TN_BF16");
     if (!(opts->cutoff >= 0.0)) return fail(c, TN_EINVAL, "cutoff must be >= 0");
@@ -1243,6 +1243,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.keep = opts->keep_intermediates;
     o.grad = opts->grad ? 1 : 0;
     o.plain = opts->plain ? 1 : 0;
+    o.late = opts->compress_late;
     if (o.plain && o.grad) return fail(c, TN_EINVAL, "the plain form has no reverse pass (grad must be 0)");
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
     // level by level every independent branch advances at once; when that holds more than the
@@ -1786,10 +1787,12 @@ tn_status tn_plan_describe(int32_t n_tensors, int32_t n_edges, const int32_t* ed
     g.offsets.assign(n_tensors + 1, 0);
     for (int v = 0; v < n_tensors; ++v) g.offsets[v + 1] = g.offsets[v] + size[v];
     if (!check_graph(g).empty()) return TN_EINVAL;
+    if (opts->gauge_r != 0 || (opts->compress_late != 0 && opts->compress_late != 1)) return TN_EINVAL;
     TreeOpts o;
     o.chi = opts->chi;
     o.cutoff = opts->cutoff;
     o.precision = opts->precision;
+    o.late = opts->compress_late;
     Plan P;
     std::string err = build_plan(g, pair_i, pair_j, n_steps, o, true, &P);
     if (!err.empty()) return TN_EINVAL;

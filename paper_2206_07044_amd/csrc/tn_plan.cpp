@@ -336,83 +336,9 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
             return os.str();
         }
         const int32_t k = g.n + t;
-        // ---------------------------------------------------------- CONTRACT(i, j) -> k
-        {
-            const int32_t vi = live[i], vj = live[j];
-            const TensorVer Ti = P->tens[vi], Tj = P->tens[vj];
-            std::vector<int32_t> shared, free_i, free_j;
-            for (int e : Ti.legs) {
-                if (std::find(Tj.legs.begin(), Tj.legs.end(), e) != Tj.legs.end()) shared.push_back(e);
-                else free_i.push_back(e);
-            }
-            for (int e : Tj.legs)
-                if (std::find(shared.begin(), shared.end(), e) == shared.end()) free_j.push_back(e);
-            const int64_t m = prod_dims(free_i, E), s = prod_dims(shared, E), q = prod_dims(free_j, E);
-            if (m * q > kMaxElems) {
-                os << "step " << t << ": intermediate of " << m * q << " elements exceeds 2^31-1";
-                return os.str();
-            }
-            P->ops.push_back({0, i, j, k, m, s, q, 0});
-            TensorVer Tk;
-            Tk.legs = free_i;
-            Tk.legs.insert(Tk.legs.end(), free_j.begin(), free_j.end());
-            Tk.size = m * q;
-            if (!shapes_only) {
-                Step st;
-                st.kind = ST_CONTRACT;
-                st.level = 1 + std::max(Ti.level, Tj.level);
-                // ordered levelling: a tree step starts no earlier than the last level of the one
-                // before it (its compressions included), so independent branches do not all hold
-                // their uncompressed intermediates at once: the memory of a sequential run
-                if (o.ordered) st.level = std::max(st.level, last_step_level);
-                st.in_a = vi;
-                st.in_b = vj;
-                st.M = m;
-                st.N = q;
-                st.K = s;
-                st.va = tensor_view(Ti, free_i, shared, E);
-                st.vb = tensor_view(Tj, shared, free_j, E);
-                add_gemm_flops(st);
-                Tk.level = st.level;
-                Tk.buf = new_buf(Tk.size * w, BUF_TENSOR, st.level);
-                P->tens.push_back(Tk);
-                st.out_t = (int32_t)P->tens.size() - 1;
-                read_tensor(vi, st.level);
-                read_tensor(vj, st.level);
-                P->steps.push_back(st);
-                if (o.grad) {
-                    // C = A B:  A_bar = C_bar B^T / (s_C s_B),  B_bar = A^T C_bar / (s_A s_C)
-                    BwdOp op;
-                    op.outs[0] = st.out_t;
-                    op.ins[0] = vi;
-                    op.ins[1] = vj;
-                    const ViewSpec cbar = tensor_view(P->tens[st.out_t], free_i, free_j, E);
-                    op.done[0] = bwd_gemm(op, 1, adj_of(st.out_t), Tj.buf, adj_of(vi), cbar,
-                                          tensor_view(Tj, free_j, shared, E), st.va, m, s, q, st.out_t, vj, 0, true);
-                    op.done[1] = bwd_gemm(op, 1, Ti.buf, adj_of(st.out_t), adj_of(vj),
-                                          tensor_view(Ti, shared, free_i, E), cbar, st.vb, s, q, m, vi, st.out_t, 0,
-                                          true);
-                    bops.push_back(op);
-                }
-            } else {
-                P->tens.push_back(Tk);
-            }
-            for (int e : shared) E[e].alive = false;
-            for (int e : free_i) (E[e].end0 == i ? E[e].end0 : E[e].end1) = k;
-            for (int e : free_j) (E[e].end0 == j ? E[e].end0 : E[e].end1) = k;
-            live[i] = live[j] = -1;
-            live[k] = (int32_t)P->tens.size() - 1;
-        }
-        // ---------------------------------------------------------- early compression of k's bonds
-        std::map<int32_t, std::vector<int32_t>> nb;   // neighbour -> shared edges in k's axis order
-        for (int e : P->tens[live[k]].legs) {
-            const int32_t other = (E[e].end0 == k) ? E[e].end1 : E[e].end0;
-            nb[other].push_back(e);
-        }
-        for (auto& kv : nb) {
-            const int32_t l = kv.first;
-            if (prod_dims(kv.second, E) <= o.chi) continue;
-            const int32_t a = k, b = l;
+        // one bond compression between the live tensors a and b: COMPRESS_TREE_GAUGE of
+        // Algorithm 1 at r = 0 (the reduced factors of a and b alone), a's free legs as rows
+        auto compress_bond = [&](const int32_t a, const int32_t b) {
             const int32_t va = live[a], vb = live[b];
             const TensorVer Ta = P->tens[va], Tb = P->tens[vb];
             std::vector<int32_t> shared, free_a, free_b;
@@ -771,7 +697,93 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 live[b] = (int32_t)P->tens.size() - 1;
             }
             for (int e : shared) E[e].alive = false;
+        };
+        // neighbour -> shared edges (in x's axis order) of the live tensor x, ascending neighbour id
+        auto neighbours = [&](const int32_t x) {
+            std::map<int32_t, std::vector<int32_t>> nb;
+            for (int e : P->tens[live[x]].legs) nb[(E[e].end0 == x) ? E[e].end1 : E[e].end0].push_back(e);
+            return nb;
+        };
+        if (o.late) {
+            // late compression: before contracting i and j, every other bond of i, then of j,
+            // larger than chi (Algorithm 1 with compress_late)
+            for (const int32_t x : {i, j}) {
+                const int32_t partner = x == i ? j : i;
+                for (auto& kv : neighbours(x))
+                    if (kv.first != partner && prod_dims(kv.second, E) > o.chi) compress_bond(x, kv.first);
+            }
         }
+        // ---------------------------------------------------------- CONTRACT(i, j) -> k
+        {
+            const int32_t vi = live[i], vj = live[j];
+            const TensorVer Ti = P->tens[vi], Tj = P->tens[vj];
+            std::vector<int32_t> shared, free_i, free_j;
+            for (int e : Ti.legs) {
+                if (std::find(Tj.legs.begin(), Tj.legs.end(), e) != Tj.legs.end()) shared.push_back(e);
+                else free_i.push_back(e);
+            }
+            for (int e : Tj.legs)
+                if (std::find(shared.begin(), shared.end(), e) == shared.end()) free_j.push_back(e);
+            const int64_t m = prod_dims(free_i, E), s = prod_dims(shared, E), q = prod_dims(free_j, E);
+            if (m * q > kMaxElems) {
+                os << "step " << t << ": intermediate of " << m * q << " elements exceeds 2^31-1";
+                return os.str();
+            }
+            P->ops.push_back({0, i, j, k, m, s, q, 0});
+            TensorVer Tk;
+            Tk.legs = free_i;
+            Tk.legs.insert(Tk.legs.end(), free_j.begin(), free_j.end());
+            Tk.size = m * q;
+            if (!shapes_only) {
+                Step st;
+                st.kind = ST_CONTRACT;
+                st.level = 1 + std::max(Ti.level, Tj.level);
+                // ordered levelling: a tree step starts no earlier than the last level of the one
+                // before it (its compressions included), so independent branches do not all hold
+                // their uncompressed intermediates at once: the memory of a sequential run
+                if (o.ordered) st.level = std::max(st.level, last_step_level);
+                st.in_a = vi;
+                st.in_b = vj;
+                st.M = m;
+                st.N = q;
+                st.K = s;
+                st.va = tensor_view(Ti, free_i, shared, E);
+                st.vb = tensor_view(Tj, shared, free_j, E);
+                add_gemm_flops(st);
+                Tk.level = st.level;
+                Tk.buf = new_buf(Tk.size * w, BUF_TENSOR, st.level);
+                P->tens.push_back(Tk);
+                st.out_t = (int32_t)P->tens.size() - 1;
+                read_tensor(vi, st.level);
+                read_tensor(vj, st.level);
+                P->steps.push_back(st);
+                if (o.grad) {
+                    // C = A B:  A_bar = C_bar B^T / (s_C s_B),  B_bar = A^T C_bar / (s_A s_C)
+                    BwdOp op;
+                    op.outs[0] = st.out_t;
+                    op.ins[0] = vi;
+                    op.ins[1] = vj;
+                    const ViewSpec cbar = tensor_view(P->tens[st.out_t], free_i, free_j, E);
+                    op.done[0] = bwd_gemm(op, 1, adj_of(st.out_t), Tj.buf, adj_of(vi), cbar,
+                                          tensor_view(Tj, free_j, shared, E), st.va, m, s, q, st.out_t, vj, 0, true);
+                    op.done[1] = bwd_gemm(op, 1, Ti.buf, adj_of(st.out_t), adj_of(vj),
+                                          tensor_view(Ti, shared, free_i, E), cbar, st.vb, s, q, m, vi, st.out_t, 0,
+                                          true);
+                    bops.push_back(op);
+                }
+            } else {
+                P->tens.push_back(Tk);
+            }
+            for (int e : shared) E[e].alive = false;
+            for (int e : free_i) (E[e].end0 == i ? E[e].end0 : E[e].end1) = k;
+            for (int e : free_j) (E[e].end0 == j ? E[e].end0 : E[e].end1) = k;
+            live[i] = live[j] = -1;
+            live[k] = (int32_t)P->tens.size() - 1;
+        }
+        // ---------------------------------------------------------- early compression of k's bonds
+        if (!o.late)
+            for (auto& kv : neighbours(k))
+                if (prod_dims(kv.second, E) > o.chi) compress_bond(k, kv.first);
     }
     int32_t last = -1;
     for (int id = 0; id < total_ids; ++id)

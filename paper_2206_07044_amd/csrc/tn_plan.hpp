@@ -34,6 +34,7 @@ struct TreeOpts {
     int32_t grad = 0;               // plan the reverse pass too
     int32_t plain = 0;              // one launch per step, no streams, no graph (the plain form)
     int32_t ordered = 0;            // contraction levels follow the tree order (memory of a sequential run)
+    int32_t late = 0;               // late compression: bonds of i and j compressed before contracting them
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).

@@ -27,20 +27,20 @@ pytestmark = pytest.mark.gpu
 FP64_RTOL = 1e-10
 
 
-def _check(g, T, pairs, chi, precision="fp64", rtol=FP64_RTOL, min_comp=0, cutoff=0.0):
+def _check(g, T, pairs, chi, precision="fp64", rtol=FP64_RTOL, min_comp=0, cutoff=0.0, late=False):
     """GPU against the oracle on one instance.  ``min_comp``: the oracle must run at least
     that many compressions (a parity case that never compresses checks exact contraction
     only).  A truncation tie flagged by the oracle makes the value comparison meaningless
     (several truncations are correct), so such a case is reported as a skip, never as a pass."""
-    want = oracle.contract_compressed(g.n, g.edges, T, pairs, chi, cutoff=cutoff)
+    want = oracle.contract_compressed(g.n, g.edges, T, pairs, chi, cutoff=cutoff, compress_late=late)
     comp = [o for o in want.ops if o.kind == "compress"]
     ties = sum(o.tie for o in comp)
-    print(f"case n={g.n} chi={chi} cutoff={cutoff} {precision}: oracle ln|Z|={want.ln_abs_z!r} "
+    print(f"case n={g.n} chi={chi} cutoff={cutoff} late={late} {precision}: oracle ln|Z|={want.ln_abs_z!r} "
           f"sign={want.sign} compressions={len(comp)} ties={ties}", flush=True)
     assert len(comp) >= min_comp, f"only {len(comp)} compressions: the case does not test truncation"
     if ties:
         pytest.skip(f"{ties} truncation tie(s) in the oracle run: several values are correct")
-    sign, lnz, m, e, stats = gpu_eval(g, T, pairs, chi, precision, cutoff=cutoff)
+    sign, lnz, m, e, stats = gpu_eval(g, T, pairs, chi, precision, cutoff=cutoff, late=late)
     if want.sign == 0:
         assert sign == 0 and m == 0.0 and e == -math.inf
         return want, None

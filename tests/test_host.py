@@ -43,14 +43,14 @@ def test_create_without_device_reports_device_error():
     assert e.value.status in (tn.TN_EDEVICE, tn.TN_EINVAL)
 
 
-def _oracle_ops(g, T, pairs, chi):
-    r = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+def _oracle_ops(g, T, pairs, chi, late=False):
+    r = oracle.contract_compressed(g.n, g.edges, T, pairs, chi, compress_late=late)
     return [(0 if o.kind == "contract" else 1, o.a, o.b, o.out, o.m, o.n, o.k, o.new_dim) for o in r.ops]
 
 
-def _lib_ops(g, pairs, chi):
+def _lib_ops(g, pairs, chi, late=False):
     eu, ev, ed = g.arrays()
-    return tn.tn_plan_describe(g.n, eu, ev, ed, [a for a, _ in pairs], [b for _, b in pairs], chi)
+    return tn.tn_plan_describe(g.n, eu, ev, ed, [a for a, _ in pairs], [b for _, b in pairs], chi, late=late)
 
 
 CASES = [
@@ -69,6 +69,20 @@ def test_schedule_matches_oracle_expansion(name, mk_g, mk_t, mk_p, chis):
     pairs = mk_p(g)
     for chi in chis:
         assert _lib_ops(g, pairs, chi) == _oracle_ops(g, T, pairs, chi)
+
+
+@pytest.mark.parametrize("name,mk_g,mk_t,mk_p,chis", CASES, ids=[c[0] for c in CASES])
+def test_late_schedule_matches_oracle_expansion(name, mk_g, mk_t, mk_p, chis):
+    """Late compression (section II.D): the planner's op list equals the oracle's, and some
+    compression runs before a contraction of the same tensor (not after it)."""
+    g = mk_g()
+    T = mk_t(g)
+    pairs = mk_p(g)
+    for chi in chis:
+        ops = _lib_ops(g, pairs, chi, late=True)
+        assert ops == _oracle_ops(g, T, pairs, chi, late=True)
+        if any(o[0] == 1 for o in ops):
+            assert ops != _lib_ops(g, pairs, chi)
 
 
 def test_schedule_12cube_counts_match_tree_trace():

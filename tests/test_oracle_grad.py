@@ -144,3 +144,25 @@ def test_kept_degenerate_pairs_match_central_differences(sig):
         want = _fd_directional(g, T, pairs, chi, dT, 1e-6)
         got = sum(float(np.sum(gr * d)) for gr, d in zip(res.grads, dT))
         assert got == pytest.approx(want, rel=1e-6, abs=1e-8)
+
+
+LATE_CASES = [c for c in CASES if c[0] in ("ising-4x4-chi2", "pmJ-2x2x3-chi3", "normal-3x3-D3-chi2", "normal-rrg12-chi3")]
+
+
+@pytest.mark.parametrize("name,g,T,pairs,chi", LATE_CASES, ids=[c[0] for c in LATE_CASES])
+def test_late_compression_gradient_matches_central_differences(name, g, T, pairs, chi):
+    res = lnz_and_grad(g.n, g.edges, T, pairs, chi, compress_late=True)
+    ref = oracle.contract_compressed(g.n, g.edges, T, pairs, chi, compress_late=True)
+    assert res.ln_abs_z == pytest.approx(ref.ln_abs_z, rel=1e-13)
+    assert any(o.kind == "compress" for o in ref.ops)
+    rng = np.random.default_rng(12)
+    for _ in range(2):
+        dT = [rng.normal(size=t.shape) * np.max(np.abs(t)) for t in T]
+        plus = [t + 1e-5 * d for t, d in zip(T, dT)]
+        minus = [t - 1e-5 * d for t, d in zip(T, dT)]
+        fp = oracle.contract_compressed(g.n, g.edges, plus, pairs, chi, compress_late=True).ln_abs_z
+        fm = oracle.contract_compressed(g.n, g.edges, minus, pairs, chi, compress_late=True).ln_abs_z
+        got = sum(float(np.sum(gr * d)) for gr, d in zip(res.grads, dT))
+        assert got == pytest.approx((fp - fm) / 2e-5, rel=2e-6, abs=1e-8)
+    for t, gr in zip(T, res.grads):
+        assert float(np.sum(t * gr)) == pytest.approx(1.0, abs=1e-11)

@@ -13,7 +13,7 @@ import pytest
 import oracle
 from oracle import exact
 from oracle.approx import _Network, _compress
-from tninputs import (dimer_tensors, greedy_tree, ising_bond_factors, ising_tensors, lattice,
+from tninputs import (uniform_tensors, dimer_tensors, greedy_tree, ising_bond_factors, ising_tensors, lattice,
                       normal_tensors, random_regular3, Graph)
 from tninputs.trees import sweep_tree
 
@@ -382,3 +382,51 @@ def test_cutoff_is_relative_not_absolute():
     absolute, _ = _probe_value(a_mat, b_mat, caps, 3, cutoff / s[0])
     assert abs(math.log(abs(rel)) - math.log(abs(absolute))) > 1e-6
     assert abs(r.ln_abs_z - math.log(abs(rel))) < 1e-12
+
+
+# ---------------------------------------------------------------------------- late compression
+def test_late_compression_before_first_contraction_is_truncated_svd():
+    """Section II.D: with compress_late the bond between A and B of the one-compression probe is
+    compressed before A's first contraction, on A's own rows; the network's value is then
+    kron(P1, P2)^T trunc(A_mat B_mat) kron(Q1, Q2), the rank-chi' truncated SVD of the product."""
+    from tninputs.probes import bond_probe
+    rng = np.random.default_rng(17)
+    a_mat = rng.normal(size=(6, 8))
+    b_mat = rng.normal(size=(8, 6))
+    caps = [rng.normal(size=d) for d in (2, 3, 3, 2)]
+    g, T, pairs = bond_probe(a_mat, b_mat, (2, 4), (2, 3), (3, 2), caps)
+    for chi in (1, 2, 3, 5):
+        r = oracle.contract_compressed(g.n, g.edges, T, pairs, chi, compress_late=True)
+        assert r.ops[0].kind == "compress" and (r.ops[0].a, r.ops[0].b) == (0, 1)
+        U, s, Vt = np.linalg.svd(a_mat @ b_mat)
+        k = min(chi, 6)
+        want = np.kron(caps[0], caps[1]) @ ((U[:, :k] * s[:k]) @ Vt[:k]) @ np.kron(caps[2], caps[3])
+        assert r.sign == np.sign(want)
+        assert r.ln_abs_z == pytest.approx(math.log(abs(want)), rel=1e-12)
+
+
+@pytest.mark.parametrize("shape,beta", [((3, 3), 0.44), ((2, 2, 3), 0.3), ((3, 4), 0.6)])
+def test_late_compression_without_truncation_is_exact(shape, beta):
+    g = lattice(shape)
+    T = ising_tensors(g, beta)
+    r = oracle.contract_compressed(g.n, g.edges, T, sweep_tree(shape), 4096, compress_late=True)
+    assert r.ln_abs_z == pytest.approx(exact.ising_brute_force(g.n, g.edges, beta, None), rel=1e-13)
+
+
+def test_late_and_early_compress_at_different_points():
+    g = lattice((6, 6))
+    T = uniform_tensors(g, -0.5, 3)
+    pairs = sweep_tree((6, 6))
+    early = oracle.contract_compressed(g.n, g.edges, T, pairs, 2)
+    late = oracle.contract_compressed(g.n, g.edges, T, pairs, 2, compress_late=True)
+    ex = oracle.contract_compressed(g.n, g.edges, T, pairs, None)
+    kinds = lambda r: [o.kind for o in r.ops]
+    assert kinds(early) != kinds(late)
+    # after every contraction of the early schedule, a compression touches the new tensor only
+    assert all(o.a >= g.n for o in early.ops if o.kind == "compress")
+    # late: every compression acts on a tensor that the next contraction consumes
+    for t, o in enumerate(late.ops):
+        if o.kind == "compress":
+            nxt = next(p for p in late.ops[t:] if p.kind == "contract")
+            assert o.a in (nxt.a, nxt.b)
+    assert early.ln_abs_z != late.ln_abs_z and ex.sign != 0
