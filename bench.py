@@ -419,6 +419,113 @@ def normal_d3_leg(tn, torch, reps):
     return out
 
 
+def tree_scoring_leg(tn, torch):
+    """Device-side tree scoring (section II.H, SI C): 64 candidate trees of the 12x12 Ising network
+    (beta = 0.44, chi = 8) from the three generator families, planned on the host and evaluated
+    as batched hipGraph replays; each candidate's error against the stored transfer-matrix value."""
+    from tninputs import ising_tensors, lattice
+    from tninputs.trees import sample_trees, sweep_tree
+    ref = (_golden("square_12.json") or {}).get("transfer_matrix_lnZ")
+    g = lattice((12, 12))
+    T = ising_tensors(g, 0.44)
+    eu, ev, ed, off, data = flat(g, T)
+    cands = sample_trees(g, 8, 64, seed=0)
+    scorer = tn.TreeScorer(g.n, eu, ev, ed, off, data, 8, device_budget_bytes=4 << 30)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scores = scorer.score([p for _, p in cands], ref_ln_abs_z=ref, chunk=64)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = [(s, lab) for s, (lab, _) in zip(scores, cands) if s.status == 0]
+    out = {"lattice": [12, 12], "beta": 0.44, "chi": 8, "candidates": len(cands), "evaluated": len(ok),
+           "rejected": len(cands) - len(ok), "seconds_incl_planning": dt, "candidates_per_s": len(cands) / dt,
+           "reference": "transfer matrix (tests/golden/square_12.json)"}
+    if ref is not None and ok:
+        errs = sorted(s.rel_error for s, _ in ok)
+        best = min(ok, key=lambda x: x[0].rel_error)
+        sweep = scorer.score([sweep_tree((12, 12))], ref_ln_abs_z=ref)[0]
+        cheap = [x for x in ok if x[0].fwd_flops <= sweep.fwd_flops]
+        out.update({"best_rel_error": errs[0], "median_rel_error": errs[len(errs) // 2], "best_tree": best[1],
+                    "best_tree_fwd_flops": best[0].fwd_flops, "sweep_tree_rel_error": sweep.rel_error,
+                    "sweep_tree_fwd_flops": sweep.fwd_flops})
+        if cheap:
+            cb = min(cheap, key=lambda x: x[0].rel_error)
+            out["best_rel_error_at_most_sweep_flops"] = cb[0].rel_error
+            out["best_tree_at_most_sweep_flops"] = cb[1]
+    return out
+
+
+def hardness_leg(tn, torch):
+    """The URand hardness transition of section IV.C: entries uniform in [lambda, 1] on the
+    16x16 square lattice with D = 4 (axis sweep tree) and on the 6x6x6(x2) diamond lattice with
+    D = 2 ('span-corner' tree), 4 tensor seeds per lambda, float64.  No exact value exists at these
+    sizes here, so the error column is the change of ln|Z| from chi to 2 chi and the sign
+    agreement of the two."""
+    from tninputs import configs
+    out = {}
+    for kind, shape, D, chi, tree in (("square", (16, 16), 4, 32, "span"), ("diamond", (6, 6, 6), 2, 8, "span-corner")):
+        rec = {"shape": list(shape), "D": D, "chi": [chi, 2 * chi], "tree": tree, "seeds": 4, "lambda": {}}
+        t0 = time.perf_counter()
+        for lam in (-1.0, -0.8, -0.7, -0.6, -0.5, -0.2, 0.0):
+            vals = {}
+            for c_ in (chi, 2 * chi):
+                ctxs = []
+                for sd in range(4):
+                    g, T, pairs = configs.urand_lattice(kind, shape, lam, c_, seed=sd, D=D, tree=tree)
+                    ctxs.append(_load(tn, g, T, pairs, c_, "fp64"))
+                batch = tn.Batch(ctxs)
+                try:
+                    mant, _ = batch.tn_batch_contract()
+                finally:
+                    batch.close()
+                vals[c_] = [c.tn_result() if m != 0.0 else (0.0, -math.inf) for c, m in zip(ctxs, mant)]
+                for c in ctxs:
+                    c.close()
+            d = [abs(a[1] - b[1]) / abs(b[1]) for a, b in zip(vals[chi], vals[2 * chi])]
+            rec["lambda"][str(lam)] = {"median_rel_dlnz_chi_vs_2chi": float(np.median(d)),
+                                       "sign_agreement": sum(a[0] == b[0] for a, b in zip(vals[chi], vals[2 * chi])) / 4,
+                                       "fraction_negative_2chi": sum(b[0] < 0 for b in vals[2 * chi]) / 4}
+        rec["seconds"] = time.perf_counter() - t0
+        out[f"{kind}"] = rec
+    return out
+
+
+def pyrochlore_leg(tn, torch, L=6, chi=4, beta=0.22, h=0.005):
+    """The ferromagnetic pyrochlore Ising model of section IV.A on L^3 x 4 sites ('span-corner'
+    tree): -beta f = ln Z / N at three inverse temperatures, its first derivative from the reverse
+    pass (d ln Z / d beta = (1/beta) sum_e J_e d ln Z / d J_e, J = 1) and the second derivative
+    d^2(-beta f)/d beta^2 by central differences of the first, float64 gradient plans."""
+    from tninputs import configs
+    g, T, pairs = configs.pyrochlore_ising(L, beta, chi)
+    eu, ev, ed, off, data = flat(g, T)
+    c = tn.Context(0)
+    c.tn_load_graph(g.n, eu, ev, ed, off, data)
+    c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, precision="fp64", grad=True)
+    J = torch.ones(g.n_edges, dtype=torch.float64, device="cuda")
+    dT = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+    dJ = torch.empty(g.n_edges, dtype=torch.float64, device="cuda")
+    rows = []
+    t0 = time.perf_counter()
+    for b in (beta - h, beta, beta + h):
+        torch.cuda.synchronize()
+        c.tn_ising_values_device(b, J.data_ptr())
+        c.tn_contract_compressed()
+        _, lnz = c.tn_result()
+        c.tn_grad_device(dT.data_ptr())
+        c.tn_ising_coupling_grad_device(b, J.data_ptr(), dT.data_ptr(), dJ.data_ptr())
+        c.tn_sync()
+        rows.append((b, lnz / g.n, float(dJ.sum().item()) / (b * g.n)))
+    dt = time.perf_counter() - t0
+    info = c.tn_plan_info()
+    c.close()
+    return {"L": L, "sites": g.n, "chi": chi, "beta": beta, "h": h, "arena_bytes": info["arena_bytes"],
+            "minus_beta_f": {f"{b:.4f}": v for b, v, _ in rows},
+            "d_minus_beta_f_dbeta": {f"{b:.4f}": d for b, _, d in rows},
+            "d2_minus_beta_f_dbeta2": (rows[2][2] - rows[0][2]) / (2 * h),
+            "d2_by_second_difference_of_lnZ": (rows[2][1] - 2 * rows[1][1] + rows[0][1]) / h ** 2,
+            "seconds_3_fwd_bwd": dt}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -428,16 +535,20 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--shape", default="12,12,12")
     ap.add_argument("--beta", type=float, default=0.22)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--fwd-bwd-steps", type=int, default=1, help="timed forward+reverse passes (0: skip)")
     ap.add_argument("--batch", type=int, default=8, help="instances in the batched leg (<= 1: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--per-chi", default="32,64", help="other chi values timed in fp32 and fp64 ('' to skip)")
+    ap.add_argument("--per-chi", default="32", help="other chi values timed in fp32 and fp64 ('' to skip)")
+    ap.add_argument("--full", action="store_true",
+                    help="also chi = 64 in the per-chi leg and the URand hardness sweep (several minutes more)")
     ap.add_argument("--no-small", action="store_true", help="skip the 8x8 Ising leg")
     ap.add_argument("--spin-glass", default="16,16", help="L,chi of the +-J spin-glass forward+reverse leg ('' to skip)")
     ap.add_argument("--no-random-graphs", action="store_true", help="skip the dimer and Normal(mu) random-graph legs")
+    ap.add_argument("--no-tree-scoring", action="store_true", help="skip the device-side tree-scoring leg")
+    ap.add_argument("--no-second-workloads", action="store_true", help="skip the pyrochlore leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -598,6 +709,8 @@ def main() -> int:
             c.close()
 
     chis = [int(x) for x in args.per_chi.split(",") if x.strip() and int(x) != args.chi]
+    if args.full and 64 not in chis and args.chi != 64:
+        chis.append(64)
     if chis:
         # the same lattice and tree at other bond dimensions: time per tree and ln|Z| against the
         # FP64 oracle, for the float32 and the float64 form
@@ -674,6 +787,14 @@ def main() -> int:
 
     if not args.no_small:
         out["ising_8x8"] = ising_8x8_leg(tn, torch, 5)
+
+    if args.full:
+        out["urand_hardness"] = hardness_leg(tn, torch)
+    if not args.no_second_workloads:
+        out["pyrochlore_ising"] = pyrochlore_leg(tn, torch)
+
+    if not args.no_tree_scoring:
+        out["tree_scoring"] = tree_scoring_leg(tn, torch)
 
     if not args.no_random_graphs:
         out["dimer_rrg"] = dimer_leg(tn, torch, 3)

@@ -2,12 +2,14 @@
 
 Evaluates Algorithm 1 of Gray & Chan, "Hyper-optimized approximate
 contraction of tensor networks with arbitrary geometry" (arXiv:2206.07044),
-with early compression and local (r = 0) QR-reduced truncated-SVD bond
-compression, in hand-written HIP kernels for gfx950 behind the C ABI of
+with early or late compression and local (r = 0) QR-reduced truncated-SVD
+bond compression, in hand-written HIP kernels for gfx950 behind the C ABI of
 include/tn.h.  This package is the thin Python binding of that library.
 """
 from ._capi import (Batch, Context, TNError, load_library, tn_plan_describe, exported_symbols, LIB_PATH, KERNEL_KINDS,
                     TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO)
+from .scoring import TreeScore, TreeScorer
 
 __all__ = ["Batch", "Context", "TNError", "load_library", "tn_plan_describe", "exported_symbols", "LIB_PATH", "KERNEL_KINDS",
-           "TN_OK", "TN_EINVAL", "TN_ESTATE", "TN_ENOMEM", "TN_EDEVICE", "TN_ENUMERIC", "TN_ZERO"]
+           "TN_OK", "TN_EINVAL", "TN_ESTATE", "TN_ENOMEM", "TN_EDEVICE", "TN_ENUMERIC", "TN_ZERO",
+           "TreeScore", "TreeScorer"]

@@ -19,6 +19,8 @@ cubic_6_chi64.json: 6x6x6 Ising, beta=0.22, chi=64, sweep tree (--cubic6-chi64):
 spin_glass_grad.json: L^3 +-J spin glass (SI F.1), beta = 0.5, couplings from default_rng(0), chi = 16,
                    sweep tree, L = 4 and 6 (--spin-glass, ~5 min of CPU; --spin-glass-8 adds L = 8):
                    the oracle's ln|Z| and d ln|Z| / d J for every bond (oracle.grad).
+square_12.json   : 12x12 open-boundary Ising, beta = 0.44: the transfer-matrix ln Z (--square12), the
+                   reference of the tree-scoring leg.
 random_graphs.json: the random-graph workloads of sections IV.B and IV.C on their Agglom trees
                    (--random-graphs, ~5 min of CPU): dimer covers of random 3-regular graphs at
                    N = 256, chi = 4 and N = 512, chi = 2; Normal(mu, 1) tensors of bond dimension
@@ -142,6 +144,10 @@ def spin_glass_grads(sizes, chi=16, beta=0.5):
     return out
 
 
+def square_12():
+    return {"shape": [12, 12], "beta": 0.44, "transfer_matrix_lnZ": exact.ising_transfer_matrix((12, 12), 0.44)}
+
+
 def _record(g, T, pairs, chi):
     t0 = time.time()
     r = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
@@ -181,6 +187,8 @@ if __name__ == "__main__":
         write("cubic_12_chi32.json", cubic_12_chi(32))
     if "--cubic6-chi64" in sys.argv:
         write("cubic_6_chi64.json", cubic_6_chi64())
+    if "--square12" in sys.argv:
+        write("square_12.json", square_12())
     if "--random-graphs" in sys.argv:
         write("random_graphs.json", random_graphs())
     if "--spin-glass" in sys.argv or "--spin-glass-8" in sys.argv:

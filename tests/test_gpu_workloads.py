@@ -91,3 +91,43 @@ def test_dimer_reduced_precision(precision):
 def test_urand_lattices(kind, shape, lam, chi, tree):
     g, T, pairs = configs.urand_lattice(kind, shape, lam, chi, tree=tree)
     _check(g, T, pairs, chi, min_comp=5)
+
+
+@pytest.mark.parametrize("L,chi,beta", [(2, 8, 0.22), (3, 4, 0.25)])
+def test_pyrochlore_ising_value_and_gradient(L, chi, beta):
+    """Section IV.A's pyrochlore Ising model: ln Z and d ln Z / d J on every bond against the
+    oracle (the bench's d(-beta f)/d beta comes from this gradient)."""
+    import torch
+    from oracle.grad import ising_coupling_grad, lnz_and_grad
+    import paper_2206_07044_amd as tn
+    g, T, pairs = configs.pyrochlore_ising(L, beta, chi)
+    want = lnz_and_grad(g.n, g.edges, T, pairs, chi)
+    ref = oracle.contract_compressed(g.n, g.edges, T, pairs, chi)
+    if any(o.tie for o in ref.ops if o.kind == "compress"):
+        pytest.skip("truncation tie")
+    assert any(o.kind == "compress" for o in ref.ops)
+    dJ_want = ising_coupling_grad(g.n, g.edges, beta, np.ones(g.n_edges), want.grads)
+    eu, ev, ed = g.arrays()
+    off = np.zeros(g.n + 1, dtype=np.int64)
+    off[1:] = np.cumsum([t.size for t in T])
+    c = tn.Context(0)
+    try:
+        c.tn_load_graph(g.n, eu, ev, ed, off, np.concatenate([t.ravel() for t in T]))
+        c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, grad=True)
+        J = torch.ones(g.n_edges, dtype=torch.float64, device="cuda")
+        dT = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+        dJ = torch.empty(g.n_edges, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        c.tn_ising_values_device(beta, J.data_ptr())
+        c.tn_contract_compressed()
+        sign, lnz = c.tn_result()
+        c.tn_grad_device(dT.data_ptr())
+        c.tn_ising_coupling_grad_device(beta, J.data_ptr(), dT.data_ptr(), dJ.data_ptr())
+        c.tn_sync()
+        got = dJ.cpu().numpy()
+    finally:
+        c.close()
+    print(f"pyrochlore L={L} chi={chi}: lnZ {lnz!r} oracle {want.ln_abs_z!r}; "
+          f"max|dJ - oracle| {np.max(np.abs(got - dJ_want)):.2e}", flush=True)
+    assert abs(lnz - want.ln_abs_z) <= 1e-10 * abs(want.ln_abs_z)
+    assert np.max(np.abs(got - dJ_want)) <= 1e-9 * np.max(np.abs(dJ_want))

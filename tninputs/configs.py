@@ -14,6 +14,7 @@ comes from ``numpy.random.default_rng`` with the seed given.
                        (section IV.C, SI F.2), Agglom-family tree.
 * ``urand_lattice``    URand tensors, entries uniform in [lambda, 1] (section III), on the
                        square, cubic, diamond or pyrochlore lattice.
+* ``pyrochlore_ising`` ferromagnetic Ising model on the pyrochlore lattice (section IV.A).
 """
 from __future__ import annotations
 
@@ -72,10 +73,27 @@ def urand_lattice(kind: str, shape: Sequence[int], lam: float, chi: int, seed: i
     else:
         raise ValueError(f"unknown lattice {kind!r}")
     T = uniform_tensors(g, lam, seed)
+    return g, T, lattice_tree(g, kind, shape, chi, tree)
+
+
+def lattice_tree(g: Graph, kind: str, shape: Sequence[int], chi: int, tree: str = "span") -> List[Tuple[int, int]]:
+    """'span': the axis sweep on square/cubic lattices, else span_tree(g, seed=0); 'span-corner':
+    span_tree grown from the least central vertex with distance-only scoring (no connectivity
+    term, no noise), the boundary-like sweep that keeps diamond and pyrochlore intermediates
+    small; 'greedy' and 'agglom': those families with seed 0."""
     if tree == "span":
         pairs = sweep_tree(shape) if kind in ("square", "cubic") else span_tree(g, seed=0)
+    elif tree == "span-corner":
+        pairs = span_tree(g, seed=0, start="min", temperature=0.0, w_connectivity=0.0)
     elif tree == "greedy":
         pairs = greedy_tree(g, chi, 0)
     else:
         pairs = agglom_tree(g, chi, seed=0)
-    return g, T, pairs
+    return pairs
+
+
+def pyrochlore_ising(L: int, beta: float, chi: int) -> Workload:
+    """Ferromagnetic Ising model (J = 1, spins along one common axis) on the L^3 x 4 pyrochlore
+    lattice of section IV.A, on the 'span-corner' tree."""
+    g = pyrochlore((L, L, L))
+    return g, ising_tensors(g, beta), lattice_tree(g, "pyrochlore", (L, L, L), chi, "span-corner")

@@ -485,3 +485,29 @@ def agglom_tree(g: Graph, chi: int, k: int = 8, seed: int = 0, noise: float = 0.
             else:
                 sim.contract(best[1], best[2])
     return sim.pairs
+
+
+def sample_trees(g: Graph, chi: int, count: int, seed: int = 0) -> List[Tuple[str, List[Tuple[int, int]]]]:
+    """Candidate trees for a host-side search (section II.H): ``count`` draws over the three
+    generator families with seeded hyper-parameters (Greedy: temperature and the simulated bond
+    dimension chi_greedy of SI C.1; Span: start vertex, temperature and score weights of SI C.2;
+    Agglom: part size k of SI C.3).  Returns (label, pairs) per candidate."""
+    rng = np.random.default_rng(seed)
+    out: List[Tuple[str, List[Tuple[int, int]]]] = []
+    for c in range(count):
+        fam = c % 3
+        s = int(rng.integers(0, 2 ** 31))
+        if fam == 0:
+            temp = float(rng.choice([0.0, 0.1, 0.25, 0.5, 1.0]))
+            chi_g = int(rng.choice([2, chi, 4 * chi]))
+            out.append((f"greedy(chi_g={chi_g}, T={temp}, seed={s})", greedy_tree(g, chi_g, s, temperature=temp)))
+        elif fam == 1:
+            start = str(rng.choice(["max", "min"]))
+            temp = float(rng.choice([0.0, 0.05, 0.2]))
+            wc = float(rng.choice([0.0, 0.5, 1.0]))
+            out.append((f"span(start={start}, T={temp}, w_conn={wc}, seed={s})",
+                        span_tree(g, seed=s, start=start, temperature=temp, w_connectivity=wc)))
+        else:
+            k = int(rng.choice([4, 8, 16]))
+            out.append((f"agglom(k={k}, seed={s})", agglom_tree(g, chi, k=k, seed=s)))
+    return out
