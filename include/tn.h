@@ -4,8 +4,8 @@
  * The library evaluates Z, the scalar value of a closed tensor network
  * (Gray & Chan, arXiv:2206.07044, section I, Eq. (tncontract)), along a
  * fixed ordered contraction tree with bond compression: Algorithm 1
- * ("Approximate contraction", section II.F) with early compression and tree
- * gauge distance r = 0.  Each compression replaces every edge shared by two
+ * ("Approximate contraction", section II.F) with early or late compression
+ * and tree-gauge distance r >= 0.  Each compression replaces every edge shared by two
  * tensors with one edge of dimension chi' = min(chi, k_A, k_B) using the
  * reduced truncated SVD of section II.C, Eq. (svd), applied through the
  * projectors P_L = R_B V s^-1/2 and P_R = s^-1/2 U^T R_A of SI section B.
@@ -74,7 +74,14 @@ typedef struct {
                                     Algorithm 1 with compress_late), before contracting i and j every
                                     other bond of i, then of j, larger than chi; ascending neighbour
                                     id in both */
-    int32_t gauge_r;             /* must be 0: compression uses only the two bond-adjacent tensors */
+    int32_t gauge_r;             /* tree-gauge distance r >= 0 (section II.C, SI A).  0: a compression
+                                    uses the two bond-adjacent tensors alone.  r >= 1: their R factors
+                                    come from the bond placed in the tree gauge of the r-local spanning
+                                    tree of live intermediate tensors around it (input tensors are not
+                                    spanned; candidates by distance, then larger bond, then smaller ids);
+                                    the projectors act on the two tensors themselves.  Computed as
+                                    environment metrics (Grams with the children's metrics applied)
+                                    on the Gram + core path for every bond size.  Not with grad. */
     int32_t precision;           /* tn_precision */
     int32_t jacobi_max_sweeps;   /* cap on one-sided Jacobi sweeps per core; 0 = default (40) */
     int64_t device_budget_bytes; /* refuse plans whose device arena exceeds this; 0 = no limit */

@@ -1,6 +1,6 @@
 """Algorithm 1 of arXiv:2206.07044 ("Approximate contraction", section II.F),
-with gauge distance r = 0 and early (default) or late compression — float64
-numpy oracle.
+with early (default) or late compression and tree-gauge distance r >= 0 —
+float64 numpy oracle.
 
 Test infrastructure only (see the package docstring).
 
@@ -155,13 +155,16 @@ def _reduced_factors(a_mat: np.ndarray, b_mat: np.ndarray):
 
 
 def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
-              scales: List[float], ops: List[OpRecord], explicit: bool) -> None:
+              scales: List[float], ops: List[OpRecord], explicit: bool, gauged=None) -> None:
     """Compress every edge between a and b into one edge of dimension chi'.
 
     QR-reduced form: R_AB = R_A R_B ~ U s V^T truncated to chi' values
     (Eq. (svd)); projectors P_L = R_B V s^-1/2 and P_R = s^-1/2 U^T R_A
     (SI B) give a' = A P_L and b' = P_R B.  With ``explicit`` the SVD is of
     the full product A B instead (the definition the QR form is equal to).
+    ``gauged`` = (A'_mat, B'_mat): the R factors come from these tree-gauged
+    virtual copies (section II.C, SI A) while the projectors still act on the
+    tensors themselves; chi' keeps the shape bound of A_mat and B_mat.
     """
     la, lb = net.legs[a], net.legs[b]
     shared = [e for e in la if e in lb]
@@ -176,10 +179,19 @@ def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
     if explicit:
         U, sig, Vt = np.linalg.svd(a_mat @ b_mat, full_matrices=False)
         ka, kb = min(ma, D), min(mb, D)
-    else:
+    elif gauged is None:
         r_a, r_b = _reduced_factors(a_mat, b_mat)
         ka, kb = r_a.shape[0], r_b.shape[1]
         U, sig, Vt = np.linalg.svd(r_a @ r_b, full_matrices=False)
+    else:
+        r_a, r_b = _reduced_factors(*gauged)
+        ka, kb = min(ma, D), min(mb, D)
+        U, sig, Vt = np.linalg.svd(r_a @ r_b, full_matrices=False)
+        short = min(chi, ka, kb) - len(sig)
+        if short > 0:   # the gauged factors have lower rank: the missing triplets are zeros
+            U = np.hstack([U, np.zeros((U.shape[0], short))])
+            Vt = np.vstack([Vt, np.zeros((short, Vt.shape[1]))])
+            sig = np.concatenate([sig, np.zeros(short)])
     new = min(chi, ka, kb)
     total = float(np.sum(sig ** 2))
     disc = float(np.sum(sig[new:] ** 2)) / total if total > 0 else 0.0
@@ -215,9 +227,78 @@ def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
     net.t[b] = _normalise(new_b.reshape(db), scales)
 
 
+def _bond_size(net: _Network, u: int, v: int) -> int:
+    return int(np.prod([net.dim[e] for e in net.legs[u] if e in net.legs[v]]))
+
+
+def _local_spanning_tree(net: _Network, a: int, b: int, r: int, n_inputs: int) -> List[Tuple[int, int]]:
+    """The r-local spanning tree of SI A grown from S0 = {a, b}: repeatedly the best candidate
+    pair (u in S, v outside) is taken, best = smallest distance from S0, then the largest bond
+    between u and v (the connectivity the SI prefers), then the smallest v, then the smallest u;
+    v joins while its distance is at most r.  Input tensors (ids below n_inputs) are not spanned
+    (SI A excludes them).  Returns the pairs (u, v) in the order they were added."""
+    import heapq
+    S = {a, b}
+    cand: list = []
+    for u in (a, b):
+        for v in sorted(net.neighbors(u)):
+            if v not in S:
+                heapq.heappush(cand, (1, -_bond_size(net, u, v), v, u))
+    tau: List[Tuple[int, int]] = []
+    while cand:
+        d, _, v, u = heapq.heappop(cand)
+        if v in S or d > r or v < n_inputs:
+            continue
+        S.add(v)
+        tau.append((u, v))
+        for w in sorted(net.neighbors(v)):
+            if w not in S:
+                heapq.heappush(cand, (d + 1, -_bond_size(net, v, w), w, v))
+    return tau
+
+
+def _tree_gauged_matrices(net: _Network, a: int, b: int, tau: List[Tuple[int, int]]):
+    """Put the bond (a, b) in the tree gauge on virtual copies (section II.C, SI A): for the pairs
+    of tau in reverse order (outer tensor v first), the R factor of v's copy matricised against
+    its bond to u is absorbed into u's copy; returns A'_mat (rows: every other leg of a's copy)
+    and B'_mat (columns: every other leg of b's copy), the bond legs in a's order."""
+    virt: Dict[int, Tuple[np.ndarray, List[int]]] = {}
+    next_virtual = [-1]
+
+    def get(x):
+        return virt[x] if x in virt else (net.t[x], list(net.legs[x]))
+
+    for u, v in reversed(tau):
+        arr, legs = get(v)
+        bond = [e for e in legs if e in net.legs[u]]          # original u-v edges, v's order
+        rest = [e for e in legs if e not in bond]
+        D = int(np.prod([net.dim[e] for e in bond]))
+        mat = np.transpose(arr, [legs.index(e) for e in rest + bond]).reshape(-1, D)
+        R = np.linalg.qr(mat, mode="r") if mat.shape[0] > D else mat      # k x D
+        uarr, ulegs = get(u)
+        Rt = R.reshape([R.shape[0]] + [net.dim[e] for e in bond])
+        out = np.tensordot(Rt, uarr, axes=(list(range(1, 1 + len(bond))), [ulegs.index(e) for e in bond]))
+        new_leg = next_virtual[0]
+        next_virtual[0] -= 1
+        virt[u] = (out, [new_leg] + [e for e in ulegs if e not in bond])
+    la = net.legs[a]
+    shared = [e for e in la if e in net.legs[b]]
+    mats = []
+    for x, first in ((a, False), (b, True)):
+        arr, legs = get(x)
+        rest = [e for e in legs if e not in shared]
+        D = int(np.prod([net.dim[e] for e in shared]))
+        if first:
+            mats.append(np.transpose(arr, [legs.index(e) for e in shared + rest]).reshape(D, -1))
+        else:
+            mats.append(np.transpose(arr, [legs.index(e) for e in rest + shared]).reshape(-1, D))
+    return mats[0], mats[1]
+
+
 def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
                         pairs: Sequence[Tuple[int, int]], chi: Optional[int], cutoff: float = 0.0,
-                        explicit: bool = False, record: bool = False, compress_late: bool = False) -> OracleResult:
+                        explicit: bool = False, record: bool = False, compress_late: bool = False,
+                        gauge_r: int = 0) -> OracleResult:
     """Run Algorithm 1 (r = 0) and return sign and ln|Z|.
 
     ``chi=None`` is exact contraction (no compression).  Step t of ``pairs``
@@ -225,13 +306,14 @@ def contract_compressed(n: int, edges: Sequence[Tuple[int, int, int]], tensors: 
     contraction every bond of the new tensor larger than chi is compressed,
     neighbours in ascending id (early compression), or, with
     ``compress_late``, the bonds of i and j are compressed just before they
-    are contracted.  With ``record`` every normalised tensor is kept in
-    creation order (inputs, then each op's outputs).
+    are contracted.  ``gauge_r`` > 0 computes every compression's R factors in
+    the tree gauge of distance r (COMPRESS_TREE_GAUGE).  With ``record`` every
+    normalised tensor is kept in creation order (inputs, then each op's outputs).
     """
     global _RECORD
     _RECORD = [] if record else None
     try:
-        res = _run(n, edges, tensors, pairs, chi, cutoff, explicit, late=compress_late)
+        res = _run(n, edges, tensors, pairs, chi, cutoff, explicit, late=compress_late, gauge_r=gauge_r)
     finally:
         rec, _RECORD = _RECORD, None
     if record:
@@ -290,7 +372,7 @@ class _OutOfTime(Exception):
 
 
 def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progress=None,
-         max_steps=None, late=False) -> OracleResult:
+         max_steps=None, late=False, gauge_r=0) -> OracleResult:
     import time
     net = _Network(n, edges, tensors)
     scales: List[float] = []
@@ -308,18 +390,26 @@ def _run(n, edges, tensors, pairs, chi, cutoff, explicit, deadline=None, progres
             k = n + t
             if i == j or i not in net.t or j not in net.t:
                 raise ValueError(f"step {t}: ({i}, {j}) are not two live tensors")
+            def compress(x, l):
+                gauged = None
+                if gauge_r > 0:
+                    tau = _local_spanning_tree(net, x, l, gauge_r, n)
+                    if tau:
+                        gauged = _tree_gauged_matrices(net, x, l, tau)
+                _compress(net, x, l, chi, cutoff, scales, ops, explicit, gauged)
+
             if late and chi is not None:
                 for x, partner in ((i, j), (j, i)):
                     for l, shared in sorted(net.neighbors(x).items()):
                         if l != partner and int(np.prod([net.dim[e] for e in shared])) > chi:
-                            _compress(net, x, l, chi, cutoff, scales, ops, explicit)
+                            compress(x, l)
             _contract(net, i, j, k, scales, ops)
             if chi is None or late:
                 continue
             for l, shared in sorted(net.neighbors(k).items()):
                 size = int(np.prod([net.dim[e] for e in shared]))
                 if size > chi:
-                    _compress(net, k, l, chi, cutoff, scales, ops, explicit)
+                    compress(k, l)
             if progress is not None:
                 progress["steps"] = t + 1
     except ZeroContraction:

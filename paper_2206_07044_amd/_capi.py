@@ -125,11 +125,11 @@ def _ptr(a: np.ndarray, ct):
 
 def make_opts(chi: int, precision: str = "fp64", cutoff: float = 0.0, max_sweeps: int = 0,
               budget: int = 0, keep: bool = False, grad: bool = False, plain: bool = False,
-              late: bool = False) -> tn_tree_opts:
+              late: bool = False, gauge_r: int = 0) -> tn_tree_opts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
-    return tn_tree_opts(int(chi), float(cutoff), int(bool(late)), 0, PRECISIONS[precision], int(max_sweeps),
-                        int(budget), int(bool(keep)), int(bool(grad)), int(bool(plain)))
+    return tn_tree_opts(int(chi), float(cutoff), int(bool(late)), int(gauge_r), PRECISIONS[precision],
+                        int(max_sweeps), int(budget), int(bool(keep)), int(bool(grad)), int(bool(plain)))
 
 
 def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int,
@@ -208,9 +208,10 @@ class Context:
 
     def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
                     max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False,
-                    grad: bool = False, plain: bool = False, late: bool = False) -> None:
+                    grad: bool = False, plain: bool = False, late: bool = False, gauge_r: int = 0) -> None:
         pi, pj = _i32(pair_i), _i32(pair_j)
-        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad, plain, late)
+        opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad, plain, late,
+                         gauge_r)
         self.state_id += 1
         self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
                                           C.byref(opts)))

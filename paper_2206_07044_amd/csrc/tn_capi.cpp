@@ -414,6 +414,61 @@ tn_status build_launches(tn_ctx* c) {
                 gemms[key].push_back(g);
                 gemm_work[key].first += st.flops;
                 gemm_work[key].second += st.bytes;
+            } else if (st.kind == ST_GAUGE) {
+                // tree gauge: a metric applied on one bond (output through the tensor's layout), or a
+                // metric-weighted Gram (split partials summed in place, as for the side Grams)
+                GemmDesc g;
+                std::memset(&g, 0, sizeof(g));
+                const bool apply = st.gauge_mode == GAUGE_APPLY;
+                std::string err = fill_view(st.va, &g.va);
+                if (err.empty()) err = fill_view(st.vb, &g.vb);
+                if (err.empty() && apply) err = fill_view(st.vc, &g.vc);
+                if (!err.empty()) return fail(c, TN_EINVAL, err);
+                g.M = (int32_t)st.M;
+                g.N = (int32_t)st.N;
+                g.K = (int32_t)st.K;
+                g.tiles_m = (int32_t)((st.M + 63) / 64);
+                g.tiles_n = (int32_t)((st.N + 63) / 64);
+                g.A = st.in_a >= 0 ? ten_ptr(st.in_a) : buf_ptr(st.a_buf);
+                g.B = buf_ptr(st.b_buf);
+                g.C = buf_ptr(st.out_buf);
+                g.scale_a = st.in_a >= 0 ? st.in_a : -1;   // the tensor's pending 1/s (a buffer has it applied)
+                g.scale_b = -1;
+                // the tensor operand in its storage precision against a float64 one
+                const int k0 = st.in_a < 0 || prec == 0 ? GEMM_F64 : prec == 1 ? GEMM_F32_X_F64 : GEMM_BF16_X_F64;
+                int key;
+                if (apply) {
+                    g.mode = GEMM_ADJ;
+                    g.splits = 1;
+                    g.k_per_split = (int32_t)st.K;
+                    key = 2 * k0;
+                } else {
+                    g.mode = GEMM_GRAM;
+                    g.splits = st.splits;
+                    g.k_per_split = st.k_per_split;
+                    key = 2 * k0 + 1;
+                    if (st.splits > 1) {
+                        ReduceDesc r;
+                        std::memset(&r, 0, sizeof(r));
+                        ViewSpec vs;
+                        vs.row_dims = {(int32_t)st.M};
+                        vs.row_strides = {st.N};
+                        vs.col_dims = {(int32_t)st.N};
+                        vs.col_strides = {1};
+                        std::string verr = make_view(vs, &r.vc);
+                        if (!verr.empty()) return fail(c, TN_EINVAL, verr);
+                        r.part = (const double*)g.C;
+                        r.out = g.C;
+                        r.M = (int32_t)st.M;
+                        r.N = (int32_t)st.N;
+                        r.splits = st.splits;
+                        r.scale_a = r.scale_b = -1;
+                        sums.push_back(r);
+                    }
+                }
+                gemms[key].push_back(g);
+                gemm_work[key].first += st.flops;
+                gemm_work[key].second += st.bytes;
             } else if (st.kind == ST_COPY) {
                 CopyDesc cd;
                 std::memset(&cd, 0, sizeof(cd));
@@ -1227,7 +1282,8 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     if (!c) return TN_EINVAL;
     if (!c->has_graph) return fail(c, TN_ESTATE, "tn_set_tree before tn_load_graph");
     if (!opts || (n_steps > 0 && (!pair_i || !pair_j))) return fail(c, TN_EINVAL, "missing tree arrays or options");
-    if (opts->gauge_r != 0) return fail(c, TN_EINVAL, "gauge_r must be 0 (local compression only)");
+    if (opts->gauge_r < 0) return fail(c, TN_EINVAL, "gauge_r must be >= 0");
+    if (opts->gauge_r > 0 && opts->grad) return fail(c, TN_EINVAL, "gauge_r >= 1 has no reverse pass (grad must be 0)");
     if (opts->compress_late != 0 && opts->compress_late != 1) return fail(c, TN_EINVAL, "compress_late must be 0 or 1");
     if (opts->precision != TN_FP64 && opts->precision != TN_FP32 && opts->precision != TN_BF16)
         return fail(c, TN_EINVAL, "precision must be TN_FP64, TN_FP32 or TN_BF16");
@@ -1244,6 +1300,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.grad = opts->grad ? 1 : 0;
     o.plain = opts->plain ? 1 : 0;
     o.late = opts->compress_late;
+    o.gauge_r = opts->gauge_r;
     if (o.plain && o.grad) return fail(c, TN_EINVAL, "the plain form has no reverse pass (grad must be 0)");
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
     // level by level every independent branch advances at once; when that holds more than the
@@ -1787,7 +1844,7 @@ tn_status tn_plan_describe(int32_t n_tensors, int32_t n_edges, const int32_t* ed
     g.offsets.assign(n_tensors + 1, 0);
     for (int v = 0; v < n_tensors; ++v) g.offsets[v + 1] = g.offsets[v] + size[v];
     if (!check_graph(g).empty()) return TN_EINVAL;
-    if (opts->gauge_r != 0 || (opts->compress_late != 0 && opts->compress_late != 1)) return TN_EINVAL;
+    if (opts->gauge_r < 0 || (opts->compress_late != 0 && opts->compress_late != 1)) return TN_EINVAL;
     TreeOpts o;
     o.chi = opts->chi;
     o.cutoff = opts->cutoff;

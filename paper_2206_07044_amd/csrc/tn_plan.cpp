@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <climits>
 #include <map>
+#include <queue>
+#include <set>
+#include <tuple>
 #include <sstream>
 
 namespace tn {
@@ -371,7 +374,184 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 c.mb = mb;
                 c.chi_new = (int32_t)nw;
                 const int32_t comp_id = (int32_t)P->comps.size();
-                const bool big = D >= kLanczosMinD && !o.grad;   // the reverse pass needs the full core spectrum
+                // ---- tree gauge (r >= 1): the r-local spanning tree of SI A over the live intermediates
+                // around (a, b), then an environment metric for every tree edge, outer tensors first:
+                // M_{v->u} = the Gram of v over every leg but its bond to u, with the metrics of v's own
+                // children applied on their bonds (the R^T R of the R factor that the inward QR would
+                // push into u); the two side Grams take the metrics of a's and b's children the same way
+                std::vector<std::pair<int32_t, int32_t>> tau;
+                if (o.gauge_r > 0) {
+                    auto bonds_of = [&](int32_t x) {
+                        std::map<int32_t, int64_t> m;
+                        for (int e : P->tens[live[x]].legs) {
+                            const int32_t other = (E[e].end0 == x) ? E[e].end1 : E[e].end0;
+                            auto it = m.find(other);
+                            m[other] = (it == m.end() ? 1 : it->second) * E[e].dim;
+                        }
+                        return m;
+                    };
+                    std::set<int32_t> S = {a, b};
+                    using Cand = std::tuple<int32_t, int64_t, int32_t, int32_t>;   // distance, -bond, v, u
+                    std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> pq;
+                    for (const int32_t u : {a, b})
+                        for (auto& kv : bonds_of(u))
+                            if (!S.count(kv.first)) pq.push(Cand{1, -kv.second, kv.first, u});
+                    while (!pq.empty()) {
+                        const Cand cd = pq.top();
+                        pq.pop();
+                        const int32_t d = std::get<0>(cd), v = std::get<2>(cd), u = std::get<3>(cd);
+                        if (S.count(v) || d > o.gauge_r || v < g.n) continue;   // input tensors are not spanned
+                        S.insert(v);
+                        tau.push_back({u, v});
+                        for (auto& kv : bonds_of(v))
+                            if (!S.count(kv.first)) pq.push(Cand{d + 1, -kv.second, kv.first, v});
+                    }
+                }
+                std::map<int32_t, std::vector<int32_t>> gchildren;
+                for (auto& pr : tau) gchildren[pr.first].push_back(pr.second);
+                struct Metric { int32_t buf, level; std::vector<int32_t> edges; };   // edges: the child's order
+                std::map<int32_t, Metric> metrics;
+                auto gram_splits = [&](int64_t Dm, int64_t K, int64_t* kps) {
+                    const int64_t tiles = ((Dm + 63) / 64) * ((Dm + 63) / 64);
+                    int64_t sp = (K + 255) / 256;
+                    sp = std::min<int64_t>(sp, std::max<int64_t>(1, 1024 / tiles));
+                    sp = std::min<int64_t>(sp, std::max<int64_t>(1, (32 << 20) / (Dm * Dm * 8)));
+                    sp = std::max<int64_t>(1, sp);
+                    int64_t k = (K + sp - 1) / sp;
+                    k = (k + kGemmK - 1) / kGemmK * kGemmK;
+                    *kps = k;
+                    return (int32_t)((K + k - 1) / k);
+                };
+                // W = X with the metrics of x's tree children applied on their bonds (x's layout, float64);
+                // returns {buffer, level} or {-1, level of x} when x has no children
+                auto apply_children = [&](int32_t x) {
+                    const int32_t ver = live[x];
+                    const TensorVer& Tx = P->tens[ver];
+                    int32_t cur = -1, cur_level = Tx.level;
+                    auto it = gchildren.find(x);
+                    if (it == gchildren.end()) return std::make_pair(cur, cur_level);
+                    for (const int32_t wch : it->second) {
+                        const Metric& M = metrics.at(wch);
+                        std::vector<int32_t> bond, rest;
+                        for (int e : Tx.legs)
+                            (std::find(M.edges.begin(), M.edges.end(), e) != M.edges.end() ? bond : rest).push_back(e);
+                        const int64_t Dm = prod_dims(bond, E);
+                        // the metric's index: its edges in the child's order, slowest first
+                        ViewSpec vb;
+                        for (int e : bond) {
+                            int64_t unit = 1;
+                            for (size_t q = std::find(M.edges.begin(), M.edges.end(), e) - M.edges.begin() + 1;
+                                 q < M.edges.size(); ++q)
+                                unit *= E[M.edges[q]].dim;
+                            vb.row_dims.push_back((int32_t)E[e].dim);
+                            vb.row_strides.push_back(unit * Dm);
+                            vb.col_dims.push_back((int32_t)E[e].dim);
+                            vb.col_strides.push_back(unit);
+                        }
+                        Step st;
+                        st.kind = ST_GAUGE;
+                        st.gauge_mode = GAUGE_APPLY;
+                        st.comp = comp_id;
+                        st.level = 1 + std::max(cur_level, M.level);
+                        st.in_a = cur < 0 ? ver : -1;
+                        st.a_buf = cur;
+                        st.b_buf = M.buf;
+                        st.M = Tx.size / Dm;
+                        st.N = Dm;
+                        st.K = Dm;
+                        st.va = tensor_view(Tx, rest, bond, E);
+                        st.vb = vb;
+                        st.vc = tensor_view(Tx, rest, bond, E);
+                        st.out_buf = new_buf(Tx.size * 8, BUF_FACTOR, st.level);
+                        st.flops = 2.0 * (double)st.M * st.N * st.K;
+                        st.bytes = (double)(cur < 0 ? w : 8) * st.M * st.K + 8.0 * st.K * st.N + 8.0 * st.M * st.N;
+                        if (cur < 0) read_tensor(ver, st.level);
+                        else touch(cur, st.level);
+                        touch(M.buf, st.level);
+                        P->steps.push_back(st);
+                        cur = st.out_buf;
+                        cur_level = st.level;
+                    }
+                    return std::make_pair(cur, cur_level);
+                };
+                // the metric-weighted Gram of x over `rest`, indexed by `bond` (in the order given)
+                auto gauge_gram = [&](int32_t x, const std::vector<int32_t>& bond, const std::vector<int32_t>& rest,
+                                      int32_t wbuf, int32_t wlevel, int32_t* out_splits) {
+                    const int32_t ver = live[x];
+                    const TensorVer& Tx = P->tens[ver];
+                    const int64_t Dm = prod_dims(bond, E), K = Tx.size / Dm;
+                    Step st;
+                    st.kind = ST_GAUGE;
+                    st.gauge_mode = GAUGE_GRAM;
+                    st.comp = comp_id;
+                    st.level = 1 + std::max(Tx.level, wlevel);
+                    st.in_a = ver;
+                    st.b_buf = wbuf;
+                    st.M = Dm;
+                    st.N = Dm;
+                    st.K = K;
+                    st.va = tensor_view(Tx, bond, rest, E);
+                    st.vb = tensor_view(Tx, rest, bond, E);   // W has x's layout
+                    int64_t kps = K;
+                    st.splits = gram_splits(Dm, K, &kps);
+                    st.k_per_split = (int32_t)kps;
+                    st.out_buf = new_buf((int64_t)st.splits * Dm * Dm * 8, BUF_GRAM, st.level);
+                    st.flops = 2.0 * (double)Dm * Dm * K;
+                    st.bytes = (double)w * Dm * K + 8.0 * Dm * K;
+                    read_tensor(ver, st.level);
+                    touch(wbuf, st.level);
+                    P->steps.push_back(st);
+                    *out_splits = st.splits;
+                    return std::make_pair(st.out_buf, st.level);
+                };
+                for (auto it = tau.rbegin(); it != tau.rend(); ++it) {
+                    const int32_t u = it->first, v = it->second;
+                    const TensorVer& Tv = P->tens[live[v]];
+                    const TensorVer& Tu = P->tens[live[u]];
+                    std::vector<int32_t> bond, rest;
+                    for (int e : Tv.legs)
+                        (std::find(Tu.legs.begin(), Tu.legs.end(), e) != Tu.legs.end() ? bond : rest).push_back(e);
+                    const std::pair<int32_t, int32_t> wv = apply_children(v);
+                    Metric m;
+                    m.edges = bond;
+                    if (wv.first < 0) {
+                        // a leaf of the tree: its plain Gram (the narrow-Gram path for small bonds)
+                        const int64_t Dm = prod_dims(bond, E), K = Tv.size / Dm;
+                        Step st;
+                        st.kind = ST_GRAM;
+                        st.comp = comp_id;
+                        st.level = Tv.level + 1;
+                        st.in_a = live[v];
+                        st.M = Dm;
+                        st.N = Dm;
+                        st.K = K;
+                        st.va = tensor_view(Tv, bond, rest, E);
+                        st.vb = tensor_view(Tv, rest, bond, E);
+                        int64_t kps = K;
+                        if (Dm <= kGramNarrowMaxD) {
+                            kps = 512;
+                            st.splits = (int32_t)((K + kps - 1) / kps);
+                        } else {
+                            st.splits = gram_splits(Dm, K, &kps);
+                        }
+                        st.k_per_split = (int32_t)kps;
+                        st.out_buf = new_buf((int64_t)st.splits * Dm * Dm * 8, BUF_GRAM, st.level);
+                        st.flops = 2.0 * (double)Dm * Dm * K;
+                        st.bytes = (double)w * Dm * K;
+                        read_tensor(live[v], st.level);
+                        P->steps.push_back(st);
+                        m.buf = st.out_buf;
+                        m.level = st.level;
+                    } else {
+                        int32_t sp = 1;
+                        const std::pair<int32_t, int32_t> gr = gauge_gram(v, bond, rest, wv.first, wv.second, &sp);
+                        m.buf = gr.first;
+                        m.level = gr.second;
+                    }
+                    metrics[v] = m;
+                }
+                const bool gauged = !tau.empty();
+                const bool big = D >= kLanczosMinD && !o.grad && !gauged;   // the reverse pass needs the full core spectrum
                 const bool xside = ma <= D || mb <= D;
                 // one explicit side and a large bond: block Krylov with the other side read in place
                 const bool krylov = big && xside && D >= kKrylovMinD;
@@ -417,6 +597,19 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         if (krylov && side != x_is_b) {   // Y: read in place by the Krylov chain
                             side_level[side] = T.level;
                             (side == 0 ? c.side_a_buf : c.side_b_buf) = -1;
+                            continue;
+                        }
+                        const std::pair<int32_t, int32_t> wside =
+                            gauged ? apply_children(side == 0 ? a : b) : std::make_pair(-1, 0);
+                        if (wside.first >= 0) {
+                            // tree gauge: the side's Gram with its children's metrics applied
+                            int32_t sp = 1;
+                            const std::pair<int32_t, int32_t> gr =
+                                gauge_gram(side == 0 ? a : b, shared, fr, wside.first, wside.second, &sp);
+                            (side == 0 ? c.gram_a : c.gram_b) = 1;
+                            (side == 0 ? c.splits_a : c.splits_b) = sp;
+                            (side == 0 ? c.side_a_buf : c.side_b_buf) = gr.first;
+                            side_level[side] = gr.second;
                             continue;
                         }
                         Step st;
@@ -916,6 +1109,12 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
             View v;
             std::string err = make_view(s.va, &v);
             if (err.empty() && s.kind == ST_GRAM) err = make_view(s.vb, &v);
+            if (!err.empty()) return err;
+        } else if (s.kind == ST_GAUGE) {
+            View v;
+            std::string err = make_view(s.va, &v);
+            if (err.empty()) err = make_view(s.vb, &v);
+            if (err.empty() && s.gauge_mode == GAUGE_APPLY) err = make_view(s.vc, &v);
             if (!err.empty()) return err;
         }
     }

@@ -35,6 +35,7 @@ struct TreeOpts {
     int32_t plain = 0;              // one launch per step, no streams, no graph (the plain form)
     int32_t ordered = 0;            // contraction levels follow the tree order (memory of a sequential run)
     int32_t late = 0;               // late compression: bonds of i and j compressed before contracting them
+    int32_t gauge_r = 0;            // tree-gauge distance r of every compression
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).
@@ -59,7 +60,12 @@ struct TensorVer {
     int32_t last_read = 0;
 };
 
-enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS, ST_KRYLOV };
+enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS, ST_KRYLOV, ST_GAUGE };
+
+// Tree-gauge steps (ST_GAUGE): 1 = apply a child's environment metric on one bond of a tensor (or of
+// an earlier apply's output), W = X x_bond M, float64 into a buffer of the tensor's layout; 2 = the
+// metric-weighted Gram X^T W over every leg but one bond (split-K partials, summed in place).
+enum GaugeMode { GAUGE_APPLY = 1, GAUGE_GRAM = 2 };
 
 // Gram steps of sides with D <= kGramNarrowMaxD run on the narrow-Gram kernel (512 rows per split)
 constexpr int kGramNarrowMaxD = 64;
@@ -82,6 +88,11 @@ struct Step {
     int32_t splits = 1, k_per_split = 0;
     ViewSpec va, vb;                // for COPY only va is used
     int32_t copy_rows = 0, copy_cols = 0;
+    // GAUGE: mode, float64 operands held in buffers (A when it is an earlier apply's output, B the
+    // metric or the applied tensor) and the output view of an apply
+    int32_t gauge_mode = 0;
+    int32_t a_buf = -1, b_buf = -1;
+    ViewSpec vc;
     // CORE
     int32_t comp = -1;              // compression index
     double flops = 0, bytes = 0;

@@ -430,3 +430,86 @@ def test_late_and_early_compress_at_different_points():
             nxt = next(p for p in late.ops[t:] if p.kind == "contract")
             assert o.a in (nxt.a, nxt.b)
     assert early.ln_abs_z != late.ln_abs_z and ex.sign != 0
+
+
+# ---------------------------------------------------------------------------- tree gauge (r >= 1)
+def _rank1_environment_network():
+    """A0 and B0 share a composite bond of 2 x 2; A0 has two more legs (dim 2) to vectors P and X,
+    B0 to vectors Q and Y, each vector an intermediate (the contraction of two inputs); A0 is then
+    contracted with a one-entry tensor, so the intermediate A's bond to B0 (4 > chi = 2) is
+    compressed while P, X, Q, Y are live intermediates next to it."""
+    rng = np.random.default_rng(23)
+    # 0 = A0, 1 = B0, 2/3 = p1/p2, 4/5 = x1/x2, 6/7 = q1/q2, 8/9 = y1/y2, 10 = one-entry Z
+    raw = [(0, 1, 2), (0, 1, 2), (0, 2, 2), (0, 4, 2), (0, 10, 1), (1, 6, 2), (1, 8, 2),
+           (2, 3, 2), (4, 5, 2), (6, 7, 2), (8, 9, 2)]
+    g = Graph(11, sorted(raw))
+    inc = g.incident()
+    T = [rng.normal(size=tuple(g.edges[e][2] for e in inc[v])) for v in range(11)]
+    T[10] = np.ones(1)
+    # P = 11, X = 12, Q = 13, Y = 14, A = 15
+    pairs = [(2, 3), (4, 5), (6, 7), (8, 9), (0, 10), (15, 11), (16, 12), (17, 1), (18, 13), (19, 14)]
+    return g, T, pairs
+
+
+def test_tree_gauge_uses_the_environment():
+    """Section II.C / SI A: with the bond (A, B0) in the tree gauge, A's R factor is that of
+    (P x X)^T A (the vectors' R factors absorbed), a single row, and B0's that of B0 (Q x Y); the
+    core is then the scalar Z itself and chi = 2 reproduces Z exactly, while the local compression
+    (r = 0) keeps the best rank-2 part of the 4 x 4 product A B0 alone and does not."""
+    g, T, pairs = _rank1_environment_network()
+    ex = oracle.contract_compressed(g.n, g.edges, T, pairs, None)
+    r0 = oracle.contract_compressed(g.n, g.edges, T, pairs, 2)
+    r1 = oracle.contract_compressed(g.n, g.edges, T, pairs, 2, gauge_r=1)
+    assert any(o.kind == "compress" for o in r1.ops)
+    assert r1.sign == ex.sign and r1.ln_abs_z == pytest.approx(ex.ln_abs_z, rel=1e-13)
+    assert abs(r0.ln_abs_z - ex.ln_abs_z) > 1e-3
+
+
+def test_local_spanning_tree_rule():
+    """SI A: grown from S0 = {a, b}; the closest candidate with the largest bond first; input
+    tensors are never spanned; nodes beyond distance r are left out."""
+    from oracle.approx import _Network, _local_spanning_tree
+    # 0..3 inputs; 4..9 intermediates (as a network they are just tensors with ids)
+    edges = sorted([(4, 5, 2), (4, 6, 3), (4, 7, 2), (5, 8, 2), (6, 9, 2), (7, 9, 2), (5, 0, 2), (0, 4, 2)])
+    edges = sorted((min(u, v), max(u, v), d) for u, v, d in edges)
+    g = Graph(10, edges)
+    inc = g.incident()
+    net = _Network(10, g.edges, [np.ones(tuple(g.edges[e][2] for e in inc[v])) for v in range(10)])
+    tau = _local_spanning_tree(net, 4, 5, 2, n_inputs=4)
+    # distance 1 from {4, 5}: 6 (bond 3) before 7 (bond 2), then 8 (bond 2); input 0 is skipped;
+    # distance 2: 9 is reached from 6 (popped first among equal bonds by the smaller u... 9 via 6)
+    assert tau == [(4, 6), (4, 7), (5, 8), (6, 9)]
+    assert _local_spanning_tree(net, 4, 5, 1, n_inputs=4) == [(4, 6), (4, 7), (5, 8)]
+
+
+@pytest.mark.parametrize("shape,beta,seed,chi", [((3, 3), 0.44, None, 2), ((3, 4), 0.6, 3, 2), ((4, 4), 0.44, 4, 4),
+                                                 ((2, 2, 3), 0.3, 5, 8)])
+def test_tree_gauge_exact_regime(shape, beta, seed, chi):
+    # compressions of rank-deficient Ising cores that truncate nothing stay exact in any gauge
+    g = lattice(shape)
+    J = None if seed is None else np.where(np.random.default_rng(seed).random(g.n_edges) < 0.5, -1.0, 1.0)
+    T = ising_tensors(g, beta, J)
+    want = exact.ising_brute_force(g.n, g.edges, beta, J)
+    for r in (1, 2, 3):
+        res = oracle.contract_compressed(g.n, g.edges, T, sweep_tree(shape), chi, gauge_r=r)
+        assert any(o.kind == "compress" for o in res.ops)
+        assert res.ln_abs_z == pytest.approx(want, rel=1e-12)
+
+
+def test_tree_gauge_improves_late_compression_2d():
+    """Section II.D, Fig. "early vs late" C: on the 2D URand model (D = 4, entries in [-0.5, 1]) with
+    late compression, a larger tree-gauge distance gives a smaller error; here on 8x8 at chi = 8
+    over six seeds (median |1 - Z/Z_exact|: r = 0 2.9e-3, r = 2 1.9e-4, r = 4 2.9e-5)."""
+    g = lattice((8, 8), dim=4)
+    pairs = sweep_tree((8, 8))
+    exact_tree = greedy_tree(g, 1 << 40, 0, temperature=0.0)
+    med = {}
+    for r in (0, 2, 4):
+        errs = []
+        for sd in range(6):
+            T = uniform_tensors(g, -0.5, sd)
+            ex = oracle.contract_compressed(g.n, g.edges, T, exact_tree, None)
+            a = oracle.contract_compressed(g.n, g.edges, T, pairs, 8, gauge_r=r, compress_late=True)
+            errs.append(abs(1.0 - a.sign * ex.sign * math.exp(a.ln_abs_z - ex.ln_abs_z)))
+        med[r] = float(np.median(errs))
+    assert med[4] < med[2] < med[0] and med[4] < 0.05 * med[0]
