@@ -526,6 +526,43 @@ def pyrochlore_leg(tn, torch, L=6, chi=4, beta=0.22, h=0.005):
             "seconds_3_fwd_bwd": dt}
 
 
+def tree_gauge_leg(tn, torch, L=10, chi=8, seeds=4):
+    """Tree-gauge compression (section II.C, SI A) with early and late compression (section II.D)
+    on the URand model of the paper's early-versus-late comparison (D = 4 square lattice, entries
+    in [-0.5, 1]): median |1 - Z/Z_exact| over seeds for r = 0, 1, 2, 4, and the time per tree.
+    Z_exact is the library's own float64 contraction along a Greedy tree at a chi above every bond
+    (no compression), a different tree and a different op sequence from the measured ones."""
+    from tninputs import greedy_tree, lattice, uniform_tensors
+    from tninputs.trees import sweep_tree
+    g = lattice((L, L), dim=4)
+    pairs = sweep_tree((L, L))
+    exact_pairs = greedy_tree(g, 1 << 40, 0, temperature=0.0)
+    out = {"lattice": [L, L], "D": 4, "lambda": -0.5, "chi": chi, "seeds": seeds,
+           "tree": "axis sweep (Span family)", "reference": "float64, Greedy tree, no compression", "runs": {}}
+    exact = []
+    for sd in range(seeds):
+        c = _load(tn, g, uniform_tensors(g, -0.5, sd), exact_pairs, 1 << 30, "fp64")
+        c.tn_contract_compressed()
+        exact.append(c.tn_result())
+        c.close()
+    for late in (False, True):
+        for r in (0, 1, 2, 4):
+            errs, times = [], []
+            for sd in range(seeds):
+                eu, ev, ed, off, data = flat(g, uniform_tensors(g, -0.5, sd))
+                c = tn.Context(0)
+                c.tn_load_graph(g.n, eu, ev, ed, off, data)
+                c.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, precision="fp64", late=late, gauge_r=r)
+                times.append(timed(c, 2, torch))
+                sign, lnz = c.tn_result()
+                c.close()
+                es, el = exact[sd]
+                errs.append(abs(1.0 - sign * es * math.exp(lnz - el)))
+            out["runs"][f"{'late' if late else 'early'}_r{r}"] = {"median_abs_1_minus_Z_over_Zexact": float(np.median(errs)),
+                                                                "ms_per_tree": 1e3 * float(np.median(times))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -548,6 +585,7 @@ def main() -> int:
     ap.add_argument("--spin-glass", default="16,16", help="L,chi of the +-J spin-glass forward+reverse leg ('' to skip)")
     ap.add_argument("--no-random-graphs", action="store_true", help="skip the dimer and Normal(mu) random-graph legs")
     ap.add_argument("--no-tree-scoring", action="store_true", help="skip the device-side tree-scoring leg")
+    ap.add_argument("--no-tree-gauge", action="store_true", help="skip the tree-gauge accuracy leg")
     ap.add_argument("--no-second-workloads", action="store_true", help="skip the pyrochlore leg")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -795,6 +833,9 @@ def main() -> int:
 
     if not args.no_tree_scoring:
         out["tree_scoring"] = tree_scoring_leg(tn, torch)
+
+    if not args.no_tree_gauge:
+        out["tree_gauge"] = tree_gauge_leg(tn, torch)
 
     if not args.no_random_graphs:
         out["dimer_rrg"] = dimer_leg(tn, torch, 3)
