@@ -578,9 +578,9 @@ def main() -> int:
     ap.add_argument("--fwd-bwd-steps", type=int, default=1, help="timed forward+reverse passes (0: skip)")
     ap.add_argument("--batch", type=int, default=8, help="instances in the batched leg (<= 1: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--per-chi", default="32", help="other chi values timed in fp32 and fp64 ('' to skip)")
+    ap.add_argument("--per-chi", default="32,64", help="other chi values timed in fp32 and fp64 ('' to skip)")
     ap.add_argument("--full", action="store_true",
-                    help="also chi = 64 in the per-chi leg and the URand hardness sweep (several minutes more)")
+                    help="also the URand hardness sweep (a minute more)")
     ap.add_argument("--no-small", action="store_true", help="skip the 8x8 Ising leg")
     ap.add_argument("--spin-glass", default="16,16", help="L,chi of the +-J spin-glass forward+reverse leg ('' to skip)")
     ap.add_argument("--no-random-graphs", action="store_true", help="skip the dimer and Normal(mu) random-graph legs")

@@ -14,8 +14,9 @@ cubic_12.json    : 12x12x12 Ising, beta=0.22, chi=16, sweep tree (--big, ~10 min
                    unmodified oracle runs is the rounding sensitivity of this instance.
 cubic_12_chi32.json: the same network and tree at chi=32 (--chi32, ~30 min of CPU): the oracle's
                    ln|Z| only.
-cubic_6_chi64.json: 6x6x6 Ising, beta=0.22, chi=64, sweep tree (--cubic6-chi64): bonds of D = 4096
-                   against 262144-row factors; the oracle's ln|Z|.
+cubic_4x4x8_chi64.json: 4x4x8 Ising, beta=0.22, chi=64, sweep tree (--cubic448-chi64, ~25 min of CPU and
+                   ~35 GB): nine bonds of D = 4096 against 262144-row factors; the oracle's ln|Z|.
+cubic_6_chi64.json: 6x6x6, the same model and chi (--cubic6-chi64, ~70 min of CPU): 25 bonds of D = 4096.
 spin_glass_grad.json: L^3 +-J spin glass (SI F.1), beta = 0.5, couplings from default_rng(0), chi = 16,
                    sweep tree, L = 4 and 6 (--spin-glass, ~5 min of CPU; --spin-glass-8 adds L = 8):
                    the oracle's ln|Z| and d ln|Z| / d J for every bond (oracle.grad).
@@ -110,18 +111,19 @@ def cubic_12_chi(chi):
             "oracle_lnZ": lnz, "cpu_seconds": time.time() - t0}
 
 
-def cubic_6_chi64():
-    """6^3 Ising, beta = 0.22, chi = 64 along the sweep tree: its corner merges give bonds of
+def cubic_chi64(shape):
+    """L1xL2xL3 Ising, beta = 0.22, chi = 64 along the sweep tree: its corner merges give bonds of
     D = 4096 (two chi-bonds), compressed against 262144-row factors."""
-    g = lattice((6, 6, 6))
+    g = lattice(shape)
     T = ising_tensors(g, 0.22)
-    p = sweep_tree((6, 6, 6))
+    p = sweep_tree(shape)
     t0 = time.time()
     r = oracle.contract_compressed(g.n, g.edges, T, p, 64)
     comp = [o for o in r.ops if o.kind == "compress"]
-    return {"shape": [6, 6, 6], "beta": 0.22, "chi": 64, "tree": "sweep_tree((6, 6, 6))",
+    return {"shape": list(shape), "beta": 0.22, "chi": 64, "tree": f"sweep_tree({tuple(shape)})",
             "oracle_lnZ": r.ln_abs_z, "compressions": len(comp), "ties": sum(o.tie for o in comp),
-            "max_bond": max(o.n for o in comp), "cpu_seconds": time.time() - t0}
+            "max_bond": max(o.n for o in comp), "bonds_4096": sum(o.n == 4096 for o in comp),
+            "cpu_seconds": time.time() - t0}
 
 
 def spin_glass_grads(sizes, chi=16, beta=0.5):
@@ -186,7 +188,9 @@ if __name__ == "__main__":
     if "--chi32" in sys.argv:
         write("cubic_12_chi32.json", cubic_12_chi(32))
     if "--cubic6-chi64" in sys.argv:
-        write("cubic_6_chi64.json", cubic_6_chi64())
+        write("cubic_6_chi64.json", cubic_chi64((6, 6, 6)))
+    if "--cubic448-chi64" in sys.argv:
+        write("cubic_4x4x8_chi64.json", cubic_chi64((4, 4, 8)))
     if "--square12" in sys.argv:
         write("square_12.json", square_12())
     if "--random-graphs" in sys.argv:

@@ -317,6 +317,24 @@ def test_krylov_bonds_reduced_precision(precision):
     assert sign == want.sign and err <= bound
 
 
+@pytest.mark.parametrize("name", ["cubic_4x4x8_chi64.json", "cubic_6_chi64.json"])
+def test_chi64_d4096_bonds_against_stored_oracle(name):
+    """chi = 64 on sweep trees whose corner merges give bonds of D = 4096 (two chi-bonds) against
+    262144-row factors: the block-Krylov path at its full size, FP64 against the oracle's stored
+    ln|Z| (written by make_golden.py) at 1e-10 relative."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        gold = json.load(f)
+    shape = tuple(gold["shape"])
+    assert gold["max_bond"] == 4096 and gold["ties"] == 0
+    g = lattice(shape)
+    sign, lnz, *_ = gpu_eval(g, ising_tensors(g, gold["beta"]), sweep_tree(shape), gold["chi"])
+    rel = abs(lnz - gold["oracle_lnZ"]) / abs(gold["oracle_lnZ"])
+    print(f"{name}: gpu {lnz!r} oracle {gold['oracle_lnZ']!r} rel {rel:.3e}", flush=True)
+    assert sign == 1.0 and rel <= FP64_RTOL
+
+
 def test_krylov_flat_spectrum_is_reported():
     """Normal(0.2, 1) entries on 5^3 at chi = 32: random cores have flat spectra, which a basis of
     4 chi' directions does not resolve; the Ritz residual check must turn that into TN_ENUMERIC
@@ -326,3 +344,45 @@ def test_krylov_flat_spectrum_is_reported():
     with pytest.raises(tn.TNError) as ei:
         gpu_eval(g, T, sweep_tree((5, 5, 5)), 32)
     assert ei.value.status == tn.TN_ENUMERIC
+
+
+# ---------------------------------------------------------------------------- Gram-route floor
+# The GPU forms R factors from float64 Gram matrices by pivoted Cholesky, which stops at pivots
+# below 1e-15 of the first: directions of a side whose singular value is below about 3.2e-8 of
+# its largest are dropped (the oracle's QR keeps them), and kept directions near the floor are
+# perturbed by the Gram's rounding.  On the one-compression probe, A (12 x 8) has rank 6 and
+# chi = 6, so the compression truncates nothing and Z = kron(P)^T A B kron(Q) exactly; the GPU's
+# error must be explained by those two effects: twice the part of Z the dropped directions carry,
+# plus four times a first-order bound of the rounding perturbation of the kept ones.
+@pytest.mark.parametrize("s_small,dropped", [([1e-7, 1e-7], 0), ([1e-9, 1e-11], 2), ([1e-6, 1e-10], 1)])
+def test_gram_route_accuracy_floor(s_small, dropped):
+    from tninputs.probes import bond_probe
+    rng = np.random.default_rng(31)
+    s_a = np.array([1.0, 1e-2, 1e-5, 1e-6] + s_small + [0.0, 0.0])          # D = 8, rank 6
+    ua, _ = np.linalg.qr(rng.normal(size=(12, 8)))
+    va, _ = np.linalg.qr(rng.normal(size=(8, 8)))
+    a_mat = (ua * s_a) @ va.T                                                # 12 x 8: a Gram side
+    b_mat = rng.normal(size=(8, 12))
+    caps = [rng.normal(size=d) + 1.0 for d in (3, 4, 3, 4)]
+    g, T, pairs = bond_probe(a_mat, b_mat, (2, 4), (3, 4), (3, 4), caps)
+    p = np.kron(caps[0], caps[1])
+    q = np.kron(caps[2], caps[3])
+    z = p @ a_mat @ b_mat @ q
+    small = (s_a > 0) & (s_a < 3.2e-8 * s_a[0])
+    assert int(np.sum(small)) == dropped
+    carried = abs(p @ ((ua * np.where(small, s_a, 0.0)) @ va.T) @ b_mat @ q)   # the dropped directions' part
+    # a kept direction i is perturbed by the Gram's rounding (about sqrt(m) u ||A||^2 per entry)
+    # through an eigenvector rotation of sqrt(m) u (s_1 / s_i)^2 at most: first-order bound
+    coupling = np.abs(p @ ua) * s_a * np.linalg.norm(b_mat @ q)
+    kept = (s_a > 0) & ~small
+    rot = np.minimum(1.0, math.sqrt(12) * 2.0 ** -53 * (s_a[0] / np.where(kept, s_a, 1.0)) ** 2)
+    perturbed = float(np.sum(np.where(kept, coupling * rot, 0.0)))
+    sign, lnz, m, e, stats = gpu_eval(g, T, pairs, 6)
+    assert len(stats[0]) == 1                                                # one compression ran
+    err = abs(sign * math.exp(lnz) - z)
+    print(f"floor case {s_small}: |Z_gpu - Z| = {err:.3e}, dropped part {carried:.3e}, rounding bound "
+          f"{perturbed:.3e}, |Z| = {abs(z):.3e}", flush=True)
+    assert sign == np.sign(z)
+    assert err <= 2.0 * carried + 4.0 * perturbed + 1e-13 * abs(z)
+    if dropped:
+        assert err >= 0.5 * carried            # the floor is real: the dropped part is missing
