@@ -87,16 +87,32 @@ typedef struct {
     int64_t device_budget_bytes; /* refuse plans whose device arena exceeds this; 0 = no limit */
     int32_t keep_intermediates;  /* 1: never reuse arena memory, so tn_read_tensor can read every
                                     intermediate after an evaluation (element-wise checks) */
-    int32_t grad;                /* 1: also plan the reverse pass (tn_grad).  Every forward tensor,
-                                    core workspace and projector stays resident for it, and every
-                                    compression takes the Gram + full-spectrum Jacobi core (the
-                                    adjoint needs all singular triplets of the core) */
+    int32_t grad;                /* 1: also plan the reverse pass (tn_grad).  Every compression
+                                    takes the Gram + full-spectrum Jacobi core (the adjoint needs
+                                    all singular triplets of the core).  What the reverse pass reads
+                                    of the forward pass (tensors, core workspaces, projectors) stays
+                                    resident unless checkpoint_segments recomputes it; reverse-pass
+                                    buffers live from their first to their last reverse level */
     int32_t plain;               /* 1: the plain form: every step (contraction, Gram, core,
                                     re-absorption, scale) is its own kernel launch, issued in order
                                     on the context's stream on every evaluation, with no grouping,
                                     no concurrent streams and no graph replay; same kernels and same
                                     results.  The baseline the grouped, captured form is measured
                                     against.  Needs grad = 0; not accepted by tn_batch_create */
+    int32_t checkpoint_segments; /* grad only: recomputation of forward intermediates.  0 or 1: none
+                                    (everything the reverse pass reads stays resident).  S >= 2: the
+                                    forward levels are cut into S consecutive segments of about
+                                    equal produced bytes; only forward buffers live across a
+                                    segment boundary (the checkpoints) are kept to the end; the
+                                    reverse pass takes the segments last to first and re-runs the
+                                    forward launches of each segment but the last before its
+                                    reverse levels (a second tn_grad with no evaluation in between
+                                    first re-runs the whole forward pass: the re-runs write over
+                                    checkpoints).  Same gradient bit for bit (the forward kernels
+                                    are deterministic), smaller arena, up to one more forward pass
+                                    of work per tn_grad.  -1: the S in
+                                    {1,2,3,4,6,8,12,16,24,32} of smallest arena.  tn_batch_grad does
+                                    not take contexts planned with S >= 2 (tn_grad per context) */
 } tn_tree_opts;
 
 typedef struct tn_ctx tn_ctx;
@@ -188,7 +204,9 @@ typedef enum {
     TN_KERNEL_SCALE = 5,
     TN_KERNEL_LANCZOS = 6,
     TN_KERNEL_BWD_GEMM = 7,      /* reverse pass: adjoint GEMMs and split-K reductions */
-    TN_KERNEL_BWD_CORE = 8       /* reverse pass: per-compression core adjoint */
+    TN_KERNEL_BWD_CORE = 8,      /* reverse pass: per-compression core adjoint */
+    TN_KERNEL_RECOMPUTE = 9      /* reverse pass: re-run of one forward segment (all its launches,
+                                    timed as one interval; flops and bytes are the segment's) */
 } tn_kernel_kind;
 
 /* Time every launch of the kinds in `kind_mask` (bit k = tn_kernel_kind k)
@@ -253,6 +271,14 @@ tn_status tn_ising_coupling_grad_device(tn_ctx* ctx, double beta, const void* J_
 /* Backward-plan totals for opts.grad = 1: algorithmic flops and bytes of the
  * reverse pass, its number of levels. */
 tn_status tn_grad_info(const tn_ctx* ctx, double* bwd_flops, double* bwd_bytes, int32_t* n_levels);
+
+/* Recomputation totals for opts.grad = 1: the number of segments S (1 = no
+ * recomputation), the forward flops re-run by one tn_grad right after an
+ * evaluation (every segment but the last that has reverse steps), and the bytes
+ * of forward buffers kept across segment boundaries.  TN_ESTATE without a
+ * grad plan. */
+tn_status tn_grad_checkpoint_info(const tn_ctx* ctx, int32_t* segments, double* recompute_flops,
+                                  int64_t* checkpoint_bytes);
 
 /* ---- Batches: independent instances evaluated together ------------------
  * Steps of different instances never depend on each other, so the schedules

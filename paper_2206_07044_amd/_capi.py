@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ESTATE", 3: "TN_ENOMEM", 4: "
                 5: "TN_ENUMERIC", 6: "TN_ZERO"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 KERNEL_KINDS = {"gemm": 0, "gram": 1, "copy": 2, "core_lds": 3, "core_global": 4, "scale": 5, "lanczos": 6,
-                "bwd_gemm": 7, "bwd_core": 8}
+                "bwd_gemm": 7, "bwd_core": 8, "recompute": 9}
 
 
 class TNError(RuntimeError):
@@ -33,7 +33,7 @@ class tn_tree_opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("cutoff", C.c_double), ("compress_late", C.c_int32),
                 ("gauge_r", C.c_int32), ("precision", C.c_int32), ("jacobi_max_sweeps", C.c_int32),
                 ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("grad", C.c_int32),
-                ("plain", C.c_int32)]
+                ("plain", C.c_int32), ("checkpoint_segments", C.c_int32)]
 
 
 _lib = None
@@ -84,6 +84,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_grad": ([P, pD], C.c_int),
         "tn_grad_device": ([P, P], C.c_int),
         "tn_grad_info": ([P, pD, pD, pI32], C.c_int),
+        "tn_grad_checkpoint_info": ([P, pI32, pD, pI64], C.c_int),
         "tn_ising_values_device": ([P, D, P], C.c_int),
         "tn_sync": ([P], C.c_int),
         "tn_batch_create": ([I32, C.POINTER(P), C.POINTER(P)], C.c_int),
@@ -110,7 +111,7 @@ def exported_symbols() -> List[str]:
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
             "tn_update_values_device", "tn_set_workspace", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
-            "tn_grad_device", "tn_grad_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
+            "tn_grad_device", "tn_grad_info", "tn_grad_checkpoint_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
             "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
             "tn_plan_describe", "tn_compress_pair", "tn_compress_pair_static"]
 
@@ -125,11 +126,12 @@ def _ptr(a: np.ndarray, ct):
 
 def make_opts(chi: int, precision: str = "fp64", cutoff: float = 0.0, max_sweeps: int = 0,
               budget: int = 0, keep: bool = False, grad: bool = False, plain: bool = False,
-              late: bool = False, gauge_r: int = 0) -> tn_tree_opts:
+              late: bool = False, gauge_r: int = 0, segments: int = 0) -> tn_tree_opts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     return tn_tree_opts(int(chi), float(cutoff), int(bool(late)), int(gauge_r), PRECISIONS[precision],
-                        int(max_sweeps), int(budget), int(bool(keep)), int(bool(grad)), int(bool(plain)))
+                        int(max_sweeps), int(budget), int(bool(keep)), int(bool(grad)), int(bool(plain)),
+                        int(segments))
 
 
 def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int,
@@ -208,10 +210,13 @@ class Context:
 
     def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
                     max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False,
-                    grad: bool = False, plain: bool = False, late: bool = False, gauge_r: int = 0) -> None:
+                    grad: bool = False, plain: bool = False, late: bool = False, gauge_r: int = 0,
+                    checkpoint_segments: int = 0) -> None:
+        """checkpoint_segments (grad only): 0/1 keep every forward buffer the reverse pass reads;
+        S >= 2 recompute forward segments in the reverse pass; -1 the S of smallest arena."""
         pi, pj = _i32(pair_i), _i32(pair_j)
         opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad, plain, late,
-                         gauge_r)
+                         gauge_r, checkpoint_segments)
         self.state_id += 1
         self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
                                           C.byref(opts)))
@@ -321,6 +326,11 @@ class Context:
         f, b, n = C.c_double(), C.c_double(), C.c_int32()
         self._check(self._lib.tn_grad_info(self._h, C.byref(f), C.byref(b), C.byref(n)))
         return {"bwd_flops": f.value, "bwd_bytes": b.value, "n_levels": n.value}
+
+    def tn_grad_checkpoint_info(self) -> dict:
+        sg, f, b = C.c_int32(), C.c_double(), C.c_int64()
+        self._check(self._lib.tn_grad_checkpoint_info(self._h, C.byref(sg), C.byref(f), C.byref(b)))
+        return {"segments": sg.value, "recompute_flops": f.value, "checkpoint_bytes": b.value}
 
 
 class Batch:

@@ -11,6 +11,10 @@ stream is synchronised before torch reads what it wrote.
     net = IsingLogZ(n, edges, pairs, chi=16, beta=0.5)            # plans once
     J = torch.ones(n_edges, dtype=torch.float64, device="cuda", requires_grad=True)
     lnz = net(J); lnz.backward()                                   # J.grad = d ln|Z| / d J
+
+checkpoint_segments (0: every forward buffer the reverse pass reads stays resident; S >= 2:
+forward segments recomputed in the reverse pass; -1: the S of smallest arena) trades device
+memory for up to one more forward pass per backward.
 """
 from __future__ import annotations
 
@@ -91,7 +95,7 @@ class _LogZFromCouplings(torch.autograd.Function):
 
 class _Planned:
     def __init__(self, n: int, edges: Sequence[Tuple[int, int, int]], offsets, pairs, chi: int,
-                 precision: str = "fp64", cutoff: float = 0.0):
+                 precision: str = "fp64", cutoff: float = 0.0, checkpoint_segments: int = 0):
         eu = np.array([e[0] for e in edges], dtype=np.int32)
         ev = np.array([e[1] for e in edges], dtype=np.int32)
         ed = np.array([e[2] for e in edges], dtype=np.int32)
@@ -100,7 +104,7 @@ class _Planned:
         self.ctx = Context(torch.cuda.current_device())
         self.ctx.tn_load_graph(n, eu, ev, ed, self.offsets, np.zeros(self.n_data))
         self.ctx.tn_set_tree([a for a, _ in pairs], [b for _, b in pairs], chi, precision=precision,
-                             cutoff=cutoff, grad=True)
+                             cutoff=cutoff, grad=True, checkpoint_segments=checkpoint_segments)
 
     def close(self) -> None:
         self.ctx.close()
@@ -118,7 +122,8 @@ class TensorLogZ(_Planned):
 class IsingLogZ(_Planned):
     """ln|Z| of the Ising model on a graph with dimension-2 edges, differentiable in J."""
 
-    def __init__(self, n: int, edges, pairs, chi: int, beta: float, precision: str = "fp64", cutoff: float = 0.0):
+    def __init__(self, n: int, edges, pairs, chi: int, beta: float, precision: str = "fp64", cutoff: float = 0.0,
+                 checkpoint_segments: int = 0):
         deg = np.zeros(n, dtype=np.int64)
         for u, v, d in edges:
             if d != 2:
@@ -127,7 +132,7 @@ class IsingLogZ(_Planned):
             deg[v] += 1
         offsets = np.zeros(n + 1, dtype=np.int64)
         offsets[1:] = np.cumsum(2 ** deg)
-        super().__init__(n, edges, offsets, pairs, chi, precision, cutoff)
+        super().__init__(n, edges, offsets, pairs, chi, precision, cutoff, checkpoint_segments)
         self.beta = float(beta)
         self.n_edges = len(edges)
 

@@ -58,6 +58,7 @@ struct tn_ctx {
     // independent kernel kinds of one level run concurrently on these (fork/join per level)
     hipStream_t aux[kLanes - 1] = {nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> sync_ev;   // fork/join events (timing disabled)
+    std::vector<hipEvent_t> rc_ev;     // the same, for re-runs of forward segments in the reverse pass
     std::string err;
 
     GraphSpec g;
@@ -123,6 +124,9 @@ struct tn_ctx {
     double* d_grad = nullptr;         // host-destined gradient staging (n_input float64)
 
     bool evaluated = false;
+    // the forward arena holds what the last forward evaluation left there (no recomputation has
+    // written over it since), so the reverse pass need not re-run the last segment
+    bool fwd_fresh = false;
     double sign = 0, lnz = 0;
     int flags = 0;
 
@@ -1186,6 +1190,7 @@ void tn_destroy(tn_ctx* c) {
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->sync_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->rc_ev) (void)hipEventDestroy(e);
     for (hipStream_t a : c->aux)
         if (a) (void)hipStreamDestroy(a);
     delete c;
@@ -1285,6 +1290,9 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     if (opts->gauge_r < 0) return fail(c, TN_EINVAL, "gauge_r must be >= 0");
     if (opts->gauge_r > 0 && opts->grad) return fail(c, TN_EINVAL, "gauge_r >= 1 has no reverse pass (grad must be 0)");
     if (opts->compress_late != 0 && opts->compress_late != 1) return fail(c, TN_EINVAL, "compress_late must be 0 or 1");
+    if (opts->checkpoint_segments < -1) return fail(c, TN_EINVAL, "checkpoint_segments must be >= -1");
+    if ((opts->checkpoint_segments > 1 || opts->checkpoint_segments == -1) && !opts->grad)
+        return fail(c, TN_EINVAL, "checkpoint_segments is a reverse-pass option (grad must be 1)");
     if (opts->precision != TN_FP64 && opts->precision != TN_FP32 && opts->precision != TN_BF16)
         return fail(c, TN_EINVAL, "precision must be TN_FP64, TN_FP32 or TN_BF16");
     if (!(opts->cutoff >= 0.0)) return fail(c, TN_EINVAL, "cutoff must be >= 0");
@@ -1301,6 +1309,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.plain = opts->plain ? 1 : 0;
     o.late = opts->compress_late;
     o.gauge_r = opts->gauge_r;
+    o.segments = opts->checkpoint_segments;
     if (o.plain && o.grad) return fail(c, TN_EINVAL, "the plain form has no reverse pass (grad must be 0)");
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
     // level by level every independent branch advances at once; when that holds more than the
@@ -1437,6 +1446,49 @@ tn_status collect_stamps(tn_ctx* c) {
 }
 
 // Enqueue one forward evaluation on the context's streams (eager, or inside a capture).
+// Enqueue one forward launch of ctx c on stream st.
+static hipError_t run_forward_launch(tn_ctx* c, const Launch& l, hipStream_t st) {
+    const Plan& P = c->plan;
+    const int prec = P.opts.precision;
+    switch (l.kind) {
+        case L_GEMM: return launch_gemm(l.key, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
+        case L_COPY: return launch_copy(l.key, c->d_copy + l.begin, l.count, l.work, c->d_scales, st);
+        case L_CORE:
+            return launch_core(l.key, prec, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps, c->d_disc,
+                               c->d_tie, c->d_sweeps, st);
+        case L_LANCZOS:
+            return launch_lanczos(l.key, c->d_lanczos + l.begin, l.count, l.max_d, c->d_scales,
+                                  P.opts.jacobi_max_sweeps, c->d_disc, c->d_tie, c->d_sweeps, st);
+        case L_GLANCZOS:
+            return launch_gram_lanczos(l.key, c->d_glanczos + l.begin, l.count, P.opts.jacobi_max_sweeps, c->d_disc,
+                                       c->d_tie, c->d_sweeps, st);
+        case L_SCALE: return launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, st);
+        case L_REDUCE: return launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, st);
+        case L_SPRE: return launch_gemm(GEMM_F64, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
+        case L_KRYLOV: {
+            hipError_t err = hipSuccess;
+            for (int64_t i = l.begin; i < l.begin + l.count && err == hipSuccess; ++i) {
+                const KOp& o = c->h_kops[i];
+                switch (o.kind) {
+                    case KO_GEMM:
+                        err = launch_gemm(o.key, c->d_gemm + o.begin, o.count, o.work, c->d_scales, c->d_maxparts, st);
+                        break;
+                    case KO_REDUCE: err = launch_reduce(0, c->d_reduce + o.begin, o.count, o.work, c->d_scales, st); break;
+                    case KO_SMALL: err = launch_small(o.key, c->d_small + o.begin, o.count, o.work, st); break;
+                    case KO_CHOL: err = launch_cholinv(c->d_chol + o.begin, o.count, st); break;
+                    case KO_CORE:
+                        err = launch_core(o.key, 0, c->d_core + o.begin, o.count, o.max_d, P.opts.jacobi_max_sweeps,
+                                          c->d_disc, c->d_tie, c->d_sweeps, st);
+                        break;
+                    case KO_CHECK: err = launch_krylov_check(c->d_kcheck + o.begin, o.count, c->d_sweeps, st); break;
+                }
+            }
+            return err;
+        }
+    }
+    return hipSuccess;
+}
+
 tn_status enqueue_forward(tn_ctx* c) {
     Plan& P = c->plan;
     const int prec = P.opts.precision;
@@ -1455,55 +1507,7 @@ tn_status enqueue_forward(tn_ctx* c) {
             c->prof_flops[l.prof] += l.flops;
             c->prof_bytes[l.prof] += l.bytes;
         }
-        hipError_t err = hipSuccess;
-        switch (l.kind) {
-            case L_GEMM:
-                err = launch_gemm(l.key, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
-                break;
-            case L_COPY:
-                err = launch_copy(l.key, c->d_copy + l.begin, l.count, l.work, c->d_scales, st);
-                break;
-            case L_CORE:
-                err = launch_core(l.key, prec, c->d_core + l.begin, l.count, l.max_d, P.opts.jacobi_max_sweeps,
-                                  c->d_disc, c->d_tie, c->d_sweeps, st);
-                break;
-            case L_LANCZOS:
-                err = launch_lanczos(l.key, c->d_lanczos + l.begin, l.count, l.max_d, c->d_scales,
-                                     P.opts.jacobi_max_sweeps, c->d_disc, c->d_tie, c->d_sweeps, st);
-                break;
-            case L_GLANCZOS:
-                err = launch_gram_lanczos(l.key, c->d_glanczos + l.begin, l.count, P.opts.jacobi_max_sweeps,
-                                          c->d_disc, c->d_tie, c->d_sweeps, st);
-                break;
-            case L_SCALE:
-                err = launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, st);
-                break;
-            case L_REDUCE:
-                err = launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, st);
-                break;
-            case L_SPRE:
-                err = launch_gemm(GEMM_F64, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
-                break;
-            case L_KRYLOV:
-                for (int64_t i = l.begin; i < l.begin + l.count && err == hipSuccess; ++i) {
-                    const KOp& o = c->h_kops[i];
-                    switch (o.kind) {
-                        case KO_GEMM:
-                            err = launch_gemm(o.key, c->d_gemm + o.begin, o.count, o.work, c->d_scales, c->d_maxparts,
-                                              st);
-                            break;
-                        case KO_REDUCE: err = launch_reduce(0, c->d_reduce + o.begin, o.count, o.work, c->d_scales, st); break;
-                        case KO_SMALL: err = launch_small(o.key, c->d_small + o.begin, o.count, o.work, st); break;
-                        case KO_CHOL: err = launch_cholinv(c->d_chol + o.begin, o.count, st); break;
-                        case KO_CORE:
-                            err = launch_core(o.key, 0, c->d_core + o.begin, o.count, o.max_d, P.opts.jacobi_max_sweeps,
-                                              c->d_disc, c->d_tie, c->d_sweeps, st);
-                            break;
-                        case KO_CHECK: err = launch_krylov_check(c->d_kcheck + o.begin, o.count, c->d_sweeps, st); break;
-                    }
-                }
-                break;
-        }
+        hipError_t err = run_forward_launch(c, l, st);
         if (err == hipSuccess && timed) err = launch_stamp(c->d_stamps + 2 * pair + 1, st);
         return err;
     };
@@ -1623,6 +1627,7 @@ tn_status tn_fetch(tn_ctx* c) {
                     "a compression did not converge (Jacobi sweep cap, or a block-Krylov basis too small for a flat "
                     "core spectrum)");
     c->evaluated = true;
+    c->fwd_fresh = true;
     if ((c->flags & 1) || c->sign == 0.0) {
         c->sign = 0.0;
         c->lnz = -INFINITY;
@@ -1742,25 +1747,73 @@ tn_status tn_grad_device(tn_ctx* c, void* out) {
     const int prec = P.opts.precision;
     hipStream_t s = c->stream;
     const int fin = P.final_tensor;
-    HIP_TRY(c, launch_seed(prec, c->arena + P.bufs[P.tens[fin].buf].off, c->arena + P.bufs[P.adj_buf[fin]].off,
-                           c->d_scales, fin, s));
-    for (const Launch& l : c->blaunches) {
-        bool timed = false;
-        tn_status st = prof_begin(c, l, s, &timed);
-        if (st != TN_OK) return st;
-        switch (l.kind) {
-            case L_GEMM:
-                HIP_TRY(c, launch_gemm(l.key, c->d_bgemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, s));
-                break;
-            case L_REDUCE:
-                HIP_TRY(c, launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, s));
-                break;
-            case L_CORE_BWD:
-                HIP_TRY(c, launch_core_bwd(l.key, c->d_cbwd + l.begin, l.count, l.max_d, s));
-                break;
+    // Segments last to first: re-run the forward launches of a segment, then its reverse levels.
+    // The last segment is not re-run: the arena holds it from the evaluation.  A re-run of
+    // segment s writes over buffers of later segments, including checkpoints that the re-runs of
+    // later segments start from, so once any re-run has happened the arena no longer holds the
+    // evaluation: a later tn_grad first re-runs the whole forward schedule (inputs and scale
+    // slots are never written over).  The seed reads the final tensor, after those re-runs.
+    const int S = P.n_segments;
+    size_t bi = 0;
+    size_t next_ev = 0;
+    auto rerun_levels = [&](int32_t first, int32_t end) -> tn_status {
+        Launch tl;
+        tl.prof = TN_KERNEL_RECOMPUTE;
+        size_t b = 0;
+        while (b < c->launches.size() && c->launches[b].level < first) ++b;
+        size_t e = b;
+        while (e < c->launches.size() && c->launches[e].level < end) {
+            tl.flops += c->launches[e].flops;
+            tl.bytes += c->launches[e].bytes;
+            ++e;
         }
+        bool timed = false;
+        if (tn_status st = prof_begin(c, tl, s, &timed); st != TN_OK) return st;
+        auto run = [&](const Launch& l, hipStream_t st) { return run_forward_launch(c, l, st); };
+        hipEvent_t pending[2] = {nullptr, nullptr};
+        int open = 0;
+        for (size_t i = b; i < e;) {
+            size_t j = i;
+            while (j < e && c->launches[j].level == c->launches[i].level) ++j;
+            HIP_TRY(c, run_level(c->launches, i, j, s, c->aux, c->rc_ev, next_ev, run, pending, j < e, open));
+            i = j;
+        }
+        if (tn_status st = join_tail(c, s, pending, open, fail); st != TN_OK) return st;
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
+        return TN_OK;
+    };
+    if (S > 1 && !c->fwd_fresh) {
+        if (tn_status st = rerun_levels(1, P.seg_begin[S]); st != TN_OK) return st;
+        c->fwd_fresh = true;
     }
+    for (int seg = S - 1; seg >= 0; --seg) {
+        if (S > 1 && seg < S - 1 && P.seg_recompute[seg]) {
+            c->fwd_fresh = false;
+            if (tn_status st = rerun_levels(P.seg_begin[seg], P.seg_begin[seg + 1]); st != TN_OK) return st;
+        }
+        if (seg == S - 1)
+            HIP_TRY(c, launch_seed(prec, c->arena + P.bufs[P.tens[fin].buf].off,
+                                   c->arena + P.bufs[P.adj_buf[fin]].off, c->d_scales, fin, s));
+        for (; bi < c->blaunches.size() && c->blaunches[bi].level <= P.seg_bend[seg]; ++bi) {
+            const Launch& l = c->blaunches[bi];
+            bool timed = false;
+            tn_status st = prof_begin(c, l, s, &timed);
+            if (st != TN_OK) return st;
+            switch (l.kind) {
+                case L_GEMM:
+                    HIP_TRY(c, launch_gemm(l.key, c->d_bgemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, s));
+                    break;
+                case L_REDUCE:
+                    HIP_TRY(c, launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, s));
+                    break;
+                case L_CORE_BWD:
+                    HIP_TRY(c, launch_core_bwd(l.key, c->d_cbwd + l.begin, l.count, l.max_d, s));
+                    break;
+            }
+            if (timed) HIP_TRY(c, hipEventRecord(c->ev_pool[c->ev_used.back().second + 1], s));
+        }
+    }
+    if (bi != c->blaunches.size()) return fail(c, TN_EINVAL, "internal: reverse launches outside every segment");
     HIP_TRY(c, launch_grad_inputs(prec, c->d_gin, (int)c->h_gin.size(), c->d_scales, (double*)out, s));
     return TN_OK;
 }
@@ -1819,6 +1872,16 @@ tn_status tn_grad_info(const tn_ctx* c, double* bwd_flops, double* bwd_bytes, in
     if (bwd_flops) *bwd_flops = c->plan.bwd_flops;
     if (bwd_bytes) *bwd_bytes = c->plan.bwd_bytes;
     if (n_levels) *n_levels = c->plan.n_blevels;
+    return TN_OK;
+}
+
+tn_status tn_grad_checkpoint_info(const tn_ctx* c, int32_t* segments, double* recompute_flops,
+                                  int64_t* checkpoint_bytes) {
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan || !c->plan.opts.grad) return TN_ESTATE;
+    if (segments) *segments = c->plan.n_segments;
+    if (recompute_flops) *recompute_flops = c->plan.recompute_flops;
+    if (checkpoint_bytes) *checkpoint_bytes = c->plan.checkpoint_bytes;
     return TN_OK;
 }
 
@@ -2249,7 +2312,7 @@ tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out) {
             return fail(ctxs[i], TN_EINVAL, "tn_batch_create: block-Krylov compressions are not merged into batches");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context appears twice");
-        grad = grad && ctxs[i]->plan.opts.grad;
+        grad = grad && ctxs[i]->plan.opts.grad && ctxs[i]->plan.n_segments <= 1;
     }
     (void)hipSetDevice(dev);
     tn_batch* b = new tn_batch();
@@ -2351,6 +2414,7 @@ tn_status tn_batch_contract(tn_batch* b, double* mantissas, double* log10_expone
         c->lnz = r[1];
         c->flags = (int)r[2];
         c->evaluated = true;
+        c->fwd_fresh = true;
         double m = 0.0, e = -INFINITY;
         tn_status st = TN_OK;
         if (c->flags & 2) st = fail(c, TN_ENUMERIC, "non-finite tensor entry");
@@ -2378,7 +2442,10 @@ tn_status tn_batch_contract(tn_batch* b, double* mantissas, double* log10_expone
 
 tn_status tn_batch_grad(tn_batch* b, void* const* dlnz_ddata_dev) {
     if (!b) return TN_EINVAL;
-    if (!b->grad) return bfail(b, TN_ESTATE, "the batch's contexts were not all planned with opts.grad");
+    if (!b->grad)
+        return bfail(b, TN_ESTATE,
+                     "the batch's contexts were not all planned with opts.grad and a single segment "
+                     "(a recomputed reverse pass runs per context: tn_grad)");
     if (!dlnz_ddata_dev) return bfail(b, TN_EINVAL, "null output array");
     for (size_t i = 0; i < b->ctxs.size(); ++i) {
         if (!dlnz_ddata_dev[i]) return bfail(b, TN_EINVAL, "null gradient buffer");

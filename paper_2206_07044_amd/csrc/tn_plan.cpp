@@ -130,6 +130,72 @@ struct BwdOp {
     int32_t comp = -1;
 };
 
+// First-fit free list over arena byte offsets; blocks are rounded up to kAlign, and an
+// allocation that fits no free block extends the top (taking a free block that touches it).
+struct FreeList {
+    std::map<int64_t, int64_t> freel;   // offset -> size
+    int64_t top;
+    explicit FreeList(int64_t base) : top(base) {}
+    int64_t alloc(int64_t bytes) {
+        bytes = align_up(bytes);
+        for (auto it = freel.begin(); it != freel.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first;
+                const int64_t rest = it->second - bytes;
+                freel.erase(it);
+                if (rest > 0) freel[off + bytes] = rest;
+                return off;
+            }
+        }
+        int64_t off = top;
+        if (!freel.empty()) {
+            auto it = std::prev(freel.end());
+            if (it->first + it->second == top) {
+                off = it->first;
+                freel.erase(it);
+            }
+        }
+        top = off + bytes;
+        return off;
+    }
+    void release(int64_t off, int64_t bytes) {
+        bytes = align_up(bytes);
+        auto it = freel.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != freel.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            freel.erase(nx);
+        }
+        if (it != freel.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                freel.erase(it);
+            }
+        }
+    }
+};
+
+// Segment starts for checkpointed recomputation: `want` contiguous ranges of forward levels
+// 1..maxl holding about equal bytes of the buffers produced in them (fewer when levels run out).
+std::vector<int32_t> segment_starts(const std::vector<Buf>& bufs, int32_t maxl, int32_t want) {
+    std::vector<double> at(maxl + 2, 0.0);
+    double total = 0;
+    for (const Buf& b : bufs)
+        if (b.kind != BUF_INPUT && b.kind != BUF_BWD && b.lo >= 1 && b.lo <= maxl) {
+            at[b.lo] += (double)b.bytes;
+            total += (double)b.bytes;
+        }
+    std::vector<int32_t> sb{1};
+    double cum = 0;
+    for (int32_t L = 1; L <= maxl && (int32_t)sb.size() < want; ++L) {
+        if (L > sb.back() && cum >= total * (double)sb.size() / want) sb.push_back(L);
+        cum += at[L];
+    }
+    sb.push_back(maxl + 1);
+    return sb;
+}
+
 }  // namespace
 
 KrylovLayout krylov_layout(int64_t n, int64_t D, int64_t my, int64_t nw, int64_t b, int64_t k, int full,
@@ -991,75 +1057,98 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
     P->n_levels = maxl;
     for (auto& b : P->bufs)
         if (b.kind == BUF_INPUT) b.hi = INT_MAX;
-    if (o.grad) {
-        // the reverse pass reads every tensor version, core workspace and projector
-        for (auto& b : P->bufs)
-            if (b.kind == BUF_TENSOR || b.kind == BUF_WORK || b.kind == BUF_PROJ) b.hi = INT_MAX;
-    }
     // the final tensor is read by the result kernel after the last level
     P->bufs[P->tens[last].buf].hi = INT_MAX;
 
-    // ---------------------------------------------------------- arena: allocate by level, free after last use
-    std::vector<std::vector<int32_t>> starts(maxl + 1), ends(maxl + 1);
-    std::vector<int32_t> persistent;
-    for (int32_t b = 0; b < (int32_t)P->bufs.size(); ++b) {
-        Buf& B = P->bufs[b];
-        if (B.kind == BUF_BWD) continue;
-        starts[std::min(B.lo, maxl)].push_back(b);
-        if (B.hi != INT_MAX) ends[std::min(B.hi, maxl)].push_back(b);
-    }
-    std::map<int64_t, int64_t> freel;   // offset -> size
-    int64_t top = 0;
-    auto alloc = [&](int64_t bytes) {
-        bytes = align_up(bytes);
-        for (auto it = freel.begin(); it != freel.end(); ++it) {
-            if (it->second >= bytes) {
-                int64_t off = it->first;
-                int64_t rest = it->second - bytes;
-                freel.erase(it);
-                if (rest > 0) freel[off + bytes] = rest;
-                return off;
-            }
-        }
-        int64_t off = top;
-        // extend a trailing free block if it touches the top
-        if (!freel.empty()) {
-            auto it = std::prev(freel.end());
-            if (it->first + it->second == top) {
-                off = it->first;
-                freel.erase(it);
-            }
-        }
-        top = off + bytes;
-        return off;
-    };
-    auto release = [&](int64_t off, int64_t bytes) {
-        bytes = align_up(bytes);
-        auto it = freel.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != freel.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            freel.erase(nx);
-        }
-        if (it != freel.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                freel.erase(it);
-            }
-        }
-    };
-    for (int L = 0; L <= maxl; ++L) {
-        // largest first for less fragmentation
-        std::sort(starts[L].begin(), starts[L].end(),
-                  [&](int32_t x, int32_t y) { return P->bufs[x].bytes > P->bufs[y].bytes; });
-        for (int32_t b : starts[L]) P->bufs[b].off = alloc(P->bufs[b].bytes);
-        if (!o.keep)
-            for (int32_t b : ends[L]) release(P->bufs[b].off, P->bufs[b].bytes);
-    }
-    // ---------------------------------------------------------- reverse pass: levels and buffers
+    // ---------------------------------------------------------- reverse pass: what each op reads
+    // A reverse op belongs to the forward level of the outputs of its forward op; the forward
+    // buffers it reads (operands, core workspace, projectors) are kept at least to that level.
+    std::vector<int32_t> bop_level(bops.size(), 0);
+    std::vector<uint8_t> bwd_read(P->bufs.size(), 0);
     if (o.grad) {
-        adj_of(last);
+        for (size_t k = 0; k < bops.size(); ++k) {
+            int32_t Lb = 0;
+            for (int32_t v : bops[k].outs)
+                if (v >= 0) Lb = std::max(Lb, P->tens[v].level);
+            bop_level[k] = Lb;
+            auto reads = [&](int32_t b) {
+                if (b < 0 || P->bufs[b].kind == BUF_BWD) return;
+                bwd_read[b] = 1;
+                touch(b, Lb);
+            };
+            for (const BStep& st : bops[k].steps) {
+                if (st.kind == BS_GEMM) {
+                    reads(st.a_buf);
+                    reads(st.b_buf);
+                } else if (st.kind == BS_CORE_BWD) {
+                    reads(P->comps[bops[k].comp].work_buf);
+                }
+            }
+        }
+    }
+    std::vector<int32_t> hi0(P->bufs.size());
+    for (size_t b = 0; b < P->bufs.size(); ++b) hi0[b] = P->bufs[b].hi;
+
+    // Lay out the arena for `want` segments (grad; 1 = every forward buffer resident) and return
+    // its size.  Forward buffers: a buffer live across a segment boundary, or the last level, is
+    // kept to the end (a checkpoint); one that lives inside a segment and is read by the reverse
+    // pass is kept to the end of its segment; the rest are freed after their last forward read.
+    // So at the last level of segment s everything the re-run of s and its reverse ops read is
+    // live at once, at disjoint offsets, and a re-run of s writes only over buffers of segment s
+    // and of later segments, whose reverse ops are done.  Reverse-pass buffers sit above the
+    // forward arena, allocated by reverse level and freed after their last use.
+    auto layout = [&](int32_t want) -> int64_t {
+        for (size_t b = 0; b < P->bufs.size(); ++b) P->bufs[b].hi = hi0[b];
+        P->bsteps.clear();
+        P->seg_begin.clear();
+        P->seg_bend.clear();
+        P->seg_recompute.clear();
+        P->recompute_flops = 0;
+        P->checkpoint_bytes = 0;
+        std::vector<int32_t> sb{1, maxl + 1};
+        if (o.grad && want > 1) sb = segment_starts(P->bufs, maxl, want);
+        const int32_t S = (int32_t)sb.size() - 1;
+        P->n_segments = S;
+        auto seg_of = [&](int32_t L) {
+            return (int32_t)(std::upper_bound(sb.begin(), sb.end(), L) - sb.begin()) - 1;
+        };
+        if (o.grad && S == 1) {
+            for (auto& b : P->bufs)
+                if (b.kind == BUF_TENSOR || b.kind == BUF_WORK || b.kind == BUF_PROJ) b.hi = INT_MAX;
+        } else if (o.grad) {
+            for (size_t b = 0; b < P->bufs.size(); ++b) {
+                Buf& B = P->bufs[b];
+                if (B.kind == BUF_INPUT || B.kind == BUF_BWD || B.hi == INT_MAX) continue;
+                const int32_t s0 = seg_of(std::max(B.lo, 1));
+                if (B.hi > maxl || seg_of(B.hi) > s0) {
+                    B.hi = INT_MAX;
+                    P->checkpoint_bytes += B.bytes;
+                } else if (bwd_read[b]) {
+                    B.hi = sb[s0 + 1] - 1;
+                }
+            }
+        }
+        // forward arena: allocate by level, free after last use
+        std::vector<std::vector<int32_t>> starts(maxl + 1), ends(maxl + 1);
+        for (int32_t b = 0; b < (int32_t)P->bufs.size(); ++b) {
+            const Buf& B = P->bufs[b];
+            if (B.kind == BUF_BWD) continue;
+            starts[std::min(B.lo, maxl)].push_back(b);
+            if (B.hi != INT_MAX) ends[std::min(B.hi, maxl)].push_back(b);
+        }
+        FreeList fwd(0);
+        for (int L = 0; L <= maxl; ++L) {
+            // largest first for less fragmentation
+            std::sort(starts[L].begin(), starts[L].end(),
+                      [&](int32_t x, int32_t y) { return P->bufs[x].bytes > P->bufs[y].bytes; });
+            for (int32_t b : starts[L]) P->bufs[b].off = fwd.alloc(P->bufs[b].bytes);
+            if (!o.keep)
+                for (int32_t b : ends[L]) fwd.release(P->bufs[b].off, P->bufs[b].bytes);
+        }
+        if (!o.grad) return fwd.top;
+        // reverse levels: segments last to first; inside one, ops in reverse creation order, each
+        // as soon as the adjoints of its outputs are complete (consumers come later in creation
+        // order and in the same or a later segment)
         std::vector<int32_t> ready(P->tens.size(), 0);
         BStep seed;
         seed.kind = BS_SEED;
@@ -1067,30 +1156,90 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
         P->bsteps.push_back(seed);
         ready[last] = 1;
         int32_t maxb = 1;
-        for (auto it = bops.rbegin(); it != bops.rend(); ++it) {
-            int32_t L0 = 0;
-            for (int32_t v : it->outs)
-                if (v >= 0) L0 = std::max(L0, ready[v]);
-            for (BStep st : it->steps) {
-                st.level += L0;
-                if (st.kind == BS_CORE_BWD) st.comp = it->comp;
-                maxb = std::max(maxb, st.level);
-                P->bsteps.push_back(st);
+        P->seg_bend.assign(S, 0);
+        P->seg_recompute.assign(S, 0);
+        for (int32_t s = S - 1; s >= 0; --s) {
+            const int32_t base = s == S - 1 ? 0 : maxb;
+            for (size_t k = bops.size(); k-- > 0;) {
+                if (seg_of(bop_level[k]) != s) continue;
+                const BwdOp& op = bops[k];
+                int32_t L0 = base;
+                for (int32_t v : op.outs)
+                    if (v >= 0) L0 = std::max(L0, ready[v]);
+                for (BStep st : op.steps) {
+                    st.level += L0;
+                    if (st.kind == BS_CORE_BWD) st.comp = op.comp;
+                    maxb = std::max(maxb, st.level);
+                    P->bsteps.push_back(st);
+                }
+                for (int t = 0; t < 2; ++t)
+                    if (op.ins[t] >= 0) ready[op.ins[t]] = L0 + op.done[t];
+                P->seg_recompute[s] = 1;
             }
-            for (int t = 0; t < 2; ++t)
-                if (it->ins[t] >= 0) ready[it->ins[t]] = L0 + it->done[t];
+            P->seg_bend[s] = maxb;
         }
         P->n_blevels = maxb;
-        for (auto& b : P->bufs)
-            if (b.kind == BUF_BWD) {
-                b.off = top;
-                top += align_up(b.bytes);
+        for (auto& st : P->steps)
+            if (seg_of(st.level) < S - 1 && P->seg_recompute[seg_of(st.level)]) P->recompute_flops += st.flops;
+        P->seg_begin = sb;
+        // reverse-pass buffers: live from their first to their last reverse level; adjoints of
+        // the inputs are read after the last level (by the gradient copy-out)
+        std::vector<int32_t> rlo(P->bufs.size(), INT_MAX), rhi(P->bufs.size(), -1);
+        auto use = [&](int32_t b, int32_t L) {
+            if (b < 0 || P->bufs[b].kind != BUF_BWD) return;
+            rlo[b] = std::min(rlo[b], L);
+            rhi[b] = std::max(rhi[b], L);
+        };
+        for (const BStep& st : P->bsteps) {
+            if (st.kind == BS_SEED) {
+                use(P->adj_buf[last], st.level);
+            } else if (st.kind == BS_CORE_BWD) {
+                const CompBwd& cb = P->cbwd[st.comp];
+                for (int32_t b : {cb.h_buf, cb.na_buf, cb.nb_buf, cb.work_buf}) use(b, st.level);
+            } else {
+                use(st.a_buf, st.level);
+                use(st.b_buf, st.level);
+                use(st.c_buf, st.level);
             }
+        }
+        for (int v = 0; v < g.n && v < (int)P->adj_buf.size(); ++v)
+            if (P->adj_buf[v] >= 0) rhi[P->adj_buf[v]] = INT_MAX;
+        std::vector<std::vector<int32_t>> rstarts(maxb + 1), rends(maxb + 1);
+        for (int32_t b = 0; b < (int32_t)P->bufs.size(); ++b) {
+            if (P->bufs[b].kind != BUF_BWD) continue;
+            if (rlo[b] == INT_MAX) rlo[b] = 1;   // never touched: any slot will do
+            if (rhi[b] < 0) rhi[b] = rlo[b];
+            rstarts[std::min(rlo[b], maxb)].push_back(b);
+            if (rhi[b] != INT_MAX) rends[std::min(rhi[b], maxb)].push_back(b);
+        }
+        FreeList rev(fwd.top);
+        for (int L = 0; L <= maxb; ++L) {
+            std::sort(rstarts[L].begin(), rstarts[L].end(),
+                      [&](int32_t x, int32_t y) { return P->bufs[x].bytes > P->bufs[y].bytes; });
+            for (int32_t b : rstarts[L]) P->bufs[b].off = rev.alloc(P->bufs[b].bytes);
+            for (int32_t b : rends[L]) rev.release(P->bufs[b].off, P->bufs[b].bytes);
+        }
+        return rev.top;
+    };
+    int32_t want = o.grad ? std::max(o.segments, 1) : 1;
+    if (o.grad && o.segments < 0) {
+        // the candidate count of smallest arena (ties: fewer segments, less re-running)
+        int64_t best = -1;
+        for (int32_t cand : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}) {
+            if (cand > 1 && cand > maxl) break;
+            const int64_t bytes = layout(cand);
+            if (best < 0 || bytes < best) {
+                best = bytes;
+                want = cand;
+            }
+        }
+    }
+    int64_t top = layout(want);
+    if (o.grad)
         for (auto& st : P->bsteps) {
             P->bwd_flops += st.flops;
             P->bwd_bytes += st.bytes;
         }
-    }
     P->arena_bytes = top;
 
     // ---------------------------------------------------------- totals

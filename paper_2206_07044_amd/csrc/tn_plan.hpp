@@ -36,6 +36,8 @@ struct TreeOpts {
     int32_t ordered = 0;            // contraction levels follow the tree order (memory of a sequential run)
     int32_t late = 0;               // late compression: bonds of i and j compressed before contracting them
     int32_t gauge_r = 0;            // tree-gauge distance r of every compression
+    int32_t segments = 0;           // grad: forward levels in this many recomputed segments (<= 1: none;
+                                    // -1: the count of smallest arena among a few candidates)
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).
@@ -186,6 +188,15 @@ struct Plan {
     std::vector<CompBwd> cbwd;
     int32_t n_blevels = 0;
     double bwd_flops = 0, bwd_bytes = 0;
+    // checkpointed recomputation (opts.segments): segment s holds forward levels
+    // [seg_begin[s], seg_begin[s+1]); the reverse pass takes the segments last to first, re-running
+    // the forward launches of a segment (all but the last, right after a forward evaluation) and
+    // then its reverse levels up to seg_bend[s].  One segment: no recomputation.
+    int32_t n_segments = 1;
+    std::vector<int32_t> seg_begin, seg_bend;
+    std::vector<uint8_t> seg_recompute;  // 1 if the segment has reverse steps, so is re-run
+    double recompute_flops = 0;          // forward flops of segments 0 .. S-2 that are re-run
+    int64_t checkpoint_bytes = 0;        // forward buffers kept across a segment boundary
 };
 
 // Validate the graph (returns "" or an error message).
