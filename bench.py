@@ -248,10 +248,11 @@ def spin_glass_leg(tn, torch, L, chi, beta, steps):
     out = {"lattice": list(shape), "beta": beta, "chi": chi, "couplings": "+-1, default_rng(0)",
            "tree": "Span family, axis-ordered spanning tree swept leaves-inwards", "n_bonds": g.n_edges}
     grads = {}
-    for prec in ("fp64", "fp32"):
+
+    def variant(prec, segments):
         c = tn.Context(0)
         c.tn_load_graph(g.n, eu, ev, ed, off, data)
-        c.tn_set_tree(pi, pj, chi, precision=prec, grad=True)
+        c.tn_set_tree(pi, pj, chi, precision=prec, grad=True, checkpoint_segments=segments)
         info, binfo = c.tn_plan_info(), c.tn_grad_info()
         dT = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
         dJ = torch.empty(g.n_edges, dtype=torch.float64, device="cuda")
@@ -274,14 +275,27 @@ def spin_glass_leg(tn, torch, L, chi, beta, steps):
         gT = dT.cpu().numpy()
         eul = np.abs([float(np.dot(data[off[v]:off[v + 1]], gT[off[v]:off[v + 1]])) - 1.0 for v in range(g.n)])
         _, tie, _ = c.tn_compress_stats()
-        grads[prec] = dJ.cpu().numpy()
         flops = info["fwd_flops"] + binfo["bwd_flops"]
-        out[prec] = {"ms_per_step": dt * 1e3, "fwd_bwd_per_s": 1.0 / dt, "tflops": flops / dt / 1e12,
-                     "fwd_flops": info["fwd_flops"], "bwd_flops": binfo["bwd_flops"],
-                     "arena_bytes": info["arena_bytes"], "ln_abs_z": lnz, "sign": sign,
-                     "euler_identity_error_max": float(eul.max()), "euler_identity_error_median": float(np.median(eul)),
-                     "tie_flags": int(np.sum(tie)), "steps": steps}
+        rec = {"ms_per_step": dt * 1e3, "fwd_bwd_per_s": 1.0 / dt, "tflops": flops / dt / 1e12,
+               "fwd_flops": info["fwd_flops"], "bwd_flops": binfo["bwd_flops"],
+               "arena_bytes": info["arena_bytes"], "ln_abs_z": lnz, "sign": sign,
+               "euler_identity_error_max": float(eul.max()), "euler_identity_error_median": float(np.median(eul)),
+               "tie_flags": int(np.sum(tie)), "steps": steps}
+        if segments != 0:
+            ck = c.tn_grad_checkpoint_info()
+            rec.update({"segments": ck["segments"], "checkpoint_bytes": ck["checkpoint_bytes"],
+                        "recompute_flops": ck["recompute_flops"]})
         c.close()
+        return rec, dJ.cpu().numpy()
+
+    for prec in ("fp64", "fp32"):
+        out[prec], grads[prec] = variant(prec, 0)
+    # FP64 with checkpointed recomputation (segment count of smallest arena)
+    rec, dJr = variant("fp64", -1)
+    rec["arena_ratio"] = rec["arena_bytes"] / out["fp64"]["arena_bytes"]
+    rec["time_ratio"] = rec["ms_per_step"] / out["fp64"]["ms_per_step"]
+    rec["dJ_max_abs_diff_vs_resident"] = float(np.max(np.abs(dJr - grads["fp64"])))
+    out["fp64_recompute"] = rec
     d = np.abs(grads["fp32"] - grads["fp64"])
     scale = float(np.max(np.abs(grads["fp64"])))
     out["dJ_fp32_vs_fp64"] = {"max_abs": float(d.max()), "median_abs": float(np.median(d)),
@@ -814,6 +828,34 @@ def main() -> int:
                         "arena_bytes": ginfo["arena_bytes"], "max_euler_identity_error": float(eul.max()),
                         "median_euler_identity_error": float(np.median(eul)), "steps": args.fwd_bwd_steps}
             gctx.close()
+            if prec != args.precision:
+                continue
+            # the same step with checkpointed recomputation (segment count of smallest arena): the
+            # reverse pass re-runs forward segments instead of keeping them resident
+            rctx = tn.Context(0)
+            rctx.tn_load_graph(g.n, eu, ev, ed, off, data)
+            rctx.tn_set_tree(pi, pj, args.chi, precision=prec, grad=True, checkpoint_segments=-1)
+            rinfo, rck = rctx.tn_plan_info(), rctx.tn_grad_checkpoint_info()
+            rdev = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+            rctx.tn_contract_compressed()
+            rctx.tn_grad_device(rdev.data_ptr())
+            rctx.tn_sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.fwd_bwd_steps):
+                rctx.tn_contract_compressed()
+                rctx.tn_grad_device(rdev.data_ptr())
+                rctx.tn_sync()
+            torch.cuda.synchronize()
+            rdt = (time.perf_counter() - t0) / args.fwd_bwd_steps
+            rg = rdev.cpu().numpy()
+            fb[prec]["recompute"] = {"segments": rck["segments"], "arena_bytes": rinfo["arena_bytes"],
+                                     "checkpoint_bytes": rck["checkpoint_bytes"],
+                                     "recompute_flops": rck["recompute_flops"], "ms_per_step": rdt * 1e3,
+                                     "arena_ratio": rinfo["arena_bytes"] / ginfo["arena_bytes"],
+                                     "time_ratio": rdt / gdt,
+                                     "gradient_max_abs_diff_vs_resident": float(np.max(np.abs(rg - gg)))}
+            rctx.close()
         out["fwd_bwd"] = fb
         if "fp64" in fb and not args.no_fp64_reference:
             out["fwd_bwd"]["tflops_vs_plain_fp64_forward"] = fb[args.precision]["tflops"] / (
