@@ -601,6 +601,7 @@ def main() -> int:
     ap.add_argument("--no-tree-scoring", action="store_true", help="skip the device-side tree-scoring leg")
     ap.add_argument("--no-tree-gauge", action="store_true", help="skip the tree-gauge accuracy leg")
     ap.add_argument("--no-second-workloads", action="store_true", help="skip the pyrochlore leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in GEMM tile table")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the executor has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -609,6 +610,13 @@ def main() -> int:
 
     import torch
     import paper_2206_07044_amd as tn
+    from paper_2206_07044_amd import autotune
+
+    # tile shapes of the skinny GEMMs: measured on this GPU for the precisions timed below, before
+    # any tree is planned (--no-autotune keeps the library's built-in table)
+    tune_report = None
+    if not args.no_autotune:
+        tune_report = autotune.tune(precisions=tuple(dict.fromkeys((args.precision, "fp64"))), copies=8)
 
     shape = tuple(int(x) for x in args.shape.split(","))
     g, T, pairs = build_instance(shape, args.beta)
@@ -691,6 +699,9 @@ def main() -> int:
             "launches_per_step": prof["launches"] / args.steps, "avg_launch_ms": avg_ms,
             "kernel_ms_per_step": {k: v["ms"] / max(1, args.warmup) for k, v in kinds.items()},
         },
+        "gemm_autotune": None if tune_report is None else {
+            "seconds": tune_report["seconds"], "classes_timed": len(tune_report["timings_us"]),
+            "changed_from_builtin": tune_report["changed"]},
     }
     g_prof = kinds["gemm"]
     if g_prof["launches"]:

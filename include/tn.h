@@ -349,6 +349,48 @@ tn_status tn_compress_pair_static(tn_ctx* ctx, const double* a_dev, const double
                                   int64_t m_b, int32_t chi, double cutoff, double* a_out, double* b_out,
                                   int32_t* chi_out);
 
+/* ---- Tile shapes of the tensor GEMMs (autotuning) ------------------------
+ * A contraction or re-absorption GEMM whose short side (M or N) is at most 32
+ * while the other exceeds 64 takes the tile shape that a process-wide table
+ * holds for its class (other GEMMs take 64 x 64 MFMA tiles).  Class index:
+ *   ((((prec * 2 + wide) * 2 + short32) * 3 + kclass) * 2 + long_unit
+ * prec: tn_precision; wide: 1 if M is the short side; short32: 1 if the short
+ * side is 17..32; kclass: 0 for K <= 4, 1 for K <= 64, 2 above; long_unit: 1 if
+ * the long operand's long axis has unit stride.  Entries are tn_gemm_tile
+ * values.  The table is read when tn_set_tree plans; plans keep their tiles.
+ * Every tile computes the same product (only the summation order differs). */
+#define TN_GEMM_CLASSES 72
+typedef enum {
+    TN_TILE_64x64 = 0,       /* MFMA, 64 x 64 */
+    TN_TILE_256x16 = 1,      /* MFMA, tall (short side <= 16) */
+    TN_TILE_16x256 = 2,      /* MFMA, wide (short side <= 16) */
+    TN_TILE_128x32 = 3,      /* MFMA, tall */
+    TN_TILE_32x128 = 4,      /* MFMA, wide */
+    TN_TILE_SKINNY_TALL16 = 5,  /* vector FMA, one row of C per thread (N <= 16, K <= 64) */
+    TN_TILE_SKINNY_TALL32 = 6,  /* the same, N <= 32 */
+    TN_TILE_SKINNY_WIDE16 = 7,  /* vector FMA, one column of C per thread (M <= 16, K <= 64) */
+    TN_TILE_SKINNY_WIDE32 = 8   /* the same, M <= 32 */
+} tn_gemm_tile;
+
+/* Copy the current table (TN_GEMM_CLASSES int32 entries, host memory). */
+tn_status tn_gemm_tiles_get(int32_t* table);
+/* Install a table (host memory), or the built-in defaults when table is NULL.
+ * TN_EINVAL, leaving the table unchanged, if an entry is not a tile for its
+ * class (a tall tile for a wide class, a 16-wide tile for a 32 side, a skinny
+ * tile with K > 64).  Not synchronised with concurrent tn_set_tree calls in
+ * other threads beyond each call seeing a whole table. */
+tn_status tn_gemm_tiles_set(const int32_t* table);
+/* Measure one class on device `device`: `copies` GEMMs of the class's
+ * representative shape (long side 65536, or 16384 for K > 64; short side 16 or
+ * 32; K = 2, 32 or 256) in one grouped launch, 10 timed launches after 2 warm-up
+ * ones.  us[t] receives the microseconds per launch of tile t (TN_TILE_*), or -1
+ * where the tile does not apply to the class; `us` holds 9 entries.  Allocates
+ * and frees its own device memory (up to about 1 GB at copies = 8).  The
+ * autotuner (paper_2206_07044_amd/autotune.py) installs the fastest tile of
+ * each class with tn_gemm_tiles_set.  TN_EINVAL for a bad class or copies
+ * outside 1..64; TN_EDEVICE on a HIP error. */
+tn_status tn_gemm_tune(int device, int32_t klass, int32_t copies, double* us);
+
 /* Host-only expansion of Algorithm 1 on shapes (no device use): writes up
  * to `cap` ops as 8 int64 each: (kind, a, b, out, m, n, k, new_dim) with
  * kind 0 = contract: (i, j, new id, free size of i, shared size, free size of

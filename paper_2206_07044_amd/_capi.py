@@ -85,6 +85,9 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_grad_device": ([P, P], C.c_int),
         "tn_grad_info": ([P, pD, pD, pI32], C.c_int),
         "tn_grad_checkpoint_info": ([P, pI32, pD, pI64], C.c_int),
+        "tn_gemm_tiles_get": ([pI32], C.c_int),
+        "tn_gemm_tiles_set": ([pI32], C.c_int),
+        "tn_gemm_tune": ([C.c_int, I32, I32, pD], C.c_int),
         "tn_ising_values_device": ([P, D, P], C.c_int),
         "tn_sync": ([P], C.c_int),
         "tn_batch_create": ([I32, C.POINTER(P), C.POINTER(P)], C.c_int),
@@ -113,7 +116,8 @@ def exported_symbols() -> List[str]:
             "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
             "tn_grad_device", "tn_grad_info", "tn_grad_checkpoint_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
             "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
-            "tn_plan_describe", "tn_compress_pair", "tn_compress_pair_static"]
+            "tn_plan_describe", "tn_compress_pair", "tn_compress_pair_static", "tn_gemm_tiles_get",
+            "tn_gemm_tiles_set", "tn_gemm_tune"]
 
 
 def _i32(a) -> np.ndarray:
@@ -152,6 +156,42 @@ def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int,
     if st != TN_OK:
         raise TNError(st, "invalid graph or tree")
     return [tuple(int(x) for x in row) for row in buf[:n_ops.value]]
+
+
+GEMM_CLASSES = 72
+GEMM_TILES = ["64x64", "256x16", "16x256", "128x32", "32x128", "skinny_tall16", "skinny_tall32", "skinny_wide16",
+              "skinny_wide32"]
+
+
+def tn_gemm_tiles_get() -> np.ndarray:
+    """The process-wide tile table (one tn_gemm_tile per class)."""
+    t = np.zeros(GEMM_CLASSES, dtype=np.int32)
+    st = load_library().tn_gemm_tiles_get(_ptr(t, C.c_int32))
+    if st != TN_OK:
+        raise TNError(st, "tn_gemm_tiles_get")
+    return t
+
+
+def tn_gemm_tiles_set(table: Optional[Sequence[int]]) -> None:
+    """Install a tile table, or the built-in defaults with None."""
+    if table is None:
+        st = load_library().tn_gemm_tiles_set(None)
+    else:
+        t = _i32(table)
+        if t.size != GEMM_CLASSES:
+            raise ValueError(f"a tile table has {GEMM_CLASSES} entries")
+        st = load_library().tn_gemm_tiles_set(_ptr(t, C.c_int32))
+    if st != TN_OK:
+        raise TNError(st, "a tile does not fit its class")
+
+
+def tn_gemm_tune(klass: int, copies: int = 8, device: int = 0) -> np.ndarray:
+    """Microseconds per grouped launch of every tile on the class's representative shape (-1: n/a)."""
+    us = np.zeros(len(GEMM_TILES), dtype=np.float64)
+    st = load_library().tn_gemm_tune(int(device), int(klass), int(copies), _ptr(us, C.c_double))
+    if st != TN_OK:
+        raise TNError(st, f"tn_gemm_tune(class {klass})")
+    return us
 
 
 class Context:

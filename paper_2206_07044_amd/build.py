@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["tn_kernels.hip", "tn_static.hip", "tn_plan.cpp", "tn_compress.cpp", "tn_krylov.cpp", "tn_capi.cpp"]
+SOURCES = ["tn_kernels.hip", "tn_static.hip", "tn_plan.cpp", "tn_compress.cpp", "tn_krylov.cpp", "tn_tune.cpp", "tn_capi.cpp"]
 LIB = os.path.join(HERE, "libtn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("CXX", "g++")

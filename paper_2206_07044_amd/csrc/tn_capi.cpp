@@ -14,6 +14,7 @@
 #include "tn_kernels.hpp"
 #include "tn_krylov.hpp"
 #include "tn_plan.hpp"
+#include "tn_tune.hpp"
 #include "tn_static.hpp"
 
 using namespace tn;
@@ -406,6 +407,12 @@ tn_status build_launches(tn_ctx* c) {
                         g.scale_b = st.in_a;
                     }
                     g.C = ten_ptr(st.out_t);
+                    // tile shape by the GEMM's short side (per-tile maxima follow the tiling)
+                    const int variant = pick_gemm_tile(prec, st.M, st.N, st.K, g.va.row_unit != 0, g.vb.col_unit != 0);
+                    int bm = 64, bn = 64;
+                    gemm_tile(variant, &bm, &bn);
+                    g.tiles_m = (int32_t)((st.M + bm - 1) / bm);
+                    g.tiles_n = (int32_t)((st.N + bn - 1) / bn);
                     g.maxpart = (int32_t)parts;
                     ScaleDesc sd{};
                     sd.maxpart = (int32_t)parts;
@@ -413,7 +420,7 @@ tn_status build_launches(tn_ctx* c) {
                     sd.tensor = st.out_t;
                     scales.push_back(sd);
                     parts += sd.nparts;
-                    key = 2 * tensor_key(prec);
+                    key = 2 * (tensor_key(prec) + kGemmVariantStride * variant);
                 }
                 gemms[key].push_back(g);
                 gemm_work[key].first += st.flops;
@@ -867,15 +874,19 @@ tn_status build_bwd_launches(tn_ctx* c) {
                 g.M = (int32_t)st.M;
                 g.N = (int32_t)st.N;
                 g.K = (int32_t)st.K;
-                g.tiles_m = (int32_t)((st.M + 63) / 64);
-                g.tiles_n = (int32_t)((st.N + 63) / 64);
+                const int variant =
+                    st.partial ? GV_64x64 : pick_gemm_tile(prec, st.M, st.N, st.K, g.va.row_unit != 0, g.vb.col_unit != 0);
+                int bm = 64, bn = 64;
+                gemm_tile(variant, &bm, &bn);
+                g.tiles_m = (int32_t)((st.M + bm - 1) / bm);
+                g.tiles_n = (int32_t)((st.N + bn - 1) / bn);
                 g.splits = st.splits;
                 g.k_per_split = st.k_per_split;
                 g.scale_a = st.scale_a;
                 g.scale_b = st.scale_b;
                 g.accumulate = st.accumulate;
                 g.mode = st.partial ? GEMM_GRAM : GEMM_ADJ;
-                const int key = st.partial ? wide_key(prec) : tensor_key(prec);
+                const int key = st.partial ? wide_key(prec) : tensor_key(prec) + kGemmVariantStride * variant;
                 gemms[key].push_back(g);
                 gwork[key].first += st.flops;
                 gwork[key].second += st.bytes;

@@ -130,16 +130,33 @@ __device__ inline double wave_max(double v) {
 // ------------------------------------------------------------------------------------------
 // Grouped gather GEMM
 // ------------------------------------------------------------------------------------------
-constexpr int kBM = 64, kBN = 64, kBK = 16, kGemmThreads = 256;
+constexpr int kBK = 16, kGemmThreads = 256;
+
+// Tile shapes (BM x BN) of the grouped GEMM; GemmVariant (tn_kernels.hpp) picks one per GEMM.
+// Four waves; square tiles put them 2 x 2, tall or wide ones 4 x 1 or 1 x 4.  Each wave owns
+// (BM / WGM) x (BN / WGN) of the tile as 16 x 16 MFMA blocks.  Skinny tiles (256 x 16, 16 x 256)
+// give the re-absorptions by a chi-column projector and the contractions over one small bond
+// whole 16-wide sides instead of a quarter of a 64-wide one, and four times the rows per
+// workgroup.
+template <int BM, int BN>
+struct TileShape {
+    static constexpr int WGM = BM == BN ? 2 : (BM > BN ? 4 : 1);
+    static constexpr int WGN = 4 / WGM;
+    static constexpr int FM = BM / WGM / 16, FN = BN / WGN / 16;   // MFMA blocks per wave
+    static constexpr int EA = BM * kBK / kGemmThreads, EB = BN * kBK / kGemmThreads;   // staged per thread
+    static_assert(FM >= 1 && FN >= 1 && EA >= 1 && EB >= 1, "tile shape");
+};
 
 // TinB: element type of B (the same as A's except for the block-Krylov passes, where a float32 or
 // bfloat16 tensor meets float64 vectors and the product is formed in float64)
-template <typename Tin, typename Tc, typename Tout, typename TinB = Tin>
+template <typename Tin, typename Tc, typename Tout, typename TinB = Tin, int BM = 64, int BN = 64>
 __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __restrict__ descs, int ndesc,
                                                              const double* __restrict__ scales,
                                                              double* __restrict__ maxparts, int64_t tile0) {
-    __shared__ Tc As[kBK][kBM + 2];
-    __shared__ Tc Bs[kBK][kBN + 2];
+    using TS = TileShape<BM, BN>;
+    constexpr int EA = TS::EA, EB = TS::EB, FM = TS::FM, FN = TS::FN;
+    __shared__ Tc As[kBK][BM + 2];
+    __shared__ Tc Bs[kBK][BN + 2];
     __shared__ double wmax[kGemmThreads / 64];
 
     const int tid = threadIdx.x;
@@ -158,30 +175,35 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     const int rem = local - split * per_split;
     const int tm = rem / d.tiles_n;
     const int tn_ = rem - tm * d.tiles_n;
-    const int m0 = tm * kBM, n0 = tn_ * kBN;
+    const int m0 = tm * BM, n0 = tn_ * BN;
     const int k_begin = split * d.k_per_split;
     const int k_end = min(K, k_begin + d.k_per_split);
 
     const Tin* __restrict__ A = (const Tin*)d.A;
     const TinB* __restrict__ B = (const TinB*)d.B;
 
-    // per-thread fixed coordinates of the 4 A and 4 B elements it stages
+    // per-thread fixed coordinates of the EA A and EB B elements it stages
     const bool a_mfast = d.va.row_unit != 0;
     const bool b_nfast = d.vb.col_unit != 0;
-    int a_m[4], a_k[4], b_k[4], b_n[4];
-    uint32_t a_off[4], b_off[4];
-    bool a_ok[4], b_ok[4];
+    int a_m[EA], a_k[EA], b_k[EB], b_n[EB];
+    uint32_t a_off[EA], b_off[EB];
+    bool a_ok[EA], b_ok[EB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < EA; ++i) {
         const int e = tid + kGemmThreads * i;
-        if (a_mfast) { a_m[i] = e & (kBM - 1); a_k[i] = e / kBM; }
-        else { a_k[i] = e & (kBK - 1); a_m[i] = e / kBK; }
-        if (b_nfast) { b_n[i] = e & (kBN - 1); b_k[i] = e / kBN; }
-        else { b_k[i] = e & (kBK - 1); b_n[i] = e / kBK; }
-        const int gm = m0 + a_m[i], gn = n0 + b_n[i];
+        if (a_mfast) { a_m[i] = e % BM; a_k[i] = e / BM; }
+        else { a_k[i] = e % kBK; a_m[i] = e / kBK; }
+        const int gm = m0 + a_m[i];
         a_ok[i] = gm < M;
-        b_ok[i] = gn < N;
         a_off[i] = a_ok[i] ? axis_offset(d.va.row, (uint32_t)gm) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+        const int e = tid + kGemmThreads * i;
+        if (b_nfast) { b_n[i] = e % BN; b_k[i] = e / BN; }
+        else { b_k[i] = e % kBK; b_n[i] = e / kBK; }
+        const int gn = n0 + b_n[i];
+        b_ok[i] = gn < N;
         b_off[i] = b_ok[i] ? axis_offset(d.vb.col, (uint32_t)gn) : 0u;
     }
 
@@ -196,26 +218,29 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
             koff_b[buf][tid - kBK] = gk < k_end ? axis_offset(d.vb.row, (uint32_t)gk) : 0u;
         }
     };
-    Tc ra[4], rb[4];
+    Tc ra[EA], rb[EB];
     auto load_chunk = [&](int buf, int kc) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < EA; ++i) {
             const int gka = kc + a_k[i];
             ra[i] = (a_ok[i] && gka < k_end) ? (Tc)A[a_off[i] + koff_a[buf][a_k[i]]] : (Tc)0;
+        }
+#pragma unroll
+        for (int i = 0; i < EB; ++i) {
             const int gkb = kc + b_k[i];
             rb[i] = (b_ok[i] && gkb < k_end) ? (Tc)B[b_off[i] + koff_b[buf][b_k[i]]] : (Tc)0;
         }
     };
 
     using acc_t = typename Mma<Tc>::acc;
-    acc_t acc[2][2];
+    acc_t acc[FM][FN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int wm = (wave % TS::WGM) * (BM / TS::WGM), wn = (wave / TS::WGM) * (BN / TS::WGN);
     const int lrow = lane & 15, lk = lane >> 4;
 
     fill_koff(0, k_begin);
@@ -224,36 +249,38 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     int buf = 0;
     for (int kc = k_begin; kc < k_end; kc += kBK) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            As[a_k[i]][a_m[i]] = ra[i];
-            Bs[b_k[i]][b_n[i]] = rb[i];
-        }
+        for (int i = 0; i < EA; ++i) As[a_k[i]][a_m[i]] = ra[i];
+#pragma unroll
+        for (int i = 0; i < EB; ++i) Bs[b_k[i]][b_n[i]] = rb[i];
         if (kc + kBK < k_end) fill_koff(buf ^ 1, kc + kBK);
         __syncthreads();
         if (kc + kBK < k_end) load_chunk(buf ^ 1, kc + kBK);
         if constexpr (Mma<Tc>::kK == 4) {
 #pragma unroll
             for (int kk = 0; kk < kBK; kk += 4) {
-                const Tc a0 = As[kk + lk][wm + lrow], a1 = As[kk + lk][wm + 16 + lrow];
-                const Tc b0 = Bs[kk + lk][wn + lrow], b1 = Bs[kk + lk][wn + 16 + lrow];
-                acc[0][0] = Mma<Tc>::run(a0, b0, acc[0][0]);
-                acc[0][1] = Mma<Tc>::run(a0, b1, acc[0][1]);
-                acc[1][0] = Mma<Tc>::run(a1, b0, acc[1][0]);
-                acc[1][1] = Mma<Tc>::run(a1, b1, acc[1][1]);
+                Tc a[FM], b[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) a[i] = As[kk + lk][wm + 16 * i + lrow];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) b[j] = Bs[kk + lk][wn + 16 * j + lrow];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = Mma<Tc>::run(a[i], b[j], acc[i][j]);
             }
         } else {   // one 16-deep instruction covers the whole K chunk
-            v4s a0, a1, b0, b1;
+            v4s a[FM], b[FN];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                a0[j] = (short)As[4 * lk + j][wm + lrow].bits;
-                a1[j] = (short)As[4 * lk + j][wm + 16 + lrow].bits;
-                b0[j] = (short)Bs[4 * lk + j][wn + lrow].bits;
-                b1[j] = (short)Bs[4 * lk + j][wn + 16 + lrow].bits;
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i) a[i][q] = (short)As[4 * lk + q][wm + 16 * i + lrow].bits;
+#pragma unroll
+                for (int j = 0; j < FN; ++j) b[j][q] = (short)Bs[4 * lk + q][wn + 16 * j + lrow].bits;
             }
-            acc[0][0] = Mma<Tc>::run(a0, b0, acc[0][0]);
-            acc[0][1] = Mma<Tc>::run(a0, b1, acc[0][1]);
-            acc[1][0] = Mma<Tc>::run(a1, b0, acc[1][0]);
-            acc[1][1] = Mma<Tc>::run(a1, b1, acc[1][1]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = Mma<Tc>::run(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
         buf ^= 1;
@@ -266,9 +293,9 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     if (d.mode == GEMM_ADJ) {
         // reverse pass: scatter into the adjoint's own layout, optionally accumulating
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gm = m0 + wm + i * 16 + Mma<Tc>::row(lane, r);
@@ -284,9 +311,9 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
     }
     const int64_t cbase = (d.mode == GEMM_GRAM) ? (int64_t)split * M * N : 0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int gm = m0 + wm + i * 16 + Mma<Tc>::row(lane, r);
@@ -305,6 +332,181 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_grouped(const GemmDesc* __r
         if (tid == 0) {
             double m = wmax[0];
             for (int w = 1; w < kGemmThreads / 64; ++w) m = fmax(m, wmax[w]);
+            maxparts[d.maxpart + local] = m;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Grouped skinny GEMM: one side of C is short (at most S = 16 or 32) and K <= kSkinnyMaxK.  These
+// are the re-absorptions A P_L and P_R B of a chi'-column projector (section II.C, SI B) and the
+// contractions over one small bond.  They move a long operand once and do 2 S K flops per element
+// of it, so they are HBM-bound: instead of padding the short side to a 64-wide MFMA tile, a
+// workgroup takes 256 indices of the long side, one per thread, keeps the small operand in LDS
+// (read as broadcasts) and accumulates all S outputs of its index in registers (float32 for
+// float32 / bfloat16 tensors, float64 for float64).  kTall: M long (each thread one row of C);
+// else N long (each thread one column).  The long operand is read along K with 16-byte vector
+// loads when K is its unit-stride axis, else one element per K with consecutive threads on
+// consecutive indices.
+// ------------------------------------------------------------------------------------------
+constexpr int kSkinnyMaxK = kSkinnyGemmMaxK, kSkinnyThreads = 256;
+
+template <typename T>
+struct Vec16;   // 16 bytes of T
+template <>
+struct Vec16<float> {
+    static constexpr int n = 4;
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+    static constexpr int n = 2;
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec16<bf16> {
+    static constexpr int n = 8;
+    typedef uint4 type;
+};
+__device__ inline double vec_elem(const Vec16<double>::type& v, int i) { return v[i]; }
+__device__ inline float vec_elem(const Vec16<float>::type& v, int i) { return v[i]; }
+__device__ inline float vec_elem(const uint4& v, int i) {   // bfloat16 i of 8, little-endian
+    const uint32_t w = i < 2 ? v.x : i < 4 ? v.y : i < 6 ? v.z : v.w;
+    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+// a stored element as the accumulation type's source: float64 stays float64, the rest float32
+__device__ inline double float_or_double(double x) { return x; }
+__device__ inline float float_or_double(float x) { return x; }
+__device__ inline float float_or_double(bf16 x) { return (float)x; }
+template <typename T>
+struct SkinnyAcc {
+    typedef float type;
+};
+template <>
+struct SkinnyAcc<double> {
+    typedef double type;
+};
+
+template <typename Tin, typename Tacc, int S, bool kTall>
+__global__ __launch_bounds__(kSkinnyThreads) void gemm_skinny_grouped(const GemmDesc* __restrict__ descs, int ndesc,
+                                                                      const double* __restrict__ scales,
+                                                                      double* __restrict__ maxparts, int64_t tile0) {
+    __shared__ Tacc small[kSkinnyMaxK][S];   // small operand, K-major, zero beyond the short side
+    __shared__ uint32_t koff[kSkinnyMaxK];   // long operand: offset of each K index
+    __shared__ double wmax[kSkinnyThreads / 64];
+    const int tid = threadIdx.x;
+    const int64_t tile = tile0 + blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_begin <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc& d = descs[lo];
+    const int M = d.M, N = d.N, K = d.K;
+    const int local = (int)(tile - d.tile_begin);
+    const int L = kTall ? M : N, SS = kTall ? N : M;   // long and short extents
+    const View& vl = kTall ? d.va : d.vb;              // long operand
+    const View& vs = kTall ? d.vb : d.va;              // small operand
+    const Axis& lax = kTall ? vl.row : vl.col;         // long operand: long axis
+    const Axis& kax = kTall ? vl.col : vl.row;         // long operand: K axis
+    const Tin* __restrict__ Xl = (const Tin*)(kTall ? d.A : d.B);
+    const Tin* __restrict__ Xs = (const Tin*)(kTall ? d.B : d.A);
+
+    for (int e = tid; e < K * S; e += kSkinnyThreads) {
+        const int k = e / S, j = e - k * S;
+        Tacc v = (Tacc)0;
+        if (j < SS) {
+            // small operand element (k, j): B[k][j] when tall, A[j][k] when wide
+            const uint32_t off = kTall ? axis_offset(vs.row, (uint32_t)k) + axis_offset(vs.col, (uint32_t)j)
+                                       : axis_offset(vs.row, (uint32_t)j) + axis_offset(vs.col, (uint32_t)k);
+            v = (Tacc)(float_or_double(Xs[off]));
+        }
+        small[k][j] = v;
+    }
+    for (int k = tid; k < K; k += kSkinnyThreads) koff[k] = axis_offset(kax, (uint32_t)k);
+    __syncthreads();
+
+    const int idx = local * kSkinnyThreads + tid;
+    const bool ok = idx < L;
+    const uint32_t base = ok ? axis_offset(lax, (uint32_t)idx) : 0u;
+    Tacc acc[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc[j] = (Tacc)0;
+
+    // 16-byte loads along K: K is one unit-stride leg, and every index's base offset is aligned
+    constexpr int V = Vec16<Tin>::n;
+    bool vec = kax.n == 1 && kax.stride[0] == 1 && K % V == 0 &&
+               ((uintptr_t)Xl & 15u) == 0;
+    for (int l = 0; l < lax.n && vec; ++l) vec = lax.stride[l] % V == 0;
+    if (ok && vec) {
+        const typename Vec16<Tin>::type* p = (const typename Vec16<Tin>::type*)(Xl + base);
+        for (int k0 = 0; k0 < K; k0 += 4 * V) {
+            typename Vec16<Tin>::type x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k0 + q * V < K) x[q] = p[(k0 >> (V == 8 ? 3 : V == 4 ? 2 : 1)) + q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (k0 + q * V >= K) break;
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                    const Tacc xv = (Tacc)vec_elem(x[q], i);
+                    const Tacc* sr = small[k0 + q * V + i];
+#pragma unroll
+                    for (int j = 0; j < S; ++j) acc[j] = fma(xv, sr[j], acc[j]);
+                }
+            }
+        }
+    } else if (ok) {
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            Tacc x[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) x[q] = k0 + q < K ? (Tacc)float_or_double(Xl[base + koff[k0 + q]]) : (Tacc)0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                if (k0 + q >= K) break;
+                const Tacc* sr = small[k0 + q];
+#pragma unroll
+                for (int j = 0; j < S; ++j) acc[j] = fma(x[q], sr[j], acc[j]);
+            }
+        }
+    }
+
+    const double factor = inv_scale(scales, d.scale_a) * inv_scale(scales, d.scale_b);
+    double local_max = 0.0;
+    if (ok) {
+        if (d.mode == GEMM_ADJ) {
+            Tin* __restrict__ C = (Tin*)d.C;
+            const uint32_t o_long = kTall ? axis_offset(d.vc.row, (uint32_t)idx) : axis_offset(d.vc.col, (uint32_t)idx);
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (j >= SS) break;
+                const uint32_t off =
+                    o_long + (kTall ? axis_offset(d.vc.col, (uint32_t)j) : axis_offset(d.vc.row, (uint32_t)j));
+                double v = (double)acc[j] * factor;
+                if (d.accumulate) v += (double)float_or_double(C[off]);
+                C[off] = (Tin)v;
+            }
+        } else {
+            Tin* __restrict__ C = (Tin*)d.C;
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                if (j >= SS) break;
+                const Tin o = (Tin)((double)acc[j] * factor);
+                if (kTall) C[(int64_t)idx * N + j] = o;
+                else C[(int64_t)j * N + idx] = o;
+                local_max = fmax(local_max, fabs((double)float_or_double(o)));
+            }
+        }
+    }
+    if (d.mode == GEMM_TENSOR) {
+        local_max = wave_max(local_max);
+        if ((tid & 63) == 0) wmax[tid >> 6] = local_max;
+        __syncthreads();
+        if (tid == 0) {
+            double m = wmax[0];
+            for (int w = 1; w < kSkinnyThreads / 64; ++w) m = fmax(m, wmax[w]);
             maxparts[d.maxpart + local] = m;
         }
     }
@@ -2579,23 +2781,69 @@ hipError_t by_prec(int prec, F&& f) {
 // workgroups (of up to 256 work-items) are issued as several launches over consecutive ranges.
 constexpr int64_t kMaxGridBlocks = (int64_t)1 << 23;
 
-hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
+// One grouped GEMM launch in tile shape `variant`.
+template <typename Tin, typename Tc, typename Tout, typename TinB = Tin>
+hipError_t gemm_variant_launch(int variant, dim3 grid, hipStream_t s, const GemmDesc* descs, int ndesc,
+                               const double* scales, double* maxparts, int64_t t0) {
+    const dim3 block(kGemmThreads);
+    switch (variant) {
+        case GV_64x64:
+            gemm_grouped<Tin, Tc, Tout, TinB, 64, 64><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_256x16:
+            gemm_grouped<Tin, Tc, Tout, TinB, 256, 16><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_16x256:
+            gemm_grouped<Tin, Tc, Tout, TinB, 16, 256><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_128x32:
+            gemm_grouped<Tin, Tc, Tout, TinB, 128, 32><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_32x128:
+            gemm_grouped<Tin, Tc, Tout, TinB, 32, 128><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_TALL16:
+            gemm_skinny_grouped<Tin, typename SkinnyAcc<Tin>::type, 16, true>
+                <<<grid, dim3(kSkinnyThreads), 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_TALL32:
+            gemm_skinny_grouped<Tin, typename SkinnyAcc<Tin>::type, 32, true>
+                <<<grid, dim3(kSkinnyThreads), 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_WIDE16:
+            gemm_skinny_grouped<Tin, typename SkinnyAcc<Tin>::type, 16, false>
+                <<<grid, dim3(kSkinnyThreads), 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        case GV_WIDE32:
+            gemm_skinny_grouped<Tin, typename SkinnyAcc<Tin>::type, 32, false>
+                <<<grid, dim3(kSkinnyThreads), 0, s>>>(descs, ndesc, scales, maxparts, t0);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(int key, const GemmDesc* descs, int ndesc, int64_t tiles, const double* scales,
                        double* maxparts, hipStream_t s) {
     if (ndesc == 0 || tiles == 0) return hipSuccess;
+    const int dtype_key = key % kGemmVariantStride, variant = key / kGemmVariantStride;
+    if (variant != GV_64x64 && dtype_key != GEMM_F64 && dtype_key != GEMM_F32 && dtype_key != GEMM_BF16)
+        return hipErrorInvalidValue;
     for (int64_t t0 = 0; t0 < tiles; t0 += kMaxGridBlocks) {
         const dim3 grid((unsigned)std::min<int64_t>(kMaxGridBlocks, tiles - t0)), block(kGemmThreads);
+        hipError_t e = hipSuccess;
         switch (dtype_key) {
             case GEMM_F64:
-                gemm_grouped<double, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                e = gemm_variant_launch<double, double, double>(variant, grid, s, descs, ndesc, scales, maxparts, t0);
                 break;
             case GEMM_F32:
-                gemm_grouped<float, float, float><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
+                e = gemm_variant_launch<float, float, float>(variant, grid, s, descs, ndesc, scales, maxparts, t0);
+                break;
+            case GEMM_BF16:
+                e = gemm_variant_launch<bf16, bf16, bf16>(variant, grid, s, descs, ndesc, scales, maxparts, t0);
                 break;
             case GEMM_F32_TO_F64:
                 gemm_grouped<float, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
-                break;
-            case GEMM_BF16:
-                gemm_grouped<bf16, bf16, bf16><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
                 break;
             case GEMM_BF16_TO_F64:
                 gemm_grouped<bf16, double, double><<<grid, block, 0, s>>>(descs, ndesc, scales, maxparts, t0);
@@ -2617,7 +2865,7 @@ hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t 
                 break;
             default: return hipErrorInvalidValue;
         }
-        const hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -14,6 +14,24 @@ enum GemmKey { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_F32_TO_F64 = 2, GEMM_BF16 = 3, G
                GEMM_GRAM_NARROW_F64 = 5, GEMM_GRAM_NARROW_F32 = 6, GEMM_GRAM_NARROW_BF16 = 7, GEMM_F32_X_F64 = 8,
                GEMM_BF16_X_F64 = 9 };
 
+// Tile shapes of the tensor GEMMs (GEMM_F64 / GEMM_F32 / GEMM_BF16, single split): a launch key is
+// GemmKey + kGemmVariantStride * variant.  The other keys take the 64 x 64 tile only.
+// GV_TALL* / GV_WIDE*: the skinny kernel (no MFMA): N (resp. M) at most 16 or 32, K at most
+// kSkinnyGemmMaxK, 256 rows (columns) of C per workgroup.
+enum GemmVariant {
+    GV_64x64 = 0, GV_256x16 = 1, GV_16x256 = 2, GV_128x32 = 3, GV_32x128 = 4,
+    GV_TALL16 = 5, GV_TALL32 = 6, GV_WIDE16 = 7, GV_WIDE32 = 8, GV_COUNT = 9
+};
+constexpr int kGemmVariantStride = 16;
+constexpr int kSkinnyGemmMaxK = 64;
+inline void gemm_tile(int variant, int* bm, int* bn) {
+    static const int dims[GV_COUNT][2] = {{64, 64}, {256, 16}, {16, 256}, {128, 32}, {32, 128},
+                                          {256, 16}, {256, 32}, {16, 256}, {32, 256}};
+    *bm = dims[variant][0];
+    *bn = dims[variant][1];
+}
+// The variant of a tensor GEMM comes from the tile table (tn_tune.hpp).
+
 constexpr int kCoreLdsMaxD = 64;
 constexpr int kLanczosMaxSteps = 512;     // cap on Krylov steps per compression
 constexpr int kLanczosLdsBytes = 150 * 1024;   // dynamic LDS for the small SVD (static use is ~4.3 KB)

@@ -197,3 +197,51 @@ def test_describe_rejects_invalid_graphs():
         tn.tn_plan_describe(3, [1], [0], [2], [0, 3], [1, 2], 4)        # u > v
     with pytest.raises(tn.TNError):
         tn.tn_plan_describe(3, [0], [1], [0], [0, 3], [1, 2], 4)        # dimension 0
+
+
+def _tile_allowed(klass, tile):
+    """The tiles include/tn.h allows for a class (short side, orientation, K)."""
+    k = (klass // 2) % 3
+    short32 = (klass // 6) % 2
+    wide = (klass // 12) % 2
+    skinny_k = k <= 1
+    if tile == 0:
+        return True
+    tall_tiles = {1: not short32, 3: True, 5: not short32 and skinny_k, 6: skinny_k}
+    wide_tiles = {2: not short32, 4: True, 7: not short32 and skinny_k, 8: skinny_k}
+    return (wide_tiles if wide else tall_tiles).get(tile, False)
+
+
+def test_gemm_tile_table_host_side():
+    from paper_2206_07044_amd import autotune
+    default = tn.tn_gemm_tiles_get().copy()
+    try:
+        assert default.size == tn.GEMM_CLASSES == 72
+        assert all(_tile_allowed(c, int(t)) for c, t in enumerate(default))
+        # class index round trip and the documented formula
+        assert autotune.class_of(1, True, False, 1, True) == ((((1 * 2 + 1) * 2 + 0) * 3 + 1) * 2) + 1
+        assert autotune.describe(autotune.class_of(0, False, True, 2, False)) == \
+            "fp64 tall short<=32 K>64 long-axis strided"
+        # every allowed tile installs; a disallowed one is refused and leaves the table as it was
+        everywhere_64 = np.zeros(72, dtype=np.int32)
+        tn.tn_gemm_tiles_set(everywhere_64)
+        assert np.array_equal(tn.tn_gemm_tiles_get(), everywhere_64)
+        for c in range(72):
+            for tile in range(len(tn.GEMM_TILES)):
+                t = everywhere_64.copy()
+                t[c] = tile
+                if _tile_allowed(c, tile):
+                    tn.tn_gemm_tiles_set(t)
+                    assert tn.tn_gemm_tiles_get()[c] == tile
+                else:
+                    before = tn.tn_gemm_tiles_get().copy()
+                    with pytest.raises(tn.TNError) as e:
+                        tn.tn_gemm_tiles_set(t)
+                    assert e.value.status == tn.TN_EINVAL
+                    assert np.array_equal(tn.tn_gemm_tiles_get(), before)
+        with pytest.raises(ValueError):
+            tn.tn_gemm_tiles_set(np.zeros(71, dtype=np.int32))
+        tn.tn_gemm_tiles_set(None)
+        assert np.array_equal(tn.tn_gemm_tiles_get(), default)
+    finally:
+        tn.tn_gemm_tiles_set(None)
