@@ -2540,6 +2540,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         __syncthreads();
     }
     int s = 0, restarts = 0, nev = 0;
+    int s_prev = 0;   // size of the last tridiagonal solve (its eigenvectors are in Vs)
     bool exhausted = false, converged = false;
     double bmax = 0.0;
     int target = d.s_min;
@@ -2586,31 +2587,46 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
             }
         }
         // eigenpairs of the s x s tridiagonal T (symmetric positive semidefinite: its
-        // one-sided Jacobi SVD gives eigenvalues as column norms and eigenvectors in Vs)
+        // one-sided Jacobi SVD gives eigenvalues as column norms and eigenvectors in Vs).
+        // Warm start: T's leading s_prev x s_prev block is the previous check's T, whose
+        // eigenvectors the previous solve left in Vs; V starts as those, extended by the
+        // identity, and W = T V.  The rotations then only resolve the coupling to the new
+        // steps, in a few sweeps instead of a full solve.
+        // (a solve in LDS copied its V to Wg, since the next Lanczos vectors reuse that room; one
+        // in the workspace left it in Vg, at the same stride as the next)
+        const double* vp = s_prev <= kTriLdsS ? Wg : Vg;
+        const int lwp = s_prev <= kTriLdsS ? s_prev : ls;
         if (s <= kTriLdsS) {
             W = lds;
             Vs = lds + (int64_t)s * s;
             lw = s;
         } else {
-            W = Wg;
+            W = Wg;   // written only after V has been read from Wg (barrier between)
             Vs = Vg;
             lw = ls;
         }
         for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
             const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
-            double v = 0.0;
-            if (r == c) v = alpha[c];
-            else if (r + 1 == c) v = beta[r];
-            else if (c + 1 == r) v = beta[c];
-            W[(int64_t)c * lw + r] = v;
-            Vs[(int64_t)c * lw + r] = (r == c) ? 1.0 : 0.0;
+            Vs[(int64_t)c * lw + r] = (c < s_prev && r < s_prev) ? vp[(int64_t)c * lwp + r] : (r == c ? 1.0 : 0.0);
         }
         __syncthreads();
+        for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
+            const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
+            const double* vc = Vs + (int64_t)c * lw;
+            double v = alpha[r] * vc[r];
+            if (r > 0) v += beta[r - 1] * vc[r - 1];
+            if (r + 1 < s) v += beta[r] * vc[r + 1];
+            W[(int64_t)c * lw + r] = v;
+        }
+        __syncthreads();
+        s_prev = s;
         int sw = 0;
         const bool jc = s <= 32 ? jacobi_svd_small<kCoreThreads, 2>(W, Vs, s, s, lw, max_sweeps, sh, &sw)
                       : s <= 64 ? jacobi_svd_small(W, Vs, s, s, lw, max_sweeps, sh, &sw)
                                 : jacobi_svd(W, Vs, s, s, lw, max_sweeps, sh, &sw);
         sorted_norms(W, s, s, lw, sig, order);
+        if (s <= kTriLdsS)   // keep V for the next check's warm start (read after the barrier below)
+            for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) Wg[idx] = Vs[idx];
         nev = s;
         const double lmax = s > 0 ? sig[order[0]] : 0.0;
         const double bl = (exhausted || s == 0) ? 0.0 : beta[s - 1];
