@@ -2539,6 +2539,13 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         for (int i = tid; i < n; i += kCoreThreads) q0[i] /= nrm;
         __syncthreads();
     }
+    // ||S||_F^2 = the sum of the squared eigenvalues of S (the completeness test below)
+    double fro2 = 0.0;
+    {
+        double part = 0.0;
+        for (int64_t idx = tid; idx < (int64_t)n * n; idx += kCoreThreads) part += S[idx] * S[idx];
+        fro2 = block_sum(part, sh);
+    }
     int s = 0, restarts = 0, nev = 0;
     int s_prev = 0;   // size of the last tridiagonal solve (its eigenvectors are in Vs)
     bool exhausted = false, converged = false;
@@ -2637,6 +2644,37 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
             if (!(lv > kNoiseRelSq * lmax)) continue;
             // residual of the Ritz pair: beta_s |last entry of its eigenvector|
             if (bl * fabs(Vs[(int64_t)c * lw + (s - 1)]) > 1e-13 * lmax) ok = false;
+        }
+        if (ok && !exhausted && s < sm) {
+            // Completeness.  A Krylov space from one start vector holds one direction of each
+            // eigenspace, so converged Ritz pairs can miss further copies of a repeated kept
+            // eigenvalue.  The eigenvalues of S other than the kept Ritz values are those of S on
+            // the complement of the kept Ritz vectors W (an invariant subspace up to their
+            // residuals).  In the basis (the other Ritz vectors Y, then the complement of Q) that
+            // operator is [[diag(theta_Y), b], [b^T, O]] with b of rank one, |b| = beta_s |last
+            // entries of Y| (S Q = Q T + beta_s q_s e^T), and O positive semidefinite with
+            // |O|_F^2 = |S|_F^2 - |T|_F^2 - 2 beta_s^2.  Its largest eigenvalue is therefore at most
+            // that of [[a, |b|], [|b|, |O|_F]] (a = the largest other Ritz value).  When that bound
+            // is below the smallest kept value, nothing can join the kept set; else the iteration
+            // goes on (to exhaustion at worst, where T holds every eigenvalue).  Kept values at the
+            // rounding floor of |O|_F^2 (lambda^2 <= 1e-13 |S|_F^2) pass unchecked.
+            int keff = 0;
+            double lcut = 0.0, kept_last2 = 0.0;
+            for (int t = 0; t < min(cn, s); ++t) {
+                const int c = order[t];
+                if (!(sig[c] > kNoiseRelSq * lmax)) break;
+                lcut = sig[c];
+                const double v = Vs[(int64_t)c * lw + (s - 1)];
+                kept_last2 += v * v;
+                ++keff;
+            }
+            double t2 = 0.0;
+            for (int j = 0; j < s; ++j) t2 += alpha[j] * alpha[j] + (j + 1 < s ? 2.0 * beta[j] * beta[j] : 0.0);
+            const double a = keff < s ? fmax(sig[order[keff]], 0.0) : 0.0;
+            const double od = sqrt(fmax(fro2 - t2 - 2.0 * bl * bl, 0.0));
+            const double bb = bl * sqrt(fmax(1.0 - kept_last2, 0.0));
+            const double bound = 0.5 * (a + od) + sqrt(0.25 * (a - od) * (a - od) + bb * bb);
+            if (keff > 0 && !(bound < lcut || lcut * lcut <= 1e-13 * fro2)) ok = false;
         }
         if (ok || exhausted || s >= sm) {
             converged = ok || exhausted;

@@ -786,7 +786,9 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         // first convergence check after chi' + 16 steps: a step is one matvec with the
                         // precomputed operator, far cheaper than the tridiagonal eigensolve of a check
                         c.s_min = (int32_t)std::min<int64_t>(n, nw + 16);
-                        c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(n, 8 * nw + 64), 512);
+                        // up to n steps: the completeness test of the kernel may run the Krylov space
+                        // to exhaustion (repeated kept eigenvalues with a heavy discarded tail)
+                        c.s_max = (int32_t)std::min<int64_t>(n, 512);
                         const int64_t sm = c.s_max, ls = sm + 1;
                         // T1 = G_Y F_X^T (D x n) when Y has a Gram, else F_X F_Y^T (n x my, my <= D)
                         const int64_t t1 = (my > D ? D : my) * n;
