@@ -516,6 +516,8 @@ tn_status build_launches(tn_ctx* c) {
                 ld.scale_b = st.in_b;
                 ld.stat = st.comp;
                 ld.kmin = (int32_t)std::min(std::min(cp.ma, cp.D), std::min(cp.mb, cp.D));
+                ld.gram_a = (const double*)buf_ptr(cp.side_a_buf);
+                ld.gram_b = (const double*)buf_ptr(cp.side_b_buf);
                 lanczos_smax = std::max(lanczos_smax, cp.s_max);
                 lanczos.push_back(ld);
                 lanczos_work.first += st.flops;

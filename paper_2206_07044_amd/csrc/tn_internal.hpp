@@ -170,6 +170,8 @@ struct LanczosDesc {
     int32_t stat, kmin;
     View va;                     // A_mat: rows = free legs of a, cols = shared legs
     View vb;                     // B_mat: rows = shared legs, cols = free legs of b
+    const double* gram_a;        // A_mat^T A_mat / s_a^2 (D x D), for ||A B||_F^2 = <G_A, G_B>
+    const double* gram_b;        // B_mat B_mat^T / s_b^2 (D x D)
 };
 
 // Large-core compression with an explicit side X: symmetric Lanczos on F_X G_Y F_X^T.

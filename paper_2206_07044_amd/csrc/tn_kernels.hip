@@ -2175,6 +2175,13 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
         __syncthreads();
     }
 
+    // ||A B||_F^2 = <G_A, G_B> (both Grams carry the scales' 1/s^2), for the completeness test
+    double fro2 = 0.0;
+    {
+        double part = 0.0;
+        for (int64_t idx = tid; idx < (int64_t)D * D; idx += kCoreThreads) part += d.gram_a[idx] * d.gram_b[idx];
+        fro2 = block_sum(part, sh);
+    }
     int s = 0, restarts = 0, extra_col = 0;
     bool exhausted = false, converged = false;
     double amax = 0.0;
@@ -2279,6 +2286,33 @@ __global__ __launch_bounds__(kCoreThreads) void lanczos_kernel(const LanczosDesc
             if (!(sv > kNoiseRel * smax_v)) continue;
             const double res = bl * fabs(W[(int64_t)c * lw + (s - 1)]) / sv;
             if (res > 1e-13 * smax_v) ok = false;
+        }
+        if (ok && !exhausted && s < smax_steps) {
+            // Completeness (see gram_lanczos_kernel): with M V_s = U_s B_s and
+            // U_s^T M = B_s V_s^T + beta_s e_s v_{s+1}^T, M on the complement of the kept triplets
+            // is [[diag(sigma_Y), c], [0, O]] with c of rank one, |c| = beta_s |last entries of
+            // the other left vectors of B_s|, and |O|_F^2 = ||A B||_F^2 - |B_s|_F^2 - beta_s^2;
+            // its largest singular value is at most that of [[a, |c|], [0, |O|_F]].  Below the
+            // smallest kept value, nothing can join the kept set; else the iteration goes on.
+            int keff = 0;
+            double scut = 0.0, kept_last2 = 0.0;
+            for (int t = 0; t < min(cn, ncol); ++t) {
+                const int c = order[t];
+                const double sv = sig[c];
+                if (!(sv > kNoiseRel * smax_v)) break;
+                scut = sv;
+                const double u = W[(int64_t)c * lw + (s - 1)] / sv;   // left vector's last entry
+                kept_last2 += u * u;
+                ++keff;
+            }
+            double b2 = 0.0;
+            for (int j = 0; j < s; ++j) b2 += alpha[j] * alpha[j] + (j + 1 < s ? beta[j] * beta[j] : 0.0);
+            const double a = keff < ncol ? fmax(sig[order[keff]], 0.0) : 0.0;
+            const double o2 = fmax(fro2 - b2 - bl * bl, 0.0);
+            const double c2 = bl * bl * fmax(1.0 - kept_last2, 0.0);
+            const double h = 0.5 * (a * a + c2 + o2);
+            const double bound = sqrt(h + sqrt(fmax(h * h - a * a * o2, 0.0)));
+            if (keff > 0 && !(bound < scut || scut * scut <= 1e-13 * fro2)) ok = false;
         }
         if (ok || exhausted || s >= smax_steps) {
             converged = ok || exhausted;

@@ -632,15 +632,57 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 c.glanczos = glanczos ? 1 : 0;
                 Step core;
                 if (lanczos) {
-                    // one step: Golub-Kahan-Lanczos truncated SVD of A_mat B_mat read through Views
+                    // one step: Golub-Kahan-Lanczos truncated SVD of A_mat B_mat read through Views.
+                    // The Grams of both sides (float64, D x D) give ||A B||_F^2 = <G_A, G_B> for the
+                    // kernel's completeness test; they are not part of the credited work (the QR
+                    // terms of both sides are credited with the compression below)
+                    int32_t gram_level = 0;
+                    for (int side = 0; side < 2; ++side) {
+                        const TensorVer& T = side == 0 ? Ta : Tb;
+                        const int32_t ver = side == 0 ? va : vb;
+                        const std::vector<int32_t>& fr = side == 0 ? free_a : free_b;
+                        const int64_t mm = side == 0 ? ma : mb;
+                        Step st;
+                        st.kind = ST_GRAM;
+                        st.level = T.level + 1;
+                        st.comp = comp_id;
+                        st.in_a = ver;
+                        st.M = D;
+                        st.N = D;
+                        st.K = mm;
+                        st.va = tensor_view(T, shared, fr, E);
+                        st.vb = tensor_view(T, fr, shared, E);
+                        const int64_t tiles = ((D + 63) / 64) * ((D + 63) / 64);
+                        int64_t splits = (mm + 255) / 256;
+                        splits = std::min<int64_t>(splits, std::max<int64_t>(1, 1024 / tiles));
+                        splits = std::min<int64_t>(splits, std::max<int64_t>(1, (32 << 20) / (D * D * 8)));
+                        splits = std::max<int64_t>(1, splits);
+                        int64_t kps = (mm + splits - 1) / splits;
+                        kps = (kps + kGemmK - 1) / kGemmK * kGemmK;
+                        splits = (mm + kps - 1) / kps;
+                        st.splits = (int32_t)splits;
+                        st.k_per_split = (int32_t)kps;
+                        st.out_buf = new_buf(splits * D * D * 8, BUF_GRAM, st.level);
+                        st.flops = 0.0;
+                        st.bytes = (double)w * mm * D;
+                        (side == 0 ? c.gram_a : c.gram_b) = 1;
+                        (side == 0 ? c.splits_a : c.splits_b) = (int32_t)splits;
+                        (side == 0 ? c.side_a_buf : c.side_b_buf) = st.out_buf;
+                        read_tensor(ver, st.level);
+                        gram_level = std::max(gram_level, st.level);
+                        P->steps.push_back(st);
+                    }
                     const int64_t r = std::min(std::min(ma, mb), D);
                     c.s_min = (int32_t)std::min<int64_t>(r, 2 * nw + 4);
                     // r + 1: the start vector's component outside the row space of A B adds one
-                    // Krylov direction before the range is exhausted
-                    c.s_max = (int32_t)std::min<int64_t>(std::min<int64_t>(r + 1, 8 * nw + 64), 512);
+                    // Krylov direction before the range is exhausted; the completeness test may run
+                    // the space that far
+                    c.s_max = (int32_t)std::min<int64_t>(r + 1, 512);
                     c.s_min = std::min(c.s_min, c.s_max);
                     core.kind = ST_LANCZOS;
-                    core.level = 1 + std::max(Ta.level, Tb.level);
+                    core.level = 1 + gram_level;
+                    touch(c.side_a_buf, core.level + 1);
+                    touch(c.side_b_buf, core.level + 1);
                     core.comp = comp_id;
                     core.in_a = va;
                     core.in_b = vb;
