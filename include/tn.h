@@ -113,7 +113,18 @@ typedef struct {
                                     of work per tn_grad.  -1: the S in
                                     {1,2,3,4,6,8,12,16,24,32} of smallest arena.  tn_batch_grad does
                                     not take contexts planned with S >= 2 (tn_grad per context) */
+    int32_t r_factor;            /* tn_r_factor: how the R-factors of a bond's tall sides (more rows
+                                    than D) are formed when D <= 64.  TN_RFACTOR_GRAM (0): float64
+                                    Gram on MFMA + pivoted Cholesky (pivots below 1e-15 of the first
+                                    dropped, i.e. directions under ~3e-8 of the largest).
+                                    TN_RFACTOR_TSQR (1): batched Householder TSQR in float64 (row
+                                    blocks of 16384 / D rows in LDS, then passes over the stacked
+                                    R's), R^T R = the Gram without forming it.  Larger D take the
+                                    Gram / Krylov routes either way.  TSQR: grad must be 0; not
+                                    accepted by tn_batch_create */
 } tn_tree_opts;
+
+typedef enum { TN_RFACTOR_GRAM = 0, TN_RFACTOR_TSQR = 1 } tn_r_factor;
 
 typedef struct tn_ctx tn_ctx;
 

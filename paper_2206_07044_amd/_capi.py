@@ -18,6 +18,7 @@ TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO = range
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ESTATE", 3: "TN_ENOMEM", 4: "TN_EDEVICE",
                 5: "TN_ENUMERIC", 6: "TN_ZERO"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+R_FACTORS = {"gram": 0, "tsqr": 1}
 KERNEL_KINDS = {"gemm": 0, "gram": 1, "copy": 2, "core_lds": 3, "core_global": 4, "scale": 5, "lanczos": 6,
                 "bwd_gemm": 7, "bwd_core": 8, "recompute": 9}
 
@@ -33,7 +34,7 @@ class tn_tree_opts(C.Structure):
     _fields_ = [("chi", C.c_int32), ("cutoff", C.c_double), ("compress_late", C.c_int32),
                 ("gauge_r", C.c_int32), ("precision", C.c_int32), ("jacobi_max_sweeps", C.c_int32),
                 ("device_budget_bytes", C.c_int64), ("keep_intermediates", C.c_int32), ("grad", C.c_int32),
-                ("plain", C.c_int32), ("checkpoint_segments", C.c_int32)]
+                ("plain", C.c_int32), ("checkpoint_segments", C.c_int32), ("r_factor", C.c_int32)]
 
 
 _lib = None
@@ -130,12 +131,14 @@ def _ptr(a: np.ndarray, ct):
 
 def make_opts(chi: int, precision: str = "fp64", cutoff: float = 0.0, max_sweeps: int = 0,
               budget: int = 0, keep: bool = False, grad: bool = False, plain: bool = False,
-              late: bool = False, gauge_r: int = 0, segments: int = 0) -> tn_tree_opts:
+              late: bool = False, gauge_r: int = 0, segments: int = 0, r_factor: str = "gram") -> tn_tree_opts:
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    if r_factor not in R_FACTORS:
+        raise ValueError(f"r_factor must be one of {sorted(R_FACTORS)}")
     return tn_tree_opts(int(chi), float(cutoff), int(bool(late)), int(gauge_r), PRECISIONS[precision],
                         int(max_sweeps), int(budget), int(bool(keep)), int(bool(grad)), int(bool(plain)),
-                        int(segments))
+                        int(segments), R_FACTORS[r_factor])
 
 
 def tn_plan_describe(n: int, edge_u, edge_v, edge_dim, pair_i, pair_j, chi: int,
@@ -251,12 +254,13 @@ class Context:
     def tn_set_tree(self, pair_i, pair_j, chi: int, precision: str = "fp64", cutoff: float = 0.0,
                     max_sweeps: int = 0, budget: int = 0, keep_intermediates: bool = False,
                     grad: bool = False, plain: bool = False, late: bool = False, gauge_r: int = 0,
-                    checkpoint_segments: int = 0) -> None:
+                    checkpoint_segments: int = 0, r_factor: str = "gram") -> None:
         """checkpoint_segments (grad only): 0/1 keep every forward buffer the reverse pass reads;
-        S >= 2 recompute forward segments in the reverse pass; -1 the S of smallest arena."""
+        S >= 2 recompute forward segments in the reverse pass; -1 the S of smallest arena.
+        r_factor: "gram" (Gram + pivoted Cholesky) or "tsqr" (Householder TSQR) for D <= 64."""
         pi, pj = _i32(pair_i), _i32(pair_j)
         opts = make_opts(chi, precision, cutoff, max_sweeps, budget, keep_intermediates, grad, plain, late,
-                         gauge_r, checkpoint_segments)
+                         gauge_r, checkpoint_segments, r_factor)
         self.state_id += 1
         self._check(self._lib.tn_set_tree(self._h, pi.size, _ptr(pi, C.c_int32), _ptr(pj, C.c_int32),
                                           C.byref(opts)))

@@ -23,7 +23,8 @@ namespace {
 
 // L_SPRE: the float64 products that form a Gram-Lanczos operator (key 0: T1, key 1: S = F_X T1)
 // L_KRYLOV: the block-Krylov chains of a level (begin/count index the chain steps, KOp)
-enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD, L_SPRE, L_KRYLOV };
+enum LaunchKind { L_GEMM = 0, L_COPY, L_CORE, L_SCALE, L_LANCZOS, L_GLANCZOS, L_REDUCE, L_CORE_BWD, L_SPRE, L_KRYLOV,
+                  L_TSQR };
 
 struct Launch {
     int kind = 0;
@@ -96,6 +97,8 @@ struct tn_ctx {
     std::vector<CholInvDesc> h_chol;
     CholInvDesc* d_chol = nullptr;
     std::vector<KrylovCheckDesc> h_kcheck;
+    std::vector<TsqrDesc> h_tsqr;   // TSQR passes (r_factor = 1)
+    TsqrDesc* d_tsqr = nullptr;
     KrylovCheckDesc* d_kcheck = nullptr;
     std::vector<Launch> launches;
     int64_t n_kernels = 0;            // kernel launches of one forward evaluation
@@ -206,6 +209,8 @@ void free_plan(tn_ctx* c) {
     dfree(c->d_chol);
     dfree(c->d_kcheck);
     c->h_kcheck.clear();
+    dfree(c->d_tsqr);
+    c->h_tsqr.clear();
     c->h_kops.clear();
     c->h_small.clear();
     c->h_chol.clear();
@@ -287,6 +292,8 @@ tn_status build_launches(tn_ctx* c) {
         std::vector<ScaleDesc> scales;
         std::vector<ReduceDesc> sums;
         std::vector<GemmDesc> spre[2];
+        std::vector<std::vector<TsqrDesc>> tsqr_pass;   // per pass, over the level's TSQR steps
+        std::pair<double, double> tsqr_work{0, 0};
         int64_t parts = 0;
         if (L < P.n_levels) {
             // Gram-Lanczos cores of the next level: their operator S = F_X G_Y F_X^T (or C1 C1^T,
@@ -522,6 +529,38 @@ tn_status build_launches(tn_ctx* c) {
                 lanczos.push_back(ld);
                 lanczos_work.first += st.flops;
                 lanczos_work.second += st.bytes;
+            } else if (st.kind == ST_TSQR) {
+                int64_t rows = st.K;
+                for (size_t p = 0; p < st.tsqr_bufs.size(); ++p) {
+                    TsqrDesc td;
+                    std::memset(&td, 0, sizeof(td));
+                    std::string err;
+                    if (p == 0) {
+                        err = fill_view(st.va, &td.v);
+                        td.src = ten_ptr(st.in_a);
+                        td.scale = st.in_a;
+                    } else {
+                        // the previous pass's stacked R's: (nb D) x D, row-major
+                        ViewSpec vs;
+                        vs.row_dims = {(int32_t)rows};
+                        vs.row_strides = {st.M};
+                        vs.col_dims = {(int32_t)st.M};
+                        vs.col_strides = {1};
+                        err = make_view(vs, &td.v);
+                        td.src = buf_ptr(st.tsqr_bufs[p - 1]);
+                        td.scale = -1;
+                    }
+                    if (!err.empty()) return fail(c, TN_EINVAL, err);
+                    td.dst = (double*)buf_ptr(st.tsqr_bufs[p]);
+                    td.rows = (int32_t)rows;
+                    td.D = (int32_t)st.M;
+                    td.nblk = st.tsqr_blocks[p];
+                    if (tsqr_pass.size() <= p) tsqr_pass.resize(p + 1);
+                    tsqr_pass[p].push_back(td);
+                    rows = (int64_t)st.tsqr_blocks[p] * st.M;
+                }
+                tsqr_work.first += st.flops;
+                tsqr_work.second += st.bytes;
             } else if (st.kind == ST_KRYLOV) {
                 krylov_steps.push_back(si);
                 krylov_work.first += st.flops;
@@ -616,6 +655,28 @@ tn_status build_launches(tn_ctx* c) {
                 c->h_reduce.push_back(r);
             }
             l.work = elems;
+            c->launches.push_back(l);
+        }
+        for (size_t p = 0; p < tsqr_pass.size(); ++p) {
+            // passes in order on one stream (the Gram lane); the first reads the tensors
+            Launch l;
+            l.level = L;
+            l.kind = L_TSQR;
+            l.key = p == 0 ? prec : 0;
+            l.prof = TN_KERNEL_GRAM;
+            if (p == 0) {
+                l.flops = tsqr_work.first;
+                l.bytes = tsqr_work.second;
+            }
+            l.begin = (int64_t)c->h_tsqr.size();
+            l.count = (int)tsqr_pass[p].size();
+            int64_t blocks = 0;
+            for (auto& td : tsqr_pass[p]) {
+                td.blk_begin = blocks;
+                blocks += td.nblk;
+                c->h_tsqr.push_back(td);
+            }
+            l.work = blocks;
             c->launches.push_back(l);
         }
         if (!copies.empty()) {
@@ -796,6 +857,12 @@ tn_status build_launches(tn_ctx* c) {
                     }
                     case L_CORE: x.max_d = c->h_core[x.begin].D; break;
                     case L_LANCZOS: x.max_d = c->h_lanczos[x.begin].s_max; break;
+                    case L_TSQR: {
+                        TsqrDesc& td = c->h_tsqr[x.begin];
+                        td.blk_begin = 0;
+                        x.work = td.nblk;
+                        break;
+                    }
                     default: break;
                 }
                 split.push_back(x);
@@ -824,6 +891,7 @@ tn_status build_launches(tn_ctx* c) {
     if ((s = upload(c, &c->d_small, c->h_small)) != TN_OK) return s;
     if ((s = upload(c, &c->d_chol, c->h_chol)) != TN_OK) return s;
     if ((s = upload(c, &c->d_kcheck, c->h_kcheck)) != TN_OK) return s;
+    if ((s = upload(c, &c->d_tsqr, c->h_tsqr)) != TN_OK) return s;
     HIP_TRY(c, hipMalloc((void**)&c->d_scales, std::max<size_t>(1, P.tens.size()) * sizeof(double)));
     HIP_TRY(c, hipMalloc((void**)&c->d_maxparts, (size_t)max_parts * sizeof(double)));
     const size_t nc = std::max<size_t>(1, P.comps.size());
@@ -1304,6 +1372,10 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     if (opts->gauge_r > 0 && opts->grad) return fail(c, TN_EINVAL, "gauge_r >= 1 has no reverse pass (grad must be 0)");
     if (opts->compress_late != 0 && opts->compress_late != 1) return fail(c, TN_EINVAL, "compress_late must be 0 or 1");
     if (opts->checkpoint_segments < -1) return fail(c, TN_EINVAL, "checkpoint_segments must be >= -1");
+    if (opts->r_factor != TN_RFACTOR_GRAM && opts->r_factor != TN_RFACTOR_TSQR)
+        return fail(c, TN_EINVAL, "r_factor must be TN_RFACTOR_GRAM or TN_RFACTOR_TSQR");
+    if (opts->r_factor == TN_RFACTOR_TSQR && opts->grad)
+        return fail(c, TN_EINVAL, "r_factor TN_RFACTOR_TSQR has no reverse pass (grad must be 0)");
     if ((opts->checkpoint_segments > 1 || opts->checkpoint_segments == -1) && !opts->grad)
         return fail(c, TN_EINVAL, "checkpoint_segments is a reverse-pass option (grad must be 1)");
     if (opts->precision != TN_FP64 && opts->precision != TN_FP32 && opts->precision != TN_BF16)
@@ -1323,6 +1395,7 @@ tn_status tn_set_tree(tn_ctx* c, int32_t n_steps, const int32_t* pair_i, const i
     o.late = opts->compress_late;
     o.gauge_r = opts->gauge_r;
     o.segments = opts->checkpoint_segments;
+    o.rfactor = opts->r_factor;
     if (o.plain && o.grad) return fail(c, TN_EINVAL, "the plain form has no reverse pass (grad must be 0)");
     std::string err = build_plan(c->g, pair_i, pair_j, n_steps, o, false, &c->plan);
     // level by level every independent branch advances at once; when that holds more than the
@@ -1478,6 +1551,7 @@ static hipError_t run_forward_launch(tn_ctx* c, const Launch& l, hipStream_t st)
         case L_SCALE: return launch_scale_finalize(c->d_scale + l.begin, l.count, c->d_maxparts, c->d_scales, st);
         case L_REDUCE: return launch_reduce(l.key, c->d_reduce + l.begin, l.count, l.work, c->d_scales, st);
         case L_SPRE: return launch_gemm(GEMM_F64, c->d_gemm + l.begin, l.count, l.work, c->d_scales, c->d_maxparts, st);
+        case L_TSQR: return launch_tsqr(l.key, c->d_tsqr + l.begin, l.count, l.work, c->d_scales, st);
         case L_KRYLOV: {
             hipError_t err = hipSuccess;
             for (int64_t i = l.begin; i < l.begin + l.count && err == hipSuccess; ++i) {
@@ -2323,6 +2397,8 @@ tn_status tn_batch_create(int32_t n, tn_ctx* const* ctxs, tn_batch** out) {
             return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context planned in the plain form");
         if (!ctxs[i]->h_kops.empty())
             return fail(ctxs[i], TN_EINVAL, "tn_batch_create: block-Krylov compressions are not merged into batches");
+        if (!ctxs[i]->h_tsqr.empty())
+            return fail(ctxs[i], TN_EINVAL, "tn_batch_create: TSQR R-factors are not merged into batches");
         for (int j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(ctxs[i], TN_EINVAL, "tn_batch_create: a context appears twice");
         grad = grad && ctxs[i]->plan.opts.grad && ctxs[i]->plan.n_segments <= 1;

@@ -156,6 +156,21 @@ struct CoreDesc {
     int32_t pad;
 };
 
+// One pass of a tall-skinny QR (TSQR) of a (rows x D) matrix read through a View: blocks of
+// tsqr_block_rows(D) rows, each block's R (Householder, float64) written to dst as a D x D
+// row-major matrix (upper triangular; rows beyond the block's own count are zero).  The next
+// pass takes the stacked R's as its input, until one block remains.
+struct TsqrDesc {
+    const void* src;             // pass 0: the tensor (its dtype); later passes: float64
+    double* dst;                 // nblk x D x D
+    int64_t blk_begin;           // first block of this op in the grouped launch
+    int32_t rows, D, nblk;
+    int32_t scale;               // tensor-scale index applied as 1/s on load (-1: none)
+    View v;                      // rows x D
+};
+constexpr int kTsqrElems = 16384;   // float64 entries of one block in LDS (128 KiB)
+TN_HD inline int tsqr_block_rows(int D) { return kTsqrElems / (D > 0 ? D : 1); }
+
 // Large-core compression by Golub-Kahan-Lanczos on M = (A/s_a)(B/s_b) read through Views.
 struct LanczosDesc {
     const void* A;               // tensor a

@@ -513,6 +513,94 @@ __global__ __launch_bounds__(kSkinnyThreads) void gemm_skinny_grouped(const Gemm
 }
 
 // ------------------------------------------------------------------------------------------
+// Batched tall-skinny QR (TSQR) for the R-factors of section II.C, Eq. (svd): the rows of a
+// matricised side are cut into blocks held in LDS (float64, column-major); a workgroup reduces
+// its block to R by Householder reflections (one column per step: the column norm, the
+// reflector's products with the columns to its right, their update), and the stacked R's of a
+// pass are the next pass's rows.  R^T R = X^T X / s^2 without forming the Gram, so directions
+// far below the largest (which the Gram route drops under 1e-15 of the first pivot) survive.
+// ------------------------------------------------------------------------------------------
+constexpr int kTsqrThreads = 256;
+
+__device__ inline double tsqr_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTsqrThreads) void tsqr_blocks(const TsqrDesc* __restrict__ descs, int ndesc,
+                                                             const double* __restrict__ scales, int64_t blk0) {
+    extern __shared__ double X[];                 // block, column-major, leading dimension br
+    __shared__ double wcol[kCoreLdsMaxD];         // v^T x_c for the columns right of the step
+    __shared__ double red[kTsqrThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t blk = blk0 + blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].blk_begin <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    const TsqrDesc& d = descs[lo];
+    const int D = d.D, br = tsqr_block_rows(D);
+    const int b = (int)(blk - d.blk_begin);
+    const int r0 = b * br, nr = min(br, d.rows - r0);
+    const double f = inv_scale(scales, d.scale);
+    const T* __restrict__ src = (const T*)d.src;
+    const bool rows_fast = d.v.row_unit != 0;
+    for (int idx = tid; idx < nr * D; idx += kTsqrThreads) {
+        int i, c;
+        if (rows_fast) {
+            i = idx % nr;
+            c = idx / nr;
+        } else {
+            c = idx % D;
+            i = idx / D;
+        }
+        X[c * br + i] = (double)src[axis_offset(d.v.row, (uint32_t)(r0 + i)) + axis_offset(d.v.col, (uint32_t)c)] * f;
+    }
+    __syncthreads();
+    const int kmax = min(nr, D);
+    for (int j = 0; j < kmax; ++j) {
+        double* xj = X + j * br;
+        double part = 0.0;
+        for (int i = j + tid; i < nr; i += kTsqrThreads) part += xj[i] * xj[i];
+        const double nrm2 = tsqr_sum(part, red);
+        if (!(nrm2 > 0.0)) continue;   // a zero column: R[j][j] = 0, nothing to reflect
+        const double x0 = xj[j];
+        const double nrm = sqrt(nrm2);
+        const double alpha = x0 > 0.0 ? -nrm : nrm;   // reflect x onto alpha e_j (no cancellation)
+        const double v0 = x0 - alpha;                  // v = x - alpha e_j
+        const double tau = 2.0 / (nrm2 - x0 * x0 + v0 * v0);
+        for (int c = j + 1 + wave; c < D; c += kTsqrThreads / 64) {
+            const double* xc = X + c * br;
+            double sdot = 0.0;
+            for (int i = j + 1 + lane; i < nr; i += 64) sdot += xj[i] * xc[i];
+            sdot = wave_sum(sdot);
+            if (lane == 0) wcol[c] = sdot + v0 * xc[j];
+        }
+        __syncthreads();
+        const int h = nr - j;
+        for (int idx = tid; idx < (D - j - 1) * h; idx += kTsqrThreads) {
+            const int c = j + 1 + idx / h, i = j + idx % h;
+            X[c * br + i] -= tau * (i == j ? v0 : xj[i]) * wcol[c];
+        }
+        __syncthreads();
+        if (tid == 0) xj[j] = alpha;
+    }
+    __syncthreads();
+    double* dst = d.dst + (int64_t)b * D * D;
+    for (int idx = tid; idx < D * D; idx += kTsqrThreads) {
+        const int r = idx / D, c = idx - r * D;
+        dst[idx] = (r < kmax && c >= r) ? X[c * br + r] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Grouped Gram of a narrow side: C[split] (D x D, float64) = f * X^T X over one row range, X the
 // (K x D) matricisation of a tensor (view va: rows = D, cols = K), D <= 64.  A workgroup takes
 // one split: chunks of kGramKC rows are staged through LDS as float64 (double buffered, one
@@ -2959,6 +3047,20 @@ hipError_t launch_gemm(int key, const GemmDesc* descs, int ndesc, int64_t tiles,
     return hipSuccess;
 }
 
+hipError_t launch_tsqr(int prec, const TsqrDesc* descs, int ndesc, int64_t blocks, const double* scales,
+                       hipStream_t s) {
+    if (ndesc == 0 || blocks == 0) return hipSuccess;
+    const size_t lds = (size_t)kTsqrElems * sizeof(double);
+    for (int64_t b0 = 0; b0 < blocks; b0 += kMaxGridBlocks) {
+        const dim3 grid((unsigned)std::min<int64_t>(kMaxGridBlocks, blocks - b0)), block(kTsqrThreads);
+        const hipError_t e = by_prec(prec, [&](auto t) {
+            tsqr_blocks<decltype(t)><<<grid, block, lds, s>>>(descs, ndesc, scales, b0);
+        });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Elementwise grouped kernels take an element offset e0 for the same reason (256 work-items each).
 constexpr int64_t kMaxGridElems = kMaxGridBlocks * 256;
 
@@ -3355,6 +3457,10 @@ hipError_t launch_ising_grad(const IsingGraph& g, double beta, const double* J, 
 size_t core_lds_bytes(int max_d) { return (size_t)4 * max_d * max_d * sizeof(double); }
 
 void init_kernel_attrs() {
+    const int tsqr_lds = kTsqrElems * (int)sizeof(double);
+    (void)hipFuncSetAttribute((const void*)tsqr_blocks<double>, hipFuncAttributeMaxDynamicSharedMemorySize, tsqr_lds);
+    (void)hipFuncSetAttribute((const void*)tsqr_blocks<float>, hipFuncAttributeMaxDynamicSharedMemorySize, tsqr_lds);
+    (void)hipFuncSetAttribute((const void*)tsqr_blocks<bf16>, hipFuncAttributeMaxDynamicSharedMemorySize, tsqr_lds);
     (void)hipFuncSetAttribute((const void*)block_jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBJLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<false, double>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);
     (void)hipFuncSetAttribute((const void*)core_kernel<false, float>, hipFuncAttributeMaxDynamicSharedMemorySize, kCoreBwdLdsBytes);

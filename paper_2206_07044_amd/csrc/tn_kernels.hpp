@@ -41,6 +41,9 @@ hipError_t launch_gemm(int dtype_key, const GemmDesc* descs, int ndesc, int64_t 
                        double* maxparts, hipStream_t s);
 hipError_t launch_copy(int prec, const CopyDesc* descs, int ndesc, int64_t total, const double* scales,
                        hipStream_t s);
+// One TSQR pass over `blocks` row blocks; prec is the input's dtype (0 float64, 1 float32, 2 bf16).
+hipError_t launch_tsqr(int prec, const TsqrDesc* descs, int ndesc, int64_t blocks, const double* scales,
+                       hipStream_t s);
 size_t core_lds_bytes(int max_d);
 hipError_t launch_core(int lds, int prec, const CoreDesc* descs, int ndesc, int max_d, int max_sweeps,
                        double* disc, int32_t* tie, int32_t* sweeps, hipStream_t s);

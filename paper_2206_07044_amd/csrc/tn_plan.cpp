@@ -17,6 +17,7 @@ constexpr int64_t kAlign = 256;
 constexpr int64_t kMaxElems = (int64_t)INT32_MAX;   // 32-bit element indexing in kernels
 constexpr int kGemmTile = 64;
 constexpr int kGemmK = 16;
+constexpr int64_t kTsqrMaxD = 64;   // TSQR blocks keep a whole D-column width in LDS
 
 struct EdgeLive {
     int64_t dim;
@@ -724,7 +725,31 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                         st.level = T.level + 1;
                         st.comp = comp_id;
                         st.in_a = ver;
-                        if (mm > D) {
+                        if (mm > D && o.rfactor == 1 && D <= kTsqrMaxD) {
+                            // TSQR: R (D x D) of A_mat (side A) or of B_mat^T (side B), R^T R = the
+                            // Gram; passes of row blocks until one block remains.  The core takes R
+                            // as an explicit factor of D rows
+                            st.kind = ST_TSQR;
+                            st.M = D;
+                            st.K = mm;
+                            st.va = tensor_view(T, fr, shared, E);
+                            st.out_buf = new_buf(D * D * 8, BUF_FACTOR, st.level);
+                            const int64_t br = tsqr_block_rows((int)D);
+                            for (int64_t rows = mm;;) {
+                                const int64_t nb = (rows + br - 1) / br;
+                                st.tsqr_blocks.push_back((int32_t)nb);
+                                if (nb == 1) {
+                                    st.tsqr_bufs.push_back(st.out_buf);
+                                    break;
+                                }
+                                st.tsqr_bufs.push_back(new_buf(nb * D * D * 8, BUF_GRAM, st.level));
+                                rows = nb * D;
+                            }
+                            // algorithmic cost of this R-factor: a QR of an (mm x D) matrix (SI section D)
+                            st.flops = 2.0 * (double)mm * D * D - 2.0 / 3.0 * (double)D * D * D;
+                            st.bytes = (double)w * mm * D;
+                            (side == 0 ? c.rows_a : c.rows_b) = (int32_t)D;
+                        } else if (mm > D) {
                             // Gram: side A -> A_mat^T A_mat ; side B -> B_mat B_mat^T  (both D x D)
                             st.kind = ST_GRAM;
                             st.M = D;
@@ -1298,7 +1323,7 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
             std::string err = make_view(s.va, &v);
             if (err.empty()) err = make_view(s.vb, &v);
             if (!err.empty()) return err;
-        } else if (s.kind == ST_GRAM || s.kind == ST_COPY) {
+        } else if (s.kind == ST_GRAM || s.kind == ST_COPY || s.kind == ST_TSQR) {
             View v;
             std::string err = make_view(s.va, &v);
             if (err.empty() && s.kind == ST_GRAM) err = make_view(s.vb, &v);

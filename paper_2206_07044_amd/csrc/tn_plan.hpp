@@ -38,6 +38,7 @@ struct TreeOpts {
     int32_t gauge_r = 0;            // tree-gauge distance r of every compression
     int32_t segments = 0;           // grad: forward levels in this many recomputed segments (<= 1: none;
                                     // -1: the count of smallest arena among a few candidates)
+    int32_t rfactor = 0;            // R-factors of tall sides with D <= 64: 0 Gram + pivoted Cholesky, 1 TSQR
 };
 
 // One op of the Algorithm 1 expansion (same fields as the host-only describe call).
@@ -62,7 +63,7 @@ struct TensorVer {
     int32_t last_read = 0;
 };
 
-enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS, ST_KRYLOV, ST_GAUGE };
+enum StepKind { ST_CONTRACT = 0, ST_GRAM, ST_COPY, ST_CORE, ST_ABSORB, ST_LANCZOS, ST_KRYLOV, ST_GAUGE, ST_TSQR };
 
 // Tree-gauge steps (ST_GAUGE): 1 = apply a child's environment metric on one bond of a tensor (or of
 // an earlier apply's output), W = X x_bond M, float64 into a buffer of the tensor's layout; 2 = the
@@ -95,6 +96,8 @@ struct Step {
     int32_t gauge_mode = 0;
     int32_t a_buf = -1, b_buf = -1;
     ViewSpec vc;
+    // TSQR: one output buffer and block count per pass (the last pass's buffer is out_buf, 1 block)
+    std::vector<int32_t> tsqr_bufs, tsqr_blocks;
     // CORE
     int32_t comp = -1;              // compression index
     double flops = 0, bytes = 0;
