@@ -87,6 +87,12 @@ __device__ inline double inv_scale(const double* scales, int idx) {
     return s > 0.0 ? 1.0 / s : 0.0;
 }
 
+// A pointer into LDS with its address space in the type, for helpers that are also called on
+// global memory: the compiler then emits LDS instructions where a generic pointer would give flat
+// ones.
+typedef __attribute__((address_space(3))) double lds_double;
+typedef lds_double* LdsPtr;
+
 // Wave reductions with DPP: xor-1 and xor-2 quad permutes, then half-row and row mirrors
 // leave every lane holding its 16-lane row's total; the four row totals are read with
 // readlane and combined in a fixed order, so every lane gets the same, deterministic value.
@@ -1341,8 +1347,9 @@ __device__ inline double row16_sum(double v) {
 // jacobi_svd for rows, cols <= 16 KR (KR <= 4): each pair is rotated by one 16-lane row of a
 // wave (KR rows of W per lane), so reductions stay inside DPP rows and a wave rotates four
 // pairs at once.  Same pair order, thresholds and result contract as jacobi_svd.
-template <int NT = kCoreThreads, int KR = 4>
-__device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
+// P: double* or an LDS-qualified pointer (LdsPtr), for callers whose W and V may live in either.
+template <int NT = kCoreThreads, int KR = 4, typename P = double*>
+__device__ bool jacobi_svd_small(P W, P V, int rows, int cols, int ld, int max_sweeps, CoreShared& sh,
                                  int* sweeps_out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int quarter = lane >> 4, ql = lane & 15;
@@ -1374,10 +1381,10 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
             for (int q = wave * 4 + quarter; q < nc / 2; q += (NT / 64) * 4) {
                 const int p1 = rr_col(q, round, nc), p2 = rr_col(nc - 1 - q, round, nc);
                 if (p1 >= cols || p2 >= cols) continue;
-                double* w1 = W + (int64_t)p1 * ld;
-                double* w2 = W + (int64_t)p2 * ld;
-                double* v1 = V + (int64_t)p1 * ld;
-                double* v2 = V + (int64_t)p2 * ld;
+                const P w1 = W + (int64_t)p1 * ld;
+                const P w2 = W + (int64_t)p2 * ld;
+                const P v1 = V + (int64_t)p1 * ld;
+                const P v2 = V + (int64_t)p2 * ld;
                 // every load up front (clamped index, then zeroed), so their latencies overlap
                 double x[KR], y[KR], xv[KR], yv[KR];
                 double a = 0.0, b = 0.0, g = 0.0;
@@ -1431,10 +1438,148 @@ __device__ bool jacobi_svd_small(double* W, double* V, int rows, int cols, int l
     return converged;
 }
 
+// The rotation of jacobi_rotation by a shorter dependent chain: with u = |d| + r,
+// c = u / sqrt(u^2 + 4 g^2) and s = sgn(d) 2g / sqrt(u^2 + 4 g^2) (u^2 + 4 g^2 = 2 r u, so these
+// are the same c and s).  r = sqrt(d^2 + 4 g^2) takes one Newton step from the hardware
+// reciprocal square root (its error only perturbs the angle); 1 / sqrt(u^2 + 4 g^2) takes one
+// third-order step, so c^2 + s^2 = 1 to rounding.
+__device__ inline void jacobi_rotation_fast(double a, double b, double g, double* c, double* s) {
+    const double d = b - a;
+    const double g2 = g * (4.0 * g);
+    const double q = fma(d, d, g2);
+    if (q > 1e-290 && q < 1e290) {
+        const double y0 = __builtin_amdgcn_rsq(q);
+        const double r0 = q * y0, h0 = 0.5 * y0;
+        const double r = fma(r0, fma(-r0, h0, 0.5), r0);
+        const double u = fabs(d) + r;
+        const double w = fma(u, u, g2);
+        const double z0 = __builtin_amdgcn_rsq(w);
+        const double e = fma(-w * z0, z0, 1.0);
+        const double z = fma(z0 * e, fma(e, 0.375, 0.5), z0);
+        *c = u * z;
+        *s = (d >= 0.0 ? 2.0 * g : -2.0 * g) * z;
+        return;
+    }
+    jacobi_rotation(a, b, g, c, s);
+}
+
+// DPP move of a double for controls that stay inside a 16-lane row (no lane reads out of bounds)
+template <int kCtrl>
+__device__ inline double dpp_row(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+// three row16_sum reductions, stage by stage
+__device__ inline void row16_sum3(double& a, double& b, double& g) {
+    a += dpp_row<0xB1>(a); b += dpp_row<0xB1>(b); g += dpp_row<0xB1>(g);
+    a += dpp_row<0x4E>(a); b += dpp_row<0x4E>(b); g += dpp_row<0x4E>(g);
+    a += dpp_row<0x141>(a); b += dpp_row<0x141>(b); g += dpp_row<0x141>(g);
+    a += dpp_row<0x140>(a); b += dpp_row<0x140>(b); g += dpp_row<0x140>(g);
+}
+
+// jacobi_svd_small for exactly 32 x 32 (rows = cols = 32, column stride ld), the D = 32 cores and
+// the Lanczos tridiagonals of 32 steps.  The first 256 threads rotate the 16 pairs of a round
+// (a 16-lane row per pair, rows i and i + 16 per lane); the rest only keep the barriers.  Round
+// r pairs tournament positions q and 31 - q, whose columns advance by one each round (31 wraps
+// to 1, position 0 keeps column 0), the order of rr_col.  Each round's rotation of V is applied
+// during the next round (V is not read by the rotations), so its loads and stores overlap the
+// next round's dependent chain; the last one is applied after the sweeps.  No row or column
+// masks.  Same thresholds, stopping rule and result contract as jacobi_svd_small.
+template <int NT, typename P>
+__device__ bool jacobi32(P W, P V, int ld, int max_sweeps, CoreShared& sh, int* sweeps_out) {
+    static_assert(NT >= 256 && NT % 64 == 0, "sixteen pairs need four waves");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = wave * 4 + (lane >> 4), ql = lane & 15;
+    const bool act = q < 16;
+    const double tol2 = (2.220446049250313e-16 * 32.0) * (2.220446049250313e-16 * 32.0);
+    double f = 0.0;
+    for (int idx = tid; idx < 1024; idx += NT) {
+        const double x = W[(idx >> 5) * ld + (idx & 31)];
+        f = fma(x, x, f);
+    }
+    f = wave_sum(f);
+    if (lane == 0) sh.rv[wave] = f;
+    __syncthreads();
+    double fro2 = 0.0;
+    for (int w = 0; w < NT / 64; ++w) fro2 += sh.rv[w];
+    const double zero2 = kZeroRel * kZeroRel * fro2;
+    bool pend = false;
+    int pv1 = 0, pv2 = 0;
+    double pc = 1.0, ps = 0.0;
+    int sweeps = 0;
+    bool converged = false;
+    for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+        __syncthreads();   // every thread has read sh.rv / the previous sweep's flags
+        if (tid == 0) sh.flag = sh.flag_big = 0;
+        __syncthreads();
+        int p1 = q, p2 = 31 - q;
+        for (int round = 0; round < 31; ++round) {
+            if (act) {
+                const auto w1 = W + p1 * ld + ql;
+                const auto w2 = W + p2 * ld + ql;
+                const double xa = w1[0], xb = w1[16], ya = w2[0], yb = w2[16];
+                const auto u1 = V + pv1 * ld + ql;
+                const auto u2 = V + pv2 * ld + ql;
+                double vx0 = 0.0, vx1 = 0.0, vy0 = 0.0, vy1 = 0.0;
+                if (pend) {
+                    vx0 = u1[0];
+                    vx1 = u1[16];
+                    vy0 = u2[0];
+                    vy1 = u2[16];
+                }
+                double a = fma(xa, xa, xb * xb), b = fma(ya, ya, yb * yb), g = fma(xa, ya, xb * yb);
+                row16_sum3(a, b, g);
+                if (pend) {
+                    u1[0] = pc * vx0 - ps * vy0;
+                    u2[0] = ps * vx0 + pc * vy0;
+                    u1[16] = pc * vx1 - ps * vy1;
+                    u2[16] = ps * vx1 + pc * vy1;
+                    pend = false;
+                }
+                if (a > zero2 && b > zero2 && g * g > tol2 * a * b) {
+                    double c, s;
+                    jacobi_rotation_fast(a, b, g, &c, &s);
+                    w1[0] = c * xa - s * ya;
+                    w2[0] = s * xa + c * ya;
+                    w1[16] = c * xb - s * yb;
+                    w2[16] = s * xb + c * yb;
+                    pend = true;
+                    pv1 = p1;
+                    pv2 = p2;
+                    pc = c;
+                    ps = s;
+                    if (ql == 0) {
+                        sh.flag = 1;
+                        if (g * g > kQuadRel2 * a * b) sh.flag_big = 1;
+                    }
+                }
+                p1 = q == 0 ? 0 : (p1 == 31 ? 1 : p1 + 1);
+                p2 = p2 == 31 ? 1 : p2 + 1;
+            }
+            __syncthreads();
+        }
+        sweeps = sweep + 1;
+        if (!sh.flag || !sh.flag_big) converged = true;
+    }
+    if (act && pend) {
+        const auto u1 = V + pv1 * ld + ql;
+        const auto u2 = V + pv2 * ld + ql;
+        const double x0 = u1[0], x1 = u1[16], y0 = u2[0], y1 = u2[16];
+        u1[0] = pc * x0 - ps * y0;
+        u2[0] = ps * x0 + pc * y0;
+        u1[16] = pc * x1 - ps * y1;
+        u2[16] = ps * x1 + pc * y1;
+    }
+    __syncthreads();
+    *sweeps_out = sweeps;
+    return converged;
+}
+
 // Column norms of W (sig[j], j < cols) and their descending order (ties: lower column first).
 // With stage (LDS, cols doubles) the ranking reads its copy of the norms instead of sig.
-template <int NT = kCoreThreads>
-__device__ void sorted_norms(const double* W, int rows, int cols, int ld, double* sig, int* order,
+template <int NT = kCoreThreads, typename P = const double*>
+__device__ void sorted_norms(P W, int rows, int cols, int ld, double* sig, int* order,
                              double* stage = nullptr) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j = wave; j < cols; j += (NT / 64)) {
@@ -2003,8 +2148,9 @@ __global__ __launch_bounds__(kLds ? kCoreLdsThreads : kCoreThreads) void core_ke
             __syncthreads();
         }
     } else if constexpr (kLds)   // ra, rb <= D <= 64
-        converged = (ra <= 32 && rb <= 32) ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
-                                           : jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
+        converged = (ra == 32 && rb == 32)   ? jacobi32<NT>(W, V, D, max_sweeps, sh, &sweeps)
+                    : (ra <= 32 && rb <= 32) ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
+                                             : jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps);
     else
         converged = (ra <= 32 && rb <= 32)     ? jacobi_svd_small<NT, 2>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
                     : (ra <= 64 && rb <= 64)   ? jacobi_svd_small<NT>(W, V, ra, rb, D, max_sweeps, sh, &sweeps)
@@ -2571,39 +2717,32 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     // S and T1 were formed before this launch by grouped float64 GEMMs, so that a Lanczos step is
     // one matvec: Y a Gram: T1 = G_Y F_X^T (D x n), S = F_X T1; Y explicit: T1 = C1 = F_X F_Y^T
     // (n x my), S = C1 C1^T
-    // y = S x: a wave per group of four rows, lanes along the contiguous columns, all sixteen
-    // loads of a group (n <= 256) issued before any is used; y lives in LDS, so no store can alias
-    // the loads of S
-    auto apply_s = [&](const double* x, double* y) {
-        if (n > 256) {
-            dense_mv(S, n, n, x, y, 1.0);
-            __syncthreads();
-            return;
-        }
-        const int lane = tid & 63, wave = tid >> 6;
-        for (int i0 = wave * 4; i0 < n; i0 += kCoreWaves * 4) {
-            double f[4][4], xv[4];
+    // y = S x.  For n <= 256, S is symmetric up to the rounding of the GEMMs that formed it, so
+    // y_i = sum_d S[d, i] x_d: thread (h, i) sums the rows d = h mod 4 of column i, reading rows of
+    // S coalesced across i with 32 loads in flight; the four row classes' partial sums meet in LDS
+    // after the vector (the room after y is free while the steps run)
+    static_assert(kCoreThreads == 1024, "four row classes of 256 columns");
+    auto apply_small = [&](const double* x, double* y) {
+        const int i = tid & 255, h = tid >> 8;
+        double acc = 0.0;
+        if (i < n) {
+            const double* sc = S + i;
+            int r = h;
+            for (; r + 4 * 31 < n; r += 4 * 32) {
+                double v[32];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int dcol = lane + 64 * c;
-                xv[c] = dcol < n ? x[dcol] : 0.0;
+                for (int u = 0; u < 32; ++u) v[u] = sc[(int64_t)(r + 4 * u) * n];
+                double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    f[r][c] = (dcol < n && i0 + r < n) ? S[(int64_t)(i0 + r) * n + dcol] : 0.0;
+                for (int u = 0; u < 32; ++u) a4[u & 3] = fma(v[u], x[r + 4 * u], a4[u & 3]);
+                acc += (a4[0] + a4[1]) + (a4[2] + a4[3]);
             }
-            double acc[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                acc[r] = 0.0;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r] = fma(f[r][c], xv[c], acc[r]);
-                acc[r] = wave_sum(acc[r]);
-            }
-            if (lane == 0)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (i0 + r < n) y[i0 + r] = acc[r];
+            for (; r < n; r += 4) acc = fma(sc[(int64_t)r * n], x[r], acc);
         }
+        double* spart = y + n;
+        spart[tid] = acc;
+        __syncthreads();
+        if (tid < n) y[tid] = (spart[tid] + spart[256 + tid]) + (spart[512 + tid] + spart[768 + tid]);
         __syncthreads();
     };
 
@@ -2616,33 +2755,77 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     // x -= Q[:, :k] (Q[:, :k]^T x), twice (classical Gram-Schmidt with reorthogonalisation).
     // Returns the sum of the two passes' coefficients of column k - 1 and ||x||^2 after them.
     const int wave = tid >> 6, lane = tid & 63;
-    auto cgs2 = [&](double* x, int k, double* last_coef) -> double {
+    auto cgs2 = [&](double* x, int k, double* last_coef, bool x_lds) -> double {
         double lc = 0.0, nrm2 = 0.0;
+        // basis in LDS and x the LDS vector lds[0, n), n <= 256, k <= 64: every wave's
+        // coefficients (up to four columns) reduced together, the update split over four column
+        // classes of 256 threads, all through LDS-derived pointers
+        const bool fast = x_lds && n <= 256 && k <= 4 * kCoreWaves && k <= jl;
         for (int pass = 0; pass < 2; ++pass) {
-            for (int c = wave; c < k; c += kCoreWaves) {
-                const double* q = qcol(c);
-                double v = 0.0;
-                for (int i = lane; i < n; i += 64) v += q[i] * x[i];
-                v = wave_sum(v);
-                if (lane == 0) coef[c] = v;
+            if (fast) {
+                double v[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int i = lane; i < n; i += 64) {
+                    const double xi = lds[i];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int c = wave + kCoreWaves * u;
+                        if (c < k) v[u] = fma(lq[(int64_t)c * n + i], xi, v[u]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = wave_sum(v[u]);
+                if (lane == 0)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (wave + kCoreWaves * u < k) coef[wave + kCoreWaves * u] = v[u];
+            } else {
+                for (int c = wave; c < k; c += kCoreWaves) {
+                    const double* q = qcol(c);
+                    double v = 0.0;
+                    for (int i = lane; i < n; i += 64) v += q[i] * x[i];
+                    v = wave_sum(v);
+                    if (lane == 0) coef[c] = v;
+                }
             }
             __syncthreads();
             if (k > 0) lc += coef[k - 1];
             double part = 0.0;
-            for (int i = tid; i < n; i += kCoreThreads) {
-                // four interleaved partial sums keep the dependent chain a quarter as long
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-                int c = 0;
-                for (; c + 4 <= k; c += 4) {
-                    s0 = fma(qcol(c)[i], coef[c], s0);
-                    s1 = fma(qcol(c + 1)[i], coef[c + 1], s1);
-                    s2 = fma(qcol(c + 2)[i], coef[c + 2], s2);
-                    s3 = fma(qcol(c + 3)[i], coef[c + 3], s3);
+            if (fast) {
+                const int i = tid & 255, h = tid >> 8;
+                double a0 = 0.0, a1 = 0.0;
+                if (i < n) {
+                    int c = h;
+                    for (; c + 4 < k; c += 8) {
+                        a0 = fma(lq[(int64_t)c * n + i], coef[c], a0);
+                        a1 = fma(lq[(int64_t)(c + 4) * n + i], coef[c + 4], a1);
+                    }
+                    if (c < k) a0 = fma(lq[(int64_t)c * n + i], coef[c], a0);
                 }
-                for (; c < k; ++c) s0 = fma(qcol(c)[i], coef[c], s0);
-                const double acc = x[i] - ((s0 + s1) + (s2 + s3));
-                x[i] = acc;
-                part += acc * acc;
+                // x occupies at most lds[0, n) or the basis room: the partial sums go after it
+                double* spart = lds + n;
+                spart[tid] = a0 + a1;
+                __syncthreads();
+                if (tid < n) {
+                    const double acc = lds[tid] - ((spart[tid] + spart[256 + tid]) + (spart[512 + tid] + spart[768 + tid]));
+                    lds[tid] = acc;
+                    part = acc * acc;
+                }
+            } else {
+                for (int i = tid; i < n; i += kCoreThreads) {
+                    // four interleaved partial sums keep the dependent chain a quarter as long
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                    int c = 0;
+                    for (; c + 4 <= k; c += 4) {
+                        s0 = fma(qcol(c)[i], coef[c], s0);
+                        s1 = fma(qcol(c + 1)[i], coef[c + 1], s1);
+                        s2 = fma(qcol(c + 2)[i], coef[c + 2], s2);
+                        s3 = fma(qcol(c + 3)[i], coef[c + 3], s3);
+                    }
+                    for (; c < k; ++c) s0 = fma(qcol(c)[i], coef[c], s0);
+                    const double acc = x[i] - ((s0 + s1) + (s2 + s3));
+                    x[i] = acc;
+                    part += acc * acc;
+                }
             }
             if (pass == 1) nrm2 = block_sum(part, sh);
             else __syncthreads();
@@ -2664,9 +2847,19 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     // ||S||_F^2 = the sum of the squared eigenvalues of S (the completeness test below)
     double fro2 = 0.0;
     {
-        double part = 0.0;
-        for (int64_t idx = tid; idx < (int64_t)n * n; idx += kCoreThreads) part += S[idx] * S[idx];
-        fro2 = block_sum(part, sh);
+        // sixteen loads in flight per thread
+        double p4[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t nn = (int64_t)n * n;
+        int64_t idx = tid;
+        for (; idx + 15 * kCoreThreads < nn; idx += 16 * kCoreThreads) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = S[idx + (int64_t)u * kCoreThreads];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) p4[u & 3] = fma(v[u], v[u], p4[u & 3]);
+        }
+        for (; idx < nn; idx += kCoreThreads) p4[0] = fma(S[idx], S[idx], p4[0]);
+        fro2 = block_sum((p4[0] + p4[1]) + (p4[2] + p4[3]), sh);
     }
     int s = 0, restarts = 0, nev = 0;
     int s_prev = 0;   // size of the last tridiagonal solve (its eigenvectors are in Vs)
@@ -2682,11 +2875,20 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     for (;;) {
         for (; s < target && !exhausted; ++s) {
             const int j = s;
-            apply_s(qcol(j), qnext);
+            // the vector and the result in LDS (n <= 256) are read and written through
+            // LDS-derived pointers, so the loops use LDS instructions rather than flat ones
+            if (n > 256) {
+                dense_mv(S, n, n, qcol(j), qnext, 1.0);
+                __syncthreads();
+            } else if (j < jl) {
+                apply_small(lq + (int64_t)j * n, lds);
+            } else {
+                apply_small(Q + (int64_t)j * n, lds);
+            }
             // full orthogonalisation against q_0..q_j: q_j's coefficient is alpha_j, the remaining
             // norm beta_j (the three-term recurrence in exact arithmetic)
             double a = 0.0;
-            const double b = sqrt(cgs2(qnext, j + 1, &a));
+            const double b = sqrt(cgs2(qnext, j + 1, &a, qnext == lds));
             alpha[j] = a;
             bmax = fmax(bmax, fmax(b, fabs(a)));
             if (j + 1 >= n) {   // the basis spans the whole space
@@ -2705,7 +2907,7 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
                 ++restarts;
                 for (int i = tid; i < n; i += kCoreThreads) qn[i] = probe_entry(i, restarts);
                 __syncthreads();
-                const double rn = sqrt(cgs2(qn, j + 1, nullptr));
+                const double rn = sqrt(cgs2(qn, j + 1, nullptr, false));
                 if (!(rn > 1e-8)) {
                     exhausted = true;
                     s = j + 1;
@@ -2725,37 +2927,46 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         // in the workspace left it in Vg, at the same stride as the next)
         const double* vp = s_prev <= kTriLdsS ? Wg : Vg;
         const int lwp = s_prev <= kTriLdsS ? s_prev : ls;
+        // one body for both homes of W and V, inlined at each call so that the LDS one compiles
+        // to LDS instructions
+        auto tri_solve = [&](auto Wp, auto Vp, int lwv) __attribute__((always_inline)) -> bool {
+            for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
+                const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
+                Vp[(int64_t)c * lwv + r] = (c < s_prev && r < s_prev) ? vp[(int64_t)c * lwp + r] : (r == c ? 1.0 : 0.0);
+            }
+            __syncthreads();
+            for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
+                const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
+                const auto vc = Vp + (int64_t)c * lwv;
+                double v = alpha[r] * vc[r];
+                if (r > 0) v += beta[r - 1] * vc[r - 1];
+                if (r + 1 < s) v += beta[r] * vc[r + 1];
+                Wp[(int64_t)c * lwv + r] = v;
+            }
+            __syncthreads();
+            int sw = 0;
+            const bool ok = s == 32 ? jacobi32<kCoreThreads>(Wp, Vp, lwv, max_sweeps, sh, &sw)
+                            : s < 32 ? jacobi_svd_small<kCoreThreads, 2>(Wp, Vp, s, s, lwv, max_sweeps, sh, &sw)
+                            : s <= 64 ? jacobi_svd_small(Wp, Vp, s, s, lwv, max_sweeps, sh, &sw)
+                                      : jacobi_svd((double*)Wp, (double*)Vp, s, s, lwv, max_sweeps, sh, &sw);
+            sorted_norms(Wp, s, s, lwv, sig, order);
+            return ok;
+        };
+        bool jc;
         if (s <= kTriLdsS) {
             W = lds;
             Vs = lds + (int64_t)s * s;
             lw = s;
+            jc = tri_solve((LdsPtr)lds, (LdsPtr)lds + (int64_t)s * s, s);
+            // keep V for the next check's warm start (read after the barrier below)
+            for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) Wg[idx] = lds[(int64_t)s * s + idx];
         } else {
             W = Wg;   // written only after V has been read from Wg (barrier between)
             Vs = Vg;
             lw = ls;
+            jc = tri_solve(Wg, Vg, ls);
         }
-        for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
-            const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
-            Vs[(int64_t)c * lw + r] = (c < s_prev && r < s_prev) ? vp[(int64_t)c * lwp + r] : (r == c ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
-            const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
-            const double* vc = Vs + (int64_t)c * lw;
-            double v = alpha[r] * vc[r];
-            if (r > 0) v += beta[r - 1] * vc[r - 1];
-            if (r + 1 < s) v += beta[r] * vc[r + 1];
-            W[(int64_t)c * lw + r] = v;
-        }
-        __syncthreads();
         s_prev = s;
-        int sw = 0;
-        const bool jc = s <= 32 ? jacobi_svd_small<kCoreThreads, 2>(W, Vs, s, s, lw, max_sweeps, sh, &sw)
-                      : s <= 64 ? jacobi_svd_small(W, Vs, s, s, lw, max_sweeps, sh, &sw)
-                                : jacobi_svd(W, Vs, s, s, lw, max_sweeps, sh, &sw);
-        sorted_norms(W, s, s, lw, sig, order);
-        if (s <= kTriLdsS)   // keep V for the next check's warm start (read after the barrier below)
-            for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) Wg[idx] = Vs[idx];
         nev = s;
         const double lmax = s > 0 ? sig[order[0]] : 0.0;
         const double bl = (exhausted || s == 0) ? 0.0 : beta[s - 1];
