@@ -2917,11 +2917,12 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
                 __syncthreads();
             }
         }
-        // eigenpairs of the s x s tridiagonal T (symmetric positive semidefinite: its
-        // one-sided Jacobi SVD gives eigenvalues as column norms and eigenvectors in Vs).
+        // eigenpairs of the s x s tridiagonal T (symmetric positive semidefinite): the one-sided
+        // Jacobi SVD of L^T V (T = L L^T) gives eigenvalues as squared column norms and
+        // eigenvectors in Vs.
         // Warm start: T's leading s_prev x s_prev block is the previous check's T, whose
         // eigenvectors the previous solve left in Vs; V starts as those, extended by the
-        // identity, and W = T V.  The rotations then only resolve the coupling to the new
+        // identity, and W = L^T V.  The rotations then only resolve the coupling to the new
         // steps, in a few sweeps instead of a full solve.
         // (a solve in LDS copied its V to Wg, since the next Lanczos vectors reuse that room; one
         // in the workspace left it in Vg, at the same stride as the next)
@@ -2934,13 +2935,32 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
                 const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
                 Vp[(int64_t)c * lwv + r] = (c < s_prev && r < s_prev) ? vp[(int64_t)c * lwp + r] : (r == c ? 1.0 : 0.0);
             }
+            // T = L L^T with L lower bidiagonal (diagonal ld_[i], subdiagonal le_[i] = L[i+1][i]),
+            // by one thread; W = L^T V then has W^T W = V^T T V, so the one-sided Jacobi below
+            // converges like a two-sided one on T (rather than on T^2, as on W = T V would) and
+            // the eigenvalues of T are the squared column norms.  T is positive semidefinite: a
+            // pivot at the rounding level of ||T|| is taken as zero, with its column of L.
+            double* ld_ = t1;   // s <= n <= D: the explicit side has at most D rows
+            double* le_ = t2;
+            if (tid == 0) {
+                double amax = 0.0;
+                for (int i = 0; i < s; ++i) amax = fmax(amax, fabs(alpha[i]));
+                const double floor_ = 1e-15 * amax;
+                double prev = 0.0;   // L[i][i-1]
+                for (int i = 0; i < s; ++i) {
+                    const double piv = alpha[i] - prev * prev;
+                    const double l = piv > floor_ ? sqrt(piv) : 0.0;
+                    ld_[i] = l;
+                    prev = (i + 1 < s && l > 0.0) ? beta[i] / l : 0.0;
+                    if (i + 1 < s) le_[i] = prev;
+                }
+            }
             __syncthreads();
             for (int64_t idx = tid; idx < (int64_t)s * s; idx += kCoreThreads) {
                 const int c = (int)(idx / s), r = (int)(idx - (int64_t)c * s);
                 const auto vc = Vp + (int64_t)c * lwv;
-                double v = alpha[r] * vc[r];
-                if (r > 0) v += beta[r - 1] * vc[r - 1];
-                if (r + 1 < s) v += beta[r] * vc[r + 1];
+                double v = ld_[r] * vc[r];
+                if (r + 1 < s) v = fma(le_[r], vc[r + 1], v);
                 Wp[(int64_t)c * lwv + r] = v;
             }
             __syncthreads();
@@ -2950,6 +2970,8 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
                             : s <= 64 ? jacobi_svd_small(Wp, Vp, s, s, lwv, max_sweeps, sh, &sw)
                                       : jacobi_svd((double*)Wp, (double*)Vp, s, s, lwv, max_sweeps, sh, &sw);
             sorted_norms(Wp, s, s, lwv, sig, order);
+            for (int j = tid; j < s; j += kCoreThreads) sig[j] = sig[j] * sig[j];
+            __syncthreads();
             return ok;
         };
         bool jc;
