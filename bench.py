@@ -42,7 +42,7 @@ PEAKS = {  # MI355X published dense peaks
 # was measured on (SHA-256 prefix of tn_kernels.hip), else the bench line reports null.
 MEASURED_TRAFFIC = {
     ("core_lds", "fp32", "ising-cubic-12x12x12-beta0.22-chi16-span-sweep"): {
-        "bytes_per_launch": 477.9 * 1024, "kernel_source_sha256": "f42cdd3f0fc4f28c",
+        "bytes_per_launch": 483.0 * 1024, "kernel_source_sha256": "cd77ecaa883773e0",
         "source": "profiles/core_lds_traffic_ising12_chi16_fp32.md"},
 }
 

@@ -46,10 +46,11 @@ def _reference(A, B, chi, cutoff=0.0):
     return k, U[:, :k] * sq, sq[:, None] * Vt[:k], s
 
 
-# (m_a, D, m_b, chi): tall-tall (both Grams, several 512-row splits and a ragged tail),
-# explicit side A, explicit side B, both explicit, D = 64, D = 1, chi above the rank
-SHAPES = [(1500, 32, 700, 8), (40, 64, 2000, 16), (3000, 48, 30, 12), (5, 16, 7, 10), (1100, 64, 1100, 64),
-          (777, 1, 333, 1), (600, 20, 9, 50)]
+# (m_a, D, m_b, chi): tall-tall (both Grams, several 512-row splits and a ragged tail; D = 32 at
+# full rank takes the 32 x 32 Jacobi, also at the tree's chi' = 16), explicit side A, explicit side
+# B, both explicit, D = 64, D = 1, chi above the rank
+SHAPES = [(1500, 32, 700, 8), (4100, 32, 2500, 16), (40, 64, 2000, 16), (3000, 48, 30, 12), (5, 16, 7, 10),
+          (1100, 64, 1100, 64), (777, 1, 333, 1), (600, 20, 9, 50)]
 
 
 @pytest.mark.parametrize("ma,D,mb,chi", SHAPES)
