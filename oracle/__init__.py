@@ -7,7 +7,9 @@ bond compression (section II.C, Eq. (svd)) and the projector form (SI B);
 ``exact`` holds independent exact references (brute force, transfer
 matrices, matching counts) used to pin it; ``grad`` is the reverse-mode
 adjoint of the same forward pass (textbook truncated-SVD adjoint over the
-complete core spectrum), the reference gradient.
+complete core spectrum), the reference gradient; ``projnet`` builds the explicit
+projector network T_P of SI B from an oracle run (its exact contraction equals the
+compressed value).
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  The library never calls it and has no fallback to it.

@@ -107,6 +107,8 @@ class _Network:
 
 
 _RECORD: Optional[List[np.ndarray]] = None
+# when a list: every compression appends (shared edge ids in P_L's row order, new edge id, P_L, P_R)
+_PROJECTORS: Optional[list] = None
 
 
 def _normalise(arr: np.ndarray, scales: List[float]) -> np.ndarray:
@@ -211,6 +213,8 @@ def _compress(net: _Network, a: int, b: int, chi: int, cutoff: float,
         p_r = inv_sqrt[:, None] * (U[:, :new].T @ r_a)  # chi' x D
         new_a = a_mat @ p_l
         new_b = p_r @ b_mat
+        if _PROJECTORS is not None:
+            _PROJECTORS.append((list(shared), net.next_edge, p_l.copy(), p_r.copy()))
     e_new = net.next_edge
     net.next_edge += 1
     ops.append(OpRecord("compress", a, b, e_new, ma, D, mb, new, disc, tie))
