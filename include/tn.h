@@ -242,6 +242,21 @@ tn_status tn_profile_read(const tn_ctx* ctx, int32_t kind, double* ms, int64_t* 
  * host `out`; *n receives the tensor's size. */
 tn_status tn_read_tensor(const tn_ctx* ctx, int32_t index, double* out, int64_t cap, int64_t* n);
 
+/* The projectors of compression `comp` (creation order, as in tn_compress_stats) of the last
+ * evaluation (section II.C, Eq. (svd); SI B): P_L (D x chi', row-major) into host `p_left` and
+ * P_R (chi' x D, row-major) into host `p_right`, as float64, `cap` >= D * chi' entries each;
+ * either may be null.  They are the ones the re-absorption applied (a' = A P_L, b' = P_R B), in
+ * the storage precision, computed from the normalised tensors: only the product P_L P_R is
+ * scale-free, which is what the explicit projector network T_P of SI B inserts on the bond.
+ * The bond: `bond_edges` receives up to `edge_cap` edge ids it bundles, in P_L's row order
+ * (slowest first; input edges 0..n_edges-1, then one new edge per compression in creation
+ * order); `info` (6 int32) receives D, chi', the new edge's id, the tree nodes a (P_L's side)
+ * and b (inputs 0..n-1, step t's result n + t) and the number of bundled edges.  The bond
+ * description needs only a tree (no evaluation); the projectors need an evaluation of a tree set
+ * with keep_intermediates = 1 (else TN_ESTATE: their memory may have been reused). */
+tn_status tn_read_projectors(const tn_ctx* ctx, int32_t comp, double* p_left, double* p_right, int64_t cap,
+                             int32_t* bond_edges, int32_t edge_cap, int32_t* info);
+
 /* Reverse pass (no counterpart in the paper, which computes no gradients):
  * d ln|Z| / d data for the last evaluated tree, where data are the input
  * tensor entries of tn_load_graph / tn_update_values.  Written to host

@@ -98,6 +98,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
         "tn_batch_grad": ([P, C.POINTER(P)], C.c_int),
         "tn_ising_coupling_grad_device": ([P, D, P, P, P], C.c_int),
         "tn_read_tensor": ([P, I32, pD, I64, pI64], C.c_int),
+        "tn_read_projectors": ([P, I32, pD, pD, I64, pI32, I32, pI32], C.c_int),
         "tn_profile": ([P, C.c_uint32], C.c_int),
         "tn_profile_read": ([P, I32, pD, pI64, pD, pD], C.c_int),
         "tn_plan_describe": ([I32, I32, pI32, pI32, pI32, I32, pI32, pI32, C.POINTER(tn_tree_opts), I64, pI64, pI64],
@@ -114,7 +115,7 @@ def load_library(path: Optional[str] = None) -> C.CDLL:
 def exported_symbols() -> List[str]:
     return ["tn_create", "tn_destroy", "tn_last_error", "tn_load_graph", "tn_update_values",
             "tn_update_values_device", "tn_set_workspace", "tn_set_tree", "tn_plan_info", "tn_contract_compressed", "tn_result",
-            "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_profile", "tn_profile_read", "tn_grad",
+            "tn_enqueue", "tn_fetch", "tn_compress_stats", "tn_read_tensor", "tn_read_projectors", "tn_profile", "tn_profile_read", "tn_grad",
             "tn_grad_device", "tn_grad_info", "tn_grad_checkpoint_info", "tn_ising_values_device", "tn_ising_coupling_grad_device", "tn_sync",
             "tn_batch_create", "tn_batch_destroy", "tn_batch_last_error", "tn_batch_contract", "tn_batch_grad",
             "tn_plan_describe", "tn_compress_pair", "tn_compress_pair_static", "tn_gemm_tiles_get",
@@ -327,6 +328,27 @@ class Context:
         out = np.zeros(max(1, n.value))
         self._check(self._lib.tn_read_tensor(self._h, int(index), _ptr(out, C.c_double), n.value, C.byref(n)))
         return out[:n.value]
+
+    def tn_read_projectors(self, comp: int, values: bool = True) -> dict:
+        """Compression `comp`'s bond (tree nodes a and b, bundled edges in P_L's row order, the new
+        edge) and, with `values`, its projectors P_L (D x chi') and P_R (chi' x D) as float64."""
+        info = np.zeros(6, dtype=np.int32)
+        self._check(self._lib.tn_read_projectors(self._h, int(comp), None, None, 0, None, 0, _ptr(info, C.c_int32)))
+        D, cn, e_new, a, b, ne = (int(x) for x in info)
+        edges = np.zeros(max(1, ne), dtype=np.int32)
+        out = {"D": D, "chi": cn, "new_edge": e_new, "a": a, "b": b}
+        if values:
+            pl = np.zeros(max(1, D * cn))
+            pr = np.zeros(max(1, D * cn))
+            self._check(self._lib.tn_read_projectors(self._h, int(comp), _ptr(pl, C.c_double), _ptr(pr, C.c_double),
+                                                     D * cn, _ptr(edges, C.c_int32), ne, _ptr(info, C.c_int32)))
+            out["p_left"] = pl[:D * cn].reshape(D, cn)
+            out["p_right"] = pr[:D * cn].reshape(cn, D)
+        else:
+            self._check(self._lib.tn_read_projectors(self._h, int(comp), None, None, 0, _ptr(edges, C.c_int32), ne,
+                                                     _ptr(info, C.c_int32)))
+        out["edges"] = [int(e) for e in edges[:ne]]
+        return out
 
     def tn_grad(self, out: Optional[np.ndarray] = None) -> np.ndarray:
         """d ln|Z| / d data (float64, the layout of the loaded data)."""

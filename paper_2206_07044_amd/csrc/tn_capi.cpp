@@ -1823,6 +1823,56 @@ tn_status tn_read_tensor(const tn_ctx* c0, int32_t index, double* out, int64_t c
     return TN_OK;
 }
 
+tn_status tn_read_projectors(const tn_ctx* c0, int32_t comp, double* p_left, double* p_right, int64_t cap,
+                             int32_t* bond_edges, int32_t edge_cap, int32_t* info) {
+    tn_ctx* c = const_cast<tn_ctx*>(c0);
+    if (!c) return TN_EINVAL;
+    if (!c->has_plan) return fail(c, TN_ESTATE, "no tree set");
+    const Plan& P = c->plan;
+    if (comp < 0 || comp >= (int32_t)P.comps.size()) return fail(c, TN_EINVAL, "compression index out of range");
+    const Compression& cp = P.comps[comp];
+    const int64_t D = cp.D, cn = cp.chi_new;
+    if (info) {
+        info[0] = (int32_t)D;
+        info[1] = (int32_t)cn;
+        info[2] = cp.e_new;
+        info[3] = cp.node_a;
+        info[4] = cp.node_b;
+        info[5] = (int32_t)cp.bond_edges.size();
+    }
+    if (bond_edges)
+        for (int32_t i = 0; i < std::min<int32_t>(edge_cap, (int32_t)cp.bond_edges.size()); ++i)
+            bond_edges[i] = cp.bond_edges[i];
+    if (!p_left && !p_right) return TN_OK;
+    if (!c->evaluated) return fail(c, TN_ESTATE, "no evaluation yet");
+    if (!P.opts.keep) return fail(c, TN_ESTATE, "projectors stay intact only with keep_intermediates = 1");
+    if (cap < D * cn) return fail(c, TN_EINVAL, "output buffers hold fewer than D * chi' entries");
+    (void)hipSetDevice(c->device);
+    for (int side = 0; side < 2; ++side) {
+        double* out = side == 0 ? p_left : p_right;
+        if (!out) continue;
+        const char* src = c->arena + P.bufs[side == 0 ? cp.pl_buf : cp.pr_buf].off;
+        const int64_t k = D * cn;
+        if (P.elem_size == 8) {
+            HIP_TRY(c, hipMemcpy(out, src, k * sizeof(double), hipMemcpyDeviceToHost));
+        } else if (P.elem_size == 4) {
+            std::vector<float> tmp(k);
+            HIP_TRY(c, hipMemcpy(tmp.data(), src, k * sizeof(float), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < k; ++i) out[i] = tmp[i];
+        } else {   // bfloat16: the upper half of a binary32
+            std::vector<uint16_t> tmp(k);
+            HIP_TRY(c, hipMemcpy(tmp.data(), src, k * sizeof(uint16_t), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < k; ++i) {
+                const uint32_t u = (uint32_t)tmp[i] << 16;
+                float f;
+                std::memcpy(&f, &u, sizeof(f));
+                out[i] = f;
+            }
+        }
+    }
+    return TN_OK;
+}
+
 tn_status tn_grad_device(tn_ctx* c, void* out) {
     if (!c) return TN_EINVAL;
     if (!out) return fail(c, TN_EINVAL, "null gradient buffer");

@@ -436,6 +436,10 @@ std::string build_plan(const GraphSpec& g, const int32_t* pi, const int32_t* pj,
                 Compression c{};
                 c.a_ver_in = va;
                 c.b_ver_in = vb;
+                c.node_a = a;
+                c.node_b = b;
+                c.e_new = e_new;
+                c.bond_edges = shared;
                 c.ma = ma;
                 c.D = D;
                 c.mb = mb;

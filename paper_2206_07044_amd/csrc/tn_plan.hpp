@@ -105,6 +105,10 @@ struct Step {
 
 struct Compression {
     int32_t a_ver_in, b_ver_in, a_ver_out, b_ver_out;
+    // the bond: tree nodes a (P_L's side) and b, the edges it bundles in P_L's row order (slowest
+    // first), the new edge that replaces them
+    int32_t node_a, node_b, e_new;
+    std::vector<int32_t> bond_edges;
     int64_t ma, D, mb;
     int32_t chi_new;
     int32_t side_a_buf, side_b_buf;     // Gram partials or explicit factor
