@@ -3038,15 +3038,35 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
         target = min(sm, s + 4);
         __syncthreads();
     }
-    // Ritz vectors w_t = Q Vs[:, order[t]]
-    for (int64_t idx = tid; idx < (int64_t)n * cn; idx += kCoreThreads) {
-        const int t = (int)(idx / n), i = (int)(idx - (int64_t)t * n);
-        double acc = 0.0;
-        if (t < nev) {
-            const int c = order[t];
-            for (int j = 0; j < nev; ++j) acc += qcol(j)[i] * Vs[(int64_t)c * lw + j];
+    // Ritz vectors w_t = Q Vs[:, order[t]]; when the basis and Vs are both in LDS (Vs right after
+    // the last solve's W, stride nev) through LDS-typed pointers, two partial sums per output
+    if (nev <= jl && nev <= kTriLdsS) {
+        const LdsPtr qb = (LdsPtr)lq;
+        const LdsPtr vb = (LdsPtr)lds + (int64_t)nev * nev;
+        for (int64_t idx = tid; idx < (int64_t)n * cn; idx += kCoreThreads) {
+            const int t = (int)(idx / n), i = (int)(idx - (int64_t)t * n);
+            double a0 = 0.0, a1 = 0.0;
+            if (t < nev) {
+                const LdsPtr vc = vb + (int64_t)order[t] * nev;
+                int j = 0;
+                for (; j + 1 < nev; j += 2) {
+                    a0 = fma(qb[(int64_t)j * n + i], vc[j], a0);
+                    a1 = fma(qb[(int64_t)(j + 1) * n + i], vc[j + 1], a1);
+                }
+                if (j < nev) a0 = fma(qb[(int64_t)j * n + i], vc[j], a0);
+            }
+            Wt[(int64_t)t * n + i] = a0 + a1;
         }
-        Wt[(int64_t)t * n + i] = acc;
+    } else {
+        for (int64_t idx = tid; idx < (int64_t)n * cn; idx += kCoreThreads) {
+            const int t = (int)(idx / n), i = (int)(idx - (int64_t)t * n);
+            double acc = 0.0;
+            if (t < nev) {
+                const int c = order[t];
+                for (int j = 0; j < nev; ++j) acc += qcol(j)[i] * Vs[(int64_t)c * lw + j];
+            }
+            Wt[(int64_t)t * n + i] = acc;
+        }
     }
     __syncthreads();
     const double lmax = nev > 0 ? sig[order[0]] : 0.0;
