@@ -1681,9 +1681,10 @@ __device__ void wg_gemm_f64(const double* __restrict__ A, int64_t ar, int64_t ac
 // memory: each wave owns 16 x 32 blocks of C (two 16 x 16 x 4 instructions per step of 4 along
 // K).  A(i, k) = A[i * ar + k * ac], B(k, j) = B[k * br + j * bc], C(i, j) = C[i * cr + j * cc],
 // stored as TC.  Ends with a barrier.
-template <typename TC, int NW = kCoreWaves>
+// PB: B's pointer type (const double*, or LdsPtr for a B staged in LDS)
+template <typename TC, int NW = kCoreWaves, typename PB = const double*>
 __device__ void wg_gemm_narrow_to(const double* __restrict__ A, int64_t ar, int64_t ac,
-                                  const double* __restrict__ B, int64_t br, int64_t bc, TC* __restrict__ C,
+                                  PB __restrict__ B, int64_t br, int64_t bc, TC* __restrict__ C,
                                   int64_t cr, int64_t cc, int M, int N, int K) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -1716,10 +1717,11 @@ __device__ void wg_gemm_narrow_to(const double* __restrict__ A, int64_t ar, int6
 }
 
 // wg_gemm_narrow_to into a row-major float64 C with leading dimension ldc.
+template <int NW = kCoreWaves, typename PB = const double*>
 __device__ inline void wg_gemm_f64_narrow(const double* __restrict__ A, int64_t ar, int64_t ac,
-                                          const double* __restrict__ B, int64_t br, int64_t bc,
+                                          PB __restrict__ B, int64_t br, int64_t bc,
                                           double* __restrict__ C, int64_t ldc, int M, int N, int K) {
-    wg_gemm_narrow_to<double>(A, ar, ac, B, br, bc, C, ldc, 1, M, N, K);
+    wg_gemm_narrow_to<double, NW, PB>(A, ar, ac, B, br, bc, C, ldc, 1, M, N, K);
 }
 
 // Block one-sided Jacobi for the global cores (64 < D <= 256): the columns of the matrix it
@@ -3072,14 +3074,22 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     const double lmax = nev > 0 ? sig[order[0]] : 0.0;
     Tp* PL = (Tp*)d.p_left;
     Tp* PR = (Tp*)d.p_right;
-    // all kept columns at once: P1 = F_X^T W, P2 = G_Y P1
-    wg_gemm_f64_narrow(FX, 1, D, Wt, 1, n, P1, cn, D, cn, n);
-    if (d.gram_y) {
-        wg_gemm_f64_narrow(T1, n, 1, Wt, 1, n, P2, cn, D, cn, n);            // T1 W = G_Y F_X^T W
+    // all kept columns at once: P1 = F_X^T W; Y a Gram: P2 = T1 W = G_Y F_X^T W; Y explicit: PY = C1^T W = F_Y F_X^T W, then
+    // P2 = F_Y^T PY.  W is staged in LDS (free after the Ritz vectors) when it fits: every wave of
+    // the products reads all of it
+    if ((int64_t)n * cn <= (int64_t)kLanczosLdsBytes / 8) {
+        for (int64_t idx = tid; idx < (int64_t)n * cn; idx += kCoreThreads) lds[idx] = Wt[idx];
+        __syncthreads();
+        const LdsPtr wl = (LdsPtr)lds;
+        wg_gemm_f64_narrow<kCoreWaves, LdsPtr>(FX, 1, D, wl, 1, n, P1, cn, D, cn, n);
+        if (d.gram_y) wg_gemm_f64_narrow<kCoreWaves, LdsPtr>(T1, n, 1, wl, 1, n, P2, cn, D, cn, n);
+        else wg_gemm_f64_narrow<kCoreWaves, LdsPtr>(T1, 1, d.my, wl, 1, n, PY, cn, d.my, cn, n);
     } else {
-        wg_gemm_f64_narrow(T1, 1, d.my, Wt, 1, n, PY, cn, d.my, cn, n);      // C1^T W = F_Y F_X^T W
-        wg_gemm_f64_narrow(d.fy, 1, D, PY, cn, 1, P2, cn, D, cn, d.my);      // F_Y^T F_Y F_X^T W
+        wg_gemm_f64_narrow(FX, 1, D, Wt, 1, n, P1, cn, D, cn, n);
+        if (d.gram_y) wg_gemm_f64_narrow(T1, n, 1, Wt, 1, n, P2, cn, D, cn, n);
+        else wg_gemm_f64_narrow(T1, 1, d.my, Wt, 1, n, PY, cn, d.my, cn, n);
     }
+    if (!d.gram_y) wg_gemm_f64_narrow(d.fy, 1, D, PY, cn, 1, P2, cn, D, cn, d.my);
     for (int idx = tid; idx < D * cn; idx += kCoreThreads) {
         const int dd = idx / cn, t = idx - dd * cn;
         const double lv = t < nev ? sig[order[t]] : 0.0;   // eigenvalue = sigma^2
