@@ -1335,12 +1335,19 @@ __device__ bool jacobi_svd_256(double* W, double* V, int rows, int cols, int ld,
     return converged;
 }
 
-// Sum over the lane's 16-lane DPP row (every lane of the row gets the row total).
+// Sum over the lane's 16-lane DPP row (every lane of the row gets the row total).  The four
+// controls stay inside the row, so no lane reads out of bounds and the moves need no old value.
+template <int kCtrl>
+__device__ inline double dpp_in_row(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
 __device__ inline double row16_sum(double v) {
-    v += dpp_mov<0xB1>(v);
-    v += dpp_mov<0x4E>(v);
-    v += dpp_mov<0x141>(v);
-    v += dpp_mov<0x140>(v);
+    v += dpp_in_row<0xB1>(v);
+    v += dpp_in_row<0x4E>(v);
+    v += dpp_in_row<0x141>(v);
+    v += dpp_in_row<0x140>(v);
     return v;
 }
 
@@ -1463,19 +1470,12 @@ __device__ inline void jacobi_rotation_fast(double a, double b, double g, double
     jacobi_rotation(a, b, g, c, s);
 }
 
-// DPP move of a double for controls that stay inside a 16-lane row (no lane reads out of bounds)
-template <int kCtrl>
-__device__ inline double dpp_row(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
 // three row16_sum reductions, stage by stage
 __device__ inline void row16_sum3(double& a, double& b, double& g) {
-    a += dpp_row<0xB1>(a); b += dpp_row<0xB1>(b); g += dpp_row<0xB1>(g);
-    a += dpp_row<0x4E>(a); b += dpp_row<0x4E>(b); g += dpp_row<0x4E>(g);
-    a += dpp_row<0x141>(a); b += dpp_row<0x141>(b); g += dpp_row<0x141>(g);
-    a += dpp_row<0x140>(a); b += dpp_row<0x140>(b); g += dpp_row<0x140>(g);
+    a += dpp_in_row<0xB1>(a); b += dpp_in_row<0xB1>(b); g += dpp_in_row<0xB1>(g);
+    a += dpp_in_row<0x4E>(a); b += dpp_in_row<0x4E>(b); g += dpp_in_row<0x4E>(g);
+    a += dpp_in_row<0x141>(a); b += dpp_in_row<0x141>(b); g += dpp_in_row<0x141>(g);
+    a += dpp_in_row<0x140>(a); b += dpp_in_row<0x140>(b); g += dpp_in_row<0x140>(g);
 }
 
 // jacobi_svd_small for exactly 32 x 32 (rows = cols = 32, column stride ld), the D = 32 cores and
@@ -1840,7 +1840,7 @@ __global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc
             const double b = row16_sum(b0 + b1), g = row16_sum(g0 + g1);
             if (in1 && gcol(p2) < rb && a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
                 double c, sn;
-                jacobi_rotation(a, b, g, &c, &sn);
+                jacobi_rotation_fast(a, b, g, &c, &sn);
                 if (ql == 0 && g * g > kQuadRel2 * a * b) s_big = 1;
                 double a0 = 0.0, a1 = 0.0;
 #pragma unroll
@@ -1891,7 +1891,7 @@ __global__ __launch_bounds__(kBJThreads) void block_jacobi_kernel(const CoreDesc
         const double a = row16_sum(a0 + a1), b = row16_sum(b0 + b1), g = row16_sum(g0 + g1);
         if (gcol(p1) < rb && gcol(p2) < rb && a > zero2 && b > zero2 && g * g > tol * tol * a * b) {
             double c, sn;
-            jacobi_rotation(a, b, g, &c, &sn);
+            jacobi_rotation_fast(a, b, g, &c, &sn);
 #pragma unroll
             for (int k = 0; k < kBJKR; ++k) {
                 w1[ql + 16 * k] = c * x[k] - sn * y[k];
