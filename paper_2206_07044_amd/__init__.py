@@ -10,9 +10,9 @@ from ._capi import (Batch, Context, TNError, load_library, tn_plan_describe, exp
                     GEMM_CLASSES, GEMM_TILES, tn_gemm_tiles_get, tn_gemm_tiles_set, tn_gemm_tune,
                     TN_OK, TN_EINVAL, TN_ESTATE, TN_ENOMEM, TN_EDEVICE, TN_ENUMERIC, TN_ZERO)
 from .scoring import TreeScore, TreeScorer
-from .projnet import projector_network
+from .projnet import frozen_projector_grad, projector_network
 
-__all__ = ["projector_network", "Batch", "Context", "TNError", "load_library", "tn_plan_describe", "exported_symbols", "LIB_PATH", "KERNEL_KINDS",
+__all__ = ["projector_network", "frozen_projector_grad", "Batch", "Context", "TNError", "load_library", "tn_plan_describe", "exported_symbols", "LIB_PATH", "KERNEL_KINDS",
            "GEMM_CLASSES", "GEMM_TILES", "tn_gemm_tiles_get", "tn_gemm_tiles_set", "tn_gemm_tune",
            "TN_OK", "TN_EINVAL", "TN_ESTATE", "TN_ENOMEM", "TN_EDEVICE", "TN_ENUMERIC", "TN_ZERO",
            "TreeScore", "TreeScorer"]

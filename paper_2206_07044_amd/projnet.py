@@ -23,12 +23,14 @@ from ._capi import tn_plan_describe
 
 
 def projector_network(ctx, n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
-                      pair_i: Sequence[int], pair_j: Sequence[int], chi: int, late: bool = False):
+                      pair_i: Sequence[int], pair_j: Sequence[int], chi: int, late: bool = False,
+                      with_axes: bool = False):
     """T_P of the last evaluation of ``ctx`` (a tree set on that graph with these pairs and chi).
 
     Returns ``(n_p, edges_p, tensors_p)`` in the input format: edges ``(u, v, dim)`` with u < v,
     every tensor's axes in ascending edge id; tensors 0..n-1 are the inputs, then P_L and P_R of
-    each compression in creation order."""
+    each compression in creation order.  With ``with_axes`` also the axis order of each tensor
+    of T_P (``tensors_p[t] = transpose(original, axes[t])``)."""
     eu = np.asarray([e[0] for e in edges], dtype=np.int32)
     ev = np.asarray([e[1] for e in edges], dtype=np.int32)
     ed = np.asarray([e[2] for e in edges], dtype=np.int32)
@@ -82,11 +84,13 @@ def projector_network(ctx, n: int, edges: Sequence[Tuple[int, int, int]], tensor
     num = {k: i for i, k in enumerate(keys)}
     ends = [[] for _ in keys]
     out_t = []
+    orders = []
     for t, ax in enumerate(axes):
         ids = [num[k] for k in ax]
         for i in ids:
             ends[i].append(t)
         order = sorted(range(len(ids)), key=lambda q: ids[q])
+        orders.append(order)
         out_t.append(np.ascontiguousarray(np.transpose(data[t], order)))
     edges_p = []
     for i, k in enumerate(keys):
@@ -94,4 +98,40 @@ def projector_network(ctx, n: int, edges: Sequence[Tuple[int, int, int]], tensor
             raise RuntimeError(f"edge {k} of T_P has {len(ends[i])} ends")
         u, v = ends[i]
         edges_p.append((min(u, v), max(u, v), dim[k]))
+    if with_axes:
+        return len(axes), edges_p, out_t, orders
     return len(axes), edges_p, out_t
+
+
+def frozen_projector_grad(ctx, n: int, edges: Sequence[Tuple[int, int, int]], tensors: Sequence[np.ndarray],
+                          pair_i: Sequence[int], pair_j: Sequence[int], chi: int, tree_p: Sequence[Tuple[int, int]],
+                          late: bool = False, device: int = 0):
+    """d ln|Z| / d T_v for every input tensor with the run's projectors held fixed: the exact
+    gradient of T_P (contracted without compression on the caller's tree ``tree_p`` over T_P's
+    tensors, every bond of which must stay within the planner's size limit), restricted to the
+    inputs and returned in their own axis order.  T_P is multilinear in the inputs, so each
+    tensor's <T_v, gradient> is 1 (Euler's identity for degree-one homogeneity)."""
+    from ._capi import Context
+    n_p, edges_p, tens_p, orders = projector_network(ctx, n, edges, tensors, pair_i, pair_j, chi, late, True)
+    eu = np.asarray([e[0] for e in edges_p], dtype=np.int32)
+    ev = np.asarray([e[1] for e in edges_p], dtype=np.int32)
+    ed = np.asarray([e[2] for e in edges_p], dtype=np.int32)
+    sizes = [t.size for t in tens_p]
+    off = np.zeros(n_p + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    c = Context(device)
+    try:
+        c.tn_load_graph(n_p, eu, ev, ed, off, np.concatenate([t.ravel() for t in tens_p]))
+        # chi above any bond the planner accepts: no compression
+        c.tn_set_tree([a for a, _ in tree_p], [b for _, b in tree_p], 2 ** 30, precision="fp64", grad=True)
+        c.tn_contract_compressed()
+        if any(d > 0.0 for d in c.tn_compress_stats()[0]):
+            raise RuntimeError("the tree over T_P compressed a bond: T_P was not contracted exactly")
+        g = c.tn_grad()
+    finally:
+        c.close()
+    out = []
+    for v in range(n):
+        gv = g[off[v]:off[v + 1]].reshape(tens_p[v].shape)
+        out.append(np.ascontiguousarray(np.transpose(gv, np.argsort(orders[v]))))
+    return out

@@ -79,3 +79,44 @@ def test_read_projectors_needs_kept_buffers():
         assert e.value.status == TN_ESTATE
     finally:
         c.close()
+
+
+def test_frozen_projector_gradient():
+    """d ln|Z| / d T_v with the run's projectors held fixed (frozen_projector_grad: the exact
+    gradient of T_P through the library's reverse pass) against central differences of T_P's
+    exact host contraction, the projectors kept, and Euler's identity <T_v, g_v> = 1 per input
+    tensor (T_P is multilinear in the inputs)."""
+    from tninputs import Graph
+    from tninputs.trees import greedy_tree
+    g = lattice((4, 4))
+    T = ising_tensors(g, 0.44)
+    pairs = sweep_tree((4, 4))
+    pi, pj = [a for a, _ in pairs], [b for _, b in pairs]
+    c = _ctx(g, T)
+    try:
+        c.tn_set_tree(pi, pj, 2, keep_intermediates=True)
+        c.tn_contract_compressed()
+        n_p, edges_p, _ = tn.projector_network(c, g.n, g.edges, T, pi, pj, 2)
+        tree_p = greedy_tree(Graph(n_p, edges_p), 2 ** 30, seed=0)
+        grads = tn.frozen_projector_grad(c, g.n, g.edges, T, pi, pj, 2, tree_p)
+        euler = [float(np.sum(T[v] * grads[v])) for v in range(g.n)]
+        print(f"Euler identity per tensor: max |<T, g> - 1| = {max(abs(e - 1.0) for e in euler):.2e}", flush=True)
+        assert max(abs(e - 1.0) for e in euler) <= 1e-10
+        rng = np.random.default_rng(7)
+        h = 1e-6
+        worst = 0.0
+        for _ in range(6):
+            v = int(rng.integers(g.n))
+            idx = tuple(int(rng.integers(d)) for d in T[v].shape)
+            vals = []
+            for sgn in (1.0, -1.0):
+                Tm = [t.copy() for t in T]
+                Tm[v][idx] += sgn * h
+                n2, e2, t2 = tn.projector_network(c, g.n, g.edges, Tm, pi, pj, 2)
+                vals.append(greedy_exact(n2, e2, t2)[1])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            worst = max(worst, abs(fd - grads[v][idx]))
+        print(f"central differences of T_P: max |fd - g| = {worst:.2e}", flush=True)
+        assert worst <= 1e-6
+    finally:
+        c.close()
