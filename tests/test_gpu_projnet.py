@@ -3,8 +3,10 @@
 tn_read_projectors exports every P_L and P_R a run applied, with the bond they act on;
 paper_2206_07044_amd.projector_network inserts them into the input network.  Contracted exactly
 on the host (greedy pairwise order, not the tree's), T_P must give the run's own compressed
-ln|Z| (float64 runs: to 1e-10 relative) on every compression path: the LDS core (D <= 64), the
-Gram-Lanczos core (D = 256), late compression, the tree gauge, a random-graph Agglom tree.
+ln|Z| (float64 runs: to 1e-10 relative) on every compression path: the LDS core (D <= 64),
+block Jacobi (both sides taller than 64 < D <= 256), the Gram-Lanczos core (D = 256), block
+Krylov (D = 729 with an explicit side), Golub-Kahan-Lanczos (both sides taller than D = 300),
+late compression, the tree gauge, a random-graph Agglom tree.
 """
 import numpy as np
 import pytest
@@ -39,6 +41,11 @@ def _cases():
     yield "normal-4x4-D3-chi3-gauge1", g, normal_tensors(g, 0.2, seed=4), sweep_tree((4, 4)), 3, {"gauge_r": 1}
     rr = random_regular3(20, seed=1)
     yield "dimer-rrg20-chi2", rr, dimer_tensors(rr), agglom_tree(rr, 2, seed=0), 2, {}
+    g = lattice((3, 3, 4), dim=3)
+    yield "normal-3x3x4-D3-chi27", g, normal_tensors(g, 0.2, seed=5), sweep_tree((3, 3, 4)), 27, {}
+    from test_gpu_lanczos_degenerate import degenerate_network
+    g, T, pairs, _ = degenerate_network(300, 600, 640, 0, "middle")
+    yield "gkl-D300-chi6", g, T, pairs, 6, {}
 
 
 CASES = list(_cases())
