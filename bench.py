@@ -42,7 +42,7 @@ PEAKS = {  # MI355X published dense peaks
 # was measured on (SHA-256 prefix of tn_kernels.hip), else the bench line reports null.
 MEASURED_TRAFFIC = {
     ("core_lds", "fp32", "ising-cubic-12x12x12-beta0.22-chi16-span-sweep"): {
-        "bytes_per_launch": 473.0 * 1024, "kernel_source_sha256": "a81c97a0785d6577",
+        "bytes_per_launch": 467.1 * 1024, "kernel_source_sha256": "a12ad17775debd7b",
         "source": "profiles/core_lds_traffic_ising12_chi16_fp32.md"},
 }
 

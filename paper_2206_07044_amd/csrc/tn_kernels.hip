@@ -1351,6 +1351,21 @@ __device__ inline double row16_sum(double v) {
     return v;
 }
 
+// One halving step of a transposed reduction over a 16-lane DPP row: the lanes l and l ^ W
+// pair up, the one with that bit clear keeps v[0, W) and the other v[W, 2 W), and each adds the
+// partner's copy of the half it keeps into v[0, W).  kFromUp / kFromDown: DPP controls that read
+// lane l - W and l + W (row_ror moves data to higher lanes; or quad permutations).
+template <int W, int kFromUp, int kFromDown>
+__device__ inline void halve_rows(double* v, bool up) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const double send = up ? v[k] : v[k + W];
+        const double keep = up ? v[k + W] : v[k];
+        const double a = dpp_in_row<kFromUp>(send), b = dpp_in_row<kFromDown>(send);
+        v[k] = keep + (up ? a : b);
+    }
+}
+
 // jacobi_svd for rows, cols <= 16 KR (KR <= 4): each pair is rotated by one 16-lane row of a
 // wave (KR rows of W per lane), so reductions stay inside DPP rows and a wave rotates four
 // pairs at once.  Same pair order, thresholds and result contract as jacobi_svd.
@@ -2719,38 +2734,66 @@ __global__ __launch_bounds__(kCoreThreads) void gram_lanczos_kernel(const GLancz
     // S and T1 were formed before this launch by grouped float64 GEMMs, so that a Lanczos step is
     // one matvec: Y a Gram: T1 = G_Y F_X^T (D x n), S = F_X T1; Y explicit: T1 = C1 = F_X F_Y^T
     // (n x my), S = C1 C1^T
-    // y = S x.  For n <= 256, S is symmetric up to the rounding of the GEMMs that formed it, so
-    // y_i = sum_d S[d, i] x_d: thread (h, i) sums the rows d = h mod 4 of column i, reading rows of
-    // S coalesced across i with 32 loads in flight; the four row classes' partial sums meet in LDS
-    // after the vector (the room after y is free while the steps run)
-    static_assert(kCoreThreads == 1024, "four row classes of 256 columns");
+    // y = S x for n <= 256.  S is symmetric up to the rounding of the GEMMs that formed it, so only
+    // its upper 32 x 32 tiles are read (288 of 512 KB at n = 256, and the S of the cores sharing
+    // an XCD then fit its L2): tile (I, J), I <= J, gives block J its column sums
+    // sum_d S[d, i] x_d and, for I < J, block I its row sums sum_i S[d, i] x_i.  Wave w takes
+    // tiles w, w + 16, ...; in a tile, lane (h, c) holds rows 16 h .. 16 h + 15 of column c.  The
+    // row sums are reduced over the 32 columns of a half wave by halving exchanges inside each
+    // 16-lane row (halve_rows over lane bits 3, 2, 1, 0) and one cross-row add, after which lane
+    // c < 16 holds row c of its half.  Each tile's 32 column and 32 row sums go to their own LDS slots after
+    // y (the room there is free while the steps run), and y_i adds its block's slots in a fixed
+    // order
+    static_assert(kCoreThreads == 1024, "16 waves over at most 36 upper tiles");
     auto apply_small = [&](const double* x, double* y) {
-        const int i = tid & 255, h = tid >> 8;
-        double acc = 0.0;
-        if (i < n) {
-            const double* sc = S + i;
-            int r = h;
-            for (; r + 4 * 31 < n; r += 4 * 32) {
-                double v[32];
-#pragma unroll
-                for (int u = 0; u < 32; ++u) v[u] = sc[(int64_t)(r + 4 * u) * n];
-                double a4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int u = 0; u < 32; ++u) a4[u & 3] = fma(v[u], x[r + 4 * u], a4[u & 3]);
-                acc += (a4[0] + a4[1]) + (a4[2] + a4[3]);
+        const int nb = (n + 31) >> 5, ntile = nb * (nb + 1) / 2;
+        double* slot = y + n;                          // ntile x 64: column sums, then row sums
+        const int c = tid & 31, hf = (tid >> 5) & 1;
+        for (int t = tid >> 6; t < ntile; t += kCoreWaves) {
+            int I = 0, rem = t;
+            while (rem >= nb - I) {
+                rem -= nb - I;
+                ++I;
             }
-            for (; r < n; r += 4) acc = fma(sc[(int64_t)r * n], x[r], acc);
+            const int J = I + rem;
+            const int col = 32 * J + c, row0 = 32 * I + 16 * hf;
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = (col < n && row0 + u < n) ? S[(int64_t)(row0 + u) * n + col] : 0.0;
+            double cs = 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (row0 + u < n) cs = fma(v[u], x[row0 + u], cs);
+            cs += __shfl_xor(cs, 32, 64);
+            if (hf == 0) slot[t * 64 + c] = cs;
+            if (I < J) {
+                const double xc = col < n ? x[col] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] *= xc;
+                halve_rows<8, 0x128, 0x128>(v, (c & 8) != 0);
+                halve_rows<4, 0x124, 0x12C>(v, (c & 4) != 0);
+                halve_rows<2, 0x4E, 0x4E>(v, (c & 2) != 0);
+                halve_rows<1, 0xB1, 0xB1>(v, (c & 1) != 0);
+                const double r = v[0] + __shfl_xor(v[0], 16, 64);
+                if (c < 16) slot[t * 64 + 32 + 16 * hf + c] = r;
+            }
         }
-        double* spart = y + n;
-        spart[tid] = acc;
         __syncthreads();
-        if (tid < n) y[tid] = (spart[tid] + spart[256 + tid]) + (spart[512 + tid] + spart[768 + tid]);
+        if (tid < n) {
+            const int J = tid >> 5, cc = tid & 31;
+            double acc = 0.0;
+            for (int I = 0; I <= J; ++I) acc += slot[(I * nb - I * (I - 1) / 2 + (J - I)) * 64 + cc];
+            for (int K = J + 1; K < nb; ++K) acc += slot[(J * nb - J * (J - 1) / 2 + (K - J)) * 64 + 32 + cc];
+            y[tid] = acc;
+        }
         __syncthreads();
     };
 
     // Lanczos basis: its first jl columns live in LDS, after the room kept for the tridiagonal
     // solve (s <= kTriLdsS), the rest in the workspace
     constexpr int kTriLdsS = 48;
+    static_assert(256 + 36 * 64 <= 2 * kTriLdsS * kTriLdsS, "the matvec slots fit in the room before the basis");
     double* lq = lds + 2 * kTriLdsS * kTriLdsS;
     const int jl = min(sm, (int)(((int64_t)kLanczosLdsBytes / 8 - 2 * kTriLdsS * kTriLdsS) / max(n, 1)));
     auto qcol = [&](int j) -> double* { return j < jl ? lq + (int64_t)j * n : Q + (int64_t)j * n; };
